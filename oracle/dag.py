@@ -1,0 +1,169 @@
+"""Contraction DAG formation (Sec. II-B, "Notation").
+
+Each input graph is a binary contraction tree.  Structurally identical
+contractions (same kind, same ordered children) are one DAG node, so trees
+share nodes but never roots unless the whole graph is identical; identical
+graphs share their root (the tree list then holds that root once).
+
+Node ids: leaves 0..L-1 in input order, then each new contraction in order of
+first appearance while graphs are scanned in order, op by op.
+parents(u) has one entry per edge, in the order edges are created.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, List, Tuple
+
+LEAF, INTERIOR, ROOT = "LEAF", "INTERIOR", "ROOT"
+K22, K32, K33, HCA = 0, 1, 2, 3
+
+# (left rank, right rank) -> output rank, per kind; HCA outputs a scalar per t.
+_RANKS = {K22: ((2, 2), 2), K32: ((3, 2), 3), K33: ((3, 3), 2), HCA: ((2, 2), 0)}
+
+
+class InvalidGraph(ValueError):
+    pass
+
+
+@dataclass
+class Dag:
+    n_leaves: int
+    kind: List[int] = field(default_factory=list)      # -1 for leaves
+    left: List[int] = field(default_factory=list)      # -1 for leaves
+    right: List[int] = field(default_factory=list)
+    rank: List[int] = field(default_factory=list)
+    nvec: List[int] = field(default_factory=list)
+    nt: List[int] = field(default_factory=list)
+    parents: List[List[int]] = field(default_factory=list)
+    root_of_graph: List[int] = field(default_factory=list)
+    tree_roots: List[int] = field(default_factory=list)   # unique roots, first-appearance order
+
+    @property
+    def n_nodes(self) -> int:
+        return len(self.kind)
+
+    def children(self, u: int) -> Tuple[int, ...]:
+        return () if self.kind[u] < 0 else (self.left[u], self.right[u])
+
+    def node_type(self, u: int) -> str:
+        if self.kind[u] < 0:
+            return LEAF
+        return ROOT if not self.parents[u] else INTERIOR
+
+    def contractions(self) -> List[int]:
+        return [u for u in range(self.n_nodes) if self.kind[u] >= 0]
+
+    def elems(self, u: int) -> int:
+        """Complex elements of the tensor of u: Nt * N^rank (0 for a root's scalar output
+        is handled by size())."""
+        return self.nt[u] * self.nvec[u] ** self.rank[u]
+
+    def size(self, u: int, elem_bytes: int = 16) -> int:
+        """u.size in bytes of the device dtype; a root's output is a per-t scalar written
+        straight to the correlator buffer and counts 0 (reading of Sec. II-C)."""
+        if self.kind[u] == HCA:
+            return 0
+        return self.elems(u) * elem_bytes
+
+    def tree_nodes(self, i: int) -> List[int]:
+        """Node set of tree T_i: the root and all its descendants (post-order, left first)."""
+        out, seen = [], set()
+
+        def visit(u):
+            if u in seen:
+                return
+            seen.add(u)
+            for c in self.children(u):
+                visit(c)
+            out.append(u)
+
+        visit(self.tree_roots[i])
+        return out
+
+
+def build(leaves, graphs) -> Dag:
+    """Merge the graphs into one DAG by hash-consing (kind, left, right).
+
+    `leaves`: sequence of objects with .rank .nvec .nt; `graphs`: sequence with
+    .ops = [(kind, left, right), ...].  Raises InvalidGraph for malformed input.
+    """
+    d = Dag(n_leaves=len(leaves))
+    for lf in leaves:
+        if lf.rank not in (2, 3) or lf.nvec < 1 or lf.nt < 1:
+            raise InvalidGraph("bad leaf shape")
+        d.kind.append(-1)
+        d.left.append(-1)
+        d.right.append(-1)
+        d.rank.append(lf.rank)
+        d.nvec.append(lf.nvec)
+        d.nt.append(lf.nt)
+        d.parents.append([])
+    table: Dict[Tuple[int, int, int], int] = {}
+    roots_seen = set()
+    for gi, g in enumerate(graphs):
+        ops = list(g.ops)
+        if not ops:
+            raise InvalidGraph("empty graph")
+        local: List[int] = []
+        consumed = [0] * len(ops)
+        for oi, (kind, l, r) in enumerate(ops):
+            if kind not in _RANKS:
+                raise InvalidGraph("bad kind")
+            if (kind == HCA) != (oi == len(ops) - 1):
+                raise InvalidGraph("the root, and only the root, must be a trace")
+            ids = []
+            for x in (l, r):
+                if x >= 0:
+                    if x >= len(leaves):
+                        raise InvalidGraph("leaf id out of range")
+                    ids.append(x)
+                else:
+                    j = -x - 1
+                    if j >= oi:
+                        raise InvalidGraph("forward or self reference")
+                    consumed[j] += 1
+                    ids.append(local[j])
+            lid, rid = ids
+            if lid == rid:
+                raise InvalidGraph("identical operands")
+            (rl, rr), ro = _RANKS[kind]
+            if d.rank[lid] != rl or d.rank[rid] != rr:
+                raise InvalidGraph("operand rank mismatch")
+            if d.nvec[lid] != d.nvec[rid] or d.nt[lid] != d.nt[rid]:
+                raise InvalidGraph("operand N or Nt mismatch")
+            key = (kind, lid, rid)
+            u = table.get(key)
+            if u is None:
+                u = len(d.kind)
+                table[key] = u
+                d.kind.append(kind)
+                d.left.append(lid)
+                d.right.append(rid)
+                d.rank.append(ro)
+                d.nvec.append(d.nvec[lid])
+                d.nt.append(d.nt[lid])
+                d.parents.append([])
+                d.parents[lid].append(u)
+                d.parents[rid].append(u)
+            local.append(u)
+        if any(c != 1 for c in consumed[:-1]):
+            raise InvalidGraph("every non-root op must be used exactly once in its graph")
+        root = local[-1]
+        d.root_of_graph.append(root)
+        if root not in roots_seen:
+            roots_seen.add(root)
+            d.tree_roots.append(root)
+    return d
+
+
+def stats(d: Dag) -> dict:
+    """|V|, |E|, F_v and F_e as defined in the Tree runtime analysis (Sec. III-B)."""
+    trees = [set(d.tree_nodes(i)) for i in range(len(d.tree_roots))]
+    ctree = [0] * d.n_nodes
+    for t in trees:
+        for u in t:
+            ctree[u] += 1
+    edges = [(c, u) for u in range(d.n_nodes) for c in d.children(u)]
+    fe = sum(sum(1 for t in trees if c in t and u in t) for c, u in edges)
+    return dict(n_nodes=d.n_nodes, n_edges=len(edges), n_trees=len(trees),
+                f_v=sum(ctree) / d.n_nodes, f_e=fe / max(1, len(edges)))

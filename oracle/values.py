@@ -1,0 +1,113 @@
+"""Correlator values in complex128 (the plain definition the method must reach).
+
+Every graph is evaluated on its own from its op list, without the DAG's
+sharing: the scheduling and eviction machinery changes only the order of work
+and where tensors live, never the values, so the result is simply the full
+contraction of each graph's tree at every time slice t.
+
+Kinds, per time slice t (no index conventions are printed in the paper; these
+are the engine's, with contracted axes trailing on the left operand and
+leading on the right; the contraction costs O(N^3), O(N^4), O(N^4)/O(N^5) as
+the paper states for meson and baryon systems):
+  K22: O[i,j]   = sum_k  X[i,k]   Y[k,j]
+  K32: O[i,j,l] = sum_k  X[i,j,k] Y[k,l]
+  K33: O[i,m]   = sum_jl X[i,j,l] Y[j,l,m]
+  HCA: C        = sum_ij P[i,j]   Q[j,i]       (the root's "contract all")
+The cross-diagram sum of a correlator c is S_c(t) = sum_{g in c} w_g C_g(t),
+taken as a correctly rounded sum (math.fsum) of the FP64 terms.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+K22, K32, K33, HCA = 0, 1, 2, 3
+
+
+def contract(kind: int, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """One binary contraction batched over the leading t axis, in complex128.
+
+    A batched matrix product (numpy.matmul) is the library primitive; the
+    reshapes only group the contracted and free axes of the definitions above."""
+    nt = X.shape[0]
+    if kind == K22:
+        return np.matmul(X, Y)
+    if kind == K32:
+        n = X.shape[1]
+        return np.matmul(X.reshape(nt, n * n, n), Y).reshape(nt, n, n, n)
+    if kind == K33:
+        n = X.shape[1]
+        return np.matmul(X.reshape(nt, n, n * n), Y.reshape(nt, n * n, n))
+    if kind == HCA:
+        return np.einsum("tij,tji->t", X, Y)
+    raise KeyError(kind)
+
+
+def contract_einsum(kind: int, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """The same definitions written as plain einsum index strings (small inputs)."""
+    spec = {K22: "tik,tkj->tij", K32: "tijk,tkl->tijl", K33: "tijl,tjlm->tim",
+            HCA: "tij,tji->t"}[kind]
+    return np.einsum(spec, X, Y)
+
+
+def evaluate_graph(leaves: Sequence[np.ndarray], ops) -> np.ndarray:
+    """C_g(t) for one graph: its ops in order; operand >= 0 is a leaf, < 0 an earlier op."""
+    vals: List[np.ndarray] = []
+    for kind, l, r in ops:
+        X = leaves[l] if l >= 0 else vals[-l - 1]
+        Y = leaves[r] if r >= 0 else vals[-r - 1]
+        vals.append(contract(kind, X, Y))
+    return vals[-1]
+
+
+def correlators(workload, graphs: Sequence[int] = None) -> Dict[int, np.ndarray]:
+    """{graph index: complex128 [nt]} for the chosen graphs (all by default)."""
+    data = [lf.data for lf in workload.leaves]
+    idx = range(len(workload.graphs)) if graphs is None else graphs
+    return {g: evaluate_graph(data, workload.graphs[g].ops) for g in idx}
+
+
+def trace4_loops(A, B, C, D) -> np.ndarray:
+    """tr(A B C D) per t by explicit index loops (tiny inputs only)."""
+    nt, n = A.shape[0], A.shape[1]
+    out = np.zeros(nt, dtype=np.complex128)
+    for t in range(nt):
+        a, b, c, d = (M[t].tolist() for M in (A, B, C, D))
+        s = 0j
+        for i in range(n):
+            for j in range(n):
+                aij = a[i][j]
+                for k in range(n):
+                    abk = aij * b[j][k]
+                    ck = c[k]
+                    for l in range(n):
+                        s += abk * ck[l] * d[l][i]
+        out[t] = s
+    return out
+
+
+def cross_sums(workload, corr_values: Dict[int, np.ndarray]) -> Dict[int, np.ndarray]:
+    """S_c(t) = sum_g w_g C_g(t), correctly rounded per component (math.fsum)."""
+    by_corr: Dict[int, List[int]] = {}
+    for g, spec in enumerate(workload.graphs):
+        by_corr.setdefault(spec.corr, []).append(g)
+    out = {}
+    for c, gs in by_corr.items():
+        nt = len(corr_values[gs[0]])
+        s = np.zeros(nt, dtype=np.complex128)
+        for t in range(nt):
+            terms = [complex(workload.graphs[g].w) * complex(corr_values[g][t]) for g in gs]
+            s[t] = complex(math.fsum(z.real for z in terms), math.fsum(z.imag for z in terms))
+        out[c] = s
+    return out
+
+
+def cross_sum_scale(workload, corr_values: Dict[int, np.ndarray]) -> Dict[int, np.ndarray]:
+    """sum_g |w_g C_g(t)| per correlator: the condition-aware error scale for S_c(t)."""
+    out: Dict[int, np.ndarray] = {}
+    for g, spec in enumerate(workload.graphs):
+        v = np.abs(complex(spec.w) * corr_values[g])
+        out[spec.corr] = out.get(spec.corr, 0) + v
+    return out

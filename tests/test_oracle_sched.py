@@ -1,0 +1,301 @@
+"""Pins of the oracle's DAG build, schedulers and memory model (CPU only).
+
+What pins what:
+  * Table sch-mem (Sec. II-C): memory contents and sizes after each contraction of
+    S1 and S2 on the Fig. 1 DAG (golden fixture, one cell read as a typo).
+  * Fig. 3's initial individual gains (b: -1 in every tree, c in T2: 0).
+  * Fig. 4's five PROCESS-CHILD cases, seen through the gain definition M - M'.
+  * Eq. (1) ranks; M_n = 0; peak_post <= peak_live; each contraction once; brute
+    force optimum <= every heuristic; F_v / F_e by hand on Fig. 1.
+"""
+import itertools
+import json
+import os
+import random
+
+import pytest
+
+from synth import workloads as W
+from oracle import dag as D
+from oracle import schedules as S
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "table_sch_mem.json")
+NAMES = dict(a=0, b=1, c=2, d=3)
+
+
+def fig1(order="fgh"):
+    wl = W.fig1_dag(order, with_data=False)
+    d = D.build(wl.leaves, wl.graphs)
+    names = dict(NAMES)
+    # roots and e by structure, independent of creation order
+    for u in d.contractions():
+        key = (d.left[u], d.right[u])
+        names[{(0, 1): "f", (1, 2): "e", (0, 4): "g", (0, 5): "g", (0, 6): "g",
+               (0, 7): "g"}.get(key, "?")] = u
+    e = names["e"]
+    for u in d.contractions():
+        if (d.left[u], d.right[u]) == (0, e):
+            names["g"] = u
+        if (d.left[u], d.right[u]) == (e, 3):
+            names["h"] = u
+    names.pop("?", None)
+    return d, names
+
+
+def unit(d):
+    return d.size(0)
+
+
+def test_fig1_structure():
+    d, n = fig1()
+    assert set(n) == set("abcdefgh")
+    assert d.node_type(n["e"]) == D.INTERIOR
+    for r in "fgh":
+        assert d.node_type(n[r]) == D.ROOT
+    assert d.n_nodes == 8 and len(d.tree_roots) == 3
+    # each contraction is binary: |E| = 2 * #non-leaf nodes
+    assert sum(len(p) for p in d.parents) == 2 * len(d.contractions())
+
+
+@pytest.mark.parametrize("which", ["S1", "S2"])
+def test_table_sch_mem(which):
+    gold = json.load(open(GOLD))["schedules"][which]
+    d, n = fig1()
+    inv = {v: k for k, v in n.items()}
+    order = [n[x] for x in gold["order"]]
+    sim = S.memsim(d, order)
+    # unit sizes: every rank-2 tensor here has the same size; roots count 0
+    assert [m // unit(d) for m in sim["M"]] == gold["size"]
+    assert [sorted(inv[u] for u in c) for c in sim["contents"]] == gold["after"]
+    assert sim["M"][-1] == 0
+
+
+def test_peak_live_vs_post_on_fig1():
+    d, n = fig1()
+    s1 = S.memsim(d, [n[x] for x in "eghf"])
+    s2 = S.memsim(d, [n[x] for x in "fegh"])
+    assert (s1["peak_post"], s2["peak_post"]) == (3 * unit(d), 2 * unit(d))
+    # while e = b.c runs in S1: b, c and the output e coexist
+    assert s1["peak_live"] == 4 * unit(d)
+    for s in (s1, s2):
+        assert s["peak_post"] <= s["peak_live"]
+
+
+def test_igain_example():
+    gold = json.load(open(GOLD))["igain_example"]
+    d, n = fig1("fgh")
+    ig = S.tree_initial_igains(d)
+    for i in range(3):
+        assert ig[i][n["b"]] == gold["b_in_every_tree"] * unit(d)
+    # the second tree holds c and e (the tree of g); c's only parent e is in it
+    assert ig[1][n["c"]] == gold["c_in_second_tree"]
+    assert [sum(g.values()) // unit(d) for g in ig] == [-2, -3, -2]
+
+
+def test_ranks_eq1():
+    d, n = fig1()
+    rk = S.ranks(d)
+    assert [rk[n[x]] for x in "abcd"] == [0, 0, 0, 0]
+    assert rk[n["e"]] == 1 and rk[n["f"]] == 1
+    assert rk[n["g"]] == 2 and rk[n["h"]] == 2
+
+
+def test_tree_and_sibling_on_fig1():
+    d, n = fig1("fgh")
+    inv = {v: k for k, v in n.items()}
+    # Tree: T_f and T_h tie at -2 (lowest index wins), then T_g has gain +1
+    assert "".join(inv[u] for u in S.tree(d)) == "fegh"
+    # Sibling picks leaf a first; with this input order f and e enter Q1 in that order
+    assert "".join(inv[u] for u in S.sibling(d)) == "fegh"
+    d2, n2 = fig1("ghf")
+    inv2 = {v: k for k, v in n2.items()}
+    # with g listed first, e precedes f in b's parent list: Sibling yields S1
+    assert "".join(inv2[u] for u in S.sibling(d2)) == "eghf"
+    assert "".join(inv2[u] for u in S.input_order(d2)) == "eghf"
+    assert "".join(inv[u] for u in S.input_order(d)) == "fegh"
+
+
+def test_fv_fe_by_hand():
+    d, _ = fig1()
+    st = D.stats(d)
+    assert st["n_edges"] == 8
+    assert abs(st["f_v"] - 13 / 8) < 1e-15
+    assert abs(st["f_e"] - 10 / 8) < 1e-15
+
+
+# ------------------------------------------------------------ Fig. 4 cases
+class _Leaf:
+    def __init__(self, rank, nvec=4, nt=1):
+        self.rank, self.nvec, self.nt = rank, nvec, nt
+
+
+class _G:
+    def __init__(self, ops):
+        self.ops = ops
+
+
+def _gain_change(leaves, graphs, first, then, target):
+    d = D.build(leaves, graphs)
+    st = S._TreeState(d, [d.size(u) for u in range(d.n_nodes)])
+    for i in first:
+        st.process(i)
+    g0 = st.gain(target)
+    st.process(then)
+    return d, g0, st.gain(target)
+
+
+def test_case_2a_and_2b():
+    # x = leaf 0 is brought in by tree 0; u = root of tree 1 (not in T_i); T_i = tree 2
+    L = [_Leaf(2) for _ in range(5)]
+    gs = [_G([(W.HCA, 0, 1)]), _G([(W.HCA, 0, 2)]), _G([(W.HCA, 0, 3)])]
+    d, g0, g1 = _gain_change(L, gs, [0], 1, 2)
+    assert g1 - g0 == d.size(0)            # 2.a: delta(x,T_i) was 1 -> +x.size
+    gs.append(_G([(W.HCA, 0, 4)]))         # another outside parent keeps x alive
+    d, g0, g1 = _gain_change(L, gs, [0], 1, 2)
+    assert g1 - g0 == 0                    # 2.b: delta(x,T_i) > 1 -> no change
+
+
+def test_case_1a_1b_1c():
+    # leaves: x=0, y=1, y2=2, y3=3, y4=4 (rank 3); m=5, m3=6, m4=7, m5=8 (rank 2).
+    # Tree 0 brings x in; T' (tree 1) and T_i (tree 2) share u = K33(x, y).
+    L = [_Leaf(3) for _ in range(5)] + [_Leaf(2) for _ in range(4)]
+    t0 = _G([(W.K33, 0, 2), (W.HCA, -1, 5)])
+    tp = _G([(W.K33, 0, 1), (W.HCA, -1, 6)])
+    ti = _G([(W.K33, 0, 1), (W.HCA, -1, 7)])
+    d, g0, g1 = _gain_change(L, [t0, tp, ti], [0], 1, 2)
+    sx, su = d.size(0), d.size(d.left[d.root_of_graph[1]])
+    assert sx != su
+    # u's own updates give +2 s_u (its igain leaves T_i's sum, then 2.a once T'
+    # has used it); case 1.a adds -s_x: x's last AVAIL parent u was in T_i.
+    assert g1 - g0 == 2 * su - sx
+    # 1.b: tau(x, T_i) = 2 (x also feeds another node of T_i) -> no x term
+    ti_b = _G([(W.K33, 0, 1), (W.K33, 0, 3), (W.HCA, -1, -2)])
+    d, g0, g1 = _gain_change(L, [t0, tp, ti_b], [0], 1, 2)
+    assert g1 - g0 == 2 * su
+    # 1.c: tau(x, T_i) = 1 and delta(x, T_i) = 1 (a third, unprocessed tree uses x)
+    tz = _G([(W.K33, 0, 4), (W.HCA, -1, 8)])
+    d, g0, g1 = _gain_change(L, [t0, tp, ti, tz], [0], 1, 2)
+    assert g1 - g0 == 2 * su
+
+
+# ------------------------------------------------------------ random DAG checks
+def random_ring(seed, n_leaves=6, n_graphs=8, lmin=3, lmax=5):
+    wl = W.meson_ring(n_leaves=n_leaves, nvec=4, nt=1, n_graphs=n_graphs, lmin=lmin,
+                      lmax=lmax, seed=seed, with_data=False)
+    return D.build(wl.leaves, wl.graphs)
+
+
+def random_mixed(seed):
+    """Mixed sizes: meson rings and baryon chains of one N in one DAG."""
+    rng = random.Random(seed)
+    leaves = [_Leaf(3) for _ in range(3)] + [_Leaf(2) for _ in range(4)]
+    gs = []
+    for _ in range(rng.randint(3, 7)):
+        if rng.random() < 0.5:
+            a, c = rng.sample(range(3), 2)
+            b, dd = rng.sample(range(3, 7), 2)
+            gs.append(_G([(W.K32, a, b), (W.K33, -1, c), (W.HCA, -2, dd)]))
+        else:
+            seq = rng.sample(range(3, 7), rng.randint(2, 4))
+            ops = []
+            cur = seq[0]
+            for x in seq[1:-1]:
+                ops.append((W.K22, cur, x))
+                cur = -len(ops)
+            ops.append((W.HCA, cur, seq[-1]))
+            gs.append(_G(ops))
+    return D.build(leaves, gs)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_heuristics_valid_and_bounded(seed):
+    d = random_ring(seed) if seed % 2 == 0 else random_mixed(seed)
+    n_contr = len(d.contractions())
+    peaks = {}
+    for pol in ("input", "sibling", "tree"):
+        order = S.schedule(d, pol)
+        assert sorted(order) == sorted(d.contractions())      # each processed once
+        sim = S.memsim(d, order)                               # raises if not topological
+        assert sim["M"][-1] == 0
+        assert sim["peak_post"] <= sim["peak_live"]
+        peaks[pol] = sim["peak_post"]
+    if n_contr <= 8:
+        opt = S.optimal_peak(d)
+        assert all(opt <= p for p in peaks.values())
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_tree_gain_cache_matches_full_recompute(seed):
+    d = random_ring(seed, n_leaves=7, n_graphs=12) if seed % 2 else random_mixed(seed)
+    assert S.tree(d) == S.tree(d, recompute_all=True)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_tree_gain_is_memory_difference(seed):
+    """tgain of the chosen tree equals M - M' measured by memsim on the prefix."""
+    d = random_mixed(seed)
+    sizes = [d.size(u) for u in range(d.n_nodes)]
+    st = S._TreeState(d, sizes)
+    order = []
+    alive = set(range(len(d.tree_roots)))
+    while alive:
+        gains = {i: st.gain(i) for i in alive}
+        best = max(sorted(alive), key=lambda i: gains[i])
+        before = _mem_after(d, order)
+        order += [u for u in st.process(best) if d.kind[u] >= 0]
+        after = _mem_after(d, order)
+        assert gains[best] == before - after
+        alive.discard(best)
+
+
+def _mem_after(d, prefix):
+    """Memory after running `prefix` under Sec. II-C, counting leaves whose users all
+    ran as released, by direct set reasoning (independent of memsim)."""
+    done = set(prefix)
+    total = 0
+    for x in range(d.n_nodes):
+        used_by = d.parents[x]
+        started = (x in done) if d.kind[x] >= 0 else any(p in done for p in used_by)
+        if started and any(p not in done for p in used_by):
+            total += d.size(x)
+    return total
+
+
+def test_build_validation():
+    L = [_Leaf(2), _Leaf(2), _Leaf(3)]
+    bad = [
+        [(W.K22, 0, 0), (W.HCA, -1, 1)],        # identical operands
+        [(W.K22, 0, 1)],                         # root is not a trace
+        [(W.HCA, 0, 1), (W.HCA, 0, 1)],          # trace before the end
+        [(W.K22, 0, 5), (W.HCA, -1, 1)],         # leaf id out of range
+        [(W.K22, 0, -1), (W.HCA, -1, 1)],        # self reference
+        [(W.K22, 2, 1), (W.HCA, -1, 1)],         # rank mismatch
+        [(W.K22, 0, 1), (W.K22, 1, 0), (W.HCA, -1, 0)],   # op 1 unused
+    ]
+    for ops in bad:
+        with pytest.raises(D.InvalidGraph):
+            D.build(L, [_G(ops)])
+    with pytest.raises(D.InvalidGraph):
+        D.build([_Leaf(2, nvec=4), _Leaf(2, nvec=5)], [_G([(W.HCA, 0, 1)])])
+
+
+def test_hash_consing_and_shared_roots():
+    wl = W.tiny_meson_perm(with_data=False)
+    d = D.build(wl.leaves, wl.graphs)
+    pairs = {tuple(g.ops[0][1:]) for g in wl.graphs} | {tuple(g.ops[1][1:]) for g in wl.graphs}
+    n_k22 = sum(1 for u in d.contractions() if d.kind[u] == W.K22)
+    assert n_k22 == len(pairs)
+    # identical graphs share one root and one tree
+    d2 = D.build(wl.leaves, wl.graphs + wl.graphs[:2])
+    assert len(d2.tree_roots) == len(d.tree_roots) == 6
+    assert d2.root_of_graph[6:] == d2.root_of_graph[:2]
+
+
+def test_optimal_peak_small_exhaustive():
+    d, n = fig1()
+    orders = list(S.topo_orders(d))
+    assert len(orders) == len(set(map(tuple, orders)))
+    # 4 contractions, e before g and h: 4!/... = 8 orders with e ahead of g and h
+    assert len(orders) == sum(1 for p in itertools.permutations("efgh")
+                              if p.index("e") < p.index("g") and p.index("e") < p.index("h"))
+    assert S.optimal_peak(d) == 2 * unit(d)
