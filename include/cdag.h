@@ -1,0 +1,204 @@
+/*
+ * cdag.h -- C ABI of the contraction-DAG engine (one MI355X GPU).
+ *
+ * The engine evaluates many-body correlation functions given as binary
+ * contraction trees over hadron-node tensors (problem statement: Sec. II-B
+ * "Notation" and Sec. II-C "Problem definition").  The trees are merged into
+ * one contraction DAG, ordered by a scheduler (Sec. III: Sibling, Algs. 1-3;
+ * Tree, Algs. 4-8; or plain input order), planned under a device-memory
+ * budget with next-use eviction and host re-upload, and executed with
+ * hand-written HIP kernels.
+ *
+ * Conventions for every entry point:
+ *   - Returns CDAG_OK (0) or a negative cdag_status; never throws.  A failed
+ *     call leaves the context usable; cdag_last_error() describes the failure
+ *     (thread-local string, valid until the next call on that thread).
+ *   - Pointers are host pointers unless named dev_*.  Output arrays are owned
+ *     by the caller; the caller passes their capacity.
+ *   - Call order: cdag_create -> build_cdag -> schedule -> [set_mem_budget]
+ *     -> [cdag_plan] -> cdag_bind_device + cdag_bind_arena -> execute ->
+ *     fetch_correlators / cdag_fetch_sums.  Out-of-order calls return
+ *     CDAG_E_STATE.  schedule, set_mem_budget, cdag_plan and execute may be
+ *     repeated; build_cdag resets everything after it.
+ *   - No entry point is thread-safe for one context; distinct contexts are
+ *     independent.
+ */
+#ifndef CDAG_H
+#define CDAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cdag_ctx cdag_ctx;
+
+enum cdag_status {
+  CDAG_OK = 0,
+  CDAG_E_INVALID = -1, /* malformed argument or graph                          */
+  CDAG_E_STATE = -2,   /* call out of order (e.g. execute before schedule)     */
+  CDAG_E_BUDGET = -3,  /* one step's operands + outputs exceed the budget      */
+  CDAG_E_HIP = -4,     /* a HIP runtime call failed                            */
+  CDAG_E_NOMEM = -5,   /* host allocation failed, or the bound arena is small  */
+  CDAG_E_RANGE = -6    /* an output capacity is too small                      */
+};
+
+/* Contraction kinds, per time slice t (row-major, contracted axes trailing on
+ * the left operand and leading on the right):
+ *   K22: O[i,j]   = sum_k  X[i,k]   Y[k,j]       meson x meson,   O(N^3)
+ *   K32: O[i,j,l] = sum_k  X[i,j,k] Y[k,l]       baryon x meson,  O(N^4)
+ *   K33: O[i,m]   = sum_jl X[i,j,l] Y[j,l,m]     baryon x baryon, O(N^4)
+ *   HCA: C        = sum_ij P[i,j]   Q[j,i]       root "contract all" (trace)
+ * (the hadron exterior contraction and contract-all operations of Sec. IV-B). */
+enum cdag_kind { CDAG_K22 = 0, CDAG_K32 = 1, CDAG_K33 = 2, CDAG_HCA = 3 };
+
+/* Schedulers: input order (each graph's tree in post-order, left first),
+ * Sibling (Sec. III-A, Algs. 1-3), Tree (Sec. III-B, Algs. 4-8). */
+enum cdag_policy { CDAG_SCHED_INPUT = 0, CDAG_SCHED_SIBLING = 1, CDAG_SCHED_TREE = 2 };
+/* OR into policy for Tree: at every selection recompute every live tree's
+ * gain M - M' from scratch and fail with CDAG_E_STATE if an incrementally
+ * maintained tgain differs (slow; a self-check). */
+#define CDAG_SCHED_CHECK 0x100
+
+/* Arithmetic of the exterior contractions.  FP64: complex128 storage and
+ * arithmetic.  FP32 and BF16X3: complex64 storage, products on the matrix
+ * cores with FP32 accumulation (BF16X3 splits each FP32 operand into a bf16
+ * hi + lo pair and keeps three of the four products).  Traces and the
+ * cross-diagram sums are FP64 in every mode. */
+enum cdag_prec { CDAG_FP64 = 0, CDAG_FP32 = 1, CDAG_BF16X3 = 2 };
+
+/* Plan op records (cdag_plan_ops). */
+enum cdag_plan_op { CDAG_OP_D2H = 0, CDAG_OP_DROP = 1, CDAG_OP_H2D = 2,
+                    CDAG_OP_ALLOC = 3, CDAG_OP_EXEC = 4, CDAG_OP_FREE = 5 };
+
+/* A leaf tensor (hadron node): complex, shape [nt][nvec]^rank, rank 2 (meson)
+ * or 3 (baryon).  host: interleaved complex128 (re, im) in row-major order,
+ * read only during build_cdag (the library keeps its own copy); may be NULL
+ * for a structure-only context (scheduling and planning work; execute then
+ * fails with CDAG_E_STATE). */
+typedef struct {
+  int32_t rank, nvec, nt, reserved;
+  const double* host;
+} cdag_leaf;
+
+/* One binary contraction inside a graph.  Operand >= 0: a leaf id; operand
+ * < 0: -(1 + index of an earlier op of the same graph). */
+typedef struct {
+  int32_t kind, left, right;
+} cdag_op;
+
+/* One graph (contraction tree, Sec. II-B): its last op is the root and must be
+ * CDAG_HCA; every other op is used exactly once by a later op.  Its correlator
+ * contributes w * C_g(t) to the cross-diagram sum of correlator corr_id. */
+typedef struct {
+  int32_t n_ops, corr_id;
+  const cdag_op* ops;
+  double w_re, w_im;
+} cdag_graph;
+
+typedef struct {
+  int64_t n_nodes, n_leaves, n_contr, n_roots, n_steps;
+  int64_t peak_post;     /* max_i M_i of Sec. II-C for the current schedule      */
+  int64_t peak_live;     /* max resident bytes while one contraction runs        */
+  int64_t peak_resident; /* max resident bytes of the budgeted plan              */
+  int64_t n_evict, n_h2d, h2d_bytes, n_d2h, d2h_bytes;
+  int64_t budget;        /* bytes the plan was made for (INT64_MAX: unlimited)   */
+  int64_t arena_bytes;   /* device bytes cdag_bind_arena must provide            */
+  int64_t tensor_highwater; /* physical high-water of the tensor pool           */
+  int64_t host_spill_bytes; /* pinned host bytes for spilled intermediates      */
+  double flops;          /* algorithmic flops, 8 per complex multiply-add        */
+  double t_sched_s, t_plan_s;
+} cdag_plan_stats;
+
+typedef struct {
+  cdag_plan_stats plan;
+  double t_total_s;   /* execute(): first enqueue to results on the host      */
+  double t_device_s;  /* compute stream, first kernel to last (HIP events)    */
+  double t_hec_s;     /* summed exterior-contraction kernel time (timing on)  */
+  double hec_flops;   /* algorithmic flops of the exterior contractions       */
+  double hec_bytes;   /* algorithmic bytes: each operand read once, output written once */
+  int64_t n_launches;
+  int64_t n_hec_launches;
+  int64_t n_graph_segments;
+} cdag_exec_stats;
+
+int cdag_create(cdag_ctx** out);
+int cdag_destroy(cdag_ctx* c);
+const char* cdag_last_error(void);
+
+/* Merge graphs into the DAG (hash-consing identical (kind, left, right)
+ * contractions; identical graphs share their root).  Node ids: leaves
+ * 0..n_leaves-1, then contractions in order of first appearance.
+ * CDAG_E_INVALID: bad shape, rank, N or Nt mismatch, operand out of range or
+ * forward, identical operands, root not HCA or HCA not last, unused op. */
+int build_cdag(cdag_ctx* c, const cdag_leaf* leaves, int64_t n_leaves,
+               const cdag_graph* graphs, int64_t n_graphs);
+
+/* Order the contractions.  order_out (nullable, capacity cap) receives node
+ * ids; *n_out (nullable) the number of contractions. */
+int schedule(cdag_ctx* c, int policy, int64_t* order_out, int64_t cap, int64_t* n_out);
+
+/* Device-memory budget in bytes for planning (UINT64_MAX: unlimited, the
+ * default). */
+int set_mem_budget(cdag_ctx* c, uint64_t bytes);
+
+/* leaves_resident: 1 keeps every leaf in a device region of its own, outside
+ * the budget, uploaded once per precision (never evicted); 0 (default) makes
+ * leaves start on the host as in Sec. II-C.  wave_max: most contractions per
+ * wave in batched mode (default 4096).  use_graphs: 1 (default) replays the
+ * step sequence from captured HIP graphs. */
+int cdag_set_options(cdag_ctx* c, int leaves_resident, int wave_max, int use_graphs);
+
+/* timing: 1 records a HIP event pair around every exterior-contraction launch
+ * on the compute stream and reports their summed duration in t_hec_s
+ * (execution then runs without graph replay); 0 (default) turns it off. */
+int cdag_set_timing(cdag_ctx* c, int timing);
+
+/* Host-only: simulate Sec. II-C for `order` (n node ids, each contraction
+ * once, topological) with element size elem_bytes (16 or 8).  M_out
+ * (nullable, capacity n) receives M_1..M_n. */
+int cdag_memsim(cdag_ctx* c, const int64_t* order, int64_t n, int elem_bytes,
+                int64_t* M_out, int64_t* peak_post, int64_t* peak_live);
+
+/* Host-only: build the budgeted plan for (prec, batched) on the current
+ * schedule and budget.  CDAG_E_BUDGET if one step cannot fit. */
+int cdag_plan(cdag_ctx* c, int prec, int batched, cdag_plan_stats* out);
+
+/* The last plan's op list: op[i] in cdag_plan_op, node[i], step[i]. */
+int cdag_plan_ops(cdag_ctx* c, int32_t* op, int64_t* node, int64_t* step, int64_t cap,
+                  int64_t* n_out);
+
+/* Introspection of the merged DAG: per node kind (-1 leaf), left, right
+ * (-1 for leaves); per input graph its root node id. */
+int cdag_get_nodes(cdag_ctx* c, int32_t* kind, int64_t* left, int64_t* right, int64_t cap,
+                   int64_t* n_out);
+int cdag_graph_roots(cdag_ctx* c, int64_t* root_of_graph, int64_t cap);
+
+/* Device binding.  device: HIP ordinal.  compute_stream, copy_stream:
+ * hipStream_t handles borrowed for the context's lifetime (copies run on the
+ * second; both must be non-NULL and distinct).  The arena is device memory of
+ * at least plan.arena_bytes bytes, 256-byte aligned, borrowed until rebound
+ * or the context is destroyed. */
+int cdag_bind_device(cdag_ctx* c, int device, void* compute_stream, void* copy_stream);
+int cdag_bind_arena(cdag_ctx* c, void* dev_arena, uint64_t bytes);
+
+/* Plan (as cdag_plan) and run the whole DAG: uploads, evictions, exterior
+ * contractions, traces, the cross-diagram sums and the copy of the results
+ * to the host.  Blocks until the results are on the host. */
+int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
+
+/* Per input graph g, C_g(t) for t < nt(g), as (re, im) doubles, graphs in
+ * input order, concatenated: 2 * sum_g nt(g) doubles. */
+int fetch_correlators(cdag_ctx* c, double* out, int64_t cap_doubles);
+
+/* Per correlator c = 0..max(corr_id), S_c(t) = sum_{g: corr_id = c} w_g C_g(t)
+ * summed in FP64 in ascending g; 2 * sum_c nt(c) doubles (nt of a correlator
+ * with no graph is 0). */
+int cdag_fetch_sums(cdag_ctx* c, double* out, int64_t cap_doubles);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDAG_H */

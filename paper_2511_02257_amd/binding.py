@@ -1,0 +1,341 @@
+"""ctypes binding of libcdagx.so (include/cdag.h): argument marshalling only.
+
+Module-level functions carry the C ABI's names; `Context` wraps one cdag_ctx.
+Every call raises CdagError on a non-zero status.  The library must have been
+built (paper_2511_02257_amd/build.py); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcdagx.so")
+
+OK, E_INVALID, E_STATE, E_BUDGET, E_HIP, E_NOMEM, E_RANGE = 0, -1, -2, -3, -4, -5, -6
+K22, K32, K33, HCA = 0, 1, 2, 3
+POLICY = {"input": 0, "sibling": 1, "tree": 2}
+SCHED_CHECK = 0x100
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+OP_NAMES = {0: "D2H", 1: "DROP", 2: "H2D", 3: "ALLOC", 4: "EXEC", 5: "FREE"}
+UNLIMITED = (1 << 64) - 1
+
+
+class CdagError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cdag error {code}: {msg}")
+        self.code = code
+
+
+class cdag_leaf(C.Structure):
+    _fields_ = [("rank", C.c_int32), ("nvec", C.c_int32), ("nt", C.c_int32),
+                ("reserved", C.c_int32), ("host", C.POINTER(C.c_double))]
+
+
+class cdag_op(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("left", C.c_int32), ("right", C.c_int32)]
+
+
+class cdag_graph(C.Structure):
+    _fields_ = [("n_ops", C.c_int32), ("corr_id", C.c_int32), ("ops", C.POINTER(cdag_op)),
+                ("w_re", C.c_double), ("w_im", C.c_double)]
+
+
+_PLAN_INT = ["n_nodes", "n_leaves", "n_contr", "n_roots", "n_steps", "peak_post", "peak_live",
+             "peak_resident", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes", "budget",
+             "arena_bytes", "tensor_highwater", "host_spill_bytes"]
+_PLAN_DBL = ["flops", "t_sched_s", "t_plan_s"]
+
+
+class cdag_plan_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in _PLAN_INT] + [(n, C.c_double) for n in _PLAN_DBL]
+
+
+class cdag_exec_stats(C.Structure):
+    _fields_ = [("plan", cdag_plan_stats), ("t_total_s", C.c_double), ("t_device_s", C.c_double),
+                ("t_hec_s", C.c_double), ("hec_flops", C.c_double), ("hec_bytes", C.c_double),
+                ("n_launches", C.c_int64), ("n_hec_launches", C.c_int64),
+                ("n_graph_segments", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2511_02257_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, I64, I32 = C.c_void_p, C.c_int64, C.c_int32
+        sig = {
+            "cdag_create": [C.POINTER(C.c_void_p)],
+            "cdag_destroy": [P],
+            "build_cdag": [P, C.POINTER(cdag_leaf), I64, C.POINTER(cdag_graph), I64],
+            "schedule": [P, C.c_int, C.POINTER(I64), I64, C.POINTER(I64)],
+            "set_mem_budget": [P, C.c_uint64],
+            "cdag_set_options": [P, C.c_int, C.c_int, C.c_int],
+            "cdag_set_timing": [P, C.c_int],
+            "cdag_memsim": [P, C.POINTER(I64), I64, C.c_int, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
+            "cdag_plan": [P, C.c_int, C.c_int, C.POINTER(cdag_plan_stats)],
+            "cdag_plan_ops": [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64), I64, C.POINTER(I64)],
+            "cdag_get_nodes": [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64), I64, C.POINTER(I64)],
+            "cdag_graph_roots": [P, C.POINTER(I64), I64],
+            "cdag_bind_device": [P, C.c_int, P, P],
+            "cdag_bind_arena": [P, P, C.c_uint64],
+            "execute": [P, C.c_int, C.c_int, C.POINTER(cdag_exec_stats)],
+            "fetch_correlators": [P, C.POINTER(C.c_double), I64],
+            "cdag_fetch_sums": [P, C.POINTER(C.c_double), I64],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.cdag_last_error.argtypes = []
+        L.cdag_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "schedule",
+            "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_memsim", "cdag_plan", "cdag_plan_ops",
+            "cdag_get_nodes", "cdag_graph_roots", "cdag_bind_device", "cdag_bind_arena",
+            "execute", "fetch_correlators", "cdag_fetch_sums")
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise CdagError(rc, lib().cdag_last_error().decode(errors="replace"))
+
+
+def _i64p(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _struct_dict(s) -> dict:
+    out = {}
+    for name, _ in s._fields_:
+        v = getattr(s, name)
+        out[name] = _struct_dict(v) if isinstance(v, C.Structure) else v
+    return out
+
+
+# ------------------------------------------------------------------ functions with the C names
+def cdag_create() -> C.c_void_p:
+    h = C.c_void_p()
+    _check(lib().cdag_create(C.byref(h)))
+    return h
+
+
+def cdag_destroy(h) -> None:
+    _check(lib().cdag_destroy(h))
+
+
+def build_cdag(h, leaves: Sequence, graphs: Sequence) -> None:
+    """leaves: objects with rank, nvec, nt and data (complex128 [nt]+[nvec]*rank, or None);
+    graphs: objects with ops [(kind, left, right)], corr and w."""
+    n = len(leaves)
+    L = (cdag_leaf * max(1, n))()
+    keep = []
+    for i, lf in enumerate(leaves):
+        L[i].rank, L[i].nvec, L[i].nt = lf.rank, lf.nvec, lf.nt
+        if getattr(lf, "data", None) is not None:
+            a = np.ascontiguousarray(lf.data, dtype=np.complex128)
+            if a.size != lf.nt * lf.nvec ** lf.rank:
+                raise ValueError(f"leaf {i}: data has {a.size} elements")
+            keep.append(a)
+            L[i].host = a.ctypes.data_as(C.POINTER(C.c_double))
+        else:
+            L[i].host = None
+    G = (cdag_graph * max(1, len(graphs)))()
+    for g, spec in enumerate(graphs):
+        ops = (cdag_op * len(spec.ops))(*[cdag_op(k, l, r) for k, l, r in spec.ops])
+        keep.append(ops)
+        w = complex(getattr(spec, "w", 1.0))
+        G[g].n_ops, G[g].corr_id, G[g].ops = len(spec.ops), int(getattr(spec, "corr", 0)), ops
+        G[g].w_re, G[g].w_im = w.real, w.imag
+    _check(lib().build_cdag(h, L, n, G, len(graphs)))
+    del keep
+
+
+def schedule(h, policy: str, check: bool = False) -> np.ndarray:
+    p = POLICY[policy] | (SCHED_CHECK if check else 0)
+    n = C.c_int64()
+    _check(lib().schedule(h, p, None, 0, C.byref(n)))
+    out = np.empty(n.value, dtype=np.int64)
+    _check(lib().schedule(h, p, _i64p(out), out.size, None))
+    return out
+
+
+def set_mem_budget(h, nbytes: Optional[int]) -> None:
+    _check(lib().set_mem_budget(h, UNLIMITED if nbytes is None else int(nbytes)))
+
+
+def cdag_set_options(h, leaves_resident=False, wave_max=4096, use_graphs=True) -> None:
+    _check(lib().cdag_set_options(h, int(leaves_resident), int(wave_max), int(use_graphs)))
+
+
+def cdag_set_timing(h, on: bool) -> None:
+    _check(lib().cdag_set_timing(h, int(bool(on))))
+
+
+def cdag_memsim(h, order: Sequence[int], elem_bytes: int = 16):
+    o = np.ascontiguousarray(order, dtype=np.int64)
+    M = np.empty(max(1, o.size), dtype=np.int64)
+    pp, pl = C.c_int64(), C.c_int64()
+    _check(lib().cdag_memsim(h, _i64p(o), o.size, elem_bytes, _i64p(M), C.byref(pp), C.byref(pl)))
+    return M[:o.size], pp.value, pl.value
+
+
+def cdag_plan(h, prec: str = "fp64", batched: bool = False) -> dict:
+    st = cdag_plan_stats()
+    _check(lib().cdag_plan(h, PREC[prec], int(batched), C.byref(st)))
+    return _struct_dict(st)
+
+
+def cdag_plan_ops(h) -> List[tuple]:
+    n = C.c_int64()
+    _check(lib().cdag_plan_ops(h, None, None, None, 0, C.byref(n)))
+    op = np.empty(n.value, dtype=np.int32)
+    node = np.empty(n.value, dtype=np.int64)
+    step = np.empty(n.value, dtype=np.int64)
+    _check(lib().cdag_plan_ops(h, op.ctypes.data_as(C.POINTER(C.c_int32)), _i64p(node), _i64p(step),
+                               n.value, None))
+    return [(OP_NAMES[int(a)], int(b), int(c)) for a, b, c in zip(op, node, step)]
+
+
+def cdag_get_nodes(h):
+    n = C.c_int64()
+    _check(lib().cdag_get_nodes(h, None, None, None, 0, C.byref(n)))
+    kind = np.empty(n.value, dtype=np.int32)
+    left = np.empty(n.value, dtype=np.int64)
+    right = np.empty(n.value, dtype=np.int64)
+    _check(lib().cdag_get_nodes(h, kind.ctypes.data_as(C.POINTER(C.c_int32)), _i64p(left), _i64p(right),
+                                n.value, None))
+    return kind, left, right
+
+
+def cdag_graph_roots(h, n_graphs: int) -> np.ndarray:
+    out = np.empty(max(1, n_graphs), dtype=np.int64)
+    _check(lib().cdag_graph_roots(h, _i64p(out), n_graphs))
+    return out[:n_graphs]
+
+
+def cdag_bind_device(h, device: int, compute_stream: int, copy_stream: int) -> None:
+    _check(lib().cdag_bind_device(h, device, C.c_void_p(compute_stream), C.c_void_p(copy_stream)))
+
+
+def cdag_bind_arena(h, ptr: int, nbytes: int) -> None:
+    _check(lib().cdag_bind_arena(h, C.c_void_p(ptr), nbytes))
+
+
+def execute(h, prec: str = "fp64", batched: bool = False) -> dict:
+    st = cdag_exec_stats()
+    _check(lib().execute(h, PREC[prec], int(batched), C.byref(st)))
+    return _struct_dict(st)
+
+
+def fetch_correlators(h, nts: Sequence[int]) -> List[np.ndarray]:
+    """Per input graph, complex128 [nt(g)]; nts: Nt of each graph in input order."""
+    total = 2 * int(sum(nts))
+    buf = np.empty(max(1, total), dtype=np.float64)
+    _check(lib().fetch_correlators(h, buf.ctypes.data_as(C.POINTER(C.c_double)), total))
+    out, o = [], 0
+    for nt in nts:
+        v = buf[o:o + 2 * nt]
+        out.append(v[0::2] + 1j * v[1::2])
+        o += 2 * nt
+    return out
+
+
+def cdag_fetch_sums(h, nts: Sequence[int]) -> List[np.ndarray]:
+    total = 2 * int(sum(nts))
+    buf = np.empty(max(1, total), dtype=np.float64)
+    _check(lib().cdag_fetch_sums(h, buf.ctypes.data_as(C.POINTER(C.c_double)), total))
+    out, o = [], 0
+    for nt in nts:
+        v = buf[o:o + 2 * nt]
+        out.append(v[0::2] + 1j * v[1::2])
+        o += 2 * nt
+    return out
+
+
+# ------------------------------------------------------------------ object wrapper
+class Context:
+    """One engine context; methods keep the C ABI's names."""
+
+    def __init__(self):
+        self.h = cdag_create()
+        self.graph_nt: List[int] = []
+        self.corr_nt: List[int] = []
+        self.n_graphs = 0
+
+    def close(self):
+        if self.h is not None:
+            cdag_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_cdag(self, leaves, graphs):
+        build_cdag(self.h, leaves, graphs)
+        nt_of = []
+        for spec in graphs:
+            first = next(x for _, l, r in spec.ops for x in (l, r) if x >= 0)
+            nt_of.append(leaves[first].nt)
+        self.graph_nt = nt_of
+        n_corr = 1 + max((int(getattr(s, "corr", 0)) for s in graphs), default=-1)
+        self.corr_nt = [0] * n_corr
+        for spec, nt in zip(graphs, nt_of):
+            self.corr_nt[int(getattr(spec, "corr", 0))] = nt
+        self.n_graphs = len(graphs)
+
+    def schedule(self, policy, check=False):
+        return schedule(self.h, policy, check)
+
+    def set_mem_budget(self, nbytes):
+        set_mem_budget(self.h, nbytes)
+
+    def set_options(self, leaves_resident=False, wave_max=4096, use_graphs=True):
+        cdag_set_options(self.h, leaves_resident, wave_max, use_graphs)
+
+    def set_timing(self, on=True):
+        cdag_set_timing(self.h, on)
+
+    def memsim(self, order, elem_bytes=16):
+        return cdag_memsim(self.h, order, elem_bytes)
+
+    def plan(self, prec="fp64", batched=False) -> Dict:
+        return cdag_plan(self.h, prec, batched)
+
+    def plan_ops(self):
+        return cdag_plan_ops(self.h)
+
+    def nodes(self):
+        return cdag_get_nodes(self.h)
+
+    def graph_roots(self):
+        return cdag_graph_roots(self.h, self.n_graphs)
+
+    def bind_device(self, device, compute_stream, copy_stream):
+        cdag_bind_device(self.h, device, compute_stream, copy_stream)
+
+    def bind_arena(self, ptr, nbytes):
+        cdag_bind_arena(self.h, ptr, nbytes)
+
+    def execute(self, prec="fp64", batched=False):
+        return execute(self.h, prec, batched)
+
+    def fetch_correlators(self):
+        return fetch_correlators(self.h, self.graph_nt)
+
+    def fetch_sums(self):
+        return cdag_fetch_sums(self.h, self.corr_nt)

@@ -1,0 +1,59 @@
+// Library context shared by the C ABI (capi.cpp) and the device runtime
+// (runtime/executor.hip).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "host/host.hpp"
+#include "host/kplan.hpp"
+#include "../../include/cdag.h"
+
+namespace cdag {
+
+struct Device;   // device-side state, defined in runtime/executor.hip
+
+struct Ctx {
+  // build
+  bool built = false;
+  Dag dag;
+  bool has_data = false;
+  std::vector<std::vector<double>> leaf_data;   // interleaved complex128 copies
+  int32_t n_corr = 0;
+  uint64_t data_version = 0;     // bumped by build_cdag (leaf data changed)
+  // schedule
+  bool scheduled = false;
+  std::vector<int64_t> order;
+  double t_sched = 0;
+  // options
+  int64_t budget = INT64_MAX;
+  bool leaves_resident = false;
+  int64_t wave_max = 4096;
+  bool use_graphs = true;
+  bool timing = false;
+  uint64_t version = 1;          // bumped by every change that invalidates a plan
+  // last plan
+  bool planned = false;
+  uint64_t plan_version = 0;
+  uint64_t plan_serial = 0;      // bumped each time a plan is (re)built
+  int plan_prec = -1, plan_batched = -1;
+  Plan plan;
+  KernelPlan kplan;
+  int64_t peak_post = 0, peak_live = 0;
+  double t_plan = 0;
+  // device
+  Device* dev = nullptr;
+  // results of the last execute
+  bool have_results = false;
+  std::vector<double> corr_host, sums_host;   // corr buffer (per tree), sums buffer
+};
+
+// Plans for (prec, batched) unless the cached plan already matches.
+void ensure_plan(Ctx& c, int prec, int batched);
+
+void device_destroy(Device* d);
+void device_bind(Ctx& c, int device, void* compute_stream, void* copy_stream);
+void device_bind_arena(Ctx& c, void* arena, uint64_t bytes);
+void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st);
+
+}  // namespace cdag

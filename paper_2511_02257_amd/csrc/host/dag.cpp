@@ -1,0 +1,167 @@
+// CDAG formation (Sec. II-B): merge binary contraction trees into one DAG by
+// hash-consing structurally identical contractions.
+#include <algorithm>
+#include <unordered_map>
+
+#include "host.hpp"
+#include "../../../include/cdag.h"
+
+namespace cdag {
+
+namespace {
+struct KeyHash {
+  size_t operator()(const std::tuple<int32_t, int64_t, int64_t>& k) const {
+    uint64_t h = (uint64_t)std::get<0>(k) * 0x9E3779B97F4A7C15ull;
+    h ^= (uint64_t)std::get<1>(k) + 0x632BE59BD9B4E019ull + (h << 6) + (h >> 2);
+    h ^= (uint64_t)std::get<2>(k) + 0x8CB92BA72F3D8DD7ull + (h << 6) + (h >> 2);
+    return (size_t)h;
+  }
+};
+
+// (left rank, right rank, output rank) per kind.
+bool kind_ranks(int32_t kind, int& rl, int& rr, int& ro) {
+  switch (kind) {
+    case K22: rl = 2; rr = 2; ro = 2; return true;
+    case K32: rl = 3; rr = 2; ro = 3; return true;
+    case K33: rl = 3; rr = 3; ro = 2; return true;
+    case HCA: rl = 2; rr = 2; ro = 0; return true;
+    default: return false;
+  }
+}
+
+[[noreturn]] void invalid(const std::string& m) { throw Error(CDAG_E_INVALID, m); }
+}  // namespace
+
+bool Dag::in_tree(int64_t u, int64_t t) const {
+  return std::binary_search(ctree.begin() + ctree_off[u], ctree.begin() + ctree_off[u + 1], t);
+}
+
+double Dag::flops(int64_t u) const {
+  const double n = nvec[u], T = nt[u];
+  switch (kind[u]) {
+    case K22: return 8.0 * T * n * n * n;
+    case K32: return 8.0 * T * n * n * n * n;
+    case K33: return 8.0 * T * n * n * n * n;
+    case HCA: return 8.0 * T * n * n;
+    default: return 0.0;
+  }
+}
+
+Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs) {
+  Dag d;
+  d.n_leaves = (int64_t)leaves.size();
+  for (const auto& l : leaves) {
+    if ((l.rank != 2 && l.rank != 3) || l.nvec < 1 || l.nt < 1) invalid("leaf: rank must be 2 or 3, nvec and nt >= 1");
+    d.kind.push_back(LEAF);
+    d.rank.push_back(l.rank);
+    d.nvec.push_back(l.nvec);
+    d.nt.push_back(l.nt);
+    d.left.push_back(-1);
+    d.right.push_back(-1);
+  }
+  std::unordered_map<std::tuple<int32_t, int64_t, int64_t>, int64_t, KeyHash> table;
+  std::vector<int64_t> local, consumed;
+  std::vector<char> root_seen;
+  for (size_t gi = 0; gi < graphs.size(); ++gi) {
+    const GraphIn& g = graphs[gi];
+    if (g.n_ops < 1 || !g.ops) invalid("graph " + std::to_string(gi) + ": no ops");
+    if (g.corr < 0) invalid("graph " + std::to_string(gi) + ": negative corr_id");
+    local.assign(g.n_ops, -1);
+    consumed.assign(g.n_ops, 0);
+    for (int32_t oi = 0; oi < g.n_ops; ++oi) {
+      const OpIn& op = g.ops[oi];
+      int rl, rr, ro;
+      std::string where = "graph " + std::to_string(gi) + " op " + std::to_string(oi) + ": ";
+      if (!kind_ranks(op.kind, rl, rr, ro)) invalid(where + "unknown kind");
+      if ((op.kind == HCA) != (oi == g.n_ops - 1)) invalid(where + "the root, and only the root, must be HCA");
+      int64_t ids[2];
+      const int32_t xs[2] = {op.left, op.right};
+      for (int s = 0; s < 2; ++s) {
+        int32_t x = xs[s];
+        if (x >= 0) {
+          if (x >= d.n_leaves) invalid(where + "leaf id out of range");
+          ids[s] = x;
+        } else {
+          int64_t j = -(int64_t)x - 1;
+          if (j >= oi) invalid(where + "forward or self reference");
+          consumed[j] += 1;
+          ids[s] = local[j];
+        }
+      }
+      if (ids[0] == ids[1]) invalid(where + "identical operands");
+      if (d.rank[ids[0]] != rl || d.rank[ids[1]] != rr) invalid(where + "operand rank mismatch");
+      if (d.nvec[ids[0]] != d.nvec[ids[1]] || d.nt[ids[0]] != d.nt[ids[1]])
+        invalid(where + "operand N or Nt mismatch");
+      auto key = std::make_tuple(op.kind, ids[0], ids[1]);
+      auto it = table.find(key);
+      int64_t u;
+      if (it == table.end()) {
+        u = d.n_nodes();
+        table.emplace(key, u);
+        d.kind.push_back(op.kind);
+        d.rank.push_back(ro);
+        d.nvec.push_back(d.nvec[ids[0]]);
+        d.nt.push_back(d.nt[ids[0]]);
+        d.left.push_back(ids[0]);
+        d.right.push_back(ids[1]);
+      } else {
+        u = it->second;
+      }
+      local[oi] = u;
+    }
+    for (int32_t oi = 0; oi + 1 < g.n_ops; ++oi)
+      if (consumed[oi] != 1)
+        invalid("graph " + std::to_string(gi) + ": every non-root op must be used exactly once");
+    int64_t root = local[g.n_ops - 1];
+    d.root_of_graph.push_back(root);
+    d.corr.push_back(g.corr);
+    d.w_re.push_back(g.w_re);
+    d.w_im.push_back(g.w_im);
+    if ((int64_t)root_seen.size() < d.n_nodes()) root_seen.resize(d.n_nodes(), 0);
+    if (!root_seen[root]) {
+      root_seen[root] = 1;
+      d.tree_root.push_back(root);
+    }
+  }
+  const int64_t n = d.n_nodes();
+  // parents in edge-creation order: node by node, left edge then right edge
+  std::vector<int64_t> cnt(n + 1, 0);
+  for (int64_t u = d.n_leaves; u < n; ++u) { cnt[d.left[u]]++; cnt[d.right[u]]++; }
+  d.par_off.assign(n + 1, 0);
+  for (int64_t u = 0; u < n; ++u) d.par_off[u + 1] = d.par_off[u] + cnt[u];
+  d.par.assign(d.par_off[n], -1);
+  std::vector<int64_t> fill(d.par_off.begin(), d.par_off.end() - 1);
+  for (int64_t u = d.n_leaves; u < n; ++u) {
+    d.par[fill[d.left[u]]++] = u;
+    d.par[fill[d.right[u]]++] = u;
+  }
+  // tree node sets: post-order DFS from each unique root, left first
+  const int64_t k = (int64_t)d.tree_root.size();
+  d.tree_off.assign(1, 0);
+  std::vector<int64_t> mark(n, -1), stack;
+  std::vector<std::vector<int64_t>> ct(n);
+  for (int64_t t = 0; t < k; ++t) {
+    // iterative post-order: (node, state) pairs, state 0 = expand, 1 = emit
+    std::vector<std::pair<int64_t, int>> st{{d.tree_root[t], 0}};
+    while (!st.empty()) {
+      auto [u, s] = st.back();
+      st.pop_back();
+      if (s == 1) { d.tree_nodes.push_back(u); ct[u].push_back(t); continue; }
+      if (mark[u] == t) continue;
+      mark[u] = t;
+      st.push_back({u, 1});
+      if (!d.is_leaf(u)) {
+        st.push_back({d.right[u], 0});
+        st.push_back({d.left[u], 0});
+      }
+    }
+    d.tree_off.push_back((int64_t)d.tree_nodes.size());
+  }
+  d.ctree_off.assign(n + 1, 0);
+  for (int64_t u = 0; u < n; ++u) d.ctree_off[u + 1] = d.ctree_off[u] + (int64_t)ct[u].size();
+  d.ctree.reserve(d.ctree_off[n]);
+  for (int64_t u = 0; u < n; ++u) d.ctree.insert(d.ctree.end(), ct[u].begin(), ct[u].end());
+  return d;
+}
+
+}  // namespace cdag

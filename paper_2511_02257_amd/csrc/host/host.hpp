@@ -1,0 +1,113 @@
+// Host-side contraction-DAG data structures: the merged DAG (Sec. II-B), the
+// schedulers (Sec. III), the memory model (Sec. II-C) and the budgeted plan.
+// Pure C++17; no GPU calls.
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace cdag {
+
+enum Kind : int32_t { K22 = 0, K32 = 1, K33 = 2, HCA = 3, LEAF = -1 };
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// Structure-of-arrays DAG.  Ids: leaves 0..n_leaves-1, then contractions in
+// order of first appearance, so every child id is smaller than its parent's.
+struct Dag {
+  int64_t n_leaves = 0;
+  std::vector<int32_t> kind, rank, nvec, nt;
+  std::vector<int64_t> left, right;
+  std::vector<int64_t> par_off, par;        // CSR parents, one entry per edge, in creation order
+  std::vector<int64_t> root_of_graph;       // per input graph
+  std::vector<int64_t> tree_root;           // unique roots, first-appearance order
+  std::vector<int64_t> tree_off, tree_nodes;  // per tree: node set in post-order (left first)
+  std::vector<int64_t> ctree_off, ctree;    // per node: ascending tree indices containing it
+  // per input graph: correlator id and weight
+  std::vector<int32_t> corr;
+  std::vector<double> w_re, w_im;
+
+  int64_t n_nodes() const { return (int64_t)kind.size(); }
+  bool is_leaf(int64_t u) const { return kind[u] < 0; }
+  int64_t n_parents(int64_t u) const { return par_off[u + 1] - par_off[u]; }
+  int64_t elems(int64_t u) const {
+    int64_t e = nt[u];
+    for (int r = 0; r < rank[u]; ++r) e *= nvec[u];
+    return e;
+  }
+  // Bytes of u's tensor in a mode with elem_bytes per complex element; a root's
+  // per-t scalar goes straight into the correlator buffer and counts 0.
+  int64_t size(int64_t u, int elem_bytes) const { return kind[u] == HCA ? 0 : elems(u) * elem_bytes; }
+  bool in_tree(int64_t u, int64_t t) const;   // binary search in ctree(u)
+  // Algorithmic flops of contraction u (8 per complex multiply-add).
+  double flops(int64_t u) const;
+};
+
+struct LeafIn { int32_t rank, nvec, nt; };
+struct OpIn { int32_t kind, left, right; };
+struct GraphIn { int32_t n_ops, corr; const OpIn* ops; double w_re, w_im; };
+
+Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs);
+
+std::vector<int64_t> sched_input(const Dag& d);
+std::vector<int64_t> sched_sibling(const Dag& d);
+// Tree scheduler; sizes in bytes of elem_bytes per element.  check=true
+// recomputes each live tree's gain from scratch at every selection and throws
+// Error(CDAG_E_STATE) on a mismatch with the incremental tgain.
+std::vector<int64_t> sched_tree(const Dag& d, int elem_bytes, bool check);
+
+struct MemSim { std::vector<int64_t> M; int64_t peak_post = 0, peak_live = 0; };
+MemSim memsim(const Dag& d, const std::vector<int64_t>& order, int elem_bytes);
+
+// ---------------------------------------------------------------- plan
+enum PlanOp : int32_t { OP_D2H = 0, OP_DROP = 1, OP_H2D = 2, OP_ALLOC = 3, OP_EXEC = 4, OP_FREE = 5 };
+
+struct PlanRec {
+  int32_t op;
+  int64_t node, step;
+  // physical placement (filled by place()): arena offset of the tensor's
+  // allocation for H2D/ALLOC; host spill offset for D2H/H2D of intermediates.
+  int64_t dev_off = -1, host_off = -1;
+  // EXEC: arena offsets of the left and right operands (dev_off: the output).
+  int64_t a_off = -1, b_off = -1;
+  // synchronisation: before this op's copy (H2D) the copy stream waits for the
+  // compute work of step wait_comp; before an ALLOC's producing kernel the
+  // compute stream waits for the copy work of step wait_copy (-1: none).
+  int64_t wait_comp = -1, wait_copy = -1;
+};
+
+struct PlanOpts {
+  int elem_bytes = 16;
+  int64_t budget = INT64_MAX;
+  bool batched = false;
+  int64_t wave_max = 4096;
+  bool leaves_resident = false;
+};
+
+struct Plan {
+  PlanOpts opts;
+  std::vector<std::vector<int64_t>> steps;  // contractions per step
+  std::vector<PlanRec> recs;
+  std::vector<int64_t> rec_off;             // per step: first record index
+  int64_t peak_resident = 0, n_evict = 0, n_h2d = 0, h2d_bytes = 0, n_d2h = 0, d2h_bytes = 0;
+  // placement
+  int64_t pool_bytes = 0;                   // physical high-water of the tensor pool
+  int64_t host_spill_bytes = 0;
+  std::vector<int64_t> leaf_off;            // leaves_resident: offsets in the leaf region
+  int64_t leaf_region_bytes = 0;
+};
+
+std::vector<std::vector<int64_t>> cut_waves(const Dag& d, const std::vector<int64_t>& order,
+                                            const std::vector<int64_t>& size, int64_t budget,
+                                            int64_t wave_max);
+Plan make_plan(const Dag& d, const std::vector<int64_t>& order, const PlanOpts& o);
+// Assign arena offsets (256-byte aligned, best fit) and host spill offsets,
+// and derive the cross-stream waits.
+void place(const Dag& d, Plan& p);
+
+}  // namespace cdag

@@ -1,0 +1,209 @@
+// Launch planning (see kplan.hpp).
+#include "kplan.hpp"
+
+#include <algorithm>
+#include <cstring>
+
+#include "../../../include/cdag.h"
+
+namespace cdag {
+
+namespace {
+int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
+
+template <class T>
+int64_t put(std::vector<uint8_t>& blob, const T& v) {
+  int64_t off = (int64_t)blob.size();
+  blob.resize(blob.size() + sizeof(T));
+  std::memcpy(blob.data() + off, &v, sizeof(T));
+  return off;
+}
+}  // namespace
+
+int64_t elem_bytes_of(int prec) { return prec == CDAG_FP64 ? 16 : 8; }
+
+void gemm_dims(const Dag& d, int64_t u, int32_t* M, int32_t* N, int32_t* K) {
+  const int32_t n = d.nvec[u];
+  switch (d.kind[u]) {
+    case K22: *M = n; *N = n; *K = n; break;
+    case K32: *M = n * n; *N = n; *K = n; break;
+    case K33: *M = n; *N = n; *K = n * n; break;
+    default: *M = *N = *K = 0; break;
+  }
+}
+
+KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec) {
+  KernelPlan kp;
+  kp.prec = prec;
+  const int64_t acc_bytes = prec == CDAG_FP64 ? 8 : 4;   // one real accumulator
+  const int ks = k_step(prec);
+  const int64_t S = (int64_t)p.steps.size();
+
+  // tree index of each root, correlator buffers
+  std::vector<int64_t> tree_of(d.n_nodes(), -1);
+  for (int64_t t = 0; t < (int64_t)d.tree_root.size(); ++t) tree_of[d.tree_root[t]] = t;
+  kp.tree_corr_off.resize(d.tree_root.size());
+  int64_t co = 0;
+  for (size_t t = 0; t < d.tree_root.size(); ++t) {
+    kp.tree_corr_off[t] = co;
+    co += 16LL * d.nt[d.tree_root[t]];
+  }
+  kp.corr_bytes = align256(std::max<int64_t>(co, 16));
+  int32_t n_corr = 0;
+  for (int32_t c : d.corr) n_corr = std::max(n_corr, c + 1);
+  kp.sum_nt.assign(n_corr, 0);
+  for (size_t g = 0; g < d.corr.size(); ++g) kp.sum_nt[d.corr[g]] = d.nt[d.root_of_graph[g]];
+  kp.sum_corr_off.resize(n_corr);
+  int64_t so = 0;
+  for (int32_t c = 0; c < n_corr; ++c) {
+    kp.sum_corr_off[c] = so;
+    so += 16LL * kp.sum_nt[c];
+  }
+  kp.sums_bytes = align256(std::max<int64_t>(so, 16));
+
+  // split-K decision per contraction (independent of batching, so results do
+  // not depend on how contractions are grouped into launches)
+  auto decomp = [&](int64_t u, HecDesc& h) {
+    gemm_dims(d, u, &h.M, &h.N, &h.K);
+    h.nt = d.nt[u];
+    h.tiles_m = (h.M + kTileM - 1) / kTileM;
+    h.tiles_n = (h.N + kTileN - 1) / kTileN;
+    int64_t base = (int64_t)h.nt * h.tiles_m * h.tiles_n;
+    int64_t splits = std::min<int64_t>((kSplitTarget + base - 1) / base, h.K / kMinKSplit);
+    splits = std::max<int64_t>(splits, 1);
+    int64_t kspl = (h.K + splits - 1) / splits;
+    kspl = (kspl + ks - 1) / ks * ks;
+    splits = (h.K + kspl - 1) / kspl;
+    h.splits = (int32_t)splits;
+    h.k_split = (int32_t)kspl;
+    h.tile_count = (int32_t)(base * splits);
+  };
+
+  // pass 1: workspace size (max over steps) and descriptor counts
+  for (int64_t s = 0; s < S; ++s) {
+    int64_t ws = 0;
+    for (int64_t u : p.steps[s]) {
+      if (d.kind[u] == HCA) continue;
+      HecDesc h{};
+      decomp(u, h);
+      if (h.splits > 1) ws += align256((int64_t)h.splits * h.nt * 2 * h.M * h.N * acc_bytes);
+    }
+    kp.ws_bytes = std::max(kp.ws_bytes, ws);
+  }
+  kp.tensors_end = align256(p.leaf_region_bytes + p.pool_bytes);
+  kp.ws_off = kp.tensors_end;
+
+  // pass 2: descriptors (host blob; arena offset = blob_off + host offset)
+  kp.launch_off.reserve(S + 1);
+  for (int64_t s = 0; s < S; ++s) {
+    kp.launch_off.push_back((int64_t)kp.launches.size());
+    std::vector<HecDesc> hec;
+    std::vector<RedDesc> red;
+    std::vector<HcaDesc> hca;
+    int64_t ws = kp.ws_off, tiles = 0, items = 0;
+    for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
+      const PlanRec& r = p.recs[ri];
+      if (r.op != OP_EXEC) continue;
+      const int64_t u = r.node;
+      kp.flops += d.flops(u);
+      if (d.kind[u] == HCA) {
+        HcaDesc h{};
+        h.p_off = r.a_off;
+        h.q_off = r.b_off;
+        h.out_off = -1 - kp.tree_corr_off[tree_of[u]];   // fixed up below (needs corr_off)
+        h.n = d.nvec[u];
+        h.nt = d.nt[u];
+        hca.push_back(h);
+        continue;
+      }
+      HecDesc h{};
+      decomp(u, h);
+      kp.hec_flops += d.flops(u);
+      kp.hec_bytes += (double)h.nt * ((double)h.M * h.K + (double)h.K * h.N + (double)h.M * h.N) *
+                      (double)elem_bytes_of(prec);
+      h.a_off = r.a_off;
+      h.b_off = r.b_off;
+      h.c_off = r.dev_off;
+      h.ws_off = -1;
+      h.tile_begin = (int32_t)tiles;
+      tiles += h.tile_count;
+      if (h.splits > 1) {
+        h.ws_off = ws;
+        RedDesc rd{};
+        rd.ws_off = ws;
+        rd.c_off = r.dev_off;
+        rd.mn = h.M * h.N;
+        rd.nt = h.nt;
+        rd.splits = h.splits;
+        rd.item_begin = (int32_t)items;
+        items += (2LL * rd.nt * rd.mn + 255) / 256;
+        red.push_back(rd);
+        ws += align256((int64_t)h.splits * h.nt * 2 * h.M * h.N * acc_bytes);
+      }
+      hec.push_back(h);
+    }
+    if (!hec.empty()) {
+      Launch L{L_HEC, (int32_t)hec.size(), 0, tiles, 0};
+      L.host_desc = (int64_t)kp.blob.size();
+      for (auto& h : hec) put(kp.blob, h);
+      kp.launches.push_back(L);
+    }
+    if (!red.empty()) {
+      Launch L{L_RED, (int32_t)red.size(), 0, items, 0};
+      L.host_desc = (int64_t)kp.blob.size();
+      for (auto& x : red) put(kp.blob, x);
+      kp.launches.push_back(L);
+    }
+    if (!hca.empty()) {
+      Launch L{L_HCA, (int32_t)hca.size(), 0, 0, 0};
+      for (auto& h : hca) { h.item_begin = (int32_t)L.n_items; L.n_items += h.nt; }
+      L.host_desc = (int64_t)kp.blob.size();
+      for (auto& h : hca) put(kp.blob, h);
+      kp.launches.push_back(L);
+    }
+  }
+  kp.launch_off.push_back((int64_t)kp.launches.size());
+
+  // cross-diagram sums: per correlator, entries in ascending graph order
+  std::vector<std::vector<int64_t>> by_corr(n_corr);
+  for (size_t g = 0; g < d.corr.size(); ++g) by_corr[d.corr[g]].push_back((int64_t)g);
+  std::vector<XsumDesc> xd;
+  std::vector<XsumEntry> xe;
+  for (int32_t c = 0; c < n_corr; ++c) {
+    XsumDesc x{};
+    x.out_off = kp.sum_corr_off[c];   // relative; fixed up below
+    x.e_begin = (int32_t)xe.size();
+    for (int64_t g : by_corr[c])
+      xe.push_back({kp.tree_corr_off[tree_of[d.root_of_graph[g]]], d.w_re[g], d.w_im[g]});
+    x.e_end = (int32_t)xe.size();
+    x.nt = kp.sum_nt[c];
+    xd.push_back(x);
+  }
+  while (kp.blob.size() % 16) kp.blob.push_back(0);
+  kp.xsum = {L_XSUM, (int32_t)xd.size(), 0, (int64_t)xd.size(), (int64_t)kp.blob.size()};
+  for (auto& x : xd) put(kp.blob, x);
+  const int64_t entries_host = (int64_t)kp.blob.size();
+  for (auto& e : xe) put(kp.blob, e);
+
+  // final layout and fix-ups of buffer-relative offsets
+  kp.blob_off = align256(kp.ws_off + kp.ws_bytes);
+  kp.corr_off = align256(kp.blob_off + (int64_t)kp.blob.size());
+  kp.sums_off = kp.corr_off + kp.corr_bytes;
+  kp.total_bytes = align256(kp.sums_off + kp.sums_bytes);
+  for (Launch& L : kp.launches) {
+    L.desc_off = kp.blob_off + L.host_desc;
+    if (L.type == L_HCA) {
+      auto* h = reinterpret_cast<HcaDesc*>(kp.blob.data() + L.host_desc);
+      for (int32_t i = 0; i < L.n_desc; ++i) h[i].out_off = kp.corr_off + (-1 - h[i].out_off);
+    }
+  }
+  kp.xsum.desc_off = kp.blob_off + kp.xsum.host_desc;
+  kp.xsum_entries_off = kp.blob_off + entries_host;
+  auto* x = reinterpret_cast<XsumDesc*>(kp.blob.data() + kp.xsum.host_desc);
+  for (int32_t i = 0; i < kp.xsum.n_desc; ++i) x[i].out_off += kp.sums_off;
+  auto* e = reinterpret_cast<XsumEntry*>(kp.blob.data() + entries_host);
+  for (size_t i = 0; i < xe.size(); ++i) e[i].root_off += kp.corr_off;
+  return kp;
+}
+
+}  // namespace cdag

@@ -1,0 +1,56 @@
+// Launch planning: turn a placed plan into per-step kernel launches with
+// arena-relative descriptor tables, and fix the arena layout.  Pure host code.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "host.hpp"
+#include "../kernels/desc.hpp"
+
+namespace cdag {
+
+enum LaunchType : int32_t { L_HEC = 0, L_RED = 1, L_HCA = 2, L_XSUM = 3 };
+
+struct Launch {
+  int32_t type;
+  int32_t n_desc;
+  int64_t desc_off;   // arena offset of the first descriptor
+  int64_t n_items;    // HEC: tiles; RED: 256-element blocks; HCA: (root, t) pairs; XSUM: correlators
+  int64_t host_desc;  // byte offset of the first descriptor in KernelPlan::blob
+};
+
+// Exterior-contraction tile shape (both precisions' kernels use it).
+constexpr int kTileM = 64, kTileN = 64;
+// k-step of the matrix-core kernels: FP64 and FP32 use 16, split-BF16 32.
+inline int k_step(int prec) { return prec == 2 ? 32 : 16; }
+// Split-K: aim for at least this many work items per contraction, keeping at
+// least kMinKSplit of K per split.
+constexpr int kSplitTarget = 512, kMinKSplit = 256;
+
+struct KernelPlan {
+  int prec = 0;
+  std::vector<int64_t> launch_off;   // per step: first launch index (size n_steps + 1)
+  std::vector<Launch> launches;
+  Launch xsum{};
+  int64_t xsum_entries_off = 0;     // arena offset of the XsumEntry table
+  std::vector<uint8_t> blob;         // all descriptor tables, uploaded to blob_off
+  // arena layout
+  int64_t tensors_end = 0;           // leaf region + tensor pool
+  int64_t ws_off = 0, ws_bytes = 0;
+  int64_t blob_off = 0;
+  int64_t corr_off = 0, corr_bytes = 0;   // per tree: [nt][2] doubles
+  int64_t sums_off = 0, sums_bytes = 0;   // per correlator: [nt][2] doubles
+  int64_t total_bytes = 0;
+  std::vector<int64_t> tree_corr_off;     // per tree: byte offset inside the corr buffer
+  std::vector<int64_t> sum_corr_off;      // per correlator: byte offset inside the sums buffer
+  std::vector<int32_t> sum_nt;            // per correlator
+  double flops = 0;
+  double hec_flops = 0, hec_bytes = 0;
+};
+
+int64_t elem_bytes_of(int prec);                 // 16 for FP64, 8 otherwise
+void gemm_dims(const Dag& d, int64_t u, int32_t* M, int32_t* N, int32_t* K);
+KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec);
+
+}  // namespace cdag

@@ -1,0 +1,341 @@
+// Contraction schedulers (Sec. III): input order, Sibling (Algs. 1-3) and
+// Tree (Algs. 4-8), plus the Sec. II-C memory model.
+//
+// Readings where the paper is silent or garbled:
+//   * Sibling picks the WAITING leaf with the smallest id when all queues are
+//     empty; queues are FIFO; PROP-DOWN visits the left child first; "the
+//     sibling of u under v" is v's other child.
+//   * Tree: TR-INIT accumulates the individual gains igain (not the counts g)
+//     into tgain; PROCESS-CHILD removes u from x's AVAIL parents; ties in the
+//     argmax go to the lowest tree index; PROCESS-CTREE visits each not yet
+//     processed node of the tree once, in post-order, left child first.
+#include <algorithm>
+#include <deque>
+#include <functional>
+#include <set>
+
+#include "host.hpp"
+#include "../../../include/cdag.h"
+
+namespace cdag {
+
+std::vector<int64_t> sched_input(const Dag& d) {
+  std::vector<char> done(d.n_nodes(), 0);
+  std::vector<int64_t> order;
+  order.reserve(d.n_nodes() - d.n_leaves);
+  std::vector<std::pair<int64_t, int>> st;
+  for (int64_t r : d.root_of_graph) {
+    st.assign(1, {r, 0});
+    while (!st.empty()) {
+      auto [u, s] = st.back();
+      st.pop_back();
+      if (d.is_leaf(u) || done[u]) continue;
+      if (s == 1) { done[u] = 1; order.push_back(u); continue; }
+      st.push_back({u, 1});
+      st.push_back({d.right[u], 0});
+      st.push_back({d.left[u], 0});
+    }
+  }
+  return order;
+}
+
+// ---------------------------------------------------------------- Sibling
+namespace {
+enum SbState : uint8_t { WAITING, QUEUED, INMEM, RELEASED };
+
+struct Sibling {
+  const Dag& d;
+  std::vector<int32_t> rank;
+  std::vector<int64_t> rs, rp;
+  std::vector<uint8_t> state;
+  std::vector<std::deque<int64_t>> q;   // q[r] for r = 1..max rank
+  std::vector<int64_t> order;
+  explicit Sibling(const Dag& dd) : d(dd) {
+    const int64_t n = d.n_nodes();
+    rank.assign(n, 0);
+    int32_t qmax = 0;
+    for (int64_t u = d.n_leaves; u < n; ++u) {   // Eq. (1); ids are topological
+      rank[u] = 1 + std::max(rank[d.left[u]], rank[d.right[u]]);
+      qmax = std::max(qmax, rank[u]);
+    }
+    rs.resize(n);
+    rp.resize(n);
+    for (int64_t u = 0; u < n; ++u) {
+      rs[u] = d.n_parents(u);
+      rp[u] = d.is_leaf(u) ? 0 : 2;
+    }
+    state.assign(n, WAITING);
+    q.resize(qmax + 1);
+  }
+  void process(int64_t u) {                       // SB-PROCESS
+    if (!d.is_leaf(u)) order.push_back(u);        // perform the contraction
+    state[u] = INMEM;
+    if (!d.is_leaf(u)) {
+      for (int64_t v : {d.left[u], d.right[u]})
+        if (--rs[v] == 0) state[v] = RELEASED;
+      if (d.n_parents(u) == 0) state[u] = RELEASED;   // a ROOT
+    }
+    for (int64_t e = d.par_off[u]; e < d.par_off[u + 1]; ++e) {
+      int64_t v = d.par[e];
+      rp[v] -= 1;
+      if (rp[v] == 1) {
+        int64_t w = d.left[v] == u ? d.right[v] : d.left[v];
+        if (state[w] == WAITING) prop_down(w);
+      } else if (rp[v] == 0) {
+        q[rank[v]].push_back(v);
+        state[v] = QUEUED;
+      }
+    }
+  }
+  void prop_down(int64_t u) {                     // SB-PROP-DOWN
+    if (state[u] != WAITING) return;
+    if (d.is_leaf(u)) { process(u); return; }
+    prop_down(d.left[u]);
+    prop_down(d.right[u]);
+  }
+  void run() {                                    // SB-SCHEDULER
+    const int64_t n_contr = d.n_nodes() - d.n_leaves;
+    int64_t next_leaf = 0;
+    while ((int64_t)order.size() < n_contr) {
+      int64_t r = (int64_t)q.size() - 1;
+      while (r >= 1 && q[r].empty()) --r;
+      int64_t u;
+      if (r < 1) {
+        while (next_leaf < d.n_leaves && state[next_leaf] != WAITING) ++next_leaf;
+        if (next_leaf >= d.n_leaves) throw Error(CDAG_E_STATE, "sibling: no WAITING leaf left");
+        u = next_leaf;
+      } else {
+        u = q[r].front();
+        q[r].pop_front();
+      }
+      process(u);
+    }
+  }
+};
+}  // namespace
+
+std::vector<int64_t> sched_sibling(const Dag& d) {
+  Sibling s(d);
+  s.run();
+  return std::move(s.order);
+}
+
+// ---------------------------------------------------------------- Tree
+namespace {
+enum TrState : uint8_t { AVAIL, TR_INMEM, TR_RELEASED };
+
+struct TauDelta { int64_t tree, tau, delta; bool in_pred; };
+
+struct TreeSched {
+  const Dag& d;
+  const int64_t k;
+  std::vector<int64_t> size;
+  std::vector<uint8_t> state;
+  std::vector<int64_t> out_av;              // |u.outAv|
+  std::vector<int64_t> igain;               // aligned with ctree: igain(T_i, u)
+  std::vector<std::vector<TauDelta>> td;    // per node: tau/delta per successor tree
+  std::vector<int64_t> tgain, cgain;
+  std::vector<char> alive;
+  std::set<std::pair<int64_t, int64_t>> pq; // (-tgain, tree) of live trees
+  std::vector<int64_t> order;
+  std::vector<int64_t> visit_mark;
+  std::vector<int64_t> tpos;                // scratch: tree -> index in td[u], or -1
+
+  TreeSched(const Dag& dd, int elem_bytes)
+      : d(dd), k((int64_t)dd.tree_root.size()) {
+    const int64_t n = d.n_nodes();
+    size.resize(n);
+    for (int64_t u = 0; u < n; ++u) size[u] = d.size(u, elem_bytes);
+    visit_mark.assign(n, -1);
+    tpos.assign(k, -1);
+  }
+
+  void set_gain(int64_t t, int64_t delta) {
+    if (delta == 0) return;
+    if (alive[t]) pq.erase({-tgain[t], t});
+    tgain[t] += delta;
+    if (alive[t]) pq.insert({-tgain[t], t});
+  }
+
+  void init() {                                   // TR-INIT
+    const int64_t n = d.n_nodes();
+    state.assign(n, AVAIL);
+    out_av.resize(n);
+    for (int64_t u = 0; u < n; ++u) out_av[u] = d.n_parents(u);
+    tgain.assign(k, 0);
+    cgain.assign(k, 0);
+    alive.assign(k, 1);
+    td.assign(n, {});
+    igain.assign(d.ctree.size(), 0);
+    // g(u, T_i) = |outAv(u)| minus the edges (u, v) with v also in T_i, i.e.
+    // the number of u's parents outside T_i.
+    for (int64_t u = 0; u < n; ++u) {
+      for (int64_t j = d.ctree_off[u]; j < d.ctree_off[u + 1]; ++j) {
+        int64_t t = d.ctree[j];
+        int64_t g = out_av[u];
+        for (int64_t e = d.par_off[u]; e < d.par_off[u + 1]; ++e)
+          if (d.in_tree(d.par[e], t)) --g;
+        igain[j] = g == 0 ? 0 : -size[u];
+        tgain[t] += igain[j];
+      }
+    }
+    for (int64_t t = 0; t < k; ++t) pq.insert({-tgain[t], t});
+  }
+
+  void process_child(int64_t u, int64_t x) {      // PROCESS-CHILD
+    for (TauDelta& e : td[x]) {
+      if (!e.in_pred) continue;
+      if (d.in_tree(u, e.tree)) {
+        if (e.tau == 1 && e.delta == 0) {          // case 1.a
+          cgain[e.tree] -= size[x];
+          set_gain(e.tree, -size[x]);
+        }
+        if (--e.tau == 0) e.in_pred = false;
+      } else {
+        if (e.delta == 1) {                        // case 2.a
+          cgain[e.tree] += size[x];
+          set_gain(e.tree, +size[x]);
+        }
+        --e.delta;
+      }
+    }
+    if (--out_av[x] == 0) state[x] = TR_RELEASED;
+  }
+
+  void process_node(int64_t u) {                  // PROCESS-NODE
+    for (int64_t j = d.ctree_off[u]; j < d.ctree_off[u + 1]; ++j) set_gain(d.ctree[j], -igain[j]);
+    // all of u's parents are AVAIL here (children are processed first)
+    std::vector<TauDelta>& v = td[u];
+    v.clear();
+    for (int64_t e = d.par_off[u]; e < d.par_off[u + 1]; ++e) {
+      int64_t p = d.par[e];
+      for (int64_t j = d.ctree_off[p]; j < d.ctree_off[p + 1]; ++j) {
+        int64_t t = d.ctree[j];
+        if (tpos[t] < 0) {
+          tpos[t] = (int64_t)v.size();
+          v.push_back({t, 0, out_av[u], true});
+        }
+        v[tpos[t]].delta -= 1;
+        v[tpos[t]].tau += 1;
+      }
+    }
+    for (const TauDelta& e : v) tpos[e.tree] = -1;
+    for (const TauDelta& e : v)
+      if (e.delta == 0) {
+        cgain[e.tree] += size[u];
+        set_gain(e.tree, +size[u]);
+      }
+    state[u] = out_av[u] == 0 ? TR_RELEASED : TR_INMEM;
+  }
+
+  void process_ctree(int64_t t) {                 // PROCESS-CTREE
+    std::vector<std::pair<int64_t, int>> st{{d.tree_root[t], 0}};
+    while (!st.empty()) {
+      auto [u, s] = st.back();
+      st.pop_back();
+      if (state[u] != AVAIL) continue;
+      if (s == 1) {
+        if (!d.is_leaf(u)) {
+          process_child(u, d.left[u]);
+          process_child(u, d.right[u]);
+          order.push_back(u);
+        }
+        process_node(u);
+        continue;
+      }
+      if (visit_mark[u] == t) continue;
+      visit_mark[u] = t;
+      st.push_back({u, 1});
+      if (!d.is_leaf(u)) {
+        st.push_back({d.right[u], 0});
+        st.push_back({d.left[u], 0});
+      }
+    }
+  }
+
+  // M - M' for tree t from the current states (no incremental fields).
+  int64_t brute_gain(int64_t t) const {
+    std::vector<int64_t> todo, touched;
+    for (int64_t j = d.tree_off[t]; j < d.tree_off[t + 1]; ++j)
+      if (state[d.tree_nodes[j]] == AVAIL) todo.push_back(d.tree_nodes[j]);
+    std::sort(todo.begin(), todo.end());
+    touched = todo;
+    for (int64_t u : todo)
+      if (!d.is_leaf(u)) { touched.push_back(d.left[u]); touched.push_back(d.right[u]); }
+    std::sort(touched.begin(), touched.end());
+    touched.erase(std::unique(touched.begin(), touched.end()), touched.end());
+    auto in_todo = [&](int64_t x) { return std::binary_search(todo.begin(), todo.end(), x); };
+    int64_t before = 0, after = 0;
+    for (int64_t x : touched) {
+      bool proc = state[x] != AVAIL;
+      bool pending_b = false, pending_a = false;
+      for (int64_t e = d.par_off[x]; e < d.par_off[x + 1]; ++e) {
+        int64_t p = d.par[e];
+        if (state[p] == AVAIL) {
+          pending_b = true;
+          if (!in_todo(p)) pending_a = true;
+        }
+      }
+      if (proc && pending_b) before += size[x];
+      if ((proc || in_todo(x)) && pending_a) after += size[x];
+    }
+    return before - after;
+  }
+
+  void run(bool check) {                          // TR-SCHEDULER
+    init();
+    for (int64_t it = 0; it < k; ++it) {
+      if (check)
+        for (int64_t t = 0; t < k; ++t)
+          if (alive[t] && brute_gain(t) != tgain[t])
+            throw Error(CDAG_E_STATE, "tree: incremental tgain of tree " + std::to_string(t) +
+                                          " is " + std::to_string(tgain[t]) + ", M - M' is " +
+                                          std::to_string(brute_gain(t)));
+      int64_t best = pq.begin()->second;          // max tgain, lowest index on ties
+      pq.erase(pq.begin());
+      alive[best] = 0;
+      process_ctree(best);
+    }
+  }
+};
+}  // namespace
+
+std::vector<int64_t> sched_tree(const Dag& d, int elem_bytes, bool check) {
+  TreeSched s(d, elem_bytes);
+  s.run(check);
+  return std::move(s.order);
+}
+
+// ---------------------------------------------------------------- memory model
+MemSim memsim(const Dag& d, const std::vector<int64_t>& order, int elem_bytes) {
+  const int64_t n = d.n_nodes();
+  std::vector<int64_t> remaining(n);
+  for (int64_t u = 0; u < n; ++u) remaining[u] = d.n_parents(u);
+  std::vector<char> in_mem(n, 0), seen(n, 0);
+  MemSim r;
+  int64_t M = 0;
+  if ((int64_t)order.size() != n - d.n_leaves) throw Error(CDAG_E_INVALID, "memsim: order must list every contraction once");
+  for (int64_t c : order) {
+    if (c < d.n_leaves || c >= n || seen[c]) throw Error(CDAG_E_INVALID, "memsim: order must list every contraction once");
+    seen[c] = 1;
+    int64_t brought = 0;
+    for (int64_t x : {d.left[c], d.right[c]}) {
+      if (!in_mem[x]) {
+        if (!d.is_leaf(x)) throw Error(CDAG_E_INVALID, "memsim: order is not topological");
+        in_mem[x] = 1;
+        brought += d.size(x, elem_bytes);
+      }
+    }
+    r.peak_live = std::max(r.peak_live, M + brought + d.size(c, elem_bytes));
+    M += brought + d.size(c, elem_bytes);
+    in_mem[c] = 1;
+    for (int64_t x : {d.left[c], d.right[c]})
+      if (--remaining[x] == 0) { in_mem[x] = 0; M -= d.size(x, elem_bytes); }
+    if (remaining[c] == 0) { in_mem[c] = 0; M -= d.size(c, elem_bytes); }
+    r.M.push_back(M);
+    r.peak_post = std::max(r.peak_post, M);
+  }
+  return r;
+}
+
+}  // namespace cdag

@@ -1,0 +1,50 @@
+// Launch descriptors shared by the host launch planner and the HIP kernels.
+// Every address is a byte offset from the arena base passed to the kernel, so
+// a descriptor table stays valid for any arena address and can be uploaded
+// once per plan.
+//
+// Tensor layout in the arena (all precisions): [nt][2][N^rank] -- per time
+// slice the real plane, then the imaginary plane, each row-major.  A
+// contraction is then, per t, the complex GEMM C_t (M x N) = A_t (M x K) B_t
+// (K x N) with row-major planes:
+//   K22: (M, N, K) = (n, n, n)
+//   K32: (M, N, K) = (n^2, n, n)     A = X[i,j | k], B = Y[k | l]
+//   K33: (M, N, K) = (n, n, n^2)     A = X[i | j,l], B = Y[j,l | m]
+#pragma once
+#include <stdint.h>
+
+namespace cdag {
+
+// One exterior contraction inside a grouped launch.
+struct HecDesc {
+  int64_t a_off, b_off, c_off;   // t = 0 slice of A, B and C
+  int64_t ws_off;                // split-K partials [splits][nt][2][M*N] (accumulator type), or -1
+  int32_t M, N, K, nt;
+  int32_t tiles_m, tiles_n, splits, k_split;   // k_split: K range per split (multiple of the k-step)
+  int32_t tile_begin, tile_count;              // this op's work items in the launch
+};
+
+// Fixed-order reduction of split-K partials into C (one per split op).
+struct RedDesc {
+  int64_t ws_off, c_off;
+  int32_t mn, nt, splits, item_begin;          // items: ceil(2*nt*mn / 256) blocks
+};
+
+// Root trace C(t) = sum_ij P[t,i,j] Q[t,j,i] into the FP64 correlator buffer.
+struct HcaDesc {
+  int64_t p_off, q_off, out_off;               // out: [nt][2] doubles
+  int32_t n, nt, item_begin, pad;              // items: one per time slice
+};
+
+// Cross-diagram sum for one correlator: sum over entries [e_begin, e_end) of
+// w * C_root(t), in entry order (ascending input graph).
+struct XsumDesc {
+  int64_t out_off;                             // [nt][2] doubles
+  int32_t e_begin, e_end, nt, pad;
+};
+struct XsumEntry {
+  int64_t root_off;                            // [nt][2] doubles
+  double w_re, w_im;
+};
+
+}  // namespace cdag

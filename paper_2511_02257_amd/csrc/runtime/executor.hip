@@ -1,0 +1,349 @@
+// Device runtime: leaf staging in pinned host memory, the arena borrowed from
+// the caller, and execution of a placed plan on two HIP streams.
+//
+// Per step s the copy stream performs the step's spills (D2H) and uploads
+// (H2D) and records ev_copy[s]; the compute stream waits for it when the step
+// uploaded operands (or when an output reuses memory a spill was still
+// reading), launches the step's kernels and records ev_comp[s].  A copy into
+// memory that kernels last touched at step k first waits for ev_comp[k].  All
+// waits come from the plan (place()), so copies overlap kernels of earlier
+// steps whenever the memory they use is already free.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <string>
+#include <thread>
+
+#include "../ctx.hpp"
+#include "../kernels/kernels.hpp"
+
+namespace cdag {
+
+namespace {
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(CDAG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPC(x) hip_check((x), #x)
+inline void ignore(hipError_t) {}
+
+double now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+}  // namespace
+
+struct Device {
+  int device = -1;
+  hipStream_t comp = nullptr, copy = nullptr;
+  char* arena = nullptr;
+  uint64_t arena_bytes = 0;
+  uint64_t arena_epoch = 0;                 // bumped when the arena is rebound
+  // pinned staging of leaves in device layout, per precision mode
+  std::vector<void*> stage[3];
+  uint64_t stage_version[3] = {0, 0, 0};
+  // pinned host spill pool
+  void* spill = nullptr;
+  int64_t spill_bytes = 0;
+  // pinned result buffer
+  void* results = nullptr;
+  int64_t results_bytes = 0;
+  std::vector<hipEvent_t> ev_comp, ev_copy;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  // what is currently uploaded
+  uint64_t blob_key = 0, blob_epoch = 0;
+  int resident_prec = -1;
+  uint64_t resident_key = 0, resident_epoch = 0;
+  // captured launch sequence
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t graph_key = 0, graph_epoch = 0;
+  // timing mode: event pairs around exterior-contraction launches
+  std::vector<hipEvent_t> tpool;
+  size_t tnext = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> tpairs;
+
+  hipEvent_t timing_event() {
+    if (tnext == tpool.size()) {
+      hipEvent_t e;
+      HIPC(hipEventCreate(&e));
+      tpool.push_back(e);
+    }
+    return tpool[tnext++];
+  }
+
+  ~Device() {
+    if (device >= 0) ignore(hipSetDevice(device));
+    if (gexec) ignore(hipGraphExecDestroy(gexec));
+    if (graph) ignore(hipGraphDestroy(graph));
+    for (auto e : ev_comp) ignore(hipEventDestroy(e));
+    for (auto e : ev_copy) ignore(hipEventDestroy(e));
+    for (auto e : tpool) ignore(hipEventDestroy(e));
+    if (t0) ignore(hipEventDestroy(t0));
+    if (t1) ignore(hipEventDestroy(t1));
+    for (auto& v : stage)
+      for (void* p : v)
+        if (p) ignore(hipHostFree(p));
+    if (spill) ignore(hipHostFree(spill));
+    if (results) ignore(hipHostFree(results));
+  }
+};
+
+void device_destroy(Device* d) { delete d; }
+
+void device_bind(Ctx& c, int device, void* compute_stream, void* copy_stream) {
+  int n = 0;
+  HIPC(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) throw Error(CDAG_E_INVALID, "device ordinal out of range");
+  if (!c.dev || c.dev->device != device) {
+    delete c.dev;
+    c.dev = nullptr;
+    c.dev = new Device();
+    c.dev->device = device;
+  }
+  HIPC(hipSetDevice(device));
+  c.dev->comp = (hipStream_t)compute_stream;
+  c.dev->copy = (hipStream_t)copy_stream;
+  if (!c.dev->t0) {
+    HIPC(hipEventCreate(&c.dev->t0));
+    HIPC(hipEventCreate(&c.dev->t1));
+  }
+  c.dev->graph_key = 0;   // captured graphs name the old streams' work; recapture
+}
+
+void device_bind_arena(Ctx& c, void* arena, uint64_t bytes) {
+  if (!c.dev) throw Error(CDAG_E_STATE, "cdag_bind_device first");
+  c.dev->arena = (char*)arena;
+  c.dev->arena_bytes = bytes;
+  c.dev->arena_epoch++;
+}
+
+namespace {
+// Interleaved complex128 [nt][e] -> planar [nt][2][e] in T.
+template <typename T>
+void to_device_layout(const double* src, T* dst, int64_t nt, int64_t e) {
+  for (int64_t t = 0; t < nt; ++t) {
+    const double* s = src + 2 * t * e;
+    T* re = dst + 2 * t * e;
+    T* im = re + e;
+    for (int64_t i = 0; i < e; ++i) {
+      re[i] = (T)s[2 * i];
+      im[i] = (T)s[2 * i + 1];
+    }
+  }
+}
+
+void ensure_stage(Ctx& c, int prec) {
+  Device& D = *c.dev;
+  if (D.stage_version[prec] == c.data_version && !D.stage[prec].empty()) return;
+  const int64_t L = c.dag.n_leaves;
+  const int eb = prec == CDAG_FP64 ? 16 : 8;
+  for (void* p : D.stage[prec])
+    if (p) ignore(hipHostFree(p));
+  D.stage[prec].assign(L, nullptr);
+  for (int64_t u = 0; u < L; ++u)
+    HIPC(hipHostMalloc(&D.stage[prec][u], (size_t)c.dag.size(u, eb), hipHostMallocDefault));
+  const unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned w = 0; w < nth; ++w)
+    th.emplace_back([&, w] {
+      for (int64_t u = w; u < L; u += nth) {
+        const int64_t e = c.dag.elems(u) / c.dag.nt[u];
+        if (prec == CDAG_FP64)
+          to_device_layout<double>(c.leaf_data[u].data(), (double*)D.stage[prec][u], c.dag.nt[u], e);
+        else
+          to_device_layout<float>(c.leaf_data[u].data(), (float*)D.stage[prec][u], c.dag.nt[u], e);
+      }
+    });
+  for (auto& t : th) t.join();
+  D.stage_version[prec] = c.data_version;
+}
+
+void ensure_events(Device& D, size_t n) {
+  while (D.ev_comp.size() < n) {
+    hipEvent_t e;
+    HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    D.ev_comp.push_back(e);
+  }
+  while (D.ev_copy.size() < n) {
+    hipEvent_t e;
+    HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    D.ev_copy.push_back(e);
+  }
+}
+
+void ensure_pinned(void*& p, int64_t& have, int64_t need_bytes) {
+  if (have >= need_bytes && p) return;
+  if (p) ignore(hipHostFree(p));
+  p = nullptr;
+  have = 0;
+  if (need_bytes <= 0) return;
+  HIPC(hipHostMalloc(&p, (size_t)need_bytes, hipHostMallocDefault));
+  have = need_bytes;
+}
+
+int64_t launch_step(const KernelPlan& kp, int64_t s, int prec, char* arena, hipStream_t st, Device* timed) {
+  int64_t n = 0;
+  for (int64_t li = kp.launch_off[s]; li < kp.launch_off[s + 1]; ++li) {
+    const Launch& L = kp.launches[li];
+    switch (L.type) {
+      case L_HEC:
+        if (timed) {
+          hipEvent_t a = timed->timing_event(), b = timed->timing_event();
+          HIPC(hipEventRecord(a, st));
+          HIPC(launch_hec(prec, arena, L.desc_off, L.n_desc, L.n_items, st));
+          HIPC(hipEventRecord(b, st));
+          timed->tpairs.push_back({a, b});
+        } else {
+          HIPC(launch_hec(prec, arena, L.desc_off, L.n_desc, L.n_items, st));
+        }
+        break;
+      case L_RED: HIPC(launch_reduce(prec, arena, L.desc_off, L.n_desc, L.n_items, st)); break;
+      case L_HCA: HIPC(launch_hca(prec, arena, L.desc_off, L.n_desc, L.n_items, st)); break;
+      default: throw Error(CDAG_E_STATE, "bad launch type");
+    }
+    ++n;
+  }
+  return n;
+}
+}  // namespace
+
+void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
+  (void)batched;
+  Device& D = *c.dev;
+  const double tw0 = now();
+  HIPC(hipSetDevice(D.device));
+  const Plan& p = c.plan;
+  const KernelPlan& kp = c.kplan;
+  if (!D.arena) throw Error(CDAG_E_STATE, "cdag_bind_arena first");
+  if ((uint64_t)kp.total_bytes > D.arena_bytes)
+    throw Error(CDAG_E_NOMEM, "arena has " + std::to_string(D.arena_bytes) + " bytes, the plan needs " +
+                                  std::to_string(kp.total_bytes));
+  const int eb = prec == CDAG_FP64 ? 16 : 8;
+  ensure_stage(c, prec);
+  ensure_pinned(D.spill, D.spill_bytes, p.host_spill_bytes);
+  ensure_pinned(D.results, D.results_bytes, kp.corr_bytes + kp.sums_bytes);
+  const int64_t S = (int64_t)p.steps.size();
+  ensure_events(D, (size_t)std::max<int64_t>(S, 1));
+
+  // descriptor tables: one upload per (plan, arena)
+  const uint64_t pkey = c.plan_serial;
+  if (D.blob_key != pkey || D.blob_epoch != D.arena_epoch) {
+    HIPC(hipMemcpyAsync(D.arena + kp.blob_off, kp.blob.data(), kp.blob.size(), hipMemcpyHostToDevice, D.comp));
+    HIPC(hipStreamSynchronize(D.comp));
+    D.blob_key = pkey;
+    D.blob_epoch = D.arena_epoch;
+  }
+  // leaves kept resident in their own region: one upload per (precision, arena, build)
+  if (c.leaves_resident &&
+      (D.resident_prec != prec || D.resident_epoch != D.arena_epoch || D.resident_key != D.stage_version[prec])) {
+    for (int64_t u = 0; u < c.dag.n_leaves; ++u)
+      HIPC(hipMemcpyAsync(D.arena + p.leaf_off[u], D.stage[prec][u], (size_t)c.dag.size(u, eb),
+                          hipMemcpyHostToDevice, D.copy));
+    HIPC(hipStreamSynchronize(D.copy));
+    D.resident_prec = prec;
+    D.resident_epoch = D.arena_epoch;
+    D.resident_key = D.stage_version[prec];
+  }
+
+  bool has_copies = false;
+  for (const PlanRec& r : p.recs)
+    if (r.op == OP_H2D || r.op == OP_D2H) { has_copies = true; break; }
+
+  int64_t n_launch = 0, n_segments = 0;
+  D.tnext = 0;
+  D.tpairs.clear();
+  Device* timed = c.timing ? &D : nullptr;
+  HIPC(hipEventRecord(D.t0, D.comp));
+  if (!has_copies && c.use_graphs && !c.timing) {
+    // no transfers: the whole step sequence is one captured graph
+    if (!D.gexec || D.graph_key != pkey || D.graph_epoch != D.arena_epoch) {
+      if (D.gexec) { ignore(hipGraphExecDestroy(D.gexec)); D.gexec = nullptr; }
+      if (D.graph) { ignore(hipGraphDestroy(D.graph)); D.graph = nullptr; }
+      hipStream_t cs;
+      HIPC(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      HIPC(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      try {
+        for (int64_t s = 0; s < S; ++s) launch_step(kp, s, prec, D.arena, cs, nullptr);
+      } catch (...) {
+        hipGraph_t g = nullptr;
+        ignore(hipStreamEndCapture(cs, &g));
+        if (g) ignore(hipGraphDestroy(g));
+        ignore(hipStreamDestroy(cs));
+        throw;
+      }
+      HIPC(hipStreamEndCapture(cs, &D.graph));
+      HIPC(hipStreamDestroy(cs));
+      HIPC(hipGraphInstantiate(&D.gexec, D.graph, nullptr, nullptr, 0));
+      D.graph_key = pkey;
+      D.graph_epoch = D.arena_epoch;
+    }
+    HIPC(hipGraphLaunch(D.gexec, D.comp));
+    n_segments = 1;
+    for (int64_t s = 0; s < S; ++s) n_launch += kp.launch_off[s + 1] - kp.launch_off[s];
+  } else {
+    int64_t copy_waited = -1, comp_waited = -1;
+    for (int64_t s = 0; s < S; ++s) {
+      bool any_copy = false, any_h2d = false;
+      int64_t need_copy = -1;
+      for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
+        const PlanRec& r = p.recs[ri];
+        const size_t sz = (size_t)c.dag.size(r.node, eb);
+        if (r.op == OP_D2H || r.op == OP_H2D) {
+          if (r.wait_comp > copy_waited) {
+            HIPC(hipStreamWaitEvent(D.copy, D.ev_comp[r.wait_comp], 0));
+            copy_waited = r.wait_comp;
+          }
+          if (r.op == OP_D2H) {
+            HIPC(hipMemcpyAsync((char*)D.spill + r.host_off, D.arena + r.dev_off, sz, hipMemcpyDeviceToHost, D.copy));
+          } else {
+            const void* src = c.dag.is_leaf(r.node) ? D.stage[prec][r.node] : (const void*)((char*)D.spill + r.host_off);
+            HIPC(hipMemcpyAsync(D.arena + r.dev_off, src, sz, hipMemcpyHostToDevice, D.copy));
+            any_h2d = true;
+          }
+          any_copy = true;
+        } else if (r.op == OP_ALLOC && r.wait_copy >= 0) {
+          need_copy = std::max(need_copy, r.wait_copy);
+        }
+      }
+      if (any_copy) HIPC(hipEventRecord(D.ev_copy[s], D.copy));
+      if (any_h2d) need_copy = std::max(need_copy, s);
+      if (need_copy > comp_waited) {
+        HIPC(hipStreamWaitEvent(D.comp, D.ev_copy[need_copy], 0));
+        comp_waited = need_copy;
+      }
+      n_launch += launch_step(kp, s, prec, D.arena, D.comp, timed);
+      HIPC(hipEventRecord(D.ev_comp[s], D.comp));
+    }
+  }
+  HIPC(launch_xsum(D.arena, kp.xsum.desc_off, kp.xsum_entries_off, kp.xsum.n_desc, D.comp));
+  n_launch++;
+  HIPC(hipEventRecord(D.t1, D.comp));
+  HIPC(hipMemcpyAsync(D.results, D.arena + kp.corr_off, (size_t)(kp.corr_bytes + kp.sums_bytes),
+                      hipMemcpyDeviceToHost, D.comp));
+  HIPC(hipStreamSynchronize(D.comp));
+  HIPC(hipStreamSynchronize(D.copy));
+  float ms = 0;
+  HIPC(hipEventElapsedTime(&ms, D.t0, D.t1));
+  c.corr_host.assign((const double*)D.results, (const double*)D.results + kp.corr_bytes / 8);
+  c.sums_host.assign((const double*)((const char*)D.results + kp.corr_bytes),
+                     (const double*)((const char*)D.results + kp.corr_bytes) + kp.sums_bytes / 8);
+  double t_hec = 0;
+  for (auto& pr : D.tpairs) {
+    float x = 0;
+    HIPC(hipEventElapsedTime(&x, pr.first, pr.second));
+    t_hec += x * 1e-3;
+  }
+  int64_t n_hec = 0;
+  for (const Launch& L : kp.launches) n_hec += L.type == L_HEC;
+  st->t_hec_s = t_hec;
+  st->hec_flops = kp.hec_flops;
+  st->hec_bytes = kp.hec_bytes;
+  st->n_hec_launches = n_hec;
+  st->t_total_s = now() - tw0;
+  st->t_device_s = ms * 1e-3;
+  st->n_launches = n_launch;
+  st->n_graph_segments = n_segments;
+}
+
+}  // namespace cdag

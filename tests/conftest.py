@@ -9,3 +9,11 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: takes more than a few seconds on the CPU")
+
+
+def pytest_runtest_setup(item):
+    if "gpu" in item.keywords:
+        import pytest
+        import torch
+        if not torch.cuda.is_available():
+            pytest.skip("needs a HIP device")

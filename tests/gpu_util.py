@@ -1,0 +1,54 @@
+"""Helpers for the GPU parity tests: run a workload through the C ABI on cuda:0
+and measure errors against the oracle."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import dag as OD
+from oracle import schedules as OS
+from oracle import values as OV
+
+
+def run(wl, policy="tree", prec="fp64", batched=False, budget=None, leaves_resident=False,
+        use_graphs=True, wave_max=4096, device=0, runner_cache={}):
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd.device import DeviceRunner
+    ctx = X.Context()
+    ctx.build_cdag(wl.leaves, wl.graphs)
+    order = ctx.schedule(policy)
+    ctx.set_mem_budget(budget)
+    ctx.set_options(leaves_resident=leaves_resident, wave_max=wave_max, use_graphs=use_graphs)
+    runner = DeviceRunner(ctx, device)
+    st = runner.run(prec, batched)
+    corr = ctx.fetch_correlators()
+    sums = ctx.fetch_sums()
+    ctx.close()
+    return dict(order=order, stats=st, corr=corr, sums=sums)
+
+
+def rel_errors(corr, ref):
+    """Per graph ||C - C_ref||_2 / ||C_ref||_2 over t."""
+    out = []
+    for g, r in ref.items():
+        out.append(np.linalg.norm(corr[g] - r) / np.linalg.norm(r))
+    return np.array(out)
+
+
+def sum_errors(wl, sums, ref_vals):
+    """Cross-diagram sums: |S - S_ref| / sum_g |w_g C_g| per t (condition-aware)."""
+    ref = OV.cross_sums(wl, ref_vals)
+    scale = OV.cross_sum_scale(wl, ref_vals)
+    worst = 0.0
+    for c, s in ref.items():
+        worst = max(worst, float(np.max(np.abs(sums[c] - s) / scale[c])))
+    return worst
+
+
+def oracle_plan_counts(wl, policy, elem_bytes, budget, batched, leaves_resident=False):
+    from oracle import planner as OP
+    d = OD.build(wl.leaves, wl.graphs)
+    order = OS.schedule(d, policy, elem_bytes)
+    res = OP.plan(d, order, elem_bytes=elem_bytes,
+                  budget=OP.UNLIMITED if budget is None else budget,
+                  batched=batched, leaves_resident=leaves_resident)
+    return d, order, res

@@ -1,0 +1,170 @@
+"""GPU parity: the HIP path through the C ABI against the oracle (marked gpu).
+
+Bars: FP64 correlators within 1e-12 (norm-wise relative over t per graph);
+FP32 within 1e-5; split-BF16 within 4e-5 (each operand keeps 16 of its 24
+significand bits, so a product carries up to ~3 * 2^-16 relative error, and a
+ring trace chains up to 7 contractions); cross sums within the same bound of
+the condition scale sum_g |w_g C_g|; plan counters equal to the oracle's;
+identical bits across schedules, budgets and batching within one precision.
+"""
+import numpy as np
+import pytest
+
+from synth import workloads as W
+from oracle import values as OV
+
+from gpu_util import run, rel_errors, sum_errors, oracle_plan_counts
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 4e-5}
+
+
+def _wl_meson_small():
+    # N = 72: two 64-wide tiles per dimension with a ragged tail of 8
+    return W.meson_ring(n_leaves=8, nvec=72, nt=5, n_graphs=40, lmin=4, lmax=7, sigma=1 / 8,
+                        n_corr=3, seed=11, name="meson_small")
+
+
+def _wl_baryon_small():
+    # N = 40: ragged tiles; K33 has K = 1600 and runs split-K
+    return W.baryon_mix(n_bar=4, n_mes=4, nvec=40, nt=3, n_graphs=12, sigma=1 / 16, n_corr=2,
+                        seed=12, name="baryon_small")
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    wl = W.config("tiny")
+    return wl, OV.correlators(wl)
+
+
+@pytest.fixture(scope="module")
+def meson_small():
+    wl = _wl_meson_small()
+    return wl, OV.correlators(wl)
+
+
+@pytest.fixture(scope="module")
+def baryon_small():
+    wl = _wl_baryon_small()
+    return wl, OV.correlators(wl)
+
+
+def test_tiny_fp64_all_modes(tiny):
+    wl, ref = tiny
+    base = None
+    for policy in ("input", "sibling", "tree"):
+        for batched in (False, True):
+            r = run(wl, policy, "fp64", batched)
+            err = rel_errors(r["corr"], ref)
+            print(f"tiny {policy} batched={batched} max rel {err.max():.3e}")
+            assert err.max() <= TOL["fp64"]
+            assert sum_errors(wl, r["sums"], ref) <= 1e-12
+            bits = np.concatenate(r["corr"]).view(np.uint64)
+            if base is None:
+                base = bits
+            assert np.array_equal(bits, base), "correlators differ across schedules/batching"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_meson_ragged_with_evictions(meson_small, prec):
+    wl, ref = meson_small
+    eb = 16 if prec == "fp64" else 8
+    # a quarter of the input-order live peak: forces spills and re-uploads
+    from oracle import dag as OD, schedules as OS
+    d = OD.build(wl.leaves, wl.graphs)
+    budget = OS.memsim(d, OS.input_order(d), eb)["peak_live"] // 4
+    results = []
+    for policy in ("input", "tree"):
+        for batched in (False, True):
+            r = run(wl, policy, prec, batched, budget=budget)
+            _, _, o = oracle_plan_counts(wl, policy, eb, budget, batched)
+            p = r["stats"]["plan"]
+            for k in ("peak_resident", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes"):
+                assert p[k] == o[k], (policy, batched, k)
+            assert p["n_evict"] > 0
+            err = rel_errors(r["corr"], ref)
+            print(f"meson_small {prec} {policy} batched={batched} evict={p['n_evict']} "
+                  f"max rel {err.max():.3e} median {np.median(err):.3e}")
+            assert err.max() <= TOL[prec]
+            results.append(np.concatenate(r["corr"]).view(np.uint64))
+    for b in results[1:]:
+        assert np.array_equal(b, results[0])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_baryon_ragged_splitk(baryon_small, prec):
+    wl, ref = baryon_small
+    results = []
+    for policy, batched in (("tree", False), ("tree", True), ("sibling", True)):
+        r = run(wl, policy, prec, batched)
+        err = rel_errors(r["corr"], ref)
+        print(f"baryon_small {prec} {policy} batched={batched} max rel {err.max():.3e} "
+              f"median {np.median(err):.3e}")
+        assert err.max() <= TOL[prec]
+        assert sum_errors(wl, r["sums"], ref) <= TOL[prec]
+        results.append(np.concatenate(r["corr"]).view(np.uint64))
+    for b in results[1:]:
+        assert np.array_equal(b, results[0])
+
+
+def test_resident_leaves_and_graph_replay(baryon_small):
+    wl, ref = baryon_small
+    a = run(wl, "tree", "fp64", True, leaves_resident=True, use_graphs=True)
+    b = run(wl, "tree", "fp64", True, leaves_resident=True, use_graphs=False)
+    assert a["stats"]["n_graph_segments"] == 1 and b["stats"]["n_graph_segments"] == 0
+    assert a["stats"]["plan"]["n_h2d"] == 0
+    assert rel_errors(a["corr"], ref).max() <= TOL["fp64"]
+    assert np.array_equal(np.concatenate(a["corr"]).view(np.uint64),
+                          np.concatenate(b["corr"]).view(np.uint64))
+
+
+def _identity(nt, n):
+    return np.broadcast_to(np.eye(n, dtype=np.complex128), (nt, n, n)).copy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_identity_trace_exact(prec):
+    nt, n = 4, 48
+    leaves = [W.Leaf(2, n, nt, _identity(nt, n)) for _ in range(4)]
+    graphs = [W.GraphSpec([(W.K22, 0, 1), (W.K22, -1, 2), (W.HCA, -2, 3)], 0, 1.0),
+              W.GraphSpec([(W.K22, 1, 2), (W.HCA, -1, 3)], 0, 1.0)]
+    wl = W.Workload("identity", leaves, graphs)
+    r = run(wl, "input", prec, False)
+    for c in r["corr"]:
+        assert np.array_equal(c, np.full(nt, n, dtype=np.complex128))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_times_identity_and_selector_exact(prec):
+    rng = np.random.default_rng(3)
+    nt, n = 3, 24
+    X2 = W._draw(rng, (nt, n, n), 0.5)
+    Y2 = W._draw(rng, (nt, n, n), 0.5)
+    X3 = W._draw(rng, (nt, n, n, n), 0.5)
+    E = np.zeros((nt, n, n, n), dtype=np.complex128)
+    for m in range(n):
+        E[:, m, 0, m] = 1.0
+    X3sel = np.ascontiguousarray(X3[:, :, :, 0])
+    leaves = [W.Leaf(2, n, nt, X2), W.Leaf(2, n, nt, _identity(nt, n)), W.Leaf(2, n, nt, Y2),
+              W.Leaf(3, n, nt, X3), W.Leaf(3, n, nt, E), W.Leaf(2, n, nt, X3sel)]
+    graphs = [W.GraphSpec([(W.K22, 0, 1), (W.HCA, -1, 2)]),      # tr((X I) Y)
+              W.GraphSpec([(W.HCA, 0, 2)]),                       # tr(X Y)
+              W.GraphSpec([(W.K33, 3, 4), (W.HCA, -1, 2)]),      # tr(K33(X3, E) Y)
+              W.GraphSpec([(W.HCA, 5, 2)])]                       # tr(X3[..,0] Y)
+    wl = W.Workload("exact", leaves, graphs)
+    r = run(wl, "input", prec, False)
+    c = r["corr"]
+    assert np.array_equal(c[0], c[1])
+    assert np.array_equal(c[2], c[3])
+    if prec == "fp64":
+        ref = OV.correlators(wl)
+        assert rel_errors(c, ref).max() <= 1e-13
+
+
+def test_deterministic_rerun(baryon_small):
+    wl, _ = baryon_small
+    a = run(wl, "tree", "fp32", True)
+    b = run(wl, "tree", "fp32", True)
+    assert np.array_equal(np.concatenate(a["corr"]).view(np.uint64),
+                          np.concatenate(b["corr"]).view(np.uint64))

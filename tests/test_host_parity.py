@@ -1,0 +1,220 @@
+"""Host parity (CPU only): the C++ library through its C ABI against the oracle.
+
+Schedules, memory-model figures, plan counters and the complete plan op lists
+must be identical; malformed input and out-of-order calls must fail cleanly
+and leave the context usable.
+"""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2511_02257_amd as X
+from paper_2511_02257_amd import binding as B
+from synth import workloads as W
+from oracle import dag as OD
+from oracle import planner as OP
+from oracle import schedules as OS
+
+HERE = os.path.dirname(__file__)
+HEADER = os.path.join(os.path.dirname(HERE), "include", "cdag.h")
+
+
+def ctx_for(wl):
+    c = X.Context()
+    c.build_cdag(wl.leaves, wl.graphs)
+    return c
+
+
+def test_library_exports_every_declared_symbol():
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", text, flags=re.M))
+    assert {"build_cdag", "schedule", "set_mem_budget", "execute", "fetch_correlators"} <= declared
+    lib = X.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(B.EXPORTED)
+
+
+class _L:
+    def __init__(self, rank, nvec=4, nt=1):
+        self.rank, self.nvec, self.nt, self.data = rank, nvec, nt, None
+
+
+class _G:
+    def __init__(self, ops, corr=0, w=1.0):
+        self.ops, self.corr, self.w = ops, corr, w
+
+
+def test_table_sch_mem_through_abi():
+    gold = json.load(open(os.path.join(HERE, "golden", "table_sch_mem.json")))["schedules"]
+    wl = W.fig1_dag("fgh", with_data=False)
+    c = ctx_for(wl)
+    # node ids from the build: a..d = 0..3, f = 4, e = 5, g = 6, h = 7
+    kind, left, right = c.nodes()
+    names = {"a": 0, "b": 1, "c": 2, "d": 3}
+    for u in range(4, 8):
+        key = (int(left[u]), int(right[u]))
+        names[{(0, 1): "f", (1, 2): "e", (0, 5): "g", (5, 3): "h"}[key]] = u
+    unit = 4 * 4 * 16
+    for which, g in gold.items():
+        M, pp, pl = c.memsim([names[x] for x in g["order"]], 16)
+        assert [int(m) // unit for m in M] == g["size"]
+    assert [int(x) for x in c.schedule("tree")] == [names[x] for x in "fegh"]
+    assert [int(x) for x in c.schedule("sibling")] == [names[x] for x in "fegh"]
+    wl2 = W.fig1_dag("ghf", with_data=False)
+    c2 = ctx_for(wl2)
+    d2 = OD.build(wl2.leaves, wl2.graphs)
+    assert list(c2.schedule("sibling")) == OS.sibling(d2)
+
+
+def _random_workloads():
+    out = []
+    for seed in range(30):
+        out.append(W.meson_ring(n_leaves=7, nvec=4, nt=2, n_graphs=14, lmin=3, lmax=6, seed=seed,
+                                with_data=False))
+    for seed in range(30):
+        out.append(W.baryon_mix(n_bar=4, n_mes=5, nvec=3, nt=2, n_graphs=12, seed=100 + seed,
+                                with_data=False))
+    for seed in range(6):
+        out.append(W.batched_mix(nvecs=(2, 3), nt=2, n_mes=6, n_bar=4, n_graphs=30, seed=200 + seed,
+                                 with_data=False))
+    return out
+
+
+WORKLOADS = _random_workloads()
+
+
+@pytest.mark.parametrize("i", range(len(WORKLOADS)))
+def test_schedules_and_plans_match_oracle(i):
+    wl = WORKLOADS[i]
+    d = OD.build(wl.leaves, wl.graphs)
+    c = ctx_for(wl)
+    kind, left, right = c.nodes()
+    assert list(left) == d.left and list(right) == d.right
+    assert [int(k) for k in kind[d.n_leaves:]] == d.kind[d.n_leaves:]
+    assert list(c.graph_roots()) == d.root_of_graph
+    for policy in ("input", "sibling", "tree"):
+        order = [int(x) for x in c.schedule(policy, check=(policy == "tree"))]
+        assert order == OS.schedule(d, policy), policy
+        for eb in (16, 8):
+            M, pp, pl = c.memsim(order, eb)
+            sim = OS.memsim(d, order, eb)
+            assert list(M) == sim["M"] and pp == sim["peak_post"] and pl == sim["peak_live"]
+        live = OS.memsim(d, order)["peak_live"]
+        for budget in (None, live // 2, live // 3):
+            c.set_mem_budget(budget)
+            for batched in (False, True):
+                for resident in (False, True):
+                    c.set_options(leaves_resident=resident)
+                    ob = OP.UNLIMITED if budget is None else budget
+                    try:
+                        ref = OP.plan(d, order, budget=ob, batched=batched, leaves_resident=resident)
+                    except OP.BudgetError:
+                        with pytest.raises(X.CdagError) as e:
+                            c.plan("fp64", batched)
+                        assert e.value.code == B.E_BUDGET
+                        continue
+                    p = c.plan("fp64", batched)
+                    for k in ("peak_resident", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes"):
+                        assert p[k] == ref[k], (policy, budget, batched, resident, k)
+                    assert p["n_steps"] == ref["n_steps"]
+                    assert c.plan_ops() == ref["ops"]
+                    assert p["tensor_highwater"] >= p["peak_resident"]
+        c.set_options(leaves_resident=False)
+        c.set_mem_budget(None)
+
+
+def test_mixed_precision_plans_halve_sizes():
+    wl = WORKLOADS[3]
+    d = OD.build(wl.leaves, wl.graphs)
+    c = ctx_for(wl)
+    order = [int(x) for x in c.schedule("tree")]
+    live = OS.memsim(d, order, 8)["peak_live"]
+    c.set_mem_budget(live // 3)
+    for prec in ("fp32", "bf16x3"):
+        p = c.plan(prec, True)
+        ref = OP.plan(d, order, elem_bytes=8, budget=live // 3, batched=True)
+        assert p["h2d_bytes"] == ref["h2d_bytes"] and p["n_evict"] == ref["n_evict"]
+
+
+GOLD_FULL = os.path.join(HERE, "golden", "full_configs.json")
+
+
+@pytest.mark.skipif(not os.path.exists(GOLD_FULL), reason="golden file not generated")
+def test_full_configs_match_stored_oracle_results():
+    """Schedules and plans on the full-size workloads against values written by
+    tests/golden/make_full_configs.py (which calls only the oracle)."""
+    import hashlib
+    gold = json.load(open(GOLD_FULL))
+    for name, entry in gold.items():
+        wl = W.config(name, with_data=False)
+        c = ctx_for(wl)
+        for policy, g in entry["policies"].items():
+            order = np.asarray(c.schedule(policy), dtype=np.int64)
+            assert hashlib.sha256(order.tobytes()).hexdigest() == g["order_sha256"], (name, policy)
+            M, pp, pl = c.memsim(order, 16)
+            assert (pp, pl) == (g["peak_post"], g["peak_live"])
+            c.set_mem_budget(entry["budget"])
+            for mode, ref in g["plans"].items():
+                p = c.plan("fp64", mode == "waves")
+                for k, v in ref.items():
+                    assert p[k] == v, (name, policy, mode, k)
+            c.set_mem_budget(None)
+
+
+def test_errors_leave_context_usable():
+    c = X.Context()
+    with pytest.raises(X.CdagError) as e:
+        c.schedule("tree")
+    assert e.value.code == B.E_STATE
+    L = [_L(2), _L(2), _L(3)]
+    bad = [
+        [(W.K22, 0, 0), (W.HCA, -1, 1)],
+        [(W.K22, 0, 1)],
+        [(W.HCA, 0, 1), (W.HCA, 0, 1)],
+        [(W.K22, 0, 7), (W.HCA, -1, 1)],
+        [(W.K22, 0, -1), (W.HCA, -1, 1)],
+        [(W.K22, 2, 1), (W.HCA, -1, 1)],
+        [(W.K22, 0, 1), (W.K22, 1, 0), (W.HCA, -1, 0)],
+        [(9, 0, 1), (W.HCA, -1, 1)],
+    ]
+    for ops in bad:
+        with pytest.raises(X.CdagError) as e:
+            c.build_cdag(L, [_G(ops)])
+        assert e.value.code == B.E_INVALID
+    with pytest.raises(X.CdagError):
+        c.build_cdag([_L(2, nvec=4), _L(2, nvec=5)], [_G([(W.HCA, 0, 1)])])
+    with pytest.raises(X.CdagError):   # one correlator, two Nt
+        c.build_cdag([_L(2, nt=1), _L(2, nt=1), _L(2, nt=2), _L(2, nt=2)],
+                     [_G([(W.HCA, 0, 1)]), _G([(W.HCA, 2, 3)])])
+    # still usable
+    wl = W.fig1_dag("fgh", with_data=False)
+    c.build_cdag(wl.leaves, wl.graphs)
+    assert len(c.schedule("tree")) == 4
+    with pytest.raises(X.CdagError) as e:          # no leaf data
+        c.execute("fp64", False)
+    assert e.value.code == B.E_STATE
+    c.set_mem_budget(2 * 4 * 4 * 16)
+    with pytest.raises(X.CdagError) as e:
+        c.plan("fp64", False)
+    assert e.value.code == B.E_BUDGET
+    c.set_mem_budget(None)
+    assert c.plan("fp64", False)["n_evict"] == 0
+    with pytest.raises(X.CdagError) as e:
+        B._check(B.lib().cdag_plan(c.h, 7, 0, None))
+    assert e.value.code == B.E_INVALID
+    with pytest.raises(X.CdagError) as e:
+        B._check(B.lib().cdag_bind_device(c.h, 0, None, None))
+    assert e.value.code == B.E_INVALID
+
+
+def test_tree_scheduler_speed_full_meson_ring():
+    wl = W.config("meson_ring", with_data=False)
+    c = ctx_for(wl)
+    import time
+    t0 = time.perf_counter()
+    c.schedule("tree")
+    assert time.perf_counter() - t0 < 5.0
