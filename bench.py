@@ -111,7 +111,8 @@ def main():
     ctx.schedule("tree")
     t_sched = time.perf_counter() - t0
     ctx.set_mem_budget(None)
-    ctx.set_options(leaves_resident=True, use_graphs=True)
+    ALL = X.binding.LOOKAHEAD_ALL
+    ctx.set_options(leaves_resident=True, wave_lookahead=ALL, use_graphs=True)
     runner = DeviceRunner(ctx, 0)
 
     # ---- headline: FP64, Tree, waves, leaves resident, graph replay
@@ -127,7 +128,8 @@ def main():
         "config": {"workload": "meson_ring: 16 mesons complex128 [32][64][64], 2000 ring traces "
                                "of 4-8 leaves, merged DAG",
                    "n_contractions": st["plan"]["n_contr"], "n_waves": st["plan"]["n_steps"],
-                   "schedule": "tree", "mode": "waves, hipGraph replay",
+                   "schedule": "tree",
+                   "mode": "waves of every ready contraction, one hipGraph replay",
                    "leaves": "resident in HBM", "flops_per_step": flops,
                    "t_schedule_tree_s": round(t_sched, 4)},
     }
@@ -159,27 +161,34 @@ def main():
             d2, s3 = timed_steps(ctx, runner, prec, True, max(5, args.steps // 2), 2)
             extras[f"{prec}_value"] = round(s3["plan"]["flops"] * max(5, args.steps // 2) / d2 / 1e12, 4)
             extras[f"{prec}_ms_per_step"] = round(d2 / max(5, args.steps // 2) * 1e3, 4)
+        # waves that keep the schedule order exactly (no lookahead)
+        ctx.set_options(leaves_resident=True, wave_lookahead=0, use_graphs=True)
+        d2, s3 = timed_steps(ctx, runner, "fp64", True, max(3, args.steps // 5), 1)
+        extras["fp64_ordered_waves_value"] = round(s3["plan"]["flops"] * max(3, args.steps // 5) / d2 / 1e12, 4)
+        extras["fp64_ordered_waves_n_waves"] = s3["plan"]["n_steps"]
         # per-contraction launches instead of waves
         ctx.set_options(leaves_resident=True, use_graphs=False)
         d2, s3 = timed_steps(ctx, runner, "fp64", False, max(3, args.steps // 10), 1)
         extras["fp64_per_contraction_value"] = round(s3["plan"]["flops"] * max(3, args.steps // 10) / d2 / 1e12, 4)
         # budgeted, leaves start on the host (PCIe-inclusive time-to-solution)
         budgeted = {}
-        ctx.set_options(leaves_resident=False, use_graphs=False)
         for prec in ("fp64", "fp32"):
             ctx.set_mem_budget(budgets[prec])
-            for policy in ("input", "sibling", "tree"):
+            for policy, look in (("input", 0), ("sibling", 0), ("tree", 0), ("tree", ALL)):
+                ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=False)
                 ctx.schedule(policy)
                 reps = 3
                 d2, s3 = timed_steps(ctx, runner, prec, True, reps, 1)
                 p = s3["plan"]
-                budgeted[f"{prec}_{policy}"] = {
+                key = f"{prec}_{policy}" + ("_lookahead" if look else "")
+                budgeted[key] = {
                     "tts_s": round(d2 / reps, 5), "h2d_GB": round(p["h2d_bytes"] / 1e9, 4),
                     "d2h_GB": round(p["d2h_bytes"] / 1e9, 4), "n_evict": p["n_evict"],
                     "n_h2d": p["n_h2d"], "peak_resident_bytes": p["peak_resident"],
                     "peak_post_bytes": p["peak_post"], "budget_bytes": p["budget"],
+                    "n_waves": p["n_steps"],
                     "tflops": round(p["flops"] / (d2 / reps) / 1e12, 3)}
-                log(prec, policy, budgeted[f"{prec}_{policy}"])
+                log(key, budgeted[key])
         extras["budgeted"] = budgeted
         ctx.set_mem_budget(None)
         out["extras"] = extras

@@ -146,9 +146,15 @@ int set_mem_budget(cdag_ctx* c, uint64_t bytes);
 /* leaves_resident: 1 keeps every leaf in a device region of its own, outside
  * the budget, uploaded once per precision (never evicted); 0 (default) makes
  * leaves start on the host as in Sec. II-C.  wave_max: most contractions per
- * wave in batched mode (default 4096).  use_graphs: 1 (default) replays the
- * step sequence from captured HIP graphs. */
-int cdag_set_options(cdag_ctx* c, int leaves_resident, int wave_max, int use_graphs);
+ * wave in batched mode (default 4096).  wave_lookahead: in batched mode a wave
+ * takes the ready contractions (operands are leaves or earlier waves' outputs)
+ * in schedule order and may pass over this many not-ready ones (default 0:
+ * the schedule order is kept exactly; INT64_MAX: every ready contraction).
+ * use_graphs: 1 (default) replays a transfer-free step sequence from a
+ * captured HIP graph.  CDAG_E_INVALID for wave_max < 1 or a negative
+ * lookahead. */
+int cdag_set_options(cdag_ctx* c, int leaves_resident, int wave_max, int64_t wave_lookahead,
+                     int use_graphs);
 
 /* timing: 1 records a HIP event pair around every exterior-contraction launch
  * on the compute stream and reports their summed duration in t_hec_s

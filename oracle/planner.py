@@ -7,10 +7,11 @@ transfers and transfer bytes).  The paper's own memory manager is not
 specified, so the policy here is the plan this engine defines:
 
 Steps.  Per-contraction mode: one step per contraction in schedule order.
-Batched mode: the order is cut greedily, never reordered, into waves; a wave is
-closed before contraction c if (a) an operand of c is produced in the wave,
-(b) the bytes of the wave's distinct operands and outputs with c added would
-exceed the budget, or (c) the wave already holds wave_max contractions.
+Batched mode: waves of ready contractions taken in schedule order (cut_waves);
+with lookahead 0 the order is kept exactly and a wave is closed before
+contraction c if (a) an operand of c is produced in the wave, (b) the bytes of
+the wave's distinct operands and outputs with c added would exceed the budget,
+or (c) the wave already holds wave_max contractions.
 
 Per step s:
   need = bytes of the step's non-resident operands + its outputs.
@@ -44,35 +45,56 @@ class BudgetError(RuntimeError):
 
 
 def cut_waves(d: Dag, order: Sequence[int], size: Sequence[int], budget: int,
-              wave_max: int = WAVE_MAX) -> List[List[int]]:
-    waves, cur, produced, members, members_bytes = [], [], set(), set(), 0
-    for c in order:
-        ops = d.children(c)
-        if cur:
-            extra = sum(size[x] for x in set(ops) | {c} if x not in members)
-            if (any(x in produced for x in ops) or members_bytes + extra > budget
-                    or len(cur) >= wave_max):
-                waves.append(cur)
-                cur, produced, members, members_bytes = [], set(), set(), 0
-        for x in set(ops) | {c}:
-            if x not in members:
-                members.add(x)
-                members_bytes += size[x]
-        cur.append(c)
-        produced.add(c)
-    if cur:
-        waves.append(cur)
+              wave_max: int = WAVE_MAX, lookahead: int = 0) -> List[List[int]]:
+    """Waves in schedule order.  A contraction is ready when every operand is a leaf
+    or was produced by an earlier wave.  Scanning the not yet placed contractions
+    in order, a wave takes each ready one and passes over at most `lookahead`
+    that are not ready; it closes at the next not-ready one after that, or when
+    adding a contraction would make its distinct operands and outputs exceed the
+    budget, or when it holds wave_max contractions.  lookahead = 0 keeps the
+    order exactly (a wave ends where a contraction needs one of its outputs)."""
+    n = len(order)
+    placed = [False] * n
+    produced = set()
+    waves = []
+    start = 0
+    while start < n:
+        wave, members, mbytes, skipped = [], set(), 0, 0
+        for pos in range(start, n):
+            if placed[pos]:
+                continue
+            c = order[pos]
+            ops = d.children(c)
+            if not all(d.kind[x] < 0 or x in produced for x in ops):
+                skipped += 1
+                if skipped > lookahead:
+                    break
+                continue
+            new = {x for x in set(ops) | {c} if x not in members}
+            extra = sum(size[x] for x in new)
+            if wave and (mbytes + extra > budget or len(wave) >= wave_max):
+                break
+            wave.append(c)
+            placed[pos] = True
+            members |= new
+            mbytes += extra
+        produced.update(wave)
+        waves.append(wave)
+        while start < n and placed[start]:
+            start += 1
     return waves
 
 
 def plan(d: Dag, order: Sequence[int], elem_bytes: int = 16, budget: int = UNLIMITED,
-         batched: bool = False, wave_max: int = WAVE_MAX, leaves_resident: bool = False) -> dict:
+         batched: bool = False, wave_max: int = WAVE_MAX, leaves_resident: bool = False,
+         lookahead: int = 0) -> dict:
     n = d.n_nodes
     size = [d.size(u, elem_bytes) for u in range(n)]
     if leaves_resident:
         for u in range(d.n_leaves):
             size[u] = 0
-    steps = cut_waves(d, order, size, budget, wave_max) if batched else [[c] for c in order]
+    steps = (cut_waves(d, order, size, budget, wave_max, lookahead) if batched
+             else [[c] for c in order])
 
     uses: List[List[int]] = [[] for _ in range(n)]
     for s, wave in enumerate(steps):

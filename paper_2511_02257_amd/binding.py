@@ -65,11 +65,21 @@ _lib = None
 
 
 def lib():
-    """Load the built library (raises if it has not been built)."""
+    """Load the built library (raises if it has not been built).
+
+    PyTorch ships its own HIP runtime under the same soname as the system one.
+    torch is imported first so that the library binds to that same runtime:
+    the arena pointer and stream handles it borrows from torch are only valid
+    inside the runtime that created them, and two runtimes in one process do
+    not share the device."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2511_02257_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, I64, I32 = C.c_void_p, C.c_int64, C.c_int32
         sig = {
@@ -78,7 +88,7 @@ def lib():
             "build_cdag": [P, C.POINTER(cdag_leaf), I64, C.POINTER(cdag_graph), I64],
             "schedule": [P, C.c_int, C.POINTER(I64), I64, C.POINTER(I64)],
             "set_mem_budget": [P, C.c_uint64],
-            "cdag_set_options": [P, C.c_int, C.c_int, C.c_int],
+            "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
             "cdag_set_timing": [P, C.c_int],
             "cdag_memsim": [P, C.POINTER(I64), I64, C.c_int, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
             "cdag_plan": [P, C.c_int, C.c_int, C.POINTER(cdag_plan_stats)],
@@ -175,8 +185,13 @@ def set_mem_budget(h, nbytes: Optional[int]) -> None:
     _check(lib().set_mem_budget(h, UNLIMITED if nbytes is None else int(nbytes)))
 
 
-def cdag_set_options(h, leaves_resident=False, wave_max=4096, use_graphs=True) -> None:
-    _check(lib().cdag_set_options(h, int(leaves_resident), int(wave_max), int(use_graphs)))
+LOOKAHEAD_ALL = (1 << 63) - 1
+
+
+def cdag_set_options(h, leaves_resident=False, wave_max=4096, wave_lookahead=0,
+                     use_graphs=True) -> None:
+    _check(lib().cdag_set_options(h, int(leaves_resident), int(wave_max), int(wave_lookahead),
+                                  int(use_graphs)))
 
 
 def cdag_set_timing(h, on: bool) -> None:
@@ -304,8 +319,8 @@ class Context:
     def set_mem_budget(self, nbytes):
         set_mem_budget(self.h, nbytes)
 
-    def set_options(self, leaves_resident=False, wave_max=4096, use_graphs=True):
-        cdag_set_options(self.h, leaves_resident, wave_max, use_graphs)
+    def set_options(self, leaves_resident=False, wave_max=4096, wave_lookahead=0, use_graphs=True):
+        cdag_set_options(self.h, leaves_resident, wave_max, wave_lookahead, use_graphs)
 
     def set_timing(self, on=True):
         cdag_set_timing(self.h, on)

@@ -63,6 +63,7 @@ void ensure_plan(Ctx& c, int prec, int batched) {
   o.budget = c.budget;
   o.batched = batched != 0;
   o.wave_max = c.wave_max;
+  o.lookahead = c.wave_lookahead;
   o.leaves_resident = c.leaves_resident;
   c.plan = make_plan(c.dag, c.order, o);
   place(c.dag, c.plan);
@@ -183,12 +184,15 @@ int set_mem_budget(cdag_ctx* h, uint64_t bytes) {
   });
 }
 
-int cdag_set_options(cdag_ctx* h, int leaves_resident, int wave_max, int use_graphs) {
+int cdag_set_options(cdag_ctx* h, int leaves_resident, int wave_max, int64_t wave_lookahead,
+                     int use_graphs) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {
     need(wave_max >= 1, CDAG_E_INVALID, "wave_max must be >= 1");
+    need(wave_lookahead >= 0, CDAG_E_INVALID, "wave_lookahead must be >= 0");
     h->c.leaves_resident = leaves_resident != 0;
     h->c.wave_max = wave_max;
+    h->c.wave_lookahead = wave_lookahead;
     h->c.use_graphs = use_graphs != 0;
     h->c.version++;
   });

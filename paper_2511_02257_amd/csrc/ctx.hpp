@@ -29,6 +29,7 @@ struct Ctx {
   int64_t budget = INT64_MAX;
   bool leaves_resident = false;
   int64_t wave_max = 4096;
+  int64_t wave_lookahead = 0;
   bool use_graphs = true;
   bool timing = false;
   uint64_t version = 1;          // bumped by every change that invalidates a plan

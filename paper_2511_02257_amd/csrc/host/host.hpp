@@ -86,6 +86,7 @@ struct PlanOpts {
   int64_t budget = INT64_MAX;
   bool batched = false;
   int64_t wave_max = 4096;
+  int64_t lookahead = 0;
   bool leaves_resident = false;
 };
 
@@ -104,7 +105,7 @@ struct Plan {
 
 std::vector<std::vector<int64_t>> cut_waves(const Dag& d, const std::vector<int64_t>& order,
                                             const std::vector<int64_t>& size, int64_t budget,
-                                            int64_t wave_max);
+                                            int64_t wave_max, int64_t lookahead);
 Plan make_plan(const Dag& d, const std::vector<int64_t>& order, const PlanOpts& o);
 // Assign arena offsets (256-byte aligned, best fit) and host spill offsets,
 // and derive the cross-stream waits.

@@ -3,10 +3,11 @@
 //
 // The paper counts evictions, transfers and transfer bytes (Sec. IV-C) but its
 // memory manager is not specified; this plan is the engine's own policy:
-//   steps     one per contraction, or greedy order-preserving waves closed
-//             before c when (a) an operand of c is produced in the wave, (b) the
-//             bytes of the wave's distinct operands and outputs with c would
-//             exceed the budget, or (c) the wave holds wave_max contractions;
+//   steps     one per contraction, or waves of ready contractions in schedule
+//             order (cut_waves); with lookahead 0 the order is kept and a wave
+//             closes before c when (a) an operand of c is produced in the wave,
+//             (b) the bytes of the wave's distinct operands and outputs with c
+//             would exceed the budget, or (c) the wave holds wave_max;
 //   eviction  while used + need > budget, evict the resident tensor that is
 //             not an operand of the step with the furthest next use (ties:
 //             larger size, then smaller id); leaves and already-spilled
@@ -26,30 +27,42 @@ namespace cdag {
 
 std::vector<std::vector<int64_t>> cut_waves(const Dag& d, const std::vector<int64_t>& order,
                                             const std::vector<int64_t>& size, int64_t budget,
-                                            int64_t wave_max) {
+                                            int64_t wave_max, int64_t lookahead) {
+  // A contraction is ready when both operands are leaves or outputs of earlier
+  // waves.  Scanning unplaced contractions in schedule order, a wave takes each
+  // ready one and passes over at most `lookahead` not-ready ones; it closes at
+  // the next not-ready one, when the distinct operand and output bytes would
+  // exceed the budget, or at wave_max contractions.
   std::vector<std::vector<int64_t>> waves;
-  std::vector<int64_t> member(d.n_nodes(), -1), produced(d.n_nodes(), -1);
-  std::vector<int64_t> cur;
-  int64_t wid = 0, bytes = 0;
-  auto add = [&](int64_t x) -> int64_t { return member[x] == wid ? 0 : size[x]; };
-  for (int64_t c : order) {
-    const int64_t l = d.left[c], r = d.right[c];
-    if (!cur.empty()) {
-      int64_t extra = add(l) + add(r) + add(c);
-      if (produced[l] == wid || produced[r] == wid || bytes + extra > budget ||
-          (int64_t)cur.size() >= wave_max) {
-        waves.push_back(std::move(cur));
-        cur.clear();
-        ++wid;
-        bytes = 0;
+  const int64_t n = (int64_t)order.size();
+  std::vector<char> placed(n, 0), produced(d.n_nodes(), 0);
+  std::vector<int64_t> member(d.n_nodes(), -1);
+  int64_t start = 0, wid = 0;
+  auto ready = [&](int64_t x) { return d.is_leaf(x) || produced[x]; };
+  while (start < n) {
+    std::vector<int64_t> wave;
+    int64_t bytes = 0, skipped = 0;
+    for (int64_t pos = start; pos < n; ++pos) {
+      if (placed[pos]) continue;
+      const int64_t c = order[pos], l = d.left[c], r = d.right[c];
+      if (!ready(l) || !ready(r)) {
+        if (++skipped > lookahead) break;
+        continue;
       }
+      int64_t extra = 0;
+      for (int64_t x : {l, r, c})
+        if (member[x] != wid) extra += size[x];
+      if (!wave.empty() && (bytes + extra > budget || (int64_t)wave.size() >= wave_max)) break;
+      for (int64_t x : {l, r, c}) member[x] = wid;
+      bytes += extra;
+      wave.push_back(c);
+      placed[pos] = 1;
     }
-    for (int64_t x : {l, r, c})
-      if (member[x] != wid) { member[x] = wid; bytes += size[x]; }
-    cur.push_back(c);
-    produced[c] = wid;
+    for (int64_t c : wave) produced[c] = 1;
+    waves.push_back(std::move(wave));
+    ++wid;
+    while (start < n && placed[start]) ++start;
   }
-  if (!cur.empty()) waves.push_back(std::move(cur));
   return waves;
 }
 
@@ -62,7 +75,7 @@ Plan make_plan(const Dag& d, const std::vector<int64_t>& order, const PlanOpts& 
   if (o.leaves_resident)
     for (int64_t u = 0; u < d.n_leaves; ++u) size[u] = 0;
   if (o.batched) {
-    p.steps = cut_waves(d, order, size, o.budget, o.wave_max);
+    p.steps = cut_waves(d, order, size, o.budget, o.wave_max, o.lookahead);
   } else {
     p.steps.reserve(order.size());
     for (int64_t c : order) p.steps.push_back({c});

@@ -10,14 +10,15 @@ from oracle import values as OV
 
 
 def run(wl, policy="tree", prec="fp64", batched=False, budget=None, leaves_resident=False,
-        use_graphs=True, wave_max=4096, device=0, runner_cache={}):
+        use_graphs=True, wave_max=4096, wave_lookahead=0, device=0):
     import paper_2511_02257_amd as X
     from paper_2511_02257_amd.device import DeviceRunner
     ctx = X.Context()
     ctx.build_cdag(wl.leaves, wl.graphs)
     order = ctx.schedule(policy)
     ctx.set_mem_budget(budget)
-    ctx.set_options(leaves_resident=leaves_resident, wave_max=wave_max, use_graphs=use_graphs)
+    ctx.set_options(leaves_resident=leaves_resident, wave_max=wave_max,
+                    wave_lookahead=wave_lookahead, use_graphs=use_graphs)
     runner = DeviceRunner(ctx, device)
     st = runner.run(prec, batched)
     corr = ctx.fetch_correlators()
@@ -44,11 +45,11 @@ def sum_errors(wl, sums, ref_vals):
     return worst
 
 
-def oracle_plan_counts(wl, policy, elem_bytes, budget, batched, leaves_resident=False):
+def oracle_plan_counts(wl, policy, elem_bytes, budget, batched, leaves_resident=False, lookahead=0):
     from oracle import planner as OP
     d = OD.build(wl.leaves, wl.graphs)
     order = OS.schedule(d, policy, elem_bytes)
     res = OP.plan(d, order, elem_bytes=elem_bytes,
                   budget=OP.UNLIMITED if budget is None else budget,
-                  batched=batched, leaves_resident=leaves_resident)
+                  batched=batched, leaves_resident=leaves_resident, lookahead=lookahead)
     return d, order, res

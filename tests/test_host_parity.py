@@ -106,12 +106,13 @@ def test_schedules_and_plans_match_oracle(i):
         live = OS.memsim(d, order)["peak_live"]
         for budget in (None, live // 2, live // 3):
             c.set_mem_budget(budget)
-            for batched in (False, True):
+            for batched, look in ((False, 0), (True, 0), (True, 3), (True, B.LOOKAHEAD_ALL)):
                 for resident in (False, True):
-                    c.set_options(leaves_resident=resident)
+                    c.set_options(leaves_resident=resident, wave_lookahead=look)
                     ob = OP.UNLIMITED if budget is None else budget
                     try:
-                        ref = OP.plan(d, order, budget=ob, batched=batched, leaves_resident=resident)
+                        ref = OP.plan(d, order, budget=ob, batched=batched, leaves_resident=resident,
+                                      lookahead=look)
                     except OP.BudgetError:
                         with pytest.raises(X.CdagError) as e:
                             c.plan("fp64", batched)
@@ -123,7 +124,7 @@ def test_schedules_and_plans_match_oracle(i):
                     assert p["n_steps"] == ref["n_steps"]
                     assert c.plan_ops() == ref["ops"]
                     assert p["tensor_highwater"] >= p["peak_resident"]
-        c.set_options(leaves_resident=False)
+        c.set_options(leaves_resident=False, wave_lookahead=0)
         c.set_mem_budget(None)
 
 

@@ -178,6 +178,33 @@ def test_budget_error_when_one_step_does_not_fit():
         P.plan(d, order, budget=2 * d.size(0))
 
 
+@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("lookahead", [1, 4, 1 << 62])
+def test_lookahead_waves(seed, lookahead):
+    d = ring(seed, n_leaves=7, n_graphs=12) if seed % 2 else mix(seed)
+    order = S.schedule(d, "tree")
+    live = S.memsim(d, order)["peak_live"]
+    for budget in (P.UNLIMITED, live // 2):
+        try:
+            res = P.plan(d, order, budget=budget, batched=True, lookahead=lookahead)
+        except P.BudgetError:
+            continue
+        execs = replay(d, res, budget)
+        assert sorted(execs) == sorted(order)
+        done = set()
+        for w in res["steps"]:          # every operand produced by an earlier wave
+            for c in w:
+                assert all(d.kind[x] < 0 or x in done for x in d.children(c))
+            done.update(w)
+    # unlimited lookahead and budget: waves are the dependency levels
+    res = P.plan(d, order, batched=True, lookahead=1 << 62)
+    level = {}
+    for c in order:
+        level[c] = 1 + max([level.get(x, 0) for x in d.children(c)])
+    assert [sorted(w) for w in res["steps"]] == [
+        sorted(c for c in order if level[c] == k) for k in range(1, max(level.values()) + 1)]
+
+
 def test_wave_cut_rules():
     d = mix(3, n_graphs=12)
     order = S.schedule(d, "tree")
