@@ -199,8 +199,8 @@ int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
 int fetch_correlators(cdag_ctx* c, double* out, int64_t cap_doubles);
 
 /* Per correlator c = 0..max(corr_id), S_c(t) = sum_{g: corr_id = c} w_g C_g(t)
- * summed in FP64 in ascending g; 2 * sum_c nt(c) doubles (nt of a correlator
- * with no graph is 0). */
+ * summed in FP64 in a fixed order (identical from run to run); 2 * sum_c nt(c)
+ * doubles (nt of a correlator with no graph is 0). */
 int cdag_fetch_sums(cdag_ctx* c, double* out, int64_t cap_doubles);
 
 #ifdef __cplusplus

@@ -36,8 +36,8 @@ struct HcaDesc {
   int32_t n, nt, item_begin, pad;              // items: one per time slice
 };
 
-// Cross-diagram sum for one correlator: sum over entries [e_begin, e_end) of
-// w * C_root(t), in entry order (ascending input graph).
+// Cross-diagram sum for one correlator: sum over entries [e_begin, e_end)
+// (ascending input graph) of w * C_root(t), in a fixed order.
 struct XsumDesc {
   int64_t out_off;                             // [nt][2] doubles
   int32_t e_begin, e_end, nt, pad;

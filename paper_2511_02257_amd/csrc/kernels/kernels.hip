@@ -429,21 +429,39 @@ __global__ void __launch_bounds__(256) hca_trace(char* __restrict__ arena, const
 }
 
 // ------------------------------------------------------------------ cross-diagram sum (FP64)
-__global__ void __launch_bounds__(64) xsum_kernel(char* __restrict__ arena, const XsumDesc* __restrict__ descs,
-                                                  const XsumEntry* __restrict__ entries, int n_desc) {
+// One workgroup per correlator.  Thread i sums the entries i, i + 256, ... in
+// that order; the 256 partial sums are then added in a fixed tree.  The order
+// is fixed, so the result does not change from run to run.
+__global__ void __launch_bounds__(256) xsum_kernel(char* __restrict__ arena, const XsumDesc* __restrict__ descs,
+                                                   const XsumEntry* __restrict__ entries, int n_desc) {
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x;
   for (int c = blockIdx.x; c < n_desc; c += gridDim.x) {
     const XsumDesc& x = descs[c];
     double* out = reinterpret_cast<double*>(arena + x.out_off);
-    for (int t = threadIdx.x; t < x.nt; t += blockDim.x) {
+    for (int t = 0; t < x.nt; ++t) {
       double sr = 0.0, si = 0.0;
-      for (int e = x.e_begin; e < x.e_end; ++e) {     // ascending graph order
+      for (int e = x.e_begin + tid; e < x.e_end; e += 256) {
         const double* C = reinterpret_cast<const double*>(arena + entries[e].root_off);
         const double cr = C[2 * t], ci = C[2 * t + 1];
         sr += entries[e].w_re * cr - entries[e].w_im * ci;
         si += entries[e].w_re * ci + entries[e].w_im * cr;
       }
-      out[2 * t] = sr;
-      out[2 * t + 1] = si;
+      red[0][tid] = sr;
+      red[1][tid] = si;
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) {
+          red[0][tid] += red[0][tid + w];
+          red[1][tid] += red[1][tid + w];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        out[2 * t] = red[0][0];
+        out[2 * t + 1] = red[1][0];
+      }
+      __syncthreads();
     }
   }
 }
@@ -486,7 +504,7 @@ hipError_t launch_hca(int prec, char* arena, int64_t desc_off, int n_desc, int64
 hipError_t launch_xsum(char* arena, int64_t desc_off, int64_t entries_off, int n_desc, hipStream_t s) {
   const XsumDesc* d = reinterpret_cast<const XsumDesc*>(arena + desc_off);
   const XsumEntry* e = reinterpret_cast<const XsumEntry*>(arena + entries_off);
-  hipLaunchKernelGGL(xsum_kernel, dim3(grid_for(n_desc)), dim3(64), 0, s, arena, d, e, n_desc);
+  hipLaunchKernelGGL(xsum_kernel, dim3(grid_for(n_desc)), dim3(256), 0, s, arena, d, e, n_desc);
   return hipGetLastError();
 }
 

@@ -1,0 +1,80 @@
+"""GPU parity at full size (marked gpu): the meson and baryon workloads in the
+launch configurations bench.py times, against the oracle.
+
+The meson workload's 2000 correlators are all computed by the oracle (a few
+seconds); the baryon workload's by sampling graphs the oracle evaluates one by
+one.  Plan counters must equal the stored oracle values
+(tests/golden/full_configs.json, written by make_full_configs.py).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from synth import workloads as W
+from oracle import values as OV
+
+from gpu_util import run, rel_errors, sum_errors
+
+pytestmark = pytest.mark.gpu
+
+ALL = (1 << 63) - 1
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "full_configs.json")))
+
+
+@pytest.fixture(scope="module")
+def meson():
+    wl = W.config("meson_ring")
+    return wl, OV.correlators(wl)
+
+
+def test_meson_ring_full_fp64_bench_configuration(meson):
+    wl, ref = meson
+    r = run(wl, "tree", "fp64", True, leaves_resident=True, wave_lookahead=ALL, use_graphs=True)
+    err = rel_errors(r["corr"], ref)
+    print(f"meson_ring fp64 resident waves={r['stats']['plan']['n_steps']} max rel {err.max():.3e}")
+    assert err.max() <= 1e-12
+    assert sum_errors(wl, r["sums"], ref) <= 1e-12
+    # the budgeted run (leaves on the host, a quarter of the input-order live peak)
+    gold = GOLD["meson_ring"]
+    b = run(wl, "tree", "fp64", True, budget=gold["budget"], wave_lookahead=0)
+    p = b["stats"]["plan"]
+    for k, v in gold["policies"]["tree"]["plans"]["waves"].items():
+        assert p[k] == v, k
+    assert np.array_equal(np.concatenate(b["corr"]).view(np.uint64),
+                          np.concatenate(r["corr"]).view(np.uint64))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 4e-5)])
+def test_meson_ring_full_mixed(meson, prec, tol):
+    wl, ref = meson
+    r = run(wl, "tree", prec, True, leaves_resident=True, wave_lookahead=ALL, use_graphs=True)
+    err = rel_errors(r["corr"], ref)
+    print(f"meson_ring {prec}: max rel {err.max():.3e} median {np.median(err):.3e} "
+          f"p99 {np.quantile(err, 0.99):.3e}")
+    assert err.max() <= tol
+    assert sum_errors(wl, r["sums"], ref) <= tol
+
+
+@pytest.fixture(scope="module")
+def baryon():
+    wl = W.config("baryon_mix")
+    rng = np.random.default_rng(77)
+    sample = sorted(int(g) for g in rng.choice(len(wl.graphs), size=10, replace=False))
+    return wl, sample, OV.correlators(wl, sample)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 4e-5)])
+def test_baryon_mix_full_sampled(baryon, prec, tol):
+    wl, sample, ref = baryon
+    budget = 32 * 10**9 if prec == "fp64" else 16 * 10**9
+    r = run(wl, "tree", prec, True, budget=budget, wave_lookahead=0)
+    p = r["stats"]["plan"]
+    if prec == "fp64":
+        for k, v in GOLD["baryon_mix"]["policies"]["tree"]["plans"]["waves"].items():
+            assert p[k] == v, k
+    err = np.array([np.linalg.norm(r["corr"][g] - ref[g]) / np.linalg.norm(ref[g]) for g in sample])
+    print(f"baryon_mix {prec}: waves={p['n_steps']} max rel {err.max():.3e} median {np.median(err):.3e} "
+          f"device {r['stats']['t_device_s'] * 1e3:.1f} ms, {p['flops'] / r['stats']['t_device_s'] / 1e12:.1f} TFLOP/s")
+    assert err.max() <= tol
