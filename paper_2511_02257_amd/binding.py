@@ -90,6 +90,8 @@ def lib():
             "set_mem_budget": [P, C.c_uint64],
             "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
             "cdag_set_timing": [P, C.c_int],
+            "cdag_set_tile": [P, C.c_int, C.c_int, C.c_int, C.c_int],
+            "cdag_get_tile": [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)],
             "cdag_memsim": [P, C.POINTER(I64), I64, C.c_int, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
             "cdag_plan": [P, C.c_int, C.c_int, C.POINTER(cdag_plan_stats)],
             "cdag_plan_ops": [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64), I64, C.POINTER(I64)],
@@ -98,6 +100,7 @@ def lib():
             "cdag_bind_device": [P, C.c_int, P, P],
             "cdag_bind_arena": [P, P, C.c_uint64],
             "execute": [P, C.c_int, C.c_int, C.POINTER(cdag_exec_stats)],
+            "cdag_autotune": [P, C.c_int, C.c_int, C.c_int, C.POINTER(I64)],
             "fetch_correlators": [P, C.POINTER(C.c_double), I64],
             "cdag_fetch_sums": [P, C.POINTER(C.c_double), I64],
         }
@@ -112,9 +115,9 @@ def lib():
 
 
 EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "schedule",
-            "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_memsim", "cdag_plan", "cdag_plan_ops",
+            "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_set_tile", "cdag_get_tile", "cdag_memsim", "cdag_plan", "cdag_plan_ops",
             "cdag_get_nodes", "cdag_graph_roots", "cdag_bind_device", "cdag_bind_arena",
-            "execute", "fetch_correlators", "cdag_fetch_sums")
+            "execute", "cdag_autotune", "fetch_correlators", "cdag_fetch_sums")
 
 
 def _check(rc: int):
@@ -198,6 +201,19 @@ def cdag_set_timing(h, on: bool) -> None:
     _check(lib().cdag_set_timing(h, int(bool(on))))
 
 
+TILES = {0: (64, 64), 1: (32, 32), 2: (48, 48), 3: (128, 64), 4: (64, 32)}
+
+
+def cdag_set_tile(h, prec: str, kind: int, nvec: int, tile: int) -> None:
+    _check(lib().cdag_set_tile(h, PREC[prec], int(kind), int(nvec), int(tile)))
+
+
+def cdag_get_tile(h, prec: str, kind: int, nvec: int) -> int:
+    t = C.c_int()
+    _check(lib().cdag_get_tile(h, PREC[prec], int(kind), int(nvec), C.byref(t)))
+    return t.value
+
+
 def cdag_memsim(h, order: Sequence[int], elem_bytes: int = 16):
     o = np.ascontiguousarray(order, dtype=np.int64)
     M = np.empty(max(1, o.size), dtype=np.int64)
@@ -252,6 +268,12 @@ def execute(h, prec: str = "fp64", batched: bool = False) -> dict:
     st = cdag_exec_stats()
     _check(lib().execute(h, PREC[prec], int(batched), C.byref(st)))
     return _struct_dict(st)
+
+
+def cdag_autotune(h, prec: str = "fp64", batched: bool = True, reps: int = 3) -> int:
+    n = C.c_int64()
+    _check(lib().cdag_autotune(h, PREC[prec], int(batched), int(reps), C.byref(n)))
+    return n.value
 
 
 def fetch_correlators(h, nts: Sequence[int]) -> List[np.ndarray]:
@@ -325,6 +347,12 @@ class Context:
     def set_timing(self, on=True):
         cdag_set_timing(self.h, on)
 
+    def set_tile(self, prec, kind, nvec, tile):
+        cdag_set_tile(self.h, prec, kind, nvec, tile)
+
+    def get_tile(self, prec, kind, nvec):
+        return cdag_get_tile(self.h, prec, kind, nvec)
+
     def memsim(self, order, elem_bytes=16):
         return cdag_memsim(self.h, order, elem_bytes)
 
@@ -348,6 +376,9 @@ class Context:
 
     def execute(self, prec="fp64", batched=False):
         return execute(self.h, prec, batched)
+
+    def autotune(self, prec="fp64", batched=True, reps=3):
+        return cdag_autotune(self.h, prec, batched, reps)
 
     def fetch_correlators(self):
         return fetch_correlators(self.h, self.graph_nt)

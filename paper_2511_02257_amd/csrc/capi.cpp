@@ -67,7 +67,7 @@ void ensure_plan(Ctx& c, int prec, int batched) {
   o.leaves_resident = c.leaves_resident;
   c.plan = make_plan(c.dag, c.order, o);
   place(c.dag, c.plan);
-  c.kplan = make_kernel_plan(c.dag, c.plan, prec);
+  c.kplan = make_kernel_plan(c.dag, c.plan, prec, c.tiles);
   MemSim ms = memsim(c.dag, c.order, eb);
   c.peak_post = ms.peak_post;
   c.peak_live = ms.peak_live;
@@ -203,6 +203,29 @@ int cdag_set_timing(cdag_ctx* h, int timing) {
   return guard([&] { h->c.timing = timing != 0; });
 }
 
+int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    elem_bytes_prec(prec);
+    need(kind >= CDAG_K22 && kind <= CDAG_K33, CDAG_E_INVALID, "kind must be K22, K32 or K33");
+    need(nvec >= 1, CDAG_E_INVALID, "nvec must be >= 1");
+    need(tile >= -1 && tile < cdag::kNumTiles, CDAG_E_INVALID, "tile out of range");
+    auto key = std::make_tuple(prec, kind, nvec);
+    if (tile < 0) h->c.tiles.erase(key); else h->c.tiles[key] = tile;
+    h->c.version++;
+  });
+}
+
+int cdag_get_tile(cdag_ctx* h, int prec, int kind, int nvec, int* tile) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    elem_bytes_prec(prec);
+    need(tile != nullptr, CDAG_E_INVALID, "tile is NULL");
+    auto it = h->c.tiles.find(std::make_tuple(prec, kind, nvec));
+    *tile = it != h->c.tiles.end() ? it->second : cdag::default_tile(prec, kind, nvec);
+  });
+}
+
 int cdag_memsim(cdag_ctx* h, const int64_t* order, int64_t n, int elem_bytes, int64_t* M_out,
                 int64_t* peak_post, int64_t* peak_live) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
@@ -333,6 +356,20 @@ int execute(cdag_ctx* h, int prec, int batched, cdag_exec_stats* out) {
     fill_plan_stats(c, &st.plan);
     c.have_results = true;
     if (out) *out = st;
+  });
+}
+
+int cdag_autotune(cdag_ctx* h, int prec, int batched, int reps, int64_t* n_tuned) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    cdag::Ctx& c = h->c;
+    need(reps >= 1, CDAG_E_INVALID, "reps must be >= 1");
+    need(c.dev != nullptr, CDAG_E_STATE, "cdag_bind_device first");
+    cdag::ensure_plan(c, prec, batched);
+    int64_t n = cdag::device_autotune(c, prec, batched, reps);
+    c.version++;
+    c.have_results = false;
+    if (n_tuned) *n_tuned = n;
   });
 }
 

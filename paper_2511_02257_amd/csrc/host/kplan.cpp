@@ -32,11 +32,41 @@ void gemm_dims(const Dag& d, int64_t u, int32_t* M, int32_t* N, int32_t* K) {
   }
 }
 
-KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec) {
+void decompose(int kind, int n, int nt, int tile, int prec, HecDesc* h) {
+  const int ks = k_step(prec);
+  switch (kind) {
+    case K22: h->M = n; h->N = n; h->K = n; break;
+    case K32: h->M = n * n; h->N = n; h->K = n; break;
+    default: h->M = n; h->N = n; h->K = n * n; break;
+  }
+  const TileShape& ts = kTileShapes[tile];
+  h->nt = nt;
+  h->tiles_m = (h->M + ts.bm - 1) / ts.bm;
+  h->tiles_n = (h->N + ts.bn - 1) / ts.bn;
+  const int64_t base = (int64_t)h->nt * h->tiles_m * h->tiles_n;
+  int64_t splits = std::min<int64_t>((kSplitTarget + base - 1) / base, h->K / kMinKSplit);
+  splits = std::max<int64_t>(splits, 1);
+  int64_t kspl = (h->K + splits - 1) / splits;
+  kspl = (kspl + ks - 1) / ks * ks;
+  splits = (h->K + kspl - 1) / kspl;
+  h->splits = (int32_t)splits;
+  h->k_split = (int32_t)kspl;
+  h->tile_count = (int32_t)(base * splits);
+}
+
+int default_tile(int prec, int kind, int n) {
+  (void)prec;
+  (void)kind;
+  if (n % 64 == 0) return 0;   // 64 x 64
+  if (n % 48 == 0) return 2;   // 48 x 48
+  if (n % 32 == 0 || n < 32) return 1;   // 32 x 32
+  return 0;
+}
+
+KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTable& tiles) {
   KernelPlan kp;
   kp.prec = prec;
   const int64_t acc_bytes = prec == CDAG_FP64 ? 8 : 4;   // one real accumulator
-  const int ks = k_step(prec);
   const int64_t S = (int64_t)p.steps.size();
 
   // tree index of each root, correlator buffers
@@ -63,20 +93,12 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec) {
 
   // split-K decision per contraction (independent of batching, so results do
   // not depend on how contractions are grouped into launches)
+  auto tile_of = [&](int64_t u) -> int {
+    auto it = tiles.find(std::make_tuple(prec, (int)d.kind[u], (int)d.nvec[u]));
+    return it != tiles.end() ? it->second : default_tile(prec, d.kind[u], d.nvec[u]);
+  };
   auto decomp = [&](int64_t u, HecDesc& h) {
-    gemm_dims(d, u, &h.M, &h.N, &h.K);
-    h.nt = d.nt[u];
-    h.tiles_m = (h.M + kTileM - 1) / kTileM;
-    h.tiles_n = (h.N + kTileN - 1) / kTileN;
-    int64_t base = (int64_t)h.nt * h.tiles_m * h.tiles_n;
-    int64_t splits = std::min<int64_t>((kSplitTarget + base - 1) / base, h.K / kMinKSplit);
-    splits = std::max<int64_t>(splits, 1);
-    int64_t kspl = (h.K + splits - 1) / splits;
-    kspl = (kspl + ks - 1) / ks * ks;
-    splits = (h.K + kspl - 1) / kspl;
-    h.splits = (int32_t)splits;
-    h.k_split = (int32_t)kspl;
-    h.tile_count = (int32_t)(base * splits);
+    decompose(d.kind[u], d.nvec[u], d.nt[u], tile_of(u), prec, &h);
   };
 
   // pass 1: workspace size (max over steps) and descriptor counts
@@ -97,10 +119,11 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec) {
   kp.launch_off.reserve(S + 1);
   for (int64_t s = 0; s < S; ++s) {
     kp.launch_off.push_back((int64_t)kp.launches.size());
-    std::vector<HecDesc> hec;
+    std::vector<HecDesc> hec[kNumTiles];
+    int64_t tiles[kNumTiles] = {0};
     std::vector<RedDesc> red;
     std::vector<HcaDesc> hca;
-    int64_t ws = kp.ws_off, tiles = 0, items = 0;
+    int64_t ws = kp.ws_off, items = 0;
     for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
       const PlanRec& r = p.recs[ri];
       if (r.op != OP_EXEC) continue;
@@ -118,6 +141,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec) {
       }
       HecDesc h{};
       decomp(u, h);
+      const int tl = tile_of(u);
       kp.hec_flops += d.flops(u);
       kp.hec_bytes += (double)h.nt * ((double)h.M * h.K + (double)h.K * h.N + (double)h.M * h.N) *
                       (double)elem_bytes_of(prec);
@@ -125,8 +149,8 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec) {
       h.b_off = r.b_off;
       h.c_off = r.dev_off;
       h.ws_off = -1;
-      h.tile_begin = (int32_t)tiles;
-      tiles += h.tile_count;
+      h.tile_begin = (int32_t)tiles[tl];
+      tiles[tl] += h.tile_count;
       if (h.splits > 1) {
         h.ws_off = ws;
         RedDesc rd{};
@@ -140,22 +164,23 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec) {
         red.push_back(rd);
         ws += align256((int64_t)h.splits * h.nt * 2 * h.M * h.N * acc_bytes);
       }
-      hec.push_back(h);
+      hec[tl].push_back(h);
     }
-    if (!hec.empty()) {
-      Launch L{L_HEC, (int32_t)hec.size(), 0, tiles, 0};
+    for (int tl = 0; tl < kNumTiles; ++tl) {
+      if (hec[tl].empty()) continue;
+      Launch L{L_HEC, tl, (int32_t)hec[tl].size(), 0, tiles[tl], 0};
       L.host_desc = (int64_t)kp.blob.size();
-      for (auto& h : hec) put(kp.blob, h);
+      for (auto& h : hec[tl]) put(kp.blob, h);
       kp.launches.push_back(L);
     }
     if (!red.empty()) {
-      Launch L{L_RED, (int32_t)red.size(), 0, items, 0};
+      Launch L{L_RED, 0, (int32_t)red.size(), 0, items, 0};
       L.host_desc = (int64_t)kp.blob.size();
       for (auto& x : red) put(kp.blob, x);
       kp.launches.push_back(L);
     }
     if (!hca.empty()) {
-      Launch L{L_HCA, (int32_t)hca.size(), 0, 0, 0};
+      Launch L{L_HCA, 0, (int32_t)hca.size(), 0, 0, 0};
       for (auto& h : hca) { h.item_begin = (int32_t)L.n_items; L.n_items += h.nt; }
       L.host_desc = (int64_t)kp.blob.size();
       for (auto& h : hca) put(kp.blob, h);
@@ -180,7 +205,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec) {
     xd.push_back(x);
   }
   while (kp.blob.size() % 16) kp.blob.push_back(0);
-  kp.xsum = {L_XSUM, (int32_t)xd.size(), 0, (int64_t)xd.size(), (int64_t)kp.blob.size()};
+  kp.xsum = {L_XSUM, 0, (int32_t)xd.size(), 0, (int64_t)xd.size(), (int64_t)kp.blob.size()};
   for (auto& x : xd) put(kp.blob, x);
   const int64_t entries_host = (int64_t)kp.blob.size();
   for (auto& e : xe) put(kp.blob, e);

@@ -3,6 +3,8 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "host.hpp"
@@ -14,14 +16,20 @@ enum LaunchType : int32_t { L_HEC = 0, L_RED = 1, L_HCA = 2, L_XSUM = 3 };
 
 struct Launch {
   int32_t type;
+  int32_t tile;       // HEC: index into kTileShapes
   int32_t n_desc;
   int64_t desc_off;   // arena offset of the first descriptor
   int64_t n_items;    // HEC: tiles; RED: 256-element blocks; HCA: (root, t) pairs; XSUM: correlators
   int64_t host_desc;  // byte offset of the first descriptor in KernelPlan::blob
 };
 
-// Exterior-contraction tile shape (both precisions' kernels use it).
-constexpr int kTileM = 64, kTileN = 64;
+// Tile choice per (precision, kind, N): an explicit table entry (set through
+// the ABI or by the autotuner) wins, else default_tile().
+using TileTable = std::map<std::tuple<int, int, int>, int>;
+int default_tile(int prec, int kind, int n);
+// GEMM dimensions, tile counts and split-K of one contraction of `kind` with
+// N = n, nt time slices and tile shape `tile` (offsets and tile_begin unset).
+void decompose(int kind, int n, int nt, int tile, int prec, HecDesc* h);
 // k-step of the matrix-core kernels: FP64 and FP32 use 16, split-BF16 32.
 inline int k_step(int prec) { return prec == 2 ? 32 : 16; }
 // Split-K: aim for at least this many work items per contraction, keeping at
@@ -51,6 +59,6 @@ struct KernelPlan {
 
 int64_t elem_bytes_of(int prec);                 // 16 for FP64, 8 otherwise
 void gemm_dims(const Dag& d, int64_t u, int32_t* M, int32_t* N, int32_t* K);
-KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec);
+KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTable& tiles);
 
 }  // namespace cdag

@@ -8,6 +8,10 @@
 // i.e. four real products per complex multiply-add (the 8-flop ZGEMM count).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+
 #include "desc.hpp"
 #include "kernels.hpp"
 
@@ -18,8 +22,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef short v8s __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 64, BN = 64, NTH = 256;
-
 __device__ __forceinline__ int find_desc(const int32_t* first, int stride_words, int n, int64_t item) {
   // largest i with first[i * stride] <= item (first[0] == 0)
   int lo = 0, hi = n - 1;
@@ -28,6 +30,46 @@ __device__ __forceinline__ int find_desc(const int32_t* first, int stride_words,
     if ((int64_t)first[(int64_t)mid * stride_words] <= item) lo = mid; else hi = mid - 1;
   }
   return lo;
+}
+
+// Tile configuration: WGM x WGN waves per workgroup, each holding TM x TN
+// blocks of 16 x 16 outputs; the workgroup tile is BM x BN.
+template <int WGM_, int WGN_, int TM_, int TN_>
+struct Tile {
+  static constexpr int WGM = WGM_, WGN = WGN_, TM = TM_, TN = TN_;
+  static constexpr int NTH = 64 * WGM * WGN;
+  static constexpr int BM = 16 * WGM * TM, BN = 16 * WGN * TN;
+};
+// Must match kTileShapes in desc.hpp, entry by entry.
+typedef Tile<2, 2, 2, 2> Tile0;   //  64 x 64, 256 threads
+typedef Tile<2, 2, 1, 1> Tile1;   //  32 x 32, 256 threads
+typedef Tile<1, 1, 3, 3> Tile2;   //  48 x 48,  64 threads
+typedef Tile<2, 2, 4, 2> Tile3;   // 128 x 64, 256 threads
+typedef Tile<2, 2, 2, 1> Tile4;   //  64 x 32, 256 threads
+
+struct WorkItem {
+  const HecDesc* h;
+  int t, m0, n0, sp, kbeg, kend;
+};
+
+template <int BM, int BN>
+__device__ __forceinline__ WorkItem decode_item(const HecDesc* descs, int n_desc, int64_t item) {
+  WorkItem w;
+  const int di = find_desc(&descs[0].tile_begin, sizeof(HecDesc) / 4, n_desc, item);
+  const HecDesc* h = &descs[di];
+  int64_t local = item - h->tile_begin;
+  w.sp = (int)(local % h->splits);
+  local /= h->splits;
+  const int tn = (int)(local % h->tiles_n);
+  local /= h->tiles_n;
+  const int tm = (int)(local % h->tiles_m);
+  w.t = (int)(local / h->tiles_m);
+  w.m0 = tm * BM;
+  w.n0 = tn * BN;
+  w.kbeg = w.sp * h->k_split;
+  w.kend = min(h->K, w.kbeg + h->k_split);
+  w.h = h;
+  return w;
 }
 
 // ------------------------------------------------------------------ FP64 / FP32
@@ -55,10 +97,6 @@ template <typename T> struct Vec2;
 template <> struct Vec2<double> { typedef double2 V; static constexpr int n = 2; };
 template <> struct Vec2<float> { typedef float4 V; static constexpr int n = 4; };
 
-constexpr int BK = 16;
-constexpr int APAD = BK + 1;    // A tile row stride in LDS (elements)
-constexpr int BPAD = BN + 16;   // B tile row stride in LDS (elements)
-
 // 8 consecutive elements of one row: vector loads when fully in range and the
 // row is 8-element aligned, otherwise element-wise with zero fill.
 template <typename T>
@@ -80,83 +118,121 @@ __device__ __forceinline__ void load8(T (&r)[8], const T* src, int valid, bool v
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(NTH) hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs,
-                                                 int n_desc, int64_t n_items) {
+// Store one 16x16 block pair (Re, Im) of accumulators with the instruction's
+// row layout; rows and columns outside M x N are skipped.
+template <typename T, typename V>
+__device__ __forceinline__ void store_block(T* C, int M, int N, int row0, int col, const V& re, const V& im,
+                                           int lk) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int m = row0 + Mfma<T>::row(lk, v);
+    if (m < M && col < N) {
+      C[(int64_t)m * N + col] = re[v];
+      C[(int64_t)M * N + (int64_t)m * N + col] = im[v];
+    }
+  }
+}
+
+template <typename T, class TL>
+__global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs,
+                                                     int n_desc, int64_t n_items) {
   typedef typename Mfma<T>::V V;
+  constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
+  constexpr int BK = 16, APAD = BK + 1, BPAD = BN + 16;
+  // the A tile is split into 8-element row segments: [plane][row][k / 8]
+  constexpr int SEGA = 2 * BM * (BK / 8), SEGB = 2 * BK * (BN / 8);
+  constexpr int LA = (SEGA + NTH - 1) / NTH, LB = (SEGB + NTH - 1) / NTH;
   __shared__ T As[2][2][BM][APAD];   // [stage][plane][m][k]
   __shared__ T Bs[2][2][BK][BPAD];   // [stage][plane][k][n]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1, li = lane & 15, lk = lane >> 4;
-  // load roles
-  const int ap = tid >> 7, ar = (tid >> 1) & 63, ah = tid & 1;
-  const int bp = tid >> 7, bk = (tid >> 3) & 15, bs = tid & 7;
+  const int wm = wave / TL::WGN, wn = wave % TL::WGN, li = lane & 15, lk = lane >> 4;
 
   for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-    const int di = find_desc(&descs[0].tile_begin, sizeof(HecDesc) / 4, n_desc, item);
-    const HecDesc& h = descs[di];
-    int64_t local = item - h.tile_begin;
-    const int sp = (int)(local % h.splits);
-    local /= h.splits;
-    const int tn = (int)(local % h.tiles_n);
-    local /= h.tiles_n;
-    const int tm = (int)(local % h.tiles_m);
-    const int t = (int)(local / h.tiles_m);
+    const WorkItem w = decode_item<BM, BN>(descs, n_desc, item);
+    const HecDesc& h = *w.h;
     const int M = h.M, N = h.N, K = h.K;
-    const int m0 = tm * BM, n0 = tn * BN;
-    const int kbeg = sp * h.k_split, kend = min(K, kbeg + h.k_split);
-    const T* A = reinterpret_cast<const T*>(arena + h.a_off) + (int64_t)t * 2 * M * K;
-    const T* B = reinterpret_cast<const T*>(arena + h.b_off) + (int64_t)t * 2 * K * N;
+    const T* A = reinterpret_cast<const T*>(arena + h.a_off) + (int64_t)w.t * 2 * M * K;
+    const T* B = reinterpret_cast<const T*>(arena + h.b_off) + (int64_t)w.t * 2 * K * N;
     const bool avec = (K & 7) == 0, bvec = (N & 7) == 0;
 
-    V cr[2][2], ci[2][2];
+    V cr[TM][TN], ci[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) { cr[i][j] = V{0, 0, 0, 0}; ci[i][j] = V{0, 0, 0, 0}; }
+      for (int j = 0; j < TN; ++j) { cr[i][j] = V{0, 0, 0, 0}; ci[i][j] = V{0, 0, 0, 0}; }
 
-    T ra[8], rb[8];
+    T ra[LA][8], rb[LB][8];
     auto gload = [&](int k0) {
-      const int am = m0 + ar, ak = k0 + 8 * ah;
-      const int av = am < M ? max(0, min(8, kend - ak)) : 0;
-      load8<T>(ra, A + (int64_t)ap * M * K + (int64_t)am * K + ak, av, avec);
-      const int bkk = k0 + bk, bn = n0 + 8 * bs;
-      const int bv = bkk < kend ? max(0, min(8, N - bn)) : 0;
-      load8<T>(rb, B + (int64_t)bp * K * N + (int64_t)bkk * N + bn, bv, bvec);
+#pragma unroll
+      for (int q = 0; q < LA; ++q) {
+        const int seg = tid + q * NTH;
+        if (seg < SEGA) {
+          const int p = seg / (2 * BM), r = (seg % (2 * BM)) >> 1, hh = seg & 1;
+          const int am = w.m0 + r, ak = k0 + 8 * hh;
+          const int av = am < M ? max(0, min(8, w.kend - ak)) : 0;
+          load8<T>(ra[q], A + (int64_t)p * M * K + (int64_t)am * K + ak, av, avec);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int seg = tid + q * NTH;
+        if (seg < SEGB) {
+          const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
+          const int kk = rem / (BN / 8), sg = rem % (BN / 8);
+          const int bkk = k0 + kk, bn = w.n0 + 8 * sg;
+          const int bv = bkk < w.kend ? max(0, min(8, N - bn)) : 0;
+          load8<T>(rb[q], B + (int64_t)p * K * N + (int64_t)bkk * N + bn, bv, bvec);
+        }
+      }
     };
     auto sstore = [&](int st) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) As[st][ap][ar][8 * ah + i] = ra[i];
+      for (int q = 0; q < LA; ++q) {
+        const int seg = tid + q * NTH;
+        if (seg < SEGA) {
+          const int p = seg / (2 * BM), r = (seg % (2 * BM)) >> 1, hh = seg & 1;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[st][bp][bk][8 * bs + i] = rb[i];
+          for (int i = 0; i < 8; ++i) As[st][p][r][8 * hh + i] = ra[q][i];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < LB; ++q) {
+        const int seg = tid + q * NTH;
+        if (seg < SEGB) {
+          const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
+          const int kk = rem / (BN / 8), sg = rem % (BN / 8);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) Bs[st][p][kk][8 * sg + i] = rb[q][i];
+        }
+      }
     };
 
-    const int nk = (kend - kbeg + BK - 1) / BK;
-    gload(kbeg);
+    const int nk = (w.kend - w.kbeg + BK - 1) / BK;
+    gload(w.kbeg);
     sstore(0);
     __syncthreads();
     for (int c = 0; c < nk; ++c) {
       const int st = c & 1;
-      if (c + 1 < nk) gload(kbeg + (c + 1) * BK);
+      if (c + 1 < nk) gload(w.kbeg + (c + 1) * BK);
 #pragma unroll
       for (int k4 = 0; k4 < BK / 4; ++k4) {
         const int kk = 4 * k4 + lk;
-        T a_r[2], a_i[2], b_r[2], b_i[2], b_n[2];
+        T a_r[TM], a_i[TM], b_r[TN], b_i[TN], b_n[TN];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          a_r[i] = As[st][0][wm * 32 + i * 16 + li][kk];
-          a_i[i] = As[st][1][wm * 32 + i * 16 + li][kk];
+        for (int i = 0; i < TM; ++i) {
+          a_r[i] = As[st][0][(wm * TM + i) * 16 + li][kk];
+          a_i[i] = As[st][1][(wm * TM + i) * 16 + li][kk];
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          b_r[j] = Bs[st][0][kk][wn * 32 + j * 16 + li];
-          b_i[j] = Bs[st][1][kk][wn * 32 + j * 16 + li];
+        for (int j = 0; j < TN; ++j) {
+          b_r[j] = Bs[st][0][kk][(wn * TN + j) * 16 + li];
+          b_i[j] = Bs[st][1][kk][(wn * TN + j) * 16 + li];
           b_n[j] = -b_i[j];
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
+          for (int j = 0; j < TN; ++j) {
             cr[i][j] = Mfma<T>::mma(a_r[i], b_r[j], cr[i][j]);
             cr[i][j] = Mfma<T>::mma(a_i[i], b_n[j], cr[i][j]);
             ci[i][j] = Mfma<T>::mma(a_r[i], b_i[j], ci[i][j]);
@@ -167,26 +243,17 @@ __global__ void __launch_bounds__(NTH) hec_mfma(char* __restrict__ arena, const 
       __syncthreads();
     }
 
-    // epilogue: lane holds rows Mfma<T>::row(lk, v), column li of each 16x16 sub-tile
     T* C;
     if (h.splits > 1)
-      C = reinterpret_cast<T*>(arena + h.ws_off) + ((int64_t)sp * h.nt + t) * 2 * M * N;
+      C = reinterpret_cast<T*>(arena + h.ws_off) + ((int64_t)w.sp * h.nt + w.t) * 2 * M * N;
     else
-      C = reinterpret_cast<T*>(arena + h.c_off) + (int64_t)t * 2 * M * N;
+      C = reinterpret_cast<T*>(arena + h.c_off) + (int64_t)w.t * 2 * M * N;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = n0 + wn * 32 + j * 16 + li;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int m = m0 + wm * 32 + i * 16 + Mfma<T>::row(lk, v);
-          if (m < M && n < N) {
-            C[(int64_t)m * N + n] = cr[i][j][v];
-            C[(int64_t)M * N + (int64_t)m * N + n] = ci[i][j][v];
-          }
-        }
-      }
+      for (int j = 0; j < TN; ++j)
+        store_block<T, V>(C, M, N, w.m0 + (wm * TM + i) * 16, w.n0 + (wn * TN + j) * 16 + li, cr[i][j],
+                          ci[i][j], lk);
   }
 }
 
@@ -194,113 +261,117 @@ __global__ void __launch_bounds__(NTH) hec_mfma(char* __restrict__ arena, const 
 // Each FP32 operand x is split as hi = bf16(x), lo = bf16(x - hi); a real
 // product is approximated by hi*hi' + hi*lo' + lo*hi' (the lo*lo' term is
 // dropped), accumulated in FP32 on the bf16 matrix cores.
-constexpr int BK3 = 32;
-constexpr int A3PAD = BK3 + 8;   // bf16 elements per A row in LDS (16-byte aligned rows)
-constexpr int B3PAD = BK3 + 8;   // B is stored transposed: [n][k]
-
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
 }
 
-__global__ void __launch_bounds__(NTH) hec_bf16x3(char* __restrict__ arena, const HecDesc* __restrict__ descs,
-                                                   int n_desc, int64_t n_items) {
-  // [stage][plane][hi/lo][row][k]: A rows are m, B rows are n (transposed)
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][2][BM][A3PAD];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][2][BN][B3PAD];
+template <class TL>
+__global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, const HecDesc* __restrict__ descs,
+                                                       int n_desc, int64_t n_items) {
+  constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
+  constexpr int BK = 32, PAD = BK + 8;     // bf16 per LDS row (16-byte aligned rows)
+  constexpr int SEGA = 2 * BM * (BK / 8), SEGB = 2 * BK * (BN / 8);
+  constexpr int LA = (SEGA + NTH - 1) / NTH, LB = (SEGB + NTH - 1) / NTH;
+  // [stage][plane][hi/lo][row][k]: A rows are m, B rows are n (B is stored transposed)
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][2][BM][PAD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][2][BN][PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1, li = lane & 15, lk = lane >> 4;
-  // A: 64 rows x 32 k x 2 planes = 4096 floats, 16 per thread: plane, row, half
-  const int ap = tid >> 7, ar = (tid >> 1) & 63, ah = tid & 1;
-  // B: 32 k x 64 n x 2 planes: plane, k row, 16-column segment
-  const int bp = tid >> 7, bk = (tid >> 2) & 31, bs = tid & 3;
+  const int wm = wave / TL::WGN, wn = wave % TL::WGN, li = lane & 15, lk = lane >> 4;
 
   for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-    const int di = find_desc(&descs[0].tile_begin, sizeof(HecDesc) / 4, n_desc, item);
-    const HecDesc& h = descs[di];
-    int64_t local = item - h.tile_begin;
-    const int sp = (int)(local % h.splits);
-    local /= h.splits;
-    const int tn = (int)(local % h.tiles_n);
-    local /= h.tiles_n;
-    const int tm = (int)(local % h.tiles_m);
-    const int t = (int)(local / h.tiles_m);
+    const WorkItem w = decode_item<BM, BN>(descs, n_desc, item);
+    const HecDesc& h = *w.h;
     const int M = h.M, N = h.N, K = h.K;
-    const int m0 = tm * BM, n0 = tn * BN;
-    const int kbeg = sp * h.k_split, kend = min(K, kbeg + h.k_split);
-    const float* A = reinterpret_cast<const float*>(arena + h.a_off) + (int64_t)t * 2 * M * K;
-    const float* B = reinterpret_cast<const float*>(arena + h.b_off) + (int64_t)t * 2 * K * N;
+    const float* A = reinterpret_cast<const float*>(arena + h.a_off) + (int64_t)w.t * 2 * M * K;
+    const float* B = reinterpret_cast<const float*>(arena + h.b_off) + (int64_t)w.t * 2 * K * N;
     const bool avec = (K & 7) == 0, bvec = (N & 7) == 0;
 
-    v4f cr[2][2], ci[2][2];
+    v4f cr[TM][TN], ci[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) { cr[i][j] = v4f{0, 0, 0, 0}; ci[i][j] = v4f{0, 0, 0, 0}; }
+      for (int j = 0; j < TN; ++j) { cr[i][j] = v4f{0, 0, 0, 0}; ci[i][j] = v4f{0, 0, 0, 0}; }
 
-    float ra[16], rb[16];
+    float ra[LA][8], rb[LB][8];
     auto gload = [&](int k0) {
-      const int am = m0 + ar;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int ak = k0 + 16 * ah + 8 * q;
-        const int av = am < M ? max(0, min(8, kend - ak)) : 0;
-        float tmp[8];
-        load8<float>(tmp, A + (int64_t)ap * M * K + (int64_t)am * K + ak, av, avec);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) ra[8 * q + i] = tmp[i];
+      for (int q = 0; q < LA; ++q) {
+        const int seg = tid + q * NTH;
+        if (seg < SEGA) {
+          const int p = seg / (4 * BM), r = (seg % (4 * BM)) >> 2, qq = seg & 3;
+          const int am = w.m0 + r, ak = k0 + 8 * qq;
+          const int av = am < M ? max(0, min(8, w.kend - ak)) : 0;
+          load8<float>(ra[q], A + (int64_t)p * M * K + (int64_t)am * K + ak, av, avec);
+        }
       }
-      const int bkk = k0 + bk;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int bn = n0 + 16 * bs + 8 * q;
-        const int bv = bkk < kend ? max(0, min(8, N - bn)) : 0;
-        float tmp[8];
-        load8<float>(tmp, B + (int64_t)bp * K * N + (int64_t)bkk * N + bn, bv, bvec);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) rb[8 * q + i] = tmp[i];
+      for (int q = 0; q < LB; ++q) {
+        const int seg = tid + q * NTH;
+        if (seg < SEGB) {
+          const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
+          const int kk = rem / (BN / 8), sg = rem % (BN / 8);
+          const int bkk = k0 + kk, bn = w.n0 + 8 * sg;
+          const int bv = bkk < w.kend ? max(0, min(8, N - bn)) : 0;
+          load8<float>(rb[q], B + (int64_t)p * K * N + (int64_t)bkk * N + bn, bv, bvec);
+        }
       }
     };
     auto sstore = [&](int st) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        __bf16 hi, lo;
-        split_bf16(ra[i], hi, lo);
-        As[st][ap][0][ar][16 * ah + i] = hi;
-        As[st][ap][1][ar][16 * ah + i] = lo;
+      for (int q = 0; q < LA; ++q) {
+        const int seg = tid + q * NTH;
+        if (seg < SEGA) {
+          const int p = seg / (4 * BM), r = (seg % (4 * BM)) >> 2, qq = seg & 3;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            __bf16 hi, lo;
+            split_bf16(ra[q][i], hi, lo);
+            As[st][p][0][r][8 * qq + i] = hi;
+            As[st][p][1][r][8 * qq + i] = lo;
+          }
+        }
       }
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        __bf16 hi, lo;
-        split_bf16(rb[i], hi, lo);
-        Bs[st][bp][0][16 * bs + i][bk] = hi;
-        Bs[st][bp][1][16 * bs + i][bk] = lo;
+      for (int q = 0; q < LB; ++q) {
+        const int seg = tid + q * NTH;
+        if (seg < SEGB) {
+          const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
+          const int kk = rem / (BN / 8), sg = rem % (BN / 8);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            __bf16 hi, lo;
+            split_bf16(rb[q][i], hi, lo);
+            Bs[st][p][0][8 * sg + i][kk] = hi;
+            Bs[st][p][1][8 * sg + i][kk] = lo;
+          }
+        }
       }
     };
 
-    const int nk = (kend - kbeg + BK3 - 1) / BK3;
-    gload(kbeg);
+    const int nk = (w.kend - w.kbeg + BK - 1) / BK;
+    gload(w.kbeg);
     sstore(0);
     __syncthreads();
     for (int c = 0; c < nk; ++c) {
       const int st = c & 1;
-      if (c + 1 < nk) gload(kbeg + (c + 1) * BK3);
+      if (c + 1 < nk) gload(w.kbeg + (c + 1) * BK);
       // one 16x16x32 step: lane holds k = 8*lk .. 8*lk+7 of row li (A) / column li (B)
-      v8bf a[2][2][2], b[2][2][2], bn_hi[2], bn_lo[2];   // [sub][plane][hi/lo]
+      v8bf a[TM][2][2], b[TN][2][2], bn_hi[TN], bn_lo[TN];   // [block][plane][hi/lo]
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-          for (int s = 0; s < 2; ++s)
-            a[i][p][s] = *reinterpret_cast<const v8bf*>(&As[st][p][s][wm * 32 + i * 16 + li][8 * lk]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
           for (int s = 0; s < 2; ++s)
-            b[j][p][s] = *reinterpret_cast<const v8bf*>(&Bs[st][p][s][wn * 32 + j * 16 + li][8 * lk]);
+            a[i][p][s] = *reinterpret_cast<const v8bf*>(&As[st][p][s][(wm * TM + i) * 16 + li][8 * lk]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int s = 0; s < 2; ++s)
+            b[j][p][s] = *reinterpret_cast<const v8bf*>(&Bs[st][p][s][(wn * TN + j) * 16 + li][8 * lk]);
         // -Bi: flip the bf16 sign bits
         v8s hs = *reinterpret_cast<v8s*>(&b[j][1][0]) ^ (short)0x8000;
         v8s ls = *reinterpret_cast<v8s*>(&b[j][1][1]) ^ (short)0x8000;
@@ -308,10 +379,10 @@ __global__ void __launch_bounds__(NTH) hec_bf16x3(char* __restrict__ arena, cons
         bn_lo[j] = *reinterpret_cast<v8bf*>(&ls);
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br, each with hi*hi + hi*lo + lo*hi
+        for (int j = 0; j < TN; ++j) {
+          // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br, each with lo*hi + hi*lo + hi*hi
 #define MM(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc, 0, 0, 0)
           MM(cr[i][j], a[i][0][1], b[j][0][0]);
           MM(cr[i][j], a[i][0][0], b[j][0][1]);
@@ -333,23 +404,15 @@ __global__ void __launch_bounds__(NTH) hec_bf16x3(char* __restrict__ arena, cons
 
     float* C;
     if (h.splits > 1)
-      C = reinterpret_cast<float*>(arena + h.ws_off) + ((int64_t)sp * h.nt + t) * 2 * M * N;
+      C = reinterpret_cast<float*>(arena + h.ws_off) + ((int64_t)w.sp * h.nt + w.t) * 2 * M * N;
     else
-      C = reinterpret_cast<float*>(arena + h.c_off) + (int64_t)t * 2 * M * N;
+      C = reinterpret_cast<float*>(arena + h.c_off) + (int64_t)w.t * 2 * M * N;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = n0 + wn * 32 + j * 16 + li;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int m = m0 + wm * 32 + i * 16 + 4 * lk + v;
-          if (m < M && n < N) {
-            C[(int64_t)m * N + n] = cr[i][j][v];
-            C[(int64_t)M * N + (int64_t)m * N + n] = ci[i][j][v];
-          }
-        }
-      }
+      for (int j = 0; j < TN; ++j)
+        store_block<float, v4f>(C, M, N, w.m0 + (wm * TM + i) * 16, w.n0 + (wn * TN + j) * 16 + li,
+                                cr[i][j], ci[i][j], lk);
   }
 }
 
@@ -468,20 +531,72 @@ __global__ void __launch_bounds__(256) xsum_kernel(char* __restrict__ arena, con
 
 // ------------------------------------------------------------------ launchers
 namespace {
+// Persistent launches: at most as many workgroups as can be resident at once
+// (compute units x occupancy of the kernel); each loops over work items with
+// a grid stride.  The occupancy query is made once per kernel.
+template <typename F>
+unsigned persistent_grid(F kernel, int block, int64_t items) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;   // (kernel, device) -> resident workgroups
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), dev);
+  int resident;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+      int cus = 0, per_cu = 0;
+      if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+        resident = 1 << 16;
+      else
+        resident = cus * per_cu;
+      cache.emplace(key, resident);
+    } else {
+      resident = it->second;
+    }
+  }
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, resident));
+}
 constexpr int64_t kMaxGrid = 1 << 20;
 unsigned grid_for(int64_t items) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, kMaxGrid)); }
 }  // namespace
 
-hipError_t launch_hec(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s) {
+template <class TL>
+void launch_hec_tile(int prec, char* arena, const HecDesc* d, int n_desc, int64_t n_items, hipStream_t s) {
+  const dim3 block(TL::NTH);
+  if (prec == 0) {
+    const dim3 grid(persistent_grid(hec_mfma<double, TL>, TL::NTH, n_items));
+    hipLaunchKernelGGL((hec_mfma<double, TL>), grid, block, 0, s, arena, d, n_desc, n_items);
+  } else if (prec == 1) {
+    const dim3 grid(persistent_grid(hec_mfma<float, TL>, TL::NTH, n_items));
+    hipLaunchKernelGGL((hec_mfma<float, TL>), grid, block, 0, s, arena, d, n_desc, n_items);
+  } else {
+    const dim3 grid(persistent_grid(hec_bf16x3<TL>, TL::NTH, n_items));
+    hipLaunchKernelGGL((hec_bf16x3<TL>), grid, block, 0, s, arena, d, n_desc, n_items);
+  }
+}
+
+hipError_t launch_hec(int prec, int tile, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
+                      hipStream_t s) {
   const HecDesc* d = reinterpret_cast<const HecDesc*>(arena + desc_off);
-  if (prec == 0)
-    hipLaunchKernelGGL(hec_mfma<double>, dim3(grid_for(n_items)), dim3(NTH), 0, s, arena, d, n_desc, n_items);
-  else if (prec == 1)
-    hipLaunchKernelGGL(hec_mfma<float>, dim3(grid_for(n_items)), dim3(NTH), 0, s, arena, d, n_desc, n_items);
-  else
-    hipLaunchKernelGGL(hec_bf16x3, dim3(grid_for(n_items)), dim3(NTH), 0, s, arena, d, n_desc, n_items);
+  switch (tile) {
+    case 0: launch_hec_tile<Tile0>(prec, arena, d, n_desc, n_items, s); break;
+    case 1: launch_hec_tile<Tile1>(prec, arena, d, n_desc, n_items, s); break;
+    case 2: launch_hec_tile<Tile2>(prec, arena, d, n_desc, n_items, s); break;
+    case 3: launch_hec_tile<Tile3>(prec, arena, d, n_desc, n_items, s); break;
+    case 4: launch_hec_tile<Tile4>(prec, arena, d, n_desc, n_items, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
+
+static_assert(Tile0::BM == kTileShapes[0].bm && Tile0::BN == kTileShapes[0].bn && Tile0::NTH == kTileShapes[0].nth, "tile 0");
+static_assert(Tile1::BM == kTileShapes[1].bm && Tile1::BN == kTileShapes[1].bn && Tile1::NTH == kTileShapes[1].nth, "tile 1");
+static_assert(Tile2::BM == kTileShapes[2].bm && Tile2::BN == kTileShapes[2].bn && Tile2::NTH == kTileShapes[2].nth, "tile 2");
+static_assert(Tile3::BM == kTileShapes[3].bm && Tile3::BN == kTileShapes[3].bn && Tile3::NTH == kTileShapes[3].nth, "tile 3");
+static_assert(Tile4::BM == kTileShapes[4].bm && Tile4::BN == kTileShapes[4].bn && Tile4::NTH == kTileShapes[4].nth, "tile 4");
 
 hipError_t launch_reduce(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s) {
   const RedDesc* d = reinterpret_cast<const RedDesc*>(arena + desc_off);

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <string>
 #include <thread>
 
@@ -54,10 +55,21 @@ struct Device {
   uint64_t blob_key = 0, blob_epoch = 0;
   int resident_prec = -1;
   uint64_t resident_key = 0, resident_epoch = 0;
-  // captured launch sequence
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  uint64_t graph_key = 0, graph_epoch = 0;
+  // captured step sequence: one graph per segment of consecutive steps
+  hipStream_t cap_comp = nullptr, cap_copy = nullptr;   // capture origin and its copy branch
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::vector<hipGraph_t> seg_graph;
+  std::vector<hipGraphExec_t> seg_exec;
+  uint64_t graph_key = 0, graph_epoch = 0, graph_stage = 0;
+  void* graph_spill = nullptr;
+
+  void drop_graphs() {
+    for (auto g : seg_exec) ignore(hipGraphExecDestroy(g));
+    for (auto g : seg_graph) ignore(hipGraphDestroy(g));
+    seg_exec.clear();
+    seg_graph.clear();
+    graph_key = 0;
+  }
   // timing mode: event pairs around exterior-contraction launches
   std::vector<hipEvent_t> tpool;
   size_t tnext = 0;
@@ -74,8 +86,11 @@ struct Device {
 
   ~Device() {
     if (device >= 0) ignore(hipSetDevice(device));
-    if (gexec) ignore(hipGraphExecDestroy(gexec));
-    if (graph) ignore(hipGraphDestroy(graph));
+    drop_graphs();
+    if (cap_comp) ignore(hipStreamDestroy(cap_comp));
+    if (cap_copy) ignore(hipStreamDestroy(cap_copy));
+    if (ev_fork) ignore(hipEventDestroy(ev_fork));
+    if (ev_join) ignore(hipEventDestroy(ev_join));
     for (auto e : ev_comp) ignore(hipEventDestroy(e));
     for (auto e : ev_copy) ignore(hipEventDestroy(e));
     for (auto e : tpool) ignore(hipEventDestroy(e));
@@ -107,8 +122,11 @@ void device_bind(Ctx& c, int device, void* compute_stream, void* copy_stream) {
   if (!c.dev->t0) {
     HIPC(hipEventCreate(&c.dev->t0));
     HIPC(hipEventCreate(&c.dev->t1));
+    HIPC(hipEventCreateWithFlags(&c.dev->ev_fork, hipEventDisableTiming));
+    HIPC(hipEventCreateWithFlags(&c.dev->ev_join, hipEventDisableTiming));
+    HIPC(hipStreamCreateWithFlags(&c.dev->cap_comp, hipStreamNonBlocking));
+    HIPC(hipStreamCreateWithFlags(&c.dev->cap_copy, hipStreamNonBlocking));
   }
-  c.dev->graph_key = 0;   // captured graphs name the old streams' work; recapture
 }
 
 void device_bind_arena(Ctx& c, void* arena, uint64_t bytes) {
@@ -191,11 +209,11 @@ int64_t launch_step(const KernelPlan& kp, int64_t s, int prec, char* arena, hipS
         if (timed) {
           hipEvent_t a = timed->timing_event(), b = timed->timing_event();
           HIPC(hipEventRecord(a, st));
-          HIPC(launch_hec(prec, arena, L.desc_off, L.n_desc, L.n_items, st));
+          HIPC(launch_hec(prec, L.tile, arena, L.desc_off, L.n_desc, L.n_items, st));
           HIPC(hipEventRecord(b, st));
           timed->tpairs.push_back({a, b});
         } else {
-          HIPC(launch_hec(prec, arena, L.desc_off, L.n_desc, L.n_items, st));
+          HIPC(launch_hec(prec, L.tile, arena, L.desc_off, L.n_desc, L.n_items, st));
         }
         break;
       case L_RED: HIPC(launch_reduce(prec, arena, L.desc_off, L.n_desc, L.n_items, st)); break;
@@ -206,7 +224,138 @@ int64_t launch_step(const KernelPlan& kp, int64_t s, int prec, char* arena, hipS
   }
   return n;
 }
+
+// Enqueue steps [s0, s1): copies on `copy`, kernels on `comp`, cross-stream
+// waits from the plan.  In a captured segment, waits on steps before s0 are
+// left out: the segments' graphs run one after another on one stream, so
+// everything before s0 has finished when the segment starts.
+int64_t issue_steps(Ctx& c, Device& D, int prec, int64_t s0, int64_t s1, hipStream_t comp,
+                    hipStream_t copy, Device* timed, bool in_capture) {
+  const Plan& p = c.plan;
+  const KernelPlan& kp = c.kplan;
+  const int eb = prec == CDAG_FP64 ? 16 : 8;
+  int64_t copy_waited = in_capture ? s0 - 1 : -1, comp_waited = in_capture ? s0 - 1 : -1;
+  int64_t n_launch = 0;
+  for (int64_t s = s0; s < s1; ++s) {
+    bool any_copy = false, any_h2d = false;
+    int64_t need_copy = -1;
+    for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
+      const PlanRec& r = p.recs[ri];
+      const size_t sz = (size_t)c.dag.size(r.node, eb);
+      if (r.op == OP_D2H || r.op == OP_H2D) {
+        if (r.wait_comp > copy_waited) {
+          HIPC(hipStreamWaitEvent(copy, D.ev_comp[r.wait_comp], 0));
+          copy_waited = r.wait_comp;
+        }
+        if (r.op == OP_D2H) {
+          HIPC(hipMemcpyAsync((char*)D.spill + r.host_off, D.arena + r.dev_off, sz, hipMemcpyDeviceToHost, copy));
+        } else {
+          const void* src = c.dag.is_leaf(r.node) ? D.stage[prec][r.node] : (const void*)((char*)D.spill + r.host_off);
+          HIPC(hipMemcpyAsync(D.arena + r.dev_off, src, sz, hipMemcpyHostToDevice, copy));
+          any_h2d = true;
+        }
+        any_copy = true;
+      } else if (r.op == OP_ALLOC && r.wait_copy >= 0) {
+        need_copy = std::max(need_copy, r.wait_copy);
+      }
+    }
+    if (any_copy) HIPC(hipEventRecord(D.ev_copy[s], copy));
+    if (any_h2d) need_copy = std::max(need_copy, s);
+    if (need_copy > comp_waited) {
+      HIPC(hipStreamWaitEvent(comp, D.ev_copy[need_copy], 0));
+      comp_waited = need_copy;
+    }
+    n_launch += launch_step(kp, s, prec, D.arena, comp, timed);
+    HIPC(hipEventRecord(D.ev_comp[s], comp));
+  }
+  return n_launch;
+}
+
+constexpr int64_t kSegmentSteps = 64;   // steps per captured graph when transfers are present
 }  // namespace
+
+// Autotuner: for every distinct (kind, N) among the exterior contractions,
+// time each tile shape on a synthetic contraction of that shape (operands in
+// the arena's tensor pool, which holds nothing between executes) and keep the
+// fastest per time slice.  The choice enters the tile table of the context.
+int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
+  Device& D = *c.dev;
+  HIPC(hipSetDevice(D.device));
+  const Plan& p = c.plan;
+  const KernelPlan& kp = c.kplan;
+  if (!D.arena) throw Error(CDAG_E_STATE, "cdag_bind_arena first");
+  if ((uint64_t)kp.total_bytes > D.arena_bytes) throw Error(CDAG_E_NOMEM, "arena smaller than the plan");
+  (void)batched;
+  const int64_t eb = prec == CDAG_FP64 ? 16 : 8, acc = prec == CDAG_FP64 ? 8 : 4;
+  auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
+  const int64_t lo = al(p.leaf_region_bytes), hi = kp.ws_off + kp.ws_bytes;
+  std::map<std::pair<int, int>, int> shapes;   // (kind, n) -> largest nt
+  for (int64_t u = c.dag.n_leaves; u < c.dag.n_nodes(); ++u)
+    if (c.dag.kind[u] != HCA) {
+      int& nt = shapes[{c.dag.kind[u], c.dag.nvec[u]}];
+      nt = std::max(nt, (int)c.dag.nt[u]);
+    }
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  int64_t tuned = 0;
+  try {
+    for (const auto& sh : shapes) {
+      const int kind = sh.first.first, n = sh.first.second;
+      double best = 1e300;
+      int best_tile = -1;
+      for (int tile = 0; tile < kNumTiles; ++tile) {
+        HecDesc h{};
+        decompose(kind, n, sh.second, tile, prec, &h);
+        const int64_t slice = (int64_t)h.M * h.K * eb + (int64_t)h.K * h.N * eb + (int64_t)h.M * h.N * eb;
+        const int64_t wslice = h.splits > 1 ? (int64_t)h.splits * 2 * h.M * h.N * acc : 0;
+        int64_t nt = std::min<int64_t>(sh.second, (hi - lo - 4096) / std::max<int64_t>(1, slice + wslice + 1024));
+        if (nt < 1) continue;
+        decompose(kind, n, (int)nt, tile, prec, &h);
+        const int64_t a = lo, b = a + al(nt * h.M * h.K * eb), cc = b + al(nt * h.K * h.N * eb);
+        const int64_t ws = cc + al(nt * h.M * h.N * eb);
+        const int64_t ws_bytes = h.splits > 1 ? al((int64_t)h.splits * nt * 2 * h.M * h.N * acc) : 0;
+        const int64_t desc = ws + ws_bytes;
+        if (desc + 256 > hi) continue;
+        h.a_off = a;
+        h.b_off = b;
+        h.c_off = cc;
+        h.ws_off = h.splits > 1 ? ws : -1;
+        h.tile_begin = 0;
+        RedDesc r{ws, cc, h.M * h.N, (int32_t)nt, h.splits, 0};
+        const int64_t red_items = (2LL * nt * h.M * h.N + 255) / 256;
+        HIPC(hipMemsetAsync(D.arena + a, 0, (size_t)(ws - a), D.comp));
+        HIPC(hipMemcpyAsync(D.arena + desc, &h, sizeof(h), hipMemcpyHostToDevice, D.comp));
+        HIPC(hipMemcpyAsync(D.arena + desc + 128, &r, sizeof(r), hipMemcpyHostToDevice, D.comp));
+        auto once = [&] {
+          HIPC(launch_hec(prec, tile, D.arena, desc, 1, h.tile_count, D.comp));
+          if (h.splits > 1) HIPC(launch_reduce(prec, D.arena, desc + 128, 1, red_items, D.comp));
+        };
+        once();
+        HIPC(hipEventRecord(e0, D.comp));
+        for (int k = 0; k < reps; ++k) once();
+        HIPC(hipEventRecord(e1, D.comp));
+        HIPC(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPC(hipEventElapsedTime(&ms, e0, e1));
+        const double per_slice = ms / reps / (double)nt;
+        if (per_slice < best) { best = per_slice; best_tile = tile; }
+      }
+      if (best_tile >= 0) {
+        c.tiles[std::make_tuple(prec, kind, n)] = best_tile;
+        ++tuned;
+      }
+    }
+  } catch (...) {
+    ignore(hipEventDestroy(e0));
+    ignore(hipEventDestroy(e1));
+    throw;
+  }
+  ignore(hipEventDestroy(e0));
+  ignore(hipEventDestroy(e1));
+  HIPC(hipStreamSynchronize(D.comp));
+  return tuned;
+}
 
 void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   (void)batched;
@@ -255,66 +404,44 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   D.tpairs.clear();
   Device* timed = c.timing ? &D : nullptr;
   HIPC(hipEventRecord(D.t0, D.comp));
-  if (!has_copies && c.use_graphs && !c.timing) {
-    // no transfers: the whole step sequence is one captured graph
-    if (!D.gexec || D.graph_key != pkey || D.graph_epoch != D.arena_epoch) {
-      if (D.gexec) { ignore(hipGraphExecDestroy(D.gexec)); D.gexec = nullptr; }
-      if (D.graph) { ignore(hipGraphDestroy(D.graph)); D.graph = nullptr; }
-      hipStream_t cs;
-      HIPC(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-      HIPC(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      try {
-        for (int64_t s = 0; s < S; ++s) launch_step(kp, s, prec, D.arena, cs, nullptr);
-      } catch (...) {
+  if (c.use_graphs && !c.timing) {
+    // replay captured segments (one segment when there are no transfers)
+    const int64_t seg = has_copies ? kSegmentSteps : std::max<int64_t>(S, 1);
+    if (D.graph_key != pkey || D.graph_epoch != D.arena_epoch || D.graph_spill != D.spill ||
+        D.graph_stage != D.stage_version[prec]) {
+      D.drop_graphs();
+      for (int64_t s0 = 0; s0 < S; s0 += seg) {
+        const int64_t s1 = std::min(S, s0 + seg);
         hipGraph_t g = nullptr;
-        ignore(hipStreamEndCapture(cs, &g));
-        if (g) ignore(hipGraphDestroy(g));
-        ignore(hipStreamDestroy(cs));
-        throw;
+        HIPC(hipStreamBeginCapture(D.cap_comp, hipStreamCaptureModeThreadLocal));
+        try {
+          HIPC(hipEventRecord(D.ev_fork, D.cap_comp));
+          HIPC(hipStreamWaitEvent(D.cap_copy, D.ev_fork, 0));
+          issue_steps(c, D, prec, s0, s1, D.cap_comp, D.cap_copy, nullptr, true);
+          HIPC(hipEventRecord(D.ev_join, D.cap_copy));
+          HIPC(hipStreamWaitEvent(D.cap_comp, D.ev_join, 0));
+        } catch (...) {
+          ignore(hipStreamEndCapture(D.cap_comp, &g));
+          if (g) ignore(hipGraphDestroy(g));
+          D.drop_graphs();
+          throw;
+        }
+        HIPC(hipStreamEndCapture(D.cap_comp, &g));
+        D.seg_graph.push_back(g);
+        hipGraphExec_t ge = nullptr;
+        HIPC(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+        D.seg_exec.push_back(ge);
       }
-      HIPC(hipStreamEndCapture(cs, &D.graph));
-      HIPC(hipStreamDestroy(cs));
-      HIPC(hipGraphInstantiate(&D.gexec, D.graph, nullptr, nullptr, 0));
       D.graph_key = pkey;
       D.graph_epoch = D.arena_epoch;
+      D.graph_spill = D.spill;
+      D.graph_stage = D.stage_version[prec];
     }
-    HIPC(hipGraphLaunch(D.gexec, D.comp));
-    n_segments = 1;
+    for (hipGraphExec_t ge : D.seg_exec) HIPC(hipGraphLaunch(ge, D.comp));
+    n_segments = (int64_t)D.seg_exec.size();
     for (int64_t s = 0; s < S; ++s) n_launch += kp.launch_off[s + 1] - kp.launch_off[s];
   } else {
-    int64_t copy_waited = -1, comp_waited = -1;
-    for (int64_t s = 0; s < S; ++s) {
-      bool any_copy = false, any_h2d = false;
-      int64_t need_copy = -1;
-      for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
-        const PlanRec& r = p.recs[ri];
-        const size_t sz = (size_t)c.dag.size(r.node, eb);
-        if (r.op == OP_D2H || r.op == OP_H2D) {
-          if (r.wait_comp > copy_waited) {
-            HIPC(hipStreamWaitEvent(D.copy, D.ev_comp[r.wait_comp], 0));
-            copy_waited = r.wait_comp;
-          }
-          if (r.op == OP_D2H) {
-            HIPC(hipMemcpyAsync((char*)D.spill + r.host_off, D.arena + r.dev_off, sz, hipMemcpyDeviceToHost, D.copy));
-          } else {
-            const void* src = c.dag.is_leaf(r.node) ? D.stage[prec][r.node] : (const void*)((char*)D.spill + r.host_off);
-            HIPC(hipMemcpyAsync(D.arena + r.dev_off, src, sz, hipMemcpyHostToDevice, D.copy));
-            any_h2d = true;
-          }
-          any_copy = true;
-        } else if (r.op == OP_ALLOC && r.wait_copy >= 0) {
-          need_copy = std::max(need_copy, r.wait_copy);
-        }
-      }
-      if (any_copy) HIPC(hipEventRecord(D.ev_copy[s], D.copy));
-      if (any_h2d) need_copy = std::max(need_copy, s);
-      if (need_copy > comp_waited) {
-        HIPC(hipStreamWaitEvent(D.comp, D.ev_copy[need_copy], 0));
-        comp_waited = need_copy;
-      }
-      n_launch += launch_step(kp, s, prec, D.arena, D.comp, timed);
-      HIPC(hipEventRecord(D.ev_comp[s], D.comp));
-    }
+    n_launch += issue_steps(c, D, prec, 0, S, D.comp, D.copy, timed, false);
   }
   HIPC(launch_xsum(D.arena, kp.xsum.desc_off, kp.xsum_entries_off, kp.xsum.n_desc, D.comp));
   n_launch++;

@@ -10,7 +10,7 @@ from oracle import values as OV
 
 
 def run(wl, policy="tree", prec="fp64", batched=False, budget=None, leaves_resident=False,
-        use_graphs=True, wave_max=4096, wave_lookahead=0, device=0):
+        use_graphs=True, wave_max=4096, wave_lookahead=0, device=0, tile=None, autotune=False):
     import paper_2511_02257_amd as X
     from paper_2511_02257_amd.device import DeviceRunner
     ctx = X.Context()
@@ -19,12 +19,20 @@ def run(wl, policy="tree", prec="fp64", batched=False, budget=None, leaves_resid
     ctx.set_mem_budget(budget)
     ctx.set_options(leaves_resident=leaves_resident, wave_max=wave_max,
                     wave_lookahead=wave_lookahead, use_graphs=use_graphs)
+    if tile is not None:
+        for lf_n in {lf.nvec for lf in wl.leaves}:
+            for kind in (0, 1, 2):
+                ctx.set_tile(prec, kind, lf_n, tile)
     runner = DeviceRunner(ctx, device)
+    tuned = None
+    if autotune:
+        runner.autotune(prec, batched, reps=2)
+        tuned = {(k, n): ctx.get_tile(prec, k, n) for n in {lf.nvec for lf in wl.leaves} for k in (0, 1, 2)}
     st = runner.run(prec, batched)
     corr = ctx.fetch_correlators()
     sums = ctx.fetch_sums()
     ctx.close()
-    return dict(order=order, stats=st, corr=corr, sums=sums)
+    return dict(order=order, stats=st, corr=corr, sums=sums, tuned=tuned)
 
 
 def rel_errors(corr, ref):

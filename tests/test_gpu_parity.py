@@ -109,6 +109,24 @@ def test_baryon_ragged_splitk(baryon_small, prec):
         assert np.array_equal(b, results[0])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+def test_every_tile_shape(meson_small, baryon_small, prec, tile):
+    for name, (wl, ref) in (("meson_small", meson_small), ("baryon_small", baryon_small)):
+        r = run(wl, "tree", prec, True, tile=tile)
+        err = rel_errors(r["corr"], ref)
+        print(f"{name} {prec} tile {tile}: max rel {err.max():.3e}")
+        assert err.max() <= TOL[prec]
+
+
+def test_autotune_then_parity(baryon_small):
+    wl, ref = baryon_small
+    for prec in ("fp64", "fp32"):
+        r = run(wl, "tree", prec, True, autotune=True)
+        print(f"autotuned {prec}: {r['tuned']}")
+        assert rel_errors(r["corr"], ref).max() <= TOL[prec]
+
+
 def test_resident_leaves_and_graph_replay(baryon_small):
     wl, ref = baryon_small
     a = run(wl, "tree", "fp64", True, leaves_resident=True, use_graphs=True)
@@ -118,6 +136,38 @@ def test_resident_leaves_and_graph_replay(baryon_small):
     assert rel_errors(a["corr"], ref).max() <= TOL["fp64"]
     assert np.array_equal(np.concatenate(a["corr"]).view(np.uint64),
                           np.concatenate(b["corr"]).view(np.uint64))
+
+
+@pytest.mark.parametrize("resident,budget_frac", [(True, None), (False, 4)])
+def test_graph_replays_match_eager(meson_small, resident, budget_frac):
+    """Captured segments replayed several times, with eager executes and host
+    synchronisation in between; every replay must equal the eager result bit for bit."""
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd.device import DeviceRunner
+    from oracle import dag as OD, schedules as OS
+    wl, ref = meson_small
+    d = OD.build(wl.leaves, wl.graphs)
+    budget = None if budget_frac is None else OS.memsim(d, OS.input_order(d))["peak_live"] // budget_frac
+    ctx = X.Context()
+    ctx.build_cdag(wl.leaves, wl.graphs)
+    ctx.schedule("tree")
+    ctx.set_mem_budget(budget)
+    runner = DeviceRunner(ctx, 0)
+    ctx.set_options(leaves_resident=resident, use_graphs=False)
+    runner.run("fp64", True)
+    eager = np.concatenate(ctx.fetch_correlators()).view(np.uint64).copy()
+    assert rel_errors(ctx.fetch_correlators(), ref).max() <= TOL["fp64"]
+    for rep in range(3):
+        ctx.set_options(leaves_resident=resident, use_graphs=True)
+        st = runner.run("fp64", True)
+        assert st["n_graph_segments"] >= 1
+        got = np.concatenate(ctx.fetch_correlators()).view(np.uint64)
+        assert np.array_equal(got, eager), f"replay {rep}"
+        runner.torch.cuda.synchronize()
+        ctx.set_options(leaves_resident=resident, use_graphs=False)
+        runner.run("fp64", True)            # eager work between replays
+        assert np.array_equal(np.concatenate(ctx.fetch_correlators()).view(np.uint64), eager)
+    ctx.close()
 
 
 def _identity(nt, n):
