@@ -56,6 +56,21 @@ def timed_steps(ctx, runner, prec, batched, steps, warmup):
     return dt, st
 
 
+def measured_traffic(tile):
+    """HBM bytes per launch of the exterior-contraction kernel from the committed
+    counter summary, or None when the kernel source or tile differs from the one
+    the counters were taken on."""
+    path = os.path.join(ROOT, "profiles", "hec_traffic_meson_ring.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    from paper_2511_02257_amd.profiling import kernel_source_sha256
+    if rec.get("kernel_sha256") != kernel_source_sha256() or rec.get("tile") != tile:
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
 def cpu_baseline(wl, seconds=12.0):
     """The oracle (numpy complex128, each graph on its own) on a bounded sample."""
     from oracle import values as OV
@@ -127,6 +142,11 @@ def main():
     ALL = X.binding.LOOKAHEAD_ALL
     ctx.set_options(leaves_resident=True, wave_lookahead=ALL, use_graphs=True)
     runner = DeviceRunner(ctx, 0)
+    tiles = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        runner.autotune(prec, True, reps=3)
+        tiles[prec] = {"K22_N64": X.TILES[ctx.get_tile(prec, 0, 64)]}
+    log("autotuned tiles", tiles)
 
     # ---- headline: FP64, Tree, waves, leaves resident, graph replay
     dt, st = timed_steps(ctx, runner, "fp64", True, args.steps, args.warmup)
@@ -144,7 +164,7 @@ def main():
                    "schedule": "tree",
                    "mode": "waves of every ready contraction, one hipGraph replay",
                    "leaves": "resident in HBM", "flops_per_step": flops,
-                   "t_schedule_tree_s": round(t_sched, 4)},
+                   "t_schedule_tree_s": round(t_sched, 4), "autotuned_tiles": tiles},
     }
 
     # ---- roofline of the exterior-contraction kernel (HIP events per launch)
@@ -158,8 +178,10 @@ def main():
         hec_n += s2["n_hec_launches"]
     ctx.set_timing(False)
     achieved = hec_f / hec_t / 1e12
+    tile64 = ctx.get_tile("fp64", 0, 64)
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
-                       "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4), "traffic": None,
+                       "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4),
+                       "traffic": measured_traffic(tile64), "tile": list(X.TILES[tile64]),
                        "kernel": "hec_mfma<double> (grouped K22 waves)",
                        "avg_launch_us": round(hec_t / hec_n * 1e6, 3),
                        "flops_per_launch": hec_f / hec_n,

@@ -1,0 +1,87 @@
+"""Summaries of rocprofv3 output for the committed profiles.
+
+traffic: HBM bytes per launch of one kernel from two counter runs (FETCH_SIZE,
+then WRITE_SIZE, in KiB per dispatch), each scaled by what the same counter
+reads for a plain device copy of known size.
+
+    python -m paper_2511_02257_amd.profiling traffic \\
+        --kernel 'hec_mfma<double' --tile 0 \\
+        --fetch gpurun_out/pmc_fetch/fetch_counter_collection.csv \\
+        --write gpurun_out/pmc_write/write_counter_collection.csv \\
+        --copy-fetch gpurun_out/pmc_copy_fetch/cf_counter_collection.csv \\
+        --copy-write gpurun_out/pmc_copy_write/cw_counter_collection.csv \\
+        --copy-bytes 1073741824 --out profiles/hec_traffic_meson_ring.json
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _values(path, kernel_substr):
+    out = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if kernel_substr in r["Kernel_Name"]:
+                out.append(float(r["Counter_Value"]))
+    return out
+
+
+def kernel_source_sha256():
+    h = hashlib.sha256()
+    for rel in ("paper_2511_02257_amd/csrc/kernels/kernels.hip", "paper_2511_02257_amd/csrc/kernels/desc.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic(args):
+    fetch = _values(args.fetch, args.kernel)
+    write = _values(args.write, args.kernel)
+    cf = _values(args.copy_fetch, args.copy_kernel)
+    cw = _values(args.copy_write, args.copy_kernel)
+    if not fetch or len(fetch) != len(write) or not cf or not cw:
+        raise SystemExit("counter files do not match the kernel names")
+    kib = args.copy_bytes / 1024.0
+    kf = kib / (sum(cf) / len(cf))
+    kw = kib / (sum(cw) / len(cw))
+    per_launch = (sum(fetch) * kf + sum(write) * kw) * 1024.0 / len(fetch)
+    rec = {
+        "kernel": args.kernel, "tile": args.tile, "dispatches": len(fetch),
+        "fetch_scale": round(kf, 5), "write_scale": round(kw, 5),
+        "fetch_bytes_per_launch": sum(fetch) * kf * 1024.0 / len(fetch),
+        "write_bytes_per_launch": sum(write) * kw * 1024.0 / len(write),
+        "traffic_bytes_per_launch": per_launch,
+        "kernel_sha256": kernel_source_sha256(),
+        "counters": "FETCH_SIZE and WRITE_SIZE (KiB per dispatch), separate rocprofv3 --pmc runs",
+    }
+    with open(args.out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--tile", type=int, required=True)
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--copy-fetch", required=True)
+    t.add_argument("--copy-write", required=True)
+    t.add_argument("--copy-kernel", default="copyBuffer")
+    t.add_argument("--copy-bytes", type=int, default=1 << 30)
+    t.add_argument("--out", required=True)
+    args = ap.parse_args()
+    if args.cmd == "traffic":
+        traffic(args)
+
+
+if __name__ == "__main__":
+    main()
