@@ -73,13 +73,16 @@ enum cdag_plan_op { CDAG_OP_D2H = 0, CDAG_OP_DROP = 1, CDAG_OP_H2D = 2,
                     CDAG_OP_ALLOC = 3, CDAG_OP_EXEC = 4, CDAG_OP_FREE = 5 };
 
 /* A leaf tensor (hadron node): complex, shape [nt][nvec]^rank, rank 2 (meson)
- * or 3 (baryon).  host: interleaved complex128 (re, im) in row-major order,
- * read only during build_cdag (the library keeps its own copy); may be NULL
- * for a structure-only context (scheduling and planning work; execute then
- * fails with CDAG_E_STATE). */
+ * or 3 (baryon).  host: interleaved (re, im) in row-major order, complex128
+ * (dtype CDAG_C128, doubles) or complex64 (dtype CDAG_C64, floats), read only
+ * during build_cdag (the library keeps its own copy in that dtype); may be
+ * NULL for a structure-only context (scheduling and planning work; execute
+ * then fails with CDAG_E_STATE).  Complex64 leaves are promoted exactly in
+ * FP64 mode. */
+enum cdag_dtype { CDAG_C128 = 0, CDAG_C64 = 1 };
 typedef struct {
-  int32_t rank, nvec, nt, reserved;
-  const double* host;
+  int32_t rank, nvec, nt, dtype;
+  const void* host;
 } cdag_leaf;
 
 /* One binary contraction inside a graph.  Operand >= 0: a leaf id; operand

@@ -56,8 +56,8 @@ def evaluate_graph(leaves: Sequence[np.ndarray], ops) -> np.ndarray:
     """C_g(t) for one graph: its ops in order; operand >= 0 is a leaf, < 0 an earlier op."""
     vals: List[np.ndarray] = []
     for kind, l, r in ops:
-        X = leaves[l] if l >= 0 else vals[-l - 1]
-        Y = leaves[r] if r >= 0 else vals[-r - 1]
+        X = np.asarray(leaves[l], dtype=np.complex128) if l >= 0 else vals[-l - 1]
+        Y = np.asarray(leaves[r], dtype=np.complex128) if r >= 0 else vals[-r - 1]
         vals.append(contract(kind, X, Y))
     return vals[-1]
 

@@ -32,7 +32,7 @@ class CdagError(RuntimeError):
 
 class cdag_leaf(C.Structure):
     _fields_ = [("rank", C.c_int32), ("nvec", C.c_int32), ("nt", C.c_int32),
-                ("reserved", C.c_int32), ("host", C.POINTER(C.c_double))]
+                ("dtype", C.c_int32), ("host", C.c_void_p)]
 
 
 class cdag_op(C.Structure):
@@ -157,12 +157,15 @@ def build_cdag(h, leaves: Sequence, graphs: Sequence) -> None:
     for i, lf in enumerate(leaves):
         L[i].rank, L[i].nvec, L[i].nt = lf.rank, lf.nvec, lf.nt
         if getattr(lf, "data", None) is not None:
-            a = np.ascontiguousarray(lf.data, dtype=np.complex128)
+            dt = np.complex64 if lf.data.dtype == np.complex64 else np.complex128
+            a = np.ascontiguousarray(lf.data, dtype=dt)
             if a.size != lf.nt * lf.nvec ** lf.rank:
                 raise ValueError(f"leaf {i}: data has {a.size} elements")
             keep.append(a)
-            L[i].host = a.ctypes.data_as(C.POINTER(C.c_double))
+            L[i].dtype = 1 if dt == np.complex64 else 0
+            L[i].host = a.ctypes.data
         else:
+            L[i].dtype = 0
             L[i].host = None
     G = (cdag_graph * max(1, len(graphs)))()
     for g, spec in enumerate(graphs):

@@ -112,6 +112,7 @@ int build_cdag(cdag_ctx* h, const cdag_leaf* leaves, int64_t n_leaves, const cda
     for (int64_t i = 0; i < n_leaves; ++i) {
       L[i] = {leaves[i].rank, leaves[i].nvec, leaves[i].nt};
       with_data += leaves[i].host != nullptr;
+      need(leaves[i].dtype == CDAG_C128 || leaves[i].dtype == CDAG_C64, CDAG_E_INVALID, "leaf dtype must be C128 or C64");
     }
     need(with_data == 0 || with_data == n_leaves, CDAG_E_INVALID, "either every leaf has host data or none");
     std::vector<cdag::GraphIn> G(n_graphs);
@@ -129,16 +130,20 @@ int build_cdag(cdag_ctx* h, const cdag_leaf* leaves, int64_t n_leaves, const cda
       need(cnt[d.corr[g]] < 0 || cnt[d.corr[g]] == nt, CDAG_E_INVALID, "graphs of one correlator differ in Nt");
       cnt[d.corr[g]] = nt;
     }
-    std::vector<std::vector<double>> data;
+    std::vector<std::vector<uint8_t>> data;
+    std::vector<int32_t> dtypes(n_leaves);
     if (with_data) {
       data.resize(n_leaves);
       for (int64_t i = 0; i < n_leaves; ++i) {
-        const int64_t e = d.elems(i);
-        data[i].assign(leaves[i].host, leaves[i].host + 2 * e);
+        const int64_t bytes = d.elems(i) * (leaves[i].dtype == CDAG_C64 ? 8 : 16);
+        const uint8_t* src = static_cast<const uint8_t*>(leaves[i].host);
+        data[i].assign(src, src + bytes);
+        dtypes[i] = leaves[i].dtype;
       }
     }
     c.dag = std::move(d);
     c.leaf_data = std::move(data);
+    c.leaf_dtype = std::move(dtypes);
     c.has_data = with_data > 0;
     c.n_corr = n_corr;
     c.built = true;

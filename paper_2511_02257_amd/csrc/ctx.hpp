@@ -18,7 +18,8 @@ struct Ctx {
   bool built = false;
   Dag dag;
   bool has_data = false;
-  std::vector<std::vector<double>> leaf_data;   // interleaved complex128 copies
+  std::vector<std::vector<uint8_t>> leaf_data;  // interleaved host copies, dtype leaf_dtype
+  std::vector<int32_t> leaf_dtype;              // CDAG_C128 or CDAG_C64 per leaf
   int32_t n_corr = 0;
   uint64_t data_version = 0;     // bumped by build_cdag (leaf data changed)
   // schedule

@@ -137,11 +137,11 @@ void device_bind_arena(Ctx& c, void* arena, uint64_t bytes) {
 }
 
 namespace {
-// Interleaved complex128 [nt][e] -> planar [nt][2][e] in T.
-template <typename T>
-void to_device_layout(const double* src, T* dst, int64_t nt, int64_t e) {
+// Interleaved complex [nt][e] (S = double or float) -> planar [nt][2][e] in T.
+template <typename S, typename T>
+void to_device_layout(const S* src, T* dst, int64_t nt, int64_t e) {
   for (int64_t t = 0; t < nt; ++t) {
-    const double* s = src + 2 * t * e;
+    const S* s = src + 2 * t * e;
     T* re = dst + 2 * t * e;
     T* im = re + e;
     for (int64_t i = 0; i < e; ++i) {
@@ -167,10 +167,15 @@ void ensure_stage(Ctx& c, int prec) {
     th.emplace_back([&, w] {
       for (int64_t u = w; u < L; u += nth) {
         const int64_t e = c.dag.elems(u) / c.dag.nt[u];
-        if (prec == CDAG_FP64)
-          to_device_layout<double>(c.leaf_data[u].data(), (double*)D.stage[prec][u], c.dag.nt[u], e);
-        else
-          to_device_layout<float>(c.leaf_data[u].data(), (float*)D.stage[prec][u], c.dag.nt[u], e);
+        const void* src = c.leaf_data[u].data();
+        const bool c64 = c.leaf_dtype[u] == CDAG_C64;
+        if (prec == CDAG_FP64) {
+          if (c64) to_device_layout<float, double>((const float*)src, (double*)D.stage[prec][u], c.dag.nt[u], e);
+          else to_device_layout<double, double>((const double*)src, (double*)D.stage[prec][u], c.dag.nt[u], e);
+        } else {
+          if (c64) to_device_layout<float, float>((const float*)src, (float*)D.stage[prec][u], c.dag.nt[u], e);
+          else to_device_layout<double, float>((const double*)src, (float*)D.stage[prec][u], c.dag.nt[u], e);
+        }
       }
     });
   for (auto& t : th) t.join();

@@ -68,17 +68,22 @@ def _streams(seed: int):
             np.random.Generator(np.random.PCG64(gs)))
 
 
-def _draw(rng, shape, sigma) -> np.ndarray:
-    """Complex128 tensor with re and im iid N(0, sigma^2), re drawn first."""
-    out = np.empty(shape, dtype=np.complex128)
-    out.real = rng.standard_normal(shape) * sigma
-    out.imag = rng.standard_normal(shape) * sigma
+def _draw(rng, shape, sigma, dtype=np.complex128) -> np.ndarray:
+    """Complex tensor with re and im iid N(0, sigma^2), re drawn first.  complex64
+    tensors draw float32 normals (a different stream than complex128 ones)."""
+    out = np.empty(shape, dtype=dtype)
+    if dtype == np.complex64:
+        out.real = rng.standard_normal(shape, dtype=np.float32) * np.float32(sigma)
+        out.imag = rng.standard_normal(shape, dtype=np.float32) * np.float32(sigma)
+    else:
+        out.real = rng.standard_normal(shape) * sigma
+        out.imag = rng.standard_normal(shape) * sigma
     return out
 
 
-def _leaf(rng, rank, nvec, nt, sigma, with_data) -> Leaf:
+def _leaf(rng, rank, nvec, nt, sigma, with_data, dtype=np.complex128) -> Leaf:
     shape = (nt,) + (nvec,) * rank
-    return Leaf(rank, nvec, nt, _draw(rng, shape, sigma) if with_data else None)
+    return Leaf(rank, nvec, nt, _draw(rng, shape, sigma, dtype) if with_data else None)
 
 
 def _ring_graph(rg, leaf_ids: List[int], lmin: int, lmax: int, n_corr: int) -> GraphSpec:
@@ -185,18 +190,20 @@ def fig1_dag(order: str = "fgh", nvec=4, nt=1, seed=7, with_data=True) -> Worklo
 BATCHED_NVECS = (32, 48, 64, 96, 128)
 
 
-def batched_mix(nvecs=BATCHED_NVECS, nt=64, n_mes=8, n_bar=8, n_graphs=9000, lmin=4, lmax=6,
-                n_corr_per_family=4, seed=1005, with_data=True, name="batched") -> Workload:
+def batched_mix(nvecs=BATCHED_NVECS, nt=64, n_mes=8, n_bar=8, n_graphs=13000, lmin=4, lmax=6,
+                n_corr_per_family=4, seed=1005, with_data=True, name="batched",
+                dtype=np.complex64) -> Workload:
     """Families of equal N, one per entry of `nvecs`; graphs are added round-robin
     over families, alternating meson rings and baryon chains within a family.
-    Entries are N(0,1)/N."""
+    Entries are N(0,1)/N, stored as complex64.  13000 graphs merge into just over
+    20,000 contractions at the default sizes."""
     rt, rg = _streams(seed)
     leaves: List[Leaf] = []
     fam = []
     for n in nvecs:
         base = len(leaves)
-        leaves += [_leaf(rt, 2, n, nt, 1.0 / n, with_data) for _ in range(n_mes)]
-        leaves += [_leaf(rt, 3, n, nt, 1.0 / n, with_data) for _ in range(n_bar)]
+        leaves += [_leaf(rt, 2, n, nt, 1.0 / n, with_data, dtype) for _ in range(n_mes)]
+        leaves += [_leaf(rt, 3, n, nt, 1.0 / n, with_data, dtype) for _ in range(n_bar)]
         fam.append((list(range(base, base + n_mes)),
                     list(range(base + n_mes, base + n_mes + n_bar))))
     graphs: List[GraphSpec] = []

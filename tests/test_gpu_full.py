@@ -78,3 +78,47 @@ def test_baryon_mix_full_sampled(baryon, prec, tol):
     print(f"baryon_mix {prec}: waves={p['n_steps']} max rel {err.max():.3e} median {np.median(err):.3e} "
           f"device {r['stats']['t_device_s'] * 1e3:.1f} ms, {p['flops'] / r['stats']['t_device_s'] / 1e12:.1f} TFLOP/s")
     assert err.max() <= tol
+
+
+@pytest.fixture(scope="module")
+def batched():
+    wl = W.config("batched")
+    # one ring and one chain from each N family (graphs alternate by family round-robin)
+    nf = len(W.BATCHED_NVECS)
+    sample = []
+    for f in range(nf):
+        fam = [g for g in range(f, len(wl.graphs), nf)]
+        ring = next(g for g in fam if wl.graphs[g].ops[0][0] == W.K22)
+        chain = next(g for g in fam if wl.graphs[g].ops[0][0] == W.K32)
+        sample += [ring, chain]
+    return wl, sorted(sample), OV.correlators(wl, sorted(sample))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 4e-5)])
+def test_batched_full_sampled(batched, prec, tol):
+    """Five N families, just over 20,000 merged contractions, complex64 storage,
+    64 GB budget: waves of every ready contraction, captured segments, autotuned tiles."""
+    wl, sample, ref = batched
+    r = run(wl, "tree", prec, True, budget=64 * 10**9, wave_lookahead=ALL, autotune=True)
+    p = r["stats"]["plan"]
+    assert p["n_contr"] >= 20000
+    err = np.array([np.linalg.norm(r["corr"][g] - ref[g]) / np.linalg.norm(ref[g]) for g in sample])
+    fams = [wl.leaves[wl.graphs[g].ops[0][1]].nvec for g in sample]
+    print(f"batched {prec}: contractions={p['n_contr']} waves={p['n_steps']} evict={p['n_evict']} "
+          f"h2d={p['h2d_bytes'] / 1e9:.2f} GB peak={p['peak_resident'] / 1e9:.2f} GB "
+          f"device {r['stats']['t_device_s'] * 1e3:.1f} ms total {r['stats']['t_total_s'] * 1e3:.1f} ms "
+          f"{p['flops'] / r['stats']['t_device_s'] / 1e12:.1f} TFLOP/s tiles {r['tuned']}")
+    for n, e in zip(fams, err):
+        print(f"   N={n}: rel {e:.3e}")
+    assert err.max() <= tol
+
+
+def test_batched_per_contraction_matches_waves(batched):
+    wl, sample, ref = batched
+    a = run(wl, "tree", "fp32", False, budget=64 * 10**9)
+    b = run(wl, "tree", "fp32", True, budget=64 * 10**9, wave_lookahead=ALL)
+    for g in sample:
+        assert np.array_equal(a["corr"][g].view(np.uint64), b["corr"][g].view(np.uint64))
+    ta, tb = a["stats"]["t_total_s"], b["stats"]["t_total_s"]
+    print(f"batched fp32: per-contraction {ta * 1e3:.1f} ms ({a['stats']['n_launches']} launches), "
+          f"waves {tb * 1e3:.1f} ms ({b['stats']['n_launches']} launches)")
