@@ -229,13 +229,21 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
           b_i[j] = Bs[st][1][kk][(wn * TN + j) * 16 + li];
           b_n[j] = -b_i[j];
         }
+        // Re += Ar Br + Ai (-Bi), Im += Ar Bi + Ai Br.  Consecutive instructions
+        // go to different accumulators; each accumulator still adds its two
+        // products in the same order.
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
           for (int j = 0; j < TN; ++j) {
             cr[i][j] = Mfma<T>::mma(a_r[i], b_r[j], cr[i][j]);
-            cr[i][j] = Mfma<T>::mma(a_i[i], b_n[j], cr[i][j]);
             ci[i][j] = Mfma<T>::mma(a_r[i], b_i[j], ci[i][j]);
+          }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            cr[i][j] = Mfma<T>::mma(a_i[i], b_n[j], cr[i][j]);
             ci[i][j] = Mfma<T>::mma(a_i[i], b_r[j], ci[i][j]);
           }
       }
@@ -378,26 +386,22 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
         bn_hi[j] = *reinterpret_cast<v8bf*>(&hs);
         bn_lo[j] = *reinterpret_cast<v8bf*>(&ls);
       }
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br, each with lo*hi + hi*lo + hi*hi
+      // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br, each real product as
+      // lo*hi + hi*lo + hi*hi.  Term by term over all accumulators, so that
+      // consecutive instructions are independent; each accumulator adds its
+      // six terms in the same order.
 #define MM(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc, 0, 0, 0)
-          MM(cr[i][j], a[i][0][1], b[j][0][0]);
-          MM(cr[i][j], a[i][0][0], b[j][0][1]);
-          MM(cr[i][j], a[i][0][0], b[j][0][0]);
-          MM(cr[i][j], a[i][1][1], bn_hi[j]);
-          MM(cr[i][j], a[i][1][0], bn_lo[j]);
-          MM(cr[i][j], a[i][1][0], bn_hi[j]);
-          MM(ci[i][j], a[i][0][1], b[j][1][0]);
-          MM(ci[i][j], a[i][0][0], b[j][1][1]);
-          MM(ci[i][j], a[i][0][0], b[j][1][0]);
-          MM(ci[i][j], a[i][1][1], b[j][0][0]);
-          MM(ci[i][j], a[i][1][0], b[j][0][1]);
-          MM(ci[i][j], a[i][1][0], b[j][0][0]);
+#define TERM(CR_X, CR_Y, CI_X, CI_Y)            \
+  _Pragma("unroll") for (int i = 0; i < TM; ++i) \
+  _Pragma("unroll") for (int j = 0; j < TN; ++j) { MM(cr[i][j], CR_X, CR_Y); MM(ci[i][j], CI_X, CI_Y); }
+      TERM(a[i][0][1], b[j][0][0], a[i][0][1], b[j][1][0])
+      TERM(a[i][0][0], b[j][0][1], a[i][0][0], b[j][1][1])
+      TERM(a[i][0][0], b[j][0][0], a[i][0][0], b[j][1][0])
+      TERM(a[i][1][1], bn_hi[j], a[i][1][1], b[j][0][0])
+      TERM(a[i][1][0], bn_lo[j], a[i][1][0], b[j][0][1])
+      TERM(a[i][1][0], bn_hi[j], a[i][1][0], b[j][0][0])
+#undef TERM
 #undef MM
-        }
       if (c + 1 < nk) sstore(st ^ 1);
       __syncthreads();
     }
