@@ -58,8 +58,8 @@ def timed_steps(ctx, runner, prec, batched, steps, warmup):
 
 def measured_traffic(tile):
     """HBM bytes per launch of the exterior-contraction kernel from the committed
-    counter summary, or None when the kernel source or tile differs from the one
-    the counters were taken on."""
+    counter summary, or None when the kernel source or variant (tile + 5 * grid)
+    differs from the one the counters were taken on."""
     path = os.path.join(ROOT, "profiles", "hec_traffic_meson_ring.json")
     if not os.path.exists(path):
         return None
@@ -144,8 +144,9 @@ def main():
     runner = DeviceRunner(ctx, 0)
     tiles = {}
     for prec in ("fp64", "fp32", "bf16x3"):
-        runner.autotune(prec, True, reps=3)
-        tiles[prec] = {"K22_N64": X.TILES[ctx.get_tile(prec, 0, 64)]}
+        runner.autotune(prec, True, reps=2, in_situ=True)
+        t, g = ctx.get_tile(prec, 0, 64)
+        tiles[prec] = {"K22_N64": {"tile": list(X.TILES[t]), "grid": X.binding.GRIDS[g]}}
     log("autotuned tiles", tiles)
 
     # ---- headline: FP64, Tree, waves, leaves resident, graph replay
@@ -178,10 +179,12 @@ def main():
         hec_n += s2["n_hec_launches"]
     ctx.set_timing(False)
     achieved = hec_f / hec_t / 1e12
-    tile64 = ctx.get_tile("fp64", 0, 64)
+    t64, g64 = ctx.get_tile("fp64", 0, 64)
+    variant = t64 + len(X.TILES) * g64
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
                        "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4),
-                       "traffic": measured_traffic(tile64), "tile": list(X.TILES[tile64]),
+                       "traffic": measured_traffic(variant), "tile": list(X.TILES[t64]),
+                       "grid": X.binding.GRIDS[g64],
                        "kernel": "hec_mfma<double> (grouped K22 waves)",
                        "avg_launch_us": round(hec_t / hec_n * 1e6, 3),
                        "flops_per_launch": hec_f / hec_n,

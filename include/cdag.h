@@ -164,14 +164,16 @@ int cdag_set_options(cdag_ctx* c, int leaves_resident, int wave_max, int64_t wav
  * (execution then runs without graph replay); 0 (default) turns it off. */
 int cdag_set_timing(cdag_ctx* c, int timing);
 
-/* Tile shape of the exterior-contraction kernels for contractions of `kind`
- * (K22, K32 or K33) with N = nvec in precision `prec`: 0 = 64x64, 1 = 32x32,
- * 2 = 48x48, 3 = 128x64, 4 = 64x32 (output rows x columns per workgroup);
- * -1 removes an explicit choice.  Without one, a default by N applies
- * (cdag_get_tile reports the choice in force).  Every shape gives results
- * within the precision's bound; bits may differ between shapes. */
-int cdag_set_tile(cdag_ctx* c, int prec, int kind, int nvec, int tile);
-int cdag_get_tile(cdag_ctx* c, int prec, int kind, int nvec, int* tile);
+/* Kernel variant of the exterior contractions of `kind` (K22, K32 or K33)
+ * with N = nvec in precision `prec`.  tile: 0 = 64x64, 1 = 32x32, 2 = 48x48,
+ * 3 = 128x64, 4 = 64x32 (output rows x columns per workgroup), -1 removes an
+ * explicit choice.  grid: 0 = persistent (compute units x occupancy
+ * workgroups striding over the work list), 1 = one workgroup per work item.
+ * Without an explicit choice a default by N applies (cdag_get_tile reports
+ * the choice in force).  Every variant gives results within the precision's
+ * bound; bits may differ between tile shapes. */
+int cdag_set_tile(cdag_ctx* c, int prec, int kind, int nvec, int tile, int grid);
+int cdag_get_tile(cdag_ctx* c, int prec, int kind, int nvec, int* tile, int* grid);
 
 /* Host-only: simulate Sec. II-C for `order` (n node ids, each contraction
  * once, topological) with element size elem_bytes (16 or 8).  M_out
@@ -206,14 +208,18 @@ int cdag_bind_arena(cdag_ctx* c, void* dev_arena, uint64_t bytes);
  * to the host.  Blocks until the results are on the host. */
 int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
 
-/* Autotuner: for every distinct (kind, N) among the exterior contractions of
- * the DAG, time each tile shape (cdag_set_tile) `reps` times on a synthetic
- * contraction of that shape placed in the bound arena's tensor pool (as
- * planned for (prec, batched); its contents are scratch between executes) and
- * keep the fastest per time slice.  *n_tuned (nullable) receives the number
- * of shapes tuned.  Needs cdag_bind_device and an arena of at least the
- * plan's arena_bytes; invalidates the current plan and results. */
-int cdag_autotune(cdag_ctx* c, int prec, int batched, int reps, int64_t* n_tuned);
+/* Autotuner over the kernel variants of cdag_set_tile, for every distinct
+ * (kind, N) among the exterior contractions of the DAG.  mode 0 (synthetic):
+ * time each variant `reps` times on one contraction of that shape placed in
+ * the bound arena's tensor pool (as planned for (prec, batched); its contents
+ * are scratch between executes) and keep the fastest per time slice.  mode 1
+ * (in situ): execute the planned DAG `reps` times per variant, shape by
+ * shape, with launch timing on, and keep the least summed exterior-contraction
+ * time (needs leaf data; costs 10 * reps executes per shape).  *n_tuned
+ * (nullable) receives the number of shapes tuned.  Needs cdag_bind_device and
+ * an arena of at least the plan's arena_bytes; invalidates the current plan
+ * and results. */
+int cdag_autotune(cdag_ctx* c, int prec, int batched, int reps, int mode, int64_t* n_tuned);
 
 /* Per input graph g, C_g(t) for t < nt(g), as (re, im) doubles, graphs in
  * input order, concatenated: 2 * sum_g nt(g) doubles. */

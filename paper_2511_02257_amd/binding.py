@@ -90,8 +90,8 @@ def lib():
             "set_mem_budget": [P, C.c_uint64],
             "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
             "cdag_set_timing": [P, C.c_int],
-            "cdag_set_tile": [P, C.c_int, C.c_int, C.c_int, C.c_int],
-            "cdag_get_tile": [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int)],
+            "cdag_set_tile": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int],
+            "cdag_get_tile": [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)],
             "cdag_memsim": [P, C.POINTER(I64), I64, C.c_int, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
             "cdag_plan": [P, C.c_int, C.c_int, C.POINTER(cdag_plan_stats)],
             "cdag_plan_ops": [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64), I64, C.POINTER(I64)],
@@ -100,7 +100,7 @@ def lib():
             "cdag_bind_device": [P, C.c_int, P, P],
             "cdag_bind_arena": [P, P, C.c_uint64],
             "execute": [P, C.c_int, C.c_int, C.POINTER(cdag_exec_stats)],
-            "cdag_autotune": [P, C.c_int, C.c_int, C.c_int, C.POINTER(I64)],
+            "cdag_autotune": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(I64)],
             "fetch_correlators": [P, C.POINTER(C.c_double), I64],
             "cdag_fetch_sums": [P, C.POINTER(C.c_double), I64],
         }
@@ -207,14 +207,18 @@ def cdag_set_timing(h, on: bool) -> None:
 TILES = {0: (64, 64), 1: (32, 32), 2: (48, 48), 3: (128, 64), 4: (64, 32)}
 
 
-def cdag_set_tile(h, prec: str, kind: int, nvec: int, tile: int) -> None:
-    _check(lib().cdag_set_tile(h, PREC[prec], int(kind), int(nvec), int(tile)))
+GRIDS = {0: "persistent", 1: "one workgroup per item"}
 
 
-def cdag_get_tile(h, prec: str, kind: int, nvec: int) -> int:
-    t = C.c_int()
-    _check(lib().cdag_get_tile(h, PREC[prec], int(kind), int(nvec), C.byref(t)))
-    return t.value
+def cdag_set_tile(h, prec: str, kind: int, nvec: int, tile: int, grid: int = 1) -> None:
+    _check(lib().cdag_set_tile(h, PREC[prec], int(kind), int(nvec), int(tile), int(grid)))
+
+
+def cdag_get_tile(h, prec: str, kind: int, nvec: int):
+    """(tile, grid) in force for that shape."""
+    t, g = C.c_int(), C.c_int()
+    _check(lib().cdag_get_tile(h, PREC[prec], int(kind), int(nvec), C.byref(t), C.byref(g)))
+    return t.value, g.value
 
 
 def cdag_memsim(h, order: Sequence[int], elem_bytes: int = 16):
@@ -273,9 +277,10 @@ def execute(h, prec: str = "fp64", batched: bool = False) -> dict:
     return _struct_dict(st)
 
 
-def cdag_autotune(h, prec: str = "fp64", batched: bool = True, reps: int = 3) -> int:
+def cdag_autotune(h, prec: str = "fp64", batched: bool = True, reps: int = 3,
+                  in_situ: bool = False) -> int:
     n = C.c_int64()
-    _check(lib().cdag_autotune(h, PREC[prec], int(batched), int(reps), C.byref(n)))
+    _check(lib().cdag_autotune(h, PREC[prec], int(batched), int(reps), int(bool(in_situ)), C.byref(n)))
     return n.value
 
 
@@ -350,8 +355,8 @@ class Context:
     def set_timing(self, on=True):
         cdag_set_timing(self.h, on)
 
-    def set_tile(self, prec, kind, nvec, tile):
-        cdag_set_tile(self.h, prec, kind, nvec, tile)
+    def set_tile(self, prec, kind, nvec, tile, grid=1):
+        cdag_set_tile(self.h, prec, kind, nvec, tile, grid)
 
     def get_tile(self, prec, kind, nvec):
         return cdag_get_tile(self.h, prec, kind, nvec)
@@ -380,8 +385,8 @@ class Context:
     def execute(self, prec="fp64", batched=False):
         return execute(self.h, prec, batched)
 
-    def autotune(self, prec="fp64", batched=True, reps=3):
-        return cdag_autotune(self.h, prec, batched, reps)
+    def autotune(self, prec="fp64", batched=True, reps=3, in_situ=False):
+        return cdag_autotune(self.h, prec, batched, reps, in_situ)
 
     def fetch_correlators(self):
         return fetch_correlators(self.h, self.graph_nt)

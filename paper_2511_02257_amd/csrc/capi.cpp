@@ -208,26 +208,29 @@ int cdag_set_timing(cdag_ctx* h, int timing) {
   return guard([&] { h->c.timing = timing != 0; });
 }
 
-int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile) {
+int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile, int grid) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {
     elem_bytes_prec(prec);
     need(kind >= CDAG_K22 && kind <= CDAG_K33, CDAG_E_INVALID, "kind must be K22, K32 or K33");
     need(nvec >= 1, CDAG_E_INVALID, "nvec must be >= 1");
     need(tile >= -1 && tile < cdag::kNumTiles, CDAG_E_INVALID, "tile out of range");
+    need(grid >= 0 && grid < cdag::kNumGrids, CDAG_E_INVALID, "grid must be 0 or 1");
     auto key = std::make_tuple(prec, kind, nvec);
-    if (tile < 0) h->c.tiles.erase(key); else h->c.tiles[key] = tile;
+    if (tile < 0) h->c.tiles.erase(key); else h->c.tiles[key] = cdag::variant_of(tile, grid);
     h->c.version++;
   });
 }
 
-int cdag_get_tile(cdag_ctx* h, int prec, int kind, int nvec, int* tile) {
+int cdag_get_tile(cdag_ctx* h, int prec, int kind, int nvec, int* tile, int* grid) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {
     elem_bytes_prec(prec);
-    need(tile != nullptr, CDAG_E_INVALID, "tile is NULL");
+    need(tile != nullptr && grid != nullptr, CDAG_E_INVALID, "tile or grid is NULL");
     auto it = h->c.tiles.find(std::make_tuple(prec, kind, nvec));
-    *tile = it != h->c.tiles.end() ? it->second : cdag::default_tile(prec, kind, nvec);
+    const int v = it != h->c.tiles.end() ? it->second : cdag::default_tile(prec, kind, nvec);
+    *tile = cdag::variant_tile(v);
+    *grid = cdag::variant_grid(v);
   });
 }
 
@@ -364,14 +367,17 @@ int execute(cdag_ctx* h, int prec, int batched, cdag_exec_stats* out) {
   });
 }
 
-int cdag_autotune(cdag_ctx* h, int prec, int batched, int reps, int64_t* n_tuned) {
+int cdag_autotune(cdag_ctx* h, int prec, int batched, int reps, int mode, int64_t* n_tuned) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {
     cdag::Ctx& c = h->c;
     need(reps >= 1, CDAG_E_INVALID, "reps must be >= 1");
+    need(mode == 0 || mode == 1, CDAG_E_INVALID, "mode must be 0 (synthetic) or 1 (in situ)");
     need(c.dev != nullptr, CDAG_E_STATE, "cdag_bind_device first");
+    need(mode == 0 || c.has_data, CDAG_E_STATE, "in-situ tuning needs leaf data");
     cdag::ensure_plan(c, prec, batched);
-    int64_t n = cdag::device_autotune(c, prec, batched, reps);
+    int64_t n = mode == 0 ? cdag::device_autotune(c, prec, batched, reps)
+                          : cdag::device_autotune_insitu(c, prec, batched, reps);
     c.version++;
     c.have_results = false;
     if (n_tuned) *n_tuned = n;

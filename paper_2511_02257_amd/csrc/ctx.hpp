@@ -33,7 +33,7 @@ struct Ctx {
   int64_t wave_lookahead = 0;
   bool use_graphs = true;
   bool timing = false;
-  TileTable tiles;               // (prec, kind, N) -> tile index overrides
+  TileTable tiles;               // (prec, kind, N) -> kernel variant overrides
   uint64_t version = 1;          // bumped by every change that invalidates a plan
   // last plan
   bool planned = false;
@@ -59,5 +59,6 @@ void device_bind(Ctx& c, int device, void* compute_stream, void* copy_stream);
 void device_bind_arena(Ctx& c, void* arena, uint64_t bytes);
 void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st);
 int64_t device_autotune(Ctx& c, int prec, int batched, int reps);
+int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps);
 
 }  // namespace cdag

@@ -57,10 +57,11 @@ void decompose(int kind, int n, int nt, int tile, int prec, HecDesc* h) {
 int default_tile(int prec, int kind, int n) {
   (void)prec;
   (void)kind;
-  if (n % 64 == 0) return 0;   // 64 x 64
-  if (n % 48 == 0) return 2;   // 48 x 48
-  if (n % 32 == 0 || n < 32) return 1;   // 32 x 32
-  return 0;
+  int tile = 0;                              // 64 x 64
+  if (n % 64 == 0) tile = 0;
+  else if (n % 48 == 0) tile = 2;            // 48 x 48
+  else if (n % 32 == 0 || n < 32) tile = 1;  // 32 x 32
+  return variant_of(tile, 1);
 }
 
 KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTable& tiles) {
@@ -119,8 +120,8 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
   kp.launch_off.reserve(S + 1);
   for (int64_t s = 0; s < S; ++s) {
     kp.launch_off.push_back((int64_t)kp.launches.size());
-    std::vector<HecDesc> hec[kNumTiles];
-    int64_t tiles[kNumTiles] = {0};
+    std::vector<HecDesc> hec[kNumVariants];
+    int64_t tiles[kNumVariants] = {0};
     std::vector<RedDesc> red;
     std::vector<HcaDesc> hca;
     int64_t ws = kp.ws_off, items = 0;
@@ -166,7 +167,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
       }
       hec[tl].push_back(h);
     }
-    for (int tl = 0; tl < kNumTiles; ++tl) {
+    for (int tl = 0; tl < kNumVariants; ++tl) {
       if (hec[tl].empty()) continue;
       Launch L{L_HEC, tl, (int32_t)hec[tl].size(), 0, tiles[tl], 0};
       L.host_desc = (int64_t)kp.blob.size();

@@ -16,17 +16,25 @@ enum LaunchType : int32_t { L_HEC = 0, L_RED = 1, L_HCA = 2, L_XSUM = 3 };
 
 struct Launch {
   int32_t type;
-  int32_t tile;       // HEC: index into kTileShapes
+  int32_t tile;       // HEC: kernel variant (tile shape and grid policy)
   int32_t n_desc;
   int64_t desc_off;   // arena offset of the first descriptor
   int64_t n_items;    // HEC: tiles; RED: 256-element blocks; HCA: (root, t) pairs; XSUM: correlators
   int64_t host_desc;  // byte offset of the first descriptor in KernelPlan::blob
 };
 
-// Tile choice per (precision, kind, N): an explicit table entry (set through
-// the ABI or by the autotuner) wins, else default_tile().
+// Kernel variant of an exterior contraction: a tile shape (index into
+// kTileShapes) and a grid policy, encoded as tile + kNumTiles * grid with
+// grid 0 = persistent (compute units x occupancy workgroups striding over
+// the work list) and grid 1 = one workgroup per work item.
+constexpr int kNumGrids = 2, kNumVariants = kNumTiles * kNumGrids;
+inline int variant_of(int tile, int grid) { return tile + kNumTiles * grid; }
+inline int variant_tile(int v) { return v % kNumTiles; }
+inline int variant_grid(int v) { return v / kNumTiles; }
+// Variant per (precision, kind, N): an explicit table entry (set through the
+// ABI or by the autotuner) wins, else default_tile().
 using TileTable = std::map<std::tuple<int, int, int>, int>;
-int default_tile(int prec, int kind, int n);
+int default_tile(int prec, int kind, int n);   // returns a variant
 // GEMM dimensions, tile counts and split-K of one contraction of `kind` with
 // N = n, nt time slices and tile shape `tile` (offsets and tile_begin unset).
 void decompose(int kind, int n, int nt, int tile, int prec, HecDesc* h);

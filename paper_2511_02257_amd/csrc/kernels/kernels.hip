@@ -568,29 +568,33 @@ unsigned grid_for(int64_t items) { return (unsigned)std::max<int64_t>(1, std::mi
 }  // namespace
 
 template <class TL>
-void launch_hec_tile(int prec, char* arena, const HecDesc* d, int n_desc, int64_t n_items, hipStream_t s) {
+void launch_hec_tile(int prec, bool persistent, char* arena, const HecDesc* d, int n_desc, int64_t n_items,
+                     hipStream_t s) {
   const dim3 block(TL::NTH);
   if (prec == 0) {
-    const dim3 grid(persistent_grid(hec_mfma<double, TL>, TL::NTH, n_items));
+    const dim3 grid(persistent ? persistent_grid(hec_mfma<double, TL>, TL::NTH, n_items) : grid_for(n_items));
     hipLaunchKernelGGL((hec_mfma<double, TL>), grid, block, 0, s, arena, d, n_desc, n_items);
   } else if (prec == 1) {
-    const dim3 grid(persistent_grid(hec_mfma<float, TL>, TL::NTH, n_items));
+    const dim3 grid(persistent ? persistent_grid(hec_mfma<float, TL>, TL::NTH, n_items) : grid_for(n_items));
     hipLaunchKernelGGL((hec_mfma<float, TL>), grid, block, 0, s, arena, d, n_desc, n_items);
   } else {
-    const dim3 grid(persistent_grid(hec_bf16x3<TL>, TL::NTH, n_items));
+    const dim3 grid(persistent ? persistent_grid(hec_bf16x3<TL>, TL::NTH, n_items) : grid_for(n_items));
     hipLaunchKernelGGL((hec_bf16x3<TL>), grid, block, 0, s, arena, d, n_desc, n_items);
   }
 }
 
-hipError_t launch_hec(int prec, int tile, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
+hipError_t launch_hec(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
                       hipStream_t s) {
   const HecDesc* d = reinterpret_cast<const HecDesc*>(arena + desc_off);
+  const int tile = variant % kNumTiles;
+  const bool persistent = variant / kNumTiles == 0;
+  if (variant < 0 || variant >= 2 * kNumTiles) return hipErrorInvalidValue;
   switch (tile) {
-    case 0: launch_hec_tile<Tile0>(prec, arena, d, n_desc, n_items, s); break;
-    case 1: launch_hec_tile<Tile1>(prec, arena, d, n_desc, n_items, s); break;
-    case 2: launch_hec_tile<Tile2>(prec, arena, d, n_desc, n_items, s); break;
-    case 3: launch_hec_tile<Tile3>(prec, arena, d, n_desc, n_items, s); break;
-    case 4: launch_hec_tile<Tile4>(prec, arena, d, n_desc, n_items, s); break;
+    case 0: launch_hec_tile<Tile0>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    case 1: launch_hec_tile<Tile1>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    case 2: launch_hec_tile<Tile2>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    case 3: launch_hec_tile<Tile3>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    case 4: launch_hec_tile<Tile4>(prec, persistent, arena, d, n_desc, n_items, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

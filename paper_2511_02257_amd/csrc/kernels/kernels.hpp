@@ -6,7 +6,7 @@
 
 namespace cdag {
 
-hipError_t launch_hec(int prec, int tile, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
+hipError_t launch_hec(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
                       hipStream_t s);
 hipError_t launch_reduce(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s);
 hipError_t launch_hca(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s);

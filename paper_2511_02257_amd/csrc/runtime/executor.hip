@@ -309,7 +309,7 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
       const int kind = sh.first.first, n = sh.first.second;
       double best = 1e300;
       int best_tile = -1;
-      for (int tile = 0; tile < kNumTiles; ++tile) {
+      for (int tile = 0; tile < kNumVariants; ++tile) {
         HecDesc h{};
         decompose(kind, n, sh.second, tile, prec, &h);
         const int64_t slice = (int64_t)h.M * h.K * eb + (int64_t)h.K * h.N * eb + (int64_t)h.M * h.N * eb;
@@ -359,6 +359,51 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
   ignore(hipEventDestroy(e0));
   ignore(hipEventDestroy(e1));
   HIPC(hipStreamSynchronize(D.comp));
+  return tuned;
+}
+
+// In-situ autotuner: for every distinct (kind, N) in turn, run the planned DAG
+// `reps` times with each kernel variant for that shape (the other shapes keep
+// their current choice), with HIP events around every exterior-contraction
+// launch, and keep the variant with the least summed launch time.
+int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
+  std::map<std::pair<int, int>, int> shapes;
+  for (int64_t u = c.dag.n_leaves; u < c.dag.n_nodes(); ++u)
+    if (c.dag.kind[u] != HCA) shapes[{c.dag.kind[u], c.dag.nvec[u]}] = 1;
+  const bool timing = c.timing;
+  c.timing = true;
+  int64_t tuned = 0;
+  try {
+    for (const auto& sh : shapes) {
+      const auto key = std::make_tuple(prec, sh.first.first, sh.first.second);
+      double best = 1e300;
+      int best_v = -1;
+      for (int v = 0; v < kNumVariants; ++v) {
+        c.tiles[key] = v;
+        c.version++;
+        ensure_plan(c, prec, batched);
+        if ((uint64_t)c.kplan.total_bytes > c.dev->arena_bytes) continue;
+        double t = 0;
+        for (int r = 0; r < reps; ++r) {
+          cdag_exec_stats st{};
+          device_execute(c, prec, batched, &st);
+          t += st.t_hec_s;
+        }
+        if (t < best) { best = t; best_v = v; }
+      }
+      if (best_v >= 0) {
+        c.tiles[key] = best_v;
+        ++tuned;
+      } else {
+        c.tiles.erase(key);
+      }
+      c.version++;
+    }
+  } catch (...) {
+    c.timing = timing;
+    throw;
+  }
+  c.timing = timing;
   return tuned;
 }
 

@@ -5,7 +5,7 @@ then WRITE_SIZE, in KiB per dispatch), each scaled by what the same counter
 reads for a plain device copy of known size.
 
     python -m paper_2511_02257_amd.profiling traffic \\
-        --kernel 'hec_mfma<double' --tile 0 \\
+        --kernel 'hec_mfma<double' --tile 5 \\
         --fetch gpurun_out/pmc_fetch/fetch_counter_collection.csv \\
         --write gpurun_out/pmc_write/write_counter_collection.csv \\
         --copy-fetch gpurun_out/pmc_copy_fetch/cf_counter_collection.csv \\
@@ -70,7 +70,7 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True)
-    t.add_argument("--tile", type=int, required=True)
+    t.add_argument("--tile", type=int, required=True, help="kernel variant: tile shape + 5 * grid")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
     t.add_argument("--copy-fetch", required=True)

@@ -111,19 +111,21 @@ def test_baryon_ragged_splitk(baryon_small, prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
-def test_every_tile_shape(meson_small, baryon_small, prec, tile):
+@pytest.mark.parametrize("grid", [0, 1])
+def test_every_tile_shape(meson_small, baryon_small, prec, tile, grid):
     for name, (wl, ref) in (("meson_small", meson_small), ("baryon_small", baryon_small)):
-        r = run(wl, "tree", prec, True, tile=tile)
+        r = run(wl, "tree", prec, True, tile=tile, grid=grid)
         err = rel_errors(r["corr"], ref)
-        print(f"{name} {prec} tile {tile}: max rel {err.max():.3e}")
+        print(f"{name} {prec} tile {tile} grid {grid}: max rel {err.max():.3e}")
         assert err.max() <= TOL[prec]
 
 
-def test_autotune_then_parity(baryon_small):
+@pytest.mark.parametrize("in_situ", [False, True])
+def test_autotune_then_parity(baryon_small, in_situ):
     wl, ref = baryon_small
     for prec in ("fp64", "fp32"):
-        r = run(wl, "tree", prec, True, autotune=True)
-        print(f"autotuned {prec}: {r['tuned']}")
+        r = run(wl, "tree", prec, True, autotune=True, in_situ=in_situ)
+        print(f"autotuned {prec} in_situ={in_situ}: {r['tuned']}")
         assert rel_errors(r["corr"], ref).max() <= TOL[prec]
 
 
