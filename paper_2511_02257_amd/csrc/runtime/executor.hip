@@ -1,13 +1,15 @@
 // Device runtime: leaf staging in pinned host memory, the arena borrowed from
 // the caller, and execution of a placed plan on two HIP streams.
 //
-// Per step s the copy stream performs the step's spills (D2H) and uploads
-// (H2D) and records ev_copy[s]; the compute stream waits for it when the step
-// uploaded operands (or when an output reuses memory a spill was still
-// reading), launches the step's kernels and records ev_comp[s].  A copy into
-// memory that kernels last touched at step k first waits for ev_comp[k].  All
-// waits come from the plan (place()), so copies overlap kernels of earlier
-// steps whenever the memory they use is already free.
+// Eager execution: per step s the copy stream performs the step's spills
+// (D2H) and uploads (H2D) and records ev_copy[s]; the compute stream waits for
+// it when the step uploaded operands (or when an output reuses memory a spill
+// was still reading), launches the step's kernels and records ev_comp[s].  A
+// copy into memory that kernels last touched at step k first waits for
+// ev_comp[k].  All waits come from the plan (place()), so copies overlap
+// kernels of earlier steps whenever the memory they use is already free.
+// Graph replay: steps are captured in segments with transfers and kernels on
+// one stream, so the stream order alone carries every dependency.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,8 +58,7 @@ struct Device {
   int resident_prec = -1;
   uint64_t resident_key = 0, resident_epoch = 0;
   // captured step sequence: one graph per segment of consecutive steps
-  hipStream_t cap_comp = nullptr, cap_copy = nullptr;   // capture origin and its copy branch
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t cap_comp = nullptr;   // stream the segments are captured on
   std::vector<hipGraph_t> seg_graph;
   std::vector<hipGraphExec_t> seg_exec;
   uint64_t graph_key = 0, graph_epoch = 0, graph_stage = 0;
@@ -88,9 +89,6 @@ struct Device {
     if (device >= 0) ignore(hipSetDevice(device));
     drop_graphs();
     if (cap_comp) ignore(hipStreamDestroy(cap_comp));
-    if (cap_copy) ignore(hipStreamDestroy(cap_copy));
-    if (ev_fork) ignore(hipEventDestroy(ev_fork));
-    if (ev_join) ignore(hipEventDestroy(ev_join));
     for (auto e : ev_comp) ignore(hipEventDestroy(e));
     for (auto e : ev_copy) ignore(hipEventDestroy(e));
     for (auto e : tpool) ignore(hipEventDestroy(e));
@@ -122,10 +120,7 @@ void device_bind(Ctx& c, int device, void* compute_stream, void* copy_stream) {
   if (!c.dev->t0) {
     HIPC(hipEventCreate(&c.dev->t0));
     HIPC(hipEventCreate(&c.dev->t1));
-    HIPC(hipEventCreateWithFlags(&c.dev->ev_fork, hipEventDisableTiming));
-    HIPC(hipEventCreateWithFlags(&c.dev->ev_join, hipEventDisableTiming));
     HIPC(hipStreamCreateWithFlags(&c.dev->cap_comp, hipStreamNonBlocking));
-    HIPC(hipStreamCreateWithFlags(&c.dev->cap_copy, hipStreamNonBlocking));
   }
 }
 
@@ -231,14 +226,17 @@ int64_t launch_step(const KernelPlan& kp, int64_t s, int prec, char* arena, hipS
 }
 
 // Enqueue steps [s0, s1): copies on `copy`, kernels on `comp`, cross-stream
-// waits from the plan.  In a captured segment, waits on steps before s0 are
-// left out: the segments' graphs run one after another on one stream, so
-// everything before s0 has finished when the segment starts.
+// waits from the plan.  With copy == comp (how segments are captured) every
+// dependency is the stream order and no event is used.  In a captured
+// segment, waits on steps before s0 are left out: the segments' graphs run one
+// after another on one stream, so everything before s0 has finished when the
+// segment starts.
 int64_t issue_steps(Ctx& c, Device& D, int prec, int64_t s0, int64_t s1, hipStream_t comp,
                     hipStream_t copy, Device* timed, bool in_capture) {
   const Plan& p = c.plan;
   const KernelPlan& kp = c.kplan;
   const int eb = prec == CDAG_FP64 ? 16 : 8;
+  const bool one_stream = copy == comp;
   int64_t copy_waited = in_capture ? s0 - 1 : -1, comp_waited = in_capture ? s0 - 1 : -1;
   int64_t n_launch = 0;
   for (int64_t s = s0; s < s1; ++s) {
@@ -248,7 +246,7 @@ int64_t issue_steps(Ctx& c, Device& D, int prec, int64_t s0, int64_t s1, hipStre
       const PlanRec& r = p.recs[ri];
       const size_t sz = (size_t)c.dag.size(r.node, eb);
       if (r.op == OP_D2H || r.op == OP_H2D) {
-        if (r.wait_comp > copy_waited) {
+        if (!one_stream && r.wait_comp > copy_waited) {
           HIPC(hipStreamWaitEvent(copy, D.ev_comp[r.wait_comp], 0));
           copy_waited = r.wait_comp;
         }
@@ -264,14 +262,16 @@ int64_t issue_steps(Ctx& c, Device& D, int prec, int64_t s0, int64_t s1, hipStre
         need_copy = std::max(need_copy, r.wait_copy);
       }
     }
-    if (any_copy) HIPC(hipEventRecord(D.ev_copy[s], copy));
-    if (any_h2d) need_copy = std::max(need_copy, s);
-    if (need_copy > comp_waited) {
-      HIPC(hipStreamWaitEvent(comp, D.ev_copy[need_copy], 0));
-      comp_waited = need_copy;
+    if (!one_stream) {
+      if (any_copy) HIPC(hipEventRecord(D.ev_copy[s], copy));
+      if (any_h2d) need_copy = std::max(need_copy, s);
+      if (need_copy > comp_waited) {
+        HIPC(hipStreamWaitEvent(comp, D.ev_copy[need_copy], 0));
+        comp_waited = need_copy;
+      }
     }
     n_launch += launch_step(kp, s, prec, D.arena, comp, timed);
-    HIPC(hipEventRecord(D.ev_comp[s], comp));
+    if (!one_stream) HIPC(hipEventRecord(D.ev_comp[s], comp));
   }
   return n_launch;
 }
@@ -465,11 +465,8 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
         hipGraph_t g = nullptr;
         HIPC(hipStreamBeginCapture(D.cap_comp, hipStreamCaptureModeThreadLocal));
         try {
-          HIPC(hipEventRecord(D.ev_fork, D.cap_comp));
-          HIPC(hipStreamWaitEvent(D.cap_copy, D.ev_fork, 0));
-          issue_steps(c, D, prec, s0, s1, D.cap_comp, D.cap_copy, nullptr, true);
-          HIPC(hipEventRecord(D.ev_join, D.cap_copy));
-          HIPC(hipStreamWaitEvent(D.cap_comp, D.ev_join, 0));
+          // transfers and kernels on the one capture stream, in step order
+          issue_steps(c, D, prec, s0, s1, D.cap_comp, D.cap_comp, nullptr, true);
         } catch (...) {
           ignore(hipStreamEndCapture(D.cap_comp, &g));
           if (g) ignore(hipGraphDestroy(g));

@@ -75,16 +75,18 @@ def test_meson_ragged_with_evictions(meson_small, prec):
     d = OD.build(wl.leaves, wl.graphs)
     budget = OS.memsim(d, OS.input_order(d), eb)["peak_live"] // 4
     results = []
-    for policy, batched, look in (("input", False, 0), ("input", True, 0), ("tree", False, 0),
-                                  ("tree", True, 0), ("tree", True, 5), ("tree", True, 1 << 62)):
-        r = run(wl, policy, prec, batched, budget=budget, wave_lookahead=look)
+    for policy, batched, look, graphs in (
+            ("input", False, 0, True), ("input", False, 0, False), ("input", True, 0, True),
+            ("tree", False, 0, False), ("tree", True, 0, True), ("tree", True, 0, False),
+            ("tree", True, 5, True), ("tree", True, 1 << 62, False)):
+        r = run(wl, policy, prec, batched, budget=budget, wave_lookahead=look, use_graphs=graphs)
         _, _, o = oracle_plan_counts(wl, policy, eb, budget, batched, lookahead=look)
         p = r["stats"]["plan"]
         for k in ("peak_resident", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes"):
             assert p[k] == o[k], (policy, batched, k)
         assert p["n_evict"] > 0
         err = rel_errors(r["corr"], ref)
-        print(f"meson_small {prec} {policy} batched={batched} lookahead={look} "
+        print(f"meson_small {prec} {policy} batched={batched} lookahead={look} graphs={graphs} "
               f"waves={p['n_steps']} evict={p['n_evict']} "
               f"max rel {err.max():.3e} median {np.median(err):.3e}")
         assert err.max() <= TOL[prec]
