@@ -58,8 +58,8 @@ def timed_steps(ctx, runner, prec, batched, steps, warmup):
 
 def measured_traffic(tile):
     """HBM bytes per launch of the exterior-contraction kernel from the committed
-    counter summary, or None when the kernel source or variant (tile + 5 * grid)
-    differs from the one the counters were taken on."""
+    counter summary, or None when the kernel source or variant differs from the
+    one the counters were taken on."""
     path = os.path.join(ROOT, "profiles", "hec_traffic_meson_ring.json")
     if not os.path.exists(path):
         return None
@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--skip-extras", action="store_true", help="only the headline value")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--fp64-variant", default=None, metavar="TILE,GRID,STAGES",
+                    help="fix the FP64 K22 kernel variant instead of autotuning it "
+                         "(so that counter runs profile the variant a timed run chose)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -144,9 +147,14 @@ def main():
     runner = DeviceRunner(ctx, 0)
     tiles = {}
     for prec in ("fp64", "fp32", "bf16x3"):
-        runner.autotune(prec, True, reps=2, in_situ=True)
-        t, g = ctx.get_tile(prec, 0, 64)
-        tiles[prec] = {"K22_N64": {"tile": list(X.TILES[t]), "grid": X.binding.GRIDS[g]}}
+        if prec == "fp64" and args.fp64_variant:
+            ctx.set_tile("fp64", 0, 64, *(int(x) for x in args.fp64_variant.split(",")))
+            runner.ensure_arena(ctx.plan("fp64", True)["arena_bytes"])
+        elif prec == "fp64" or not args.skip_extras:
+            runner.autotune(prec, True, reps=2, in_situ=True)
+        t, g, st = ctx.get_tile(prec, 0, 64)
+        tiles[prec] = {"K22_N64": {"tile": list(X.TILES[t]), "grid": X.binding.GRIDS[g],
+                                   "lds_stages": st}}
     log("autotuned tiles", tiles)
 
     # ---- headline: FP64, Tree, waves, leaves resident, graph replay
@@ -179,12 +187,13 @@ def main():
         hec_n += s2["n_hec_launches"]
     ctx.set_timing(False)
     achieved = hec_f / hec_t / 1e12
-    t64, g64 = ctx.get_tile("fp64", 0, 64)
-    variant = t64 + len(X.TILES) * g64
+    t64, g64, st64 = ctx.get_tile("fp64", 0, 64)
+    variant = X.binding.variant_index(t64, g64, st64)
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
                        "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4),
                        "traffic": measured_traffic(variant), "tile": list(X.TILES[t64]),
-                       "grid": X.binding.GRIDS[g64],
+                       "grid": X.binding.GRIDS[g64], "lds_stages": st64,
+                       "variant": [t64, g64, st64],
                        "kernel": "hec_mfma<double> (grouped K22 waves)",
                        "avg_launch_us": round(hec_t / hec_n * 1e6, 3),
                        "flops_per_launch": hec_f / hec_n,

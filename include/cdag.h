@@ -110,6 +110,7 @@ typedef struct {
   int64_t arena_bytes;   /* device bytes cdag_bind_arena must provide            */
   int64_t tensor_highwater; /* physical high-water of the tensor pool           */
   int64_t host_spill_bytes; /* pinned host bytes for spilled intermediates      */
+  int64_t hec_items;     /* exterior-contraction work items (output tiles x K splits) */
   double flops;          /* algorithmic flops, 8 per complex multiply-add        */
   double t_sched_s, t_plan_s;
 } cdag_plan_stats;
@@ -169,11 +170,13 @@ int cdag_set_timing(cdag_ctx* c, int timing);
  * 3 = 128x64, 4 = 64x32 (output rows x columns per workgroup), -1 removes an
  * explicit choice.  grid: 0 = persistent (compute units x occupancy
  * workgroups striding over the work list), 1 = one workgroup per work item.
+ * lds_stages: 2 = double-buffered operand tiles in LDS, 1 = a single buffer
+ * refilled from registers (half the LDS, more workgroups per compute unit).
  * Without an explicit choice a default by N applies (cdag_get_tile reports
  * the choice in force).  Every variant gives results within the precision's
  * bound; bits may differ between tile shapes. */
-int cdag_set_tile(cdag_ctx* c, int prec, int kind, int nvec, int tile, int grid);
-int cdag_get_tile(cdag_ctx* c, int prec, int kind, int nvec, int* tile, int* grid);
+int cdag_set_tile(cdag_ctx* c, int prec, int kind, int nvec, int tile, int grid, int lds_stages);
+int cdag_get_tile(cdag_ctx* c, int prec, int kind, int nvec, int* tile, int* grid, int* lds_stages);
 
 /* Host-only: simulate Sec. II-C for `order` (n node ids, each contraction
  * once, topological) with element size elem_bytes (16 or 8).  M_out
@@ -215,7 +218,7 @@ int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
  * are scratch between executes) and keep the fastest per time slice.  mode 1
  * (in situ): execute the planned DAG `reps` times per variant, shape by
  * shape, with launch timing on, and keep the least summed exterior-contraction
- * time (needs leaf data; costs 10 * reps executes per shape).  *n_tuned
+ * time (needs leaf data; costs 20 * reps executes per shape).  *n_tuned
  * (nullable) receives the number of shapes tuned.  Needs cdag_bind_device and
  * an arena of at least the plan's arena_bytes; invalidates the current plan
  * and results. */

@@ -46,7 +46,7 @@ class cdag_graph(C.Structure):
 
 _PLAN_INT = ["n_nodes", "n_leaves", "n_contr", "n_roots", "n_steps", "peak_post", "peak_live",
              "peak_resident", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes", "budget",
-             "arena_bytes", "tensor_highwater", "host_spill_bytes"]
+             "arena_bytes", "tensor_highwater", "host_spill_bytes", "hec_items"]
 _PLAN_DBL = ["flops", "t_sched_s", "t_plan_s"]
 
 
@@ -90,8 +90,9 @@ def lib():
             "set_mem_budget": [P, C.c_uint64],
             "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
             "cdag_set_timing": [P, C.c_int],
-            "cdag_set_tile": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int],
-            "cdag_get_tile": [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)],
+            "cdag_set_tile": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int],
+            "cdag_get_tile": [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                              C.POINTER(C.c_int)],
             "cdag_memsim": [P, C.POINTER(I64), I64, C.c_int, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
             "cdag_plan": [P, C.c_int, C.c_int, C.POINTER(cdag_plan_stats)],
             "cdag_plan_ops": [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64), I64, C.POINTER(I64)],
@@ -210,15 +211,22 @@ TILES = {0: (64, 64), 1: (32, 32), 2: (48, 48), 3: (128, 64), 4: (64, 32)}
 GRIDS = {0: "persistent", 1: "one workgroup per item"}
 
 
-def cdag_set_tile(h, prec: str, kind: int, nvec: int, tile: int, grid: int = 1) -> None:
-    _check(lib().cdag_set_tile(h, PREC[prec], int(kind), int(nvec), int(tile), int(grid)))
+def variant_index(tile: int, grid: int, lds_stages: int) -> int:
+    """The library's single-integer encoding of a kernel variant."""
+    return tile + len(TILES) * (grid + 2 * (2 - lds_stages))
+
+
+def cdag_set_tile(h, prec: str, kind: int, nvec: int, tile: int, grid: int = 1,
+                  lds_stages: int = 2) -> None:
+    _check(lib().cdag_set_tile(h, PREC[prec], int(kind), int(nvec), int(tile), int(grid),
+                               int(lds_stages)))
 
 
 def cdag_get_tile(h, prec: str, kind: int, nvec: int):
-    """(tile, grid) in force for that shape."""
-    t, g = C.c_int(), C.c_int()
-    _check(lib().cdag_get_tile(h, PREC[prec], int(kind), int(nvec), C.byref(t), C.byref(g)))
-    return t.value, g.value
+    """(tile, grid, lds_stages) in force for that shape."""
+    t, g, st = C.c_int(), C.c_int(), C.c_int()
+    _check(lib().cdag_get_tile(h, PREC[prec], int(kind), int(nvec), C.byref(t), C.byref(g), C.byref(st)))
+    return t.value, g.value, st.value
 
 
 def cdag_memsim(h, order: Sequence[int], elem_bytes: int = 16):
@@ -355,8 +363,8 @@ class Context:
     def set_timing(self, on=True):
         cdag_set_timing(self.h, on)
 
-    def set_tile(self, prec, kind, nvec, tile, grid=1):
-        cdag_set_tile(self.h, prec, kind, nvec, tile, grid)
+    def set_tile(self, prec, kind, nvec, tile, grid=1, lds_stages=2):
+        cdag_set_tile(self.h, prec, kind, nvec, tile, grid, lds_stages)
 
     def get_tile(self, prec, kind, nvec):
         return cdag_get_tile(self.h, prec, kind, nvec)

@@ -208,7 +208,7 @@ int cdag_set_timing(cdag_ctx* h, int timing) {
   return guard([&] { h->c.timing = timing != 0; });
 }
 
-int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile, int grid) {
+int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile, int grid, int lds_stages) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {
     elem_bytes_prec(prec);
@@ -216,21 +216,23 @@ int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile, int grid)
     need(nvec >= 1, CDAG_E_INVALID, "nvec must be >= 1");
     need(tile >= -1 && tile < cdag::kNumTiles, CDAG_E_INVALID, "tile out of range");
     need(grid >= 0 && grid < cdag::kNumGrids, CDAG_E_INVALID, "grid must be 0 or 1");
+    need(lds_stages == 1 || lds_stages == 2, CDAG_E_INVALID, "lds_stages must be 1 or 2");
     auto key = std::make_tuple(prec, kind, nvec);
-    if (tile < 0) h->c.tiles.erase(key); else h->c.tiles[key] = cdag::variant_of(tile, grid);
+    if (tile < 0) h->c.tiles.erase(key); else h->c.tiles[key] = cdag::variant_of(tile, grid, lds_stages);
     h->c.version++;
   });
 }
 
-int cdag_get_tile(cdag_ctx* h, int prec, int kind, int nvec, int* tile, int* grid) {
+int cdag_get_tile(cdag_ctx* h, int prec, int kind, int nvec, int* tile, int* grid, int* lds_stages) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {
     elem_bytes_prec(prec);
-    need(tile != nullptr && grid != nullptr, CDAG_E_INVALID, "tile or grid is NULL");
+    need(tile != nullptr && grid != nullptr && lds_stages != nullptr, CDAG_E_INVALID, "NULL output");
     auto it = h->c.tiles.find(std::make_tuple(prec, kind, nvec));
     const int v = it != h->c.tiles.end() ? it->second : cdag::default_tile(prec, kind, nvec);
     *tile = cdag::variant_tile(v);
     *grid = cdag::variant_grid(v);
+    *lds_stages = cdag::variant_stages(v);
   });
 }
 
@@ -270,6 +272,7 @@ static void fill_plan_stats(const cdag::Ctx& c, cdag_plan_stats* s) {
   s->arena_bytes = c.kplan.total_bytes;
   s->tensor_highwater = p.leaf_region_bytes + p.pool_bytes;
   s->host_spill_bytes = p.host_spill_bytes;
+  s->hec_items = c.kplan.hec_items;
   s->flops = c.kplan.flops;
   s->t_sched_s = c.t_sched;
   s->t_plan_s = c.t_plan;

@@ -32,14 +32,15 @@ void gemm_dims(const Dag& d, int64_t u, int32_t* M, int32_t* N, int32_t* K) {
   }
 }
 
-void decompose(int kind, int n, int nt, int tile, int prec, HecDesc* h) {
+void decompose(int kind, int n, int nt, int variant, int prec, HecDesc* h) {
+  if (variant < 0 || variant >= kNumVariants) throw std::invalid_argument("kernel variant out of range");
   const int ks = k_step(prec);
   switch (kind) {
     case K22: h->M = n; h->N = n; h->K = n; break;
     case K32: h->M = n * n; h->N = n; h->K = n; break;
     default: h->M = n; h->N = n; h->K = n * n; break;
   }
-  const TileShape& ts = kTileShapes[tile];
+  const TileShape& ts = kTileShapes[variant_tile(variant)];
   h->nt = nt;
   h->tiles_m = (h->M + ts.bm - 1) / ts.bm;
   h->tiles_n = (h->N + ts.bn - 1) / ts.bn;
@@ -152,6 +153,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
       h.ws_off = -1;
       h.tile_begin = (int32_t)tiles[tl];
       tiles[tl] += h.tile_count;
+      kp.hec_items += h.tile_count;
       if (h.splits > 1) {
         h.ws_off = ws;
         RedDesc rd{};

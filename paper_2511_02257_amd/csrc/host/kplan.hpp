@@ -24,13 +24,17 @@ struct Launch {
 };
 
 // Kernel variant of an exterior contraction: a tile shape (index into
-// kTileShapes) and a grid policy, encoded as tile + kNumTiles * grid with
-// grid 0 = persistent (compute units x occupancy workgroups striding over
-// the work list) and grid 1 = one workgroup per work item.
-constexpr int kNumGrids = 2, kNumVariants = kNumTiles * kNumGrids;
-inline int variant_of(int tile, int grid) { return tile + kNumTiles * grid; }
+// kTileShapes), a grid policy and the LDS stages, encoded as
+// tile + kNumTiles * (grid + 2 * (2 - stages)) with grid 0 = persistent
+// (compute units x occupancy workgroups striding over the work list),
+// grid 1 = one workgroup per work item, and stages 2 (double buffer) or 1.
+constexpr int kNumGrids = 2, kNumVariants = kNumTiles * kNumGrids * 2;
+inline int variant_of(int tile, int grid, int stages = 2) {
+  return tile + kNumTiles * (grid + 2 * (2 - stages));
+}
 inline int variant_tile(int v) { return v % kNumTiles; }
-inline int variant_grid(int v) { return v / kNumTiles; }
+inline int variant_grid(int v) { return (v / kNumTiles) % 2; }
+inline int variant_stages(int v) { return 2 - v / (2 * kNumTiles); }
 // Variant per (precision, kind, N): an explicit table entry (set through the
 // ABI or by the autotuner) wins, else default_tile().
 using TileTable = std::map<std::tuple<int, int, int>, int>;
@@ -63,6 +67,7 @@ struct KernelPlan {
   std::vector<int32_t> sum_nt;            // per correlator
   double flops = 0;
   double hec_flops = 0, hec_bytes = 0;
+  int64_t hec_items = 0;                  // summed over all exterior-contraction launches
 };
 
 int64_t elem_bytes_of(int prec);                 // 16 for FP64, 8 otherwise

@@ -133,7 +133,10 @@ __device__ __forceinline__ void store_block(T* C, int M, int N, int row0, int co
   }
 }
 
-template <typename T, class TL>
+// ST: LDS stages.  2 = double buffer (one barrier per k-chunk); 1 = one
+// buffer refilled from the register prefetch (two barriers per k-chunk, half
+// the LDS, more workgroups per compute unit).
+template <typename T, class TL, int ST>
 __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs,
                                                      int n_desc, int64_t n_items) {
   typedef typename Mfma<T>::V V;
@@ -142,8 +145,8 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
   // the A tile is split into 8-element row segments: [plane][row][k / 8]
   constexpr int SEGA = 2 * BM * (BK / 8), SEGB = 2 * BK * (BN / 8);
   constexpr int LA = (SEGA + NTH - 1) / NTH, LB = (SEGB + NTH - 1) / NTH;
-  __shared__ T As[2][2][BM][APAD];   // [stage][plane][m][k]
-  __shared__ T Bs[2][2][BK][BPAD];   // [stage][plane][k][n]
+  __shared__ T As[ST][2][BM][APAD];   // [stage][plane][m][k]
+  __shared__ T Bs[ST][2][BK][BPAD];   // [stage][plane][k][n]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / TL::WGN, wn = wave % TL::WGN, li = lane & 15, lk = lane >> 4;
 
@@ -209,10 +212,16 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
 
     const int nk = (w.kend - w.kbeg + BK - 1) / BK;
     gload(w.kbeg);
-    sstore(0);
-    __syncthreads();
+    if (ST == 2) {
+      sstore(0);
+      __syncthreads();
+    }
     for (int c = 0; c < nk; ++c) {
-      const int st = c & 1;
+      const int st = ST == 2 ? (c & 1) : 0;
+      if (ST == 1) {
+        sstore(0);
+        __syncthreads();
+      }
       if (c + 1 < nk) gload(w.kbeg + (c + 1) * BK);
 #pragma unroll
       for (int k4 = 0; k4 < BK / 4; ++k4) {
@@ -247,7 +256,7 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
             ci[i][j] = Mfma<T>::mma(a_i[i], b_r[j], ci[i][j]);
           }
       }
-      if (c + 1 < nk) sstore(st ^ 1);
+      if (ST == 2 && c + 1 < nk) sstore(st ^ 1);
       __syncthreads();
     }
 
@@ -274,7 +283,7 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-template <class TL>
+template <class TL, int ST>
 __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, const HecDesc* __restrict__ descs,
                                                        int n_desc, int64_t n_items) {
   constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
@@ -282,8 +291,8 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
   constexpr int SEGA = 2 * BM * (BK / 8), SEGB = 2 * BK * (BN / 8);
   constexpr int LA = (SEGA + NTH - 1) / NTH, LB = (SEGB + NTH - 1) / NTH;
   // [stage][plane][hi/lo][row][k]: A rows are m, B rows are n (B is stored transposed)
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][2][BM][PAD];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][2][BN][PAD];
+  __shared__ __attribute__((aligned(16))) __bf16 As[ST][2][2][BM][PAD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[ST][2][2][BN][PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / TL::WGN, wn = wave % TL::WGN, li = lane & 15, lk = lane >> 4;
 
@@ -359,10 +368,16 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
 
     const int nk = (w.kend - w.kbeg + BK - 1) / BK;
     gload(w.kbeg);
-    sstore(0);
-    __syncthreads();
+    if (ST == 2) {
+      sstore(0);
+      __syncthreads();
+    }
     for (int c = 0; c < nk; ++c) {
-      const int st = c & 1;
+      const int st = ST == 2 ? (c & 1) : 0;
+      if (ST == 1) {
+        sstore(0);
+        __syncthreads();
+      }
       if (c + 1 < nk) gload(w.kbeg + (c + 1) * BK);
       // one 16x16x32 step: lane holds k = 8*lk .. 8*lk+7 of row li (A) / column li (B)
       v8bf a[TM][2][2], b[TN][2][2], bn_hi[TN], bn_lo[TN];   // [block][plane][hi/lo]
@@ -402,7 +417,7 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
       TERM(a[i][1][0], bn_hi[j], a[i][1][0], b[j][0][0])
 #undef TERM
 #undef MM
-      if (c + 1 < nk) sstore(st ^ 1);
+      if (ST == 2 && c + 1 < nk) sstore(st ^ 1);
       __syncthreads();
     }
 
@@ -567,36 +582,46 @@ constexpr int64_t kMaxGrid = 1 << 20;
 unsigned grid_for(int64_t items) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, kMaxGrid)); }
 }  // namespace
 
-template <class TL>
+template <class TL, int ST>
 void launch_hec_tile(int prec, bool persistent, char* arena, const HecDesc* d, int n_desc, int64_t n_items,
                      hipStream_t s) {
   const dim3 block(TL::NTH);
   if (prec == 0) {
-    const dim3 grid(persistent ? persistent_grid(hec_mfma<double, TL>, TL::NTH, n_items) : grid_for(n_items));
-    hipLaunchKernelGGL((hec_mfma<double, TL>), grid, block, 0, s, arena, d, n_desc, n_items);
+    const dim3 grid(persistent ? persistent_grid(hec_mfma<double, TL, ST>, TL::NTH, n_items) : grid_for(n_items));
+    hipLaunchKernelGGL((hec_mfma<double, TL, ST>), grid, block, 0, s, arena, d, n_desc, n_items);
   } else if (prec == 1) {
-    const dim3 grid(persistent ? persistent_grid(hec_mfma<float, TL>, TL::NTH, n_items) : grid_for(n_items));
-    hipLaunchKernelGGL((hec_mfma<float, TL>), grid, block, 0, s, arena, d, n_desc, n_items);
+    const dim3 grid(persistent ? persistent_grid(hec_mfma<float, TL, ST>, TL::NTH, n_items) : grid_for(n_items));
+    hipLaunchKernelGGL((hec_mfma<float, TL, ST>), grid, block, 0, s, arena, d, n_desc, n_items);
   } else {
-    const dim3 grid(persistent ? persistent_grid(hec_bf16x3<TL>, TL::NTH, n_items) : grid_for(n_items));
-    hipLaunchKernelGGL((hec_bf16x3<TL>), grid, block, 0, s, arena, d, n_desc, n_items);
+    const dim3 grid(persistent ? persistent_grid(hec_bf16x3<TL, ST>, TL::NTH, n_items) : grid_for(n_items));
+    hipLaunchKernelGGL((hec_bf16x3<TL, ST>), grid, block, 0, s, arena, d, n_desc, n_items);
   }
 }
 
+template <int ST>
+void launch_hec_stages(int prec, int tile, bool persistent, char* arena, const HecDesc* d, int n_desc,
+                       int64_t n_items, hipStream_t s) {
+  switch (tile) {
+    case 0: launch_hec_tile<Tile0, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    case 1: launch_hec_tile<Tile1, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    case 2: launch_hec_tile<Tile2, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    case 3: launch_hec_tile<Tile3, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    default: launch_hec_tile<Tile4, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
+  }
+}
+
+// variant = tile + kNumTiles * (grid + 2 * stage_choice), stage_choice 0: two
+// LDS stages, 1: one; grid 0: persistent, 1: one workgroup per work item.
 hipError_t launch_hec(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
                       hipStream_t s) {
+  if (variant < 0 || variant >= 4 * kNumTiles) return hipErrorInvalidValue;
   const HecDesc* d = reinterpret_cast<const HecDesc*>(arena + desc_off);
   const int tile = variant % kNumTiles;
-  const bool persistent = variant / kNumTiles == 0;
-  if (variant < 0 || variant >= 2 * kNumTiles) return hipErrorInvalidValue;
-  switch (tile) {
-    case 0: launch_hec_tile<Tile0>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    case 1: launch_hec_tile<Tile1>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    case 2: launch_hec_tile<Tile2>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    case 3: launch_hec_tile<Tile3>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    case 4: launch_hec_tile<Tile4>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    default: return hipErrorInvalidValue;
-  }
+  const bool persistent = (variant / kNumTiles) % 2 == 0;
+  if (variant / (2 * kNumTiles) == 0)
+    launch_hec_stages<2>(prec, tile, persistent, arena, d, n_desc, n_items, s);
+  else
+    launch_hec_stages<1>(prec, tile, persistent, arena, d, n_desc, n_items, s);
   return hipGetLastError();
 }
 

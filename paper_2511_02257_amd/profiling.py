@@ -70,7 +70,7 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True)
-    t.add_argument("--tile", type=int, required=True, help="kernel variant: tile shape + 5 * grid")
+    t.add_argument("--tile", type=int, required=True, help="kernel variant index (binding.variant_index)")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
     t.add_argument("--copy-fetch", required=True)

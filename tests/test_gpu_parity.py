@@ -114,11 +114,12 @@ def test_baryon_ragged_splitk(baryon_small, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("grid", [0, 1])
-def test_every_tile_shape(meson_small, baryon_small, prec, tile, grid):
+@pytest.mark.parametrize("stages", [2, 1])
+def test_every_tile_shape(meson_small, baryon_small, prec, tile, grid, stages):
     for name, (wl, ref) in (("meson_small", meson_small), ("baryon_small", baryon_small)):
-        r = run(wl, "tree", prec, True, tile=tile, grid=grid)
+        r = run(wl, "tree", prec, True, tile=tile, grid=grid, lds_stages=stages)
         err = rel_errors(r["corr"], ref)
-        print(f"{name} {prec} tile {tile} grid {grid}: max rel {err.max():.3e}")
+        print(f"{name} {prec} tile {tile} grid {grid} stages {stages}: max rel {err.max():.3e}")
         assert err.max() <= TOL[prec]
 
 

@@ -166,6 +166,34 @@ def test_full_configs_match_stored_oracle_results():
             c.set_mem_budget(None)
 
 
+def test_kernel_variants_round_trip_and_share_decomposition():
+    """Every (tile, grid, lds_stages) choice is stored and reported back.  Work
+    items are output tiles of the chosen shape (times the K splits): with no
+    split (K = N = 72 < 512) their count is sum over contractions of
+    Nt * ceil(M / bm) * ceil(N / bn), whatever the grid policy and LDS stages."""
+    wl = W.meson_ring(n_leaves=6, nvec=72, nt=5, n_graphs=20, lmin=4, lmax=6, with_data=False)
+    d = OD.build(wl.leaves, wl.graphs)
+    n_k22 = sum(1 for u in range(d.n_nodes) if d.kind[u] == W.K22)
+    c = ctx_for(wl)
+    c.schedule("tree")
+    for tile, (bm, bn) in sorted(X.TILES.items()):
+        want = n_k22 * 5 * (-(-72 // bm)) * (-(-72 // bn))
+        for grid in (0, 1):
+            for stages in (2, 1):
+                for prec in ("fp64", "fp32", "bf16x3"):
+                    for kind in (0, 1, 2):
+                        c.set_tile(prec, kind, 72, tile, grid, stages)
+                        assert c.get_tile(prec, kind, 72) == (tile, grid, stages)
+                    assert c.plan(prec, True)["hec_items"] == want, (tile, grid, stages, prec)
+    for bad in ((5, 1, 2), (-2, 1, 2), (0, 2, 2), (0, 1, 3), (0, 1, 0)):
+        with pytest.raises(X.CdagError) as e:
+            c.set_tile("fp64", 0, 72, *bad)
+        assert e.value.code == B.E_INVALID
+    c.set_tile("fp64", 0, 72, -1)          # back to the default choice
+    t, g, st = c.get_tile("fp64", 0, 72)
+    assert t in X.TILES and (g, st) == (1, 2)
+
+
 def test_errors_leave_context_usable():
     c = X.Context()
     with pytest.raises(X.CdagError) as e:
