@@ -56,7 +56,7 @@ def timed_steps(ctx, runner, prec, batched, steps, warmup):
     return dt, st
 
 
-def measured_traffic(tile):
+def measured_traffic(variant):
     """HBM bytes per launch of the exterior-contraction kernel from the committed
     counter summary, or None when the kernel source or variant differs from the
     one the counters were taken on."""
@@ -66,7 +66,7 @@ def measured_traffic(tile):
     with open(path) as f:
         rec = json.load(f)
     from paper_2511_02257_amd.profiling import kernel_source_sha256
-    if rec.get("kernel_sha256") != kernel_source_sha256() or rec.get("tile") != tile:
+    if rec.get("kernel_sha256") != kernel_source_sha256() or rec.get("variant") != variant:
         return None
     return rec.get("traffic_bytes_per_launch")
 

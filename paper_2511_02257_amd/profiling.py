@@ -5,7 +5,7 @@ then WRITE_SIZE, in KiB per dispatch), each scaled by what the same counter
 reads for a plain device copy of known size.
 
     python -m paper_2511_02257_amd.profiling traffic \\
-        --kernel 'hec_mfma<double' --tile 5 \\
+        --kernel 'hec_mfma<double' --variant 15 \\
         --fetch gpurun_out/pmc_fetch/fetch_counter_collection.csv \\
         --write gpurun_out/pmc_write/write_counter_collection.csv \\
         --copy-fetch gpurun_out/pmc_copy_fetch/cf_counter_collection.csv \\
@@ -52,7 +52,7 @@ def traffic(args):
     kw = kib / (sum(cw) / len(cw))
     per_launch = (sum(fetch) * kf + sum(write) * kw) * 1024.0 / len(fetch)
     rec = {
-        "kernel": args.kernel, "tile": args.tile, "dispatches": len(fetch),
+        "kernel": args.kernel, "variant": args.variant, "dispatches": len(fetch),
         "fetch_scale": round(kf, 5), "write_scale": round(kw, 5),
         "fetch_bytes_per_launch": sum(fetch) * kf * 1024.0 / len(fetch),
         "write_bytes_per_launch": sum(write) * kw * 1024.0 / len(write),
@@ -70,7 +70,7 @@ def main():
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--kernel", required=True)
-    t.add_argument("--tile", type=int, required=True, help="kernel variant index (binding.variant_index)")
+    t.add_argument("--variant", type=int, required=True, help="kernel variant index (binding.variant_index)")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
     t.add_argument("--copy-fetch", required=True)
