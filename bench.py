@@ -71,6 +71,86 @@ def measured_traffic(variant):
     return rec.get("traffic_bytes_per_launch")
 
 
+KIND_NAMES = {0: "K22", 1: "K32", 2: "K33", 3: "HCA"}
+
+
+def kernel_table(records, prec):
+    """Launch records of one timed execute, summed per (launch type, kinds):
+    time, algorithmic flops and bytes, and the rates against the MI355X peaks.
+    A split-K contraction kind also gets an entry that charges its reduction
+    kernels to it ("hec+reduce")."""
+    agg = {}
+    for r in records:
+        key = r["type"] if r["type"] == "xsum" else r["type"] + ":" + "+".join(KIND_NAMES[k] for k in r["kinds"])
+        a = agg.setdefault(key, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
+        a["launches"] += 1
+        a["ms"] += r["ms"]
+        a["flops"] += r["flops"]
+        a["bytes"] += r["bytes"]
+    for key in [k for k in agg if k.startswith("reduce:")]:
+        hk = "hec:" + key.split(":", 1)[1]
+        if hk in agg:
+            agg["hec+reduce:" + key.split(":", 1)[1]] = {
+                "launches": agg[hk]["launches"] + agg[key]["launches"],
+                "ms": agg[hk]["ms"] + agg[key]["ms"], "flops": agg[hk]["flops"],
+                "bytes": agg[hk]["bytes"]}
+    for key, a in agg.items():
+        sec = a["ms"] * 1e-3
+        if sec <= 0:
+            continue
+        a["TFLOP/s"] = round(a["flops"] / sec / 1e12, 3)
+        a["GB/s"] = round(a["bytes"] / sec / 1e9, 1)
+        if key.startswith("hec"):
+            a["frac_mfma"] = round(a["flops"] / sec / 1e12 / PEAK[prec], 4)
+        if not key.startswith("reduce"):
+            a["frac_hbm"] = round(a["bytes"] / sec / 1e9 / HBM_PEAK, 4)
+        a["ms"] = round(a["ms"], 4)
+    return agg
+
+
+def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True):
+    """One config at its full size, Tree schedule, waves of every ready
+    contraction, leaves resident, graph replay: autotuned variants, time per
+    execute, and per-kernel rates from a timed execute."""
+    import torch
+    wl = W.config(name)
+    log(f"{name}: workload built")
+    shapes = set()
+    for g in wl.graphs:
+        n = next(wl.leaves[o].nvec for op in g.ops for o in op[1:] if o >= 0)
+        shapes.update((kind, n) for kind, _, _ in g.ops if kind != 3)
+    shapes = sorted(shapes)
+    ctx = X.Context()
+    ctx.build_cdag(wl.leaves, wl.graphs)
+    del wl
+    ctx.schedule("tree")
+    ctx.set_mem_budget(None)
+    ctx.set_options(leaves_resident=True, wave_lookahead=X.binding.LOOKAHEAD_ALL, use_graphs=True)
+    runner = DeviceRunner(ctx, 0)
+    res = {}
+    for prec in precs:
+        runner.autotune(prec, True, reps=1, in_situ=in_situ)
+        dt, st = timed_steps(ctx, runner, prec, True, steps, 1)
+        p = st["plan"]
+        ctx.set_timing(True)
+        runner.run(prec, True)
+        recs = ctx.launch_records()
+        ctx.set_timing(False)
+        res[prec] = {
+            "tflops": round(p["flops"] * steps / dt / 1e12, 3),
+            "ms_per_step": round(dt / steps * 1e3, 3), "n_waves": p["n_steps"],
+            "n_contractions": p["n_contr"], "flops_per_step": p["flops"],
+            "arena_GB": round(p["arena_bytes"] / 1e9, 2),
+            "variants": {f"{KIND_NAMES[k]}_N{n}": list(ctx.get_tile(prec, k, n)) for k, n in shapes},
+            "kernels": kernel_table(recs, prec)}
+        log(name, prec, res[prec])
+    ctx.close()
+    runner.arena = None
+    del runner
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(wl, seconds=12.0):
     """The oracle (numpy complex128, each graph on its own) on a bounded sample."""
     from oracle import values as OV
@@ -107,6 +187,10 @@ def main():
     ap.add_argument("--fp64-variant", default=None, metavar="TILE,GRID,STAGES",
                     help="fix the FP64 K22 kernel variant instead of autotuning it "
                          "(so that counter runs profile the variant a timed run chose)")
+    ap.add_argument("--workload", default="meson_ring",
+                    choices=("meson_ring", "baryon_mix", "batched"),
+                    help="meson_ring: the headline line (default). baryon_mix, batched: that config "
+                         "alone at full size, resident, with per-kernel rates (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -129,6 +213,21 @@ def main():
     from synth import workloads as W
     import paper_2511_02257_amd as X
     from paper_2511_02257_amd.device import DeviceRunner
+
+    if args.workload != "meson_ring":
+        precs = ("fp64", "fp32", "bf16x3") if args.workload == "baryon_mix" else ("fp32", "bf16x3")
+        res = workload_rooflines(args.workload, precs, args.steps, X, W, DeviceRunner,
+                                 in_situ=args.workload == "baryon_mix")
+        head = res[precs[0]]
+        print(json.dumps({
+            "metric": METRIC, "value": head["tflops"], "unit": "complex TFLOP/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": head["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if precs[0] == "fp64" else "c64 storage, f32 accumulate",
+            "data": "synthetic",
+            "config": {"workload": args.workload + " (full size, leaves resident, no budget)"},
+            "per_precision": res}), flush=True)
+        return
 
     wl = W.config("meson_ring")
     log("workload built")
@@ -185,6 +284,7 @@ def main():
         hec_f += s2["hec_flops"]
         hec_b += s2["hec_bytes"]
         hec_n += s2["n_hec_launches"]
+    kernels = kernel_table(ctx.launch_records(), "fp64")
     ctx.set_timing(False)
     achieved = hec_f / hec_t / 1e12
     t64, g64, st64 = ctx.get_tile("fp64", 0, 64)
@@ -198,7 +298,8 @@ def main():
                        "avg_launch_us": round(hec_t / hec_n * 1e6, 3),
                        "flops_per_launch": hec_f / hec_n,
                        "alg_bytes_per_launch": hec_b / hec_n,
-                       "achieved_GBps": round(hec_b / hec_t / 1e9, 1)}
+                       "achieved_GBps": round(hec_b / hec_t / 1e9, 1),
+                       "all_kernels_last_execute": kernels}
     log("roofline", out["roofline"])
 
     if not args.skip_extras:
@@ -238,6 +339,9 @@ def main():
                 log(key, budgeted[key])
         extras["budgeted"] = budgeted
         ctx.set_mem_budget(None)
+        # the baryon configuration (FP64) and its precision form, per-kernel rates
+        extras["baryon_mix"] = workload_rooflines("baryon_mix", ("fp64", "fp32", "bf16x3"),
+                                                  max(3, args.steps // 10), X, W, DeviceRunner)
         out["extras"] = extras
 
     out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

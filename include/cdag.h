@@ -127,6 +127,22 @@ typedef struct {
   int64_t n_graph_segments;
 } cdag_exec_stats;
 
+/* One kernel launch of a timed execute (cdag_set_timing(c, 1)). */
+enum cdag_launch_type { CDAG_LAUNCH_HEC = 0, CDAG_LAUNCH_REDUCE = 1, CDAG_LAUNCH_HCA = 2,
+                        CDAG_LAUNCH_XSUM = 3 };
+typedef struct {
+  int32_t type;       /* cdag_launch_type                                                */
+  int32_t variant;    /* HEC: kernel variant index; else 0                              */
+  int32_t kinds;      /* bit k set when a contraction of cdag_kind k is in the launch  */
+  int32_t reserved;
+  int64_t step;       /* plan step (wave); -1 for the cross-diagram sum                */
+  int64_t n_items;    /* workgroup work items                                            */
+  double flops;       /* algorithmic flops (8 per complex multiply-add)                 */
+  double bytes;       /* HEC, HCA: algorithmic bytes (operands read once, output written
+                         once); REDUCE: split-K workspace read + output write; XSUM: 0  */
+  double ms;          /* duration between HIP events on the compute stream              */
+} cdag_launch_record;
+
 int cdag_create(cdag_ctx** out);
 int cdag_destroy(cdag_ctx* c);
 const char* cdag_last_error(void);
@@ -160,10 +176,14 @@ int set_mem_budget(cdag_ctx* c, uint64_t bytes);
 int cdag_set_options(cdag_ctx* c, int leaves_resident, int wave_max, int64_t wave_lookahead,
                      int use_graphs);
 
-/* timing: 1 records a HIP event pair around every exterior-contraction launch
- * on the compute stream and reports their summed duration in t_hec_s
- * (execution then runs without graph replay); 0 (default) turns it off. */
+/* timing: 1 records a HIP event pair around every kernel launch on the
+ * compute stream, reports the summed exterior-contraction durations in t_hec_s
+ * and keeps per-launch records (execution then runs without graph replay);
+ * 0 (default) turns it off. */
 int cdag_set_timing(cdag_ctx* c, int timing);
+/* Per-launch records of the last execute made with timing on, in launch order.
+ * *n_out (nullable) receives the count; at most cap records are written. */
+int cdag_launch_records(cdag_ctx* c, cdag_launch_record* out, int64_t cap, int64_t* n_out);
 
 /* Kernel variant of the exterior contractions of `kind` (K22, K32 or K33)
  * with N = nvec in precision `prec`.  tile: 0 = 64x64, 1 = 32x32, 2 = 48x48,

@@ -61,6 +61,14 @@ class cdag_exec_stats(C.Structure):
                 ("n_graph_segments", C.c_int64)]
 
 
+class cdag_launch_record(C.Structure):
+    _fields_ = [("type", C.c_int32), ("variant", C.c_int32), ("kinds", C.c_int32),
+                ("reserved", C.c_int32), ("step", C.c_int64), ("n_items", C.c_int64),
+                ("flops", C.c_double), ("bytes", C.c_double), ("ms", C.c_double)]
+
+
+LAUNCH_TYPES = {0: "hec", 1: "reduce", 2: "hca", 3: "xsum"}
+
 _lib = None
 
 
@@ -90,6 +98,7 @@ def lib():
             "set_mem_budget": [P, C.c_uint64],
             "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
             "cdag_set_timing": [P, C.c_int],
+            "cdag_launch_records": [P, C.POINTER(cdag_launch_record), I64, C.POINTER(I64)],
             "cdag_set_tile": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int],
             "cdag_get_tile": [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                               C.POINTER(C.c_int)],
@@ -116,7 +125,7 @@ def lib():
 
 
 EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "schedule",
-            "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_set_tile", "cdag_get_tile", "cdag_memsim", "cdag_plan", "cdag_plan_ops",
+            "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_launch_records", "cdag_set_tile", "cdag_get_tile", "cdag_memsim", "cdag_plan", "cdag_plan_ops",
             "cdag_get_nodes", "cdag_graph_roots", "cdag_bind_device", "cdag_bind_arena",
             "execute", "cdag_autotune", "fetch_correlators", "cdag_fetch_sums")
 
@@ -203,6 +212,20 @@ def cdag_set_options(h, leaves_resident=False, wave_max=4096, wave_lookahead=0,
 
 def cdag_set_timing(h, on: bool) -> None:
     _check(lib().cdag_set_timing(h, int(bool(on))))
+
+
+def cdag_launch_records(h):
+    """Per-launch records of the last timed execute, as a list of dicts."""
+    n = C.c_int64()
+    _check(lib().cdag_launch_records(h, None, 0, C.byref(n)))
+    buf = (cdag_launch_record * max(1, n.value))()
+    _check(lib().cdag_launch_records(h, buf, n.value, C.byref(n)))
+    out = []
+    for r in buf[:n.value]:
+        out.append({"type": LAUNCH_TYPES[r.type], "variant": r.variant,
+                    "kinds": [k for k in range(4) if r.kinds >> k & 1], "step": r.step,
+                    "n_items": r.n_items, "flops": r.flops, "bytes": r.bytes, "ms": r.ms})
+    return out
 
 
 TILES = {0: (64, 64), 1: (32, 32), 2: (48, 48), 3: (128, 64), 4: (64, 32)}
@@ -362,6 +385,9 @@ class Context:
 
     def set_timing(self, on=True):
         cdag_set_timing(self.h, on)
+
+    def launch_records(self):
+        return cdag_launch_records(self.h)
 
     def set_tile(self, prec, kind, nvec, tile, grid=1, lds_stages=2):
         cdag_set_tile(self.h, prec, kind, nvec, tile, grid, lds_stages)

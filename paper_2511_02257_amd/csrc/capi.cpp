@@ -208,6 +208,17 @@ int cdag_set_timing(cdag_ctx* h, int timing) {
   return guard([&] { h->c.timing = timing != 0; });
 }
 
+int cdag_launch_records(cdag_ctx* h, cdag_launch_record* out, int64_t cap, int64_t* n_out) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    need(cap >= 0 && (cap == 0 || out != nullptr), CDAG_E_INVALID, "out is NULL");
+    const auto& r = h->c.records;
+    const int64_t n = std::min<int64_t>(cap, (int64_t)r.size());
+    for (int64_t i = 0; i < n; ++i) out[i] = r[i];
+    if (n_out) *n_out = (int64_t)r.size();
+  });
+}
+
 int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile, int grid, int lds_stages) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {

@@ -49,6 +49,7 @@ struct Ctx {
   // results of the last execute
   bool have_results = false;
   std::vector<double> corr_host, sums_host;   // corr buffer (per tree), sums buffer
+  std::vector<cdag_launch_record> records;    // per launch of the last timed execute
 };
 
 // Plans for (prec, batched) unless the cached plan already matches.

@@ -123,6 +123,10 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
     kp.launch_off.push_back((int64_t)kp.launches.size());
     std::vector<HecDesc> hec[kNumVariants];
     int64_t tiles[kNumVariants] = {0};
+    double v_flops[kNumVariants] = {0}, v_bytes[kNumVariants] = {0};
+    int32_t v_kinds[kNumVariants] = {0};
+    double red_bytes = 0, hca_flops = 0, hca_bytes = 0;
+    int32_t red_kinds = 0;
     std::vector<RedDesc> red;
     std::vector<HcaDesc> hca;
     int64_t ws = kp.ws_off, items = 0;
@@ -139,14 +143,20 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
         h.n = d.nvec[u];
         h.nt = d.nt[u];
         hca.push_back(h);
+        hca_flops += d.flops(u);
+        hca_bytes += 2.0 * h.nt * (double)h.n * h.n * (double)elem_bytes_of(prec);
         continue;
       }
       HecDesc h{};
       decomp(u, h);
       const int tl = tile_of(u);
+      const double ab = (double)h.nt * ((double)h.M * h.K + (double)h.K * h.N + (double)h.M * h.N) *
+                        (double)elem_bytes_of(prec);
       kp.hec_flops += d.flops(u);
-      kp.hec_bytes += (double)h.nt * ((double)h.M * h.K + (double)h.K * h.N + (double)h.M * h.N) *
-                      (double)elem_bytes_of(prec);
+      kp.hec_bytes += ab;
+      v_flops[tl] += d.flops(u);
+      v_bytes[tl] += ab;
+      v_kinds[tl] |= 1 << d.kind[u];
       h.a_off = r.a_off;
       h.b_off = r.b_off;
       h.c_off = r.dev_off;
@@ -165,6 +175,8 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
         rd.item_begin = (int32_t)items;
         items += (2LL * rd.nt * rd.mn + 255) / 256;
         red.push_back(rd);
+        red_bytes += 2.0 * rd.nt * (double)rd.mn * ((double)rd.splits * acc_bytes + elem_bytes_of(prec));
+        red_kinds |= 1 << d.kind[u];
         ws += align256((int64_t)h.splits * h.nt * 2 * h.M * h.N * acc_bytes);
       }
       hec[tl].push_back(h);
@@ -172,18 +184,26 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
     for (int tl = 0; tl < kNumVariants; ++tl) {
       if (hec[tl].empty()) continue;
       Launch L{L_HEC, tl, (int32_t)hec[tl].size(), 0, tiles[tl], 0};
+      L.flops = v_flops[tl];
+      L.bytes = v_bytes[tl];
+      L.kinds = v_kinds[tl];
       L.host_desc = (int64_t)kp.blob.size();
       for (auto& h : hec[tl]) put(kp.blob, h);
       kp.launches.push_back(L);
     }
     if (!red.empty()) {
       Launch L{L_RED, 0, (int32_t)red.size(), 0, items, 0};
+      L.bytes = red_bytes;
+      L.kinds = red_kinds;
       L.host_desc = (int64_t)kp.blob.size();
       for (auto& x : red) put(kp.blob, x);
       kp.launches.push_back(L);
     }
     if (!hca.empty()) {
       Launch L{L_HCA, 0, (int32_t)hca.size(), 0, 0, 0};
+      L.flops = hca_flops;
+      L.bytes = hca_bytes;
+      L.kinds = 1 << HCA;
       for (auto& h : hca) { h.item_begin = (int32_t)L.n_items; L.n_items += h.nt; }
       L.host_desc = (int64_t)kp.blob.size();
       for (auto& h : hca) put(kp.blob, h);

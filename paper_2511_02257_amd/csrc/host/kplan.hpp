@@ -21,6 +21,9 @@ struct Launch {
   int64_t desc_off;   // arena offset of the first descriptor
   int64_t n_items;    // HEC: tiles; RED: 256-element blocks; HCA: (root, t) pairs; XSUM: correlators
   int64_t host_desc;  // byte offset of the first descriptor in KernelPlan::blob
+  double flops = 0;   // algorithmic flops of the launch (HEC, HCA)
+  double bytes = 0;   // HEC, HCA: algorithmic bytes; RED: workspace read + output write
+  int32_t kinds = 0;  // bit k set when a contraction of kind k is in the launch
 };
 
 // Kernel variant of an exterior contraction: a tile shape (index into

@@ -18,6 +18,7 @@
 #include <map>
 #include <string>
 #include <thread>
+#include <tuple>
 
 #include "../ctx.hpp"
 #include "../kernels/kernels.hpp"
@@ -74,7 +75,7 @@ struct Device {
   // timing mode: event pairs around exterior-contraction launches
   std::vector<hipEvent_t> tpool;
   size_t tnext = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> tpairs;
+  std::vector<std::tuple<int64_t, hipEvent_t, hipEvent_t>> tpairs;   // launch index (-1: xsum)
 
   hipEvent_t timing_event() {
     if (tnext == tpool.size()) {
@@ -200,25 +201,28 @@ void ensure_pinned(void*& p, int64_t& have, int64_t need_bytes) {
   have = need_bytes;
 }
 
+hipError_t launch_one(const Launch& L, int prec, char* arena, hipStream_t st) {
+  switch (L.type) {
+    case L_HEC: return launch_hec(prec, L.tile, arena, L.desc_off, L.n_desc, L.n_items, st);
+    case L_RED: return launch_reduce(prec, arena, L.desc_off, L.n_desc, L.n_items, st);
+    case L_HCA: return launch_hca(prec, arena, L.desc_off, L.n_desc, L.n_items, st);
+    default: throw Error(CDAG_E_STATE, "bad launch type");
+  }
+}
+
+// Kernels of step s; with `timed`, every launch is bracketed by an event pair.
 int64_t launch_step(const KernelPlan& kp, int64_t s, int prec, char* arena, hipStream_t st, Device* timed) {
   int64_t n = 0;
   for (int64_t li = kp.launch_off[s]; li < kp.launch_off[s + 1]; ++li) {
     const Launch& L = kp.launches[li];
-    switch (L.type) {
-      case L_HEC:
-        if (timed) {
-          hipEvent_t a = timed->timing_event(), b = timed->timing_event();
-          HIPC(hipEventRecord(a, st));
-          HIPC(launch_hec(prec, L.tile, arena, L.desc_off, L.n_desc, L.n_items, st));
-          HIPC(hipEventRecord(b, st));
-          timed->tpairs.push_back({a, b});
-        } else {
-          HIPC(launch_hec(prec, L.tile, arena, L.desc_off, L.n_desc, L.n_items, st));
-        }
-        break;
-      case L_RED: HIPC(launch_reduce(prec, arena, L.desc_off, L.n_desc, L.n_items, st)); break;
-      case L_HCA: HIPC(launch_hca(prec, arena, L.desc_off, L.n_desc, L.n_items, st)); break;
-      default: throw Error(CDAG_E_STATE, "bad launch type");
+    if (timed) {
+      hipEvent_t a = timed->timing_event(), b = timed->timing_event();
+      HIPC(hipEventRecord(a, st));
+      HIPC(launch_one(L, prec, arena, st));
+      HIPC(hipEventRecord(b, st));
+      timed->tpairs.push_back({li, a, b});
+    } else {
+      HIPC(launch_one(L, prec, arena, st));
     }
     ++n;
   }
@@ -364,8 +368,9 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
 
 // In-situ autotuner: for every distinct (kind, N) in turn, run the planned DAG
 // `reps` times with each kernel variant for that shape (the other shapes keep
-// their current choice), with HIP events around every exterior-contraction
-// launch, and keep the variant with the least summed launch time.
+// their current choice), with HIP events around every launch, and keep the
+// variant with the least summed time of exterior contractions plus split-K
+// reductions.
 int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
   std::map<std::pair<int, int>, int> shapes;
   for (int64_t u = c.dag.n_leaves; u < c.dag.n_nodes(); ++u)
@@ -387,7 +392,8 @@ int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
         for (int r = 0; r < reps; ++r) {
           cdag_exec_stats st{};
           device_execute(c, prec, batched, &st);
-          t += st.t_hec_s;
+          for (const cdag_launch_record& rec : c.records)
+            if (rec.type == CDAG_LAUNCH_HEC || rec.type == CDAG_LAUNCH_REDUCE) t += rec.ms;
         }
         if (t < best) { best = t; best_v = v; }
       }
@@ -490,7 +496,15 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   } else {
     n_launch += issue_steps(c, D, prec, 0, S, D.comp, D.copy, timed, false);
   }
-  HIPC(launch_xsum(D.arena, kp.xsum.desc_off, kp.xsum_entries_off, kp.xsum.n_desc, D.comp));
+  if (timed) {
+    hipEvent_t a = D.timing_event(), b = D.timing_event();
+    HIPC(hipEventRecord(a, D.comp));
+    HIPC(launch_xsum(D.arena, kp.xsum.desc_off, kp.xsum_entries_off, kp.xsum.n_desc, D.comp));
+    HIPC(hipEventRecord(b, D.comp));
+    D.tpairs.push_back({-1, a, b});
+  } else {
+    HIPC(launch_xsum(D.arena, kp.xsum.desc_off, kp.xsum_entries_off, kp.xsum.n_desc, D.comp));
+  }
   n_launch++;
   HIPC(hipEventRecord(D.t1, D.comp));
   HIPC(hipMemcpyAsync(D.results, D.arena + kp.corr_off, (size_t)(kp.corr_bytes + kp.sums_bytes),
@@ -503,10 +517,29 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   c.sums_host.assign((const double*)((const char*)D.results + kp.corr_bytes),
                      (const double*)((const char*)D.results + kp.corr_bytes) + kp.sums_bytes / 8);
   double t_hec = 0;
-  for (auto& pr : D.tpairs) {
-    float x = 0;
-    HIPC(hipEventElapsedTime(&x, pr.first, pr.second));
-    t_hec += x * 1e-3;
+  if (timed) {
+    // launch index -> plan step
+    std::vector<int64_t> step_of(kp.launches.size(), -1);
+    for (int64_t s = 0; s < S; ++s)
+      for (int64_t li = kp.launch_off[s]; li < kp.launch_off[s + 1]; ++li) step_of[li] = s;
+    c.records.clear();
+    for (auto& pr : D.tpairs) {
+      float x = 0;
+      HIPC(hipEventElapsedTime(&x, std::get<1>(pr), std::get<2>(pr)));
+      const int64_t li = std::get<0>(pr);
+      const Launch& L = li >= 0 ? kp.launches[li] : kp.xsum;
+      cdag_launch_record r{};
+      r.type = L.type;
+      r.variant = L.type == L_HEC ? L.tile : 0;
+      r.kinds = L.kinds;
+      r.step = li >= 0 ? step_of[li] : -1;
+      r.n_items = L.n_items;
+      r.flops = L.flops;
+      r.bytes = L.bytes;
+      r.ms = x;
+      c.records.push_back(r);
+      if (L.type == L_HEC) t_hec += x * 1e-3;
+    }
   }
   int64_t n_hec = 0;
   for (const Launch& L : kp.launches) n_hec += L.type == L_HEC;

@@ -132,6 +132,39 @@ def test_autotune_then_parity(baryon_small, in_situ):
         assert rel_errors(r["corr"], ref).max() <= TOL[prec]
 
 
+def test_timed_execute_records_every_launch(baryon_small):
+    """Timing mode: one record per kernel launch, carrying the plan's flops and
+    bytes, in step order with the cross sum last; results unchanged."""
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd.device import DeviceRunner
+    wl, ref = baryon_small
+    ctx = X.Context()
+    ctx.build_cdag(wl.leaves, wl.graphs)
+    ctx.schedule("tree")
+    ctx.set_options(wave_lookahead=X.binding.LOOKAHEAD_ALL)
+    runner = DeviceRunner(ctx, 0)
+    ctx.set_timing(True)
+    st = runner.run("fp64", True)
+    recs = ctx.launch_records()
+    corr = ctx.fetch_correlators()
+    ctx.close()
+    assert len(recs) == st["n_launches"]
+    hec = [r for r in recs if r["type"] == "hec"]
+    assert len(hec) == st["n_hec_launches"]
+    assert sum(r["flops"] for r in hec) == st["hec_flops"]
+    assert sum(r["bytes"] for r in hec) == st["hec_bytes"]
+    hca = [r for r in recs if r["type"] == "hca"]
+    assert sum(r["flops"] for r in hec + hca) == st["plan"]["flops"]
+    assert sum(r["n_items"] for r in hca) == 3 * st["plan"]["n_roots"]     # (root, t) pairs
+    assert any(r["type"] == "reduce" and r["kinds"] == [2] for r in recs)   # K33 split-K
+    assert recs[-1]["type"] == "xsum" and recs[-1]["step"] == -1
+    steps = [r["step"] for r in recs[:-1]]
+    assert steps == sorted(steps)
+    assert all(r["ms"] > 0 for r in recs)
+    assert abs(sum(r["ms"] for r in hec) * 1e-3 - st["t_hec_s"]) <= 1e-9 * max(1, len(hec))
+    assert rel_errors(corr, ref).max() <= TOL["fp64"]
+
+
 def test_resident_leaves_and_graph_replay(baryon_small):
     wl, ref = baryon_small
     a = run(wl, "tree", "fp64", True, leaves_resident=True, use_graphs=True)

@@ -194,6 +194,15 @@ def test_kernel_variants_round_trip_and_share_decomposition():
     assert t in X.TILES and (g, st) == (1, 2)
 
 
+def test_launch_records_empty_without_a_timed_execute():
+    wl = W.fig1_dag("fgh", with_data=False)
+    c = ctx_for(wl)
+    assert c.launch_records() == []
+    with pytest.raises(X.CdagError) as e:
+        B._check(B.lib().cdag_launch_records(c.h, None, 4, None))
+    assert e.value.code == B.E_INVALID
+
+
 def test_errors_leave_context_usable():
     c = X.Context()
     with pytest.raises(X.CdagError) as e:
