@@ -108,7 +108,7 @@ def kernel_table(records, prec):
     return agg
 
 
-def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True):
+def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True, fixed=None):
     """One config at its full size, Tree schedule, waves of every ready
     contraction, leaves resident, graph replay: autotuned variants, time per
     execute, and per-kernel rates from a timed execute."""
@@ -128,8 +128,15 @@ def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True):
     ctx.set_options(leaves_resident=True, wave_lookahead=X.binding.LOOKAHEAD_ALL, use_graphs=True)
     runner = DeviceRunner(ctx, 0)
     res = {}
+    inv = {v: k for k, v in KIND_NAMES.items()}
     for prec in precs:
-        runner.autotune(prec, True, reps=1, in_situ=in_situ)
+        if fixed and prec in fixed:
+            for key, choice in fixed[prec].items():
+                kname, n = key.split("_N")
+                ctx.set_tile(prec, inv[kname], int(n), *choice)
+            runner.ensure_arena(ctx.plan(prec, True)["arena_bytes"])
+        else:
+            runner.autotune(prec, True, reps=1, in_situ=in_situ)
         dt, st = timed_steps(ctx, runner, prec, True, steps, 1)
         p = st["plan"]
         ctx.set_timing(True)
@@ -191,6 +198,9 @@ def main():
                     choices=("meson_ring", "baryon_mix", "batched"),
                     help="meson_ring: the headline line (default). baryon_mix, batched: that config "
                          "alone at full size, resident, with per-kernel rates (for profiling)")
+    ap.add_argument("--variants-from", default=None, metavar="JSON",
+                    help="with --workload baryon_mix or batched: take the kernel choices from the "
+                         "JSON line of an earlier run of the same workload instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -216,8 +226,13 @@ def main():
 
     if args.workload != "meson_ring":
         precs = ("fp64", "fp32", "bf16x3") if args.workload == "baryon_mix" else ("fp32", "bf16x3")
+        fixed = None
+        if args.variants_from:
+            with open(args.variants_from) as f:
+                prev = json.loads(f.read().strip().splitlines()[-1])
+            fixed = {p: r["variants"] for p, r in prev["per_precision"].items()}
         res = workload_rooflines(args.workload, precs, args.steps, X, W, DeviceRunner,
-                                 in_situ=args.workload == "baryon_mix")
+                                 in_situ=args.workload == "baryon_mix", fixed=fixed)
         head = res[precs[0]]
         print(json.dumps({
             "metric": METRIC, "value": head["tflops"], "unit": "complex TFLOP/s", "n_gpus": 1,
@@ -251,7 +266,7 @@ def main():
             runner.ensure_arena(ctx.plan("fp64", True)["arena_bytes"])
         elif prec == "fp64" or not args.skip_extras:
             runner.autotune(prec, True, reps=2, in_situ=True)
-        t, g, st = ctx.get_tile(prec, 0, 64)
+        t, g, st, _ = ctx.get_tile(prec, 0, 64)
         tiles[prec] = {"K22_N64": {"tile": list(X.TILES[t]), "grid": X.binding.GRIDS[g],
                                    "lds_stages": st}}
     log("autotuned tiles", tiles)
@@ -287,7 +302,7 @@ def main():
     kernels = kernel_table(ctx.launch_records(), "fp64")
     ctx.set_timing(False)
     achieved = hec_f / hec_t / 1e12
-    t64, g64, st64 = ctx.get_tile("fp64", 0, 64)
+    t64, g64, st64, _ = ctx.get_tile("fp64", 0, 64)
     variant = X.binding.variant_index(t64, g64, st64)
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
                        "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4),

@@ -192,11 +192,17 @@ int cdag_launch_records(cdag_ctx* c, cdag_launch_record* out, int64_t cap, int64
  * workgroups striding over the work list), 1 = one workgroup per work item.
  * lds_stages: 2 = double-buffered operand tiles in LDS, 1 = a single buffer
  * refilled from registers (half the LDS, more workgroups per compute unit).
- * Without an explicit choice a default by N applies (cdag_get_tile reports
- * the choice in force).  Every variant gives results within the precision's
- * bound; bits may differ between tile shapes. */
-int cdag_set_tile(cdag_ctx* c, int prec, int kind, int nvec, int tile, int grid, int lds_stages);
-int cdag_get_tile(cdag_ctx* c, int prec, int kind, int nvec, int* tile, int* grid, int* lds_stages);
+ * split_k: 1 = a contraction with fewer than 512 output tiles and K >= 512 is
+ * cut into K splits summed by a fixed-order reduction; 0 = never split (one
+ * work item per output tile, the whole K in one accumulator).
+ * Without an explicit choice a default by N applies (split_k 1;
+ * cdag_get_tile reports the choice in force).  Every choice gives results
+ * within the precision's bound; bits may differ between choices, never with
+ * the grouping of contractions into launches. */
+int cdag_set_tile(cdag_ctx* c, int prec, int kind, int nvec, int tile, int grid, int lds_stages,
+                  int split_k);
+int cdag_get_tile(cdag_ctx* c, int prec, int kind, int nvec, int* tile, int* grid, int* lds_stages,
+                  int* split_k);
 
 /* Host-only: simulate Sec. II-C for `order` (n node ids, each contraction
  * once, topological) with element size elem_bytes (16 or 8).  M_out
@@ -235,10 +241,11 @@ int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
  * (kind, N) among the exterior contractions of the DAG.  mode 0 (synthetic):
  * time each variant `reps` times on one contraction of that shape placed in
  * the bound arena's tensor pool (as planned for (prec, batched); its contents
- * are scratch between executes) and keep the fastest per time slice.  mode 1
- * (in situ): execute the planned DAG `reps` times per variant, shape by
- * shape, with launch timing on, and keep the least summed exterior-contraction
- * time (needs leaf data; costs 20 * reps executes per shape).  *n_tuned
+ * are scratch between executes) and keep the fastest per time slice (split_k
+ * stays 1).  mode 1 (in situ): execute the planned DAG `reps` times per
+ * variant and split_k setting, shape by shape, with launch timing on, and keep
+ * the least summed time of exterior contractions and split-K reductions
+ * (needs leaf data; costs up to 40 * reps executes per shape).  *n_tuned
  * (nullable) receives the number of shapes tuned.  Needs cdag_bind_device and
  * an arena of at least the plan's arena_bytes; invalidates the current plan
  * and results. */

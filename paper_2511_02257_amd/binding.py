@@ -99,9 +99,9 @@ def lib():
             "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
             "cdag_set_timing": [P, C.c_int],
             "cdag_launch_records": [P, C.POINTER(cdag_launch_record), I64, C.POINTER(I64)],
-            "cdag_set_tile": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int],
+            "cdag_set_tile": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int],
             "cdag_get_tile": [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                              C.POINTER(C.c_int)],
+                              C.POINTER(C.c_int), C.POINTER(C.c_int)],
             "cdag_memsim": [P, C.POINTER(I64), I64, C.c_int, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
             "cdag_plan": [P, C.c_int, C.c_int, C.POINTER(cdag_plan_stats)],
             "cdag_plan_ops": [P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64), I64, C.POINTER(I64)],
@@ -240,16 +240,17 @@ def variant_index(tile: int, grid: int, lds_stages: int) -> int:
 
 
 def cdag_set_tile(h, prec: str, kind: int, nvec: int, tile: int, grid: int = 1,
-                  lds_stages: int = 2) -> None:
+                  lds_stages: int = 2, split_k: int = 1) -> None:
     _check(lib().cdag_set_tile(h, PREC[prec], int(kind), int(nvec), int(tile), int(grid),
-                               int(lds_stages)))
+                               int(lds_stages), int(split_k)))
 
 
 def cdag_get_tile(h, prec: str, kind: int, nvec: int):
-    """(tile, grid, lds_stages) in force for that shape."""
-    t, g, st = C.c_int(), C.c_int(), C.c_int()
-    _check(lib().cdag_get_tile(h, PREC[prec], int(kind), int(nvec), C.byref(t), C.byref(g), C.byref(st)))
-    return t.value, g.value, st.value
+    """(tile, grid, lds_stages, split_k) in force for that shape."""
+    t, g, st, sk = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    _check(lib().cdag_get_tile(h, PREC[prec], int(kind), int(nvec), C.byref(t), C.byref(g), C.byref(st),
+                               C.byref(sk)))
+    return t.value, g.value, st.value, sk.value
 
 
 def cdag_memsim(h, order: Sequence[int], elem_bytes: int = 16):
@@ -389,8 +390,8 @@ class Context:
     def launch_records(self):
         return cdag_launch_records(self.h)
 
-    def set_tile(self, prec, kind, nvec, tile, grid=1, lds_stages=2):
-        cdag_set_tile(self.h, prec, kind, nvec, tile, grid, lds_stages)
+    def set_tile(self, prec, kind, nvec, tile, grid=1, lds_stages=2, split_k=1):
+        cdag_set_tile(self.h, prec, kind, nvec, tile, grid, lds_stages, split_k)
 
     def get_tile(self, prec, kind, nvec):
         return cdag_get_tile(self.h, prec, kind, nvec)

@@ -219,7 +219,7 @@ int cdag_launch_records(cdag_ctx* h, cdag_launch_record* out, int64_t cap, int64
   });
 }
 
-int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile, int grid, int lds_stages) {
+int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile, int grid, int lds_stages, int split_k) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {
     elem_bytes_prec(prec);
@@ -228,19 +228,27 @@ int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile, int grid,
     need(tile >= -1 && tile < cdag::kNumTiles, CDAG_E_INVALID, "tile out of range");
     need(grid >= 0 && grid < cdag::kNumGrids, CDAG_E_INVALID, "grid must be 0 or 1");
     need(lds_stages == 1 || lds_stages == 2, CDAG_E_INVALID, "lds_stages must be 1 or 2");
+    need(split_k == 0 || split_k == 1, CDAG_E_INVALID, "split_k must be 0 or 1");
     auto key = std::make_tuple(prec, kind, nvec);
-    if (tile < 0) h->c.tiles.erase(key); else h->c.tiles[key] = cdag::variant_of(tile, grid, lds_stages);
+    if (tile < 0)
+      h->c.tiles.erase(key);
+    else
+      h->c.tiles[key] = cdag::choice_of(cdag::variant_of(tile, grid, lds_stages), split_k != 0);
     h->c.version++;
   });
 }
 
-int cdag_get_tile(cdag_ctx* h, int prec, int kind, int nvec, int* tile, int* grid, int* lds_stages) {
+int cdag_get_tile(cdag_ctx* h, int prec, int kind, int nvec, int* tile, int* grid, int* lds_stages,
+                  int* split_k) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {
     elem_bytes_prec(prec);
-    need(tile != nullptr && grid != nullptr && lds_stages != nullptr, CDAG_E_INVALID, "NULL output");
+    need(tile != nullptr && grid != nullptr && lds_stages != nullptr && split_k != nullptr, CDAG_E_INVALID,
+         "NULL output");
     auto it = h->c.tiles.find(std::make_tuple(prec, kind, nvec));
-    const int v = it != h->c.tiles.end() ? it->second : cdag::default_tile(prec, kind, nvec);
+    const int ch = it != h->c.tiles.end() ? it->second : cdag::default_tile(prec, kind, nvec);
+    const int v = cdag::choice_variant(ch);
+    *split_k = cdag::choice_split_k(ch) ? 1 : 0;
     *tile = cdag::variant_tile(v);
     *grid = cdag::variant_grid(v);
     *lds_stages = cdag::variant_stages(v);

@@ -32,8 +32,9 @@ void gemm_dims(const Dag& d, int64_t u, int32_t* M, int32_t* N, int32_t* K) {
   }
 }
 
-void decompose(int kind, int n, int nt, int variant, int prec, HecDesc* h) {
-  if (variant < 0 || variant >= kNumVariants) throw std::invalid_argument("kernel variant out of range");
+void decompose(int kind, int n, int nt, int choice, int prec, HecDesc* h) {
+  if (choice < 0 || choice >= kNumChoices) throw std::invalid_argument("kernel choice out of range");
+  const int variant = choice_variant(choice);
   const int ks = k_step(prec);
   switch (kind) {
     case K22: h->M = n; h->N = n; h->K = n; break;
@@ -46,7 +47,7 @@ void decompose(int kind, int n, int nt, int variant, int prec, HecDesc* h) {
   h->tiles_n = (h->N + ts.bn - 1) / ts.bn;
   const int64_t base = (int64_t)h->nt * h->tiles_m * h->tiles_n;
   int64_t splits = std::min<int64_t>((kSplitTarget + base - 1) / base, h->K / kMinKSplit);
-  splits = std::max<int64_t>(splits, 1);
+  splits = choice_split_k(choice) ? std::max<int64_t>(splits, 1) : 1;
   int64_t kspl = (h->K + splits - 1) / splits;
   kspl = (kspl + ks - 1) / ks * ks;
   splits = (h->K + kspl - 1) / kspl;
@@ -62,7 +63,7 @@ int default_tile(int prec, int kind, int n) {
   if (n % 64 == 0) tile = 0;
   else if (n % 48 == 0) tile = 2;            // 48 x 48
   else if (n % 32 == 0 || n < 32) tile = 1;  // 32 x 32
-  return variant_of(tile, 1);
+  return choice_of(variant_of(tile, 1), true);
 }
 
 KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTable& tiles) {
@@ -149,7 +150,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
       }
       HecDesc h{};
       decomp(u, h);
-      const int tl = tile_of(u);
+      const int tl = choice_variant(tile_of(u));
       const double ab = (double)h.nt * ((double)h.M * h.K + (double)h.K * h.N + (double)h.M * h.N) *
                         (double)elem_bytes_of(prec);
       kp.hec_flops += d.flops(u);

@@ -38,13 +38,22 @@ inline int variant_of(int tile, int grid, int stages = 2) {
 inline int variant_tile(int v) { return v % kNumTiles; }
 inline int variant_grid(int v) { return (v / kNumTiles) % 2; }
 inline int variant_stages(int v) { return 2 - v / (2 * kNumTiles); }
-// Variant per (precision, kind, N): an explicit table entry (set through the
+// A kernel choice is a variant plus the split-K mode:
+// choice = variant + kNumVariants * (split-K allowed ? 0 : 1).  Split-K, when
+// allowed, follows the per-contraction rule of decompose(); either way the
+// split count depends only on the contraction and the choice, never on how
+// contractions are grouped into launches.
+constexpr int kNumChoices = 2 * kNumVariants;
+inline int choice_of(int variant, bool split_k) { return variant + kNumVariants * (split_k ? 0 : 1); }
+inline int choice_variant(int c) { return c % kNumVariants; }
+inline bool choice_split_k(int c) { return c < kNumVariants; }
+// Choice per (precision, kind, N): an explicit table entry (set through the
 // ABI or by the autotuner) wins, else default_tile().
 using TileTable = std::map<std::tuple<int, int, int>, int>;
-int default_tile(int prec, int kind, int n);   // returns a variant
+int default_tile(int prec, int kind, int n);   // returns a choice
 // GEMM dimensions, tile counts and split-K of one contraction of `kind` with
-// N = n, nt time slices and tile shape `tile` (offsets and tile_begin unset).
-void decompose(int kind, int n, int nt, int tile, int prec, HecDesc* h);
+// N = n, nt time slices and kernel `choice` (offsets and tile_begin unset).
+void decompose(int kind, int n, int nt, int choice, int prec, HecDesc* h);
 // k-step of the matrix-core kernels: FP64 and FP32 use 16, split-BF16 32.
 inline int k_step(int prec) { return prec == 2 ? 32 : 16; }
 // Split-K: aim for at least this many work items per contraction, keeping at

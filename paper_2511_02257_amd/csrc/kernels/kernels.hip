@@ -453,60 +453,83 @@ __global__ void __launch_bounds__(256) splitk_reduce(char* __restrict__ arena, c
 }
 
 // ------------------------------------------------------------------ root trace (FP64)
+// 4 consecutive elements of one row: vector loads when all 4 are in range and
+// the row is 4-element aligned, otherwise element-wise with zero fill.
+template <typename T>
+__device__ __forceinline__ void load4(T (&r)[4], const T* src, int valid, bool vec) {
+  if (vec && valid == 4) {
+    typedef typename Vec2<T>::V V;
+    constexpr int W = Vec2<T>::n;
+    const V* s = reinterpret_cast<const V*>(src);
+#pragma unroll
+    for (int q = 0; q < 4 / W; ++q) {
+      V v = s[q];
+      const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int x = 0; x < W; ++x) r[q * W + x] = e[x];
+    }
+  } else {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) r[x] = x < valid ? src[x] : T(0);
+  }
+}
+
+// C(t) = sum_ij P[i,j] Q[j,i]: one wave per (root, t), four per workgroup.
+// Lane l takes the 4 x 4 blocks b = l, l + 64, ... with block row ib = b / nb
+// and block column jb = b % nb (nb = ceil(N / 4)): it reads rows 4ib.. of P
+// over columns 4jb.. and rows 4jb.. of Q over columns 4ib.., so every load is
+// a row segment and the transpose happens in registers (no LDS, no barrier).
+// Products and sums in FP64 (exact products for FP32 inputs); each lane adds
+// its blocks in order and the 64 lane sums meet in a fixed butterfly, so the
+// result depends only on the data and N.
 template <typename T>
 __global__ void __launch_bounds__(256) hca_trace(char* __restrict__ arena, const HcaDesc* __restrict__ descs,
                                                  int n_desc, int64_t n_items) {
-  __shared__ T Qs[2][32][33];
-  __shared__ double red[2][256];
-  const int tid = threadIdx.x;
-  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t base = (int64_t)blockIdx.x * 4; base < n_items; base += (int64_t)gridDim.x * 4) {
+    const int64_t item = base + wave;
+    if (item >= n_items) break;
     const int di = find_desc(&descs[0].item_begin, sizeof(HcaDesc) / 4, n_desc, item);
     const HcaDesc& h = descs[di];
     const int t = (int)(item - h.item_begin), n = h.n;
     const int64_t nn = (int64_t)n * n;
     const T* P = reinterpret_cast<const T*>(arena + h.p_off) + (int64_t)t * 2 * nn;
     const T* Q = reinterpret_cast<const T*>(arena + h.q_off) + (int64_t)t * 2 * nn;
+    const int nb = (n + 3) >> 2;
+    const bool vec = (n & 3) == 0;
     double sr = 0.0, si = 0.0;
-    for (int bi = 0; bi < n; bi += 32)
-      for (int bj = 0; bj < n; bj += 32) {
-        __syncthreads();
+    for (int b = lane; b < nb * nb; b += 64) {
+      const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
+      const int vj = min(4, n - j0), vi = min(4, n - i0);
+      T pr[4][4], pi[4][4], qr[4][4], qi[4][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {           // Qs[p][r][c] = Q[p][bj + r][bi + c]
-          const int idx = tid + 256 * q, r = idx >> 5, c = idx & 31;
-          const bool ok = bj + r < n && bi + c < n;
-          const int64_t o = (int64_t)(bj + r) * n + bi + c;
-          Qs[0][r][c] = ok ? Q[o] : T(0);
-          Qs[1][r][c] = ok ? Q[nn + o] : T(0);
-        }
-        __syncthreads();
+      for (int r = 0; r < 4; ++r) {
+        const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
+        load4<T>(pr[r], P + po, i0 + r < n ? vj : 0, vec);
+        load4<T>(pi[r], P + nn + po, i0 + r < n ? vj : 0, vec);
+        load4<T>(qr[r], Q + qo, j0 + r < n ? vi : 0, vec);
+        load4<T>(qi[r], Q + nn + qo, j0 + r < n ? vi : 0, vec);
+      }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {           // P[bi + r][bj + c] * Q[bj + c][bi + r]
-          const int idx = tid + 256 * q, r = idx >> 5, c = idx & 31;
-          if (bi + r < n && bj + c < n) {
-            const int64_t o = (int64_t)(bi + r) * n + bj + c;
-            const double pr = (double)P[o], pi = (double)P[nn + o];
-            const double qr = (double)Qs[0][c][r], qi = (double)Qs[1][c][r];
-            sr += pr * qr - pi * qi;
-            si += pr * qi + pi * qr;
-          }
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double xr = (double)pr[a][c], xi = (double)pi[a][c];
+          const double yr = (double)qr[c][a], yi = (double)qi[c][a];
+          sr += xr * yr - xi * yi;
+          si += xr * yi + xi * yr;
         }
-      }
-    red[0][tid] = sr;
-    red[1][tid] = si;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {         // fixed-order tree
-      if (tid < w) {
-        red[0][tid] += red[0][tid + w];
-        red[1][tid] += red[1][tid + w];
-      }
-      __syncthreads();
     }
-    if (tid == 0) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      sr += __shfl_xor(sr, o);
+      si += __shfl_xor(si, o);
+    }
+    if (lane == 0) {
       double* out = reinterpret_cast<double*>(arena + h.out_off);
-      out[2 * t] = red[0][0];
-      out[2 * t + 1] = red[1][0];
+      out[2 * t] = sr;
+      out[2 * t + 1] = si;
     }
-    __syncthreads();
   }
 }
 
@@ -643,9 +666,11 @@ hipError_t launch_reduce(int prec, char* arena, int64_t desc_off, int n_desc, in
 hipError_t launch_hca(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s) {
   const HcaDesc* d = reinterpret_cast<const HcaDesc*>(arena + desc_off);
   if (prec == 0)
-    hipLaunchKernelGGL(hca_trace<double>, dim3(grid_for(n_items)), dim3(256), 0, s, arena, d, n_desc, n_items);
+    hipLaunchKernelGGL(hca_trace<double>, dim3(grid_for((n_items + 3) / 4)), dim3(256), 0, s, arena, d, n_desc,
+                       n_items);
   else
-    hipLaunchKernelGGL(hca_trace<float>, dim3(grid_for(n_items)), dim3(256), 0, s, arena, d, n_desc, n_items);
+    hipLaunchKernelGGL(hca_trace<float>, dim3(grid_for((n_items + 3) / 4)), dim3(256), 0, s, arena, d, n_desc,
+                       n_items);
   return hipGetLastError();
 }
 

@@ -372,9 +372,12 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
 // variant with the least summed time of exterior contractions plus split-K
 // reductions.
 int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
-  std::map<std::pair<int, int>, int> shapes;
+  std::map<std::pair<int, int>, int> shapes;   // (kind, n) -> largest nt
   for (int64_t u = c.dag.n_leaves; u < c.dag.n_nodes(); ++u)
-    if (c.dag.kind[u] != HCA) shapes[{c.dag.kind[u], c.dag.nvec[u]}] = 1;
+    if (c.dag.kind[u] != HCA) {
+      int& nt = shapes[{c.dag.kind[u], c.dag.nvec[u]}];
+      nt = std::max(nt, (int)c.dag.nt[u]);
+    }
   const bool timing = c.timing;
   c.timing = true;
   int64_t tuned = 0;
@@ -383,7 +386,13 @@ int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
       const auto key = std::make_tuple(prec, sh.first.first, sh.first.second);
       double best = 1e300;
       int best_v = -1;
-      for (int v = 0; v < kNumVariants; ++v) {
+      for (int v = 0; v < kNumChoices; ++v) {
+        if (!choice_split_k(v)) {
+          // the no-split setting only differs where the rule would split
+          HecDesc h{};
+          decompose(sh.first.first, sh.first.second, sh.second, choice_variant(v), prec, &h);
+          if (h.splits == 1) continue;
+        }
         c.tiles[key] = v;
         c.version++;
         ensure_plan(c, prec, batched);

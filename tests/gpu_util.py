@@ -11,7 +11,7 @@ from oracle import values as OV
 
 def run(wl, policy="tree", prec="fp64", batched=False, budget=None, leaves_resident=False,
         use_graphs=True, wave_max=4096, wave_lookahead=0, device=0, tile=None, grid=1,
-        lds_stages=2, autotune=False, in_situ=False):
+        lds_stages=2, split_k=1, autotune=False, in_situ=False):
     import paper_2511_02257_amd as X
     from paper_2511_02257_amd.device import DeviceRunner
     ctx = X.Context()
@@ -23,7 +23,7 @@ def run(wl, policy="tree", prec="fp64", batched=False, budget=None, leaves_resid
     if tile is not None:
         for lf_n in {lf.nvec for lf in wl.leaves}:
             for kind in (0, 1, 2):
-                ctx.set_tile(prec, kind, lf_n, tile, grid, lds_stages)
+                ctx.set_tile(prec, kind, lf_n, tile, grid, lds_stages, split_k)
     runner = DeviceRunner(ctx, device)
     tuned = None
     if autotune:

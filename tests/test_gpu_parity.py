@@ -123,6 +123,24 @@ def test_every_tile_shape(meson_small, baryon_small, prec, tile, grid, stages):
         assert err.max() <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_without_split_k(baryon_small, prec):
+    """split_k 0: K33 (K = 1600) runs as one work item per output tile with the
+    whole K in one accumulator; the result matches the oracle and does not
+    depend on grouping (waves vs one launch per contraction)."""
+    wl, ref = baryon_small
+    a = run(wl, "tree", prec, True, tile=0, grid=1, split_k=0)
+    b = run(wl, "tree", prec, False, tile=0, grid=1, split_k=0)
+    c = run(wl, "tree", prec, True, tile=0, grid=1, split_k=1)
+    assert a["stats"]["plan"]["hec_items"] < c["stats"]["plan"]["hec_items"]
+    for r in (a, b):
+        err = rel_errors(r["corr"], ref)
+        print(f"baryon_small {prec} no split-K: max rel {err.max():.3e}")
+        assert err.max() <= TOL[prec]
+    assert np.array_equal(np.concatenate(a["corr"]).view(np.uint64),
+                          np.concatenate(b["corr"]).view(np.uint64))
+
+
 @pytest.mark.parametrize("in_situ", [False, True])
 def test_autotune_then_parity(baryon_small, in_situ):
     wl, ref = baryon_small

@@ -167,9 +167,9 @@ def test_full_configs_match_stored_oracle_results():
 
 
 def test_kernel_variants_round_trip_and_share_decomposition():
-    """Every (tile, grid, lds_stages) choice is stored and reported back.  Work
-    items are output tiles of the chosen shape (times the K splits): with no
-    split (K = N = 72 < 512) their count is sum over contractions of
+    """Every (tile, grid, lds_stages, split_k) choice is stored and reported
+    back.  Work items are output tiles of the chosen shape (times the K splits):
+    with no split (K = N = 72 < 512) their count is sum over contractions of
     Nt * ceil(M / bm) * ceil(N / bn), whatever the grid policy and LDS stages."""
     wl = W.meson_ring(n_leaves=6, nvec=72, nt=5, n_graphs=20, lmin=4, lmax=6, with_data=False)
     d = OD.build(wl.leaves, wl.graphs)
@@ -180,18 +180,43 @@ def test_kernel_variants_round_trip_and_share_decomposition():
         want = n_k22 * 5 * (-(-72 // bm)) * (-(-72 // bn))
         for grid in (0, 1):
             for stages in (2, 1):
-                for prec in ("fp64", "fp32", "bf16x3"):
-                    for kind in (0, 1, 2):
-                        c.set_tile(prec, kind, 72, tile, grid, stages)
-                        assert c.get_tile(prec, kind, 72) == (tile, grid, stages)
-                    assert c.plan(prec, True)["hec_items"] == want, (tile, grid, stages, prec)
-    for bad in ((5, 1, 2), (-2, 1, 2), (0, 2, 2), (0, 1, 3), (0, 1, 0)):
+                for split in (1, 0):
+                    for prec in ("fp64", "fp32", "bf16x3"):
+                        for kind in (0, 1, 2):
+                            c.set_tile(prec, kind, 72, tile, grid, stages, split)
+                            assert c.get_tile(prec, kind, 72) == (tile, grid, stages, split)
+                        assert c.plan(prec, True)["hec_items"] == want, (tile, grid, stages, prec)
+    for bad in ((5, 1, 2, 1), (-2, 1, 2, 1), (0, 2, 2, 1), (0, 1, 3, 1), (0, 1, 0, 1), (0, 1, 2, 2)):
         with pytest.raises(X.CdagError) as e:
             c.set_tile("fp64", 0, 72, *bad)
         assert e.value.code == B.E_INVALID
     c.set_tile("fp64", 0, 72, -1)          # back to the default choice
-    t, g, st = c.get_tile("fp64", 0, 72)
-    assert t in X.TILES and (g, st) == (1, 2)
+    t, g, st, sk = c.get_tile("fp64", 0, 72)
+    assert t in X.TILES and (g, st, sk) == (1, 2, 1)
+
+
+def test_split_k_choice_sets_the_work_items():
+    """K33 at N = 40 has K = 1600: with split_k 1 and fewer than 512 output
+    tiles it is cut into min(ceil(512 / tiles), K / 256) splits, rounded to
+    whole k-steps; with split_k 0 each output tile is one work item."""
+    wl = W.baryon_mix(n_bar=3, n_mes=3, nvec=40, nt=5, n_graphs=12, with_data=False)
+    d = OD.build(wl.leaves, wl.graphs)
+    n_k = {k: sum(1 for u in range(d.n_nodes) if d.kind[u] == k) for k in (W.K32, W.K33)}
+    c = ctx_for(wl)
+    c.schedule("tree")
+    for tile, (bm, bn) in sorted(X.TILES.items()):
+        for prec, kstep in (("fp64", 16), ("fp32", 16), ("bf16x3", 32)):
+            k32 = n_k[W.K32] * 5 * (-(-1600 // bm)) * (-(-40 // bn))   # K32: M = N^2, K = N: no split
+            base33 = 5 * (-(-40 // bm)) * (-(-40 // bn))
+            for kind in (1, 2):
+                c.set_tile(prec, kind, 40, tile, 1, 2, 0)
+            assert c.plan(prec, True)["hec_items"] == k32 + n_k[W.K33] * base33
+            for kind in (1, 2):
+                c.set_tile(prec, kind, 40, tile, 1, 2, 1)
+            splits = max(1, min(-(-512 // base33), 1600 // 256))
+            kspl = -(-(-(-1600 // splits)) // kstep) * kstep
+            splits = -(-1600 // kspl)
+            assert c.plan(prec, True)["hec_items"] == k32 + n_k[W.K33] * base33 * splits, (tile, prec)
 
 
 def test_launch_records_empty_without_a_timed_execute():
