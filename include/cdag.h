@@ -224,6 +224,14 @@ int cdag_get_nodes(cdag_ctx* c, int32_t* kind, int64_t* left, int64_t* right, in
                    int64_t* n_out);
 int cdag_graph_roots(cdag_ctx* c, int64_t* root_of_graph, int64_t cap);
 
+/* Size of the merged DAG and the Sec. III-B runtime factors: F_v = average
+ * over vertices of the number of trees containing the vertex; F_e = average
+ * over edges (child, parent) of the number of trees containing both ends
+ * (every tree that holds the parent holds its children).  Trees are counted
+ * per unique root.  Any output pointer may be NULL. */
+int cdag_dag_stats(cdag_ctx* c, int64_t* n_vertices, int64_t* n_edges, int64_t* n_trees, double* f_v,
+                   double* f_e);
+
 /* Device binding.  device: HIP ordinal.  compute_stream, copy_stream:
  * hipStream_t handles borrowed for the context's lifetime (copies run on the
  * second; both must be non-NULL and distinct).  The arena is device memory of

@@ -98,6 +98,8 @@ def lib():
             "set_mem_budget": [P, C.c_uint64],
             "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
             "cdag_set_timing": [P, C.c_int],
+            "cdag_dag_stats": [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double)],
             "cdag_launch_records": [P, C.POINTER(cdag_launch_record), I64, C.POINTER(I64)],
             "cdag_set_tile": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int],
             "cdag_get_tile": [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
@@ -125,7 +127,7 @@ def lib():
 
 
 EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "schedule",
-            "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_launch_records", "cdag_set_tile", "cdag_get_tile", "cdag_memsim", "cdag_plan", "cdag_plan_ops",
+            "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_launch_records", "cdag_dag_stats", "cdag_set_tile", "cdag_get_tile", "cdag_memsim", "cdag_plan", "cdag_plan_ops",
             "cdag_get_nodes", "cdag_graph_roots", "cdag_bind_device", "cdag_bind_arena",
             "execute", "cdag_autotune", "fetch_correlators", "cdag_fetch_sums")
 
@@ -212,6 +214,15 @@ def cdag_set_options(h, leaves_resident=False, wave_max=4096, wave_lookahead=0,
 
 def cdag_set_timing(h, on: bool) -> None:
     _check(lib().cdag_set_timing(h, int(bool(on))))
+
+
+def cdag_dag_stats(h):
+    """{n_vertices, n_edges, n_trees, f_v, f_e} of the merged DAG."""
+    v, e, k = C.c_int64(), C.c_int64(), C.c_int64()
+    fv, fe = C.c_double(), C.c_double()
+    _check(lib().cdag_dag_stats(h, C.byref(v), C.byref(e), C.byref(k), C.byref(fv), C.byref(fe)))
+    return {"n_vertices": v.value, "n_edges": e.value, "n_trees": k.value, "f_v": fv.value,
+            "f_e": fe.value}
 
 
 def cdag_launch_records(h):
@@ -389,6 +400,9 @@ class Context:
 
     def launch_records(self):
         return cdag_launch_records(self.h)
+
+    def dag_stats(self):
+        return cdag_dag_stats(self.h)
 
     def set_tile(self, prec, kind, nvec, tile, grid=1, lds_stages=2, split_k=1):
         cdag_set_tile(self.h, prec, kind, nvec, tile, grid, lds_stages, split_k)

@@ -352,6 +352,27 @@ int cdag_graph_roots(cdag_ctx* h, int64_t* roots, int64_t cap) {
   });
 }
 
+int cdag_dag_stats(cdag_ctx* h, int64_t* n_vertices, int64_t* n_edges, int64_t* n_trees, double* f_v,
+                   double* f_e) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    need(h->c.built, CDAG_E_STATE, "build_cdag first");
+    const cdag::Dag& d = h->c.dag;
+    const int64_t V = d.n_nodes(), E = 2 * (V - d.n_leaves);
+    double sv = 0, se = 0;
+    for (int64_t u = 0; u < V; ++u) {
+      const int64_t c = d.ctree_off[u + 1] - d.ctree_off[u];
+      sv += (double)c;
+      if (!d.is_leaf(u)) se += 2.0 * (double)c;
+    }
+    if (n_vertices) *n_vertices = V;
+    if (n_edges) *n_edges = E;
+    if (n_trees) *n_trees = (int64_t)d.tree_root.size();
+    if (f_v) *f_v = V ? sv / (double)V : 0.0;
+    if (f_e) *f_e = E ? se / (double)E : 0.0;
+  });
+}
+
 int cdag_bind_device(cdag_ctx* h, int device, void* compute_stream, void* copy_stream) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {

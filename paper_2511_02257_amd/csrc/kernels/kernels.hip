@@ -72,6 +72,38 @@ __device__ __forceinline__ WorkItem decode_item(const HecDesc* descs, int n_desc
   return w;
 }
 
+// Operand view of one work item: the contraction's descriptor, the A and B
+// slices of its time slice, and the tile and K range.
+template <typename T>
+struct ItemView {
+  const HecDesc* h;
+  const T* A;
+  const T* B;
+  int M, N, K, t, sp, m0, n0, kbeg, kend;
+  bool avec, bvec;   // rows of A (B) allow 8-element vector loads
+};
+
+template <typename T, int BM, int BN>
+__device__ __forceinline__ ItemView<T> view_item(char* arena, const HecDesc* descs, int n_desc, int64_t item) {
+  const WorkItem w = decode_item<BM, BN>(descs, n_desc, item);
+  ItemView<T> v;
+  v.h = w.h;
+  v.M = w.h->M;
+  v.N = w.h->N;
+  v.K = w.h->K;
+  v.t = w.t;
+  v.sp = w.sp;
+  v.m0 = w.m0;
+  v.n0 = w.n0;
+  v.kbeg = w.kbeg;
+  v.kend = w.kend;
+  v.A = reinterpret_cast<const T*>(arena + w.h->a_off) + (int64_t)w.t * 2 * v.M * v.K;
+  v.B = reinterpret_cast<const T*>(arena + w.h->b_off) + (int64_t)w.t * 2 * v.K * v.N;
+  v.avec = (v.K & 7) == 0;
+  v.bvec = (v.N & 7) == 0;
+  return v;
+}
+
 // ------------------------------------------------------------------ FP64 / FP32
 template <typename T> struct Mfma;
 // Output layout of one 16x16 block: lane l, register v holds column l % 16 and
@@ -135,8 +167,9 @@ __device__ __forceinline__ void store_block(T* C, int M, int N, int row0, int co
 
 // ST: LDS stages.  2 = double buffer (one barrier per k-chunk); 1 = one
 // buffer refilled from the register prefetch (two barriers per k-chunk, half
-// the LDS, more workgroups per compute unit).
-template <typename T, class TL, int ST>
+// the LDS, more workgroups per compute unit).  PF: a workgroup that strides
+// over several items (persistent grid) prefetches its next item.
+template <typename T, class TL, int ST, bool PF>
 __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs,
                                                      int n_desc, int64_t n_items) {
   typedef typename Mfma<T>::V V;
@@ -150,13 +183,64 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / TL::WGN, wn = wave % TL::WGN, li = lane & 15, lk = lane >> 4;
 
-  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-    const WorkItem w = decode_item<BM, BN>(descs, n_desc, item);
-    const HecDesc& h = *w.h;
-    const int M = h.M, N = h.N, K = h.K;
-    const T* A = reinterpret_cast<const T*>(arena + h.a_off) + (int64_t)w.t * 2 * M * K;
-    const T* B = reinterpret_cast<const T*>(arena + h.b_off) + (int64_t)w.t * 2 * K * N;
-    const bool avec = (K & 7) == 0, bvec = (N & 7) == 0;
+  T ra[LA][8], rb[LB][8];
+  auto gload = [&](const ItemView<T>& o, int k0) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int seg = tid + q * NTH;
+      if (seg < SEGA) {
+        const int p = seg / (2 * BM), r = (seg % (2 * BM)) >> 1, hh = seg & 1;
+        const int am = o.m0 + r, ak = k0 + 8 * hh;
+        const int av = am < o.M ? max(0, min(8, o.kend - ak)) : 0;
+        load8<T>(ra[q], o.A + (int64_t)p * o.M * o.K + (int64_t)am * o.K + ak, av, o.avec);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int seg = tid + q * NTH;
+      if (seg < SEGB) {
+        const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
+        const int kk = rem / (BN / 8), sg = rem % (BN / 8);
+        const int bkk = k0 + kk, bn = o.n0 + 8 * sg;
+        const int bv = bkk < o.kend ? max(0, min(8, o.N - bn)) : 0;
+        load8<T>(rb[q], o.B + (int64_t)p * o.K * o.N + (int64_t)bkk * o.N + bn, bv, o.bvec);
+      }
+    }
+  };
+  auto sstore = [&](int st) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int seg = tid + q * NTH;
+      if (seg < SEGA) {
+        const int p = seg / (2 * BM), r = (seg % (2 * BM)) >> 1, hh = seg & 1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) As[st][p][r][8 * hh + i] = ra[q][i];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int seg = tid + q * NTH;
+      if (seg < SEGB) {
+        const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
+        const int kk = rem / (BN / 8), sg = rem % (BN / 8);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Bs[st][p][kk][8 * sg + i] = rb[q][i];
+      }
+    }
+  };
+
+  int64_t item = blockIdx.x;
+  if (item >= n_items) return;
+  ItemView<T> cur = view_item<T, BM, BN>(arena, descs, n_desc, item);
+  gload(cur, cur.kbeg);
+  for (;;) {
+    // With PF the next item is located now and its first k-slice is loaded
+    // during this item's last slice, so the workgroup never waits for a fresh
+    // item's first loads.
+    const int64_t next = item + gridDim.x;
+    const bool has_next = next < n_items;
+    ItemView<T> nxt = cur;
+    if (PF && has_next) nxt = view_item<T, BM, BN>(arena, descs, n_desc, next);
 
     V cr[TM][TN], ci[TM][TN];
 #pragma unroll
@@ -164,54 +248,7 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
 #pragma unroll
       for (int j = 0; j < TN; ++j) { cr[i][j] = V{0, 0, 0, 0}; ci[i][j] = V{0, 0, 0, 0}; }
 
-    T ra[LA][8], rb[LB][8];
-    auto gload = [&](int k0) {
-#pragma unroll
-      for (int q = 0; q < LA; ++q) {
-        const int seg = tid + q * NTH;
-        if (seg < SEGA) {
-          const int p = seg / (2 * BM), r = (seg % (2 * BM)) >> 1, hh = seg & 1;
-          const int am = w.m0 + r, ak = k0 + 8 * hh;
-          const int av = am < M ? max(0, min(8, w.kend - ak)) : 0;
-          load8<T>(ra[q], A + (int64_t)p * M * K + (int64_t)am * K + ak, av, avec);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < LB; ++q) {
-        const int seg = tid + q * NTH;
-        if (seg < SEGB) {
-          const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
-          const int kk = rem / (BN / 8), sg = rem % (BN / 8);
-          const int bkk = k0 + kk, bn = w.n0 + 8 * sg;
-          const int bv = bkk < w.kend ? max(0, min(8, N - bn)) : 0;
-          load8<T>(rb[q], B + (int64_t)p * K * N + (int64_t)bkk * N + bn, bv, bvec);
-        }
-      }
-    };
-    auto sstore = [&](int st) {
-#pragma unroll
-      for (int q = 0; q < LA; ++q) {
-        const int seg = tid + q * NTH;
-        if (seg < SEGA) {
-          const int p = seg / (2 * BM), r = (seg % (2 * BM)) >> 1, hh = seg & 1;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) As[st][p][r][8 * hh + i] = ra[q][i];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < LB; ++q) {
-        const int seg = tid + q * NTH;
-        if (seg < SEGB) {
-          const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
-          const int kk = rem / (BN / 8), sg = rem % (BN / 8);
-#pragma unroll
-          for (int i = 0; i < 8; ++i) Bs[st][p][kk][8 * sg + i] = rb[q][i];
-        }
-      }
-    };
-
-    const int nk = (w.kend - w.kbeg + BK - 1) / BK;
-    gload(w.kbeg);
+    const int nk = (cur.kend - cur.kbeg + BK - 1) / BK;
     if (ST == 2) {
       sstore(0);
       __syncthreads();
@@ -222,7 +259,10 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
         sstore(0);
         __syncthreads();
       }
-      if (c + 1 < nk) gload(w.kbeg + (c + 1) * BK);
+      if (c + 1 < nk)
+        gload(cur, cur.kbeg + (c + 1) * BK);
+      else if (PF && has_next)
+        gload(nxt, nxt.kbeg);
 #pragma unroll
       for (int k4 = 0; k4 < BK / 4; ++k4) {
         const int kk = 4 * k4 + lk;
@@ -260,17 +300,27 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
       __syncthreads();
     }
 
+    const HecDesc& h = *cur.h;
+    const int M = cur.M, N = cur.N;
     T* C;
     if (h.splits > 1)
-      C = reinterpret_cast<T*>(arena + h.ws_off) + ((int64_t)w.sp * h.nt + w.t) * 2 * M * N;
+      C = reinterpret_cast<T*>(arena + h.ws_off) + ((int64_t)cur.sp * h.nt + cur.t) * 2 * M * N;
     else
-      C = reinterpret_cast<T*>(arena + h.c_off) + (int64_t)w.t * 2 * M * N;
+      C = reinterpret_cast<T*>(arena + h.c_off) + (int64_t)cur.t * 2 * M * N;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j)
-        store_block<T, V>(C, M, N, w.m0 + (wm * TM + i) * 16, w.n0 + (wn * TN + j) * 16 + li, cr[i][j],
+        store_block<T, V>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li, cr[i][j],
                           ci[i][j], lk);
+    if (!has_next) break;
+    item = next;
+    if (PF) {
+      cur = nxt;
+    } else {
+      cur = view_item<T, BM, BN>(arena, descs, n_desc, item);
+      gload(cur, cur.kbeg);
+    }
   }
 }
 
@@ -283,7 +333,7 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-template <class TL, int ST>
+template <class TL, int ST, bool PF>
 __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, const HecDesc* __restrict__ descs,
                                                        int n_desc, int64_t n_items) {
   constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
@@ -296,13 +346,73 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / TL::WGN, wn = wave % TL::WGN, li = lane & 15, lk = lane >> 4;
 
-  for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
-    const WorkItem w = decode_item<BM, BN>(descs, n_desc, item);
-    const HecDesc& h = *w.h;
-    const int M = h.M, N = h.N, K = h.K;
-    const float* A = reinterpret_cast<const float*>(arena + h.a_off) + (int64_t)w.t * 2 * M * K;
-    const float* B = reinterpret_cast<const float*>(arena + h.b_off) + (int64_t)w.t * 2 * K * N;
-    const bool avec = (K & 7) == 0, bvec = (N & 7) == 0;
+  float ra[LA][8], rb[LB][8];
+  auto gload = [&](const ItemView<float>& o, int k0) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int seg = tid + q * NTH;
+      if (seg < SEGA) {
+        const int p = seg / (4 * BM), r = (seg % (4 * BM)) >> 2, qq = seg & 3;
+        const int am = o.m0 + r, ak = k0 + 8 * qq;
+        const int av = am < o.M ? max(0, min(8, o.kend - ak)) : 0;
+        load8<float>(ra[q], o.A + (int64_t)p * o.M * o.K + (int64_t)am * o.K + ak, av, o.avec);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int seg = tid + q * NTH;
+      if (seg < SEGB) {
+        const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
+        const int kk = rem / (BN / 8), sg = rem % (BN / 8);
+        const int bkk = k0 + kk, bn = o.n0 + 8 * sg;
+        const int bv = bkk < o.kend ? max(0, min(8, o.N - bn)) : 0;
+        load8<float>(rb[q], o.B + (int64_t)p * o.K * o.N + (int64_t)bkk * o.N + bn, bv, o.bvec);
+      }
+    }
+  };
+  auto sstore = [&](int st) {
+#pragma unroll
+    for (int q = 0; q < LA; ++q) {
+      const int seg = tid + q * NTH;
+      if (seg < SEGA) {
+        const int p = seg / (4 * BM), r = (seg % (4 * BM)) >> 2, qq = seg & 3;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          __bf16 hi, lo;
+          split_bf16(ra[q][i], hi, lo);
+          As[st][p][0][r][8 * qq + i] = hi;
+          As[st][p][1][r][8 * qq + i] = lo;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < LB; ++q) {
+      const int seg = tid + q * NTH;
+      if (seg < SEGB) {
+        const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
+        const int kk = rem / (BN / 8), sg = rem % (BN / 8);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          __bf16 hi, lo;
+          split_bf16(rb[q][i], hi, lo);
+          Bs[st][p][0][8 * sg + i][kk] = hi;
+          Bs[st][p][1][8 * sg + i][kk] = lo;
+        }
+      }
+    }
+  };
+
+  int64_t item = blockIdx.x;
+  if (item >= n_items) return;
+  ItemView<float> cur = view_item<float, BM, BN>(arena, descs, n_desc, item);
+  gload(cur, cur.kbeg);
+  for (;;) {
+    // with PF: next item located now, its first k-slice loaded during this
+    // item's last slice
+    const int64_t next = item + gridDim.x;
+    const bool has_next = next < n_items;
+    ItemView<float> nxt = cur;
+    if (PF && has_next) nxt = view_item<float, BM, BN>(arena, descs, n_desc, next);
 
     v4f cr[TM][TN], ci[TM][TN];
 #pragma unroll
@@ -310,64 +420,7 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
 #pragma unroll
       for (int j = 0; j < TN; ++j) { cr[i][j] = v4f{0, 0, 0, 0}; ci[i][j] = v4f{0, 0, 0, 0}; }
 
-    float ra[LA][8], rb[LB][8];
-    auto gload = [&](int k0) {
-#pragma unroll
-      for (int q = 0; q < LA; ++q) {
-        const int seg = tid + q * NTH;
-        if (seg < SEGA) {
-          const int p = seg / (4 * BM), r = (seg % (4 * BM)) >> 2, qq = seg & 3;
-          const int am = w.m0 + r, ak = k0 + 8 * qq;
-          const int av = am < M ? max(0, min(8, w.kend - ak)) : 0;
-          load8<float>(ra[q], A + (int64_t)p * M * K + (int64_t)am * K + ak, av, avec);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < LB; ++q) {
-        const int seg = tid + q * NTH;
-        if (seg < SEGB) {
-          const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
-          const int kk = rem / (BN / 8), sg = rem % (BN / 8);
-          const int bkk = k0 + kk, bn = w.n0 + 8 * sg;
-          const int bv = bkk < w.kend ? max(0, min(8, N - bn)) : 0;
-          load8<float>(rb[q], B + (int64_t)p * K * N + (int64_t)bkk * N + bn, bv, bvec);
-        }
-      }
-    };
-    auto sstore = [&](int st) {
-#pragma unroll
-      for (int q = 0; q < LA; ++q) {
-        const int seg = tid + q * NTH;
-        if (seg < SEGA) {
-          const int p = seg / (4 * BM), r = (seg % (4 * BM)) >> 2, qq = seg & 3;
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            __bf16 hi, lo;
-            split_bf16(ra[q][i], hi, lo);
-            As[st][p][0][r][8 * qq + i] = hi;
-            As[st][p][1][r][8 * qq + i] = lo;
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < LB; ++q) {
-        const int seg = tid + q * NTH;
-        if (seg < SEGB) {
-          const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
-          const int kk = rem / (BN / 8), sg = rem % (BN / 8);
-#pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            __bf16 hi, lo;
-            split_bf16(rb[q][i], hi, lo);
-            Bs[st][p][0][8 * sg + i][kk] = hi;
-            Bs[st][p][1][8 * sg + i][kk] = lo;
-          }
-        }
-      }
-    };
-
-    const int nk = (w.kend - w.kbeg + BK - 1) / BK;
-    gload(w.kbeg);
+    const int nk = (cur.kend - cur.kbeg + BK - 1) / BK;
     if (ST == 2) {
       sstore(0);
       __syncthreads();
@@ -378,7 +431,10 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
         sstore(0);
         __syncthreads();
       }
-      if (c + 1 < nk) gload(w.kbeg + (c + 1) * BK);
+      if (c + 1 < nk)
+        gload(cur, cur.kbeg + (c + 1) * BK);
+      else if (PF && has_next)
+        gload(nxt, nxt.kbeg);
       // one 16x16x32 step: lane holds k = 8*lk .. 8*lk+7 of row li (A) / column li (B)
       v8bf a[TM][2][2], b[TN][2][2], bn_hi[TN], bn_lo[TN];   // [block][plane][hi/lo]
 #pragma unroll
@@ -421,17 +477,27 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
       __syncthreads();
     }
 
+    const HecDesc& h = *cur.h;
+    const int M = cur.M, N = cur.N;
     float* C;
     if (h.splits > 1)
-      C = reinterpret_cast<float*>(arena + h.ws_off) + ((int64_t)w.sp * h.nt + w.t) * 2 * M * N;
+      C = reinterpret_cast<float*>(arena + h.ws_off) + ((int64_t)cur.sp * h.nt + cur.t) * 2 * M * N;
     else
-      C = reinterpret_cast<float*>(arena + h.c_off) + (int64_t)w.t * 2 * M * N;
+      C = reinterpret_cast<float*>(arena + h.c_off) + (int64_t)cur.t * 2 * M * N;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j)
-        store_block<float, v4f>(C, M, N, w.m0 + (wm * TM + i) * 16, w.n0 + (wn * TN + j) * 16 + li,
+        store_block<float, v4f>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li,
                                 cr[i][j], ci[i][j], lk);
+    if (!has_next) break;
+    item = next;
+    if (PF) {
+      cur = nxt;
+    } else {
+      cur = view_item<float, BM, BN>(arena, descs, n_desc, item);
+      gload(cur, cur.kbeg);
+    }
   }
 }
 
@@ -605,20 +671,33 @@ constexpr int64_t kMaxGrid = 1 << 20;
 unsigned grid_for(int64_t items) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, kMaxGrid)); }
 }  // namespace
 
+template <class TL, int ST, bool PF>
+void launch_hec_kernel(int prec, unsigned grid, char* arena, const HecDesc* d, int n_desc, int64_t n_items,
+                       hipStream_t s) {
+  const dim3 block(TL::NTH);
+  if (prec == 0)
+    hipLaunchKernelGGL((hec_mfma<double, TL, ST, PF>), dim3(grid), block, 0, s, arena, d, n_desc, n_items);
+  else if (prec == 1)
+    hipLaunchKernelGGL((hec_mfma<float, TL, ST, PF>), dim3(grid), block, 0, s, arena, d, n_desc, n_items);
+  else
+    hipLaunchKernelGGL((hec_bf16x3<TL, ST, PF>), dim3(grid), block, 0, s, arena, d, n_desc, n_items);
+}
+
 template <class TL, int ST>
 void launch_hec_tile(int prec, bool persistent, char* arena, const HecDesc* d, int n_desc, int64_t n_items,
                      hipStream_t s) {
-  const dim3 block(TL::NTH);
-  if (prec == 0) {
-    const dim3 grid(persistent ? persistent_grid(hec_mfma<double, TL, ST>, TL::NTH, n_items) : grid_for(n_items));
-    hipLaunchKernelGGL((hec_mfma<double, TL, ST>), grid, block, 0, s, arena, d, n_desc, n_items);
-  } else if (prec == 1) {
-    const dim3 grid(persistent ? persistent_grid(hec_mfma<float, TL, ST>, TL::NTH, n_items) : grid_for(n_items));
-    hipLaunchKernelGGL((hec_mfma<float, TL, ST>), grid, block, 0, s, arena, d, n_desc, n_items);
-  } else {
-    const dim3 grid(persistent ? persistent_grid(hec_bf16x3<TL, ST>, TL::NTH, n_items) : grid_for(n_items));
-    hipLaunchKernelGGL((hec_bf16x3<TL, ST>), grid, block, 0, s, arena, d, n_desc, n_items);
+  if (!persistent) {
+    launch_hec_kernel<TL, ST, false>(prec, grid_for(n_items), arena, d, n_desc, n_items, s);
+    return;
   }
+  unsigned grid;
+  if (prec == 0)
+    grid = persistent_grid(hec_mfma<double, TL, ST, true>, TL::NTH, n_items);
+  else if (prec == 1)
+    grid = persistent_grid(hec_mfma<float, TL, ST, true>, TL::NTH, n_items);
+  else
+    grid = persistent_grid(hec_bf16x3<TL, ST, true>, TL::NTH, n_items);
+  launch_hec_kernel<TL, ST, true>(prec, grid, arena, d, n_desc, n_items, s);
 }
 
 template <int ST>
