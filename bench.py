@@ -158,6 +158,54 @@ def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True, fix
     return res
 
 
+def corr_func_study(rows=None):
+    """Host-only: the peak-memory study (Sec. V-B) and the scheduler-time study
+    (Table sch-time) on the Table corr-func-shaped DAGs.  Per row: DAG size
+    and F_v / F_e, then for the input order, Sibling and Tree the wall time of
+    the schedule call and the peak memory (after-release M_i peak and live
+    peak during an op), in units of the greatest common divisor of the
+    distinct tensor sizes as the paper plots them."""
+    import math
+    from synth import corr_func as CF
+    import paper_2511_02257_amd as X
+    out = {}
+    for row in rows or list(CF.TABLE):
+        wl = CF.corr_func_like(row)
+        ctx = X.Context()
+        t0 = time.perf_counter()
+        ctx.build_cdag(wl.leaves, wl.graphs)
+        t_build = time.perf_counter() - t0
+        st = ctx.dag_stats()
+        kind, _, _ = ctx.nodes()
+        sizes = set()
+        for lf in wl.leaves:
+            sizes.add(lf.nt * lf.nvec ** lf.rank * 16)
+        rank_of = {0: 2, 1: 3, 2: 2}
+        n = wl.leaves[0].nvec
+        for k in set(int(x) for x in kind[len(wl.leaves):]):
+            if k in rank_of:
+                sizes.add(wl.leaves[0].nt * n ** rank_of[k] * 16)
+        unit = 0
+        for z in sizes:
+            unit = math.gcd(unit, z)
+        res = {"system": CF.TABLE[row]["system"], "graphs": len(wl.graphs), "leaves": len(wl.leaves),
+               "N": n, "build_ms": round(t_build * 1e3, 1), **{k: (round(v, 3) if isinstance(v, float) else v)
+                                                           for k, v in st.items()}}
+        for policy in ("input", "sibling", "tree"):
+            t0 = time.perf_counter()
+            order = ctx.schedule(policy)
+            dt = time.perf_counter() - t0
+            _, pp, pl = ctx.memsim(order, 16)
+            res[policy] = {"ms": round(dt * 1e3, 2), "peak_post_units": int(pp // unit),
+                           "peak_live_units": int(pl // unit)}
+        best = min(res["sibling"]["peak_post_units"], res["tree"]["peak_post_units"])
+        res["input_over_best"] = round(res["input"]["peak_post_units"] / max(1, best), 3)
+        out[row] = res
+        log(row, res)
+        ctx.close()
+    return out
+
+
 def cpu_baseline(wl, seconds=12.0):
     """The oracle (numpy complex128, each graph on its own) on a bounded sample."""
     from oracle import values as OV
@@ -201,6 +249,9 @@ def main():
     ap.add_argument("--variants-from", default=None, metavar="JSON",
                     help="with --workload baryon_mix or batched: take the kernel choices from the "
                          "JSON line of an earlier run of the same workload instead of autotuning")
+    ap.add_argument("--study", default=None, choices=("corr_func",),
+                    help="host-only: peak memory and scheduler time on the Table corr-func-shaped "
+                         "DAGs (no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -214,6 +265,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": n, "copy_calibration_bytes_written": n,
                           "launches": 3}))
+        return
+    if args.study == "corr_func":
+        print(json.dumps({"study": "corr_func", "rows": corr_func_study()}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is not "

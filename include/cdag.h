@@ -247,10 +247,12 @@ int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
 
 /* Autotuner over the kernel variants of cdag_set_tile, for every distinct
  * (kind, N) among the exterior contractions of the DAG.  mode 0 (synthetic):
- * time each variant `reps` times on one contraction of that shape placed in
- * the bound arena's tensor pool (as planned for (prec, batched); its contents
- * are scratch between executes) and keep the fastest per time slice (split_k
- * stays 1).  mode 1 (in situ): execute the planned DAG `reps` times per
+ * time each variant and split_k setting `reps` times on a batch of time
+ * slices of that shape (at least 4096 work items, as in a wave of such
+ * contractions, at most 64 contractions' worth; split counts as for one
+ * contraction) placed in the bound arena's tensor pool (as planned for
+ * (prec, batched); its contents are scratch between executes) and keep the
+ * fastest per time slice.  mode 1 (in situ): execute the planned DAG `reps` times per
  * variant and split_k setting, shape by shape, with launch timing on, and keep
  * the least summed time of exterior contractions and split-K reductions
  * (needs leaf data; costs up to 40 * reps executes per shape).  *n_tuned

@@ -124,7 +124,10 @@ std::vector<int64_t> sched_sibling(const Dag& d) {
 namespace {
 enum TrState : uint8_t { AVAIL, TR_INMEM, TR_RELEASED };
 
-struct TauDelta { int64_t tree, tau, delta; bool in_pred; };
+// Per (node x, successor tree T): tau = unprocessed parents of x inside T.
+// The paper's delta (unprocessed parents of x outside T) is not stored: it is
+// out_av[x] - tau, so processing a parent outside T needs no per-tree update.
+struct Pred { int64_t tree, tau; bool in_pred; };
 
 struct TreeSched {
   const Dag& d;
@@ -133,13 +136,17 @@ struct TreeSched {
   std::vector<uint8_t> state;
   std::vector<int64_t> out_av;              // |u.outAv|
   std::vector<int64_t> igain;               // aligned with ctree: igain(T_i, u)
-  std::vector<std::vector<TauDelta>> td;    // per node: tau/delta per successor tree
+  std::vector<std::vector<Pred>> td;        // per node: one entry per successor tree, by tree
+  // per node: tau value -> indices into td[node] (entries whose tau changed
+  // since they were filed are stale and skipped)
+  std::vector<std::vector<std::vector<int32_t>>> bucket;
+  std::vector<int64_t> cnt;                 // scratch: per tree counter
+  std::vector<int64_t> touched;             // scratch: trees with a nonzero counter
   std::vector<int64_t> tgain, cgain;
   std::vector<char> alive;
   std::set<std::pair<int64_t, int64_t>> pq; // (-tgain, tree) of live trees
   std::vector<int64_t> order;
   std::vector<int64_t> visit_mark;
-  std::vector<int64_t> tpos;                // scratch: tree -> index in td[u], or -1
 
   TreeSched(const Dag& dd, int elem_bytes)
       : d(dd), k((int64_t)dd.tree_root.size()) {
@@ -147,7 +154,22 @@ struct TreeSched {
     size.resize(n);
     for (int64_t u = 0; u < n; ++u) size[u] = d.size(u, elem_bytes);
     visit_mark.assign(n, -1);
-    tpos.assign(k, -1);
+    cnt.assign(k, 0);
+  }
+
+  // cnt[t] = number of parents of u inside tree t (trees listed in touched).
+  void count_parents_in_trees(int64_t u) {
+    for (int64_t e = d.par_off[u]; e < d.par_off[u + 1]; ++e) {
+      const int64_t p = d.par[e];
+      for (int64_t j = d.ctree_off[p]; j < d.ctree_off[p + 1]; ++j) {
+        const int64_t t = d.ctree[j];
+        if (cnt[t]++ == 0) touched.push_back(t);
+      }
+    }
+  }
+  void clear_counts() {
+    for (int64_t t : touched) cnt[t] = 0;
+    touched.clear();
   }
 
   void set_gain(int64_t t, int64_t delta) {
@@ -166,38 +188,52 @@ struct TreeSched {
     cgain.assign(k, 0);
     alive.assign(k, 1);
     td.assign(n, {});
+    bucket.assign(n, {});
     igain.assign(d.ctree.size(), 0);
     // g(u, T_i) = |outAv(u)| minus the edges (u, v) with v also in T_i, i.e.
-    // the number of u's parents outside T_i.
+    // the number of u's parents outside T_i.  Parents inside each tree are
+    // counted from the parents' tree lists: O(sum over edges of |ctree|).
     for (int64_t u = 0; u < n; ++u) {
+      count_parents_in_trees(u);
       for (int64_t j = d.ctree_off[u]; j < d.ctree_off[u + 1]; ++j) {
-        int64_t t = d.ctree[j];
-        int64_t g = out_av[u];
-        for (int64_t e = d.par_off[u]; e < d.par_off[u + 1]; ++e)
-          if (d.in_tree(d.par[e], t)) --g;
+        const int64_t t = d.ctree[j];
+        const int64_t g = out_av[u] - cnt[t];
         igain[j] = g == 0 ? 0 : -size[u];
         tgain[t] += igain[j];
       }
+      clear_counts();
     }
     for (int64_t t = 0; t < k; ++t) pq.insert({-tgain[t], t});
   }
 
   void process_child(int64_t u, int64_t x) {      // PROCESS-CHILD
-    for (TauDelta& e : td[x]) {
-      if (!e.in_pred) continue;
-      if (d.in_tree(u, e.tree)) {
-        if (e.tau == 1 && e.delta == 0) {          // case 1.a
-          cgain[e.tree] -= size[x];
-          set_gain(e.tree, -size[x]);
-        }
-        if (--e.tau == 0) e.in_pred = false;
-      } else {
-        if (e.delta == 1) {                        // case 2.a
-          cgain[e.tree] += size[x];
-          set_gain(e.tree, +size[x]);
-        }
-        --e.delta;
+    std::vector<Pred>& v = td[x];
+    const int64_t a = out_av[x];                  // before u is counted as processed
+    // Trees without u: delta = a - tau drops by one.  It reaches 0 (case 2.a)
+    // exactly for the entries with tau == a - 1.
+    if (a - 1 >= 1) {
+      for (int32_t i : bucket[x][a - 1]) {
+        const Pred& e = v[i];
+        if (!e.in_pred || e.tau != a - 1 || d.in_tree(u, e.tree)) continue;
+        cgain[e.tree] += size[x];
+        set_gain(e.tree, +size[x]);
       }
+    }
+    // Trees with u: tau drops by one, delta stays (case 1).
+    for (int64_t j = d.ctree_off[u]; j < d.ctree_off[u + 1]; ++j) {
+      const int64_t t = d.ctree[j];
+      const auto it = std::lower_bound(v.begin(), v.end(), t,
+                                       [](const Pred& e, int64_t tr) { return e.tree < tr; });
+      Pred& e = *it;                              // every tree of a parent of x has an entry
+      if (!e.in_pred) continue;
+      if (e.tau == 1 && a - e.tau == 0) {         // case 1.a
+        cgain[t] -= size[x];
+        set_gain(t, -size[x]);
+      }
+      if (--e.tau == 0)
+        e.in_pred = false;
+      else
+        bucket[x][e.tau].push_back((int32_t)(it - v.begin()));
     }
     if (--out_av[x] == 0) state[x] = TR_RELEASED;
   }
@@ -205,26 +241,21 @@ struct TreeSched {
   void process_node(int64_t u) {                  // PROCESS-NODE
     for (int64_t j = d.ctree_off[u]; j < d.ctree_off[u + 1]; ++j) set_gain(d.ctree[j], -igain[j]);
     // all of u's parents are AVAIL here (children are processed first)
-    std::vector<TauDelta>& v = td[u];
+    count_parents_in_trees(u);
+    std::vector<Pred>& v = td[u];
     v.clear();
-    for (int64_t e = d.par_off[u]; e < d.par_off[u + 1]; ++e) {
-      int64_t p = d.par[e];
-      for (int64_t j = d.ctree_off[p]; j < d.ctree_off[p + 1]; ++j) {
-        int64_t t = d.ctree[j];
-        if (tpos[t] < 0) {
-          tpos[t] = (int64_t)v.size();
-          v.push_back({t, 0, out_av[u], true});
-        }
-        v[tpos[t]].delta -= 1;
-        v[tpos[t]].tau += 1;
+    std::sort(touched.begin(), touched.end());
+    for (int64_t t : touched) v.push_back({t, cnt[t], true});
+    clear_counts();
+    auto& b = bucket[u];
+    b.assign((size_t)d.n_parents(u) + 1, {});
+    for (size_t i = 0; i < v.size(); ++i) {
+      b[v[i].tau].push_back((int32_t)i);
+      if (out_av[u] - v[i].tau == 0) {            // delta == 0
+        cgain[v[i].tree] += size[u];
+        set_gain(v[i].tree, +size[u]);
       }
     }
-    for (const TauDelta& e : v) tpos[e.tree] = -1;
-    for (const TauDelta& e : v)
-      if (e.delta == 0) {
-        cgain[e.tree] += size[u];
-        set_gain(e.tree, +size[u]);
-      }
     state[u] = out_av[u] == 0 ? TR_RELEASED : TR_INMEM;
   }
 

@@ -313,14 +313,25 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
       const int kind = sh.first.first, n = sh.first.second;
       double best = 1e300;
       int best_tile = -1;
-      for (int tile = 0; tile < kNumVariants; ++tile) {
+      for (int ch = 0; ch < kNumChoices; ++ch) {
         HecDesc h{};
-        decompose(kind, n, sh.second, tile, prec, &h);
+        decompose(kind, n, sh.second, ch, prec, &h);   // split count of a real contraction
+        if (!choice_split_k(ch)) {
+          HecDesc a{};
+          decompose(kind, n, sh.second, choice_variant(ch), prec, &a);
+          if (a.splits == 1) continue;                  // same work items as the split choice
+        }
+        const int64_t slice_items = (int64_t)h.tiles_m * h.tiles_n * h.splits;
         const int64_t slice = (int64_t)h.M * h.K * eb + (int64_t)h.K * h.N * eb + (int64_t)h.M * h.N * eb;
         const int64_t wslice = h.splits > 1 ? (int64_t)h.splits * 2 * h.M * h.N * acc : 0;
-        int64_t nt = std::min<int64_t>(sh.second, (hi - lo - 4096) / std::max<int64_t>(1, slice + wslice + 1024));
-        if (nt < 1) continue;
-        decompose(kind, n, (int)nt, tile, prec, &h);
+        // A wave holds many contractions of one shape: time a batch of slices
+        // with at least 4096 work items (at most 64 contractions' worth).
+        int64_t want = std::max<int64_t>(sh.second, (4096 + slice_items - 1) / slice_items);
+        want = std::min<int64_t>(want, 64LL * sh.second);
+        int64_t nt = std::min<int64_t>(want, (hi - lo - 4096) / std::max<int64_t>(1, slice + wslice + 1024));
+        if (nt < 1 || nt * slice_items > INT32_MAX) continue;
+        h.nt = (int32_t)nt;
+        h.tile_count = (int32_t)(nt * slice_items);
         const int64_t a = lo, b = a + al(nt * h.M * h.K * eb), cc = b + al(nt * h.K * h.N * eb);
         const int64_t ws = cc + al(nt * h.M * h.N * eb);
         const int64_t ws_bytes = h.splits > 1 ? al((int64_t)h.splits * nt * 2 * h.M * h.N * acc) : 0;
@@ -337,7 +348,7 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
         HIPC(hipMemcpyAsync(D.arena + desc, &h, sizeof(h), hipMemcpyHostToDevice, D.comp));
         HIPC(hipMemcpyAsync(D.arena + desc + 128, &r, sizeof(r), hipMemcpyHostToDevice, D.comp));
         auto once = [&] {
-          HIPC(launch_hec(prec, tile, D.arena, desc, 1, h.tile_count, D.comp));
+          HIPC(launch_hec(prec, choice_variant(ch), D.arena, desc, 1, h.tile_count, D.comp));
           if (h.splits > 1) HIPC(launch_reduce(prec, D.arena, desc + 128, 1, red_items, D.comp));
         };
         once();
@@ -348,7 +359,7 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
         float ms = 0;
         HIPC(hipEventElapsedTime(&ms, e0, e1));
         const double per_slice = ms / reps / (double)nt;
-        if (per_slice < best) { best = per_slice; best_tile = tile; }
+        if (per_slice < best) { best = per_slice; best_tile = ch; }
       }
       if (best_tile >= 0) {
         c.tiles[std::make_tuple(prec, kind, n)] = best_tile;

@@ -49,12 +49,12 @@ TABLE = {
 # Generator settings per row: leaf counts (mesons, baryons), the tree-size
 # mix of the system's templates, and the fitted skew.
 PARAMS: Dict[str, dict] = {
-    "a0-111":   dict(n_mes=492, n_bar=0, mix=(0.22, 0.58, 0.20), skew=0.0),
-    "a0-d3":    dict(n_mes=210, n_bar=0, mix=(0.30, 0.55, 0.15), skew=0.0),
-    "f0":       dict(n_mes=765, n_bar=0, mix=(0.82, 0.15, 0.03), skew=0.0),
-    "roper":    dict(n_mes=187, n_bar=187, mix=(0.48, 0.52), skew=0.0),
-    "deuteron": dict(n_mes=74, n_bar=74, mix=(0.10, 0.30, 0.60), skew=0.0),
-    "tritium":  dict(n_mes=0, n_bar=8, mix=(0.60, 0.40), skew=0.0),
+    "a0-111":   dict(n_mes=492, n_bar=0, mix=(0.22, 0.58, 0.20), skew=1.3624),
+    "a0-d3":    dict(n_mes=210, n_bar=0, mix=(0.30, 0.55, 0.15), skew=1.4745),
+    "f0":       dict(n_mes=765, n_bar=0, mix=(0.82, 0.15, 0.03), skew=1.3304),
+    "roper":    dict(n_mes=187, n_bar=187, mix=(0.48, 0.52), skew=1.2416),
+    "deuteron": dict(n_mes=74, n_bar=74, mix=(0.10, 0.30, 0.60), skew=1.3248),
+    "tritium":  dict(n_mes=0, n_bar=8, mix=(0.60, 0.40), skew=0.4449),
 }
 
 

@@ -128,6 +128,44 @@ def test_schedules_and_plans_match_oracle(i):
         c.set_mem_budget(None)
 
 
+from synth import corr_func as CF   # noqa: E402
+
+
+@pytest.mark.parametrize("row", sorted(CF.TABLE))
+def test_corr_func_shaped_dags_match_oracle(row):
+    """Table corr-func-shaped DAGs at 150 trees: DAG statistics, every schedule
+    and its memory simulation against the oracle (with the incremental Tree
+    gains checked against recomputed ones at every selection)."""
+    wl = CF.corr_func_like(row, n_trees=150)
+    for lf in wl.leaves:
+        lf.nvec = 3
+    d = OD.build(wl.leaves, wl.graphs)
+    c = ctx_for(wl)
+    st, ref = c.dag_stats(), OD.stats(d)
+    assert (st["n_vertices"], st["n_edges"], st["n_trees"]) == (ref["n_nodes"], ref["n_edges"], ref["n_trees"])
+    assert abs(st["f_v"] - ref["f_v"]) < 1e-12 and abs(st["f_e"] - ref["f_e"]) < 1e-12
+    for policy in ("input", "sibling", "tree"):
+        order = [int(x) for x in c.schedule(policy, check=(policy == "tree"))]
+        assert order == OS.schedule(d, policy), policy
+        M, pp, pl = c.memsim(order, 16)
+        sim = OS.memsim(d, order, 16)
+        assert list(M) == sim["M"] and pp == sim["peak_post"] and pl == sim["peak_live"]
+
+
+def test_corr_func_shapes_reach_the_table_sizes():
+    """The generators reproduce the table's tree count and leaf count exactly
+    and its vertex count within 0.1 % (full size; structure only)."""
+    for row in ("a0-d3", "tritium"):
+        tab = CF.TABLE[row]
+        wl = CF.corr_func_like(row)
+        assert len(wl.graphs) == tab["trees"]
+        assert len(wl.leaves) == tab["V"] - tab["E"] // 2
+        c = ctx_for(wl)
+        st = c.dag_stats()
+        assert abs(st["n_vertices"] - tab["V"]) <= 0.001 * tab["V"], (row, st)
+        assert st["n_edges"] == 2 * (st["n_vertices"] - len(wl.leaves))
+
+
 def test_mixed_precision_plans_halve_sizes():
     wl = WORKLOADS[3]
     d = OD.build(wl.leaves, wl.graphs)
