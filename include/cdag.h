@@ -50,8 +50,14 @@ enum cdag_status {
  *   K32: O[i,j,l] = sum_k  X[i,j,k] Y[k,l]       baryon x meson,  O(N^4)
  *   K33: O[i,m]   = sum_jl X[i,j,l] Y[j,l,m]     baryon x baryon, O(N^4)
  *   HCA: C        = sum_ij P[i,j]   Q[j,i]       root "contract all" (trace)
- * (the hadron exterior contraction and contract-all operations of Sec. IV-B). */
-enum cdag_kind { CDAG_K22 = 0, CDAG_K32 = 1, CDAG_K33 = 2, CDAG_HCA = 3 };
+ *   C1, C2, C3: the last c = 1, 2, 3 axes of X against the first c axes of
+ *        Y, for operand and output ranks 2..4, e.g. C1 on two rank-3 tensors
+ *        O[i,j,l,m] = sum_k X[i,j,k] Y[k,l,m] (rank 4, O(N^5)).  A C1 on ranks
+ *        (2,2) or (3,2) and a C2 on (3,3) is stored as K22, K32 or K33.
+ * (the hadron exterior contraction and contract-all operations of Sec. IV-B;
+ * the general kinds give the rank-4 intermediates of larger systems). */
+enum cdag_kind { CDAG_K22 = 0, CDAG_K32 = 1, CDAG_K33 = 2, CDAG_HCA = 3,
+                 CDAG_C1 = 4, CDAG_C2 = 5, CDAG_C3 = 6 };
 
 /* Schedulers: input order (each graph's tree in post-order, left first),
  * Sibling (Sec. III-A, Algs. 1-3), Tree (Sec. III-B, Algs. 4-8). */
@@ -72,8 +78,8 @@ enum cdag_prec { CDAG_FP64 = 0, CDAG_FP32 = 1, CDAG_BF16X3 = 2 };
 enum cdag_plan_op { CDAG_OP_D2H = 0, CDAG_OP_DROP = 1, CDAG_OP_H2D = 2,
                     CDAG_OP_ALLOC = 3, CDAG_OP_EXEC = 4, CDAG_OP_FREE = 5 };
 
-/* A leaf tensor (hadron node): complex, shape [nt][nvec]^rank, rank 2 (meson)
- * or 3 (baryon).  host: interleaved (re, im) in row-major order, complex128
+/* A leaf tensor (hadron node): complex, shape [nt][nvec]^rank, rank 2 (meson),
+ * 3 (baryon) or 4.  host: interleaved (re, im) in row-major order, complex128
  * (dtype CDAG_C128, doubles) or complex64 (dtype CDAG_C64, floats), read only
  * during build_cdag (the library keeps its own copy in that dtype); may be
  * NULL for a structure-only context (scheduling and planning work; execute
@@ -150,8 +156,10 @@ const char* cdag_last_error(void);
 /* Merge graphs into the DAG (hash-consing identical (kind, left, right)
  * contractions; identical graphs share their root).  Node ids: leaves
  * 0..n_leaves-1, then contractions in order of first appearance.
- * CDAG_E_INVALID: bad shape, rank, N or Nt mismatch, operand out of range or
- * forward, identical operands, root not HCA or HCA not last, unused op. */
+ * CDAG_E_INVALID: bad shape, rank (operands and outputs 2..4; HCA on two
+ * rank-2 operands), N or Nt mismatch, a GEMM dimension (N^(free or
+ * contracted axes)) above 2^31, operand out of range or forward, identical
+ * operands, root not HCA or HCA not last, unused op. */
 int build_cdag(cdag_ctx* c, const cdag_leaf* leaves, int64_t n_leaves,
                const cdag_graph* graphs, int64_t n_graphs);
 
@@ -185,7 +193,8 @@ int cdag_set_timing(cdag_ctx* c, int timing);
  * *n_out (nullable) receives the count; at most cap records are written. */
 int cdag_launch_records(cdag_ctx* c, cdag_launch_record* out, int64_t cap, int64_t* n_out);
 
-/* Kernel variant of the exterior contractions of `kind` (K22, K32 or K33)
+/* Kernel variant of the exterior contractions of `kind` (K22, K32, K33, C1,
+ * C2 or C3; a general kind shares one entry over all its operand ranks)
  * with N = nvec in precision `prec`.  tile: 0 = 64x64, 1 = 32x32, 2 = 48x48,
  * 3 = 128x64, 4 = 64x32 (output rows x columns per workgroup), -1 removes an
  * explicit choice.  grid: 0 = persistent (compute units x occupancy

@@ -16,9 +16,36 @@ from typing import Dict, List, Tuple
 
 LEAF, INTERIOR, ROOT = "LEAF", "INTERIOR", "ROOT"
 K22, K32, K33, HCA = 0, 1, 2, 3
+# General contractions of the last c axes of the left operand with the first c
+# axes of the right one (c = 1, 2, 3), for operand and output ranks 2..4.
+C1, C2, C3 = 4, 5, 6
+MIN_RANK, MAX_RANK = 2, 4
 
-# (left rank, right rank) -> output rank, per kind; HCA outputs a scalar per t.
+# (left rank, right rank) -> output rank, per named kind; HCA outputs a scalar per t.
 _RANKS = {K22: ((2, 2), 2), K32: ((3, 2), 3), K33: ((3, 3), 2), HCA: ((2, 2), 0)}
+# The named kinds are the general contractions with these (left rank, right rank, c).
+_NAMED = {(2, 2, 1): K22, (3, 2, 1): K32, (3, 3, 2): K33}
+
+
+def contracted_axes(kind: int) -> int:
+    """c of a (named or general) exterior contraction."""
+    return {K22: 1, K32: 1, K33: 2, C1: 1, C2: 2, C3: 3}[kind]
+
+
+def normalize(kind: int, rl: int, rr: int):
+    """(kind, output rank) of an exterior contraction of operands of ranks rl, rr:
+    a general kind that equals a named one becomes the named kind.  Raises
+    InvalidGraph when the ranks do not fit the kind."""
+    if kind in (C1, C2, C3):
+        c = contracted_axes(kind)
+        ro = rl + rr - 2 * c
+        if not (MIN_RANK <= rl <= MAX_RANK and MIN_RANK <= rr <= MAX_RANK and MIN_RANK <= ro <= MAX_RANK):
+            raise InvalidGraph("operand or output rank out of range")
+        return _NAMED.get((rl, rr, c), kind), ro
+    (el, er), ro = _RANKS[kind]
+    if (rl, rr) != (el, er):
+        raise InvalidGraph("operand rank mismatch")
+    return kind, ro
 
 
 class InvalidGraph(ValueError):
@@ -89,7 +116,7 @@ def build(leaves, graphs) -> Dag:
     """
     d = Dag(n_leaves=len(leaves))
     for lf in leaves:
-        if lf.rank not in (2, 3) or lf.nvec < 1 or lf.nt < 1:
+        if not MIN_RANK <= lf.rank <= MAX_RANK or lf.nvec < 1 or lf.nt < 1:
             raise InvalidGraph("bad leaf shape")
         d.kind.append(-1)
         d.left.append(-1)
@@ -107,7 +134,7 @@ def build(leaves, graphs) -> Dag:
         local: List[int] = []
         consumed = [0] * len(ops)
         for oi, (kind, l, r) in enumerate(ops):
-            if kind not in _RANKS:
+            if kind not in _RANKS and kind not in (C1, C2, C3):
                 raise InvalidGraph("bad kind")
             if (kind == HCA) != (oi == len(ops) - 1):
                 raise InvalidGraph("the root, and only the root, must be a trace")
@@ -126,9 +153,7 @@ def build(leaves, graphs) -> Dag:
             lid, rid = ids
             if lid == rid:
                 raise InvalidGraph("identical operands")
-            (rl, rr), ro = _RANKS[kind]
-            if d.rank[lid] != rl or d.rank[rid] != rr:
-                raise InvalidGraph("operand rank mismatch")
+            kind, ro = normalize(kind, d.rank[lid], d.rank[rid])
             if d.nvec[lid] != d.nvec[rid] or d.nt[lid] != d.nt[rid]:
                 raise InvalidGraph("operand N or Nt mismatch")
             key = (kind, lid, rid)

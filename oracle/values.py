@@ -13,6 +13,10 @@ the paper states for meson and baryon systems):
   K32: O[i,j,l] = sum_k  X[i,j,k] Y[k,l]
   K33: O[i,m]   = sum_jl X[i,j,l] Y[j,l,m]
   HCA: C        = sum_ij P[i,j]   Q[j,i]       (the root's "contract all")
+  C1, C2, C3: the last c = 1, 2, 3 axes of X against the first c axes of Y,
+       e.g. C1 on two rank-3 tensors: O[i,j,l,m] = sum_k X[i,j,k] Y[k,l,m]
+       (rank 4, O(N^5) per time slice); K22, K32 and K33 are C1, C1 and C2
+       on ranks (2,2), (3,2) and (3,3).
 The cross-diagram sum of a correlator c is S_c(t) = sum_{g in c} w_g C_g(t),
 taken as a correctly rounded sum (math.fsum) of the FP64 terms.
 """
@@ -24,32 +28,34 @@ from typing import Dict, List, Sequence
 import numpy as np
 
 K22, K32, K33, HCA = 0, 1, 2, 3
+C1, C2, C3 = 4, 5, 6
+_AXES = {K22: 1, K32: 1, K33: 2, C1: 1, C2: 2, C3: 3}
 
 
 def contract(kind: int, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
     """One binary contraction batched over the leading t axis, in complex128.
 
     A batched matrix product (numpy.matmul) is the library primitive; the
-    reshapes only group the contracted and free axes of the definitions above."""
-    nt = X.shape[0]
-    if kind == K22:
-        return np.matmul(X, Y)
-    if kind == K32:
-        n = X.shape[1]
-        return np.matmul(X.reshape(nt, n * n, n), Y).reshape(nt, n, n, n)
-    if kind == K33:
-        n = X.shape[1]
-        return np.matmul(X.reshape(nt, n, n * n), Y.reshape(nt, n * n, n))
+    reshapes only group the free and contracted axes of the definitions above
+    (free axes of X, then the c contracted ones; contracted axes of Y, then its
+    free ones)."""
     if kind == HCA:
         return np.einsum("tij,tji->t", X, Y)
-    raise KeyError(kind)
+    nt, n = X.shape[0], X.shape[1]
+    c = _AXES[kind]
+    rl, rr = X.ndim - 1, Y.ndim - 1
+    out = np.matmul(X.reshape(nt, n ** (rl - c), n ** c), Y.reshape(nt, n ** c, n ** (rr - c)))
+    return out.reshape((nt,) + (n,) * (rl + rr - 2 * c))
 
 
 def contract_einsum(kind: int, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
     """The same definitions written as plain einsum index strings (small inputs)."""
-    spec = {K22: "tik,tkj->tij", K32: "tijk,tkl->tijl", K33: "tijl,tjlm->tim",
-            HCA: "tij,tji->t"}[kind]
-    return np.einsum(spec, X, Y)
+    if kind == HCA:
+        return np.einsum("tij,tji->t", X, Y)
+    c = _AXES[kind]
+    rl, rr = X.ndim - 1, Y.ndim - 1
+    free_l, summed, free_r = "abcd"[:rl - c], "efg"[:c], "hijk"[:rr - c]
+    return np.einsum(f"t{free_l}{summed},t{summed}{free_r}->t{free_l}{free_r}", X, Y)
 
 
 def evaluate_graph(leaves: Sequence[np.ndarray], ops) -> np.ndarray:

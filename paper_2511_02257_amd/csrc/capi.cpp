@@ -223,7 +223,8 @@ int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile, int grid,
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {
     elem_bytes_prec(prec);
-    need(kind >= CDAG_K22 && kind <= CDAG_K33, CDAG_E_INVALID, "kind must be K22, K32 or K33");
+    need(kind >= CDAG_K22 && kind <= CDAG_C3 && kind != CDAG_HCA, CDAG_E_INVALID,
+         "kind must be an exterior contraction (K22, K32, K33, C1, C2, C3)");
     need(nvec >= 1, CDAG_E_INVALID, "nvec must be >= 1");
     need(tile >= -1 && tile < cdag::kNumTiles, CDAG_E_INVALID, "tile out of range");
     need(grid >= 0 && grid < cdag::kNumGrids, CDAG_E_INVALID, "grid must be 0 or 1");

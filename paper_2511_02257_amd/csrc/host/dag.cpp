@@ -1,6 +1,7 @@
 // CDAG formation (Sec. II-B): merge binary contraction trees into one DAG by
 // hash-consing structurally identical contractions.
 #include <algorithm>
+#include <climits>
 #include <unordered_map>
 
 #include "host.hpp"
@@ -18,15 +19,10 @@ struct KeyHash {
   }
 };
 
-// (left rank, right rank, output rank) per kind.
-bool kind_ranks(int32_t kind, int& rl, int& rr, int& ro) {
-  switch (kind) {
-    case K22: rl = 2; rr = 2; ro = 2; return true;
-    case K32: rl = 3; rr = 2; ro = 3; return true;
-    case K33: rl = 3; rr = 3; ro = 2; return true;
-    case HCA: rl = 2; rr = 2; ro = 0; return true;
-    default: return false;
-  }
+int64_t ipow(int64_t n, int e) {
+  int64_t r = 1;
+  for (int i = 0; i < e; ++i) r *= n;
+  return r;
 }
 
 [[noreturn]] void invalid(const std::string& m) { throw Error(CDAG_E_INVALID, m); }
@@ -36,22 +32,28 @@ bool Dag::in_tree(int64_t u, int64_t t) const {
   return std::binary_search(ctree.begin() + ctree_off[u], ctree.begin() + ctree_off[u + 1], t);
 }
 
+void Dag::gemm_shape(int64_t u, int64_t* M, int64_t* Ncols, int64_t* K) const {
+  const int c = contracted_axes(kind[u]);
+  const int64_t n = nvec[u];
+  *M = ipow(n, rank[left[u]] - c);
+  *Ncols = ipow(n, rank[right[u]] - c);
+  *K = ipow(n, c);
+}
+
 double Dag::flops(int64_t u) const {
-  const double n = nvec[u], T = nt[u];
-  switch (kind[u]) {
-    case K22: return 8.0 * T * n * n * n;
-    case K32: return 8.0 * T * n * n * n * n;
-    case K33: return 8.0 * T * n * n * n * n;
-    case HCA: return 8.0 * T * n * n;
-    default: return 0.0;
-  }
+  if (kind[u] < 0) return 0.0;
+  if (kind[u] == HCA) return 8.0 * nt[u] * (double)nvec[u] * nvec[u];
+  int64_t M, N, K;
+  gemm_shape(u, &M, &N, &K);
+  return 8.0 * nt[u] * (double)M * (double)N * (double)K;
 }
 
 Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs) {
   Dag d;
   d.n_leaves = (int64_t)leaves.size();
   for (const auto& l : leaves) {
-    if ((l.rank != 2 && l.rank != 3) || l.nvec < 1 || l.nt < 1) invalid("leaf: rank must be 2 or 3, nvec and nt >= 1");
+    if (l.rank < kMinRank || l.rank > kMaxRank || l.nvec < 1 || l.nt < 1)
+      invalid("leaf: rank must be 2..4, nvec and nt >= 1");
     d.kind.push_back(LEAF);
     d.rank.push_back(l.rank);
     d.nvec.push_back(l.nvec);
@@ -70,9 +72,8 @@ Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs)
     consumed.assign(g.n_ops, 0);
     for (int32_t oi = 0; oi < g.n_ops; ++oi) {
       const OpIn& op = g.ops[oi];
-      int rl, rr, ro;
       std::string where = "graph " + std::to_string(gi) + " op " + std::to_string(oi) + ": ";
-      if (!kind_ranks(op.kind, rl, rr, ro)) invalid(where + "unknown kind");
+      if (op.kind < K22 || op.kind > C3) invalid(where + "unknown kind");
       if ((op.kind == HCA) != (oi == g.n_ops - 1)) invalid(where + "the root, and only the root, must be HCA");
       int64_t ids[2];
       const int32_t xs[2] = {op.left, op.right};
@@ -89,16 +90,36 @@ Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs)
         }
       }
       if (ids[0] == ids[1]) invalid(where + "identical operands");
-      if (d.rank[ids[0]] != rl || d.rank[ids[1]] != rr) invalid(where + "operand rank mismatch");
+      const int rl = d.rank[ids[0]], rr = d.rank[ids[1]];
+      int32_t kind = op.kind;
+      int ro;
+      if (kind == HCA) {
+        if (rl != 2 || rr != 2) invalid(where + "operand rank mismatch");
+        ro = 0;
+      } else {
+        const int c = contracted_axes(kind);
+        ro = rl + rr - 2 * c;
+        if (kind == K22 && (rl != 2 || rr != 2)) invalid(where + "operand rank mismatch");
+        if (kind == K32 && (rl != 3 || rr != 2)) invalid(where + "operand rank mismatch");
+        if (kind == K33 && (rl != 3 || rr != 3)) invalid(where + "operand rank mismatch");
+        if (ro < kMinRank || ro > kMaxRank) invalid(where + "output rank out of range");
+        const int64_t n = d.nvec[ids[0]];
+        if (ipow(n, std::max(std::max(rl - c, rr - c), c)) > (int64_t)INT32_MAX)
+          invalid(where + "a GEMM dimension of the contraction exceeds 2^31");
+        // a general contraction with the ranks of a named kind is that kind
+        if (kind == C1 && rl == 2 && rr == 2) kind = K22;
+        if (kind == C1 && rl == 3 && rr == 2) kind = K32;
+        if (kind == C2 && rl == 3 && rr == 3) kind = K33;
+      }
       if (d.nvec[ids[0]] != d.nvec[ids[1]] || d.nt[ids[0]] != d.nt[ids[1]])
         invalid(where + "operand N or Nt mismatch");
-      auto key = std::make_tuple(op.kind, ids[0], ids[1]);
+      auto key = std::make_tuple(kind, ids[0], ids[1]);
       auto it = table.find(key);
       int64_t u;
       if (it == table.end()) {
         u = d.n_nodes();
         table.emplace(key, u);
-        d.kind.push_back(op.kind);
+        d.kind.push_back(kind);
         d.rank.push_back(ro);
         d.nvec.push_back(d.nvec[ids[0]]);
         d.nt.push_back(d.nt[ids[0]]);

@@ -10,7 +10,20 @@
 
 namespace cdag {
 
-enum Kind : int32_t { K22 = 0, K32 = 1, K33 = 2, HCA = 3, LEAF = -1 };
+// Named kinds K22, K32, K33 and the general contractions C1, C2, C3 of the
+// last c axes of the left operand with the first c axes of the right one
+// (operand and output ranks 2..4); a general contraction with the ranks of a
+// named kind is stored as that kind.
+enum Kind : int32_t { K22 = 0, K32 = 1, K33 = 2, HCA = 3, C1 = 4, C2 = 5, C3 = 6, LEAF = -1 };
+constexpr int kMinRank = 2, kMaxRank = 4;
+inline int contracted_axes(int kind) {
+  switch (kind) {
+    case K22: case K32: case C1: return 1;
+    case K33: case C2: return 2;
+    case C3: return 3;
+    default: return 0;
+  }
+}
 
 struct Error : std::runtime_error {
   int code;
@@ -46,6 +59,9 @@ struct Dag {
   bool in_tree(int64_t u, int64_t t) const;   // binary search in ctree(u)
   // Algorithmic flops of contraction u (8 per complex multiply-add).
   double flops(int64_t u) const;
+  // Exterior contraction u as a complex GEMM per time slice: M = N^(rl - c),
+  // Ncols = N^(rr - c), K = N^c for operand ranks rl, rr and c contracted axes.
+  void gemm_shape(int64_t u, int64_t* M, int64_t* Ncols, int64_t* K) const;
 };
 
 struct LeafIn { int32_t rank, nvec, nt; };

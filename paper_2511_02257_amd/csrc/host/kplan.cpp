@@ -2,6 +2,7 @@
 #include "kplan.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 
 #include "../../../include/cdag.h"
@@ -22,25 +23,33 @@ int64_t put(std::vector<uint8_t>& blob, const T& v) {
 
 int64_t elem_bytes_of(int prec) { return prec == CDAG_FP64 ? 16 : 8; }
 
-void gemm_dims(const Dag& d, int64_t u, int32_t* M, int32_t* N, int32_t* K) {
-  const int32_t n = d.nvec[u];
-  switch (d.kind[u]) {
-    case K22: *M = n; *N = n; *K = n; break;
-    case K32: *M = n * n; *N = n; *K = n; break;
-    case K33: *M = n; *N = n; *K = n * n; break;
-    default: *M = *N = *K = 0; break;
+std::map<std::pair<int, int>, TuneShape> tune_shapes(const Dag& d) {
+  std::map<std::pair<int, int>, TuneShape> out;
+  for (int64_t u = d.n_leaves; u < d.n_nodes(); ++u) {
+    if (d.kind[u] == HCA) continue;
+    Gemm g;
+    d.gemm_shape(u, &g.M, &g.N, &g.K);
+    auto it = out.find({d.kind[u], d.nvec[u]});
+    if (it == out.end()) {
+      out[{d.kind[u], d.nvec[u]}] = {d.nt[u], g};
+      continue;
+    }
+    TuneShape& t = it->second;
+    t.nt = std::max(t.nt, (int)d.nt[u]);
+    if ((double)g.M * g.N * g.K > (double)t.gemm.M * t.gemm.N * t.gemm.K) t.gemm = g;
   }
+  return out;
 }
 
-void decompose(int kind, int n, int nt, int choice, int prec, HecDesc* h) {
+void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h) {
   if (choice < 0 || choice >= kNumChoices) throw std::invalid_argument("kernel choice out of range");
+  if (g.M > INT32_MAX || g.N > INT32_MAX || g.K > INT32_MAX)
+    throw Error(CDAG_E_INVALID, "contraction dimensions exceed 2^31");
   const int variant = choice_variant(choice);
   const int ks = k_step(prec);
-  switch (kind) {
-    case K22: h->M = n; h->N = n; h->K = n; break;
-    case K32: h->M = n * n; h->N = n; h->K = n; break;
-    default: h->M = n; h->N = n; h->K = n * n; break;
-  }
+  h->M = (int32_t)g.M;
+  h->N = (int32_t)g.N;
+  h->K = (int32_t)g.K;
   const TileShape& ts = kTileShapes[variant_tile(variant)];
   h->nt = nt;
   h->tiles_m = (h->M + ts.bm - 1) / ts.bm;
@@ -101,7 +110,9 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
     return it != tiles.end() ? it->second : default_tile(prec, d.kind[u], d.nvec[u]);
   };
   auto decomp = [&](int64_t u, HecDesc& h) {
-    decompose(d.kind[u], d.nvec[u], d.nt[u], tile_of(u), prec, &h);
+    Gemm g;
+    d.gemm_shape(u, &g.M, &g.N, &g.K);
+    decompose(g, d.nt[u], tile_of(u), prec, &h);
   };
 
   // pass 1: workspace size (max over steps) and descriptor counts

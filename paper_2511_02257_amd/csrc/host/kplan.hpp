@@ -51,9 +51,16 @@ inline bool choice_split_k(int c) { return c < kNumVariants; }
 // ABI or by the autotuner) wins, else default_tile().
 using TileTable = std::map<std::tuple<int, int, int>, int>;
 int default_tile(int prec, int kind, int n);   // returns a choice
-// GEMM dimensions, tile counts and split-K of one contraction of `kind` with
-// N = n, nt time slices and kernel `choice` (offsets and tile_begin unset).
-void decompose(int kind, int n, int nt, int choice, int prec, HecDesc* h);
+// Complex GEMM per time slice of an exterior contraction (Dag::gemm_shape).
+struct Gemm { int64_t M, N, K; };
+// GEMM dimensions, tile counts and split-K of one contraction with GEMM g, nt
+// time slices and kernel `choice` (offsets and tile_begin unset).
+void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h);
+// Distinct (kind, N) among the exterior contractions of d (the keys of the
+// kernel-choice table), each with its largest Nt and its largest GEMM (a
+// general kind can occur with several operand ranks).
+struct TuneShape { int nt; Gemm gemm; };
+std::map<std::pair<int, int>, TuneShape> tune_shapes(const Dag& d);
 // k-step of the matrix-core kernels: FP64 and FP32 use 16, split-BF16 32.
 inline int k_step(int prec) { return prec == 2 ? 32 : 16; }
 // Split-K: aim for at least this many work items per contraction, keeping at
@@ -83,7 +90,6 @@ struct KernelPlan {
 };
 
 int64_t elem_bytes_of(int prec);                 // 16 for FP64, 8 otherwise
-void gemm_dims(const Dag& d, int64_t u, int32_t* M, int32_t* N, int32_t* K);
 KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTable& tiles);
 
 }  // namespace cdag

@@ -298,12 +298,7 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
   const int64_t eb = prec == CDAG_FP64 ? 16 : 8, acc = prec == CDAG_FP64 ? 8 : 4;
   auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
   const int64_t lo = al(p.leaf_region_bytes), hi = kp.ws_off + kp.ws_bytes;
-  std::map<std::pair<int, int>, int> shapes;   // (kind, n) -> largest nt
-  for (int64_t u = c.dag.n_leaves; u < c.dag.n_nodes(); ++u)
-    if (c.dag.kind[u] != HCA) {
-      int& nt = shapes[{c.dag.kind[u], c.dag.nvec[u]}];
-      nt = std::max(nt, (int)c.dag.nt[u]);
-    }
+  const auto shapes = tune_shapes(c.dag);
   hipEvent_t e0, e1;
   HIPC(hipEventCreate(&e0));
   HIPC(hipEventCreate(&e1));
@@ -313,12 +308,13 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
       const int kind = sh.first.first, n = sh.first.second;
       double best = 1e300;
       int best_tile = -1;
+      const int snt = sh.second.nt;
       for (int ch = 0; ch < kNumChoices; ++ch) {
         HecDesc h{};
-        decompose(kind, n, sh.second, ch, prec, &h);   // split count of a real contraction
+        decompose(sh.second.gemm, snt, ch, prec, &h);   // split count of a real contraction
         if (!choice_split_k(ch)) {
           HecDesc a{};
-          decompose(kind, n, sh.second, choice_variant(ch), prec, &a);
+          decompose(sh.second.gemm, snt, choice_variant(ch), prec, &a);
           if (a.splits == 1) continue;                  // same work items as the split choice
         }
         const int64_t slice_items = (int64_t)h.tiles_m * h.tiles_n * h.splits;
@@ -326,8 +322,8 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
         const int64_t wslice = h.splits > 1 ? (int64_t)h.splits * 2 * h.M * h.N * acc : 0;
         // A wave holds many contractions of one shape: time a batch of slices
         // with at least 4096 work items (at most 64 contractions' worth).
-        int64_t want = std::max<int64_t>(sh.second, (4096 + slice_items - 1) / slice_items);
-        want = std::min<int64_t>(want, 64LL * sh.second);
+        int64_t want = std::max<int64_t>(snt, (4096 + slice_items - 1) / slice_items);
+        want = std::min<int64_t>(want, 64LL * snt);
         int64_t nt = std::min<int64_t>(want, (hi - lo - 4096) / std::max<int64_t>(1, slice + wslice + 1024));
         if (nt < 1 || nt * slice_items > INT32_MAX) continue;
         h.nt = (int32_t)nt;
@@ -383,12 +379,7 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
 // variant with the least summed time of exterior contractions plus split-K
 // reductions.
 int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
-  std::map<std::pair<int, int>, int> shapes;   // (kind, n) -> largest nt
-  for (int64_t u = c.dag.n_leaves; u < c.dag.n_nodes(); ++u)
-    if (c.dag.kind[u] != HCA) {
-      int& nt = shapes[{c.dag.kind[u], c.dag.nvec[u]}];
-      nt = std::max(nt, (int)c.dag.nt[u]);
-    }
+  const auto shapes = tune_shapes(c.dag);
   const bool timing = c.timing;
   c.timing = true;
   int64_t tuned = 0;
@@ -401,7 +392,7 @@ int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
         if (!choice_split_k(v)) {
           // the no-split setting only differs where the rule would split
           HecDesc h{};
-          decompose(sh.first.first, sh.first.second, sh.second, choice_variant(v), prec, &h);
+          decompose(sh.second.gemm, sh.second.nt, choice_variant(v), prec, &h);
           if (h.splits == 1) continue;
         }
         c.tiles[key] = v;

@@ -10,7 +10,7 @@ and about the same number of merged contractions, and report the F_v and F_e
 they reach.  Structure only: no tensor data, no method arithmetic.
 
 Each system uses tree templates over meson leaves (rank 2) and baryon leaves
-(rank 3) with the engine's kinds (K22, K32, K33, HCA):
+(rank 3) with the engine's kinds (K22, K32, K33, the general C1 and C2, HCA):
 
   MxM, MxMxM  meson rings tr(A_1 ... A_L), products built left to right, so
               rings that share a prefix share its product.
@@ -18,9 +18,9 @@ Each system uses tree templates over meson leaves (rank 2) and baryon leaves
   BxB         two baryon pairs K33(B, B'), one side optionally through K32
               with a meson first, the other optionally closed by a meson,
               then HCA.
-  BxBxB       baryon pairs folded into further baryons through K32 and K33,
-              two such chains closed by HCA (the paper's O(N^5) rank-4 step is
-              outside the engine's kinds, so this system stays O(N^4)).
+  BxBxB       two baryons contracted over one index into a rank-4 tensor
+              (C1, the O(N^5) step), folded with a third and a fourth baryon
+              (C2, K33); the other side a baryon pair or the same chain; HCA.
 The template mix sets the mean tree size to the row's F_v |V| / k.
 
 Sharing comes from skewed leaf draws: leaf i of a system is drawn with weight
@@ -34,7 +34,7 @@ from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
-from .workloads import GraphSpec, K22, K32, K33, HCA, Leaf, Workload
+from .workloads import GraphSpec, K22, K32, K33, HCA, C1, C2, Leaf, Workload
 
 # Table corr-func: system, #trees, N, #vertices, #edges, F_v, F_e.
 TABLE = {
@@ -54,7 +54,7 @@ PARAMS: Dict[str, dict] = {
     "f0":       dict(n_mes=765, n_bar=0, mix=(0.82, 0.15, 0.03), skew=1.3304),
     "roper":    dict(n_mes=187, n_bar=187, mix=(0.48, 0.52), skew=1.2416),
     "deuteron": dict(n_mes=74, n_bar=74, mix=(0.10, 0.30, 0.60), skew=1.3248),
-    "tritium":  dict(n_mes=0, n_bar=8, mix=(0.60, 0.40), skew=0.4449),
+    "tritium":  dict(n_mes=0, n_bar=8, mix=(0.60, 0.40), skew=0.5226),
 }
 
 
@@ -127,16 +127,18 @@ def _graph(system: str, mix, mes: Optional[_Draw], bar: Optional[_Draw], rg) -> 
         return GraphSpec(ops)
     if system == "BxBxB":
         b = bar.pick(6 + 2 * t)
-        ops.append((K33, b[0], b[1]))            # pair 1 -> rank 2
-        ops.append((K32, b[2], -1))              # folded into a third baryon -> rank 3
+        ops.append((C1, b[0], b[1]))             # two baryons over one index -> rank 4, O(N^5)
+        ops.append((C2, -1, b[2]))               # a third baryon over two indices -> rank 3
         ops.append((K33, -2, b[3]))              # -> rank 2
         x = -3
-        ops.append((K33, b[4], b[5]))            # pair 2
-        y = -4
-        if t == 1:                               # pair 2 folded the same way
-            ops.append((K32, b[6], y))
-            ops.append((K33, -len(ops), b[7]))
-            y = -len(ops)
+        if t == 0:
+            ops.append((K33, b[4], b[5]))        # a baryon pair -> rank 2
+            y = -4
+        else:                                    # the second side through rank 4 as well
+            ops.append((C1, b[4], b[5]))
+            ops.append((C2, -4, b[6]))
+            ops.append((K33, -5, b[7]))
+            y = -6
         ops.append((HCA, x, y))
         return GraphSpec(ops)
     raise KeyError(system)

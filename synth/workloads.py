@@ -27,7 +27,8 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 K22, K32, K33, HCA = 0, 1, 2, 3
-KIND_NAMES = {K22: "K22", K32: "K32", K33: "K33", HCA: "HCA"}
+C1, C2, C3 = 4, 5, 6      # general: last c axes of X against the first c of Y
+KIND_NAMES = {K22: "K22", K32: "K32", K33: "K33", HCA: "HCA", C1: "C1", C2: "C2", C3: "C3"}
 
 
 @dataclass
@@ -185,6 +186,45 @@ def fig1_dag(order: str = "fgh", nvec=4, nt=1, seed=7, with_data=True) -> Worklo
     }
     return Workload("fig1_" + order, leaves, [spec[ch] for ch in order],
                     meta=dict(seed=seed, kind="fig1"))
+
+
+def _rank4_graph(rg, bar: List[int], mes: List[int], r4: List[int], n_corr: int) -> GraphSpec:
+    """One graph through a rank-4 intermediate; four templates (a..d distinct):
+      0: HCA(K33(C2(C1(B_a, B_b), B_c), B_d), M_e)     rank 4 -> 3 -> 2
+      1: HCA(C3(C1(B_a, B_b), R_c), M_e)               rank 4 with a rank-4 leaf -> 2
+      2: HCA(K33(C1(M_e, B_a), B_b), M_f)              C1 on ranks (2, 3) -> 3 -> 2
+      3: HCA(C2(R_c, M_e), M_f)                        rank-4 leaf against a meson -> 2"""
+    t = int(rg.integers(0, 4))
+    b = [bar[int(i)] for i in rg.choice(len(bar), size=4, replace=False)]
+    m = [mes[int(i)] for i in rg.choice(len(mes), size=2, replace=False)]
+    r = r4[int(rg.integers(0, len(r4)))]
+    if t == 0:
+        ops = [(C1, b[0], b[1]), (C2, -1, b[2]), (K33, -2, b[3]), (HCA, -3, m[0])]
+    elif t == 1:
+        ops = [(C1, b[0], b[1]), (C3, -1, r), (HCA, -2, m[0])]
+    elif t == 2:
+        ops = [(C1, m[0], b[0]), (K33, -1, b[1]), (HCA, -2, m[1])]
+    else:
+        ops = [(C2, r, m[0]), (HCA, -1, m[1])]
+    corr = int(rg.integers(0, n_corr))
+    w = float(rg.choice(np.array([-1.0, 1.0])))
+    return GraphSpec(ops, corr, w)
+
+
+def rank4_mix(n_bar=5, n_mes=4, n_r4=2, nvec=6, nt=3, n_graphs=24, sigma=None, n_corr=2, seed=1006,
+              with_data=True, name="rank4") -> Workload:
+    """Graphs with rank-4 intermediates and rank-4 leaves through the general
+    contractions C1, C2, C3 (tritium-like O(N^5) steps); entries N(0,1)/N."""
+    rt, rg = _streams(seed)
+    sg = 1.0 / nvec if sigma is None else sigma
+    leaves = [_leaf(rt, 3, nvec, nt, sg, with_data) for _ in range(n_bar)]
+    leaves += [_leaf(rt, 2, nvec, nt, sg, with_data) for _ in range(n_mes)]
+    leaves += [_leaf(rt, 4, nvec, nt, sg, with_data) for _ in range(n_r4)]
+    bar = list(range(n_bar))
+    mes = list(range(n_bar, n_bar + n_mes))
+    r4 = list(range(n_bar + n_mes, n_bar + n_mes + n_r4))
+    graphs = [_rank4_graph(rg, bar, mes, r4, n_corr) for _ in range(n_graphs)]
+    return Workload(name, leaves, graphs, meta=dict(seed=seed, kind="rank4"))
 
 
 BATCHED_NVECS = (32, 48, 64, 96, 128)

@@ -22,13 +22,13 @@ def run(wl, policy="tree", prec="fp64", batched=False, budget=None, leaves_resid
                     wave_lookahead=wave_lookahead, use_graphs=use_graphs)
     if tile is not None:
         for lf_n in {lf.nvec for lf in wl.leaves}:
-            for kind in (0, 1, 2):
+            for kind in (0, 1, 2, 4, 5, 6):
                 ctx.set_tile(prec, kind, lf_n, tile, grid, lds_stages, split_k)
     runner = DeviceRunner(ctx, device)
     tuned = None
     if autotune:
         runner.autotune(prec, batched, reps=2, in_situ=in_situ)
-        tuned = {(k, n): ctx.get_tile(prec, k, n) for n in {lf.nvec for lf in wl.leaves} for k in (0, 1, 2)}
+        tuned = {(k, n): ctx.get_tile(prec, k, n) for n in {lf.nvec for lf in wl.leaves} for k in (0, 1, 2, 4, 5, 6)}
     st = runner.run(prec, batched)
     corr = ctx.fetch_correlators()
     sums = ctx.fetch_sums()

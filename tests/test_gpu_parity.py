@@ -32,6 +32,19 @@ def _wl_baryon_small():
                         seed=12, name="baryon_small")
 
 
+def _wl_rank4_small():
+    # N = 10: rank-4 intermediates (C1 on two baryons, GEMM 100 x 100 x 10),
+    # C2 of rank 4 x 3 (100 x 10 x 100) and C3 of rank 4 x 4 (10 x 10 x 1000,
+    # split-K with a ragged tail); ragged tiles everywhere
+    return W.rank4_mix(n_bar=5, n_mes=4, n_r4=2, nvec=10, nt=3, n_graphs=24, seed=14, name="rank4_small")
+
+
+@pytest.fixture(scope="module")
+def rank4_small():
+    wl = _wl_rank4_small()
+    return wl, OV.correlators(wl)
+
+
 @pytest.fixture(scope="module")
 def tiny():
     wl = W.config("tiny")
@@ -139,6 +152,31 @@ def test_without_split_k(baryon_small, prec):
         assert err.max() <= TOL[prec]
     assert np.array_equal(np.concatenate(a["corr"]).view(np.uint64),
                           np.concatenate(b["corr"]).view(np.uint64))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_rank4_general_contractions(rank4_small, prec):
+    """General contractions through rank-4 intermediates: every schedule and
+    batching mode, with and without split-K, against the oracle."""
+    wl, ref = rank4_small
+    from oracle import dag as OD
+    d = OD.build(wl.leaves, wl.graphs)
+    assert {W.C1, W.C2, W.C3} <= set(d.kind)
+    base = None
+    for policy, batched in (("input", False), ("tree", True), ("sibling", True)):
+        r = run(wl, policy, prec, batched)
+        err = rel_errors(r["corr"], ref)
+        print(f"rank4_small {prec} {policy} batched={batched}: max rel {err.max():.3e}")
+        assert err.max() <= TOL[prec]
+        assert sum_errors(wl, r["sums"], ref) <= TOL[prec]
+        bits = np.concatenate(r["corr"]).view(np.uint64)
+        if base is None:
+            base = bits
+        assert np.array_equal(bits, base)
+    r = run(wl, "tree", prec, True, tile=1, grid=0, lds_stages=1, split_k=0)
+    err = rel_errors(r["corr"], ref)
+    print(f"rank4_small {prec} 32x32 persistent, no split-K: max rel {err.max():.3e}")
+    assert err.max() <= TOL[prec]
 
 
 @pytest.mark.parametrize("in_situ", [False, True])

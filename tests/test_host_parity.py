@@ -81,6 +81,8 @@ def _random_workloads():
     for seed in range(6):
         out.append(W.batched_mix(nvecs=(2, 3), nt=2, n_mes=6, n_bar=4, n_graphs=30, seed=200 + seed,
                                  with_data=False))
+    for seed in range(10):
+        out.append(W.rank4_mix(nvec=3, nt=2, n_graphs=16, seed=300 + seed, with_data=False))
     return out
 
 
@@ -164,6 +166,37 @@ def test_corr_func_shapes_reach_the_table_sizes():
         st = c.dag_stats()
         assert abs(st["n_vertices"] - tab["V"]) <= 0.001 * tab["V"], (row, st)
         assert st["n_edges"] == 2 * (st["n_vertices"] - len(wl.leaves))
+
+
+def test_general_kinds_flops_and_validation():
+    """Plan flops are 8 Nt M N K per exterior contraction (M = N^(rl-c),
+    N^(rr-c), K = N^c) plus 8 Nt N^2 per trace; rank rules as in the oracle."""
+    wl = W.rank4_mix(nvec=3, nt=2, n_graphs=30, seed=401, with_data=False)
+    d = OD.build(wl.leaves, wl.graphs)
+    want = 0
+    for u in range(d.n_nodes):
+        k = d.kind[u]
+        if k < 0:
+            continue
+        n, nt = d.nvec[u], d.nt[u]
+        if k == W.HCA:
+            want += 8 * nt * n * n
+            continue
+        c = OD.contracted_axes(k)
+        rl, rr = d.rank[d.left[u]], d.rank[d.right[u]]
+        want += 8 * nt * n ** (rl - c) * n ** (rr - c) * n ** c
+    assert any(d.kind[u] in (W.C1, W.C2, W.C3) for u in range(d.n_nodes))
+    c = ctx_for(wl)
+    c.schedule("tree")
+    assert c.plan("fp64", True)["flops"] == want
+    L = [_L(2), _L(3), _L(4), _L(4), _L(3)]
+    for ops in ([(W.C2, 0, 1), (W.HCA, -1, 0)], [(W.C1, 2, 3), (W.HCA, -1, 0)],
+                [(W.C3, 1, 4), (W.HCA, -1, 0)], [(7, 0, 1), (W.HCA, -1, 0)]):
+        with pytest.raises(X.CdagError) as e:
+            c.build_cdag(L, [_G(ops)])
+        assert e.value.code == B.E_INVALID
+    with pytest.raises(X.CdagError):
+        c.build_cdag([_L(5), _L(2)], [_G([(W.HCA, 0, 1)])])
 
 
 def test_mixed_precision_plans_halve_sizes():

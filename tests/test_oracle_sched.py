@@ -277,6 +277,37 @@ def test_build_validation():
             D.build(L, [_G(ops)])
     with pytest.raises(D.InvalidGraph):
         D.build([_Leaf(2, nvec=4), _Leaf(2, nvec=5)], [_G([(W.HCA, 0, 1)])])
+    # general contractions: operand and output ranks must stay within 2..4
+    L4 = [_Leaf(2), _Leaf(3), _Leaf(4), _Leaf(4), _Leaf(3)]
+    for ops in ([(W.C2, 0, 1), (W.HCA, -1, 0)],          # output rank 1
+                [(W.C1, 2, 3), (W.HCA, -1, 0)],          # output rank 6
+                [(W.C3, 1, 4), (W.HCA, -1, 0)],          # output rank 0
+                [(9, 0, 1), (W.HCA, -1, 0)]):            # no such kind
+        with pytest.raises(D.InvalidGraph):
+            D.build(L4, [_G(ops)])
+    with pytest.raises(D.InvalidGraph):
+        D.build([_Leaf(5), _Leaf(2)], [_G([(W.HCA, 0, 1)])])
+
+
+def test_general_kinds_normalize_and_merge():
+    """A general contraction with the ranks of a named kind is that kind, so it
+    merges with it; others keep their kind and get the output rank
+    rl + rr - 2c."""
+    L = [_Leaf(2), _Leaf(2), _Leaf(3), _Leaf(3), _Leaf(2), _Leaf(4)]
+    g1 = _G([(W.K22, 0, 1), (W.HCA, -1, 4)])
+    g2 = _G([(W.C1, 0, 1), (W.K22, -1, 4), (W.HCA, -2, 0)])
+    g3 = _G([(W.C1, 2, 3), (W.C3, -1, 5), (W.HCA, -2, 4)])      # rank 4, then 4x4 over 3 -> 2
+    g4 = _G([(W.C2, 2, 3), (W.HCA, -1, 4)])                       # = K33
+    d = D.build(L, [g1, g2, g3, g4])
+    k22 = d.root_of_graph[0] - 1
+    assert d.kind[k22] == W.K22 and d.left[k22] == 0 and d.right[k22] == 1
+    assert d.n_nodes == 6 + 10 - 1                                # 10 ops; C1(0, 1) of g2 merged
+    c1 = next(u for u in range(d.n_nodes) if d.kind[u] == W.C1)
+    assert d.rank[c1] == 4 and (d.left[c1], d.right[c1]) == (2, 3)
+    c3 = next(u for u in range(d.n_nodes) if d.kind[u] == W.C3)
+    assert d.rank[c3] == 2
+    k33 = next(u for u in range(d.n_nodes) if d.kind[u] == W.K33)
+    assert (d.left[k33], d.right[k33]) == (2, 3)
 
 
 def test_hash_consing_and_shared_roots():

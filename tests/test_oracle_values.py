@@ -6,7 +6,10 @@
   * Permutation and selector tensors pick out entries exactly, which fixes every
     index convention (a transposed operand or wrong contracted axis fails).
   * Linearity in each leaf; the cross-diagram sum is correctly rounded.
+  * General contractions (C1, C2, C3 over operand ranks 2..4) against explicit
+    index loops.
 """
+import itertools
 import math
 
 import numpy as np
@@ -99,6 +102,41 @@ def test_matmul_form_equals_einsum_form(kind):
     X = W._draw(rng, (nt,) + (n,) * shp[0], 1.0)
     Y = W._draw(rng, (nt,) + (n,) * shp[1], 1.0)
     assert rel(V.contract(kind, X, Y), V.contract_einsum(kind, X, Y)) < 1e-14
+
+
+GENERAL = [(W.C1, 3, 3), (W.C1, 4, 2), (W.C1, 2, 4), (W.C2, 4, 3), (W.C2, 3, 4), (W.C2, 4, 4),
+           (W.C2, 4, 2), (W.C3, 4, 4), (W.C1, 3, 2), (W.C2, 3, 3)]
+
+
+@pytest.mark.parametrize("kind,rl,rr", GENERAL)
+def test_general_contraction_by_index_loops(kind, rl, rr):
+    """O[a.., h..] = sum_e.. X[a.., e..] Y[e.., h..] with c = kind - 3 summed axes,
+    written as loops over every index tuple (N = 3, two time slices)."""
+    rng = np.random.default_rng(100 + 10 * kind + rl + rr)
+    nt, n, c = 2, 3, kind - 3
+    X = W._draw(rng, (nt,) + (n,) * rl, 1.0)
+    Y = W._draw(rng, (nt,) + (n,) * rr, 1.0)
+    ro = rl + rr - 2 * c
+    want = np.zeros((nt,) + (n,) * ro, dtype=np.complex128)
+    for t in range(nt):
+        for fl in itertools.product(range(n), repeat=rl - c):
+            for fr in itertools.product(range(n), repeat=rr - c):
+                acc = 0j
+                for sm in itertools.product(range(n), repeat=c):
+                    acc += X[(t,) + fl + sm] * Y[(t,) + sm + fr]
+                want[(t,) + fl + fr] = acc
+    got = V.contract(kind, X, Y)
+    assert got.shape == want.shape
+    assert rel(got, want) < 1e-14
+    assert rel(V.contract_einsum(kind, X, Y), want) < 1e-14
+
+
+def test_named_kinds_are_general_contractions():
+    rng = np.random.default_rng(7)
+    for named, general, rl, rr in ((W.K22, W.C1, 2, 2), (W.K32, W.C1, 3, 2), (W.K33, W.C2, 3, 3)):
+        X = W._draw(rng, (2,) + (4,) * rl, 1.0)
+        Y = W._draw(rng, (2,) + (4,) * rr, 1.0)
+        assert np.array_equal(V.contract(named, X, Y), V.contract(general, X, Y))
 
 
 def test_linearity():
