@@ -22,12 +22,22 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef short v8s __attribute__((ext_vector_type(8)));
 
+// Largest i with first[i * stride] <= item, where first[0] == 0 and the
+// values strictly increase.  Called by all 64 lanes of a wave with the same
+// item: each round the lanes read the starts of 64 equal blocks of the
+// remaining range and a ballot picks the block holding the item, so n
+// descriptors take ceil(log64 n) dependent loads instead of log2 n.
 __device__ __forceinline__ int find_desc(const int32_t* first, int stride_words, int n, int64_t item) {
-  // largest i with first[i * stride] <= item (first[0] == 0)
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if ((int64_t)first[(int64_t)mid * stride_words] <= item) lo = mid; else hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int lo = 0, cnt = n;
+  while (cnt > 1) {
+    const int step = (cnt + 63) >> 6;
+    const bool in_range = lane * step < cnt;
+    const bool ok = in_range && (int64_t)first[(int64_t)(lo + lane * step) * stride_words] <= item;
+    const unsigned long long m = __ballot(ok);
+    const int last = 63 - __clzll(m);       // lane 0 always holds: first[lo] <= item
+    lo += last * step;
+    cnt = min(step, cnt - last * step);
   }
   return lo;
 }
