@@ -239,7 +239,8 @@ def cdag_launch_records(h):
     return out
 
 
-TILES = {0: (64, 64), 1: (32, 32), 2: (48, 48), 3: (128, 64), 4: (64, 32)}
+TILES = {0: (64, 64), 1: (32, 32), 2: (48, 48), 3: (128, 64), 4: (64, 32), 5: (64, 64)}
+TILE_THREADS = {0: 256, 1: 256, 2: 64, 3: 256, 4: 256, 5: 512}
 
 
 GRIDS = {0: "persistent", 1: "one workgroup per item"}

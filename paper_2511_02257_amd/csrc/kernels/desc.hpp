@@ -18,9 +18,9 @@ namespace cdag {
 // Exterior-contraction tile shapes (workgroup output tile BM x BN, threads).
 // The kernels instantiate exactly these, in this order.
 struct TileShape { int32_t bm, bn, nth; };
-constexpr int kNumTiles = 5;
+constexpr int kNumTiles = 6;
 constexpr TileShape kTileShapes[kNumTiles] = {
-    {64, 64, 256}, {32, 32, 256}, {48, 48, 64}, {128, 64, 256}, {64, 32, 256}};
+    {64, 64, 256}, {32, 32, 256}, {48, 48, 64}, {128, 64, 256}, {64, 32, 256}, {64, 64, 512}};
 
 // One exterior contraction inside a grouped launch.
 struct HecDesc {

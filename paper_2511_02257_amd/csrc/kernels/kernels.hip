@@ -56,6 +56,7 @@ typedef Tile<2, 2, 1, 1> Tile1;   //  32 x 32, 256 threads
 typedef Tile<1, 1, 3, 3> Tile2;   //  48 x 48,  64 threads
 typedef Tile<2, 2, 4, 2> Tile3;   // 128 x 64, 256 threads
 typedef Tile<2, 2, 2, 1> Tile4;   //  64 x 32, 256 threads
+typedef Tile<2, 4, 2, 1> Tile5;   //  64 x 64, 512 threads (half the accumulators per wave)
 
 struct WorkItem {
   const HecDesc* h;
@@ -160,6 +161,25 @@ __device__ __forceinline__ void load8(T (&r)[8], const T* src, int valid, bool v
   }
 }
 
+// One 16-byte chunk (W = 16 / sizeof(T) elements) of a row: a vector load when
+// all W are in range and rows are W-element aligned, otherwise element-wise
+// with zero fill.
+template <typename T>
+__device__ __forceinline__ void load16b(T (&r)[16 / sizeof(T)], const T* src, int valid, bool vec) {
+  constexpr int W = 16 / (int)sizeof(T);
+  typedef typename Vec2<T>::V V;
+  static_assert(sizeof(V) == 16, "one vector per chunk");
+  if (vec && valid == W) {
+    V v = *reinterpret_cast<const V*>(src);
+    const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+    for (int i = 0; i < W; ++i) r[i] = e[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < W; ++i) r[i] = i < valid ? src[i] : T(0);
+  }
+}
+
 // Store one 16x16 block pair (Re, Im) of accumulators with the instruction's
 // row layout; rows and columns outside M x N are skipped.
 template <typename T, typename V>
@@ -185,15 +205,20 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
   typedef typename Mfma<T>::V V;
   constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
   constexpr int BK = 16, APAD = BK + 1, BPAD = BN + 16;
-  // the A tile is split into 8-element row segments: [plane][row][k / 8]
-  constexpr int SEGA = 2 * BM * (BK / 8), SEGB = 2 * BK * (BN / 8);
+  // The A tile is split into 8-element row segments ([plane][row][k / 8]); the
+  // B tile into 16-byte row chunks of W elements ([plane][k][n / W]), so that
+  // consecutive lanes load and store consecutive 16 bytes (coalesced loads,
+  // LDS stores free of bank conflicts).
+  constexpr int W = 16 / (int)sizeof(T);
+  constexpr int SEGA = 2 * BM * (BK / 8), SEGB = 2 * BK * (BN / W);
   constexpr int LA = (SEGA + NTH - 1) / NTH, LB = (SEGB + NTH - 1) / NTH;
-  __shared__ T As[ST][2][BM][APAD];   // [stage][plane][m][k]
-  __shared__ T Bs[ST][2][BK][BPAD];   // [stage][plane][k][n]
+  static_assert(BN % W == 0, "B chunks must tile the row");
+  __shared__ __attribute__((aligned(16))) T As[ST][2][BM][APAD];   // [stage][plane][m][k]
+  __shared__ __attribute__((aligned(16))) T Bs[ST][2][BK][BPAD];   // [stage][plane][k][n]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / TL::WGN, wn = wave % TL::WGN, li = lane & 15, lk = lane >> 4;
 
-  T ra[LA][8], rb[LB][8];
+  T ra[LA][8], rb[LB][W];
   auto gload = [&](const ItemView<T>& o, int k0) {
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
@@ -205,15 +230,16 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
         load8<T>(ra[q], o.A + (int64_t)p * o.M * o.K + (int64_t)am * o.K + ak, av, o.avec);
       }
     }
+    const bool bvw = (o.N % W) == 0;
 #pragma unroll
     for (int q = 0; q < LB; ++q) {
       const int seg = tid + q * NTH;
       if (seg < SEGB) {
-        const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
-        const int kk = rem / (BN / 8), sg = rem % (BN / 8);
-        const int bkk = k0 + kk, bn = o.n0 + 8 * sg;
-        const int bv = bkk < o.kend ? max(0, min(8, o.N - bn)) : 0;
-        load8<T>(rb[q], o.B + (int64_t)p * o.K * o.N + (int64_t)bkk * o.N + bn, bv, o.bvec);
+        const int p = seg / (BK * (BN / W)), rem = seg % (BK * (BN / W));
+        const int kk = rem / (BN / W), cw = rem % (BN / W);
+        const int bkk = k0 + kk, bn = o.n0 + W * cw;
+        const int bv = bkk < o.kend ? max(0, min(W, o.N - bn)) : 0;
+        load16b<T>(rb[q], o.B + (int64_t)p * o.K * o.N + (int64_t)bkk * o.N + bn, bv, bvw);
       }
     }
   };
@@ -231,10 +257,10 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
     for (int q = 0; q < LB; ++q) {
       const int seg = tid + q * NTH;
       if (seg < SEGB) {
-        const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
-        const int kk = rem / (BN / 8), sg = rem % (BN / 8);
+        const int p = seg / (BK * (BN / W)), rem = seg % (BK * (BN / W));
+        const int kk = rem / (BN / W), cw = rem % (BN / W);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) Bs[st][p][kk][8 * sg + i] = rb[q][i];
+        for (int i = 0; i < W; ++i) Bs[st][p][kk][W * cw + i] = rb[q][i];
       }
     }
   };
@@ -718,7 +744,8 @@ void launch_hec_stages(int prec, int tile, bool persistent, char* arena, const H
     case 1: launch_hec_tile<Tile1, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
     case 2: launch_hec_tile<Tile2, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
     case 3: launch_hec_tile<Tile3, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    default: launch_hec_tile<Tile4, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    case 4: launch_hec_tile<Tile4, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    default: launch_hec_tile<Tile5, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
   }
 }
 
@@ -742,6 +769,7 @@ static_assert(Tile1::BM == kTileShapes[1].bm && Tile1::BN == kTileShapes[1].bn &
 static_assert(Tile2::BM == kTileShapes[2].bm && Tile2::BN == kTileShapes[2].bn && Tile2::NTH == kTileShapes[2].nth, "tile 2");
 static_assert(Tile3::BM == kTileShapes[3].bm && Tile3::BN == kTileShapes[3].bn && Tile3::NTH == kTileShapes[3].nth, "tile 3");
 static_assert(Tile4::BM == kTileShapes[4].bm && Tile4::BN == kTileShapes[4].bn && Tile4::NTH == kTileShapes[4].nth, "tile 4");
+static_assert(Tile5::BM == kTileShapes[5].bm && Tile5::BN == kTileShapes[5].bn && Tile5::NTH == kTileShapes[5].nth, "tile 5");
 
 hipError_t launch_reduce(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s) {
   const RedDesc* d = reinterpret_cast<const RedDesc*>(arena + desc_off);

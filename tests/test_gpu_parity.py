@@ -125,7 +125,7 @@ def test_baryon_ragged_splitk(baryon_small, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("grid", [0, 1])
 @pytest.mark.parametrize("stages", [2, 1])
 def test_every_tile_shape(meson_small, baryon_small, prec, tile, grid, stages):

@@ -257,7 +257,7 @@ def test_kernel_variants_round_trip_and_share_decomposition():
                             c.set_tile(prec, kind, 72, tile, grid, stages, split)
                             assert c.get_tile(prec, kind, 72) == (tile, grid, stages, split)
                         assert c.plan(prec, True)["hec_items"] == want, (tile, grid, stages, prec)
-    for bad in ((5, 1, 2, 1), (-2, 1, 2, 1), (0, 2, 2, 1), (0, 1, 3, 1), (0, 1, 0, 1), (0, 1, 2, 2)):
+    for bad in ((6, 1, 2, 1), (-2, 1, 2, 1), (0, 2, 2, 1), (0, 1, 3, 1), (0, 1, 0, 1), (0, 1, 2, 2)):
         with pytest.raises(X.CdagError) as e:
             c.set_tile("fp64", 0, 72, *bad)
         assert e.value.code == B.E_INVALID
