@@ -159,12 +159,14 @@ def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True, fix
 
 
 def corr_func_study(rows=None):
-    """Host-only: the peak-memory study (Sec. V-B) and the scheduler-time study
-    (Table sch-time) on the Table corr-func-shaped DAGs.  Per row: DAG size
-    and F_v / F_e, then for the input order, Sibling and Tree the wall time of
-    the schedule call and the peak memory (after-release M_i peak and live
-    peak during an op), in units of the greatest common divisor of the
-    distinct tensor sizes as the paper plots them."""
+    """Host-only: the peak-memory study (Sec. V-B), the scheduler-time study
+    (Table sch-time) and the data-movement counts (evictions, transfers and
+    their size, Sec. V-C) on the Table corr-func-shaped DAGs.  Per row: DAG
+    size and F_v / F_e, then for the input order, Sibling and Tree the wall
+    time of the schedule call, the peak memory (after-release M_i peak and
+    live peak during an op) and the budgeted plan's counts, sizes in units of
+    the greatest common divisor of the distinct tensor sizes as the paper
+    plots them."""
     import math
     from synth import corr_func as CF
     import paper_2511_02257_amd as X
@@ -200,6 +202,27 @@ def corr_func_study(rows=None):
                            "peak_live_units": int(pl // unit)}
         best = min(res["sibling"]["peak_post_units"], res["tree"]["peak_post_units"])
         res["input_over_best"] = round(res["input"]["peak_post_units"] / max(1, best), 3)
+        # Budgeted plans (the data-movement study): a budget of half the lower
+        # live peak of Sibling and Tree, so every schedule must evict;
+        # per-contraction steps in schedule order.
+        # (raised by quarters while one contraction alone does not fit)
+        b_units = max(min(res["sibling"]["peak_live_units"], res["tree"]["peak_live_units"]) // 2, 1)
+        while True:
+            ctx.set_mem_budget(b_units * unit)
+            try:
+                plans = {}
+                for policy in ("input", "sibling", "tree"):
+                    ctx.schedule(policy)
+                    plans[policy] = ctx.plan("fp64", False)
+                break
+            except X.CdagError:
+                b_units += max(1, b_units // 4)
+        res["budget_units"] = b_units
+        for policy, p in plans.items():
+            res[policy]["plan"] = {"n_evict": p["n_evict"], "n_transfers": p["n_h2d"] + p["n_d2h"],
+                                   "h2d_units": int(p["h2d_bytes"] // unit),
+                                   "d2h_units": int(p["d2h_bytes"] // unit)}
+        ctx.set_mem_budget(None)
         out[row] = res
         log(row, res)
         ctx.close()
@@ -388,17 +411,28 @@ def main():
         d2, s3 = timed_steps(ctx, runner, "fp64", False, max(3, args.steps // 10), 1)
         extras["fp64_per_contraction_value"] = round(s3["plan"]["flops"] * max(3, args.steps // 10) / d2 / 1e12, 4)
         # budgeted, leaves start on the host (PCIe-inclusive time-to-solution)
+        # Each schedule runs with eager launches on two streams (copies overlap
+        # kernels) and with captured segments on one stream (fewer launches);
+        # the faster is reported, with the other's time beside it.  The Tree
+        # schedule is also cut into waves with growing lookahead.
         budgeted = {}
         for prec in ("fp64", "fp32"):
             ctx.set_mem_budget(budgets[prec])
-            for policy, look in (("input", 0), ("sibling", 0), ("tree", 0), ("tree", ALL)):
-                ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=False)
+            for policy, look in (("input", 0), ("sibling", 0), ("tree", 0), ("tree", 4), ("tree", 16),
+                                 ("tree", ALL)):
                 ctx.schedule(policy)
                 reps = 3
-                d2, s3 = timed_steps(ctx, runner, prec, True, reps, 1)
+                tts = {}
+                for graphs in (False, True):
+                    ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=graphs)
+                    d2, s3 = timed_steps(ctx, runner, prec, True, reps, 1)
+                    tts["graphs" if graphs else "eager"] = d2 / reps
+                d2 = min(tts.values()) * reps
                 p = s3["plan"]
-                key = f"{prec}_{policy}" + ("_lookahead" if look else "")
+                key = f"{prec}_{policy}" + ("" if not look else ("_lookahead_all" if look == ALL
+                                                                   else f"_lookahead{look}"))
                 budgeted[key] = {
+                    "tts_eager_s": round(tts["eager"], 5), "tts_graphs_s": round(tts["graphs"], 5),
                     "tts_s": round(d2 / reps, 5), "h2d_GB": round(p["h2d_bytes"] / 1e9, 4),
                     "d2h_GB": round(p["d2h_bytes"] / 1e9, 4), "n_evict": p["n_evict"],
                     "n_h2d": p["n_h2d"], "peak_resident_bytes": p["peak_resident"],
