@@ -66,9 +66,10 @@ def measured_traffic(variant):
     with open(path) as f:
         rec = json.load(f)
     from paper_2511_02257_amd.profiling import kernel_source_sha256
-    if rec.get("kernel_sha256") != kernel_source_sha256() or rec.get("variant") != variant:
+    if rec.get("kernel_sha256") != kernel_source_sha256():
         return None
-    return rec.get("traffic_bytes_per_launch")
+    entry = rec.get("variants", {}).get(str(variant))
+    return None if entry is None else entry.get("traffic_bytes_per_launch")
 
 
 KIND_NAMES = {0: "K22", 1: "K32", 2: "K33", 3: "HCA"}
@@ -136,7 +137,7 @@ def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True, fix
                 ctx.set_tile(prec, inv[kname], int(n), *choice)
             runner.ensure_arena(ctx.plan(prec, True)["arena_bytes"])
         else:
-            runner.autotune(prec, True, reps=1, in_situ=in_situ)
+            runner.autotune(prec, True, reps=2 if in_situ else 1, in_situ=in_situ)
         dt, st = timed_steps(ctx, runner, prec, True, steps, 1)
         p = st["plan"]
         ctx.set_timing(True)
@@ -342,7 +343,7 @@ def main():
             ctx.set_tile("fp64", 0, 64, *(int(x) for x in args.fp64_variant.split(",")))
             runner.ensure_arena(ctx.plan("fp64", True)["arena_bytes"])
         elif prec == "fp64" or not args.skip_extras:
-            runner.autotune(prec, True, reps=2, in_situ=True)
+            runner.autotune(prec, True, reps=3, in_situ=True)
         t, g, st, _ = ctx.get_tile(prec, 0, 64)
         tiles[prec] = {"K22_N64": {"tile": list(X.TILES[t]), "grid": X.binding.GRIDS[g],
                                    "lds_stages": st}}

@@ -263,7 +263,8 @@ int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
  * (prec, batched); its contents are scratch between executes) and keep the
  * fastest per time slice.  mode 1 (in situ): execute the planned DAG `reps` times per
  * variant and split_k setting, shape by shape, with launch timing on, and keep
- * the least summed time of exterior contractions and split-K reductions
+ * the least time of exterior contractions and split-K reductions in the
+ * fastest of the reps
  * (needs leaf data; costs up to 40 * reps executes per shape).  *n_tuned
  * (nullable) receives the number of shapes tuned.  Needs cdag_bind_device and
  * an arena of at least the plan's arena_bytes; invalidates the current plan

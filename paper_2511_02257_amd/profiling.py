@@ -1,8 +1,10 @@
 """Summaries of rocprofv3 output for the committed profiles.
 
-traffic: HBM bytes per launch of one kernel from two counter runs (FETCH_SIZE,
-then WRITE_SIZE, in KiB per dispatch), each scaled by what the same counter
-reads for a plain device copy of known size.
+traffic: HBM bytes per launch of one kernel variant from two counter runs
+(FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), each scaled by what the
+same counter reads for a plain device copy of known size.  Entries for several
+variants of the same kernel source accumulate in one file; a different source
+hash starts the file afresh.
 
     python -m paper_2511_02257_amd.profiling traffic \\
         --kernel 'hec_mfma<double' --variant 15 \\
@@ -51,15 +53,22 @@ def traffic(args):
     kf = kib / (sum(cf) / len(cf))
     kw = kib / (sum(cw) / len(cw))
     per_launch = (sum(fetch) * kf + sum(write) * kw) * 1024.0 / len(fetch)
-    rec = {
-        "kernel": args.kernel, "variant": args.variant, "dispatches": len(fetch),
+    entry = {
+        "dispatches": len(fetch),
         "fetch_scale": round(kf, 5), "write_scale": round(kw, 5),
         "fetch_bytes_per_launch": sum(fetch) * kf * 1024.0 / len(fetch),
         "write_bytes_per_launch": sum(write) * kw * 1024.0 / len(write),
         "traffic_bytes_per_launch": per_launch,
-        "kernel_sha256": kernel_source_sha256(),
-        "counters": "FETCH_SIZE and WRITE_SIZE (KiB per dispatch), separate rocprofv3 --pmc runs",
     }
+    sha = kernel_source_sha256()
+    rec = {}
+    if os.path.exists(args.out):
+        with open(args.out) as f:
+            rec = json.load(f)
+    if rec.get("kernel_sha256") != sha or rec.get("kernel") != args.kernel:
+        rec = {"kernel": args.kernel, "kernel_sha256": sha, "variants": {},
+               "counters": "FETCH_SIZE and WRITE_SIZE (KiB per dispatch), separate rocprofv3 --pmc runs"}
+    rec["variants"][str(args.variant)] = entry
     with open(args.out, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
