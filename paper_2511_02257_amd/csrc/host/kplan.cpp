@@ -137,8 +137,8 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
   // kernel that produces the canonical operand q also writes the trace's
   // block partials when the other operand is already in place and stays
   // there: leaves resident, no evictions (so no tensor moves), q produced in
-  // a later step than the other operand, q an N x N GEMM output with one
-  // K split, and q not fused with another root already.
+  // a later step than the other operand, q a one-split rank-2 output, and q
+  // not fused with another root already.
   std::vector<int32_t> level(d.n_nodes(), 0);
   for (int64_t u = d.n_leaves; u < d.n_nodes(); ++u)
     level[u] = 1 + std::max(level[d.left[u]], level[d.right[u]]);
@@ -162,9 +162,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
     if (!d.is_leaf(o) && step_of[o] >= step_of[q]) continue;
     HecDesc hq{};
     decomp(q, hq);
-    // the epilogue maps GEMM rows and columns to the N x N matrix, so the
-    // GEMM must be N x N (not, e.g., C2 on ranks (4, 2): N^2 x 1)
-    if (hq.splits != 1 || hq.M != d.nvec[q] || hq.N != d.nvec[q]) continue;
+    if (hq.splits != 1) continue;
     fused_root[q] = u;
     part_of[u] = part_bytes;
     const int64_t nb = (d.nvec[u] + 15) / 16;

