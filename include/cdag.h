@@ -117,10 +117,6 @@ typedef struct {
   int64_t tensor_highwater; /* physical high-water of the tensor pool           */
   int64_t host_spill_bytes; /* pinned host bytes for spilled intermediates      */
   int64_t hec_items;     /* exterior-contraction work items (output tiles x K splits) */
-  int64_t n_fused_traces; /* root traces whose block partials the producing
-                             contraction's kernel writes (leaves resident, no
-                             evictions); the others are computed by the trace
-                             kernel, with the same arithmetic and bits      */
   double flops;          /* algorithmic flops, 8 per complex multiply-add        */
   double t_sched_s, t_plan_s;
 } cdag_plan_stats;

@@ -46,7 +46,7 @@ class cdag_graph(C.Structure):
 
 _PLAN_INT = ["n_nodes", "n_leaves", "n_contr", "n_roots", "n_steps", "peak_post", "peak_live",
              "peak_resident", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes", "budget",
-             "arena_bytes", "tensor_highwater", "host_spill_bytes", "hec_items", "n_fused_traces"]
+             "arena_bytes", "tensor_highwater", "host_spill_bytes", "hec_items"]
 _PLAN_DBL = ["flops", "t_sched_s", "t_plan_s"]
 
 

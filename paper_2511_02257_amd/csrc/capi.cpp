@@ -293,7 +293,6 @@ static void fill_plan_stats(const cdag::Ctx& c, cdag_plan_stats* s) {
   s->tensor_highwater = p.leaf_region_bytes + p.pool_bytes;
   s->host_spill_bytes = p.host_spill_bytes;
   s->hec_items = c.kplan.hec_items;
-  s->n_fused_traces = c.kplan.n_fused;
   s->flops = c.kplan.flops;
   s->t_sched_s = c.t_sched;
   s->t_plan_s = c.t_plan;

@@ -50,9 +50,6 @@ void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h) {
   h->M = (int32_t)g.M;
   h->N = (int32_t)g.N;
   h->K = (int32_t)g.K;
-  h->tr_p_off = -1;          // no fused root trace unless the kernel plan sets one
-  h->tr_part_off = -1;
-  h->tr_nb = 0;
   const TileShape& ts = kTileShapes[variant_tile(variant)];
   h->nt = nt;
   h->tiles_m = (h->M + ts.bm - 1) / ts.bm;
@@ -132,50 +129,6 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
   kp.tensors_end = align256(p.leaf_region_bytes + p.pool_bytes);
   kp.ws_off = kp.tensors_end;
 
-  // Root traces: canonical operand (the child of larger dependency level,
-  // right on a tie; a property of the DAG alone) and trace fusion.  The
-  // kernel that produces the canonical operand q also writes the trace's
-  // block partials when the other operand is already in place and stays
-  // there: leaves resident, no evictions (so no tensor moves), q produced in
-  // a later step than the other operand, q a one-split rank-2 output, and q
-  // not fused with another root already.
-  std::vector<int32_t> level(d.n_nodes(), 0);
-  for (int64_t u = d.n_leaves; u < d.n_nodes(); ++u)
-    level[u] = 1 + std::max(level[d.left[u]], level[d.right[u]]);
-  std::vector<int64_t> step_of(d.n_nodes(), -1), exec_rec(d.n_nodes(), -1);
-  for (int64_t s = 0; s < S; ++s)
-    for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri)
-      if (p.recs[ri].op == OP_EXEC) {
-        step_of[p.recs[ri].node] = s;
-        exec_rec[p.recs[ri].node] = ri;
-      }
-  auto canonical_right = [&](int64_t root) { return level[d.right[root]] >= level[d.left[root]]; };
-  std::vector<int64_t> fused_root(d.n_nodes(), -1);   // q -> root whose trace it carries
-  std::vector<int64_t> part_of(d.n_nodes(), -1);      // root -> partial buffer offset
-  int64_t part_bytes = 0;
-  const bool can_fuse = p.opts.leaves_resident && p.n_evict == 0;
-  for (int64_t u = d.n_leaves; can_fuse && u < d.n_nodes(); ++u) {
-    if (d.kind[u] != HCA) continue;
-    const bool cr = canonical_right(u);
-    const int64_t q = cr ? d.right[u] : d.left[u], o = cr ? d.left[u] : d.right[u];
-    if (d.is_leaf(q) || d.kind[q] == HCA || d.rank[q] != 2 || fused_root[q] >= 0) continue;
-    if (!d.is_leaf(o) && step_of[o] >= step_of[q]) continue;
-    HecDesc hq{};
-    decomp(q, hq);
-    if (hq.splits != 1) continue;
-    fused_root[q] = u;
-    part_of[u] = part_bytes;
-    const int64_t nb = (d.nvec[u] + 15) / 16;
-    part_bytes += align256((int64_t)d.nt[u] * nb * nb * 16);
-  }
-  kp.part_off = align256(kp.ws_off + kp.ws_bytes);
-  kp.part_bytes = part_bytes;
-  for (int64_t u = 0; u < d.n_nodes(); ++u)
-    if (part_of[u] >= 0) {
-      part_of[u] += kp.part_off;
-      ++kp.n_fused;
-    }
-
   // pass 2: descriptors (host blob; arena offset = blob_off + host offset)
   kp.launch_off.reserve(S + 1);
   for (int64_t s = 0; s < S; ++s) {
@@ -196,19 +149,14 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
       kp.flops += d.flops(u);
       if (d.kind[u] == HCA) {
         HcaDesc h{};
-        const bool cr = canonical_right(u);
-        h.p_off = cr ? r.a_off : r.b_off;
-        h.q_off = cr ? r.b_off : r.a_off;
-        h.part_off = part_of[u];
-        h.fused = part_of[u] >= 0 ? 1 : 0;
+        h.p_off = r.a_off;
+        h.q_off = r.b_off;
         h.out_off = -1 - kp.tree_corr_off[tree_of[u]];   // fixed up below (needs corr_off)
         h.n = d.nvec[u];
         h.nt = d.nt[u];
         hca.push_back(h);
         hca_flops += d.flops(u);
-        const double nb = (double)((h.n + 15) / 16);
-        hca_bytes += h.fused ? 16.0 * h.nt * nb * nb        // the block partials
-                             : 2.0 * h.nt * (double)h.n * h.n * (double)elem_bytes_of(prec);
+        hca_bytes += 2.0 * h.nt * (double)h.n * h.n * (double)elem_bytes_of(prec);
         continue;
       }
       HecDesc h{};
@@ -225,15 +173,6 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
       h.b_off = r.b_off;
       h.c_off = r.dev_off;
       h.ws_off = -1;
-      h.tr_p_off = -1;
-      h.tr_part_off = -1;
-      if (fused_root[u] >= 0) {
-        const int64_t root = fused_root[u];
-        const PlanRec& rr = p.recs[exec_rec[root]];
-        h.tr_p_off = canonical_right(root) ? rr.a_off : rr.b_off;   // the other operand
-        h.tr_part_off = part_of[root];
-        h.tr_nb = (d.nvec[u] + 15) / 16;
-      }
       h.tile_begin = (int32_t)tiles[tl];
       tiles[tl] += h.tile_count;
       kp.hec_items += h.tile_count;
@@ -307,7 +246,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
   for (auto& e : xe) put(kp.blob, e);
 
   // final layout and fix-ups of buffer-relative offsets
-  kp.blob_off = align256(kp.part_off + kp.part_bytes);
+  kp.blob_off = align256(kp.ws_off + kp.ws_bytes);
   kp.corr_off = align256(kp.blob_off + (int64_t)kp.blob.size());
   kp.sums_off = kp.corr_off + kp.corr_bytes;
   kp.total_bytes = align256(kp.sums_off + kp.sums_bytes);

@@ -77,8 +77,6 @@ struct KernelPlan {
   // arena layout
   int64_t tensors_end = 0;           // leaf region + tensor pool
   int64_t ws_off = 0, ws_bytes = 0;
-  int64_t part_off = 0, part_bytes = 0;   // fused root-trace block partials
-  int64_t n_fused = 0;                    // root traces computed in a producer's epilogue
   int64_t blob_off = 0;
   int64_t corr_off = 0, corr_bytes = 0;   // per tree: [nt][2] doubles
   int64_t sums_off = 0, sums_bytes = 0;   // per correlator: [nt][2] doubles

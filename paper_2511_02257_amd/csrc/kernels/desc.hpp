@@ -29,11 +29,6 @@ struct HecDesc {
   int32_t M, N, K, nt;
   int32_t tiles_m, tiles_n, splits, k_split;   // k_split: K range per split (multiple of the k-step)
   int32_t tile_begin, tile_count;              // this op's work items in the launch
-  // Fused root trace (tr_p_off >= 0): this contraction's output is the
-  // canonical operand Q of a root trace; its epilogue writes the per-16x16-
-  // block partials of sum Q[r][c] P[c][r] to tr_part_off ([nt][nb][nb] double2).
-  int64_t tr_p_off, tr_part_off;               // P's t = 0 slice; partials
-  int32_t tr_nb, tr_pad;
 };
 
 // Fixed-order reduction of split-K partials into C (one per split op).
@@ -42,15 +37,10 @@ struct RedDesc {
   int32_t mn, nt, splits, item_begin;          // items: ceil(2*nt*mn / 256) blocks
 };
 
-// Root trace C(t) = sum_rc Q[t,r,c] P[t,c,r] into the FP64 correlator buffer,
-// Q the canonical operand (the child of larger dependency level, right on a
-// tie), summed in a fixed order: per 16x16 block of Q a lane-and-butterfly
-// partial, blocks in row-major order.  fused: the partials were written by the
-// kernel that produced Q (part_off); else they are computed here from P, Q.
+// Root trace C(t) = sum_ij P[t,i,j] Q[t,j,i] into the FP64 correlator buffer.
 struct HcaDesc {
   int64_t p_off, q_off, out_off;               // out: [nt][2] doubles
-  int64_t part_off;                            // fused: [nt][nb][nb] double2
-  int32_t n, nt, item_begin, fused;            // items: one per time slice
+  int32_t n, nt, item_begin, pad;              // items: one per time slice
 };
 
 // Cross-diagram sum for one correlator: sum over entries [e_begin, e_end)

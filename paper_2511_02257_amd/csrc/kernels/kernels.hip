@@ -140,32 +140,6 @@ template <typename T> struct Vec2;
 template <> struct Vec2<double> { typedef double2 V; static constexpr int n = 2; };
 template <> struct Vec2<float> { typedef float4 V; static constexpr int n = 4; };
 
-// One 16x16 block of a root trace sum_rc Q[r][c] P[c][r]: lane l holds the
-// four (r, c) of the block that the matrix cores' output layout gives it
-// (c = column l % 16, r = Mfma<T>::row(l / 16, v)), adds its products over
-// v = 0..3 and the 64 lane sums meet in a fixed butterfly.  Shared by the
-// exterior-contraction epilogue (Q in registers) and the trace kernel (Q from
-// memory), so both give the same bits.  Products and sums in FP64.
-template <typename T>
-__device__ __forceinline__ void trace_block(const T (&qr)[4], const T (&qi)[4], const T (&pr)[4],
-                                            const T (&pi)[4], double& sr, double& si) {
-  sr = 0.0;
-  si = 0.0;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const double xr = (double)qr[v], xi = (double)qi[v], yr = (double)pr[v], yi = (double)pi[v];
-    sr = fma(xr, yr, sr);
-    sr = fma(-xi, yi, sr);
-    si = fma(xr, yi, si);
-    si = fma(xi, yr, si);
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    sr += __shfl_xor(sr, o);
-    si += __shfl_xor(si, o);
-  }
-}
-
 // 8 consecutive elements of one row: vector loads when fully in range and the
 // row is 8-element aligned, otherwise element-wise with zero fill.
 template <typename T>
@@ -219,43 +193,6 @@ __device__ __forceinline__ void store_block(T* C, int M, int N, int row0, int co
       C[(int64_t)M * N + (int64_t)m * N + col] = im[v];
     }
   }
-}
-
-// Fused root trace: this wave's TM x TN output blocks are blocks of the
-// canonical operand Q of a root trace (N x N); write each in-range block's
-// partial, with P read from memory, to the partial buffer.
-template <typename T, typename V, int TM, int TN>
-__device__ __forceinline__ void trace_epilogue(char* arena, const HecDesc& h, int t, int N, int r_wave, int c_wave,
-                                               const V (&cr)[TM][TN], const V (&ci)[TM][TN], int lane) {
-  const int nb = h.tr_nb, li = lane & 15, lk = lane >> 4;
-  const int64_t NN = (int64_t)N * N;
-  const T* P = reinterpret_cast<const T*>(arena + h.tr_p_off) + (int64_t)t * 2 * NN;
-  double* part = reinterpret_cast<double*>(arena + h.tr_part_off) + (int64_t)t * nb * nb * 2;
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      const int r0 = r_wave + i * 16, c0 = c_wave + j * 16;
-      const int bi = r0 >> 4, bj = c0 >> 4;
-      if (bi >= nb || bj >= nb) continue;         // the whole block lies outside N x N
-      T qr[4], qi[4], pr[4], pi[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = r0 + Mfma<T>::row(lk, v), c = c0 + li;
-        const bool ok = r < N && c < N;
-        const int64_t po = (int64_t)c * N + r;
-        qr[v] = ok ? (T)cr[i][j][v] : T(0);
-        qi[v] = ok ? (T)ci[i][j][v] : T(0);
-        pr[v] = ok ? P[po] : T(0);
-        pi[v] = ok ? P[NN + po] : T(0);
-      }
-      double sr, si;
-      trace_block<T>(qr, qi, pr, pi, sr, si);
-      if (lane == 0) {
-        part[2 * (bi * nb + bj)] = sr;
-        part[2 * (bi * nb + bj) + 1] = si;
-      }
-    }
 }
 
 // ST: LDS stages.  2 = double buffer (one barrier per k-chunk); 1 = one
@@ -412,8 +349,6 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
       for (int j = 0; j < TN; ++j)
         store_block<T, V>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li, cr[i][j],
                           ci[i][j], lk);
-    if (h.tr_p_off >= 0) trace_epilogue<T, V, TM, TN>(arena, h, cur.t, N, cur.m0 + wm * TM * 16,
-                                                      cur.n0 + wn * TN * 16, cr, ci, lane);
     if (!has_next) break;
     item = next;
     if (PF) {
@@ -591,8 +526,6 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
       for (int j = 0; j < TN; ++j)
         store_block<float, v4f>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li,
                                 cr[i][j], ci[i][j], lk);
-    if (h.tr_p_off >= 0) trace_epilogue<float, v4f, TM, TN>(arena, h, cur.t, N, cur.m0 + wm * TM * 16,
-                                                            cur.n0 + wn * TN * 16, cr, ci, lane);
     if (!has_next) break;
     item = next;
     if (PF) {
@@ -622,54 +555,82 @@ __global__ void __launch_bounds__(256) splitk_reduce(char* __restrict__ arena, c
 }
 
 // ------------------------------------------------------------------ root trace (FP64)
-// Root trace C(t) = sum_rc Q[r][c] P[c][r], one wave per (root, t), four per
-// workgroup: the sum over the 16x16 blocks of Q in row-major order of the
-// block partials of trace_block, either read from the partial buffer (written
-// by the kernel that produced Q) or computed here from P and Q in memory.
+// 4 consecutive elements of one row: vector loads when all 4 are in range and
+// the row is 4-element aligned, otherwise element-wise with zero fill.
+template <typename T>
+__device__ __forceinline__ void load4(T (&r)[4], const T* src, int valid, bool vec) {
+  if (vec && valid == 4) {
+    typedef typename Vec2<T>::V V;
+    constexpr int W = Vec2<T>::n;
+    const V* s = reinterpret_cast<const V*>(src);
+#pragma unroll
+    for (int q = 0; q < 4 / W; ++q) {
+      V v = s[q];
+      const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+      for (int x = 0; x < W; ++x) r[q * W + x] = e[x];
+    }
+  } else {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) r[x] = x < valid ? src[x] : T(0);
+  }
+}
+
+// C(t) = sum_ij P[i,j] Q[j,i]: one wave per (root, t), four per workgroup.
+// Lane l takes the 4 x 4 blocks b = l, l + 64, ... with block row ib = b / nb
+// and block column jb = b % nb (nb = ceil(N / 4)): it reads rows 4ib.. of P
+// over columns 4jb.. and rows 4jb.. of Q over columns 4ib.., so every load is
+// a row segment and the transpose happens in registers (no LDS, no barrier).
+// Products and sums in FP64 (exact products for FP32 inputs); each lane adds
+// its blocks in order and the 64 lane sums meet in a fixed butterfly, so the
+// result depends only on the data and N.
 template <typename T>
 __global__ void __launch_bounds__(256) hca_trace(char* __restrict__ arena, const HcaDesc* __restrict__ descs,
                                                  int n_desc, int64_t n_items) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t base = (int64_t)blockIdx.x * 4; base < n_items; base += (int64_t)gridDim.x * 4) {
     const int64_t item = base + wave;
     if (item >= n_items) break;
     const int di = find_desc(&descs[0].item_begin, sizeof(HcaDesc) / 4, n_desc, item);
     const HcaDesc& h = descs[di];
-    const int t = (int)(item - h.item_begin), n = h.n, nb = (n + 15) >> 4;
+    const int t = (int)(item - h.item_begin), n = h.n;
     const int64_t nn = (int64_t)n * n;
-    double cr = 0.0, ci = 0.0;
-    if (h.fused) {
-      const double* part = reinterpret_cast<const double*>(arena + h.part_off) + (int64_t)t * nb * nb * 2;
-      for (int b = 0; b < nb * nb; ++b) {
-        cr += part[2 * b];
-        ci += part[2 * b + 1];
-      }
-    } else {
-      const T* P = reinterpret_cast<const T*>(arena + h.p_off) + (int64_t)t * 2 * nn;
-      const T* Q = reinterpret_cast<const T*>(arena + h.q_off) + (int64_t)t * 2 * nn;
-      for (int bi = 0; bi < nb; ++bi)
-        for (int bj = 0; bj < nb; ++bj) {
-          T qr[4], qi[4], pr[4], pi[4];
+    const T* P = reinterpret_cast<const T*>(arena + h.p_off) + (int64_t)t * 2 * nn;
+    const T* Q = reinterpret_cast<const T*>(arena + h.q_off) + (int64_t)t * 2 * nn;
+    const int nb = (n + 3) >> 2;
+    const bool vec = (n & 3) == 0;
+    double sr = 0.0, si = 0.0;
+    for (int b = lane; b < nb * nb; b += 64) {
+      const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
+      const int vj = min(4, n - j0), vi = min(4, n - i0);
+      T pr[4][4], pi[4][4], qr[4][4], qi[4][4];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int r = 16 * bi + Mfma<T>::row(lk, v), c = 16 * bj + li;
-            const bool ok = r < n && c < n;
-            const int64_t qo = (int64_t)r * n + c, po = (int64_t)c * n + r;
-            qr[v] = ok ? Q[qo] : T(0);
-            qi[v] = ok ? Q[nn + qo] : T(0);
-            pr[v] = ok ? P[po] : T(0);
-            pi[v] = ok ? P[nn + po] : T(0);
-          }
-          double sr, si;
-          trace_block<T>(qr, qi, pr, pi, sr, si);
-          cr += sr;
-          ci += si;
+      for (int r = 0; r < 4; ++r) {
+        const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
+        load4<T>(pr[r], P + po, i0 + r < n ? vj : 0, vec);
+        load4<T>(pi[r], P + nn + po, i0 + r < n ? vj : 0, vec);
+        load4<T>(qr[r], Q + qo, j0 + r < n ? vi : 0, vec);
+        load4<T>(qi[r], Q + nn + qo, j0 + r < n ? vi : 0, vec);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double xr = (double)pr[a][c], xi = (double)pi[a][c];
+          const double yr = (double)qr[c][a], yi = (double)qi[c][a];
+          sr += xr * yr - xi * yi;
+          si += xr * yi + xi * yr;
         }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      sr += __shfl_xor(sr, o);
+      si += __shfl_xor(si, o);
     }
     if (lane == 0) {
       double* out = reinterpret_cast<double*>(arena + h.out_off);
-      out[2 * t] = cr;
-      out[2 * t + 1] = ci;
+      out[2 * t] = sr;
+      out[2 * t + 1] = si;
     }
   }
 }

@@ -179,27 +179,6 @@ def test_rank4_general_contractions(rank4_small, prec):
     assert err.max() <= TOL[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-def test_fused_traces_same_bits(meson_small, baryon_small, rank4_small, prec):
-    """Root traces fused into the producing contraction (leaves resident, no
-    evictions) give the same bits as the trace kernel computing them from
-    memory (leaves streamed), and match the oracle."""
-    ALL = 1 << 62
-    for name, (wl, ref), split in (("meson_small", meson_small, 1), ("baryon_small", baryon_small, 0),
-                                   ("rank4_small", rank4_small, 0)):
-        a = run(wl, "tree", prec, True, leaves_resident=True, wave_lookahead=ALL, tile=0, grid=1,
-                split_k=split)
-        b = run(wl, "tree", prec, True, leaves_resident=False, wave_lookahead=ALL, tile=0, grid=1,
-                split_k=split)
-        c = run(wl, "tree", prec, False, leaves_resident=False, tile=0, grid=1, split_k=split)
-        nf = a["stats"]["plan"]["n_fused_traces"]
-        print(f"{name} {prec}: {nf} fused traces of {a['stats']['plan']['n_roots']}")
-        assert nf > 0 and b["stats"]["plan"]["n_fused_traces"] == 0
-        assert rel_errors(a["corr"], ref).max() <= TOL[prec]
-        bits = [np.concatenate(r["corr"]).view(np.uint64) for r in (a, b, c)]
-        assert np.array_equal(bits[0], bits[1]) and np.array_equal(bits[0], bits[2])
-
-
 @pytest.mark.parametrize("in_situ", [False, True])
 def test_autotune_then_parity(baryon_small, in_situ):
     wl, ref = baryon_small

@@ -199,52 +199,6 @@ def test_general_kinds_flops_and_validation():
         c.build_cdag([_L(5), _L(2)], [_G([(W.HCA, 0, 1)])])
 
 
-def _expected_fused_traces(d, steps):
-    """Root traces the kernel plan fuses into the producer of their canonical
-    operand (the child of larger dependency level, right on a tie): the
-    canonical operand is a contraction with a rank-2 output not fused yet,
-    produced in a later step than the other operand (or the other is a leaf).
-    K22 only here, so no contraction is split."""
-    level = [0] * d.n_nodes
-    for u in range(d.n_leaves, d.n_nodes):
-        level[u] = 1 + max(level[d.left[u]], level[d.right[u]])
-    step = {u: s for s, us in enumerate(steps) for u in us}
-    fused, taken = 0, set()
-    for u in range(d.n_leaves, d.n_nodes):
-        if d.kind[u] != W.HCA:
-            continue
-        cr = level[d.right[u]] >= level[d.left[u]]
-        q, o = (d.right[u], d.left[u]) if cr else (d.left[u], d.right[u])
-        if d.kind[q] < 0 or q in taken:
-            continue
-        if d.kind[o] >= 0 and step[o] >= step[q]:
-            continue
-        taken.add(q)
-        fused += 1
-    return fused
-
-
-def test_trace_fusion_decisions():
-    wl = W.meson_ring(n_leaves=7, nvec=4, nt=2, n_graphs=40, lmin=3, lmax=6, seed=77, with_data=False)
-    d = OD.build(wl.leaves, wl.graphs)
-    c = ctx_for(wl)
-    order = [int(x) for x in c.schedule("tree")]
-    for look in (0, 3, B.LOOKAHEAD_ALL):
-        c.set_options(leaves_resident=True, wave_lookahead=look)
-        ref = OP.plan(d, order, budget=OP.UNLIMITED, batched=True, leaves_resident=True, lookahead=look)
-        p = c.plan("fp64", True)
-        assert p["n_evict"] == 0
-        assert p["n_fused_traces"] == _expected_fused_traces(d, ref["steps"]) > 0, look
-    c.set_options(leaves_resident=False, wave_lookahead=B.LOOKAHEAD_ALL)
-    assert c.plan("fp64", True)["n_fused_traces"] == 0          # leaves not resident
-    c.set_options(leaves_resident=True, wave_lookahead=B.LOOKAHEAD_ALL)
-    live = OS.memsim(d, order)["peak_live"]
-    c.set_mem_budget(live // 3)
-    assert c.plan("fp64", True)["n_evict"] > 0 and c.plan("fp64", True)["n_fused_traces"] == 0
-    c.set_mem_budget(None)
-    c.set_options(leaves_resident=False, wave_lookahead=0)
-
-
 def test_mixed_precision_plans_halve_sizes():
     wl = WORKLOADS[3]
     d = OD.build(wl.leaves, wl.graphs)
