@@ -3,9 +3,13 @@
 // cross-diagram sum.  Tensor layout and descriptors: desc.hpp.
 //
 // Exterior contraction = per time slice a complex GEMM C = A B with planar
-// (re, im) operands.  With real matrix-core products only:
-//   Re C = Ar Br - Ai Bi,  Im C = Ar Bi + Ai Br
-// i.e. four real products per complex multiply-add (the 8-flop ZGEMM count).
+// (re, im) operands.  With real matrix-core products only, either
+//   Re C = Ar Br - Ai Bi,  Im C = Ar Bi + Ai Br              (four products)
+// or Gauss's form with three,
+//   P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi),  Re C = P1 - P2,
+//   Im C = P3 - (P1 + P2).
+// Flop counts use the ZGEMM convention (8 flops per complex multiply-add)
+// whichever form runs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -278,11 +282,21 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
     ItemView<T> nxt = cur;
     if (PF && has_next) nxt = view_item<T, BM, BN>(arena, descs, n_desc, next);
 
-    V cr[TM][TN], ci[TM][TN];
+    // Complex products.  With G3 (Gauss), three real products per complex one:
+    // P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi), then Re = P1 - P2 and
+    // Im = P3 - (P1 + P2).  Otherwise four, Re (in P1) += Ar Br + Ai (-Bi) and
+    // Im (in P3) += Ar Bi + Ai Br.  G3 needs a third accumulator, so it is used
+    // only where a wave holds at most two 16 x 16 blocks.
+    constexpr bool G3 = TM * TN <= 2;
+    V p1[TM][TN], p2[TM][TN], p3[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) { cr[i][j] = V{0, 0, 0, 0}; ci[i][j] = V{0, 0, 0, 0}; }
+      for (int j = 0; j < TN; ++j) {
+        p1[i][j] = V{0, 0, 0, 0};
+        p2[i][j] = V{0, 0, 0, 0};
+        p3[i][j] = V{0, 0, 0, 0};
+      }
 
     const int nk = (cur.kend - cur.kbeg + BK - 1) / BK;
     if (ST == 2) {
@@ -302,7 +316,7 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
 #pragma unroll
       for (int k4 = 0; k4 < BK / 4; ++k4) {
         const int kk = 4 * k4 + lk;
-        T a_r[TM], a_i[TM], b_r[TN], b_i[TN], b_n[TN];
+        T a_r[TM], a_i[TM], b_r[TN], b_i[TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
           a_r[i] = As[st][0][(wm * TM + i) * 16 + li][kk];
@@ -312,25 +326,37 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
         for (int j = 0; j < TN; ++j) {
           b_r[j] = Bs[st][0][kk][(wn * TN + j) * 16 + li];
           b_i[j] = Bs[st][1][kk][(wn * TN + j) * 16 + li];
-          b_n[j] = -b_i[j];
         }
-        // Re += Ar Br + Ai (-Bi), Im += Ar Bi + Ai Br.  Consecutive instructions
-        // go to different accumulators; each accumulator still adds its two
-        // products in the same order.
+        if constexpr (G3) {
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+          for (int i = 0; i < TM; ++i)
 #pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            cr[i][j] = Mfma<T>::mma(a_r[i], b_r[j], cr[i][j]);
-            ci[i][j] = Mfma<T>::mma(a_r[i], b_i[j], ci[i][j]);
-          }
+            for (int j = 0; j < TN; ++j) {
+              p1[i][j] = Mfma<T>::mma(a_r[i], b_r[j], p1[i][j]);
+              p2[i][j] = Mfma<T>::mma(a_i[i], b_i[j], p2[i][j]);
+              p3[i][j] = Mfma<T>::mma(a_r[i] + a_i[i], b_r[j] + b_i[j], p3[i][j]);
+            }
+        } else {
+          T b_n[TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+          for (int j = 0; j < TN; ++j) b_n[j] = -b_i[j];
+          // Consecutive instructions go to different accumulators; each
+          // accumulator still adds its two products in the same order.
 #pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            cr[i][j] = Mfma<T>::mma(a_i[i], b_n[j], cr[i][j]);
-            ci[i][j] = Mfma<T>::mma(a_i[i], b_r[j], ci[i][j]);
-          }
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              p1[i][j] = Mfma<T>::mma(a_r[i], b_r[j], p1[i][j]);
+              p3[i][j] = Mfma<T>::mma(a_r[i], b_i[j], p3[i][j]);
+            }
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              p1[i][j] = Mfma<T>::mma(a_i[i], b_n[j], p1[i][j]);
+              p3[i][j] = Mfma<T>::mma(a_i[i], b_r[j], p3[i][j]);
+            }
+        }
       }
       if (ST == 2 && c + 1 < nk) sstore(st ^ 1);
       __syncthreads();
@@ -346,9 +372,17 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
-        store_block<T, V>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li, cr[i][j],
-                          ci[i][j], lk);
+      for (int j = 0; j < TN; ++j) {
+        V re = p1[i][j], im = p3[i][j];
+        if constexpr (G3) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            re[v] = p1[i][j][v] - p2[i][j][v];
+            im[v] = p3[i][j][v] - (p1[i][j][v] + p2[i][j][v]);
+          }
+        }
+        store_block<T, V>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li, re, im, lk);
+      }
     if (!has_next) break;
     item = next;
     if (PF) {

@@ -281,7 +281,13 @@ def test_identity_trace_exact(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_times_identity_and_selector_exact(prec):
+@pytest.mark.parametrize("tile", [0, 1])
+def test_times_identity_and_selector(prec, tile):
+    """X I and a selector tensor against the direct trace.  Tile 0 (64 x 64,
+    four real products per complex one) reproduces the direct trace bit for
+    bit: every product is by 0 or 1 and every sum adds zeros.  Tile 1 (32 x 32,
+    Gauss's three products) rounds Ar + Ai and then cancels Ar against it, so
+    there the two agree only to rounding."""
     rng = np.random.default_rng(3)
     nt, n = 3, 24
     X2 = W._draw(rng, (nt, n, n), 0.5)
@@ -298,10 +304,14 @@ def test_times_identity_and_selector_exact(prec):
               W.GraphSpec([(W.K33, 3, 4), (W.HCA, -1, 2)]),      # tr(K33(X3, E) Y)
               W.GraphSpec([(W.HCA, 5, 2)])]                       # tr(X3[..,0] Y)
     wl = W.Workload("exact", leaves, graphs)
-    r = run(wl, "input", prec, False)
+    r = run(wl, "input", prec, False, tile=tile)
     c = r["corr"]
-    assert np.array_equal(c[0], c[1])
-    assert np.array_equal(c[2], c[3])
+    if tile == 0:
+        assert np.array_equal(c[0], c[1])
+        assert np.array_equal(c[2], c[3])
+    else:
+        bound = 1e-13 if prec == "fp64" else TOL[prec]
+        assert rel_errors(c, {0: c[1], 2: c[3]}).max() <= bound
     if prec == "fp64":
         ref = OV.correlators(wl)
         assert rel_errors(c, ref).max() <= 1e-13
