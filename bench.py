@@ -230,6 +230,35 @@ def corr_func_study(rows=None):
     return out
 
 
+def general_study(shares=(0.02, 0.05, 0.1), n_trees=40000):
+    """Host-only: input order and Tree on general DAGs whose nodes have one to
+    four children (synth/general.py: 400 leaves, trees of depth 3, an inner slot
+    reusing an existing node with probability `share`).  Per DAG: size, F_v and
+    F_e, the wall time of each schedule call and its peak memory (node sizes in
+    bytes, 1..1000 per node, roots 0)."""
+    from synth.general import random_general
+    import paper_2511_02257_amd as X
+    out = []
+    for share in shares:
+        nl, sizes, kids = random_general(7, n_leaves=400, n_trees=n_trees, max_arity=4, depth=3,
+                                         share=share)
+        ctx = X.Context()
+        ctx.build_general(nl, sizes, kids)
+        res = {"share": share, **{k: (round(v, 3) if isinstance(v, float) else v)
+                                  for k, v in ctx.dag_stats().items()}}
+        for policy in ("input", "tree"):
+            t0 = time.perf_counter()
+            order = ctx.schedule(policy)
+            dt = time.perf_counter() - t0
+            _, pp, pl = ctx.memsim(order)
+            res[policy] = {"ms": round(dt * 1e3, 1), "peak_post": int(pp), "peak_live": int(pl)}
+        res["input_over_tree"] = round(res["input"]["peak_post"] / max(1, res["tree"]["peak_post"]), 3)
+        log("general", res)
+        out.append(res)
+        ctx.close()
+    return out
+
+
 def cpu_baseline(wl, seconds=12.0):
     """The oracle (numpy complex128, each graph on its own) on a bounded sample."""
     from oracle import values as OV
@@ -273,7 +302,7 @@ def main():
     ap.add_argument("--variants-from", default=None, metavar="JSON",
                     help="with --workload baryon_mix or batched: take the kernel choices from the "
                          "JSON line of an earlier run of the same workload instead of autotuning")
-    ap.add_argument("--study", default=None, choices=("corr_func",),
+    ap.add_argument("--study", default=None, choices=("corr_func", "general"),
                     help="host-only: peak memory and scheduler time on the Table corr-func-shaped "
                          "DAGs (no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -292,6 +321,9 @@ def main():
         return
     if args.study == "corr_func":
         print(json.dumps({"study": "corr_func", "rows": corr_func_study()}), flush=True)
+        return
+    if args.study == "general":
+        print(json.dumps({"study": "general", "dags": general_study()}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is not "

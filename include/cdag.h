@@ -163,6 +163,26 @@ const char* cdag_last_error(void);
 int build_cdag(cdag_ctx* c, const cdag_leaf* leaves, int64_t n_leaves,
                const cdag_graph* graphs, int64_t n_graphs);
 
+/* Host-only: a general DAG for scheduling and the memory model, whose nodes
+ * may have any number of children (Sec. II-B notes that the schedulers extend
+ * to that case; Sec. III-B that the Tree scheduler needs neither two children
+ * per node nor trees that are trees).  Nodes 0..n_leaves-1 are leaves; node
+ * u >= n_leaves has the children child[child_off[u] .. child_off[u+1]-1]
+ * (operand order; ids below u; no repeats; at least one); size_bytes[u] is
+ * the size of u's tensor in bytes.  Trees are rooted at the non-leaf nodes
+ * without parents, in ascending id.  All three arrays are read during the
+ * call only (child_off has n_nodes + 1 entries, child_off[0] = 0).  Replaces
+ * the DAG like build_cdag.  Afterwards schedule (input order and Tree; Sibling
+ * only when every non-leaf has two children), cdag_memsim (elem_bytes is then
+ * ignored: the given sizes apply), cdag_get_nodes (kind 7 for non-leaves,
+ * left/right for two-child nodes, else -1) and cdag_dag_stats apply;
+ * cdag_plan, execute and cdag_autotune return CDAG_E_STATE.
+ * CDAG_E_INVALID: counts out of range (n_nodes < 2^31), a NULL array, a
+ * decreasing child_off, a leaf with children, a non-leaf without, a child id
+ * outside [0, u), a repeated child, a negative size. */
+int cdag_build_general(cdag_ctx* c, int64_t n_nodes, int64_t n_leaves, const int64_t* size_bytes,
+                       const int64_t* child_off, const int64_t* child);
+
 /* Order the contractions.  order_out (nullable, capacity cap) receives node
  * ids; *n_out (nullable) the number of contractions. */
 int schedule(cdag_ctx* c, int policy, int64_t* order_out, int64_t cap, int64_t* n_out);
@@ -196,8 +216,10 @@ int cdag_launch_records(cdag_ctx* c, cdag_launch_record* out, int64_t cap, int64
 /* Kernel variant of the exterior contractions of `kind` (K22, K32, K33, C1,
  * C2 or C3; a general kind shares one entry over all its operand ranks)
  * with N = nvec in precision `prec`.  tile: 0 = 64x64, 1 = 32x32, 2 = 48x48,
- * 3 = 128x64, 4 = 64x32 (output rows x columns per workgroup), -1 removes an
- * explicit choice.  grid: 0 = persistent (compute units x occupancy
+ * 3 = 128x64, 4 = 64x32, 5 = 64x64 with 512 threads (output rows x columns
+ * per workgroup), -1 removes an explicit choice.  In FP64 and FP32, tiles 1,
+ * 4 and 5 form each complex product from three real ones (Gauss), the others
+ * from four.  grid: 0 = persistent (compute units x occupancy
  * workgroups striding over the work list), 1 = one workgroup per work item.
  * lds_stages: 2 = double-buffered operand tiles in LDS, 1 = a single buffer
  * refilled from registers (half the LDS, more workgroups per compute unit).
@@ -214,7 +236,8 @@ int cdag_get_tile(cdag_ctx* c, int prec, int kind, int nvec, int* tile, int* gri
                   int* split_k);
 
 /* Host-only: simulate Sec. II-C for `order` (n node ids, each contraction
- * once, topological) with element size elem_bytes (16 or 8).  M_out
+ * once, topological) with element size elem_bytes (16 or 8; a general DAG
+ * uses its given sizes).  M_out
  * (nullable, capacity n) receives M_1..M_n. */
 int cdag_memsim(cdag_ctx* c, const int64_t* order, int64_t n, int elem_bytes,
                 int64_t* M_out, int64_t* peak_post, int64_t* peak_live);

@@ -3,7 +3,8 @@
 Plain, slow, obviously-correct Python/numpy implementations of what the GPU
 path computes, written from the paper's definitions:
 
-  dag.py        CDAG formation from contraction trees (Sec. II-B).
+  dag.py        CDAG formation from contraction trees (Sec. II-B), and general
+                DAGs whose nodes have any number of children.
   schedules.py  input-order, Sibling (Algs. 1-3) and Tree (Sec. III-B, from the
                 gain definition M - M' rather than the incremental Algs. 5-8),
                 the memory model of Sec. II-C, and a brute-force optimum.

@@ -1,4 +1,5 @@
-"""Contraction DAG formation (Sec. II-B, "Notation").
+"""Contraction DAG formation (Sec. II-B, "Notation"), and general DAGs whose
+nodes have any number of children (for scheduling only).
 
 Each input graph is a binary contraction tree.  Structurally identical
 contractions (same kind, same ordered children) are one DAG node, so trees
@@ -178,6 +179,61 @@ def build(leaves, graphs) -> Dag:
         if root not in roots_seen:
             roots_seen.add(root)
             d.tree_roots.append(root)
+    return d
+
+
+NARY = 7   # a node of a general DAG
+
+
+@dataclass
+class GeneralDag(Dag):
+    """A DAG whose nodes may have any number of children, with sizes given per node
+    in bytes.  Sec. II-B remarks that the schedulers extend to nodes with any number
+    of children, and Sec. III-B that the Tree scheduler needs neither two children
+    per node nor trees that are trees.  Only scheduling and the memory model apply:
+    there are no tensor shapes."""
+    kids: List[Tuple[int, ...]] = field(default_factory=list)
+    sizes: List[int] = field(default_factory=list)
+
+    def children(self, u: int) -> Tuple[int, ...]:
+        return self.kids[u]
+
+    def size(self, u: int, elem_bytes: int = 16) -> int:
+        return self.sizes[u]
+
+
+def general(n_leaves: int, sizes, children) -> GeneralDag:
+    """Nodes 0..n_leaves-1 are leaves; node u lists its children (operand order,
+    ids below u, no repeats, at least one for a non-leaf).  Trees are rooted at the
+    non-leaf nodes without parents, in ascending id; parents(u) has one entry per
+    edge, node by node and children in order.  Raises InvalidGraph on bad input."""
+    n = len(sizes)
+    if len(children) != n or not 0 <= n_leaves <= n:
+        raise InvalidGraph("counts")
+    d = GeneralDag(n_leaves=n_leaves)
+    for u in range(n):
+        kids = tuple(int(x) for x in children[u])
+        if sizes[u] < 0:
+            raise InvalidGraph("negative size")
+        if u < n_leaves and kids:
+            raise InvalidGraph("a leaf has no children")
+        if u >= n_leaves and not kids:
+            raise InvalidGraph("a non-leaf node needs a child")
+        if any(not 0 <= x < u for x in kids) or len(set(kids)) != len(kids):
+            raise InvalidGraph("child ids must be distinct and below the node")
+        d.kids.append(kids)
+        d.sizes.append(int(sizes[u]))
+        d.kind.append(-1 if u < n_leaves else NARY)
+        d.left.append(kids[0] if len(kids) == 2 else -1)
+        d.right.append(kids[1] if len(kids) == 2 else -1)
+        d.rank.append(0)
+        d.nvec.append(0)
+        d.nt.append(0)
+        d.parents.append([])
+        for x in kids:
+            d.parents[x].append(u)
+    d.tree_roots = [u for u in range(n_leaves, n) if not d.parents[u]]
+    d.root_of_graph = list(d.tree_roots)
     return d
 
 

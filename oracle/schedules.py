@@ -1,7 +1,8 @@
 """Contraction orders and the memory model (Sec. II-C and Sec. III).
 
-input_order  graphs in input order, each root's subtree in post-order, left child
-             first, each contraction emitted once (the plain baseline).
+input_order  graphs in input order, each root's subtree in post-order, children
+             in operand order (left first), each contraction emitted once (the
+             plain baseline).
 sibling      the Sibling scheduler, Algs. 1-3 (SB-SCHEDULER, SB-PROCESS,
              SB-PROP-DOWN), Eq. (1) for ranks.
 tree         the Tree scheduler written from its definition: repeatedly pick the
@@ -41,8 +42,8 @@ def input_order(d: Dag) -> List[int]:
     def visit(u):
         if u in done or d.kind[u] < 0:
             return
-        visit(d.left[u])
-        visit(d.right[u])
+        for c in d.children(u):
+            visit(c)
         done.add(u)
         order.append(u)
 
@@ -65,6 +66,10 @@ def ranks(d: Dag) -> List[int]:
 
 
 def sibling(d: Dag) -> List[int]:
+    """Algs. 1-3; the sibling of a node is its parent's other child, so every
+    contraction must have exactly two children (ValueError otherwise)."""
+    if any(len(d.children(u)) != 2 for u in d.contractions()):
+        raise ValueError("sibling: every contraction needs two children")
     rank = ranks(d)
     rs = [len(d.parents[u]) for u in range(d.n_nodes)]
     rp = [len(d.children(u)) for u in range(d.n_nodes)]

@@ -94,6 +94,7 @@ def lib():
             "cdag_create": [C.POINTER(C.c_void_p)],
             "cdag_destroy": [P],
             "build_cdag": [P, C.POINTER(cdag_leaf), I64, C.POINTER(cdag_graph), I64],
+            "cdag_build_general": [P, I64, I64, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
             "schedule": [P, C.c_int, C.POINTER(I64), I64, C.POINTER(I64)],
             "set_mem_budget": [P, C.c_uint64],
             "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
@@ -126,7 +127,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "schedule",
+EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "cdag_build_general", "schedule",
             "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_launch_records", "cdag_dag_stats", "cdag_set_tile", "cdag_get_tile", "cdag_memsim", "cdag_plan", "cdag_plan_ops",
             "cdag_get_nodes", "cdag_graph_roots", "cdag_bind_device", "cdag_bind_arena",
             "execute", "cdag_autotune", "fetch_correlators", "cdag_fetch_sums")
@@ -188,6 +189,20 @@ def build_cdag(h, leaves: Sequence, graphs: Sequence) -> None:
         G[g].w_re, G[g].w_im = w.real, w.imag
     _check(lib().build_cdag(h, L, n, G, len(graphs)))
     del keep
+
+
+def cdag_build_general(h, n_leaves: int, sizes: Sequence[int], children: Sequence[Sequence[int]]) -> None:
+    """A general DAG: sizes[u] in bytes for every node, children[u] (empty for the
+    n_leaves leaves) in operand order."""
+    n = len(sizes)
+    if len(children) != n:
+        raise ValueError("sizes and children differ in length")
+    size = np.ascontiguousarray(sizes, dtype=np.int64)
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(c) for c in children])
+    flat = np.ascontiguousarray([x for c in children for x in c] or [0], dtype=np.int64)
+    _check(lib().cdag_build_general(h, n, int(n_leaves), _i64p(size) if n else None, _i64p(off),
+                                    _i64p(flat)))
 
 
 def schedule(h, policy: str, check: bool = False) -> np.ndarray:
@@ -386,6 +401,10 @@ class Context:
         for spec, nt in zip(graphs, nt_of):
             self.corr_nt[int(getattr(spec, "corr", 0))] = nt
         self.n_graphs = len(graphs)
+
+    def build_general(self, n_leaves, sizes, children):
+        cdag_build_general(self.h, n_leaves, sizes, children)
+        self.graph_nt, self.corr_nt, self.n_graphs = [], [], 0
 
     def schedule(self, policy, check=False):
         return schedule(self.h, policy, check)

@@ -52,6 +52,7 @@ int elem_bytes_prec(int prec) {
 namespace cdag {
 void ensure_plan(Ctx& c, int prec, int batched) {
   need(c.built, CDAG_E_STATE, "build_cdag first");
+  need(!c.dag.general, CDAG_E_STATE, "a general DAG has no tensor shapes: it can be scheduled and simulated only");
   need(c.scheduled, CDAG_E_STATE, "schedule first");
   const int eb = elem_bytes_prec(prec);
   batched = batched ? 1 : 0;
@@ -146,6 +147,26 @@ int build_cdag(cdag_ctx* h, const cdag_leaf* leaves, int64_t n_leaves, const cda
     c.leaf_dtype = std::move(dtypes);
     c.has_data = with_data > 0;
     c.n_corr = n_corr;
+    c.built = true;
+    c.data_version++;
+    c.scheduled = false;
+    c.planned = false;
+    c.have_results = false;
+    c.version++;
+  });
+}
+
+int cdag_build_general(cdag_ctx* h, int64_t n_nodes, int64_t n_leaves, const int64_t* size_bytes,
+                       const int64_t* child_off, const int64_t* child) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    cdag::Ctx& c = h->c;
+    cdag::Dag d = cdag::build_general(n_nodes, n_leaves, size_bytes, child_off, child);
+    c.dag = std::move(d);
+    c.leaf_data.clear();
+    c.leaf_dtype.clear();
+    c.has_data = false;
+    c.n_corr = 0;
     c.built = true;
     c.data_version++;
     c.scheduled = false;
@@ -359,12 +380,12 @@ int cdag_dag_stats(cdag_ctx* h, int64_t* n_vertices, int64_t* n_edges, int64_t* 
   return guard([&] {
     need(h->c.built, CDAG_E_STATE, "build_cdag first");
     const cdag::Dag& d = h->c.dag;
-    const int64_t V = d.n_nodes(), E = 2 * (V - d.n_leaves);
+    const int64_t V = d.n_nodes(), E = (int64_t)d.child.size();
     double sv = 0, se = 0;
     for (int64_t u = 0; u < V; ++u) {
       const int64_t c = d.ctree_off[u + 1] - d.ctree_off[u];
       sv += (double)c;
-      if (!d.is_leaf(u)) se += 2.0 * (double)c;
+      se += (double)d.n_children(u) * (double)c;
     }
     if (n_vertices) *n_vertices = V;
     if (n_edges) *n_edges = E;

@@ -26,6 +26,44 @@ int64_t ipow(int64_t n, int e) {
 }
 
 [[noreturn]] void invalid(const std::string& m) { throw Error(CDAG_E_INVALID, m); }
+
+// Parents, tree node sets and per-node tree lists from the children and the
+// tree roots.
+void finish(Dag& d) {
+  const int64_t n = d.n_nodes();
+  // parents in edge-creation order: node by node, children in operand order
+  std::vector<int64_t> cnt(n + 1, 0);
+  for (int64_t x : d.child) cnt[x]++;
+  d.par_off.assign(n + 1, 0);
+  for (int64_t u = 0; u < n; ++u) d.par_off[u + 1] = d.par_off[u] + cnt[u];
+  d.par.assign(d.par_off[n], -1);
+  std::vector<int64_t> fill(d.par_off.begin(), d.par_off.end() - 1);
+  for (int64_t u = d.n_leaves; u < n; ++u)
+    for (const int64_t* x = d.children_begin(u); x != d.children_end(u); ++x) d.par[fill[*x]++] = u;
+  // tree node sets: post-order DFS from each unique root, children in order
+  const int64_t k = (int64_t)d.tree_root.size();
+  d.tree_off.assign(1, 0);
+  std::vector<int64_t> mark(n, -1);
+  std::vector<std::vector<int64_t>> ct(n);
+  for (int64_t t = 0; t < k; ++t) {
+    // iterative post-order: (node, state) pairs, state 0 = expand, 1 = emit
+    std::vector<std::pair<int64_t, int>> st{{d.tree_root[t], 0}};
+    while (!st.empty()) {
+      auto [u, s] = st.back();
+      st.pop_back();
+      if (s == 1) { d.tree_nodes.push_back(u); ct[u].push_back(t); continue; }
+      if (mark[u] == t) continue;
+      mark[u] = t;
+      st.push_back({u, 1});
+      for (const int64_t* x = d.children_end(u); x != d.children_begin(u);) st.push_back({*--x, 0});
+    }
+    d.tree_off.push_back((int64_t)d.tree_nodes.size());
+  }
+  d.ctree_off.assign(n + 1, 0);
+  for (int64_t u = 0; u < n; ++u) d.ctree_off[u + 1] = d.ctree_off[u] + (int64_t)ct[u].size();
+  d.ctree.reserve(d.ctree_off[n]);
+  for (int64_t u = 0; u < n; ++u) d.ctree.insert(d.ctree.end(), ct[u].begin(), ct[u].end());
+}
 }  // namespace
 
 bool Dag::in_tree(int64_t u, int64_t t) const {
@@ -145,43 +183,65 @@ Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs)
     }
   }
   const int64_t n = d.n_nodes();
-  // parents in edge-creation order: node by node, left edge then right edge
-  std::vector<int64_t> cnt(n + 1, 0);
-  for (int64_t u = d.n_leaves; u < n; ++u) { cnt[d.left[u]]++; cnt[d.right[u]]++; }
-  d.par_off.assign(n + 1, 0);
-  for (int64_t u = 0; u < n; ++u) d.par_off[u + 1] = d.par_off[u] + cnt[u];
-  d.par.assign(d.par_off[n], -1);
-  std::vector<int64_t> fill(d.par_off.begin(), d.par_off.end() - 1);
+  d.child_off.assign(n + 1, 0);
+  for (int64_t u = 0; u < n; ++u) d.child_off[u + 1] = d.child_off[u] + (d.is_leaf(u) ? 0 : 2);
+  d.child.reserve(d.child_off[n]);
   for (int64_t u = d.n_leaves; u < n; ++u) {
-    d.par[fill[d.left[u]]++] = u;
-    d.par[fill[d.right[u]]++] = u;
+    d.child.push_back(d.left[u]);
+    d.child.push_back(d.right[u]);
   }
-  // tree node sets: post-order DFS from each unique root, left first
-  const int64_t k = (int64_t)d.tree_root.size();
-  d.tree_off.assign(1, 0);
-  std::vector<int64_t> mark(n, -1), stack;
-  std::vector<std::vector<int64_t>> ct(n);
-  for (int64_t t = 0; t < k; ++t) {
-    // iterative post-order: (node, state) pairs, state 0 = expand, 1 = emit
-    std::vector<std::pair<int64_t, int>> st{{d.tree_root[t], 0}};
-    while (!st.empty()) {
-      auto [u, s] = st.back();
-      st.pop_back();
-      if (s == 1) { d.tree_nodes.push_back(u); ct[u].push_back(t); continue; }
-      if (mark[u] == t) continue;
-      mark[u] = t;
-      st.push_back({u, 1});
-      if (!d.is_leaf(u)) {
-        st.push_back({d.right[u], 0});
-        st.push_back({d.left[u], 0});
+  finish(d);
+  return d;
+}
+
+Dag build_general(int64_t n_nodes, int64_t n_leaves, const int64_t* size, const int64_t* child_off,
+                  const int64_t* child) {
+  if (n_leaves < 0 || n_nodes < n_leaves || n_nodes >= (1LL << 31)) invalid("general: need 0 <= n_leaves <= n_nodes < 2^31");
+  if (n_nodes > 0 && (!size || !child_off)) invalid("general: size or child_off is NULL");
+  if (n_nodes > 0 && child_off[0] != 0) invalid("general: child_off[0] must be 0");
+  Dag d;
+  d.general = true;
+  d.n_leaves = n_leaves;
+  d.kind.assign(n_nodes, NARY);
+  d.rank.assign(n_nodes, 0);
+  d.nvec.assign(n_nodes, 0);
+  d.nt.assign(n_nodes, 0);
+  d.left.assign(n_nodes, -1);
+  d.right.assign(n_nodes, -1);
+  d.fixed_size.assign(size, size + n_nodes);
+  d.child_off.assign(n_nodes + 1, 0);
+  std::vector<int64_t> last_parent(n_nodes, -1);
+  for (int64_t u = 0; u < n_nodes; ++u) {
+    const std::string where = "general: node " + std::to_string(u) + ": ";
+    if (size[u] < 0) invalid(where + "negative size");
+    const int64_t b = child_off[u], e = child_off[u + 1];
+    if (e < b) invalid(where + "child_off must not decrease");
+    if (u < n_leaves) {
+      if (e != b) invalid(where + "a leaf has no children");
+      d.kind[u] = LEAF;
+    } else {
+      if (e == b) invalid(where + "a non-leaf node needs at least one child");
+      if (!child) invalid("general: child is NULL");
+      for (int64_t j = b; j < e; ++j) {
+        const int64_t x = child[j];
+        if (x < 0 || x >= u) invalid(where + "child ids must lie in [0, u)");
+        if (last_parent[x] == u) invalid(where + "repeated child");
+        last_parent[x] = u;
+        d.child.push_back(x);
+      }
+      if (e - b == 2) {
+        d.left[u] = child[b];
+        d.right[u] = child[b + 1];
       }
     }
-    d.tree_off.push_back((int64_t)d.tree_nodes.size());
+    d.child_off[u + 1] = (int64_t)d.child.size();
   }
-  d.ctree_off.assign(n + 1, 0);
-  for (int64_t u = 0; u < n; ++u) d.ctree_off[u + 1] = d.ctree_off[u] + (int64_t)ct[u].size();
-  d.ctree.reserve(d.ctree_off[n]);
-  for (int64_t u = 0; u < n; ++u) d.ctree.insert(d.ctree.end(), ct[u].begin(), ct[u].end());
+  std::vector<char> has_parent(n_nodes, 0);
+  for (int64_t x : d.child) has_parent[x] = 1;
+  for (int64_t u = n_leaves; u < n_nodes; ++u)
+    if (!has_parent[u]) d.tree_root.push_back(u);
+  d.root_of_graph = d.tree_root;
+  finish(d);
   return d;
 }
 

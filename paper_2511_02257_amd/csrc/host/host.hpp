@@ -14,7 +14,9 @@ namespace cdag {
 // last c axes of the left operand with the first c axes of the right one
 // (operand and output ranks 2..4); a general contraction with the ranks of a
 // named kind is stored as that kind.
-enum Kind : int32_t { K22 = 0, K32 = 1, K33 = 2, HCA = 3, C1 = 4, C2 = 5, C3 = 6, LEAF = -1 };
+// NARY marks a node of a general DAG (any number of children, sizes given
+// by the caller), which is scheduled and simulated but never executed.
+enum Kind : int32_t { K22 = 0, K32 = 1, K33 = 2, HCA = 3, C1 = 4, C2 = 5, C3 = 6, NARY = 7, LEAF = -1 };
 constexpr int kMinRank = 2, kMaxRank = 4;
 inline int contracted_axes(int kind) {
   switch (kind) {
@@ -35,7 +37,8 @@ struct Error : std::runtime_error {
 struct Dag {
   int64_t n_leaves = 0;
   std::vector<int32_t> kind, rank, nvec, nt;
-  std::vector<int64_t> left, right;
+  std::vector<int64_t> left, right;         // binary nodes; -1 otherwise
+  std::vector<int64_t> child_off, child;    // CSR children in operand order (left, right)
   std::vector<int64_t> par_off, par;        // CSR parents, one entry per edge, in creation order
   std::vector<int64_t> root_of_graph;       // per input graph
   std::vector<int64_t> tree_root;           // unique roots, first-appearance order
@@ -44,10 +47,17 @@ struct Dag {
   // per input graph: correlator id and weight
   std::vector<int32_t> corr;
   std::vector<double> w_re, w_im;
+  // A general DAG (build_general) carries per-node sizes in bytes instead of
+  // tensor shapes; it can be scheduled and simulated, not planned or run.
+  bool general = false;
+  std::vector<int64_t> fixed_size;
 
   int64_t n_nodes() const { return (int64_t)kind.size(); }
   bool is_leaf(int64_t u) const { return kind[u] < 0; }
   int64_t n_parents(int64_t u) const { return par_off[u + 1] - par_off[u]; }
+  int64_t n_children(int64_t u) const { return child_off[u + 1] - child_off[u]; }
+  const int64_t* children_begin(int64_t u) const { return child.data() + child_off[u]; }
+  const int64_t* children_end(int64_t u) const { return child.data() + child_off[u + 1]; }
   int64_t elems(int64_t u) const {
     int64_t e = nt[u];
     for (int r = 0; r < rank[u]; ++r) e *= nvec[u];
@@ -55,7 +65,10 @@ struct Dag {
   }
   // Bytes of u's tensor in a mode with elem_bytes per complex element; a root's
   // per-t scalar goes straight into the correlator buffer and counts 0.
-  int64_t size(int64_t u, int elem_bytes) const { return kind[u] == HCA ? 0 : elems(u) * elem_bytes; }
+  int64_t size(int64_t u, int elem_bytes) const {
+    if (general) return fixed_size[u];
+    return kind[u] == HCA ? 0 : elems(u) * elem_bytes;
+  }
   bool in_tree(int64_t u, int64_t t) const;   // binary search in ctree(u)
   // Algorithmic flops of contraction u (8 per complex multiply-add).
   double flops(int64_t u) const;
@@ -69,8 +82,15 @@ struct OpIn { int32_t kind, left, right; };
 struct GraphIn { int32_t n_ops, corr; const OpIn* ops; double w_re, w_im; };
 
 Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs);
+// A general DAG: nodes 0..n_leaves-1 are leaves, every other node lists its
+// children (child_off/child, CSR, ids smaller than its own, no repeats) and
+// size[u] is the bytes of u's tensor.  Trees are rooted at the non-leaf nodes
+// without parents, in id order.  Throws Error(CDAG_E_INVALID) on bad input.
+Dag build_general(int64_t n_nodes, int64_t n_leaves, const int64_t* size, const int64_t* child_off,
+                  const int64_t* child);
 
 std::vector<int64_t> sched_input(const Dag& d);
+// Sibling needs every contraction to have exactly two children.
 std::vector<int64_t> sched_sibling(const Dag& d);
 // Tree scheduler; sizes in bytes of elem_bytes per element.  check=true
 // recomputes each live tree's gain from scratch at every selection and throws

@@ -9,6 +9,8 @@
 //     into tgain; PROCESS-CHILD removes u from x's AVAIL parents; ties in the
 //     argmax go to the lowest tree index; PROCESS-CTREE visits each not yet
 //     processed node of the tree once, in post-order, left child first.
+//   * Input order and Tree take any number of children per node (in operand
+//     order); Sibling, which uses a node's sibling, needs exactly two.
 #include <algorithm>
 #include <deque>
 #include <functional>
@@ -32,8 +34,7 @@ std::vector<int64_t> sched_input(const Dag& d) {
       if (d.is_leaf(u) || done[u]) continue;
       if (s == 1) { done[u] = 1; order.push_back(u); continue; }
       st.push_back({u, 1});
-      st.push_back({d.right[u], 0});
-      st.push_back({d.left[u], 0});
+      for (const int64_t* x = d.children_end(u); x != d.children_begin(u);) st.push_back({*--x, 0});
     }
   }
   return order;
@@ -52,6 +53,9 @@ struct Sibling {
   std::vector<int64_t> order;
   explicit Sibling(const Dag& dd) : d(dd) {
     const int64_t n = d.n_nodes();
+    for (int64_t u = d.n_leaves; u < n; ++u)
+      if (d.n_children(u) != 2)
+        throw Error(CDAG_E_INVALID, "sibling: node " + std::to_string(u) + " does not have two children");
     rank.assign(n, 0);
     int32_t qmax = 0;
     for (int64_t u = d.n_leaves; u < n; ++u) {   // Eq. (1); ids are topological
@@ -267,8 +271,7 @@ struct TreeSched {
       if (state[u] != AVAIL) continue;
       if (s == 1) {
         if (!d.is_leaf(u)) {
-          process_child(u, d.left[u]);
-          process_child(u, d.right[u]);
+          for (const int64_t* x = d.children_begin(u); x != d.children_end(u); ++x) process_child(u, *x);
           order.push_back(u);
         }
         process_node(u);
@@ -277,10 +280,7 @@ struct TreeSched {
       if (visit_mark[u] == t) continue;
       visit_mark[u] = t;
       st.push_back({u, 1});
-      if (!d.is_leaf(u)) {
-        st.push_back({d.right[u], 0});
-        st.push_back({d.left[u], 0});
-      }
+      for (const int64_t* x = d.children_end(u); x != d.children_begin(u);) st.push_back({*--x, 0});
     }
   }
 
@@ -291,8 +291,7 @@ struct TreeSched {
       if (state[d.tree_nodes[j]] == AVAIL) todo.push_back(d.tree_nodes[j]);
     std::sort(todo.begin(), todo.end());
     touched = todo;
-    for (int64_t u : todo)
-      if (!d.is_leaf(u)) { touched.push_back(d.left[u]); touched.push_back(d.right[u]); }
+    for (int64_t u : todo) touched.insert(touched.end(), d.children_begin(u), d.children_end(u));
     std::sort(touched.begin(), touched.end());
     touched.erase(std::unique(touched.begin(), touched.end()), touched.end());
     auto in_todo = [&](int64_t x) { return std::binary_search(todo.begin(), todo.end(), x); };
@@ -350,7 +349,8 @@ MemSim memsim(const Dag& d, const std::vector<int64_t>& order, int elem_bytes) {
     if (c < d.n_leaves || c >= n || seen[c]) throw Error(CDAG_E_INVALID, "memsim: order must list every contraction once");
     seen[c] = 1;
     int64_t brought = 0;
-    for (int64_t x : {d.left[c], d.right[c]}) {
+    for (const int64_t* px = d.children_begin(c); px != d.children_end(c); ++px) {
+      const int64_t x = *px;
       if (!in_mem[x]) {
         if (!d.is_leaf(x)) throw Error(CDAG_E_INVALID, "memsim: order is not topological");
         in_mem[x] = 1;
@@ -360,8 +360,8 @@ MemSim memsim(const Dag& d, const std::vector<int64_t>& order, int elem_bytes) {
     r.peak_live = std::max(r.peak_live, M + brought + d.size(c, elem_bytes));
     M += brought + d.size(c, elem_bytes);
     in_mem[c] = 1;
-    for (int64_t x : {d.left[c], d.right[c]})
-      if (--remaining[x] == 0) { in_mem[x] = 0; M -= d.size(x, elem_bytes); }
+    for (const int64_t* px = d.children_begin(c); px != d.children_end(c); ++px)
+      if (--remaining[*px] == 0) { in_mem[*px] = 0; M -= d.size(*px, elem_bytes); }
     if (remaining[c] == 0) { in_mem[c] = 0; M -= d.size(c, elem_bytes); }
     r.M.push_back(M);
     r.peak_post = std::max(r.peak_post, M);

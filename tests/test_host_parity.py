@@ -352,3 +352,83 @@ def test_tree_scheduler_speed_full_meson_ring():
     t0 = time.perf_counter()
     c.schedule("tree")
     assert time.perf_counter() - t0 < 5.0
+
+
+# ---------------------------------------------------------------- general DAGs (any number of children)
+def _general_cases():
+    from synth.general import random_general
+    for seed in range(40):
+        yield seed, random_general(seed, n_leaves=6 + seed % 10, n_trees=3 + seed % 12,
+                                   max_arity=1 + seed % 5, depth=2 + seed % 3,
+                                   share=(0.0, 0.2, 0.5)[seed % 3])
+
+
+@pytest.mark.parametrize("seed,case", list(_general_cases()))
+def test_general_dag_matches_oracle(seed, case):
+    """Input order, Tree (with its incremental gains checked against M - M' at
+    every pick), the memory model and the DAG statistics on general DAGs."""
+    nl, sizes, kids = case
+    d = OD.general(nl, sizes, kids)
+    c = X.Context()
+    c.build_general(nl, sizes, kids)
+    for pol in ("input", "tree"):
+        got = list(c.schedule(pol, check=(pol == "tree")))
+        ref = OS.schedule(d, pol)
+        assert got == ref, pol
+        M, post, live = c.memsim(got)
+        sim = OS.memsim(d, ref)
+        assert (list(M), post, live) == (sim["M"], sim["peak_post"], sim["peak_live"])
+    st, so = c.dag_stats(), OD.stats(d)
+    assert (st["n_vertices"], st["n_edges"], st["n_trees"]) == (so["n_nodes"], so["n_edges"], so["n_trees"])
+    assert st["f_v"] == pytest.approx(so["f_v"], abs=1e-12) and st["f_e"] == pytest.approx(so["f_e"], abs=1e-12)
+    if any(len(k) != 2 for k in kids[nl:]):
+        with pytest.raises(X.CdagError) as e:
+            c.schedule("sibling")
+        assert e.value.code == B.E_INVALID
+    c.close()
+
+
+def test_general_dag_of_a_contraction_dag():
+    """A contraction DAG handed over as a general DAG (its FP64 node sizes) gets
+    the same input, Sibling and Tree orders and memory figures as the original."""
+    wl = W.config("meson_ring", with_data=False)
+    c = ctx_for(wl)
+    kind, left, right = c.nodes()
+    d = OD.build(wl.leaves, wl.graphs)
+    kids = [d.children(u) for u in range(d.n_nodes)]
+    g = X.Context()
+    g.build_general(d.n_leaves, [d.size(u, 16) for u in range(d.n_nodes)], kids)
+    for pol in ("input", "sibling", "tree"):
+        a, b = list(c.schedule(pol)), list(g.schedule(pol))
+        assert a == b, pol
+        assert [list(x) if hasattr(x, "__len__") else x for x in c.memsim(a)] == \
+               [list(x) if hasattr(x, "__len__") else x for x in g.memsim(b)]
+    gk, gl, gr = g.nodes()
+    assert list(gl) == list(left) and list(gr) == list(right)
+    assert all(k == 7 for k in gk[d.n_leaves:]) and all(k == -1 for k in gk[:d.n_leaves])
+    c.close()
+    g.close()
+
+
+def test_general_dag_validation_and_state():
+    c = X.Context()
+    bad = [
+        (2, [1, 1, 1], [(), (), ()]),            # non-leaf without children
+        (2, [1, 1, 1], [(), (0,), (0, 1)]),      # leaf with a child
+        (2, [1, 1, 1], [(), (), (0, 0)]),        # repeated child
+        (2, [1, 1, 1], [(), (), (0, 2)]),        # child id not below the node
+        (2, [1, 1, -1], [(), (), (0, 1)]),       # negative size
+        (3, [1, 1], [(), ()]),                   # more leaves than nodes
+    ]
+    for nl, sizes, kids in bad:
+        with pytest.raises(X.CdagError) as e:
+            c.build_general(nl, sizes, kids)
+        assert e.value.code == B.E_INVALID
+    c.build_general(2, [4, 8, 0], [(), (), (0, 1)])
+    assert list(c.schedule("tree")) == [2]
+    M, post, live = c.memsim([2])
+    assert (list(M), post, live) == ([0], 0, 12)
+    with pytest.raises(X.CdagError) as e:
+        c.plan("fp64", True)
+    assert e.value.code == B.E_STATE
+    c.close()

@@ -330,3 +330,99 @@ def test_optimal_peak_small_exhaustive():
     assert len(orders) == sum(1 for p in itertools.permutations("efgh")
                               if p.index("e") < p.index("g") and p.index("e") < p.index("h"))
     assert S.optimal_peak(d) == 2 * unit(d)
+
+
+# ---------------------------------------------------------------- general DAGs (any number of children)
+def _hand_general():
+    """Leaves a, b, c, d (ids 0-3, sizes 1, 2, 4, 8); x = (a, b, c) of size 16
+    (id 4, three children); roots r0 = (x, d) (id 5), r1 = (c, d) (id 6) and
+    r2 = (x) (id 7, one child), all of size 0."""
+    return D.general(4, [1, 2, 4, 8, 16, 0, 0, 0], [(), (), (), (), (0, 1, 2), (4, 3), (2, 3), (4,)])
+
+
+def test_general_hand_example():
+    """Worked by hand from the gain definition M - M' and Sec. II-C.
+
+    Initially nothing is processed (M = 0), so gain(T) = -(bytes that stay
+    resident after T: processed nodes with an unprocessed parent).
+      T0 = {a,b,c,d,x,r0}: c (r1 pending) 4 + d (r1) 8 + x (r2) 16  -> -28
+      T1 = {c,d,r1}:       c (x pending) 4 + d (r0) 8                -> -12
+      T2 = {a,b,c,x,r2}:   c (r1) 4 + x (r0) 16                      -> -20
+    T1 is taken (order r1), leaving c and d resident (M = 12).  Then
+      T0: before, c and d count 12; after, only x (r2 pending) 16     -> -4
+      T2: before, c counts 4; after, x (r0 pending) 16                -> -12
+    so T0 (x, r0), then T2 (r2): Tree order [6, 4, 5, 7].  Its memory:
+      r1 brings c, d: 12 live, 12 after;  x brings a, b: 12 + 3 + 16 = 31 live,
+      a, b, c released -> 24;  r0: d released -> 16;  r2: x released -> 0.
+    Input order [4, 5, 6, 7]: x brings a, b, c (23 live, 20 after: c, x);
+      r0 brings d (28, nothing released: d feeds r1, x feeds r2); r1 -> 16; r2 -> 0."""
+    d = _hand_general()
+    assert d.tree_roots == [5, 6, 7]
+    assert d.parents[2] == [4, 6] and d.parents[3] == [5, 6] and d.parents[4] == [5, 7]
+    st = S._TreeState(d, [d.size(u) for u in range(d.n_nodes)])
+    assert [st.gain(i) for i in range(3)] == [-28, -12, -20]
+    assert S.tree(d) == [6, 4, 5, 7]
+    assert S.input_order(d) == [4, 5, 6, 7]
+    t = S.memsim(d, [6, 4, 5, 7])
+    assert (t["M"], t["peak_post"], t["peak_live"]) == ([12, 24, 16, 0], 24, 31)
+    i = S.memsim(d, [4, 5, 6, 7])
+    assert (i["M"], i["peak_post"], i["peak_live"]) == ([20, 28, 16, 0], 28, 28)
+    # brute force over the 12 topological orders: 20 (e.g. x, r2, r1, r0)
+    assert S.optimal_peak(d) == 20
+    with pytest.raises(ValueError):
+        S.sibling(d)                                           # x has three children
+
+
+def test_general_binary_reduces_to_build():
+    """A binary DAG given as a general DAG (its own node sizes) schedules and
+    simulates exactly like the contraction DAG it came from."""
+    for seed in range(6):
+        d = random_mixed(seed) if seed % 2 else random_ring(seed)
+        g = D.general(d.n_leaves, [d.size(u) for u in range(d.n_nodes)],
+                      [d.children(u) for u in range(d.n_nodes)])
+        assert g.tree_roots == d.tree_roots                    # first appearance = ascending id
+        for pol in ("input", "sibling", "tree"):
+            a, b = S.schedule(d, pol), S.schedule(g, pol)
+            assert a == b, (seed, pol)
+            assert S.memsim(d, a) == S.memsim(g, b)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_general_tree_gain_is_memory_difference(seed):
+    """On general DAGs too, the chosen tree's gain equals the drop in resident
+    bytes measured by direct set reasoning, and the order is valid."""
+    from synth.general import random_general
+    nl, sz, ch = random_general(seed, n_leaves=5 + seed % 4, n_trees=3 + seed % 5,
+                                max_arity=1 + seed % 4, share=(0.0, 0.3, 0.6)[seed % 3])
+    d = D.general(nl, sz, ch)
+    st = S._TreeState(d, [d.size(u) for u in range(d.n_nodes)])
+    order = []
+    alive = set(range(len(d.tree_roots)))
+    while alive:
+        gains = {i: st.gain(i) for i in alive}
+        best = max(sorted(alive), key=lambda i: gains[i])
+        before = _mem_after(d, order)
+        order += [u for u in st.process(best) if d.kind[u] >= 0]
+        assert gains[best] == before - _mem_after(d, order)
+        alive.discard(best)
+    assert order == S.tree(d) == S.tree(d, recompute_all=True)
+    assert sorted(order) == sorted(d.contractions())
+    sim = S.memsim(d, order)
+    assert sim["M"][-1] == 0 and sim["peak_post"] <= sim["peak_live"]
+    if len(d.contractions()) <= 7:
+        assert S.optimal_peak(d) <= sim["peak_post"]
+
+
+def test_general_validation():
+    ok = ([1, 1, 1], [(), (), (0, 1)])
+    D.general(2, *ok)
+    for nl, sizes, kids in [
+        (2, [1, 1, 1], [(), (), ()]),            # non-leaf without children
+        (2, [1, 1, 1], [(), (0,), (0, 1)]),      # leaf with a child
+        (2, [1, 1, 1], [(), (), (0, 0)]),        # repeated child
+        (2, [1, 1, 1], [(), (), (0, 2)]),        # self reference
+        (2, [1, 1, -1], [(), (), (0, 1)]),       # negative size
+        (3, [1, 1], [(), ()]),                   # more leaves than nodes
+    ]:
+        with pytest.raises(D.InvalidGraph):
+            D.general(nl, sizes, kids)
