@@ -610,6 +610,21 @@ __device__ __forceinline__ void load4(T (&r)[4], const T* src, int valid, bool v
   }
 }
 
+// Four consecutive elements from a 16-byte aligned address, as vector loads.
+template <typename T>
+__device__ __forceinline__ void load4v(T (&r)[4], const T* src) {
+  typedef typename Vec2<T>::V V;
+  constexpr int W = Vec2<T>::n;
+  const V* s = reinterpret_cast<const V*>(src);
+#pragma unroll
+  for (int q = 0; q < 4 / W; ++q) {
+    V v = s[q];
+    const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+    for (int x = 0; x < W; ++x) r[q * W + x] = e[x];
+  }
+}
+
 // C(t) = sum_ij P[i,j] Q[j,i]: one wave per (root, t), four per workgroup.
 // Lane l takes the 4 x 4 blocks b = l, l + 64, ... with block row ib = b / nb
 // and block column jb = b % nb (nb = ceil(N / 4)): it reads rows 4ib.. of P
@@ -632,20 +647,9 @@ __global__ void __launch_bounds__(256) hca_trace(char* __restrict__ arena, const
     const T* P = reinterpret_cast<const T*>(arena + h.p_off) + (int64_t)t * 2 * nn;
     const T* Q = reinterpret_cast<const T*>(arena + h.q_off) + (int64_t)t * 2 * nn;
     const int nb = (n + 3) >> 2;
-    const bool vec = (n & 3) == 0;
     double sr = 0.0, si = 0.0;
-    for (int b = lane; b < nb * nb; b += 64) {
-      const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
-      const int vj = min(4, n - j0), vi = min(4, n - i0);
-      T pr[4][4], pi[4][4], qr[4][4], qi[4][4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
-        load4<T>(pr[r], P + po, i0 + r < n ? vj : 0, vec);
-        load4<T>(pi[r], P + nn + po, i0 + r < n ? vj : 0, vec);
-        load4<T>(qr[r], Q + qo, j0 + r < n ? vi : 0, vec);
-        load4<T>(qi[r], Q + nn + qo, j0 + r < n ? vi : 0, vec);
-      }
+    T pr[4][4], pi[4][4], qr[4][4], qi[4][4];
+    auto accumulate = [&]() {
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -655,6 +659,41 @@ __global__ void __launch_bounds__(256) hca_trace(char* __restrict__ arena, const
           sr += xr * yr - xi * yi;
           si += xr * yi + xi * yr;
         }
+    };
+    if ((n & 3) == 0) {
+      // N a multiple of 4: every block is whole and every row segment is a
+      // 16-byte aligned run, so the loads are plain vector loads (no masks,
+      // which would otherwise be merged into element-wise loads).
+      for (int b = lane; b < nb * nb; b += 64) {
+        const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
+          load4v<T>(pr[r], P + po);
+          load4v<T>(pi[r], P + nn + po);
+          load4v<T>(qr[r], Q + qo);
+          load4v<T>(qi[r], Q + nn + qo);
+        }
+        // Keep every load of the block ahead of its first use, so that the
+        // wave has them all in flight at once instead of waiting between
+        // groups of loads.
+        __builtin_amdgcn_sched_barrier(0);
+        accumulate();
+      }
+    } else {
+      for (int b = lane; b < nb * nb; b += 64) {
+        const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
+        const int vj = min(4, n - j0), vi = min(4, n - i0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
+          load4<T>(pr[r], P + po, i0 + r < n ? vj : 0, false);
+          load4<T>(pi[r], P + nn + po, i0 + r < n ? vj : 0, false);
+          load4<T>(qr[r], Q + qo, j0 + r < n ? vi : 0, false);
+          load4<T>(qi[r], Q + nn + qo, j0 + r < n ? vi : 0, false);
+        }
+        accumulate();
+      }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
