@@ -323,3 +323,29 @@ def test_deterministic_rerun(baryon_small):
     b = run(wl, "tree", "fp32", True)
     assert np.array_equal(np.concatenate(a["corr"]).view(np.uint64),
                           np.concatenate(b["corr"]).view(np.uint64))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_traces_with_mixed_n_in_one_launch(prec):
+    """Roots with N = 10 (partial 4 x 4 blocks, masked loads) and N = 12 and 16
+    (whole blocks, vector loads) in the same trace launch, and a DAG whose roots
+    all have N a multiple of 4; both match the oracle."""
+    rng = np.random.default_rng(21)
+    nt = 3
+    leaves, graphs = [], []
+    for n in (10, 12, 16):
+        base = len(leaves)
+        leaves += [W.Leaf(2, n, nt, W._draw(rng, (nt, n, n), 0.5)) for _ in range(3)]
+        graphs.append(W.GraphSpec([(W.K22, base, base + 1), (W.HCA, -1, base + 2)]))
+        graphs.append(W.GraphSpec([(W.HCA, base + 2, base)]))
+    for wl in (W.Workload("mixed_n", leaves, graphs),
+               W.Workload("whole_n", leaves[3:], [W.GraphSpec([(k, l - 3 if l >= 0 else l, r - 3 if r >= 0 else r)
+                                                               for k, l, r in g.ops]) for g in graphs[2:]])):
+        ref = OV.correlators(wl)
+        # every ready contraction joins the first wave, so the leaf-only roots
+        # of all three N share one trace launch
+        r = run(wl, "tree", prec, True, wave_lookahead=(1 << 63) - 1)
+        assert r["stats"]["plan"]["n_steps"] == 2
+        err = rel_errors(r["corr"], ref)
+        print(f"{wl.name} {prec}: max rel {err.max():.3e}")
+        assert err.max() <= TOL[prec]
