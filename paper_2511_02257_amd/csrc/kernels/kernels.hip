@@ -73,6 +73,19 @@ __device__ __forceinline__ WorkItem decode_item(const HecDesc* descs, int n_desc
   const int di = find_desc(&descs[0].tile_begin, sizeof(HecDesc) / 4, n_desc, item);
   const HecDesc* h = &descs[di];
   int64_t local = item - h->tile_begin;
+  // XCD-aware order.  Workgroups go to the eight XCDs round robin (item mod 8
+  // for one workgroup per item, and for a persistent grid of a multiple of 8
+  // workgroups).  When the contraction's items start on a multiple of 8 and Nt
+  // is one, item x + 8 j takes time slice x + 8 (j / T), tile j mod T (T tiles
+  // per slice): every tile of a slice runs on one XCD, one after another, so
+  // the operand panels they share come from that XCD's L2, and each XCD reads
+  // only its own slices.  A bijection of the contraction's items; with T = 1
+  // it is the identity.
+  const int64_t T = (int64_t)h->splits * h->tiles_n * h->tiles_m;
+  if (T > 1 && ((h->tile_begin | h->nt) & 7) == 0) {
+    const int32_t x = (int32_t)(local & 7), j = (int32_t)(local >> 3), T32 = (int32_t)T;
+    local = (int64_t)(x + 8 * (j / T32)) * T + (j % T32);
+  }
   w.sp = (int)(local % h->splits);
   local /= h->splits;
   const int tn = (int)(local % h->tiles_n);

@@ -349,3 +349,26 @@ def test_traces_with_mixed_n_in_one_launch(prec):
         err = rel_errors(r["corr"], ref)
         print(f"{wl.name} {prec}: max rel {err.max():.3e}")
         assert err.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("tile", [0, 1, 3, 5])
+def test_xcd_item_order_with_nt_multiple_of_8(prec, tile):
+    """Nt = 8 and 16 put contractions whose items start on a multiple of 8 on
+    the XCD-aware item order (all tiles of a time slice on one XCD), ragged
+    multi-tile contractions included (N = 40, K32 with 50 row tiles, K33 with
+    K = 1600 split or not).  Results match the oracle and do not depend on
+    grouping, whether or not the order applies to a contraction."""
+    for nt in (8, 16):
+        wl = W.baryon_mix(n_bar=3, n_mes=3, nvec=40, nt=nt, n_graphs=8, sigma=1 / 16, n_corr=2,
+                          seed=30 + nt, name=f"baryon_nt{nt}")
+        ref = OV.correlators(wl)
+        for split_k in (1, 0):
+            a = run(wl, "tree", prec, True, tile=tile, grid=1, split_k=split_k)
+            b = run(wl, "tree", prec, False, tile=tile, grid=0, split_k=split_k)
+            for r in (a, b):
+                err = rel_errors(r["corr"], ref)
+                assert err.max() <= TOL[prec], (nt, split_k, err.max())
+            print(f"baryon nt={nt} {prec} tile {tile} split_k {split_k}: max rel {err.max():.3e}")
+            assert np.array_equal(np.concatenate(a["corr"]).view(np.uint64),
+                                  np.concatenate(b["corr"]).view(np.uint64))
