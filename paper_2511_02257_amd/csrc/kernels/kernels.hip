@@ -421,15 +421,20 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
                                                        int n_desc, int64_t n_items) {
   constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
   constexpr int BK = 32, PAD = BK + 8;     // bf16 per LDS row (16-byte aligned rows)
-  constexpr int SEGA = 2 * BM * (BK / 8), SEGB = 2 * BK * (BN / 8);
+  // A: segments of 8 consecutive k of one row m.  B: segments of 8 consecutive
+  // k of two adjacent columns n (consecutive lanes take consecutive column
+  // pairs, so each of the 8 loads is coalesced), which become two 16-byte rows
+  // of the transposed LDS tile.
+  constexpr int SEGA = 2 * BM * (BK / 8), SEGB = 2 * (BK / 8) * (BN / 2);
   constexpr int LA = (SEGA + NTH - 1) / NTH, LB = (SEGB + NTH - 1) / NTH;
+  static_assert(BN % 2 == 0, "B column pairs");
   // [stage][plane][hi/lo][row][k]: A rows are m, B rows are n (B is stored transposed)
   __shared__ __attribute__((aligned(16))) __bf16 As[ST][2][2][BM][PAD];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[ST][2][2][BN][PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / TL::WGN, wn = wave % TL::WGN, li = lane & 15, lk = lane >> 4;
 
-  float ra[LA][8], rb[LB][8];
+  float ra[LA][8], rb[LB][8][2];
   auto gload = [&](const ItemView<float>& o, int k0) {
 #pragma unroll
     for (int q = 0; q < LA; ++q) {
@@ -445,11 +450,24 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
     for (int q = 0; q < LB; ++q) {
       const int seg = tid + q * NTH;
       if (seg < SEGB) {
-        const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
-        const int kk = rem / (BN / 8), sg = rem % (BN / 8);
-        const int bkk = k0 + kk, bn = o.n0 + 8 * sg;
-        const int bv = bkk < o.kend ? max(0, min(8, o.N - bn)) : 0;
-        load8<float>(rb[q], o.B + (int64_t)p * o.K * o.N + (int64_t)bkk * o.N + bn, bv, o.bvec);
+        const int p = seg / ((BK / 8) * (BN / 2)), rem = seg % ((BK / 8) * (BN / 2));
+        const int g = rem / (BN / 2), cp = rem % (BN / 2);
+        const int bk0 = k0 + 8 * g, bn = o.n0 + 2 * cp;
+        const float* src = o.B + (int64_t)p * o.K * o.N + (int64_t)bk0 * o.N + bn;
+        if (bk0 + 8 <= o.kend && bn + 2 <= o.N && (o.N & 1) == 0) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const float2 v = *reinterpret_cast<const float2*>(src + (int64_t)i * o.N);
+            rb[q][i][0] = v.x;
+            rb[q][i][1] = v.y;
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+              rb[q][i][c] = (bk0 + i < o.kend && bn + c < o.N) ? src[(int64_t)i * o.N + c] : 0.0f;
+        }
       }
     }
   };
@@ -472,14 +490,20 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
     for (int q = 0; q < LB; ++q) {
       const int seg = tid + q * NTH;
       if (seg < SEGB) {
-        const int p = seg / (BK * (BN / 8)), rem = seg % (BK * (BN / 8));
-        const int kk = rem / (BN / 8), sg = rem % (BN / 8);
+        const int p = seg / ((BK / 8) * (BN / 2)), rem = seg % ((BK / 8) * (BN / 2));
+        const int g = rem / (BN / 2), cp = rem % (BN / 2);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          __bf16 hi, lo;
-          split_bf16(rb[q][i], hi, lo);
-          Bs[st][p][0][8 * sg + i][kk] = hi;
-          Bs[st][p][1][8 * sg + i][kk] = lo;
+        for (int c = 0; c < 2; ++c) {
+          v8bf hi, lo;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            __bf16 h, l;
+            split_bf16(rb[q][i][c], h, l);
+            hi[i] = h;
+            lo[i] = l;
+          }
+          *reinterpret_cast<v8bf*>(&Bs[st][p][0][2 * cp + c][8 * g]) = hi;
+          *reinterpret_cast<v8bf*>(&Bs[st][p][1][2 * cp + c][8 * g]) = lo;
         }
       }
     }
