@@ -685,14 +685,17 @@ __global__ void __launch_bounds__(256) hca_trace(char* __restrict__ arena, const
     const T* Q = reinterpret_cast<const T*>(arena + h.q_off) + (int64_t)t * 2 * nn;
     const int nb = (n + 3) >> 2;
     double sr = 0.0, si = 0.0;
-    T pr[4][4], pi[4][4], qr[4][4], qi[4][4];
-    auto accumulate = [&]() {
+    // FP32 blocks are half the bytes, so the whole-block path keeps two of
+    // them in flight per lane (the same bytes as one FP64 block).
+    constexpr int BPI = sizeof(T) == 4 ? 2 : 1;
+    T pr[BPI][4][4], pi[BPI][4][4], qr[BPI][4][4], qi[BPI][4][4];
+    auto accumulate = [&](int u) {
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const double xr = (double)pr[a][c], xi = (double)pi[a][c];
-          const double yr = (double)qr[c][a], yi = (double)qi[c][a];
+          const double xr = (double)pr[u][a][c], xi = (double)pi[u][a][c];
+          const double yr = (double)qr[u][c][a], yi = (double)qi[u][c][a];
           sr += xr * yr - xi * yi;
           si += xr * yi + xi * yr;
         }
@@ -701,21 +704,28 @@ __global__ void __launch_bounds__(256) hca_trace(char* __restrict__ arena, const
       // N a multiple of 4: every block is whole and every row segment is a
       // 16-byte aligned run, so the loads are plain vector loads (no masks,
       // which would otherwise be merged into element-wise loads).
-      for (int b = lane; b < nb * nb; b += 64) {
-        const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
+      for (int b0 = lane; b0 < nb * nb; b0 += 64 * BPI) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
-          load4v<T>(pr[r], P + po);
-          load4v<T>(pi[r], P + nn + po);
-          load4v<T>(qr[r], Q + qo);
-          load4v<T>(qi[r], Q + nn + qo);
+        for (int u = 0; u < BPI; ++u) {
+          // a block past the end reloads block b0 (in bounds) and is not added
+          const int b = b0 + 64 * u < nb * nb ? b0 + 64 * u : b0;
+          const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
+            load4v<T>(pr[u][r], P + po);
+            load4v<T>(pi[u][r], P + nn + po);
+            load4v<T>(qr[u][r], Q + qo);
+            load4v<T>(qi[u][r], Q + nn + qo);
+          }
         }
-        // Keep every load of the block ahead of its first use, so that the
-        // wave has them all in flight at once instead of waiting between
+        // Keep every load of the iteration ahead of its first use, so that
+        // the wave has them all in flight at once instead of waiting between
         // groups of loads.
         __builtin_amdgcn_sched_barrier(0);
-        accumulate();
+#pragma unroll
+        for (int u = 0; u < BPI; ++u)
+          if (b0 + 64 * u < nb * nb) accumulate(u);
       }
     } else {
       for (int b = lane; b < nb * nb; b += 64) {
@@ -724,12 +734,12 @@ __global__ void __launch_bounds__(256) hca_trace(char* __restrict__ arena, const
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
-          load4<T>(pr[r], P + po, i0 + r < n ? vj : 0, false);
-          load4<T>(pi[r], P + nn + po, i0 + r < n ? vj : 0, false);
-          load4<T>(qr[r], Q + qo, j0 + r < n ? vi : 0, false);
-          load4<T>(qi[r], Q + nn + qo, j0 + r < n ? vi : 0, false);
+          load4<T>(pr[0][r], P + po, i0 + r < n ? vj : 0, false);
+          load4<T>(pi[0][r], P + nn + po, i0 + r < n ? vj : 0, false);
+          load4<T>(qr[0][r], Q + qo, j0 + r < n ? vi : 0, false);
+          load4<T>(qi[0][r], Q + nn + qo, j0 + r < n ? vi : 0, false);
         }
-        accumulate();
+        accumulate(0);
       }
     }
 #pragma unroll
