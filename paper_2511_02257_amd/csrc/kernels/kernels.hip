@@ -198,16 +198,26 @@ __device__ __forceinline__ void load16b(T (&r)[16 / sizeof(T)], const T* src, in
 }
 
 // Store one 16x16 block pair (Re, Im) of accumulators with the instruction's
-// row layout; rows and columns outside M x N are skipped.
-template <typename T, typename V>
+// row layout; rows and columns outside M x N are skipped.  NT: non-temporal
+// stores, which keep a launch's outputs (read by a later wave, long after the
+// caches have turned over) from displacing the operands that its other work
+// items are still reading from L2.
+template <typename T, typename V, bool NT>
 __device__ __forceinline__ void store_block(T* C, int M, int N, int row0, int col, const V& re, const V& im,
                                            int lk) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int m = row0 + Mfma<T>::row(lk, v);
     if (m < M && col < N) {
-      C[(int64_t)m * N + col] = re[v];
-      C[(int64_t)M * N + (int64_t)m * N + col] = im[v];
+      T* pr = &C[(int64_t)m * N + col];
+      T* pi = &C[(int64_t)M * N + (int64_t)m * N + col];
+      if (NT) {
+        __builtin_nontemporal_store(re[v], pr);
+        __builtin_nontemporal_store(im[v], pi);
+      } else {
+        *pr = re[v];
+        *pi = im[v];
+      }
     }
   }
 }
@@ -394,7 +404,8 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
             im[v] = p3[i][j][v] - (p1[i][j][v] + p2[i][j][v]);
           }
         }
-        store_block<T, V>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li, re, im, lk);
+        store_block<T, V, true>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li, re, im,
+                                lk);
       }
     if (!has_next) break;
     item = next;
@@ -595,7 +606,7 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j)
-        store_block<float, v4f>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li,
+        store_block<float, v4f, false>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li,
                                 cr[i][j], ci[i][j], lk);
     if (!has_next) break;
     item = next;
