@@ -108,7 +108,7 @@ struct ItemView {
   const T* A;
   const T* B;
   int M, N, K, t, sp, m0, n0, kbeg, kend;
-  bool avec, bvec;   // rows of A (B) allow 8-element vector loads
+  bool avec;         // rows of A allow 8-element vector loads
 };
 
 template <typename T, int BM, int BN>
@@ -128,7 +128,6 @@ __device__ __forceinline__ ItemView<T> view_item(char* arena, const HecDesc* des
   v.A = reinterpret_cast<const T*>(arena + w.h->a_off) + (int64_t)w.t * 2 * v.M * v.K;
   v.B = reinterpret_cast<const T*>(arena + w.h->b_off) + (int64_t)w.t * 2 * v.K * v.N;
   v.avec = (v.K & 7) == 0;
-  v.bvec = (v.N & 7) == 0;
   return v;
 }
 
