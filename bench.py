@@ -109,12 +109,49 @@ def kernel_table(records, prec):
     return agg
 
 
-def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True, fixed=None):
+def budgeted_schedules(ctx, runner, prec, budget, X):
+    """Time-to-solution under the configuration's HBM budget with the leaves
+    starting in pinned host memory (every transfer inside the time): input
+    order, Sibling and Tree cut into waves with lookahead 16 and replayed from
+    captured segments, Tree without lookahead, and Tree with one eager launch
+    per contraction.  One warm-up and one timed execute each."""
+    out = {}
+    ctx.set_mem_budget(budget)
+    for policy, look, batched in (("input", 16, True), ("sibling", 16, True), ("tree", 16, True),
+                                  ("tree", 0, True), ("tree", 16, False)):
+        ctx.schedule(policy)
+        ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=batched)
+        key = policy + (f"_lookahead{look}" if look and batched else "") + ("" if batched else "_per_contraction")
+        try:
+            dt, st = timed_steps(ctx, runner, prec, batched, 1, 1)
+            p = st["plan"]
+            timing = {"tts_s": round(dt, 4), "tflops": round(p["flops"] / dt / 1e12, 3)}
+        except X.CdagError as e:
+            # e.g. pinned host memory for the spilled intermediates not available:
+            # the plan's counts are still exact, the time is not measured
+            p = ctx.plan(prec, batched)
+            timing = {"tts_s": None, "error": str(e)[:160],
+                      "host_spill_GB": round(p["host_spill_bytes"] / 1e9, 3)}
+        out[key] = {**timing,
+                    "h2d_GB": round(p["h2d_bytes"] / 1e9, 3), "d2h_GB": round(p["d2h_bytes"] / 1e9, 3),
+                    "n_evict": p["n_evict"], "peak_resident_GB": round(p["peak_resident"] / 1e9, 3),
+                    "peak_post_GB": round(p["peak_post"] / 1e9, 3), "n_steps": p["n_steps"],
+                    "budget_GB": round(budget / 1e9, 3)}
+        log(prec, key, out[key])
+    ctx.set_mem_budget(None)
+    ctx.schedule("tree")
+    ctx.set_options(leaves_resident=True, wave_lookahead=X.binding.LOOKAHEAD_ALL, use_graphs=True)
+    return out
+
+
+def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True, fixed=None, budgeted=False):
     """One config at its full size, Tree schedule, waves of every ready
     contraction, leaves resident, graph replay: autotuned variants, time per
-    execute, and per-kernel rates from a timed execute."""
+    execute, and per-kernel rates from a timed execute.  budgeted: also the
+    schedules under the configuration's HBM budget (budgeted_schedules)."""
     import torch
     wl = W.config(name)
+    budget = wl.budget_bytes
     log(f"{name}: workload built")
     shapes = set()
     for g in wl.graphs:
@@ -151,6 +188,8 @@ def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True, fix
             "arena_GB": round(p["arena_bytes"] / 1e9, 2),
             "variants": {f"{KIND_NAMES[k]}_N{n}": list(ctx.get_tile(prec, k, n)) for k, n in shapes},
             "kernels": kernel_table(recs, prec)}
+        if budgeted and budget:
+            res[prec]["budgeted"] = budgeted_schedules(ctx, runner, prec, budget, X)
         log(name, prec, res[prec])
     ctx.close()
     runner.arena = None
@@ -302,6 +341,9 @@ def main():
     ap.add_argument("--variants-from", default=None, metavar="JSON",
                     help="with --workload baryon_mix or batched: take the kernel choices from the "
                          "JSON line of an earlier run of the same workload instead of autotuning")
+    ap.add_argument("--budgeted", action="store_true",
+                    help="with --workload: also time input order, Sibling and Tree under the "
+                         "configuration's HBM budget with the leaves starting on the host")
     ap.add_argument("--study", default=None, choices=("corr_func", "general"),
                     help="host-only: peak memory and scheduler time on the Table corr-func-shaped "
                          "DAGs (no GPU)")
@@ -342,7 +384,7 @@ def main():
                 prev = json.loads(f.read().strip().splitlines()[-1])
             fixed = {p: r["variants"] for p, r in prev["per_precision"].items()}
         res = workload_rooflines(args.workload, precs, args.steps, X, W, DeviceRunner,
-                                 in_situ=args.workload == "baryon_mix", fixed=fixed)
+                                 in_situ=args.workload == "baryon_mix", fixed=fixed, budgeted=args.budgeted)
         head = res[precs[0]]
         print(json.dumps({
             "metric": METRIC, "value": head["tflops"], "unit": "complex TFLOP/s", "n_gpus": 1,

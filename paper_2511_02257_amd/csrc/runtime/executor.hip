@@ -26,8 +26,14 @@
 namespace cdag {
 
 namespace {
+inline void ignore_last_error() { (void)hipGetLastError(); }
+// A failed call also leaves its code as the thread's last error; it is read
+// (and so cleared) here, or a later launch check would report it again.
 void hip_check(hipError_t e, const char* what) {
-  if (e != hipSuccess) throw Error(CDAG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  if (e != hipSuccess) {
+    ignore_last_error();
+    throw Error(CDAG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  }
 }
 #define HIPC(x) hip_check((x), #x)
 inline void ignore(hipError_t) {}
