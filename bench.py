@@ -114,7 +114,11 @@ def budgeted_schedules(ctx, runner, prec, budget, X):
     starting in pinned host memory (every transfer inside the time): input
     order, Sibling and Tree cut into waves with lookahead 16 and replayed from
     captured segments, Tree without lookahead, and Tree with one eager launch
-    per contraction.  One warm-up and one timed execute each."""
+    per contraction.  One warm-up and one timed execute each.  Every run's
+    correlators are compared bit for bit with those of the resident run that
+    precedes this call."""
+    import numpy as np
+    ref = np.concatenate(ctx.fetch_correlators()).view(np.uint64)
     out = {}
     ctx.set_mem_budget(budget)
     for policy, look, batched in (("input", 16, True), ("sibling", 16, True), ("tree", 16, True),
@@ -125,7 +129,9 @@ def budgeted_schedules(ctx, runner, prec, budget, X):
         try:
             dt, st = timed_steps(ctx, runner, prec, batched, 1, 1)
             p = st["plan"]
-            timing = {"tts_s": round(dt, 4), "tflops": round(p["flops"] / dt / 1e12, 3)}
+            same = bool(np.array_equal(np.concatenate(ctx.fetch_correlators()).view(np.uint64), ref))
+            timing = {"tts_s": round(dt, 4), "tflops": round(p["flops"] / dt / 1e12, 3),
+                      "bits_equal_resident": same}
         except X.CdagError as e:
             # e.g. pinned host memory for the spilled intermediates not available:
             # the plan's counts are still exact, the time is not measured

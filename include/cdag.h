@@ -115,7 +115,7 @@ typedef struct {
   int64_t budget;        /* bytes the plan was made for (INT64_MAX: unlimited)   */
   int64_t arena_bytes;   /* device bytes cdag_bind_arena must provide            */
   int64_t tensor_highwater; /* physical high-water of the tensor pool           */
-  int64_t host_spill_bytes; /* pinned host bytes for spilled intermediates      */
+  int64_t host_spill_bytes; /* host bytes for spilled intermediates (pinned)     */
   int64_t hec_items;     /* exterior-contraction work items (output tiles x K splits) */
   double flops;          /* algorithmic flops, 8 per complex multiply-add        */
   double t_sched_s, t_plan_s;
@@ -274,7 +274,11 @@ int cdag_bind_arena(cdag_ctx* c, void* dev_arena, uint64_t bytes);
 
 /* Plan (as cdag_plan) and run the whole DAG: uploads, evictions, exterior
  * contractions, traces, the cross-diagram sums and the copy of the results
- * to the host.  Blocks until the results are on the host. */
+ * to the host.  Blocks until the results are on the host.  Spilled
+ * intermediates go to a pinned host pool of plan.host_spill_bytes; when a
+ * pinned allocation of that size fails the pool is pageable memory and the
+ * steps run eagerly (no captured segments).  CDAG_E_NOMEM if neither can be
+ * allocated. */
 int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
 
 /* Autotuner over the kernel variants of cdag_set_tile, for every distinct

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <cstdlib>
 #include <thread>
 #include <tuple>
 
@@ -52,9 +53,11 @@ struct Device {
   // pinned staging of leaves in device layout, per precision mode
   std::vector<void*> stage[3];
   uint64_t stage_version[3] = {0, 0, 0};
-  // pinned host spill pool
+  // host spill pool: pinned, or pageable when a pinned allocation of the
+  // plan's size fails (then steps run eagerly, without captured segments)
   void* spill = nullptr;
   int64_t spill_bytes = 0;
+  bool spill_pageable = false;
   // pinned result buffer
   void* results = nullptr;
   int64_t results_bytes = 0;
@@ -104,8 +107,15 @@ struct Device {
     for (auto& v : stage)
       for (void* p : v)
         if (p) ignore(hipHostFree(p));
-    if (spill) ignore(hipHostFree(spill));
+    free_spill();
     if (results) ignore(hipHostFree(results));
+  }
+  void free_spill() {
+    if (spill && spill_pageable) std::free(spill);
+    else if (spill) ignore(hipHostFree(spill));
+    spill = nullptr;
+    spill_bytes = 0;
+    spill_pageable = false;
   }
 };
 
@@ -195,6 +205,21 @@ void ensure_events(Device& D, size_t n) {
     HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     D.ev_copy.push_back(e);
   }
+}
+
+// The spill pool holds the plan's spilled intermediates at once.  Pinned
+// memory of that size may be refused; pageable memory then takes its place.
+void ensure_spill(Device& D, int64_t need_bytes) {
+  if (D.spill && D.spill_bytes >= need_bytes) return;
+  D.free_spill();
+  if (need_bytes <= 0) return;
+  if (hipHostMalloc(&D.spill, (size_t)need_bytes, hipHostMallocDefault) != hipSuccess) {
+    ignore_last_error();
+    D.spill = std::malloc((size_t)need_bytes);
+    if (!D.spill) throw Error(CDAG_E_NOMEM, "host spill pool of " + std::to_string(need_bytes) + " bytes");
+    D.spill_pageable = true;
+  }
+  D.spill_bytes = need_bytes;
 }
 
 void ensure_pinned(void*& p, int64_t& have, int64_t need_bytes) {
@@ -445,7 +470,7 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
                                   std::to_string(kp.total_bytes));
   const int eb = prec == CDAG_FP64 ? 16 : 8;
   ensure_stage(c, prec);
-  ensure_pinned(D.spill, D.spill_bytes, p.host_spill_bytes);
+  ensure_spill(D, p.host_spill_bytes);
   ensure_pinned(D.results, D.results_bytes, kp.corr_bytes + kp.sums_bytes);
   const int64_t S = (int64_t)p.steps.size();
   ensure_events(D, (size_t)std::max<int64_t>(S, 1));
@@ -479,7 +504,7 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   D.tpairs.clear();
   Device* timed = c.timing ? &D : nullptr;
   HIPC(hipEventRecord(D.t0, D.comp));
-  if (c.use_graphs && !c.timing) {
+  if (c.use_graphs && !c.timing && !D.spill_pageable) {
     // replay captured segments (one segment when there are no transfers)
     const int64_t seg = has_copies ? kSegmentSteps : std::max<int64_t>(S, 1);
     if (D.graph_key != pkey || D.graph_epoch != D.arena_epoch || D.graph_spill != D.spill ||
