@@ -206,12 +206,13 @@ def cdag_build_general(h, n_leaves: int, sizes: Sequence[int], children: Sequenc
 
 
 def schedule(h, policy: str, check: bool = False) -> np.ndarray:
+    """One schedule call: the order has at most one entry per DAG node."""
     p = POLICY[policy] | (SCHED_CHECK if check else 0)
+    cap = max(1, cdag_dag_stats(h)["n_vertices"])
+    out = np.empty(cap, dtype=np.int64)
     n = C.c_int64()
-    _check(lib().schedule(h, p, None, 0, C.byref(n)))
-    out = np.empty(n.value, dtype=np.int64)
-    _check(lib().schedule(h, p, _i64p(out), out.size, None))
-    return out
+    _check(lib().schedule(h, p, _i64p(out), cap, C.byref(n)))
+    return out[:n.value].copy()
 
 
 def set_mem_budget(h, nbytes: Optional[int]) -> None:

@@ -14,7 +14,7 @@
 #include <algorithm>
 #include <deque>
 #include <functional>
-#include <set>
+#include <queue>
 
 #include "host.hpp"
 #include "../../../include/cdag.h"
@@ -148,7 +148,10 @@ struct TreeSched {
   std::vector<int64_t> touched;             // scratch: trees with a nonzero counter
   std::vector<int64_t> tgain, cgain;
   std::vector<char> alive;
-  std::set<std::pair<int64_t, int64_t>> pq; // (-tgain, tree) of live trees
+  // (tgain, -tree) entries of live trees in a max-heap; an entry whose gain
+  // is no longer the tree's current gain, or whose tree is processed, is stale
+  // and skipped when it reaches the top (the top is max tgain, lowest index)
+  std::priority_queue<std::pair<int64_t, int64_t>> pq;
   std::vector<int64_t> order;
   std::vector<int64_t> visit_mark;
 
@@ -178,9 +181,8 @@ struct TreeSched {
 
   void set_gain(int64_t t, int64_t delta) {
     if (delta == 0) return;
-    if (alive[t]) pq.erase({-tgain[t], t});
     tgain[t] += delta;
-    if (alive[t]) pq.insert({-tgain[t], t});
+    if (alive[t]) pq.push({tgain[t], -t});
   }
 
   void init() {                                   // TR-INIT
@@ -207,7 +209,7 @@ struct TreeSched {
       }
       clear_counts();
     }
-    for (int64_t t = 0; t < k; ++t) pq.insert({-tgain[t], t});
+    for (int64_t t = 0; t < k; ++t) pq.push({tgain[t], -t});
   }
 
   void process_child(int64_t u, int64_t x) {      // PROCESS-CHILD
@@ -321,8 +323,9 @@ struct TreeSched {
             throw Error(CDAG_E_STATE, "tree: incremental tgain of tree " + std::to_string(t) +
                                           " is " + std::to_string(tgain[t]) + ", M - M' is " +
                                           std::to_string(brute_gain(t)));
-      int64_t best = pq.begin()->second;          // max tgain, lowest index on ties
-      pq.erase(pq.begin());
+      while (!alive[-pq.top().second] || pq.top().first != tgain[-pq.top().second]) pq.pop();
+      const int64_t best = -pq.top().second;      // max tgain, lowest index on ties
+      pq.pop();
       alive[best] = 0;
       process_ctree(best);
     }
