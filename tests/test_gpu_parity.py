@@ -372,3 +372,36 @@ def test_xcd_item_order_with_nt_multiple_of_8(prec, tile):
             print(f"baryon nt={nt} {prec} tile {tile} split_k {split_k}: max rel {err.max():.3e}")
             assert np.array_equal(np.concatenate(a["corr"]).view(np.uint64),
                                   np.concatenate(b["corr"]).view(np.uint64))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("policy,look", [("input", 0), ("tree", 0), ("tree", 16)])
+def test_captured_transfer_segments_replay(meson_small, prec, policy, look):
+    """Captured segments with spills and re-uploads on the forked copy stream
+    (a quarter of the input-order live peak), replayed five times with eager
+    executes between replays: every replay equals the eager result bit for bit."""
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd.device import DeviceRunner
+    from oracle import dag as OD, schedules as OS
+    wl, ref = meson_small
+    eb = 16 if prec == "fp64" else 8
+    d = OD.build(wl.leaves, wl.graphs)
+    budget = OS.memsim(d, OS.input_order(d), eb)["peak_live"] // 4
+    ctx = X.Context()
+    ctx.build_cdag(wl.leaves, wl.graphs)
+    ctx.schedule(policy)
+    ctx.set_mem_budget(budget)
+    runner = DeviceRunner(ctx, 0)
+    ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=False)
+    st = runner.run(prec, True)
+    assert st["plan"]["n_d2h"] > 0 and st["plan"]["n_h2d"] > 0
+    eager = np.concatenate(ctx.fetch_correlators()).view(np.uint64).copy()
+    assert rel_errors(ctx.fetch_correlators(), ref).max() <= TOL[prec]
+    for rep in range(5):
+        ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=True)
+        st = runner.run(prec, True)
+        assert st["n_graph_segments"] >= 1
+        assert np.array_equal(np.concatenate(ctx.fetch_correlators()).view(np.uint64), eager), f"replay {rep}"
+        ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=False)
+        runner.run(prec, True)
+    ctx.close()
