@@ -324,10 +324,17 @@ def cpu_baseline(wl, seconds=12.0):
             flops += 8.0 * T * N ** 3 if kind == 0 else 8.0 * T * N * N
         n += 1
     dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": flops / dt / 1e12, "unit": "complex TFLOP/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"first {n} of {len(wl.graphs)} graphs, each evaluated on its own with "
-                      f"numpy complex128 matmul (no DAG sharing), {dt:.1f} s"}
+                      f"numpy complex128 matmul (no DAG sharing), {dt:.1f} s",
+            "cpu": cpu, "host_cpus": os.cpu_count()}
 
 
 def main():
