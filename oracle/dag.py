@@ -247,4 +247,4 @@ def stats(d: Dag) -> dict:
     edges = [(c, u) for u in range(d.n_nodes) for c in d.children(u)]
     fe = sum(sum(1 for t in trees if c in t and u in t) for c, u in edges)
     return dict(n_nodes=d.n_nodes, n_edges=len(edges), n_trees=len(trees),
-                f_v=sum(ctree) / d.n_nodes, f_e=fe / max(1, len(edges)))
+                f_v=sum(ctree) / max(1, d.n_nodes), f_e=fe / max(1, len(edges)))

@@ -74,7 +74,7 @@ def sibling(d: Dag) -> List[int]:
     rs = [len(d.parents[u]) for u in range(d.n_nodes)]
     rp = [len(d.children(u)) for u in range(d.n_nodes)]
     state = [WAITING] * d.n_nodes
-    queues: Dict[int, deque] = {i: deque() for i in range(1, max(rank) + 1)}
+    queues: Dict[int, deque] = {i: deque() for i in range(1, max(rank, default=0) + 1)}
     n_contr = len(d.contractions())
     order: List[int] = []
 

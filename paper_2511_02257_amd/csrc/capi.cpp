@@ -145,7 +145,7 @@ int build_cdag(cdag_ctx* h, const cdag_leaf* leaves, int64_t n_leaves, const cda
     c.dag = std::move(d);
     c.leaf_data = std::move(data);
     c.leaf_dtype = std::move(dtypes);
-    c.has_data = with_data > 0;
+    c.has_data = with_data > 0 || n_leaves == 0;   // an empty DAG executes trivially
     c.n_corr = n_corr;
     c.built = true;
     c.data_version++;

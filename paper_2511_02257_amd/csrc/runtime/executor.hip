@@ -412,6 +412,7 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
 int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
   const auto shapes = tune_shapes(c.dag);
   const bool timing = c.timing;
+  const auto tiles = c.tiles;                  // restored if a trial execute throws
   c.timing = true;
   int64_t tuned = 0;
   try {
@@ -451,6 +452,8 @@ int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
     }
   } catch (...) {
     c.timing = timing;
+    c.tiles = tiles;
+    c.version++;
     throw;
   }
   c.timing = timing;
@@ -551,8 +554,9 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   }
   n_launch++;
   HIPC(hipEventRecord(D.t1, D.comp));
-  HIPC(hipMemcpyAsync(D.results, D.arena + kp.corr_off, (size_t)(kp.corr_bytes + kp.sums_bytes),
-                      hipMemcpyDeviceToHost, D.comp));
+  if (kp.corr_bytes + kp.sums_bytes > 0)
+    HIPC(hipMemcpyAsync(D.results, D.arena + kp.corr_off, (size_t)(kp.corr_bytes + kp.sums_bytes),
+                        hipMemcpyDeviceToHost, D.comp));
   HIPC(hipStreamSynchronize(D.comp));
   HIPC(hipStreamSynchronize(D.copy));
   float ms = 0;

@@ -405,3 +405,38 @@ def test_captured_transfer_segments_replay(meson_small, prec, policy, look):
         ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=False)
         runner.run(prec, True)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_degenerate_dags(prec):
+    """Edge cases of the method: a DAG of leaves with no graph; roots that
+    trace two leaves directly (no contraction); N = 1 and Nt = 1 (every tile
+    ragged, K = 1); N = 3 (partial trace blocks); a graph given twice (one
+    shared root, two outputs) and the same leaves traced in both orders."""
+    rng = np.random.default_rng(21)
+    empty = W.Workload("leaves_only", [W.Leaf(2, 4, 2, W._draw(rng, (2, 4, 4), 0.5))], [])
+    r = run(empty, "tree", prec, False)
+    assert r["corr"] == [] and r["sums"] == []
+    assert r["stats"]["plan"]["n_contr"] == 0
+
+    for n, nt in ((1, 1), (3, 2)):
+        m = [W.Leaf(2, n, nt, W._draw(rng, (nt, n, n), 0.5)) for _ in range(3)]
+        b = [W.Leaf(3, n, nt, W._draw(rng, (nt, n, n, n), 0.5)) for _ in range(2)]
+        leaves = m + b
+        ring = [(W.K22, 0, 1), (W.K22, -1, 2), (W.HCA, -2, 0)]
+        chain = [(W.K32, 3, 0), (W.K33, -1, 4), (W.HCA, -2, 1)]
+        graphs = [W.GraphSpec([(W.HCA, 0, 1)], 0, 1.0),
+                  W.GraphSpec([(W.HCA, 1, 0)], 0, -1.0),
+                  W.GraphSpec(ring, 1, 1.0),
+                  W.GraphSpec(list(ring), 1, 0.5),
+                  W.GraphSpec(chain, 2, 1.0)]
+        wl = W.Workload(f"degenerate_n{n}", leaves, graphs)
+        ref = OV.correlators(wl)
+        for policy in ("input", "tree"):
+            r = run(wl, policy, prec, False)
+            err = rel_errors(r["corr"], ref)
+            print(f"degenerate N={n} Nt={nt} {prec} {policy}: max rel {err.max():.3e}")
+            assert err.max() <= TOL[prec]
+            assert np.array_equal(r["corr"][2], r["corr"][3])
+            assert sum_errors(wl, r["sums"], ref) <= TOL[prec]
+            assert r["stats"]["plan"]["n_contr"] == 2 + 3 + 3    # two traces, one shared ring, chain

@@ -432,3 +432,29 @@ def test_general_dag_validation_and_state():
         c.plan("fp64", True)
     assert e.value.code == B.E_STATE
     c.close()
+
+
+@pytest.mark.parametrize("n_leaves", [0, 3])
+def test_dag_without_graphs(n_leaves):
+    """No graph: every schedule is empty, the plan has no step and moves no byte,
+    on both sides."""
+    rng = np.random.default_rng(5)
+    leaves = [W.Leaf(2, 4, 2, W._draw(rng, (2, 4, 4), 0.5)) for _ in range(n_leaves)]
+    wl = W.Workload("no_graphs", leaves, [])
+    c = ctx_for(wl)
+    for policy in ("input", "sibling", "tree"):
+        assert len(c.schedule(policy)) == 0
+        d, order, res = OP_counts(wl, policy)
+        assert list(order) == []
+        p = c.plan("fp64")
+        assert p["n_contr"] == 0 and p["n_steps"] == 0 and p["n_roots"] == 0
+        for k in ("n_h2d", "h2d_bytes", "n_d2h", "n_evict", "peak_resident"):
+            assert p[k] == res[k] == 0, k
+        assert p["peak_live"] == p["peak_post"] == 0
+    c.close()
+
+
+def OP_counts(wl, policy):
+    d = OD.build(wl.leaves, wl.graphs)
+    order = OS.schedule(d, policy, 16)
+    return d, order, OP.plan(d, order, elem_bytes=16, budget=OP.UNLIMITED, batched=False)
