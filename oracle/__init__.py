@@ -7,7 +7,9 @@ path computes, written from the paper's definitions:
                 DAGs whose nodes have any number of children.
   schedules.py  input-order, Sibling (Algs. 1-3) and Tree (Sec. III-B, from the
                 gain definition M - M' rather than the incremental Algs. 5-8),
-                the memory model of Sec. II-C, and a brute-force optimum.
+                the node-based gain scheduler the conclusions propose (the same
+                gain per ready node), the memory model of Sec. II-C, and a
+                brute-force optimum.
   planner.py    the budgeted next-use eviction plan and wave cut.
   values.py     correlator values in complex128 and the cross-diagram sum.
 

@@ -9,6 +9,10 @@ tree         the Tree scheduler written from its definition: repeatedly pick the
              unprocessed tree whose processing changes memory by the largest gain
              M - M' (Sec. III-B), then process its unprocessed nodes in
              topological order, left to right.
+node_gain    a node-based gain scheduler, the one the conclusions name as future
+             work: repeatedly run the ready contraction whose execution changes
+             memory by the largest gain M - M' (the Tree scheduler's gain concept,
+             Sec. III-B, taken to single nodes), M and M' measured by memsim.
 memsim       the memory model of Sec. II-C: M_i after each contraction, plus the
              live peak during a contraction (inputs, newly brought leaves and the
              output coexist).
@@ -22,6 +26,8 @@ Readings where the paper is silent (same list as the design notes):
     order of first appearance.
   * A leaf costs memory from its first use by a contraction; a root's output
     costs 0.
+  * node_gain: a contraction is ready when every non-leaf child has run (leaves
+    are always available); ties go to the lowest node id.
 """
 from __future__ import annotations
 
@@ -215,13 +221,14 @@ def tree_initial_igains(d: Dag, elem_bytes: int = 16) -> List[Dict[int, int]]:
 
 
 # ---------------------------------------------------------------- memory model
-def memsim(d: Dag, order: Sequence[int], elem_bytes: int = 16) -> dict:
+def memsim(d: Dag, order: Sequence[int], elem_bytes: int = 16, partial: bool = False) -> dict:
     """Sec. II-C: for each contraction c_i, (i) bring leaves c_i needs, (ii) perform it,
     (iii) release every tensor nothing pending depends on (the output of a root too).
 
     Returns M = [M_1..M_n], peak_post = max M_i, peak_live = the largest
     resident total while a contraction runs (M_{i-1} + first-touch leaves +
-    output), and the memory contents after each contraction."""
+    output), and the memory contents after each contraction.  With partial,
+    the order may be a topological prefix of a complete one."""
     size = [d.size(u, elem_bytes) for u in range(d.n_nodes)]
     remaining = [len(d.parents[u]) for u in range(d.n_nodes)]
     in_mem: Set[int] = set()
@@ -251,9 +258,32 @@ def memsim(d: Dag, order: Sequence[int], elem_bytes: int = 16) -> dict:
             M -= size[c]
         Ms.append(M)
         contents.append(sorted(in_mem))
-    if len(seen) != len(d.contractions()):
+    if not partial and len(seen) != len(d.contractions()):
         raise ValueError("order must cover every contraction")
     return dict(M=Ms, peak_post=max(Ms) if Ms else 0, peak_live=peak_live, contents=contents)
+
+
+def node_gain(d: Dag, elem_bytes: int = 16) -> List[int]:
+    """Node-based gain scheduler, from its definition: with the prefix P run so
+    far (memory M after it, by memsim), run next the ready contraction v whose
+    M' (memory after P + [v], by memsim) is smallest, i.e. whose gain M - M' is
+    largest; ties to the lowest id.  Quadratic in memsim calls: small DAGs."""
+    contr = d.contractions()
+    done: Set[int] = set()
+    order: List[int] = []
+    M = 0
+    while len(order) < len(contr):
+        best, best_gain, best_M = None, None, None
+        for v in contr:
+            if v in done or any(d.kind[x] >= 0 and x not in done for x in d.children(v)):
+                continue
+            Mv = memsim(d, order + [v], elem_bytes, partial=True)["M"][-1]
+            if best is None or M - Mv > best_gain:
+                best, best_gain, best_M = v, M - Mv, Mv
+        order.append(best)
+        done.add(best)
+        M = best_M
+    return order
 
 
 def topo_orders(d: Dag):
@@ -288,8 +318,10 @@ def schedule(d: Dag, policy: str, elem_bytes: int = 16) -> List[int]:
         return sibling(d)
     if policy == "tree":
         return tree(d, elem_bytes)
+    if policy == "node":
+        return node_gain(d, elem_bytes)
     raise KeyError(policy)
 
 
-__all__ = ["input_order", "sibling", "tree", "ranks", "memsim", "optimal_peak",
+__all__ = ["input_order", "sibling", "tree", "node_gain", "ranks", "memsim", "optimal_peak",
            "topo_orders", "tree_initial_igains", "schedule"]

@@ -7,6 +7,9 @@ What pins what:
   * Fig. 4's five PROCESS-CHILD cases, seen through the gain definition M - M'.
   * Eq. (1) ranks; M_n = 0; peak_post <= peak_live; each contraction once; brute
     force optimum <= every heuristic; F_v / F_e by hand on Fig. 1.
+  * Node-based gain scheduler: two DAGs worked by hand; every pick is the ready
+    contraction with the largest drop in resident bytes by direct set reasoning
+    (independent of memsim), lowest id on ties; a chain has one order.
 """
 import itertools
 import json
@@ -212,7 +215,7 @@ def test_heuristics_valid_and_bounded(seed):
     d = random_ring(seed) if seed % 2 == 0 else random_mixed(seed)
     n_contr = len(d.contractions())
     peaks = {}
-    for pol in ("input", "sibling", "tree"):
+    for pol in ("input", "sibling", "tree", "node"):
         order = S.schedule(d, pol)
         assert sorted(order) == sorted(d.contractions())      # each processed once
         sim = S.memsim(d, order)                               # raises if not topological
@@ -426,3 +429,73 @@ def test_general_validation():
     ]:
         with pytest.raises(D.InvalidGraph):
             D.general(nl, sizes, kids)
+
+
+# ---------------------------------------------------------------- node-based gain scheduler
+def test_node_gain_hand_examples():
+    """Worked by hand: gain(v) = released - brought - output under Sec. II-C.
+
+    Fig. 1 (leaves 256 B, e 256 B, roots 0): f and e both start at -512 (f brings
+    a, b; e brings b, c, adds e and releases c), the tie goes to f (id 4); then e
+    is the only ready node (releases b, c, brings c: 0); then g releases a (+256)
+    against h (brings and releases d: 0).  Order f, e, g, h; M 512, 512, 256, 0.
+
+    Leaves p, q, r (ids 0-2, sizes 4, 2, 1); x = (p, q) size 5 (id 3);
+    y = (q, r) size 1 (id 4); roots s = (x) (id 5) and t = (y, p) (id 6).
+      step 1: x: -6 - 5 = -11;  y: -3 - 1 + 1 (r) = -3            -> y, M 3
+      step 2: x: -4 - 5 + 2 (q) = -7;  t: -4 + 1 (y) = -3          -> t, M 6
+      step 3: x: -5 + 4 + 2 = +1                                   -> x, M 5
+      step 4: s releases x                                         -> s, M 0
+    Input order (x, s, y, t) peaks at 11 (x brings p, q and adds x); Tree
+    takes the same order; the brute-force optimum is 6, which node gain meets."""
+    d, names = fig1()
+    order = S.node_gain(d)
+    assert order == [names[x] for x in "fegh"]
+    assert S.memsim(d, order)["M"] == [512, 512, 256, 0]
+
+    g = D.general(3, [4, 2, 1, 5, 1, 0, 0], [(), (), (), (0, 1), (1, 2), (3,), (4, 0)])
+    assert S.node_gain(g) == [4, 6, 3, 5]
+    assert S.memsim(g, [4, 6, 3, 5])["M"] == [3, 6, 5, 0]
+    assert S.input_order(g) == S.tree(g) == [3, 5, 4, 6]
+    assert S.memsim(g, [3, 5, 4, 6])["peak_post"] == 11
+    assert S.optimal_peak(g) == 6
+
+    h = _hand_general()
+    assert S.node_gain(h) == [6, 4, 5, 7]
+
+
+def test_node_gain_chain_has_one_order():
+    """A chain of contractions has a single topological order."""
+    n = 6
+    kids = [()] * (n + 1) + [(0, 1)] + [(n + 1 + k, k + 2) for k in range(n - 1)]
+    sizes = [1] * (n + 1) + [3] * (n - 1) + [0]
+    d = D.general(n + 1, sizes, kids)
+    assert S.node_gain(d) == list(range(n + 1, 2 * n + 1))
+
+
+def _check_node_picks(d, order):
+    done = []
+    for v in order:
+        ready = [u for u in d.contractions() if u not in done
+                 and all(d.kind[x] < 0 or x in done for x in d.children(u))]
+        before = _mem_after(d, done)
+        drop = {u: before - _mem_after(d, done + [u]) for u in ready}
+        best = max(drop.values())
+        assert v == min(u for u in ready if drop[u] == best)
+        done.append(v)
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_node_gain_picks_the_largest_drop(seed):
+    """Every pick of node_gain is the ready contraction whose run lowers the
+    resident bytes most, measured by direct set reasoning; ties to the lowest id."""
+    if seed < 12:
+        d = random_ring(seed, n_leaves=7, n_graphs=10) if seed % 2 else random_mixed(seed)
+    else:
+        from synth.general import random_general
+        nl, sz, ch = random_general(seed, n_leaves=5 + seed % 4, n_trees=3 + seed % 5,
+                                    max_arity=1 + seed % 4, share=(0.0, 0.3, 0.6)[seed % 3])
+        d = D.general(nl, sz, ch)
+    order = S.node_gain(d)
+    assert sorted(order) == sorted(d.contractions())
+    _check_node_picks(d, order)
