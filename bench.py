@@ -205,11 +205,11 @@ def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True, fix
 
 
 def corr_func_study(rows=None):
-    """Host-only: the peak-memory study (Sec. V-B), the scheduler-time study
+    """Host-only: the peak-memory study (Sec. IV-B), the scheduler-time study
     (Table sch-time) and the data-movement counts (evictions, transfers and
-    their size, Sec. V-C) on the Table corr-func-shaped DAGs.  Per row: DAG
-    size and F_v / F_e, then for the input order, Sibling and Tree the wall
-    time of the schedule call, the peak memory (after-release M_i peak and
+    their size, Sec. IV-C) on the Table corr-func-shaped DAGs.  Per row: DAG
+    size and F_v / F_e, then for the input order, Sibling, Tree and node gain
+    the wall time of the schedule call, the peak memory (after-release M_i peak and
     live peak during an op) and the budgeted plan's counts, sizes in units of
     the greatest common divisor of the distinct tensor sizes as the paper
     plots them."""
@@ -239,7 +239,7 @@ def corr_func_study(rows=None):
         res = {"system": CF.TABLE[row]["system"], "graphs": len(wl.graphs), "leaves": len(wl.leaves),
                "N": n, "build_ms": round(t_build * 1e3, 1), **{k: (round(v, 3) if isinstance(v, float) else v)
                                                            for k, v in st.items()}}
-        for policy in ("input", "sibling", "tree"):
+        for policy in ("input", "sibling", "tree", "node"):
             t0 = time.perf_counter()
             order = ctx.schedule(policy)
             dt = time.perf_counter() - t0
@@ -257,7 +257,7 @@ def corr_func_study(rows=None):
             ctx.set_mem_budget(b_units * unit)
             try:
                 plans = {}
-                for policy in ("input", "sibling", "tree"):
+                for policy in ("input", "sibling", "tree", "node"):
                     ctx.schedule(policy)
                     plans[policy] = ctx.plan("fp64", False)
                 break
@@ -276,7 +276,7 @@ def corr_func_study(rows=None):
 
 
 def general_study(shares=(0.02, 0.05, 0.1), n_trees=40000):
-    """Host-only: input order and Tree on general DAGs whose nodes have one to
+    """Host-only: input order, Tree and node gain on general DAGs whose nodes have one to
     four children (synth/general.py: 400 leaves, trees of depth 3, an inner slot
     reusing an existing node with probability `share`).  Per DAG: size, F_v and
     F_e, the wall time of each schedule call and its peak memory (node sizes in
@@ -291,7 +291,7 @@ def general_study(shares=(0.02, 0.05, 0.1), n_trees=40000):
         ctx.build_general(nl, sizes, kids)
         res = {"share": share, **{k: (round(v, 3) if isinstance(v, float) else v)
                                   for k, v in ctx.dag_stats().items()}}
-        for policy in ("input", "tree"):
+        for policy in ("input", "tree", "node"):
             t0 = time.perf_counter()
             order = ctx.schedule(policy)
             dt = time.perf_counter() - t0

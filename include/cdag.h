@@ -5,7 +5,8 @@
  * contraction trees over hadron-node tensors (problem statement: Sec. II-B
  * "Notation" and Sec. II-C "Problem definition").  The trees are merged into
  * one contraction DAG, ordered by a scheduler (Sec. III: Sibling, Algs. 1-3;
- * Tree, Algs. 4-8; or plain input order), planned under a device-memory
+ * Tree, Algs. 4-8; a node-based gain scheduler; or plain input order),
+ * planned under a device-memory
  * budget with next-use eviction and host re-upload, and executed with
  * hand-written HIP kernels.
  *
@@ -60,8 +61,15 @@ enum cdag_kind { CDAG_K22 = 0, CDAG_K32 = 1, CDAG_K33 = 2, CDAG_HCA = 3,
                  CDAG_C1 = 4, CDAG_C2 = 5, CDAG_C3 = 6 };
 
 /* Schedulers: input order (each graph's tree in post-order, left first),
- * Sibling (Sec. III-A, Algs. 1-3), Tree (Sec. III-B, Algs. 4-8). */
-enum cdag_policy { CDAG_SCHED_INPUT = 0, CDAG_SCHED_SIBLING = 1, CDAG_SCHED_TREE = 2 };
+ * Sibling (Sec. III-A, Algs. 1-3), Tree (Sec. III-B, Algs. 4-8), and Node:
+ * the node-based gain scheduler the conclusions propose as future work.  Node
+ * runs next the ready contraction (non-leaf children already run) whose
+ * execution lowers the Sec. II-C memory the most, i.e. the largest gain
+ * M - M' of Sec. III-B for a single node: released children - leaves brought
+ * in - its output (0 for a contraction without parents); ties to the lowest
+ * node id. */
+enum cdag_policy { CDAG_SCHED_INPUT = 0, CDAG_SCHED_SIBLING = 1, CDAG_SCHED_TREE = 2,
+                   CDAG_SCHED_NODE = 3 };
 /* OR into policy for Tree: at every selection recompute every live tree's
  * gain M - M' from scratch and fail with CDAG_E_STATE if an incrementally
  * maintained tgain differs (slow; a self-check). */
@@ -172,8 +180,8 @@ int build_cdag(cdag_ctx* c, const cdag_leaf* leaves, int64_t n_leaves,
  * the size of u's tensor in bytes.  Trees are rooted at the non-leaf nodes
  * without parents, in ascending id.  All three arrays are read during the
  * call only (child_off has n_nodes + 1 entries, child_off[0] = 0).  Replaces
- * the DAG like build_cdag.  Afterwards schedule (input order and Tree; Sibling
- * only when every non-leaf has two children), cdag_memsim (elem_bytes is then
+ * the DAG like build_cdag.  Afterwards schedule (input order, Tree and Node;
+ * Sibling only when every non-leaf has two children), cdag_memsim (elem_bytes is then
  * ignored: the given sizes apply), cdag_get_nodes (kind 7 for non-leaves,
  * left/right for two-child nodes, else -1) and cdag_dag_stats apply;
  * cdag_plan, execute and cdag_autotune return CDAG_E_STATE.

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libcdagx.so")
 
 OK, E_INVALID, E_STATE, E_BUDGET, E_HIP, E_NOMEM, E_RANGE = 0, -1, -2, -3, -4, -5, -6
 K22, K32, K33, HCA = 0, 1, 2, 3
-POLICY = {"input": 0, "sibling": 1, "tree": 2}
+POLICY = {"input": 0, "sibling": 1, "tree": 2, "node": 3}
 SCHED_CHECK = 0x100
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 OP_NAMES = {0: "D2H", 1: "DROP", 2: "H2D", 3: "ALLOC", 4: "EXEC", 5: "FREE"}

@@ -1,5 +1,6 @@
-// Contraction schedulers (Sec. III): input order, Sibling (Algs. 1-3) and
-// Tree (Algs. 4-8), plus the Sec. II-C memory model.
+// Contraction schedulers (Sec. III): input order, Sibling (Algs. 1-3), Tree
+// (Algs. 4-8) and a node-based gain scheduler (the conclusions' future work),
+// plus the Sec. II-C memory model.
 //
 // Readings where the paper is silent or garbled:
 //   * Sibling picks the WAITING leaf with the smallest id when all queues are
@@ -337,6 +338,86 @@ std::vector<int64_t> sched_tree(const Dag& d, int elem_bytes, bool check) {
   TreeSched s(d, elem_bytes);
   s.run(check);
   return std::move(s.order);
+}
+
+// ---------------------------------------------------------------- node gain
+// Node-based gain scheduler: the Tree scheduler's gain M - M' (Sec. III-B)
+// taken down to single contractions, as the conclusions propose.  Running v
+// under the Sec. II-C model brings in v's leaf children that are not yet
+// resident, adds v's output (nothing for a contraction without parents, whose
+// output is released at once) and releases every child whose last pending
+// parent is v, so gain(v) = released - brought - output.  A contraction is
+// ready once its non-leaf children have run; the ready one with the largest
+// gain runs next, ties to the lowest id.  Running v changes another node's
+// gain in two cases only: a leaf child of v that v brought in no longer costs
+// its other parents anything, and a child left with one pending parent is
+// released by that parent.  Those gains are recomputed and pushed again (each
+// leaf's parents are scanned once, each child's once when one parent is left,
+// so O(E) scans in all); stale heap entries are skipped.
+std::vector<int64_t> sched_node(const Dag& d, int elem_bytes) {
+  const int64_t n = d.n_nodes();
+  std::vector<int64_t> pending(n), waiting(n, 0), gain(n, 0);
+  std::vector<char> resident(n, 0), done(n, 0);
+  for (int64_t u = 0; u < n; ++u) pending[u] = d.n_parents(u);
+  for (int64_t u = d.n_leaves; u < n; ++u)
+    for (const int64_t* px = d.children_begin(u); px != d.children_end(u); ++px) waiting[u] += !d.is_leaf(*px);
+  auto eval = [&](int64_t v) {
+    int64_t g = d.n_parents(v) ? -d.size(v, elem_bytes) : 0;
+    for (const int64_t* px = d.children_begin(v); px != d.children_end(v); ++px) {
+      const int64_t sx = d.size(*px, elem_bytes);
+      if (!resident[*px]) g -= sx;            // a leaf not brought in yet
+      if (pending[*px] == 1) g += sx;         // v is its last pending parent
+    }
+    return g;
+  };
+  std::priority_queue<std::pair<int64_t, int64_t>> pq;   // (gain, -id): largest gain, then lowest id
+  for (int64_t u = d.n_leaves; u < n; ++u)
+    if (waiting[u] == 0) {
+      gain[u] = eval(u);
+      pq.push({gain[u], -u});
+    }
+  std::vector<int64_t> order;
+  order.reserve(n - d.n_leaves);
+  while (!pq.empty()) {
+    const int64_t g = pq.top().first, v = -pq.top().second;
+    pq.pop();
+    if (done[v] || g != gain[v]) continue;
+    done[v] = 1;
+    order.push_back(v);
+    auto refresh = [&](int64_t q) {
+      if (done[q] || waiting[q] != 0) return;
+      const int64_t ng = eval(q);
+      if (ng != gain[q]) {
+        gain[q] = ng;
+        pq.push({ng, -q});
+      }
+    };
+    for (const int64_t* px = d.children_begin(v); px != d.children_end(v); ++px) {
+      const int64_t x = *px;
+      const bool brought = !resident[x];
+      resident[x] = --pending[x] > 0;
+      if (pending[x] == 0) continue;
+      if (brought) {
+        for (int64_t pi = d.par_off[x]; pi < d.par_off[x + 1]; ++pi) refresh(d.par[pi]);
+      } else if (pending[x] == 1) {
+        for (int64_t pi = d.par_off[x]; pi < d.par_off[x + 1]; ++pi)
+          if (!done[d.par[pi]]) {
+            refresh(d.par[pi]);
+            break;
+          }
+      }
+    }
+    resident[v] = pending[v] > 0;
+    for (int64_t pi = d.par_off[v]; pi < d.par_off[v + 1]; ++pi) {
+      const int64_t q = d.par[pi];
+      if (--waiting[q] == 0) {
+        gain[q] = eval(q);
+        pq.push({gain[q], -q});
+      }
+    }
+  }
+  if ((int64_t)order.size() != n - d.n_leaves) throw Error(CDAG_E_STATE, "node scheduler: a contraction never became ready");
+  return order;
 }
 
 // ---------------------------------------------------------------- memory model

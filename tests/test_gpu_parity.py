@@ -66,7 +66,7 @@ def baryon_small():
 def test_tiny_fp64_all_modes(tiny):
     wl, ref = tiny
     base = None
-    for policy in ("input", "sibling", "tree"):
+    for policy in ("input", "sibling", "tree", "node"):
         for batched in (False, True):
             r = run(wl, policy, "fp64", batched)
             err = rel_errors(r["corr"], ref)
@@ -91,7 +91,8 @@ def test_meson_ragged_with_evictions(meson_small, prec):
     for policy, batched, look, graphs in (
             ("input", False, 0, True), ("input", False, 0, False), ("input", True, 0, True),
             ("tree", False, 0, False), ("tree", True, 0, True), ("tree", True, 0, False),
-            ("tree", True, 5, True), ("tree", True, 1 << 62, False)):
+            ("tree", True, 5, True), ("tree", True, 1 << 62, False),
+            ("node", False, 0, True), ("node", True, 0, False)):
         r = run(wl, policy, prec, batched, budget=budget, wave_lookahead=look, use_graphs=graphs)
         _, _, o = oracle_plan_counts(wl, policy, eb, budget, batched, lookahead=look)
         p = r["stats"]["plan"]

@@ -98,7 +98,7 @@ def test_schedules_and_plans_match_oracle(i):
     assert list(left) == d.left and list(right) == d.right
     assert [int(k) for k in kind[d.n_leaves:]] == d.kind[d.n_leaves:]
     assert list(c.graph_roots()) == d.root_of_graph
-    for policy in ("input", "sibling", "tree"):
+    for policy in ("input", "sibling", "tree", "node"):
         order = [int(x) for x in c.schedule(policy, check=(policy == "tree"))]
         assert order == OS.schedule(d, policy), policy
         for eb in (16, 8):
@@ -366,12 +366,13 @@ def _general_cases():
 @pytest.mark.parametrize("seed,case", list(_general_cases()))
 def test_general_dag_matches_oracle(seed, case):
     """Input order, Tree (with its incremental gains checked against M - M' at
-    every pick), the memory model and the DAG statistics on general DAGs."""
+    every pick), node gain, the memory model and the DAG statistics on general
+    DAGs."""
     nl, sizes, kids = case
     d = OD.general(nl, sizes, kids)
     c = X.Context()
     c.build_general(nl, sizes, kids)
-    for pol in ("input", "tree"):
+    for pol in ("input", "tree", "node"):
         got = list(c.schedule(pol, check=(pol == "tree")))
         ref = OS.schedule(d, pol)
         assert got == ref, pol
@@ -390,7 +391,8 @@ def test_general_dag_matches_oracle(seed, case):
 
 def test_general_dag_of_a_contraction_dag():
     """A contraction DAG handed over as a general DAG (its FP64 node sizes) gets
-    the same input, Sibling and Tree orders and memory figures as the original."""
+    the same input, Sibling, Tree and node-gain orders and memory figures as
+    the original."""
     wl = W.config("meson_ring", with_data=False)
     c = ctx_for(wl)
     kind, left, right = c.nodes()
@@ -398,7 +400,7 @@ def test_general_dag_of_a_contraction_dag():
     kids = [d.children(u) for u in range(d.n_nodes)]
     g = X.Context()
     g.build_general(d.n_leaves, [d.size(u, 16) for u in range(d.n_nodes)], kids)
-    for pol in ("input", "sibling", "tree"):
+    for pol in ("input", "sibling", "tree", "node"):
         a, b = list(c.schedule(pol)), list(g.schedule(pol))
         assert a == b, pol
         assert [list(x) if hasattr(x, "__len__") else x for x in c.memsim(a)] == \
