@@ -13,7 +13,7 @@ per complex multiply-add) with the leaves already resident in HBM.
 
 The same line also reports: the budgeted runs (HBM budget = a quarter of the
 input-order schedule's live peak, leaves starting in pinned host memory,
-spills and re-uploads over PCIe) for the input-order, Sibling and Tree
+spills and re-uploads over PCIe) for the input-order, Sibling, Tree and node-gain
 schedules: time-to-solution, H2D/D2H GB, evictions, peak resident bytes; the
 FP32 and split-BF16 modes; per-contraction launches vs waves; the roofline of
 the exterior-contraction kernel; and the CPU oracle on a bounded sample.
@@ -507,7 +507,7 @@ def main():
         for prec in ("fp64", "fp32"):
             ctx.set_mem_budget(budgets[prec])
             for policy, look in (("input", 0), ("sibling", 0), ("tree", 0), ("tree", 4), ("tree", 16),
-                                 ("tree", ALL)):
+                                 ("tree", ALL), ("node", 0), ("node", 16)):
                 ctx.schedule(policy)
                 reps = 3
                 tts = {}
