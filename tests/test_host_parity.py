@@ -38,6 +38,22 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(B.EXPORTED)
 
 
+def test_binding_constants_match_the_header():
+    """Status codes, kinds, policies, precisions and the check flag: the
+    binding's numbers are the header's."""
+    text = open(HEADER).read()
+    val = {k: int(v, 0) for k, v in re.findall(r"\b(CDAG_[A-Z0-9_]+)\s*=\s*(-?(?:0x)?[0-9a-fA-F]+)", text)}
+    val.update({k: int(v, 0) for k, v in re.findall(r"#define\s+(CDAG_[A-Z0-9_]+)\s+(0x[0-9a-fA-F]+|\d+)", text)})
+    assert (B.OK, B.E_INVALID, B.E_STATE, B.E_BUDGET, B.E_HIP, B.E_NOMEM, B.E_RANGE) == tuple(
+        val[k] for k in ("CDAG_OK", "CDAG_E_INVALID", "CDAG_E_STATE", "CDAG_E_BUDGET", "CDAG_E_HIP",
+                         "CDAG_E_NOMEM", "CDAG_E_RANGE"))
+    assert (B.K22, B.K32, B.K33, B.HCA) == tuple(val[f"CDAG_{k}"] for k in ("K22", "K32", "K33", "HCA"))
+    assert B.POLICY == {p: val[f"CDAG_SCHED_{p.upper()}"] for p in ("input", "sibling", "tree", "node")}
+    assert B.PREC == {"fp64": val["CDAG_FP64"], "fp32": val["CDAG_FP32"], "bf16x3": val["CDAG_BF16X3"]}
+    assert B.SCHED_CHECK == val["CDAG_SCHED_CHECK"]
+    assert (W.C1, W.C2, W.C3) == (val["CDAG_C1"], val["CDAG_C2"], val["CDAG_C3"])
+
+
 class _L:
     def __init__(self, rank, nvec=4, nt=1):
         self.rank, self.nvec, self.nt, self.data = rank, nvec, nt, None
