@@ -180,10 +180,11 @@ int build_cdag(cdag_ctx* c, const cdag_leaf* leaves, int64_t n_leaves,
  * the size of u's tensor in bytes.  Trees are rooted at the non-leaf nodes
  * without parents, in ascending id.  All three arrays are read during the
  * call only (child_off has n_nodes + 1 entries, child_off[0] = 0).  Replaces
- * the DAG like build_cdag.  Afterwards schedule (input order, Tree and Node;
- * Sibling only when every non-leaf has two children), cdag_memsim (elem_bytes is then
- * ignored: the given sizes apply), cdag_get_nodes (kind 7 for non-leaves,
- * left/right for two-child nodes, else -1) and cdag_dag_stats apply;
+ * the DAG like build_cdag.  Afterwards schedule (input order, Tree and
+ * Node; Sibling only when every non-leaf has two children), cdag_memsim
+ * (elem_bytes is then ignored: the given sizes apply), cdag_get_nodes (kind 7
+ * for non-leaves, left/right for two-child nodes, else -1) and cdag_dag_stats
+ * apply;
  * cdag_plan, execute and cdag_autotune return CDAG_E_STATE.
  * CDAG_E_INVALID: counts out of range (n_nodes < 2^31), a NULL array, a
  * decreasing child_off, a leaf with children, a non-leaf without, a child id
@@ -245,8 +246,7 @@ int cdag_get_tile(cdag_ctx* c, int prec, int kind, int nvec, int* tile, int* gri
 
 /* Host-only: simulate Sec. II-C for `order` (n node ids, each contraction
  * once, topological) with element size elem_bytes (16 or 8; a general DAG
- * uses its given sizes).  M_out
- * (nullable, capacity n) receives M_1..M_n. */
+ * uses its given sizes).  M_out (nullable, capacity n) receives M_1..M_n. */
 int cdag_memsim(cdag_ctx* c, const int64_t* order, int64_t n, int elem_bytes,
                 int64_t* M_out, int64_t* peak_post, int64_t* peak_live);
 
