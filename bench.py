@@ -72,7 +72,7 @@ def measured_traffic(variant):
     return None if entry is None else entry.get("traffic_bytes_per_launch")
 
 
-KIND_NAMES = {0: "K22", 1: "K32", 2: "K33", 3: "HCA"}
+KIND_NAMES = {0: "K22", 1: "K32", 2: "K33", 3: "HCA", 4: "C1", 5: "C2", 6: "C3"}
 
 
 def kernel_table(records, prec):
@@ -82,6 +82,8 @@ def kernel_table(records, prec):
     kernels to it ("hec+reduce")."""
     agg = {}
     for r in records:
+        if r["type"] in ("h2d", "d2h"):
+            continue
         key = r["type"] if r["type"] == "xsum" else r["type"] + ":" + "+".join(KIND_NAMES[k] for k in r["kinds"])
         a = agg.setdefault(key, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
         a["launches"] += 1
@@ -107,6 +109,41 @@ def kernel_table(records, prec):
             a["frac_hbm"] = round(a["bytes"] / sec / 1e9 / HBM_PEAK, 4)
         a["ms"] = round(a["ms"], 4)
     return agg
+
+
+def link_reference(torch, nbytes=1 << 30, reps=5):
+    """Plain pinned-host <-> device copies of nbytes through torch on one
+    stream, timed with events: the host link's practical rate per direction."""
+    host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = {}
+    for name, dst, src in (("h2d", dev, host), ("d2h", host, dev)):
+        dst.copy_(src, non_blocking=True)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            dst.copy_(src, non_blocking=True)
+        b.record()
+        b.synchronize()
+        out[f"{name}_GBps"] = round(nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9, 2)
+    del host, dev
+    return out
+
+
+def transfer_rates(records, tts_s):
+    """Per direction: transfers, bytes and summed copy time of one timed
+    execute, the achieved rate while copying, and the copy stream's busy
+    share of the time-to-solution."""
+    out = {}
+    for kind in ("h2d", "d2h"):
+        rs = [r for r in records if r["type"] == kind]
+        ms = sum(r["ms"] for r in rs)
+        nbytes = sum(r["bytes"] for r in rs)
+        out[kind] = {"n": len(rs), "GB": round(nbytes / 1e9, 4), "copy_ms": round(ms, 3),
+                     "GBps": round(nbytes / (ms * 1e-3) / 1e9, 2) if ms > 0 else None}
+    busy = sum(out[k]["copy_ms"] for k in out)
+    out["copy_busy_frac_of_tts"] = round(busy * 1e-3 / tts_s, 3) if tts_s else None
+    return out
 
 
 def budgeted_schedules(ctx, runner, prec, budget, X):
@@ -529,6 +566,23 @@ def main():
                     "tflops": round(p["flops"] / (d2 / reps) / 1e12, 3)}
                 log(key, budgeted[key])
         extras["budgeted"] = budgeted
+        # the host-transfer step on its own: per-copy events on the copy stream
+        # in a timed (eager) execute of the budgeted FP64 Tree order, lookahead 16
+        ctx.set_mem_budget(budgets["fp64"])
+        ctx.schedule("tree")
+        ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=False)
+        ctx.set_timing(True)
+        runner.run("fp64", True)                     # plans and warms up
+        runner.torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runner.run("fp64", True)
+        runner.torch.cuda.synchronize()
+        tts = time.perf_counter() - t0
+        recs = ctx.launch_records()
+        ctx.set_timing(False)
+        extras["transfers"] = {"fp64_tree_lookahead16": transfer_rates(recs, tts),
+                               "link_reference": link_reference(runner.torch)}
+        log("transfers", extras["transfers"])
         ctx.set_mem_budget(None)
         # the baryon configuration (FP64) and its precision form, per-kernel rates
         extras["baryon_mix"] = workload_rooflines("baryon_mix", ("fp64", "fp32", "bf16x3"),

@@ -141,20 +141,26 @@ typedef struct {
   int64_t n_graph_segments;
 } cdag_exec_stats;
 
-/* One kernel launch of a timed execute (cdag_set_timing(c, 1)). */
+/* One kernel launch, or one host transfer, of a timed execute
+ * (cdag_set_timing(c, 1)).  Transfers are the uploads and spills of a
+ * budgeted plan (Sec. II-A's movement between host and device memory). */
 enum cdag_launch_type { CDAG_LAUNCH_HEC = 0, CDAG_LAUNCH_REDUCE = 1, CDAG_LAUNCH_HCA = 2,
-                        CDAG_LAUNCH_XSUM = 3 };
+                        CDAG_LAUNCH_XSUM = 3, CDAG_LAUNCH_H2D = 4, CDAG_LAUNCH_D2H = 5 };
 typedef struct {
   int32_t type;       /* cdag_launch_type                                                */
   int32_t variant;    /* HEC: kernel variant index; else 0                              */
-  int32_t kinds;      /* bit k set when a contraction of cdag_kind k is in the launch  */
+  int32_t kinds;      /* bit k set when a contraction of cdag_kind k is in the launch;
+                         H2D, D2H: the moved tensor's cdag_kind bit (leaves: 0)         */
   int32_t reserved;
   int64_t step;       /* plan step (wave); -1 for the cross-diagram sum                */
-  int64_t n_items;    /* workgroup work items                                            */
-  double flops;       /* algorithmic flops (8 per complex multiply-add)                 */
+  int64_t n_items;    /* workgroup work items; H2D, D2H: 1                               */
+  double flops;       /* algorithmic flops (8 per complex multiply-add); transfers: 0   */
   double bytes;       /* HEC, HCA: algorithmic bytes (operands read once, output written
-                         once); REDUCE: split-K workspace read + output write; XSUM: 0  */
-  double ms;          /* duration between HIP events on the compute stream              */
+                         once); REDUCE: split-K workspace read + output write; XSUM: 0;
+                         H2D, D2H: the tensor's bytes                                   */
+  double ms;          /* duration between HIP events around the launch or the copy, on
+                         the stream that runs it (transfers: the copy stream, after any
+                         wait for the compute stream)                                   */
 } cdag_launch_record;
 
 int cdag_create(cdag_ctx** out);
@@ -214,8 +220,9 @@ int cdag_set_options(cdag_ctx* c, int leaves_resident, int wave_max, int64_t wav
                      int use_graphs);
 
 /* timing: 1 records a HIP event pair around every kernel launch on the
- * compute stream, reports the summed exterior-contraction durations in t_hec_s
- * and keeps per-launch records (execution then runs without graph replay);
+ * compute stream and around every host transfer on the copy stream, reports
+ * the summed exterior-contraction durations in t_hec_s and keeps per-launch
+ * and per-transfer records (execution then runs without graph replay);
  * 0 (default) turns it off. */
 int cdag_set_timing(cdag_ctx* c, int timing);
 /* Per-launch records of the last execute made with timing on, in launch order.

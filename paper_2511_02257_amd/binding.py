@@ -67,7 +67,7 @@ class cdag_launch_record(C.Structure):
                 ("flops", C.c_double), ("bytes", C.c_double), ("ms", C.c_double)]
 
 
-LAUNCH_TYPES = {0: "hec", 1: "reduce", 2: "hca", 3: "xsum"}
+LAUNCH_TYPES = {0: "hec", 1: "reduce", 2: "hca", 3: "xsum", 4: "h2d", 5: "d2h"}
 
 _lib = None
 
@@ -242,7 +242,7 @@ def cdag_dag_stats(h):
 
 
 def cdag_launch_records(h):
-    """Per-launch records of the last timed execute, as a list of dicts."""
+    """Per-launch and per-transfer records of the last timed execute, as a list of dicts."""
     n = C.c_int64()
     _check(lib().cdag_launch_records(h, None, 0, C.byref(n)))
     buf = (cdag_launch_record * max(1, n.value))()
@@ -250,7 +250,7 @@ def cdag_launch_records(h):
     out = []
     for r in buf[:n.value]:
         out.append({"type": LAUNCH_TYPES[r.type], "variant": r.variant,
-                    "kinds": [k for k in range(4) if r.kinds >> k & 1], "step": r.step,
+                    "kinds": [k for k in range(7) if r.kinds >> k & 1], "step": r.step,
                     "n_items": r.n_items, "flops": r.flops, "bytes": r.bytes, "ms": r.ms})
     return out
 

@@ -81,10 +81,17 @@ struct Device {
     seg_graph.clear();
     graph_key = 0;
   }
-  // timing mode: event pairs around exterior-contraction launches
+  // timing mode: event pairs around kernel launches and host transfers
   std::vector<hipEvent_t> tpool;
   size_t tnext = 0;
-  std::vector<std::tuple<int64_t, hipEvent_t, hipEvent_t>> tpairs;   // launch index (-1: xsum)
+  struct TPair {
+    int64_t launch;          // launch index; -1: cross sum; -2: a transfer
+    int32_t type, kinds;     // transfers: CDAG_LAUNCH_H2D / D2H and the tensor's kind bit
+    int64_t step;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<TPair> tpairs;
 
   hipEvent_t timing_event() {
     if (tnext == tpool.size()) {
@@ -251,7 +258,7 @@ int64_t launch_step(const KernelPlan& kp, int64_t s, int prec, char* arena, hipS
       HIPC(hipEventRecord(a, st));
       HIPC(launch_one(L, prec, arena, st));
       HIPC(hipEventRecord(b, st));
-      timed->tpairs.push_back({li, a, b});
+      timed->tpairs.push_back({li, 0, 0, s, 0.0, a, b});
     } else {
       HIPC(launch_one(L, prec, arena, st));
     }
@@ -285,12 +292,24 @@ int64_t issue_steps(Ctx& c, Device& D, int prec, int64_t s0, int64_t s1, hipStre
           HIPC(hipStreamWaitEvent(copy, D.ev_comp[r.wait_comp], 0));
           copy_waited = r.wait_comp;
         }
+        hipEvent_t ta = nullptr, tb = nullptr;
+        if (timed) {
+          ta = timed->timing_event();
+          tb = timed->timing_event();
+          HIPC(hipEventRecord(ta, copy));
+        }
         if (r.op == OP_D2H) {
           HIPC(hipMemcpyAsync((char*)D.spill + r.host_off, D.arena + r.dev_off, sz, hipMemcpyDeviceToHost, copy));
         } else {
           const void* src = c.dag.is_leaf(r.node) ? D.stage[prec][r.node] : (const void*)((char*)D.spill + r.host_off);
           HIPC(hipMemcpyAsync(D.arena + r.dev_off, src, sz, hipMemcpyHostToDevice, copy));
           any_h2d = true;
+        }
+        if (timed) {
+          HIPC(hipEventRecord(tb, copy));
+          const int32_t k = c.dag.kind[r.node];
+          timed->tpairs.push_back({-2, r.op == OP_D2H ? CDAG_LAUNCH_D2H : CDAG_LAUNCH_H2D,
+                                   k >= 0 ? (1 << k) : 0, s, (double)sz, ta, tb});
         }
         any_copy = true;
       } else if (r.op == OP_ALLOC && r.wait_copy >= 0) {
@@ -548,7 +567,7 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
     HIPC(hipEventRecord(a, D.comp));
     HIPC(launch_xsum(D.arena, kp.xsum.desc_off, kp.xsum_entries_off, kp.xsum.n_desc, D.comp));
     HIPC(hipEventRecord(b, D.comp));
-    D.tpairs.push_back({-1, a, b});
+    D.tpairs.push_back({-1, 0, 0, -1, 0.0, a, b});
   } else {
     HIPC(launch_xsum(D.arena, kp.xsum.desc_off, kp.xsum_entries_off, kp.xsum.n_desc, D.comp));
   }
@@ -566,25 +585,28 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
                      (const double*)((const char*)D.results + kp.corr_bytes) + kp.sums_bytes / 8);
   double t_hec = 0;
   if (timed) {
-    // launch index -> plan step
-    std::vector<int64_t> step_of(kp.launches.size(), -1);
-    for (int64_t s = 0; s < S; ++s)
-      for (int64_t li = kp.launch_off[s]; li < kp.launch_off[s + 1]; ++li) step_of[li] = s;
     c.records.clear();
-    for (auto& pr : D.tpairs) {
+    for (const Device::TPair& pr : D.tpairs) {
       float x = 0;
-      HIPC(hipEventElapsedTime(&x, std::get<1>(pr), std::get<2>(pr)));
-      const int64_t li = std::get<0>(pr);
-      const Launch& L = li >= 0 ? kp.launches[li] : kp.xsum;
+      HIPC(hipEventElapsedTime(&x, pr.a, pr.b));
       cdag_launch_record r{};
+      r.step = pr.step;
+      r.ms = x;
+      if (pr.launch == -2) {
+        r.type = pr.type;
+        r.kinds = pr.kinds;
+        r.n_items = 1;
+        r.bytes = pr.bytes;
+        c.records.push_back(r);
+        continue;
+      }
+      const Launch& L = pr.launch >= 0 ? kp.launches[pr.launch] : kp.xsum;
       r.type = L.type;
       r.variant = L.type == L_HEC ? L.tile : 0;
       r.kinds = L.kinds;
-      r.step = li >= 0 ? step_of[li] : -1;
       r.n_items = L.n_items;
       r.flops = L.flops;
       r.bytes = L.bytes;
-      r.ms = x;
       c.records.push_back(r);
       if (L.type == L_HEC) t_hec += x * 1e-3;
     }

@@ -191,7 +191,8 @@ def test_autotune_then_parity(baryon_small, in_situ):
 
 def test_timed_execute_records_every_launch(baryon_small):
     """Timing mode: one record per kernel launch, carrying the plan's flops and
-    bytes, in step order with the cross sum last; results unchanged."""
+    bytes, and one per host transfer (the leaves start on the host here), in
+    step order with the cross sum last; results unchanged."""
     import paper_2511_02257_amd as X
     from paper_2511_02257_amd.device import DeviceRunner
     wl, ref = baryon_small
@@ -202,10 +203,18 @@ def test_timed_execute_records_every_launch(baryon_small):
     runner = DeviceRunner(ctx, 0)
     ctx.set_timing(True)
     st = runner.run("fp64", True)
-    recs = ctx.launch_records()
+    records = ctx.launch_records()
     corr = ctx.fetch_correlators()
     ctx.close()
+    moves = [r for r in records if r["type"] in ("h2d", "d2h")]
+    recs = [r for r in records if r["type"] not in ("h2d", "d2h")]
     assert len(recs) == st["n_launches"]
+    p = st["plan"]
+    assert sum(r["type"] == "h2d" for r in moves) == p["n_h2d"] > 0
+    assert sum(r["type"] == "d2h" for r in moves) == p["n_d2h"]
+    assert sum(r["bytes"] for r in moves if r["type"] == "h2d") == p["h2d_bytes"]
+    assert all(r["ms"] > 0 and r["flops"] == 0 and r["n_items"] == 1 for r in moves)
+    assert [r["step"] for r in records[:-1]] == sorted(r["step"] for r in records[:-1])
     hec = [r for r in recs if r["type"] == "hec"]
     assert len(hec) == st["n_hec_launches"]
     assert sum(r["flops"] for r in hec) == st["hec_flops"]
