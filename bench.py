@@ -111,22 +111,25 @@ def kernel_table(records, prec):
     return agg
 
 
-def link_reference(torch, nbytes=1 << 30, reps=5):
-    """Plain pinned-host <-> device copies of nbytes through torch on one
-    stream, timed with events: the host link's practical rate per direction."""
-    host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
-    dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+def link_reference(torch, sizes=(2 << 20, 8 << 20, 1 << 30), total=4 << 30):
+    """Plain pinned-host <-> device copies through torch on one stream, timed
+    with events: the host link's practical rate per direction, for copies of
+    one tensor's size (2 MiB: a meson tensor) and for large ones."""
     out = {}
-    for name, dst, src in (("h2d", dev, host), ("d2h", host, dev)):
-        dst.copy_(src, non_blocking=True)
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
+    for nbytes in sizes:
+        reps = max(4, total // nbytes)
+        host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+        dev = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        for name, dst, src in (("h2d", dev, host), ("d2h", host, dev)):
             dst.copy_(src, non_blocking=True)
-        b.record()
-        b.synchronize()
-        out[f"{name}_GBps"] = round(nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9, 2)
-    del host, dev
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                dst.copy_(src, non_blocking=True)
+            b.record()
+            b.synchronize()
+            out[f"{name}_{nbytes >> 20}MiB_GBps"] = round(nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9, 2)
+        del host, dev
     return out
 
 
@@ -143,6 +146,31 @@ def transfer_rates(records, tts_s):
                      "GBps": round(nbytes / (ms * 1e-3) / 1e9, 2) if ms > 0 else None}
     busy = sum(out[k]["copy_ms"] for k in out)
     out["copy_busy_frac_of_tts"] = round(busy * 1e-3 / tts_s, 3) if tts_s else None
+    return out
+
+
+def transfer_study(ctx, runner, budget, reps=1, link=True):
+    """The host-transfer step on its own: per-copy events on the copy stream in
+    timed (eager) executes of the budgeted FP64 Tree order with lookahead 16,
+    beside the pinned-copy link reference.  An event pair around a copy that
+    waits for the compute stream can include part of that wait."""
+    ctx.set_mem_budget(budget)
+    ctx.schedule("tree")
+    ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=False)
+    ctx.set_timing(True)
+    runner.run("fp64", True)                     # plans and warms up
+    runner.torch.cuda.synchronize()
+    runs = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        runner.run("fp64", True)
+        runner.torch.cuda.synchronize()
+        runs.append(transfer_rates(ctx.launch_records(), time.perf_counter() - t0))
+    ctx.set_timing(False)
+    out = {"fp64_tree_lookahead16": runs[-1]}
+    if link:
+        out["link_reference"] = link_reference(runner.torch)
+    log("transfers", out)
     return out
 
 
@@ -399,6 +427,10 @@ def main():
                          "DAGs (no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
+    ap.add_argument("--transfers", action="store_true",
+                    help="only the budgeted meson transfers: --steps timed eager FP64 executes "
+                         "(Tree, lookahead 16, leaves on the host) with per-copy events, no other "
+                         "copies (for a memory-copy trace)")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -461,6 +493,11 @@ def main():
     ALL = X.binding.LOOKAHEAD_ALL
     ctx.set_options(leaves_resident=True, wave_lookahead=ALL, use_graphs=True)
     runner = DeviceRunner(ctx, 0)
+    if args.transfers:
+        print(json.dumps({"transfers": transfer_study(ctx, runner, budgets["fp64"], reps=args.steps,
+                                                      link=False),
+                          "budget_bytes": budgets["fp64"]}), flush=True)
+        return
     tiles = {}
     for prec in ("fp64", "fp32", "bf16x3"):
         if prec == "fp64" and args.fp64_variant:
@@ -566,23 +603,7 @@ def main():
                     "tflops": round(p["flops"] / (d2 / reps) / 1e12, 3)}
                 log(key, budgeted[key])
         extras["budgeted"] = budgeted
-        # the host-transfer step on its own: per-copy events on the copy stream
-        # in a timed (eager) execute of the budgeted FP64 Tree order, lookahead 16
-        ctx.set_mem_budget(budgets["fp64"])
-        ctx.schedule("tree")
-        ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=False)
-        ctx.set_timing(True)
-        runner.run("fp64", True)                     # plans and warms up
-        runner.torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        runner.run("fp64", True)
-        runner.torch.cuda.synchronize()
-        tts = time.perf_counter() - t0
-        recs = ctx.launch_records()
-        ctx.set_timing(False)
-        extras["transfers"] = {"fp64_tree_lookahead16": transfer_rates(recs, tts),
-                               "link_reference": link_reference(runner.torch)}
-        log("transfers", extras["transfers"])
+        extras["transfers"] = transfer_study(ctx, runner, budgets["fp64"])
         ctx.set_mem_budget(None)
         # the baryon configuration (FP64) and its precision form, per-kernel rates
         extras["baryon_mix"] = workload_rooflines("baryon_mix", ("fp64", "fp32", "bf16x3"),
