@@ -163,6 +163,24 @@ typedef struct {
                          wait for the compute stream)                                   */
 } cdag_launch_record;
 
+/* One record of a traced execute (cdag_trace_execute). */
+enum cdag_trace_op { CDAG_TR_RECORD = 0, CDAG_TR_WAIT = 1, CDAG_TR_READ = 2, CDAG_TR_WRITE = 3 };
+enum cdag_trace_space { CDAG_SPACE_ARENA = 0, CDAG_SPACE_SPILL = 1, CDAG_SPACE_STAGE = 2 };
+typedef struct {
+  int32_t op;       /* cdag_trace_op                                                     */
+  int32_t stream;   /* 0: the compute stream, 1: the copy stream                         */
+  int64_t seq;      /* READ, WRITE: number of the operation (one host transfer, or all
+                       kernels of one step) they belong to; -1 for events               */
+  int64_t step;     /* plan step that issues the record                                  */
+  int64_t node;     /* READ, WRITE: the tensor; -1 for events                            */
+  int64_t event;    /* RECORD, WAIT: 2 * step + stream of the event's step and stream    */
+  int32_t space;    /* READ, WRITE: cdag_trace_space of the range                        */
+  int32_t reserved;
+  int64_t off;      /* READ, WRITE: byte offset in the space (STAGE: 0 within the leaf's
+                       own staging buffer)                                               */
+  int64_t bytes;    /* READ, WRITE: bytes                                                */
+} cdag_trace_rec;
+
 int cdag_create(cdag_ctx** out);
 int cdag_destroy(cdag_ctx* c);
 const char* cdag_last_error(void);
@@ -225,6 +243,19 @@ int cdag_set_options(cdag_ctx* c, int leaves_resident, int wave_max, int64_t wav
  * and per-transfer records (execution then runs without graph replay);
  * 0 (default) turns it off. */
 int cdag_set_timing(cdag_ctx* c, int timing);
+/* Host-only: the eager two-stream issue order that execute would follow for
+ * (prec, batched), recorded without any HIP call: per step, the copy stream's
+ * waits for compute events, its transfers (the ranges each reads and writes),
+ * its event record, the compute stream's waits for copy events, the ranges
+ * the step's kernels read and write, and the compute event record.  It lets a
+ * CPU check that every pair of conflicting accesses is ordered by a stream or
+ * an event (the plan's data movement, Sec. II-A and Sec. IV-C).  *n_out
+ * (nullable) receives the count; at most cap records are written.
+ * fail_at >= 0 makes the walk fail with CDAG_E_HIP at that record, as a failed
+ * HIP call would (an error-path check).  Needs schedule; no device. */
+int cdag_trace_execute(cdag_ctx* c, int prec, int batched, cdag_trace_rec* out, int64_t cap, int64_t* n_out,
+                       int64_t fail_at);
+
 /* Per-launch records of the last execute made with timing on, in launch order.
  * *n_out (nullable) receives the count; at most cap records are written. */
 int cdag_launch_records(cdag_ctx* c, cdag_launch_record* out, int64_t cap, int64_t* n_out);

@@ -69,6 +69,16 @@ class cdag_launch_record(C.Structure):
 
 LAUNCH_TYPES = {0: "hec", 1: "reduce", 2: "hca", 3: "xsum", 4: "h2d", 5: "d2h"}
 
+
+class cdag_trace_rec(C.Structure):
+    _fields_ = [("op", C.c_int32), ("stream", C.c_int32), ("seq", C.c_int64), ("step", C.c_int64),
+                ("node", C.c_int64), ("event", C.c_int64), ("space", C.c_int32), ("reserved", C.c_int32),
+                ("off", C.c_int64), ("bytes", C.c_int64)]
+
+
+TRACE_OPS = {0: "record", 1: "wait", 2: "read", 3: "write"}
+TRACE_SPACES = {0: "arena", 1: "spill", 2: "stage"}
+
 _lib = None
 
 
@@ -102,6 +112,7 @@ def lib():
             "cdag_dag_stats": [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double),
                                C.POINTER(C.c_double)],
             "cdag_launch_records": [P, C.POINTER(cdag_launch_record), I64, C.POINTER(I64)],
+            "cdag_trace_execute": [P, C.c_int, C.c_int, C.POINTER(cdag_trace_rec), I64, C.POINTER(I64), I64],
             "cdag_set_tile": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int],
             "cdag_get_tile": [P, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                               C.POINTER(C.c_int), C.POINTER(C.c_int)],
@@ -128,7 +139,9 @@ def lib():
 
 
 EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "cdag_build_general", "schedule",
-            "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_launch_records", "cdag_dag_stats", "cdag_set_tile", "cdag_get_tile", "cdag_memsim", "cdag_plan", "cdag_plan_ops",
+            "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_launch_records",
+            "cdag_trace_execute", "cdag_dag_stats", "cdag_set_tile", "cdag_get_tile", "cdag_memsim",
+            "cdag_plan", "cdag_plan_ops",
             "cdag_get_nodes", "cdag_graph_roots", "cdag_bind_device", "cdag_bind_arena",
             "execute", "cdag_autotune", "fetch_correlators", "cdag_fetch_sums")
 
@@ -265,6 +278,17 @@ GRIDS = {0: "persistent", 1: "one workgroup per item"}
 def variant_index(tile: int, grid: int, lds_stages: int) -> int:
     """The library's single-integer encoding of a kernel variant."""
     return tile + len(TILES) * (grid + 2 * (2 - lds_stages))
+
+
+def cdag_trace_execute(h, prec: str = "fp64", batched: bool = False, fail_at: int = -1) -> List[dict]:
+    """The eager two-stream issue order of an execute, recorded without HIP."""
+    n = C.c_int64()
+    _check(lib().cdag_trace_execute(h, PREC[prec], int(batched), None, 0, C.byref(n), int(fail_at)))
+    buf = (cdag_trace_rec * max(1, n.value))()
+    _check(lib().cdag_trace_execute(h, PREC[prec], int(batched), buf, n.value, C.byref(n), int(fail_at)))
+    return [{"op": TRACE_OPS[r.op], "stream": r.stream, "seq": r.seq, "step": r.step, "node": r.node,
+             "event": r.event, "space": TRACE_SPACES.get(r.space), "off": r.off, "bytes": r.bytes}
+            for r in buf[:n.value]]
 
 
 def cdag_set_tile(h, prec: str, kind: int, nvec: int, tile: int, grid: int = 1,
@@ -454,6 +478,9 @@ class Context:
 
     def execute(self, prec="fp64", batched=False):
         return execute(self.h, prec, batched)
+
+    def trace_execute(self, prec="fp64", batched=False, fail_at=-1):
+        return cdag_trace_execute(self.h, prec, batched, fail_at)
 
     def autotune(self, prec="fp64", batched=True, reps=3, in_situ=False):
         return cdag_autotune(self.h, prec, batched, reps, in_situ)

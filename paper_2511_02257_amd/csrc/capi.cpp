@@ -241,6 +241,20 @@ int cdag_launch_records(cdag_ctx* h, cdag_launch_record* out, int64_t cap, int64
   });
 }
 
+int cdag_trace_execute(cdag_ctx* h, int prec, int batched, cdag_trace_rec* out, int64_t cap, int64_t* n_out,
+                       int64_t fail_at) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    need(cap >= 0 && (cap == 0 || out != nullptr), CDAG_E_INVALID, "out is NULL");
+    cdag::ensure_plan(h->c, prec, batched);
+    std::vector<cdag_trace_rec> t;
+    cdag::trace_execute(h->c, prec, t, fail_at);
+    const int64_t n = std::min<int64_t>(cap, (int64_t)t.size());
+    if (n > 0) std::memcpy(out, t.data(), (size_t)n * sizeof(cdag_trace_rec));
+    if (n_out) *n_out = (int64_t)t.size();
+  });
+}
+
 int cdag_set_tile(cdag_ctx* h, int prec, int kind, int nvec, int tile, int grid, int lds_stages, int split_k) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {

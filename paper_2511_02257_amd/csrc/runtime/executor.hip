@@ -267,18 +267,18 @@ int64_t launch_step(const KernelPlan& kp, int64_t s, int prec, char* arena, hipS
   return n;
 }
 
-// Enqueue steps [s0, s1): copies on `copy`, kernels on `comp`, cross-stream
-// waits from the plan.  With copy == comp (how segments are captured) every
-// dependency is the stream order and no event is used.  In a captured
-// segment, waits on steps before s0 are left out: the segments' graphs run one
-// after another on one stream, so everything before s0 has finished when the
-// segment starts.
-int64_t issue_steps(Ctx& c, Device& D, int prec, int64_t s0, int64_t s1, hipStream_t comp,
-                    hipStream_t copy, Device* timed, bool in_capture) {
+// Walk steps [s0, s1): each step's copies (with waits for the compute work
+// that last used their memory), then its kernels (after waiting for the copies
+// they need), with cross-stream waits from the plan.  With one_stream (how
+// segments are captured) every dependency is the stream order and no event is
+// used.  In a captured segment, waits on steps before s0 are left out: the
+// segments' graphs run one after another on one stream, so everything before
+// s0 has finished when the segment starts.  Ops issues the work (HipOps) or
+// records it (TraceOps).
+template <class Ops>
+int64_t walk_steps(const Ctx& c, int prec, int64_t s0, int64_t s1, bool one_stream, bool in_capture, Ops& ops) {
   const Plan& p = c.plan;
-  const KernelPlan& kp = c.kplan;
   const int eb = prec == CDAG_FP64 ? 16 : 8;
-  const bool one_stream = copy == comp;
   int64_t copy_waited = in_capture ? s0 - 1 : -1, comp_waited = in_capture ? s0 - 1 : -1;
   int64_t n_launch = 0;
   for (int64_t s = s0; s < s1; ++s) {
@@ -286,49 +286,144 @@ int64_t issue_steps(Ctx& c, Device& D, int prec, int64_t s0, int64_t s1, hipStre
     int64_t need_copy = -1;
     for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
       const PlanRec& r = p.recs[ri];
-      const size_t sz = (size_t)c.dag.size(r.node, eb);
       if (r.op == OP_D2H || r.op == OP_H2D) {
         if (!one_stream && r.wait_comp > copy_waited) {
-          HIPC(hipStreamWaitEvent(copy, D.ev_comp[r.wait_comp], 0));
+          ops.copy_waits_for_compute(r.wait_comp, s);
           copy_waited = r.wait_comp;
         }
-        hipEvent_t ta = nullptr, tb = nullptr;
-        if (timed) {
-          ta = timed->timing_event();
-          tb = timed->timing_event();
-          HIPC(hipEventRecord(ta, copy));
-        }
-        if (r.op == OP_D2H) {
-          HIPC(hipMemcpyAsync((char*)D.spill + r.host_off, D.arena + r.dev_off, sz, hipMemcpyDeviceToHost, copy));
-        } else {
-          const void* src = c.dag.is_leaf(r.node) ? D.stage[prec][r.node] : (const void*)((char*)D.spill + r.host_off);
-          HIPC(hipMemcpyAsync(D.arena + r.dev_off, src, sz, hipMemcpyHostToDevice, copy));
-          any_h2d = true;
-        }
-        if (timed) {
-          HIPC(hipEventRecord(tb, copy));
-          const int32_t k = c.dag.kind[r.node];
-          timed->tpairs.push_back({-2, r.op == OP_D2H ? CDAG_LAUNCH_D2H : CDAG_LAUNCH_H2D,
-                                   k >= 0 ? (1 << k) : 0, s, (double)sz, ta, tb});
-        }
+        ops.transfer(r, c.dag.size(r.node, eb), s);
+        any_h2d |= r.op == OP_H2D;
         any_copy = true;
       } else if (r.op == OP_ALLOC && r.wait_copy >= 0) {
         need_copy = std::max(need_copy, r.wait_copy);
       }
     }
     if (!one_stream) {
-      if (any_copy) HIPC(hipEventRecord(D.ev_copy[s], copy));
+      if (any_copy) ops.record_copy(s);
       if (any_h2d) need_copy = std::max(need_copy, s);
       if (need_copy > comp_waited) {
-        HIPC(hipStreamWaitEvent(comp, D.ev_copy[need_copy], 0));
+        ops.compute_waits_for_copy(need_copy, s);
         comp_waited = need_copy;
       }
     }
-    n_launch += launch_step(kp, s, prec, D.arena, comp, timed);
-    if (!one_stream) HIPC(hipEventRecord(D.ev_comp[s], comp));
+    n_launch += ops.launch(s);
+    if (!one_stream) ops.record_compute(s);
   }
   return n_launch;
 }
+
+// The issuing form: transfers on copy_s, kernels on comp_s, the device's
+// events ev_comp[s] / ev_copy[s] of step s.
+struct HipOps {
+  const Ctx& c;
+  Device& D;
+  int prec;
+  hipStream_t comp_s, copy_s;
+  Device* timed;
+
+  void copy_waits_for_compute(int64_t step, int64_t) { HIPC(hipStreamWaitEvent(copy_s, D.ev_comp[step], 0)); }
+  void compute_waits_for_copy(int64_t step, int64_t) { HIPC(hipStreamWaitEvent(comp_s, D.ev_copy[step], 0)); }
+  void record_copy(int64_t s) { HIPC(hipEventRecord(D.ev_copy[s], copy_s)); }
+  void record_compute(int64_t s) { HIPC(hipEventRecord(D.ev_comp[s], comp_s)); }
+  int64_t launch(int64_t s) { return launch_step(c.kplan, s, prec, D.arena, comp_s, timed); }
+  void transfer(const PlanRec& r, int64_t bytes, int64_t s) {
+    const size_t sz = (size_t)bytes;
+    hipEvent_t ta = nullptr, tb = nullptr;
+    if (timed) {
+      ta = timed->timing_event();
+      tb = timed->timing_event();
+      HIPC(hipEventRecord(ta, copy_s));
+    }
+    if (r.op == OP_D2H) {
+      HIPC(hipMemcpyAsync((char*)D.spill + r.host_off, D.arena + r.dev_off, sz, hipMemcpyDeviceToHost, copy_s));
+    } else {
+      const void* src = c.dag.is_leaf(r.node) ? D.stage[prec][r.node] : (const void*)((char*)D.spill + r.host_off);
+      HIPC(hipMemcpyAsync(D.arena + r.dev_off, src, sz, hipMemcpyHostToDevice, copy_s));
+    }
+    if (timed) {
+      HIPC(hipEventRecord(tb, copy_s));
+      const int32_t k = c.dag.kind[r.node];
+      timed->tpairs.push_back({-2, r.op == OP_D2H ? CDAG_LAUNCH_D2H : CDAG_LAUNCH_H2D,
+                               k >= 0 ? (1 << k) : 0, s, (double)sz, ta, tb});
+    }
+  }
+};
+
+int64_t issue_steps(Ctx& c, Device& D, int prec, int64_t s0, int64_t s1, hipStream_t comp, hipStream_t copy,
+                    Device* timed, bool in_capture) {
+  HipOps ops{c, D, prec, comp, copy, timed};
+  return walk_steps(c, prec, s0, s1, copy == comp, in_capture, ops);
+}
+
+// The recording form: the same walk with no HIP call, writing what each stream
+// would do (event records and waits, and the byte ranges that every transfer
+// and every step's kernels read and write).  fail_at >= 0 throws at that
+// record, as a failed HIP call would.
+struct TraceOps {
+  const Ctx& c;
+  int prec;
+  std::vector<cdag_trace_rec>& out;
+  int64_t fail_at;
+  int64_t seq = 0;
+
+  void put(const cdag_trace_rec& r) {
+    if ((int64_t)out.size() == fail_at)
+      throw Error(CDAG_E_HIP, "injected failure at trace record " + std::to_string(fail_at));
+    out.push_back(r);
+  }
+  static cdag_trace_rec blank(int32_t op, int32_t stream, int64_t step) {
+    cdag_trace_rec r{};
+    r.op = op;
+    r.stream = stream;
+    r.step = step;
+    r.seq = r.node = r.event = -1;
+    return r;
+  }
+  void event(int32_t op, int32_t stream, int64_t ev_step, int32_t ev_stream, int64_t s) {
+    cdag_trace_rec r = blank(op, stream, s);
+    r.event = 2 * ev_step + ev_stream;
+    put(r);
+  }
+  void access(int32_t op, int32_t stream, int64_t s, int64_t node, int32_t space, int64_t off, int64_t bytes) {
+    cdag_trace_rec r = blank(op, stream, s);
+    r.seq = seq;
+    r.node = node;
+    r.space = space;
+    r.off = off;
+    r.bytes = bytes;
+    put(r);
+  }
+  void copy_waits_for_compute(int64_t step, int64_t s) { event(CDAG_TR_WAIT, 1, step, 0, s); }
+  void compute_waits_for_copy(int64_t step, int64_t s) { event(CDAG_TR_WAIT, 0, step, 1, s); }
+  void record_copy(int64_t s) { event(CDAG_TR_RECORD, 1, s, 1, s); }
+  void record_compute(int64_t s) { event(CDAG_TR_RECORD, 0, s, 0, s); }
+  void transfer(const PlanRec& r, int64_t bytes, int64_t s) {
+    if (r.op == OP_D2H) {
+      access(CDAG_TR_READ, 1, s, r.node, CDAG_SPACE_ARENA, r.dev_off, bytes);
+      access(CDAG_TR_WRITE, 1, s, r.node, CDAG_SPACE_SPILL, r.host_off, bytes);
+    } else {
+      if (c.dag.is_leaf(r.node)) access(CDAG_TR_READ, 1, s, r.node, CDAG_SPACE_STAGE, 0, bytes);
+      else access(CDAG_TR_READ, 1, s, r.node, CDAG_SPACE_SPILL, r.host_off, bytes);
+      access(CDAG_TR_WRITE, 1, s, r.node, CDAG_SPACE_ARENA, r.dev_off, bytes);
+    }
+    ++seq;
+  }
+  int64_t launch(int64_t s) {
+    const Plan& p = c.plan;
+    const int eb = prec == CDAG_FP64 ? 16 : 8;
+    for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
+      const PlanRec& r = p.recs[ri];
+      if (r.op != OP_EXEC) continue;
+      const int64_t* ch = c.dag.children_begin(r.node);
+      access(CDAG_TR_READ, 0, s, ch[0], CDAG_SPACE_ARENA, r.a_off, c.dag.size(ch[0], eb));
+      access(CDAG_TR_READ, 0, s, ch[1], CDAG_SPACE_ARENA, r.b_off, c.dag.size(ch[1], eb));
+      if (c.dag.kind[r.node] != HCA)
+        access(CDAG_TR_WRITE, 0, s, r.node, CDAG_SPACE_ARENA, r.dev_off, c.dag.size(r.node, eb));
+    }
+    ++seq;
+    return c.kplan.launch_off[s + 1] - c.kplan.launch_off[s];
+  }
+};
 
 constexpr int64_t kSegmentSteps = 64;   // steps per captured graph when transfers are present
 }  // namespace
@@ -477,6 +572,12 @@ int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
   }
   c.timing = timing;
   return tuned;
+}
+
+void trace_execute(const Ctx& c, int prec, std::vector<cdag_trace_rec>& out, int64_t fail_at) {
+  out.clear();
+  TraceOps ops{c, prec, out, fail_at};
+  walk_steps(c, prec, 0, (int64_t)c.plan.steps.size(), false, false, ops);
 }
 
 void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {

@@ -1,0 +1,160 @@
+"""Executor walk without a GPU (CPU only): the eager two-stream issue order,
+recorded by cdag_trace_execute, checked for races.
+
+A happens-before check with vector clocks over the two streams: every pair of
+accesses to overlapping bytes of the same space (device arena, host spill
+pool, a leaf's staging buffer) where one is a write must be ordered, by the
+stream order or by an event the later stream waited for.  The checker is
+pinned by planting mistakes in the trace (a wait taken out) and requiring that
+it reports them.  Transfers must follow the plan's op list, every wait must
+name an event recorded earlier, and an injected failure at any record must
+leave the context usable.
+"""
+import pytest
+
+import paper_2511_02257_amd as X
+from paper_2511_02257_amd import binding as B
+from synth import workloads as W
+from oracle import dag as OD
+from oracle import schedules as OS
+
+
+def races(trace):
+    """(earlier record index, later record index) of every unordered conflicting pair."""
+    clock = {0: [0, 0], 1: [0, 0]}
+    events = {}
+    op_clock = {}
+    seen = []          # (index, space key, lo, hi, write, stream, clock, seq)
+    bad = []
+    for i, r in enumerate(trace):
+        st = r["stream"]
+        if r["op"] == "record":
+            events[r["event"]] = list(clock[st])
+            continue
+        if r["op"] == "wait":
+            e = events[r["event"]]
+            clock[st] = [max(a, b) for a, b in zip(clock[st], e)]
+            continue
+        if r["seq"] not in op_clock:
+            clock[st][st] += 1
+            op_clock[r["seq"]] = list(clock[st])
+        vc = op_clock[r["seq"]]
+        key = (r["space"], r["node"] if r["space"] == "stage" else None)
+        lo, hi, w = r["off"], r["off"] + r["bytes"], r["op"] == "write"
+        for j, k2, lo2, hi2, w2, st2, vc2, seq2 in seen:
+            if k2 == key and seq2 != r["seq"] and (w or w2) and lo2 < hi and lo < hi2:
+                if vc2[st2] > vc[st2]:
+                    bad.append((j, i))
+        seen.append((i, key, lo, hi, w, st, vc, r["seq"]))
+    return bad
+
+
+def _ctx(wl):
+    c = X.Context()
+    c.build_cdag(wl.leaves, wl.graphs)
+    return c
+
+
+def _cases():
+    yield "meson", W.meson_ring(n_leaves=8, nvec=8, nt=2, n_graphs=24, lmin=4, lmax=7, seed=31,
+                                with_data=False)
+    yield "baryon", W.baryon_mix(n_bar=4, n_mes=4, nvec=4, nt=2, n_graphs=10, seed=32, with_data=False)
+    yield "rank4", W.rank4_mix(nvec=3, nt=2, n_graphs=12, seed=33, with_data=False)
+
+
+CASES = list(_cases())
+
+
+def _budget(wl, frac):
+    d = OD.build(wl.leaves, wl.graphs)
+    return OS.memsim(d, OS.input_order(d), 16)["peak_live"] // frac
+
+
+@pytest.mark.parametrize("name,wl", CASES, ids=[n for n, _ in CASES])
+@pytest.mark.parametrize("policy", ["input", "tree", "node"])
+def test_eager_walk_has_no_races(name, wl, policy):
+    c = _ctx(wl)
+    c.schedule(policy)
+    checked = 0
+    for frac in (None, 3, 5):
+        budget = None if frac is None else _budget(wl, frac)
+        c.set_mem_budget(budget)
+        for batched, look, resident in ((False, 0, False), (True, 0, False), (True, 16, False),
+                                        (True, B.LOOKAHEAD_ALL, True)):
+            c.set_options(leaves_resident=resident, wave_lookahead=look)
+            for prec in ("fp64", "fp32"):
+                try:
+                    p = c.plan(prec, batched)
+                except X.CdagError as e:
+                    assert e.code == B.E_BUDGET
+                    continue
+                t = c.trace_execute(prec, batched)
+                assert races(t) == [], (name, policy, frac, batched, look, resident, prec)
+                # transfers in the plan's order, one per H2D / D2H record
+                moves = [(r["node"], r["step"]) for r in t if r["op"] == "write" and
+                         (r["stream"] == 1)]
+                plan = [(node, step) for op, node, step in c.plan_ops() if op in ("H2D", "D2H")]
+                assert moves == plan
+                assert p["n_h2d"] + p["n_d2h"] == len(plan)
+                recorded = set()
+                for r in t:
+                    if r["op"] == "record":
+                        recorded.add(r["event"])
+                    elif r["op"] == "wait":
+                        assert r["event"] in recorded
+                checked += 1
+    assert checked >= 10
+    c.close()
+
+
+def test_checker_finds_planted_missing_waits():
+    """Waits taken out of a budgeted walk: of a sample of single waits, at
+    least one leaves a conflicting pair unordered; taking all out leaves many."""
+    name, wl = CASES[0]
+    c = _ctx(wl)
+    c.schedule("tree")
+    c.set_mem_budget(_budget(wl, 4))
+    c.set_options(leaves_resident=False, wave_lookahead=0)
+    t = c.trace_execute("fp64", False)
+    c.close()
+    assert races(t) == []
+    waits = [i for i, r in enumerate(t) if r["op"] == "wait"]
+    assert len(waits) > 10
+    found = 0
+    for i in waits[::max(1, len(waits) // 12)]:
+        found += bool(races(t[:i] + t[i + 1:]))
+    assert found >= 1
+    assert len(races([r for r in t if r["op"] != "wait"])) > 10
+    # the copy stream's first wait guards an upload into memory that a kernel
+    # of an earlier step still reads; without it that pair is unordered
+    k = next(i for i, r in enumerate(t) if r["op"] == "wait" and r["stream"] == 1)
+    assert races(t[:k] + t[k + 1:])
+
+
+def test_injected_failures_leave_the_context_usable():
+    name, wl = CASES[0]
+    c = _ctx(wl)
+    c.schedule("tree")
+    c.set_mem_budget(_budget(wl, 4))
+    full = c.trace_execute("fp64", False)
+    for k in (0, 1, len(full) // 2, len(full) - 1):
+        with pytest.raises(X.CdagError) as e:
+            c.trace_execute("fp64", False, fail_at=k)
+        assert e.value.code == B.E_HIP
+        assert "injected" in str(e.value)
+        assert c.trace_execute("fp64", False) == full
+    assert c.trace_execute("fp64", False, fail_at=len(full)) == full      # past the end: no failure
+    c.close()
+
+
+def test_trace_needs_a_schedule_and_shapes():
+    c = X.Context()
+    with pytest.raises(X.CdagError) as e:
+        c.trace_execute()
+    assert e.value.code == B.E_STATE
+    c.build_general(2, [1, 1, 0], [(), (), (0, 1)])
+    c.schedule("tree")
+    with pytest.raises(X.CdagError) as e:
+        c.trace_execute()
+    assert e.value.code == B.E_STATE
+    c.close()
