@@ -506,8 +506,8 @@ def main():
         elif prec == "fp64" or not args.skip_extras:
             runner.autotune(prec, True, reps=3, in_situ=True)
         t, g, st, _ = ctx.get_tile(prec, 0, 64)
-        tiles[prec] = {"K22_N64": {"tile": list(X.TILES[t]), "grid": X.binding.GRIDS[g],
-                                   "lds_stages": st}}
+        tiles[prec] = {"K22_N64": {"tile": list(X.TILES[t]), "threads": X.binding.TILE_THREADS[t],
+                                   "grid": X.binding.GRIDS[g], "lds_stages": st}}
     log("autotuned tiles", tiles)
 
     # ---- headline: FP64, Tree, waves, leaves resident, graph replay
@@ -546,6 +546,7 @@ def main():
     out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
                        "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4),
                        "traffic": measured_traffic(variant), "tile": list(X.TILES[t64]),
+                       "threads": X.binding.TILE_THREADS[t64],
                        "grid": X.binding.GRIDS[g64], "lds_stages": st64,
                        "variant": [t64, g64, st64],
                        "kernel": "hec_mfma<double> (grouped K22 waves)",
