@@ -450,3 +450,37 @@ def test_degenerate_dags(prec):
             assert np.array_equal(r["corr"][2], r["corr"][3])
             assert sum_errors(wl, r["sums"], ref) <= TOL[prec]
             assert r["stats"]["plan"]["n_contr"] == 2 + 3 + 3    # two traces, one shared ring, chain
+
+
+def test_recorded_walk_is_the_executed_walk(meson_small):
+    """The eager execute issues its transfers and kernels in the order that
+    cdag_trace_execute records without a GPU (the walk the CPU race check
+    covers): same transfers (direction, step, bytes) in the same order, and
+    kernels in the same steps."""
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd.device import DeviceRunner
+    from oracle import dag as OD, schedules as OS
+    wl, ref = meson_small
+    d = OD.build(wl.leaves, wl.graphs)
+    budget = OS.memsim(d, OS.input_order(d), 16)["peak_live"] // 4
+    ctx = X.Context()
+    ctx.build_cdag(wl.leaves, wl.graphs)
+    ctx.schedule("tree")
+    ctx.set_mem_budget(budget)
+    ctx.set_options(leaves_resident=False, wave_lookahead=0, use_graphs=False)
+    runner = DeviceRunner(ctx, 0)
+    for batched in (False, True):
+        trace = ctx.trace_execute("fp64", batched)
+        ctx.set_timing(True)
+        runner.run("fp64", batched)
+        recs = ctx.launch_records()
+        ctx.set_timing(False)
+        corr = ctx.fetch_correlators()
+        assert rel_errors(corr, ref).max() <= TOL["fp64"]
+        want = [("d2h" if r["space"] == "spill" else "h2d", r["step"], r["bytes"])
+                for r in trace if r["op"] == "write" and r["stream"] == 1]
+        got = [(r["type"], r["step"], int(r["bytes"])) for r in recs if r["type"] in ("h2d", "d2h")]
+        assert got == want and len(got) > 0
+        assert sorted({r["step"] for r in trace if r["stream"] == 0 and r["op"] == "read"}) == \
+            sorted({r["step"] for r in recs if r["type"] in ("hec", "hca", "reduce")})
+    ctx.close()
