@@ -220,6 +220,16 @@ int cdag_build_general(cdag_ctx* c, int64_t n_nodes, int64_t n_leaves, const int
  * ids; *n_out (nullable) the number of contractions. */
 int schedule(cdag_ctx* c, int policy, int64_t* order_out, int64_t cap, int64_t* n_out);
 
+/* Install a contraction order found earlier (a saved schedule) instead of
+ * scheduling: order lists every contraction once, children before parents.
+ * The paper notes that a schedule, once found, serves any N; the order
+ * depends only on the DAG's structure, so an order saved from a DAG built
+ * with other N or Nt applies when the node ids match.  The order is copied.
+ * CDAG_E_INVALID: n differs from the number of contractions, an id out of
+ * range, a leaf, a repeat, or a contraction before one of its children.
+ * CDAG_E_STATE: no DAG built. */
+int cdag_set_order(cdag_ctx* c, const int64_t* order, int64_t n);
+
 /* Device-memory budget in bytes for planning (UINT64_MAX: unlimited, the
  * default). */
 int set_mem_budget(cdag_ctx* c, uint64_t bytes);

@@ -107,6 +107,7 @@ def lib():
             "cdag_build_general": [P, I64, I64, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
             "schedule": [P, C.c_int, C.POINTER(I64), I64, C.POINTER(I64)],
             "set_mem_budget": [P, C.c_uint64],
+            "cdag_set_order": [P, C.POINTER(I64), I64],
             "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
             "cdag_set_timing": [P, C.c_int],
             "cdag_dag_stats": [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double),
@@ -139,7 +140,7 @@ def lib():
 
 
 EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "cdag_build_general", "schedule",
-            "set_mem_budget", "cdag_set_options", "cdag_set_timing", "cdag_launch_records",
+            "set_mem_budget", "cdag_set_order", "cdag_set_options", "cdag_set_timing", "cdag_launch_records",
             "cdag_trace_execute", "cdag_dag_stats", "cdag_set_tile", "cdag_get_tile", "cdag_memsim",
             "cdag_plan", "cdag_plan_ops",
             "cdag_get_nodes", "cdag_graph_roots", "cdag_bind_device", "cdag_bind_arena",
@@ -226,6 +227,11 @@ def schedule(h, policy: str, check: bool = False) -> np.ndarray:
     n = C.c_int64()
     _check(lib().schedule(h, p, _i64p(out), cap, C.byref(n)))
     return out[:n.value].copy()
+
+
+def cdag_set_order(h, order: Sequence[int]) -> None:
+    a = np.ascontiguousarray(order, dtype=np.int64)
+    _check(lib().cdag_set_order(h, _i64p(a), len(a)))
 
 
 def set_mem_budget(h, nbytes: Optional[int]) -> None:
@@ -433,6 +439,9 @@ class Context:
 
     def schedule(self, policy, check=False):
         return schedule(self.h, policy, check)
+
+    def set_order(self, order):
+        cdag_set_order(self.h, order)
 
     def set_mem_budget(self, nbytes):
         set_mem_budget(self.h, nbytes)

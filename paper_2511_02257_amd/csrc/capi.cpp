@@ -203,6 +203,30 @@ int schedule(cdag_ctx* h, int policy, int64_t* order_out, int64_t cap, int64_t* 
   });
 }
 
+int cdag_set_order(cdag_ctx* h, const int64_t* order, int64_t n) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    cdag::Ctx& c = h->c;
+    need(c.built, CDAG_E_STATE, "build_cdag first");
+    const cdag::Dag& d = c.dag;
+    need(n == d.n_nodes() - d.n_leaves, CDAG_E_INVALID, "order must list every contraction once");
+    need(n == 0 || order != nullptr, CDAG_E_INVALID, "order is NULL");
+    std::vector<char> done(d.n_nodes(), 0);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t u = order[i];
+      need(u >= d.n_leaves && u < d.n_nodes(), CDAG_E_INVALID, "order: id out of range or a leaf");
+      need(!done[u], CDAG_E_INVALID, "order: a contraction is listed twice");
+      for (const int64_t* px = d.children_begin(u); px != d.children_end(u); ++px)
+        need(d.is_leaf(*px) || done[*px], CDAG_E_INVALID, "order: a contraction comes before its child");
+      done[u] = 1;
+    }
+    c.order.assign(order, order + n);
+    c.t_sched = 0.0;
+    c.scheduled = true;
+    c.version++;
+  });
+}
+
 int set_mem_budget(cdag_ctx* h, uint64_t bytes) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {

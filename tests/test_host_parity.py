@@ -476,3 +476,61 @@ def OP_counts(wl, policy):
     d = OD.build(wl.leaves, wl.graphs)
     order = OS.schedule(d, policy, 16)
     return d, order, OP.plan(d, order, elem_bytes=16, budget=OP.UNLIMITED, batched=False)
+
+
+def test_saved_order_serves_another_n():
+    """A schedule found once is installed on a DAG of the same structure built
+    with another N and Nt (the paper reuses schedules across N): same plan ops,
+    and memory figures that scale with the element count."""
+    small = W.meson_ring(n_leaves=8, nvec=4, nt=2, n_graphs=30, lmin=4, lmax=7, seed=41, with_data=False)
+    big = W.meson_ring(n_leaves=8, nvec=16, nt=3, n_graphs=30, lmin=4, lmax=7, seed=41, with_data=False)
+    a, b = ctx_for(small), ctx_for(big)
+    for policy in ("tree", "sibling", "node"):
+        order = a.schedule(policy)
+        b.set_order(order)
+        assert list(b.schedule(policy)) == list(order)        # what b would find itself
+        b.set_order(order)
+        scale = (16 * 16 * 3) // (4 * 4 * 2)
+        Ma, pa, la = a.memsim(order, 16)
+        Mb, pb, lb = b.memsim(order, 16)
+        assert [x * scale for x in Ma] == list(Mb) and pa * scale == pb and la * scale == lb
+        for budget_frac in (None, 3):
+            for c, wl in ((a, small), (b, big)):
+                if budget_frac is None:
+                    c.set_mem_budget(None)
+                else:
+                    d = OD.build(wl.leaves, wl.graphs)
+                    c.set_mem_budget(OS.memsim(d, [int(x) for x in order], 16)["peak_live"] // budget_frac)
+            a.plan("fp64", True)
+            b.plan("fp64", True)
+            assert a.plan_ops() == b.plan_ops()
+        a.set_mem_budget(None)
+        b.set_mem_budget(None)
+    a.close()
+    b.close()
+
+
+def test_set_order_validation():
+    wl = W.fig1_dag("fgh", with_data=False)
+    c = X.Context()
+    with pytest.raises(X.CdagError) as e:
+        c.set_order([4, 5, 6, 7])
+    assert e.value.code == B.E_STATE
+    c.build_cdag(wl.leaves, wl.graphs)
+    good = [int(x) for x in c.schedule("tree")]
+    d = OD.build(wl.leaves, wl.graphs)
+    e_id = next(u for u in d.contractions() if (d.left[u], d.right[u]) == (1, 2))
+    g_id = next(u for u in d.contractions() if d.left[u] == 0 and d.right[u] == e_id)
+    bad = [good[:-1],                                  # one missing
+           good + [good[0]],                           # too many
+           [good[0]] * len(good),                      # repeats
+           [0] + good[1:],                             # a leaf
+           [99] + good[1:],                            # out of range
+           [g_id] + [u for u in good if u != g_id]]    # g before its child e
+    for o in bad:
+        with pytest.raises(X.CdagError) as e:
+            c.set_order(o)
+        assert e.value.code == B.E_INVALID, o
+    c.set_order(good)
+    assert c.plan("fp64", False)["n_contr"] == 4
+    c.close()
