@@ -8,10 +8,10 @@ hash starts the file afresh.
 
     python -m paper_2511_02257_amd.profiling traffic \\
         --kernel 'hec_mfma<double' --variant 15 \\
-        --fetch gpurun_out/pmc_fetch/fetch_counter_collection.csv \\
-        --write gpurun_out/pmc_write/write_counter_collection.csv \\
-        --copy-fetch gpurun_out/pmc_copy_fetch/cf_counter_collection.csv \\
-        --copy-write gpurun_out/pmc_copy_write/cw_counter_collection.csv \\
+        --fetch out/pmc_fetch/fetch_counter_collection.csv \\
+        --write out/pmc_write/write_counter_collection.csv \\
+        --copy-fetch out/pmc_copy_fetch/cf_counter_collection.csv \\
+        --copy-write out/pmc_copy_write/cw_counter_collection.csv \\
         --copy-bytes 1073741824 --out profiles/hec_traffic_meson_ring.json
 """
 from __future__ import annotations
