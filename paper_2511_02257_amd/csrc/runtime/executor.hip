@@ -9,7 +9,9 @@
 // ev_comp[k].  All waits come from the plan (place()), so copies overlap
 // kernels of earlier steps whenever the memory they use is already free.
 // Graph replay: steps are captured in segments with transfers and kernels on
-// one stream, so the stream order alone carries every dependency.
+// one stream, so the stream order alone carries every dependency.  The eager
+// walk can also be recorded instead of issued (trace_execute), so that its
+// ordering can be checked on a host without a GPU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
