@@ -44,6 +44,12 @@ def test_meson_ring_full_fp64_bench_configuration(meson):
         assert p[k] == v, k
     assert np.array_equal(np.concatenate(b["corr"]).view(np.uint64),
                           np.concatenate(r["corr"]).view(np.uint64))
+    # the node-gain order under the same budget, waves with lookahead 16 and
+    # captured segments: same bits
+    n = run(wl, "node", "fp64", True, budget=gold["budget"], wave_lookahead=16)
+    assert n["stats"]["plan"]["n_evict"] > 0
+    assert np.array_equal(np.concatenate(n["corr"]).view(np.uint64),
+                          np.concatenate(r["corr"]).view(np.uint64))
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 4e-5)])
