@@ -177,7 +177,7 @@ def transfer_study(ctx, runner, budget, reps=1, link=True):
 def budgeted_schedules(ctx, runner, prec, budget, X):
     """Time-to-solution under the configuration's HBM budget with the leaves
     starting in pinned host memory (every transfer inside the time): input
-    order, Sibling and Tree cut into waves with lookahead 16 and replayed from
+    order, Sibling, Tree and node gain cut into waves with lookahead 16 and replayed from
     captured segments, Tree without lookahead, and Tree with one eager launch
     per contraction.  One warm-up and one timed execute each.  Every run's
     correlators are compared bit for bit with those of the resident run that
@@ -187,7 +187,7 @@ def budgeted_schedules(ctx, runner, prec, budget, X):
     out = {}
     ctx.set_mem_budget(budget)
     for policy, look, batched in (("input", 16, True), ("sibling", 16, True), ("tree", 16, True),
-                                  ("tree", 0, True), ("tree", 16, False)):
+                                  ("node", 16, True), ("tree", 0, True), ("tree", 16, False)):
         ctx.schedule(policy)
         ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=batched)
         key = policy + (f"_lookahead{look}" if look and batched else "") + ("" if batched else "_per_contraction")
