@@ -527,6 +527,14 @@ def main():
                    "mode": "waves of every ready contraction, one hipGraph replay",
                    "leaves": "resident in HBM", "flops_per_step": flops,
                    "t_schedule_tree_s": round(t_sched, 4), "autotuned_tiles": tiles},
+        # memory of the timed run: HBM held by the arena (leaves, tensor pool,
+        # split-K workspace, descriptors, results), the plan's resident peak, and
+        # host-to-device bytes per step (0: the leaves stay resident after the
+        # first upload).  The budgeted runs under extras carry the same figures.
+        "memory": {"arena_GB": round(st["plan"]["arena_bytes"] / 1e9, 4),
+                   "tensor_highwater_GB": round(st["plan"]["tensor_highwater"] / 1e9, 4),
+                   "peak_live_GB": round(st["plan"]["peak_live"] / 1e9, 4),
+                   "h2d_GB_per_step": round(st["plan"]["h2d_bytes"] / 1e9, 4)},
     }
 
     # ---- roofline of the exterior-contraction kernel (HIP events per launch)
