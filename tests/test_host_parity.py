@@ -534,3 +534,20 @@ def test_set_order_validation():
     c.set_order(good)
     assert c.plan("fp64", False)["n_contr"] == 4
     c.close()
+
+
+def test_header_is_plain_c99(tmp_path):
+    """include/cdag.h compiles as C99 with warnings as errors (the ABI is C)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "use.c"
+    src.write_text('#include "cdag.h"\n'
+                   "int main(void) { cdag_ctx* c = 0; cdag_trace_rec t; cdag_launch_record l;\n"
+                   "  cdag_plan_stats p; cdag_exec_stats e; (void)t; (void)l; (void)p; (void)e;\n"
+                   "  return cdag_create(&c); }\n")
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                        "-I", os.path.dirname(HEADER), "-c", str(src), "-o", str(tmp_path / "use.o")],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
