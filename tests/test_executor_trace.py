@@ -49,6 +49,71 @@ def races(trace):
     return bad
 
 
+def races_by_segment(trace):
+    """The same happens-before check, kept per byte segment: each segment holds
+    its last write and the reads since, so a new access is compared with those
+    only (an earlier write is ordered before the last one, or that pair was
+    already reported).  Finds a race exactly when races() does; fast enough
+    for full-size walks.  Returns the number of unordered pairs it saw."""
+    import bisect
+    clock = {0: [0, 0], 1: [0, 0]}
+    events = {}
+    op_clock = {}
+    spaces = {}        # key -> (los, segs); segs[k] = [lo, hi, last write, reads since]
+    n_bad = 0
+    for i, r in enumerate(trace):
+        st = r["stream"]
+        if r["op"] == "record":
+            events[r["event"]] = list(clock[st])
+            continue
+        if r["op"] == "wait":
+            clock[st] = [max(a, b) for a, b in zip(clock[st], events[r["event"]])]
+            continue
+        if r["seq"] not in op_clock:
+            clock[st][st] += 1
+            op_clock[r["seq"]] = list(clock[st])
+        cur = (st, op_clock[r["seq"]], r["seq"])
+        key = (r["space"], r["node"] if r["space"] == "stage" else None)
+        los, segs = spaces.setdefault(key, ([], []))
+        lo, hi, w = r["off"], r["off"] + r["bytes"], r["op"] == "write"
+
+        def split(x):
+            k = bisect.bisect_right(los, x) - 1
+            if k >= 0 and segs[k][0] < x < segs[k][1]:
+                a = segs[k]
+                b = [x, a[1], a[2], list(a[3])]
+                a[1] = x
+                los.insert(k + 1, x)
+                segs.insert(k + 1, b)
+        split(lo)
+        split(hi)
+        k = bisect.bisect_left(los, lo)
+        pos = lo
+        while True:
+            if k < len(segs) and segs[k][0] < hi:
+                if segs[k][0] > pos:                       # a gap nothing touched yet
+                    los.insert(k, pos)
+                    segs.insert(k, [pos, segs[k][0], None, []])
+                seg = segs[k]
+            elif pos < hi:
+                los.insert(k, pos)
+                segs.insert(k, [pos, hi, None, []])
+                seg = segs[k]
+            else:
+                break
+            prior = ([seg[2]] if seg[2] is not None else []) + (seg[3] if w else [])
+            for p_st, p_vc, p_seq in prior:
+                if p_seq != cur[2] and p_vc[p_st] > cur[1][p_st]:
+                    n_bad += 1
+            if w:
+                seg[2], seg[3] = cur, []
+            else:
+                seg[3].append(cur)
+            pos = seg[1]
+            k += 1
+    return n_bad
+
+
 def _ctx(wl):
     c = X.Context()
     c.build_cdag(wl.leaves, wl.graphs)
@@ -158,3 +223,40 @@ def test_trace_needs_a_schedule_and_shapes():
         c.trace_execute()
     assert e.value.code == B.E_STATE
     c.close()
+
+
+def test_segment_checker_agrees_with_the_pairwise_one():
+    """On clean walks and on walks with planted missing waits, both checkers
+    agree on whether there is a race."""
+    name, wl = CASES[0]
+    c = _ctx(wl)
+    for policy in ("tree", "input"):
+        c.schedule(policy)
+        c.set_mem_budget(_budget(wl, 4))
+        t = c.trace_execute("fp64", False)
+        assert races(t) == [] and races_by_segment(t) == 0
+        waits = [i for i, r in enumerate(t) if r["op"] == "wait"]
+        for i in waits[::max(1, len(waits) // 15)]:
+            u = t[:i] + t[i + 1:]
+            assert bool(races(u)) == (races_by_segment(u) > 0), i
+        u = [r for r in t if r["op"] != "wait"]
+        assert races_by_segment(u) > 0
+    c.close()
+
+
+@pytest.mark.parametrize("policy,look", [("input", 0), ("tree", 0), ("tree", 16), ("node", 16)])
+def test_full_meson_budgeted_walk_has_no_races(policy, look):
+    """The bench's budgeted meson configuration at full size (2000 graphs,
+    leaves on the host, a quarter of the input-order live peak, FP64)."""
+    wl = W.config("meson_ring", with_data=False)
+    c = _ctx(wl)
+    c.schedule("input")
+    budget = c.plan("fp64", False)["peak_live"] // 4
+    c.schedule(policy)
+    c.set_mem_budget(budget)
+    c.set_options(leaves_resident=False, wave_lookahead=look)
+    p = c.plan("fp64", True)
+    t = c.trace_execute("fp64", True)
+    c.close()
+    assert p["n_evict"] > 0 and p["n_d2h"] > 0
+    assert races_by_segment(t) == 0
