@@ -49,13 +49,57 @@ def races(trace):
     return bad
 
 
+def _visit(los, segs, lo, hi, fresh):
+    """Segments of one space covering [lo, hi), split at lo and hi, with gaps
+    filled by fresh(a, b) segments; segs[k] = [lo, hi, ...], sorted, disjoint."""
+    import bisect
+
+    def split(x):
+        k = bisect.bisect_right(los, x) - 1
+        if k >= 0 and segs[k][0] < x < segs[k][1]:
+            a = segs[k]
+            b = [x, a[1]] + [list(v) if isinstance(v, list) else v for v in a[2:]]
+            a[1] = x
+            los.insert(k + 1, x)
+            segs.insert(k + 1, b)
+    split(lo)
+    split(hi)
+    k = bisect.bisect_left(los, lo)
+    pos = lo
+    while pos < hi:
+        end = segs[k][0] if k < len(segs) and segs[k][0] < hi else hi
+        if end > pos:                                  # a gap nothing touched yet
+            los.insert(k, pos)
+            segs.insert(k, fresh(pos, end))
+        yield segs[k]
+        pos = segs[k][1]
+        k += 1
+
+
+def provenance_errors(trace):
+    """Reads whose bytes were last written by another tensor (or never written):
+    every device range a kernel or a spill reads must hold that tensor, and
+    every spill-pool range an upload reads must hold its spilled copy."""
+    spaces = {}
+    bad = []
+    for i, r in enumerate(trace):
+        if r["op"] not in ("read", "write") or r["space"] == "stage":
+            continue
+        los, segs = spaces.setdefault(r["space"], ([], []))
+        for seg in _visit(los, segs, r["off"], r["off"] + r["bytes"], lambda a, b: [a, b, None]):
+            if r["op"] == "write":
+                seg[2] = r["node"]
+            elif seg[2] != r["node"]:
+                bad.append((i, r["node"], seg[2]))
+    return bad
+
+
 def races_by_segment(trace):
     """The same happens-before check, kept per byte segment: each segment holds
     its last write and the reads since, so a new access is compared with those
     only (an earlier write is ordered before the last one, or that pair was
     already reported).  Finds a race exactly when races() does; fast enough
     for full-size walks.  Returns the number of unordered pairs it saw."""
-    import bisect
     clock = {0: [0, 0], 1: [0, 0]}
     events = {}
     op_clock = {}
@@ -75,32 +119,8 @@ def races_by_segment(trace):
         cur = (st, op_clock[r["seq"]], r["seq"])
         key = (r["space"], r["node"] if r["space"] == "stage" else None)
         los, segs = spaces.setdefault(key, ([], []))
-        lo, hi, w = r["off"], r["off"] + r["bytes"], r["op"] == "write"
-
-        def split(x):
-            k = bisect.bisect_right(los, x) - 1
-            if k >= 0 and segs[k][0] < x < segs[k][1]:
-                a = segs[k]
-                b = [x, a[1], a[2], list(a[3])]
-                a[1] = x
-                los.insert(k + 1, x)
-                segs.insert(k + 1, b)
-        split(lo)
-        split(hi)
-        k = bisect.bisect_left(los, lo)
-        pos = lo
-        while True:
-            if k < len(segs) and segs[k][0] < hi:
-                if segs[k][0] > pos:                       # a gap nothing touched yet
-                    los.insert(k, pos)
-                    segs.insert(k, [pos, segs[k][0], None, []])
-                seg = segs[k]
-            elif pos < hi:
-                los.insert(k, pos)
-                segs.insert(k, [pos, hi, None, []])
-                seg = segs[k]
-            else:
-                break
+        w = r["op"] == "write"
+        for seg in _visit(los, segs, r["off"], r["off"] + r["bytes"], lambda a, b: [a, b, None, []]):
             prior = ([seg[2]] if seg[2] is not None else []) + (seg[3] if w else [])
             for p_st, p_vc, p_seq in prior:
                 if p_seq != cur[2] and p_vc[p_st] > cur[1][p_st]:
@@ -109,8 +129,6 @@ def races_by_segment(trace):
                 seg[2], seg[3] = cur, []
             else:
                 seg[3].append(cur)
-            pos = seg[1]
-            k += 1
     return n_bad
 
 
@@ -247,7 +265,8 @@ def test_segment_checker_agrees_with_the_pairwise_one():
 @pytest.mark.parametrize("policy,look", [("input", 0), ("tree", 0), ("tree", 16), ("node", 16)])
 def test_full_meson_budgeted_walk_has_no_races(policy, look):
     """The bench's budgeted meson configuration at full size (2000 graphs,
-    leaves on the host, a quarter of the input-order live peak, FP64)."""
+    leaves on the host, a quarter of the input-order live peak, FP64): no
+    race, and every read finds its tensor."""
     wl = W.config("meson_ring", with_data=False)
     c = _ctx(wl)
     c.schedule("input")
@@ -260,3 +279,42 @@ def test_full_meson_budgeted_walk_has_no_races(policy, look):
     c.close()
     assert p["n_evict"] > 0 and p["n_d2h"] > 0
     assert races_by_segment(t) == 0
+    assert provenance_errors(t) == []
+
+
+@pytest.mark.parametrize("name,wl", CASES, ids=[n for n, _ in CASES])
+def test_every_read_finds_its_tensor(name, wl):
+    """Placement (arena and spill-pool offsets): every range read holds the
+    tensor that is read, across budgets, waves and resident leaves."""
+    c = _ctx(wl)
+    for policy in ("input", "tree"):
+        c.schedule(policy)
+        for frac in (None, 3, 5):
+            c.set_mem_budget(None if frac is None else _budget(wl, frac))
+            for batched, look, resident in ((False, 0, False), (True, 16, False), (True, 0, True)):
+                c.set_options(leaves_resident=resident, wave_lookahead=look)
+                try:
+                    c.plan("fp64", batched)
+                except X.CdagError:
+                    continue
+                t = c.trace_execute("fp64", batched)
+                if resident:   # resident leaves are uploaded once, outside the walk
+                    t = [r for r in t if not (r["op"] == "read" and r["node"] < len(wl.leaves))]
+                assert provenance_errors(t) == [], (policy, frac, batched, look, resident)
+    c.close()
+
+
+def test_provenance_check_finds_a_planted_overlap():
+    """Moving one upload's destination onto another live tensor is reported."""
+    name, wl = CASES[0]
+    c = _ctx(wl)
+    c.schedule("tree")
+    c.set_mem_budget(_budget(wl, 4))
+    t = c.trace_execute("fp64", False)
+    c.close()
+    assert provenance_errors(t) == []
+    ups = [i for i, r in enumerate(t) if r["op"] == "write" and r["stream"] == 1 and r["space"] == "arena"]
+    k1, k2 = ups[0], ups[1]
+    u = [dict(r) for r in t]
+    u[k2]["off"] = u[k1]["off"]             # second upload lands on the first
+    assert provenance_errors(u)
