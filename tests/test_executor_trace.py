@@ -262,20 +262,21 @@ def test_segment_checker_agrees_with_the_pairwise_one():
     c.close()
 
 
-@pytest.mark.parametrize("policy,look", [("input", 0), ("tree", 0), ("tree", 16), ("node", 16)])
-def test_full_meson_budgeted_walk_has_no_races(policy, look):
+@pytest.mark.parametrize("policy,look,prec", [("input", 0, "fp64"), ("tree", 0, "fp64"), ("tree", 16, "fp64"),
+                                              ("node", 16, "fp64"), ("tree", 16, "fp32"), ("input", 0, "fp32")])
+def test_full_meson_budgeted_walk_has_no_races(policy, look, prec):
     """The bench's budgeted meson configuration at full size (2000 graphs,
-    leaves on the host, a quarter of the input-order live peak, FP64): no
-    race, and every read finds its tensor."""
+    leaves on the host, a quarter of the input-order live peak of the
+    precision): no race, and every read finds its tensor."""
     wl = W.config("meson_ring", with_data=False)
     c = _ctx(wl)
     c.schedule("input")
-    budget = c.plan("fp64", False)["peak_live"] // 4
+    budget = c.plan(prec, False)["peak_live"] // 4
     c.schedule(policy)
     c.set_mem_budget(budget)
     c.set_options(leaves_resident=False, wave_lookahead=look)
-    p = c.plan("fp64", True)
-    t = c.trace_execute("fp64", True)
+    p = c.plan(prec, True)
+    t = c.trace_execute(prec, True)
     c.close()
     assert p["n_evict"] > 0 and p["n_d2h"] > 0
     assert races_by_segment(t) == 0
