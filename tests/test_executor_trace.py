@@ -319,3 +319,23 @@ def test_provenance_check_finds_a_planted_overlap():
     u = [dict(r) for r in t]
     u[k2]["off"] = u[k1]["off"]             # second upload lands on the first
     assert provenance_errors(u)
+
+
+@pytest.mark.parametrize("name,prec", [("batched", "fp32"), ("baryon_mix", "fp64")])
+@pytest.mark.parametrize("policy", ["input", "tree"])
+def test_full_configuration_walks_under_their_budgets(name, prec, policy):
+    """The batched (20,301 contractions; input order evicts 2,967 times there)
+    and baryon configurations at full size under their own budgets, waves with
+    lookahead 16: no race, every read finds its tensor."""
+    wl = W.config(name, with_data=False)
+    c = _ctx(wl)
+    c.schedule(policy)
+    c.set_mem_budget(wl.budget_bytes)
+    c.set_options(leaves_resident=False, wave_lookahead=16)
+    p = c.plan(prec, True)
+    t = c.trace_execute(prec, True)
+    c.close()
+    if name == "batched" and policy == "input":
+        assert p["n_evict"] > 0 and p["n_d2h"] > 0
+    assert races_by_segment(t) == 0
+    assert provenance_errors(t) == []
