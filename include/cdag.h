@@ -266,8 +266,10 @@ int cdag_set_timing(cdag_ctx* c, int timing);
 int cdag_trace_execute(cdag_ctx* c, int prec, int batched, cdag_trace_rec* out, int64_t cap, int64_t* n_out,
                        int64_t fail_at);
 
-/* Per-launch records of the last execute made with timing on, in launch order.
- * *n_out (nullable) receives the count; at most cap records are written. */
+/* Records of the last execute made with timing on, in issue order: one per
+ * kernel launch and one per host transfer (a transfer comes before the
+ * kernels of its step).  *n_out (nullable) receives the count; at most cap
+ * records are written. */
 int cdag_launch_records(cdag_ctx* c, cdag_launch_record* out, int64_t cap, int64_t* n_out);
 
 /* Kernel variant of the exterior contractions of `kind` (K22, K32, K33, C1,
