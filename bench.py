@@ -15,8 +15,10 @@ The same line also reports: the budgeted runs (HBM budget = a quarter of the
 input-order schedule's live peak, leaves starting in pinned host memory,
 spills and re-uploads over PCIe) for the input-order, Sibling, Tree and node-gain
 schedules: time-to-solution, H2D/D2H GB, evictions, peak resident bytes; the
-FP32 and split-BF16 modes; per-contraction launches vs waves; the roofline of
-the exterior-contraction kernel; and the CPU oracle on a bounded sample.
+host-transfer rates beside a pinned-copy link reference; the memory of the
+headline run (arena, live peak, H2D per step); the FP32 and split-BF16 modes;
+per-contraction launches vs waves; the roofline of the exterior-contraction
+kernel; and the CPU oracle on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
