@@ -72,7 +72,9 @@ enum cdag_policy { CDAG_SCHED_INPUT = 0, CDAG_SCHED_SIBLING = 1, CDAG_SCHED_TREE
                    CDAG_SCHED_NODE = 3 };
 /* OR into policy for Tree: at every selection recompute every live tree's
  * gain M - M' from scratch and fail with CDAG_E_STATE if an incrementally
- * maintained tgain differs (slow; a self-check). */
+ * maintained tgain differs (slow; a self-check).  For Node: at every pick
+ * recompute the gain of every ready contraction and fail with CDAG_E_STATE if
+ * a cached gain differs or the pick is not the largest. */
 #define CDAG_SCHED_CHECK 0x100
 
 /* Arithmetic of the exterior contractions.  FP64: complex128 storage and

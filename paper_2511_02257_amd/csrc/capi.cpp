@@ -188,7 +188,7 @@ int schedule(cdag_ctx* h, int policy, int64_t* order_out, int64_t cap, int64_t* 
     if (p == CDAG_SCHED_INPUT) o = cdag::sched_input(c.dag);
     else if (p == CDAG_SCHED_SIBLING) o = cdag::sched_sibling(c.dag);
     else if (p == CDAG_SCHED_TREE) o = cdag::sched_tree(c.dag, 16, check);
-    else if (p == CDAG_SCHED_NODE) o = cdag::sched_node(c.dag, 16);
+    else if (p == CDAG_SCHED_NODE) o = cdag::sched_node(c.dag, 16, check);
     else throw cdag::Error(CDAG_E_INVALID, "unknown policy");
     double t = now() - t0;
     if (n_out) *n_out = (int64_t)o.size();

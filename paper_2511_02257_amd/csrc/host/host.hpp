@@ -97,8 +97,10 @@ std::vector<int64_t> sched_sibling(const Dag& d);
 // Error(CDAG_E_STATE) on a mismatch with the incremental tgain.
 std::vector<int64_t> sched_tree(const Dag& d, int elem_bytes, bool check);
 // Node-based gain scheduler: the ready contraction with the largest gain
-// M - M' under the memory model runs next (ties to the lowest id).
-std::vector<int64_t> sched_node(const Dag& d, int elem_bytes);
+// M - M' under the memory model runs next (ties to the lowest id).  check=true
+// recomputes every ready gain at each pick and throws Error(CDAG_E_STATE) if a
+// cached gain is stale or the pick is not the largest.
+std::vector<int64_t> sched_node(const Dag& d, int elem_bytes, bool check);
 
 struct MemSim { std::vector<int64_t> M; int64_t peak_post = 0, peak_live = 0; };
 MemSim memsim(const Dag& d, const std::vector<int64_t>& order, int elem_bytes);

@@ -354,7 +354,7 @@ std::vector<int64_t> sched_tree(const Dag& d, int elem_bytes, bool check) {
 // released by that parent.  Those gains are recomputed and pushed again (each
 // leaf's parents are scanned once, each child's once when one parent is left,
 // so O(E) scans in all); stale heap entries are skipped.
-std::vector<int64_t> sched_node(const Dag& d, int elem_bytes) {
+std::vector<int64_t> sched_node(const Dag& d, int elem_bytes, bool check) {
   const int64_t n = d.n_nodes();
   std::vector<int64_t> pending(n), waiting(n, 0), gain(n, 0);
   std::vector<char> resident(n, 0), done(n, 0);
@@ -382,6 +382,13 @@ std::vector<int64_t> sched_node(const Dag& d, int elem_bytes) {
     const int64_t g = pq.top().first, v = -pq.top().second;
     pq.pop();
     if (done[v] || g != gain[v]) continue;
+    if (check)   // every ready gain current, and v the largest (lowest id on ties)
+      for (int64_t q = d.n_leaves; q < n; ++q) {
+        if (done[q] || waiting[q] != 0) continue;
+        const int64_t e = eval(q);
+        if (e != gain[q]) throw Error(CDAG_E_STATE, "node scheduler: a stale gain at node " + std::to_string(q));
+        if (e > g || (e == g && q < v)) throw Error(CDAG_E_STATE, "node scheduler: a better node was passed over");
+      }
     done[v] = 1;
     order.push_back(v);
     auto refresh = [&](int64_t q) {

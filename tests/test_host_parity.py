@@ -115,7 +115,7 @@ def test_schedules_and_plans_match_oracle(i):
     assert [int(k) for k in kind[d.n_leaves:]] == d.kind[d.n_leaves:]
     assert list(c.graph_roots()) == d.root_of_graph
     for policy in ("input", "sibling", "tree", "node"):
-        order = [int(x) for x in c.schedule(policy, check=(policy == "tree"))]
+        order = [int(x) for x in c.schedule(policy, check=(policy in ("tree", "node")))]
         assert order == OS.schedule(d, policy), policy
         for eb in (16, 8):
             M, pp, pl = c.memsim(order, eb)
@@ -163,7 +163,7 @@ def test_corr_func_shaped_dags_match_oracle(row):
     assert (st["n_vertices"], st["n_edges"], st["n_trees"]) == (ref["n_nodes"], ref["n_edges"], ref["n_trees"])
     assert abs(st["f_v"] - ref["f_v"]) < 1e-12 and abs(st["f_e"] - ref["f_e"]) < 1e-12
     for policy in ("input", "sibling", "tree"):
-        order = [int(x) for x in c.schedule(policy, check=(policy == "tree"))]
+        order = [int(x) for x in c.schedule(policy, check=(policy in ("tree", "node")))]
         assert order == OS.schedule(d, policy), policy
         M, pp, pl = c.memsim(order, 16)
         sim = OS.memsim(d, order, 16)
@@ -389,7 +389,7 @@ def test_general_dag_matches_oracle(seed, case):
     c = X.Context()
     c.build_general(nl, sizes, kids)
     for pol in ("input", "tree", "node"):
-        got = list(c.schedule(pol, check=(pol == "tree")))
+        got = list(c.schedule(pol, check=(pol in ("tree", "node"))))
         ref = OS.schedule(d, pol)
         assert got == ref, pol
         M, post, live = c.memsim(got)
@@ -551,3 +551,20 @@ def test_header_is_plain_c99(tmp_path):
                         "-I", os.path.dirname(HEADER), "-c", str(src), "-o", str(tmp_path / "use.o")],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
+
+
+@pytest.mark.parametrize("which", ["meson_ring", "baryon_mix", "a0-d3", "tritium", "general"])
+def test_node_scheduler_self_check_at_full_size(which):
+    """Where the oracle is too slow (quadratic in the DAG), the library's own
+    check mode verifies every pick of the node scheduler: each ready gain
+    recomputed equals the cached one, and the pick is the largest."""
+    c = X.Context()
+    if which == "general":
+        from synth.general import random_general
+        nl, sizes, kids = random_general(7, n_leaves=200, n_trees=4000, max_arity=4, depth=3, share=0.05)
+        c.build_general(nl, sizes, kids)
+    else:
+        wl = CF.corr_func_like(which) if which in CF.TABLE else W.config(which, with_data=False)
+        c.build_cdag(wl.leaves, wl.graphs)
+    assert list(c.schedule("node", check=True)) == list(c.schedule("node"))
+    c.close()
