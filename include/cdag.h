@@ -141,6 +141,11 @@ typedef struct {
   int64_t n_launches;
   int64_t n_hec_launches;
   int64_t n_graph_segments;
+  double t_kernels_s;     /* summed duration of every kernel launch (timing on; else 0) */
+  double t_copy_s;        /* summed duration of the host transfers on the copy stream
+                             (timing on; else 0)                                    */
+  int64_t arena_highwater; /* arena bytes the plan uses: leaf region, tensor pool
+                              high-water, split-K workspace, descriptors, results   */
 } cdag_exec_stats;
 
 /* One kernel launch, or one host transfer, of a timed execute
@@ -183,13 +188,26 @@ typedef struct {
   int64_t bytes;    /* READ, WRITE: bytes                                                */
 } cdag_trace_rec;
 
+/* Context lifetime: cdag_create stores a new, empty context in *out (owned by
+ * the caller until cdag_destroy, which also releases the library's pinned
+ * staging, spill pool, events and captured graphs; destroying NULL is a no-op).
+ * CDAG_E_INVALID for a NULL out. */
 int cdag_create(cdag_ctx** out);
 int cdag_destroy(cdag_ctx* c);
+/* Text of the last failure on the calling thread (empty after a success);
+ * owned by the library, valid until the thread's next call. */
 const char* cdag_last_error(void);
 
-/* Merge graphs into the DAG (hash-consing identical (kind, left, right)
+/* build_cdag -- Sec. II-B ("Notation"): the correlation function's graphs,
+ * each a binary contraction tree over hadron-node tensors, are merged into one
+ * contraction DAG whose vertices are tensors and whose edges join a
+ * contraction's output to its operands; structurally identical sub-trees
+ * become one vertex, so common intermediates are computed once.
+ * Merge graphs into the DAG (hash-consing identical (kind, left, right)
  * contractions; identical graphs share their root).  Node ids: leaves
  * 0..n_leaves-1, then contractions in order of first appearance.
+ * leaves[0..n_leaves) and graphs[0..n_graphs) are caller-owned and read during
+ * the call only (each leaf's host data is copied).
  * CDAG_E_INVALID: bad shape, rank (operands and outputs 2..4; HCA on two
  * rank-2 operands), N or Nt mismatch, a GEMM dimension (N^(free or
  * contracted axes)) above 2^31, operand out of range or forward, identical
@@ -218,8 +236,18 @@ int build_cdag(cdag_ctx* c, const cdag_leaf* leaves, int64_t n_leaves,
 int cdag_build_general(cdag_ctx* c, int64_t n_nodes, int64_t n_leaves, const int64_t* size_bytes,
                        const int64_t* child_off, const int64_t* child);
 
-/* Order the contractions.  order_out (nullable, capacity cap) receives node
- * ids; *n_out (nullable) the number of contractions. */
+/* schedule -- Sec. III ("Scheduling heuristics"): a total order of the
+ * contractions that respects the DAG (children before parents) and keeps the
+ * Sec. II-C peak memory low.  policy: CDAG_SCHED_INPUT (each graph in turn,
+ * post-order), CDAG_SCHED_SIBLING (Sec. III-A, Algs. 1-3 with the rank of
+ * Eq. (1)), CDAG_SCHED_TREE (Sec. III-B, Algs. 4-8: the tree with the largest
+ * gain M - M' next), CDAG_SCHED_NODE (the node-based gain scheduler named in
+ * Sec. VI); OR CDAG_SCHED_CHECK for the self-check.  order_out (nullable,
+ * caller-owned, capacity cap) receives node ids; *n_out (nullable) the number
+ * of contractions.  CDAG_E_RANGE if cap is too small for a non-NULL
+ * order_out; CDAG_E_INVALID for an unknown policy or Sibling on a node
+ * without two children; CDAG_E_STATE before a DAG is built.  The order stays
+ * in force for cdag_plan and execute. */
 int schedule(cdag_ctx* c, int policy, int64_t* order_out, int64_t cap, int64_t* n_out);
 
 /* Install a contraction order found earlier (a saved schedule) instead of
@@ -232,8 +260,15 @@ int schedule(cdag_ctx* c, int policy, int64_t* order_out, int64_t cap, int64_t* 
  * CDAG_E_STATE: no DAG built. */
 int cdag_set_order(cdag_ctx* c, const int64_t* order, int64_t n);
 
-/* Device-memory budget in bytes for planning (UINT64_MAX: unlimited, the
- * default). */
+/* set_mem_budget -- Sec. II-C ("Problem definition"): the device memory the
+ * execution may hold at once.  Memory is charged as in Sec. II-C (a leaf from
+ * its first use, an intermediate from its production until its last parent
+ * has run; a root's scalar output costs nothing); when the schedule's live
+ * bytes exceed the budget, the plan evicts (next use furthest away; an
+ * intermediate is copied to host memory once) and uploads again, the data
+ * movement Sec. IV-C counts.  bytes: the budget (UINT64_MAX: unlimited, the
+ * default).  CDAG_E_STATE before a DAG is built.  A budget that one step cannot
+ * fit in is reported by cdag_plan / execute with CDAG_E_BUDGET. */
 int set_mem_budget(cdag_ctx* c, uint64_t bytes);
 
 /* leaves_resident: 1 keeps every leaf in a device region of its own, outside
@@ -332,9 +367,19 @@ int cdag_dag_stats(cdag_ctx* c, int64_t* n_vertices, int64_t* n_edges, int64_t* 
 int cdag_bind_device(cdag_ctx* c, int device, void* compute_stream, void* copy_stream);
 int cdag_bind_arena(cdag_ctx* c, void* dev_arena, uint64_t bytes);
 
-/* Plan (as cdag_plan) and run the whole DAG: uploads, evictions, exterior
+/* execute -- Sec. II-C and Sec. IV-B/IV-C: evaluate every graph of the DAG
+ * in the scheduled order under the memory budget, as the paper's runtime does
+ * with its queue of exterior contractions, contract-all operations on roots,
+ * deletions, and evictions with host re-uploads (Sec. II-A, GPU memory
+ * management).
+ * Plan (as cdag_plan) and run the whole DAG: uploads, evictions, exterior
  * contractions, traces, the cross-diagram sums and the copy of the results
- * to the host.  Blocks until the results are on the host.  Spilled
+ * to the host.  Blocks until the results are on the host.  prec: cdag_prec;
+ * batched: 0 one contraction per step, 1 waves of ready contractions
+ * (cdag_set_options).  out (nullable, caller-owned) receives the statistics.
+ * CDAG_E_STATE without schedule, bound device and arena, or leaf data;
+ * CDAG_E_NOMEM if the arena is smaller than plan.arena_bytes; CDAG_E_BUDGET as
+ * cdag_plan; CDAG_E_HIP if a HIP call fails (the context stays usable).  Spilled
  * intermediates go to a pinned host pool of plan.host_spill_bytes; when a
  * pinned allocation of that size fails the pool is pageable memory and the
  * steps run eagerly (no captured segments).  CDAG_E_NOMEM if neither can be
@@ -358,8 +403,14 @@ int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
  * and results. */
 int cdag_autotune(cdag_ctx* c, int prec, int batched, int reps, int mode, int64_t* n_tuned);
 
-/* Per input graph g, C_g(t) for t < nt(g), as (re, im) doubles, graphs in
- * input order, concatenated: 2 * sum_g nt(g) doubles. */
+/* fetch_correlators -- Sec. I and Sec. II-B: the value of each graph, the
+ * full contraction of its tree per time slice (the terms whose sum is the
+ * correlation function).
+ * Per input graph g, C_g(t) for t < nt(g), as (re, im) doubles, graphs in
+ * input order, concatenated: 2 * sum_g nt(g) doubles into the caller-owned
+ * out of capacity cap_doubles.  Graphs merged into one root get equal rows.
+ * CDAG_E_STATE before a successful execute; CDAG_E_RANGE if cap_doubles is
+ * too small. */
 int fetch_correlators(cdag_ctx* c, double* out, int64_t cap_doubles);
 
 /* Per correlator c = 0..max(corr_id), S_c(t) = sum_{g: corr_id = c} w_g C_g(t)

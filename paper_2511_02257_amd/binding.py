@@ -58,7 +58,8 @@ class cdag_exec_stats(C.Structure):
     _fields_ = [("plan", cdag_plan_stats), ("t_total_s", C.c_double), ("t_device_s", C.c_double),
                 ("t_hec_s", C.c_double), ("hec_flops", C.c_double), ("hec_bytes", C.c_double),
                 ("n_launches", C.c_int64), ("n_hec_launches", C.c_int64),
-                ("n_graph_segments", C.c_int64)]
+                ("n_graph_segments", C.c_int64), ("t_kernels_s", C.c_double), ("t_copy_s", C.c_double),
+                ("arena_highwater", C.c_int64)]
 
 
 class cdag_launch_record(C.Structure):

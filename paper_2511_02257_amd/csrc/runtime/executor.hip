@@ -686,7 +686,7 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   c.corr_host.assign((const double*)D.results, (const double*)D.results + kp.corr_bytes / 8);
   c.sums_host.assign((const double*)((const char*)D.results + kp.corr_bytes),
                      (const double*)((const char*)D.results + kp.corr_bytes) + kp.sums_bytes / 8);
-  double t_hec = 0;
+  double t_hec = 0, t_kern = 0, t_copy = 0;
   if (timed) {
     c.records.clear();
     for (const Device::TPair& pr : D.tpairs) {
@@ -701,8 +701,10 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
         r.n_items = 1;
         r.bytes = pr.bytes;
         c.records.push_back(r);
+        t_copy += x * 1e-3;
         continue;
       }
+      t_kern += x * 1e-3;
       const Launch& L = pr.launch >= 0 ? kp.launches[pr.launch] : kp.xsum;
       r.type = L.type;
       r.variant = L.type == L_HEC ? L.tile : 0;
@@ -717,6 +719,9 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   int64_t n_hec = 0;
   for (const Launch& L : kp.launches) n_hec += L.type == L_HEC;
   st->t_hec_s = t_hec;
+  st->t_kernels_s = t_kern;
+  st->t_copy_s = t_copy;
+  st->arena_highwater = kp.total_bytes;
   st->hec_flops = kp.hec_flops;
   st->hec_bytes = kp.hec_bytes;
   st->n_hec_launches = n_hec;

@@ -167,3 +167,26 @@ def test_cross_sum_correctly_rounded():
     rng = np.random.default_rng(0)
     ints = rng.integers(-1000, 1000, size=100)
     assert math.fsum(float(i) for i in ints) == float(ints.sum())
+
+
+def test_cross_sum_scale_by_hand():
+    """sum_g |w_g C_g(t)|, the denominator of every cross-sum error bound, on
+    values worked by hand: |3+4i| = 5, |2i (1+i)| = 2 sqrt 2, and a weight of
+    -1 must count positively (a dropped abs or weight changes every entry)."""
+    class G:
+        def __init__(self, corr, w):
+            self.corr, self.w, self.ops = corr, w, []
+
+    class Wl:
+        graphs = [G(0, 3 + 4j), G(0, -1.0), G(1, 2j), G(1, 0.5)]
+
+    vals = {0: np.array([1 + 0j, 2j]), 1: np.array([3 - 4j, 0j]),
+            2: np.array([1 + 1j, -1 + 0j]), 3: np.array([0j, -6 + 8j])}
+    sc = V.cross_sum_scale(Wl, vals)
+    assert set(sc) == {0, 1}
+    assert np.allclose(sc[0], [5 + 5, 10 + 0], rtol=0, atol=1e-15)
+    assert np.allclose(sc[1], [2 * math.sqrt(2) + 0, 2 + 5], rtol=0, atol=1e-15)
+    # the scale bounds the sum it normalises: |S_c(t)| <= scale_c(t)
+    s = V.cross_sums(Wl, vals)
+    for c in sc:
+        assert np.all(np.abs(s[c]) <= sc[c] * (1 + 1e-15))
