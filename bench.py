@@ -1,26 +1,32 @@
 """Benchmark: contraction-DAG execution on one MI355X.
 
-Workload (the memory-bound meson configuration): 16 meson leaves, complex128
-[Nt=32][64][64], entries N(0,1)/8; 2000 seeded ring traces of 4..8 distinct
-leaves contracted as random binary trees, common sub-products merged.
+Headline workload (the baryon configuration as stated): 12 baryon leaves
+complex128 [Nt=32][64][64][64] and 12 meson leaves [32][64][64], entries
+N(0,1)/64; 500 seeded chains X = K32(B_a, M_b), Y = K33(X, B_c),
+C(t) = tr(Y M_d) merged into one DAG (139 K32, 440 K33, 500 traces); FP64;
+HBM budget 32e9 bytes; Tree schedule; the leaves start in pinned host memory.
 
-One step = one execute() of the whole scheduled DAG: every exterior
-contraction (grouped per wave), every root trace, the FP64 cross-diagram sums
-and the copy of all correlators to the host.  The DAG is built, scheduled
-(Tree) and planned once; the schedule is reused by every step, as the paper
-reuses a schedule across runs.  `value` is algorithmic complex TFLOP/s (8 flops
-per complex multiply-add) with the leaves already resident in HBM.
+One step = one execute() of the whole DAG with every leaf upload inside it:
+uploads, exterior contractions, root traces, the FP64 cross-diagram sums and
+the copy of every correlator to the host.  The execute runs in passes over
+slices of the time axis (uploads of one pass overlap the contractions of the
+previous one) and picks its issue mode (eager on three streams, or one graph
+over them) by a short trial.  `value` is the algorithmic complex TFLOP/s of the
+time-to-solution (8 flops per complex multiply-add; DAG-shared work counted
+once).
 
-The same line also reports: the budgeted runs (HBM budget = a quarter of the
-input-order schedule's live peak, leaves starting in pinned host memory,
-spills and re-uploads over PCIe) for the input-order, Sibling, Tree and node-gain
-schedules: time-to-solution, H2D/D2H GB, evictions, peak resident bytes; the
-host-transfer rates beside a pinned-copy link reference; the memory of the
-headline run (arena, live peak, H2D per step); the FP32 and split-BF16 modes;
-per-contraction launches vs waves; the roofline of the exterior-contraction
-kernel; and the CPU oracle on a bounded sample.
+The same JSON line also carries: the same DAG with every leaf resident (the
+kernel-only reference) and in one pass (whole tensors, the paper's memory
+model); its precision form (complex FP32, split-BF16 with two and with three
+pieces) with each correlator's error against the FP64 oracle on the sample the
+CPU baseline evaluates; the memory-bound meson configuration under a quarter of
+the input-order live peak (input order vs Tree, issue modes, host-transfer
+rates beside a pinned-copy link reference); the batched configuration under
+64e9 bytes (waves vs one launch per contraction); the roofline of the dominant
+kernel (FP64 K33); and the CPU oracle on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --only headline|precision|meson|batched   (one part)
 """
 from __future__ import annotations
 
@@ -36,15 +42,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "CDAG time-to-solution, complex TFLOP/s, H2D GB, peak HBM (FP64 vs mixed)"
-PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0}   # TFLOP/s per algorithmic flop
+# Peaks per algorithmic flop (8 per complex multiply-add): FP64 and FP32
+# matrix cores; split-BF16 runs 3 (two pieces) or 6 (three pieces) bf16
+# products per real product on the 2.5 PFLOP/s dense BF16 matrix cores.
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0, "bf16x6": 2500.0 / 6.0}
 HBM_PEAK = 8000.0   # GB/s
+KIND_NAMES = {0: "K22", 1: "K32", 2: "K33", 3: "HCA", 4: "C1", 5: "C2", 6: "C3"}
+GAUSS_TILES = {1, 4, 5}   # FP64/FP32 tiles forming a complex product from three real ones
+ALL = (1 << 63) - 1
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def timed_steps(ctx, runner, prec, batched, steps, warmup):
+def timed_steps(runner, prec, batched, steps, warmup):
     for _ in range(warmup):
         runner.run(prec, batched)
     torch = runner.torch
@@ -54,51 +66,35 @@ def timed_steps(ctx, runner, prec, batched, steps, warmup):
     for _ in range(steps):
         st = runner.run(prec, batched)
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return dt, st
-
-
-def measured_traffic(variant):
-    """HBM bytes per launch of the exterior-contraction kernel from the committed
-    counter summary, or None when the kernel source or variant differs from the
-    one the counters were taken on."""
-    path = os.path.join(ROOT, "profiles", "hec_traffic_meson_ring.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    from paper_2511_02257_amd.profiling import kernel_source_sha256
-    if rec.get("kernel_sha256") != kernel_source_sha256():
-        return None
-    entry = rec.get("variants", {}).get(str(variant))
-    return None if entry is None else entry.get("traffic_bytes_per_launch")
-
-
-KIND_NAMES = {0: "K22", 1: "K32", 2: "K33", 3: "HCA", 4: "C1", 5: "C2", 6: "C3"}
+    return time.perf_counter() - t0, st
 
 
 def kernel_table(records, prec):
     """Launch records of one timed execute, summed per (launch type, kinds):
     time, algorithmic flops and bytes, and the rates against the MI355X peaks.
-    A split-K contraction kind also gets an entry that charges its reduction
-    kernels to it ("hec+reduce")."""
+    frac_mfma counts algorithmic flops; frac_pipe the flops the matrix cores
+    execute (three real products per complex one in the Gauss tiles: 3/4 of
+    the algorithmic count).  A split-K contraction kind also gets an entry
+    that charges its reduction kernels to it ("hec+reduce")."""
     agg = {}
     for r in records:
         if r["type"] in ("h2d", "d2h"):
             continue
         key = r["type"] if r["type"] == "xsum" else r["type"] + ":" + "+".join(KIND_NAMES[k] for k in r["kinds"])
-        a = agg.setdefault(key, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0})
+        a = agg.setdefault(key, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0, "pipe_flops": 0.0})
         a["launches"] += 1
         a["ms"] += r["ms"]
         a["flops"] += r["flops"]
         a["bytes"] += r["bytes"]
+        gauss = r["type"] == "hec" and prec in ("fp64", "fp32") and r["variant"] % 6 in GAUSS_TILES
+        a["pipe_flops"] += r["flops"] * (0.75 if gauss else 1.0)
     for key in [k for k in agg if k.startswith("reduce:")]:
         hk = "hec:" + key.split(":", 1)[1]
         if hk in agg:
             agg["hec+reduce:" + key.split(":", 1)[1]] = {
                 "launches": agg[hk]["launches"] + agg[key]["launches"],
                 "ms": agg[hk]["ms"] + agg[key]["ms"], "flops": agg[hk]["flops"],
-                "bytes": agg[hk]["bytes"]}
+                "bytes": agg[hk]["bytes"], "pipe_flops": agg[hk]["pipe_flops"]}
     for key, a in agg.items():
         sec = a["ms"] * 1e-3
         if sec <= 0:
@@ -107,9 +103,11 @@ def kernel_table(records, prec):
         a["GB/s"] = round(a["bytes"] / sec / 1e9, 1)
         if key.startswith("hec"):
             a["frac_mfma"] = round(a["flops"] / sec / 1e12 / PEAK[prec], 4)
+            a["frac_pipe"] = round(a["pipe_flops"] / sec / 1e12 / PEAK[prec], 4)
         if not key.startswith("reduce"):
             a["frac_hbm"] = round(a["bytes"] / sec / 1e9 / HBM_PEAK, 4)
         a["ms"] = round(a["ms"], 4)
+        del a["pipe_flops"]
     return agg
 
 
@@ -137,138 +135,284 @@ def link_reference(torch, sizes=(2 << 20, 8 << 20, 1 << 30), total=4 << 30):
 
 def transfer_rates(records, tts_s):
     """Per direction: transfers, bytes and summed copy time of one timed
-    execute, the achieved rate while copying, and the copy stream's busy
-    share of the time-to-solution."""
+    execute, the achieved rate while copying, and each stream's busy share of
+    the time-to-solution."""
     out = {}
     for kind in ("h2d", "d2h"):
         rs = [r for r in records if r["type"] == kind]
         ms = sum(r["ms"] for r in rs)
         nbytes = sum(r["bytes"] for r in rs)
         out[kind] = {"n": len(rs), "GB": round(nbytes / 1e9, 4), "copy_ms": round(ms, 3),
-                     "GBps": round(nbytes / (ms * 1e-3) / 1e9, 2) if ms > 0 else None}
-    busy = sum(out[k]["copy_ms"] for k in out)
-    out["copy_busy_frac_of_tts"] = round(busy * 1e-3 / tts_s, 3) if tts_s else None
+                     "GBps": round(nbytes / (ms * 1e-3) / 1e9, 2) if ms > 0 else None,
+                     "busy_frac_of_tts": round(ms * 1e-3 / tts_s, 3) if tts_s else None}
     return out
 
 
-def transfer_study(ctx, runner, budget, reps=1, link=True):
-    """The host-transfer step on its own: per-copy events on the copy stream in
-    timed (eager) executes of the budgeted FP64 Tree order with lookahead 16,
-    beside the pinned-copy link reference.  An event pair around a copy that
-    waits for the compute stream can include part of that wait."""
-    ctx.set_mem_budget(budget)
-    ctx.schedule("tree")
-    ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=False)
-    ctx.set_timing(True)
-    runner.run("fp64", True)                     # plans and warms up
-    runner.torch.cuda.synchronize()
-    runs = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        runner.run("fp64", True)
-        runner.torch.cuda.synchronize()
-        runs.append(transfer_rates(ctx.launch_records(), time.perf_counter() - t0))
-    ctx.set_timing(False)
-    out = {"fp64_tree_lookahead16": runs[-1]}
-    if link:
-        out["link_reference"] = link_reference(runner.torch)
-    log("transfers", out)
-    return out
+def plan_summary(p):
+    return {"h2d_GB": round(p["h2d_bytes"] / 1e9, 4), "d2h_GB": round(p["d2h_bytes"] / 1e9, 4),
+            "n_evict": p["n_evict"], "n_h2d": p["n_h2d"], "n_d2h": p["n_d2h"],
+            "peak_resident_GB": round(p["peak_resident"] / 1e9, 4),
+            "arena_GB": round(p["arena_bytes"] / 1e9, 4), "budget_GB": round(p["budget"] / 1e9, 4)
+            if p["budget"] < (1 << 62) else None, "n_steps": p["n_steps"]}
 
 
-def budgeted_schedules(ctx, runner, prec, budget, X):
-    """Time-to-solution under the configuration's HBM budget with the leaves
-    starting in pinned host memory (every transfer inside the time): input
-    order, Sibling, Tree and node gain cut into waves with lookahead 16 and replayed from
-    captured segments, Tree without lookahead, and Tree with one eager launch
-    per contraction.  One warm-up and one timed execute each.  Every run's
-    correlators are compared bit for bit with those of the resident run that
-    precedes this call."""
-    import numpy as np
-    ref = np.concatenate(ctx.fetch_correlators()).view(np.uint64)
-    out = {}
-    ctx.set_mem_budget(budget)
-    for policy, look, batched in (("input", 16, True), ("sibling", 16, True), ("tree", 16, True),
-                                  ("node", 16, True), ("tree", 0, True), ("tree", 16, False)):
-        ctx.schedule(policy)
-        ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=batched)
-        key = policy + (f"_lookahead{look}" if look and batched else "") + ("" if batched else "_per_contraction")
-        try:
-            dt, st = timed_steps(ctx, runner, prec, batched, 1, 1)
-            p = st["plan"]
-            same = bool(np.array_equal(np.concatenate(ctx.fetch_correlators()).view(np.uint64), ref))
-            timing = {"tts_s": round(dt, 4), "tflops": round(p["flops"] / dt / 1e12, 3),
-                      "bits_equal_resident": same}
-        except X.CdagError as e:
-            # e.g. pinned host memory for the spilled intermediates not available:
-            # the plan's counts are still exact, the time is not measured
-            p = ctx.plan(prec, batched)
-            timing = {"tts_s": None, "error": str(e)[:160],
-                      "host_spill_GB": round(p["host_spill_bytes"] / 1e9, 3)}
-        out[key] = {**timing,
-                    "h2d_GB": round(p["h2d_bytes"] / 1e9, 3), "d2h_GB": round(p["d2h_bytes"] / 1e9, 3),
-                    "n_evict": p["n_evict"], "peak_resident_GB": round(p["peak_resident"] / 1e9, 3),
-                    "peak_post_GB": round(p["peak_post"] / 1e9, 3), "n_steps": p["n_steps"],
-                    "budget_GB": round(budget / 1e9, 3)}
-        log(prec, key, out[key])
-    ctx.set_mem_budget(None)
-    ctx.schedule("tree")
-    ctx.set_options(leaves_resident=True, wave_lookahead=X.binding.LOOKAHEAD_ALL, use_graphs=True)
-    return out
+def best_mode(runner, ctx, prec, batched, modes=(0, 2), reps=2, **opts):
+    """Issue mode by trial: one warm-up and `reps` timed executes per mode;
+    returns (mode, {mode: seconds per execute})."""
+    times = {}
+    for m in modes:
+        ctx.set_options(use_graphs=m, **opts)
+        dt, _ = timed_steps(runner, prec, batched, reps, 1)
+        times[m] = dt / reps
+    m = min(times, key=times.get)
+    ctx.set_options(use_graphs=m, **opts)
+    return m, times
 
 
-def workload_rooflines(name, precs, steps, X, W, DeviceRunner, in_situ=True, fixed=None, budgeted=False):
-    """One config at its full size, Tree schedule, waves of every ready
-    contraction, leaves resident, graph replay: autotuned variants, time per
-    execute, and per-kernel rates from a timed execute.  budgeted: also the
-    schedules under the configuration's HBM budget (budgeted_schedules)."""
-    import torch
-    wl = W.config(name)
+def sample_bits(ctx, sample):
+    corr = ctx.fetch_correlators()
+    return {g: corr[g].copy() for g in sample}
+
+
+# ---------------------------------------------------------------- headline
+def headline(args, X, W, DeviceRunner, sample):
+    """The baryon configuration as stated, FP64, plus its references: every
+    leaf resident (kernel time), one pass (whole tensors), the precision
+    forms.  Returns (line fields, extras, correlators of the sample per
+    precision)."""
+    torch = __import__("torch")
+    wl = W.config("baryon_mix")
     budget = wl.budget_bytes
-    log(f"{name}: workload built")
-    shapes = set()
-    for g in wl.graphs:
-        n = next(wl.leaves[o].nvec for op in g.ops for o in op[1:] if o >= 0)
-        shapes.update((kind, n) for kind, _, _ in g.ops if kind != 3)
-    shapes = sorted(shapes)
     ctx = X.Context()
     ctx.build_cdag(wl.leaves, wl.graphs)
     del wl
+    t0 = time.perf_counter()
     ctx.schedule("tree")
-    ctx.set_mem_budget(None)
-    ctx.set_options(leaves_resident=True, wave_lookahead=X.binding.LOOKAHEAD_ALL, use_graphs=True)
+    t_sched = time.perf_counter() - t0
     runner = DeviceRunner(ctx, 0)
-    res = {}
-    inv = {v: k for k, v in KIND_NAMES.items()}
-    for prec in precs:
-        if fixed and prec in fixed:
-            for key, choice in fixed[prec].items():
+    ctx.set_mem_budget(budget)
+    ctx.set_time_chunks(args.chunks)
+    opts = dict(leaves_resident=False, wave_lookahead=ALL)
+    ctx.set_options(use_graphs=0, **opts)
+    tiles = {}
+    if args.tiles_from:
+        with open(args.tiles_from) as f:
+            prev = json.loads(f.read().strip().splitlines()[-1])
+        tiles = prev["config"]["kernel_choices"]
+        for prec, table in tiles.items():
+            for key, choice in table.items():
                 kname, n = key.split("_N")
-                ctx.set_tile(prec, inv[kname], int(n), *choice)
-            runner.ensure_arena(ctx.plan(prec, True)["arena_bytes"])
-        else:
-            runner.autotune(prec, True, reps=2 if in_situ else 1, in_situ=in_situ)
-        dt, st = timed_steps(ctx, runner, prec, True, steps, 1)
-        p = st["plan"]
-        ctx.set_timing(True)
-        runner.run(prec, True)
-        recs = ctx.launch_records()
-        ctx.set_timing(False)
-        res[prec] = {
-            "tflops": round(p["flops"] * steps / dt / 1e12, 3),
-            "ms_per_step": round(dt / steps * 1e3, 3), "n_waves": p["n_steps"],
-            "n_contractions": p["n_contr"], "flops_per_step": p["flops"],
-            "arena_GB": round(p["arena_bytes"] / 1e9, 2),
-            "variants": {f"{KIND_NAMES[k]}_N{n}": list(ctx.get_tile(prec, k, n)) for k, n in shapes},
-            "kernels": kernel_table(recs, prec)}
-        if budgeted and budget:
-            res[prec]["budgeted"] = budgeted_schedules(ctx, runner, prec, budget, X)
-        log(name, prec, res[prec])
+                ctx.set_tile(prec, {v: k for k, v in KIND_NAMES.items()}[kname], int(n), *choice)
+        runner.ensure_arena(ctx.plan("fp64", True)["arena_bytes"])
+    else:
+        runner.autotune("fp64", True, reps=2, in_situ=True)
+        tiles["fp64"] = {f"{KIND_NAMES[k]}_N64": list(ctx.get_tile("fp64", k, 64)) for k in (1, 2)}
+    log("fp64 kernel choices", tiles["fp64"])
+    mode, mode_times = best_mode(runner, ctx, "fp64", True, **opts)
+    dt, st = timed_steps(runner, "fp64", True, args.steps, args.warmup)
+    p = st["plan"]
+    corr = {"fp64": sample_bits(ctx, sample)}
+    tts = dt / args.steps
+    value = p["flops"] / tts / 1e12
+    log(f"headline: {tts * 1e3:.2f} ms/step, {value:.2f} TFLOP/s, mode {mode} {mode_times}")
+    fields = {
+        "value": round(value, 4), "ms_per_step": round(tts * 1e3, 4),
+        "config": {
+            "workload": "baryon_mix as stated: 12 baryons complex128 [32][64][64][64] + 12 mesons "
+                        "[32][64][64], N(0,1)/64, 500 chains K32 -> K33 -> trace merged "
+                        f"({p['n_contr']} nodes), HBM budget 32e9 B, leaves start in pinned host "
+                        "memory (every upload timed), Tree schedule",
+            "schedule": "tree", "t_schedule_s": round(t_sched, 4), "precision": "fp64",
+            "time_slice_passes": args.chunks, "wave_lookahead": "all ready",
+            "issue_mode": X.binding.GRAPH_MODES[mode],
+            "issue_mode_trial_ms": {X.binding.GRAPH_MODES[m]: round(t * 1e3, 3) for m, t in mode_times.items()},
+            "flops_per_step": p["flops"], **plan_summary(p), "kernel_choices": tiles},
+    }
+    # roofline of the dominant kernel: FP64 K33 launches, HIP events per launch
+    ctx.set_options(use_graphs=0, **opts)
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    runner.run("fp64", True)
+    torch.cuda.synchronize()
+    t_timed = time.perf_counter() - t0
+    recs = ctx.launch_records()
+    ctx.set_timing(False)
+    k33 = [r for r in recs if r["type"] == "hec" and r["kinds"] == [2]]
+    ms = sum(r["ms"] for r in k33) / len(k33)
+    fl = sum(r["flops"] for r in k33) / len(k33)
+    by = sum(r["bytes"] for r in k33) / len(k33)
+    variant = k33[0]["variant"]
+    gauss = variant % 6 in GAUSS_TILES
+    achieved = fl / (ms * 1e-3) / 1e12
+    fields["roofline"] = {
+        "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK["fp64"], 4),
+        "traffic": measured_traffic("baryon_mix", variant),
+        "kernel": "hec_mfma<double> (grouped K33 launches of the headline execute)",
+        "variant": variant, "launches_per_step": len(k33), "avg_launch_us": round(ms * 1e3, 3),
+        "flops_per_launch": fl, "alg_bytes_per_launch": by,
+        "achieved_GBps": round(by / (ms * 1e-3) / 1e9, 1),
+        "executed_flops_per_launch": fl * (0.75 if gauss else 1.0),
+        "frac_pipe": round(achieved * (0.75 if gauss else 1.0) / PEAK["fp64"], 4),
+        "all_kernels_timed_execute": kernel_table(recs, "fp64"),
+        "transfers_timed_execute": transfer_rates(recs, t_timed)}
+    extras = {}
+    # references on the same DAG: one pass (whole tensors), and every leaf resident
+    for name, chunks, resident in (("one_pass", 1, False), ("resident", 1, True)):
+        ctx.set_time_chunks(chunks)
+        o = dict(leaves_resident=resident, wave_lookahead=ALL)
+        m, mt = best_mode(runner, ctx, "fp64", True, modes=(0, 2) if not resident else (1,), **o)
+        d2, s2 = timed_steps(runner, "fp64", True, max(3, args.steps // 4), 1)
+        extras[f"fp64_{name}"] = {"ms_per_step": round(d2 / max(3, args.steps // 4) * 1e3, 3),
+                                  "issue_mode": X.binding.GRAPH_MODES[m], **plan_summary(s2["plan"])}
+        log(name, extras[f"fp64_{name}"])
+    res_ms = extras["fp64_resident"]["ms_per_step"]
+    h2d_floor_ms = p["h2d_bytes"] / 1e9 / args.link_GBps * 1e3
+    extras["fp64_overlap"] = {
+        "tts_over_max_kernel_or_link": round(tts * 1e3 / max(res_ms, h2d_floor_ms), 3),
+        "resident_ms": res_ms, "h2d_floor_ms": round(h2d_floor_ms, 3), "link_GBps_assumed": args.link_GBps}
+    # the precision form: same DAG, budget and passes, complex64 storage
+    ctx.set_time_chunks(args.chunks)
+    for prec in ("fp32", "bf16x3", "bf16x6"):
+        if prec not in tiles:
+            ctx.set_options(use_graphs=0, **opts)
+            runner.autotune(prec, True, reps=1, in_situ=True)
+            tiles[prec] = {f"{KIND_NAMES[k]}_N64": list(ctx.get_tile(prec, k, 64)) for k in (1, 2)}
+        m, mt = best_mode(runner, ctx, prec, True, **opts)
+        n = max(3, args.steps // 2)
+        d2, s2 = timed_steps(runner, prec, True, n, 1)
+        corr[prec] = sample_bits(ctx, sample)
+        extras[prec] = {"ms_per_step": round(d2 / n * 1e3, 3),
+                        "tflops": round(s2["plan"]["flops"] / (d2 / n) / 1e12, 3),
+                        "speedup_vs_fp64": round(tts / (d2 / n), 3),
+                        "issue_mode": X.binding.GRAPH_MODES[m], "kernel_choices": tiles[prec],
+                        **plan_summary(s2["plan"])}
+        log(prec, extras[prec])
     ctx.close()
     runner.arena = None
     del runner
     torch.cuda.empty_cache()
-    return res
+    return fields, extras, corr
+
+
+def measured_traffic(workload, variant):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel source or variant differs from the one the
+    counters were taken on."""
+    path = os.path.join(ROOT, "profiles", f"hec_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    from paper_2511_02257_amd.profiling import kernel_source_sha256
+    if rec.get("kernel_sha256") != kernel_source_sha256():
+        return None
+    entry = rec.get("variants", {}).get(str(variant))
+    return None if entry is None else entry.get("traffic_bytes_per_launch")
+
+
+# ---------------------------------------------------------------- meson
+def meson_budgeted(args, X, W, DeviceRunner):
+    """The memory-bound meson configuration: 16 mesons complex128 [32][64][64],
+    2000 ring traces; budget a quarter of the input-order live peak; leaves in
+    pinned host memory.  Input order and Tree (waves with lookahead 16, and
+    Tree without lookahead) in each issue mode; host-transfer rates of the
+    eager Tree run beside a pinned-copy link reference."""
+    torch = __import__("torch")
+    wl = W.config("meson_ring")
+    ctx = X.Context()
+    ctx.build_cdag(wl.leaves, wl.graphs)
+    del wl
+    ctx.schedule("input")
+    budget = ctx.plan("fp64", False)["peak_live"] // 4
+    runner = DeviceRunner(ctx, 0)
+    ctx.schedule("tree")
+    ctx.set_options(leaves_resident=True, wave_lookahead=ALL, use_graphs=1)
+    runner.autotune("fp64", True, reps=1, in_situ=False)
+    ref = None
+    out = {"budget_bytes": budget}
+    d2, s2 = timed_steps(runner, "fp64", True, 10, 2)
+    out["resident_tree_ms"] = round(d2 / 10 * 1e3, 3)
+    ref = np.concatenate(ctx.fetch_correlators()).view(np.uint64).copy()
+    ctx.set_mem_budget(budget)
+    for policy, look in (("input", 16), ("tree", 16), ("tree", 0), ("node", 16)):
+        ctx.schedule(policy)
+        row = {}
+        for mode in (0, 1, 2):
+            ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=mode)
+            d2, s2 = timed_steps(runner, "fp64", True, 3, 1)
+            row[X.binding.GRAPH_MODES[mode] + "_ms"] = round(d2 / 3 * 1e3, 3)
+        row["bits_equal_resident"] = bool(np.array_equal(np.concatenate(ctx.fetch_correlators()).view(np.uint64), ref))
+        row.update(plan_summary(s2["plan"]))
+        row["tflops_best"] = round(s2["plan"]["flops"] / (min(v for k, v in row.items() if k.endswith("_ms")) * 1e-3) / 1e12, 3)
+        out[f"{policy}_lookahead{look}"] = row
+        log("meson", policy, look, row)
+    ctx.schedule("tree")
+    ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=0)
+    ctx.set_timing(True)
+    t0 = time.perf_counter()
+    runner.run("fp64", True)
+    torch.cuda.synchronize()
+    out["transfers_tree_lookahead16_eager"] = transfer_rates(ctx.launch_records(), time.perf_counter() - t0)
+    ctx.set_timing(False)
+    out["link_reference"] = link_reference(torch)
+    link = out["link_reference"].get("h2d_2MiB_GBps")
+    best = min(v for k, v in out["tree_lookahead16"].items() if k.endswith("_ms"))
+    if link:
+        floor = out["tree_lookahead16"]["h2d_GB"] / link * 1e3
+        out["tree_lookahead16_over_link_floor"] = round(best / floor, 3)
+    ctx.close()
+    runner.arena = None
+    del runner
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------- batched
+def batched_budgeted(args, X, W, DeviceRunner):
+    """The batched configuration: five N families (32..128), Nt = 64, complex64
+    storage, just over 20,000 contractions; HBM budget 64e9 bytes; leaves in
+    pinned host memory; Tree order; synthetic autotuner.  Waves (one grouped
+    launch per kernel choice and wave) against one launch per contraction,
+    FP32 (and split-BF16 with two pieces, waves)."""
+    torch = __import__("torch")
+    wl = W.config("batched")
+    ctx = X.Context()
+    ctx.build_cdag(wl.leaves, wl.graphs)
+    budget = wl.budget_bytes
+    del wl
+    ctx.schedule("tree")
+    ctx.set_mem_budget(budget)
+    runner = DeviceRunner(ctx, 0)
+    out = {}
+    for prec in ("fp32", "bf16x3"):
+        ctx.set_time_chunks(1)
+        ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=0)
+        runner.autotune(prec, True, reps=1, in_situ=False)
+        ref = None
+        rows = (("waves_lookahead16", True, 1, 16), ("waves_lookahead16_4passes", True, 4, 16),
+                ("per_contraction", False, 1, 0))
+        for name, batched, chunks, look in rows:
+            if prec != "fp32" and not batched:
+                continue
+            ctx.set_time_chunks(chunks)
+            m, mt = best_mode(runner, ctx, prec, batched, modes=(0, 2) if batched else (0,), reps=1,
+                              leaves_resident=False, wave_lookahead=look)
+            d2, s2 = timed_steps(runner, prec, batched, 1, 0)
+            bits = np.concatenate(ctx.fetch_correlators()).view(np.uint64)
+            if ref is None:
+                ref = bits.copy()
+            row = {"tts_s": round(d2, 4), "tflops": round(s2["plan"]["flops"] / d2 / 1e12, 3),
+                   "issue_mode": X.binding.GRAPH_MODES[m], "n_hec_launches": s2["n_hec_launches"],
+                   "n_launches": s2["n_launches"], "bits_equal_first": bool(np.array_equal(bits, ref)),
+                   "n_contractions": s2["plan"]["n_contr"], **plan_summary(s2["plan"])}
+            out[f"{prec}_{name}"] = row
+            log("batched", prec, name, row)
+    ctx.close()
+    runner.arena = None
+    del runner
+    torch.cuda.empty_cache()
+    return out
 
 
 def corr_func_study(rows=None):
@@ -371,68 +515,69 @@ def general_study(shares=(0.02, 0.05, 0.1), n_trees=40000):
     return out
 
 
-def cpu_baseline(wl, seconds=12.0):
-    """The oracle (numpy complex128, each graph on its own) on a bounded sample."""
+def cpu_baseline(seconds):
+    """The oracle (numpy complex128, each graph evaluated on its own) on the
+    first graphs of the headline workload, for about `seconds`; returns the
+    baseline record and the oracle's correlators of the sample."""
     from oracle import values as OV
+    from synth import workloads as W
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
+    wl = W.config("baryon_mix")
     data = [lf.data for lf in wl.leaves]
-    flops = 0.0
+    ref = {}
     t0 = time.perf_counter()
     n = 0
     while time.perf_counter() - t0 < seconds and n < len(wl.graphs):
-        ops = wl.graphs[n].ops
-        OV.evaluate_graph(data, ops)
-        for kind, l, r in ops:
-            N, T = wl.leaves[0].nvec, wl.leaves[0].nt
-            flops += 8.0 * T * N ** 3 if kind == 0 else 8.0 * T * N * N
+        ref[n] = OV.evaluate_graph(data, wl.graphs[n].ops)
         n += 1
     dt = time.perf_counter() - t0
+    N, T = 64, 32
+    per_graph_flops = 2 * 8.0 * T * N ** 4 + 8.0 * T * N * N       # K32 + K33 + trace, no sharing
     cpu = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
             cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
-    return {"value": flops / dt / 1e12, "unit": "complex TFLOP/s", "cores": int(threads),
+    tts_all = dt / n * len(wl.graphs)
+    return {"value": round(per_graph_flops * n / dt / 1e12, 5), "unit": "complex TFLOP/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"first {n} of {len(wl.graphs)} graphs, each evaluated on its own with "
-                      f"numpy complex128 matmul (no DAG sharing), {dt:.1f} s",
-            "cpu": cpu, "host_cpus": os.cpu_count()}
+            "sample": f"first {n} of {len(wl.graphs)} graphs of the headline workload, each evaluated on its "
+                      f"own with numpy complex128 tensordot (no DAG sharing, no memory budget), {dt:.1f} s",
+            "time_to_solution_extrapolated_s": round(tts_all, 2),
+            "cpu": cpu, "host_cpus": os.cpu_count()}, ref
+
+
+def errors_vs_oracle(corr, ref):
+    """Per correlator of the sample: ||C - C_ref|| / ||C_ref|| over t."""
+    errs = np.array([np.linalg.norm(corr[g] - ref[g]) / np.linalg.norm(ref[g]) for g in ref])
+    return {"graphs": len(errs), "max": float(errs.max()), "median": float(np.median(errs))}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--skip-extras", action="store_true", help="only the headline value")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--chunks", type=int, default=8, help="time-slice passes of the headline execute")
+    ap.add_argument("--link-GBps", type=float, default=55.0,
+                    help="host-link rate for the upload floor of the headline (large pinned copies)")
+    ap.add_argument("--only", default=None, choices=("headline", "meson", "batched"),
+                    help="one part: the headline (with its references and precision form), the budgeted "
+                         "meson configuration, or the batched configuration")
+    ap.add_argument("--tiles-from", default=None, metavar="JSON",
+                    help="take the headline's kernel choices from the JSON line of an earlier run "
+                         "instead of autotuning (so that profiled runs use the same kernels)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--fp64-variant", default=None, metavar="TILE,GRID,STAGES",
-                    help="fix the FP64 K22 kernel variant instead of autotuning it "
-                         "(so that counter runs profile the variant a timed run chose)")
-    ap.add_argument("--workload", default="meson_ring",
-                    choices=("meson_ring", "baryon_mix", "batched"),
-                    help="meson_ring: the headline line (default). baryon_mix, batched: that config "
-                         "alone at full size, resident, with per-kernel rates (for profiling)")
-    ap.add_argument("--variants-from", default=None, metavar="JSON",
-                    help="with --workload baryon_mix or batched: take the kernel choices from the "
-                         "JSON line of an earlier run of the same workload instead of autotuning")
-    ap.add_argument("--budgeted", action="store_true",
-                    help="with --workload: also time input order, Sibling and Tree under the "
-                         "configuration's HBM budget with the leaves starting on the host")
     ap.add_argument("--study", default=None, choices=("corr_func", "general"),
                     help="host-only: peak memory and scheduler time on the Table corr-func-shaped "
-                         "DAGs (no GPU)")
+                         "DAGs, or on general DAGs (no GPU)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
-    ap.add_argument("--transfers", action="store_true",
-                    help="only the budgeted meson transfers: --steps timed eager FP64 executes "
-                         "(Tree, lookahead 16, leaves on the host) with per-copy events, no other "
-                         "copies (for a memory-copy trace)")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -460,168 +605,28 @@ def main():
     import paper_2511_02257_amd as X
     from paper_2511_02257_amd.device import DeviceRunner
 
-    if args.workload != "meson_ring":
-        precs = ("fp64", "fp32", "bf16x3") if args.workload == "baryon_mix" else ("fp32", "bf16x3")
-        fixed = None
-        if args.variants_from:
-            with open(args.variants_from) as f:
-                prev = json.loads(f.read().strip().splitlines()[-1])
-            fixed = {p: r["variants"] for p, r in prev["per_precision"].items()}
-        res = workload_rooflines(args.workload, precs, args.steps, X, W, DeviceRunner,
-                                 in_situ=args.workload == "baryon_mix", fixed=fixed, budgeted=args.budgeted)
-        head = res[precs[0]]
-        print(json.dumps({
-            "metric": METRIC, "value": head["tflops"], "unit": "complex TFLOP/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": 1, "ms_per_step": head["ms_per_step"],
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f64" if precs[0] == "fp64" else "c64 storage, f32 accumulate",
-            "data": "synthetic",
-            "config": {"workload": args.workload + " (full size, leaves resident, no budget)"},
-            "per_precision": res}), flush=True)
+    out = {"metric": METRIC, "unit": "complex TFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic"}
+    if args.only == "meson":
+        print(json.dumps({"meson_ring_budgeted": meson_budgeted(args, X, W, DeviceRunner)}), flush=True)
         return
-
-    wl = W.config("meson_ring")
-    log("workload built")
-    ctx = X.Context()
-    ctx.build_cdag(wl.leaves, wl.graphs)
-    # budget: a quarter of the input-order schedule's live peak
-    ctx.schedule("input")
-    live = {p: ctx.plan(p, False)["peak_live"] for p in ("fp64", "fp32")}
-    budgets = {"fp64": live["fp64"] // 4, "fp32": live["fp32"] // 4, "bf16x3": live["fp32"] // 4}
-    t0 = time.perf_counter()
-    ctx.schedule("tree")
-    t_sched = time.perf_counter() - t0
-    ctx.set_mem_budget(None)
-    ALL = X.binding.LOOKAHEAD_ALL
-    ctx.set_options(leaves_resident=True, wave_lookahead=ALL, use_graphs=True)
-    runner = DeviceRunner(ctx, 0)
-    if args.transfers:
-        print(json.dumps({"transfers": transfer_study(ctx, runner, budgets["fp64"], reps=args.steps,
-                                                      link=False),
-                          "budget_bytes": budgets["fp64"]}), flush=True)
+    if args.only == "batched":
+        print(json.dumps({"batched_budgeted": batched_budgeted(args, X, W, DeviceRunner)}), flush=True)
         return
-    tiles = {}
-    for prec in ("fp64", "fp32", "bf16x3"):
-        if prec == "fp64" and args.fp64_variant:
-            ctx.set_tile("fp64", 0, 64, *(int(x) for x in args.fp64_variant.split(",")))
-            runner.ensure_arena(ctx.plan("fp64", True)["arena_bytes"])
-        elif prec == "fp64" or not args.skip_extras:
-            runner.autotune(prec, True, reps=3, in_situ=True)
-        t, g, st, _ = ctx.get_tile(prec, 0, 64)
-        tiles[prec] = {"K22_N64": {"tile": list(X.TILES[t]), "threads": X.binding.TILE_THREADS[t],
-                                   "grid": X.binding.GRIDS[g], "lds_stages": st}}
-    log("autotuned tiles", tiles)
-
-    # ---- headline: FP64, Tree, waves, leaves resident, graph replay
-    dt, st = timed_steps(ctx, runner, "fp64", True, args.steps, args.warmup)
-    flops = st["plan"]["flops"]
-    value = flops * args.steps / dt / 1e12
-    log(f"fp64 waves: {dt / args.steps * 1e3:.3f} ms/step, {value:.2f} TFLOP/s")
-    out = {
-        "metric": METRIC, "value": round(value, 4), "unit": "complex TFLOP/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(dt / args.steps * 1e3, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "meson_ring: 16 mesons complex128 [32][64][64], 2000 ring traces "
-                               "of 4-8 leaves, merged DAG",
-                   "n_contractions": st["plan"]["n_contr"], "n_waves": st["plan"]["n_steps"],
-                   "schedule": "tree",
-                   "mode": "waves of every ready contraction, one hipGraph replay",
-                   "leaves": "resident in HBM", "flops_per_step": flops,
-                   "t_schedule_tree_s": round(t_sched, 4), "autotuned_tiles": tiles},
-        # memory of the timed run: HBM held by the arena (leaves, tensor pool,
-        # split-K workspace, descriptors, results), the plan's resident peak, and
-        # host-to-device bytes per step (0: the leaves stay resident after the
-        # first upload).  The budgeted runs under extras carry the same figures.
-        "memory": {"arena_GB": round(st["plan"]["arena_bytes"] / 1e9, 4),
-                   "tensor_highwater_GB": round(st["plan"]["tensor_highwater"] / 1e9, 4),
-                   "peak_live_GB": round(st["plan"]["peak_live"] / 1e9, 4),
-                   "h2d_GB_per_step": round(st["plan"]["h2d_bytes"] / 1e9, 4)},
-    }
-
-    # ---- roofline of the exterior-contraction kernel (HIP events per launch)
-    ctx.set_timing(True)
-    hec_t, hec_f, hec_b, hec_n = 0.0, 0.0, 0.0, 0
-    for _ in range(max(1, args.steps // 5)):
-        s2 = runner.run("fp64", True)
-        hec_t += s2["t_hec_s"]
-        hec_f += s2["hec_flops"]
-        hec_b += s2["hec_bytes"]
-        hec_n += s2["n_hec_launches"]
-    kernels = kernel_table(ctx.launch_records(), "fp64")
-    ctx.set_timing(False)
-    achieved = hec_f / hec_t / 1e12
-    t64, g64, st64, _ = ctx.get_tile("fp64", 0, 64)
-    variant = X.binding.variant_index(t64, g64, st64)
-    out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"],
-                       "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp64"], 4),
-                       "traffic": measured_traffic(variant), "tile": list(X.TILES[t64]),
-                       "threads": X.binding.TILE_THREADS[t64],
-                       "grid": X.binding.GRIDS[g64], "lds_stages": st64,
-                       "variant": [t64, g64, st64],
-                       "kernel": "hec_mfma<double> (grouped K22 waves)",
-                       "avg_launch_us": round(hec_t / hec_n * 1e6, 3),
-                       "flops_per_launch": hec_f / hec_n,
-                       "alg_bytes_per_launch": hec_b / hec_n,
-                       "achieved_GBps": round(hec_b / hec_t / 1e9, 1),
-                       "all_kernels_last_execute": kernels}
-    log("roofline", out["roofline"])
-
-    if not args.skip_extras:
-        extras = {}
-        # mixed precision, same resident mode
-        for prec in ("fp32", "bf16x3"):
-            d2, s3 = timed_steps(ctx, runner, prec, True, max(5, args.steps // 2), 2)
-            extras[f"{prec}_value"] = round(s3["plan"]["flops"] * max(5, args.steps // 2) / d2 / 1e12, 4)
-            extras[f"{prec}_ms_per_step"] = round(d2 / max(5, args.steps // 2) * 1e3, 4)
-        # waves that keep the schedule order exactly (no lookahead)
-        ctx.set_options(leaves_resident=True, wave_lookahead=0, use_graphs=True)
-        d2, s3 = timed_steps(ctx, runner, "fp64", True, max(3, args.steps // 5), 1)
-        extras["fp64_ordered_waves_value"] = round(s3["plan"]["flops"] * max(3, args.steps // 5) / d2 / 1e12, 4)
-        extras["fp64_ordered_waves_n_waves"] = s3["plan"]["n_steps"]
-        # per-contraction launches instead of waves
-        ctx.set_options(leaves_resident=True, use_graphs=False)
-        d2, s3 = timed_steps(ctx, runner, "fp64", False, max(3, args.steps // 10), 1)
-        extras["fp64_per_contraction_value"] = round(s3["plan"]["flops"] * max(3, args.steps // 10) / d2 / 1e12, 4)
-        # budgeted, leaves start on the host (PCIe-inclusive time-to-solution)
-        # Each schedule runs with eager launches on two streams (copies overlap
-        # kernels) and with captured segments on one stream (fewer launches);
-        # the faster is reported, with the other's time beside it.  The Tree
-        # schedule is also cut into waves with growing lookahead.
-        budgeted = {}
-        for prec in ("fp64", "fp32"):
-            ctx.set_mem_budget(budgets[prec])
-            for policy, look in (("input", 0), ("sibling", 0), ("tree", 0), ("tree", 4), ("tree", 16),
-                                 ("tree", ALL), ("node", 0), ("node", 16)):
-                ctx.schedule(policy)
-                reps = 3
-                tts = {}
-                for graphs in (False, True):
-                    ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=graphs)
-                    d2, s3 = timed_steps(ctx, runner, prec, True, reps, 1)
-                    tts["graphs" if graphs else "eager"] = d2 / reps
-                d2 = min(tts.values()) * reps
-                p = s3["plan"]
-                key = f"{prec}_{policy}" + ("" if not look else ("_lookahead_all" if look == ALL
-                                                                   else f"_lookahead{look}"))
-                budgeted[key] = {
-                    "tts_eager_s": round(tts["eager"], 5), "tts_graphs_s": round(tts["graphs"], 5),
-                    "tts_s": round(d2 / reps, 5), "h2d_GB": round(p["h2d_bytes"] / 1e9, 4),
-                    "d2h_GB": round(p["d2h_bytes"] / 1e9, 4), "n_evict": p["n_evict"],
-                    "n_h2d": p["n_h2d"], "peak_resident_bytes": p["peak_resident"],
-                    "peak_post_bytes": p["peak_post"], "budget_bytes": p["budget"],
-                    "n_waves": p["n_steps"],
-                    "tflops": round(p["flops"] / (d2 / reps) / 1e12, 3)}
-                log(key, budgeted[key])
-        extras["budgeted"] = budgeted
-        extras["transfers"] = transfer_study(ctx, runner, budgets["fp64"])
-        ctx.set_mem_budget(None)
-        # the baryon configuration (FP64) and its precision form, per-kernel rates
-        extras["baryon_mix"] = workload_rooflines("baryon_mix", ("fp64", "fp32", "bf16x3"),
-                                                  max(3, args.steps // 10), X, W, DeviceRunner)
-        out["extras"] = extras
-
-    out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    # the oracle's sample first (its correlators also give the precision errors)
+    base, ref = cpu_baseline(args.cpu_seconds if args.only is None else min(args.cpu_seconds, 3.0))
+    fields, extras, corr = headline(args, X, W, DeviceRunner, sorted(ref))
+    out.update(fields)
+    errs = {p: errors_vs_oracle(c, ref) for p, c in corr.items()}
+    out["config"]["correlator_error_vs_fp64_oracle"] = errs["fp64"]
+    for p in ("fp32", "bf16x3", "bf16x6"):
+        extras[p]["correlator_error_vs_fp64_oracle"] = errs[p]
+    out["extras"] = {"baryon_mix": extras}
+    if args.only is None:
+        out["extras"]["meson_ring_budgeted"] = meson_budgeted(args, X, W, DeviceRunner)
+        out["extras"]["batched_budgeted"] = batched_budgeted(args, X, W, DeviceRunner)
+    out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
 
 

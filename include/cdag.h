@@ -78,11 +78,14 @@ enum cdag_policy { CDAG_SCHED_INPUT = 0, CDAG_SCHED_SIBLING = 1, CDAG_SCHED_TREE
 #define CDAG_SCHED_CHECK 0x100
 
 /* Arithmetic of the exterior contractions.  FP64: complex128 storage and
- * arithmetic.  FP32 and BF16X3: complex64 storage, products on the matrix
- * cores with FP32 accumulation (BF16X3 splits each FP32 operand into a bf16
- * hi + lo pair and keeps three of the four products).  Traces and the
- * cross-diagram sums are FP64 in every mode. */
-enum cdag_prec { CDAG_FP64 = 0, CDAG_FP32 = 1, CDAG_BF16X3 = 2 };
+ * arithmetic.  FP32, BF16X3 and BF16X6: complex64 storage, products on the
+ * matrix cores with FP32 accumulation.  BF16X3 splits each FP32 operand into
+ * a bf16 hi + lo pair and keeps three of the four piece products (about
+ * 2^-16 relative error per product); BF16X6 splits it into three bf16 pieces
+ * and keeps the six piece products whose order is at most 2^-16 (about the
+ * FP32 rounding of the operands).  Traces and the cross-diagram sums are FP64
+ * in every mode. */
+enum cdag_prec { CDAG_FP64 = 0, CDAG_FP32 = 1, CDAG_BF16X3 = 2, CDAG_BF16X6 = 3 };
 
 /* Plan op records (cdag_plan_ops). */
 enum cdag_plan_op { CDAG_OP_D2H = 0, CDAG_OP_DROP = 1, CDAG_OP_H2D = 2,
@@ -137,13 +140,14 @@ typedef struct {
   double t_device_s;  /* compute stream, first kernel to last (HIP events)    */
   double t_hec_s;     /* summed exterior-contraction kernel time (timing on)  */
   double hec_flops;   /* algorithmic flops of the exterior contractions       */
-  double hec_bytes;   /* algorithmic bytes: each operand read once, output written once */
+  double hec_bytes;   /* algorithmic bytes: per launch, each distinct operand read once,
+                         each output written once                                   */
   int64_t n_launches;
   int64_t n_hec_launches;
   int64_t n_graph_segments;
   double t_kernels_s;     /* summed duration of every kernel launch (timing on; else 0) */
-  double t_copy_s;        /* summed duration of the host transfers on the copy stream
-                             (timing on; else 0)                                    */
+  double t_copy_s;        /* summed duration of the host transfers on the upload and
+                             spill streams (timing on; else 0)                      */
   int64_t arena_highwater; /* arena bytes the plan uses: leaf region, tensor pool
                               high-water, split-K workspace, descriptors, results   */
 } cdag_exec_stats;
@@ -162,12 +166,13 @@ typedef struct {
   int64_t step;       /* plan step (wave); -1 for the cross-diagram sum                */
   int64_t n_items;    /* workgroup work items; H2D, D2H: 1                               */
   double flops;       /* algorithmic flops (8 per complex multiply-add); transfers: 0   */
-  double bytes;       /* HEC, HCA: algorithmic bytes (operands read once, output written
-                         once); REDUCE: split-K workspace read + output write; XSUM: 0;
+  double bytes;       /* HEC, HCA: algorithmic bytes (each distinct operand of the launch
+                         read once, each output written once); REDUCE: split-K
+                         workspace read + output write; XSUM: 0;
                          H2D, D2H: the tensor's bytes                                   */
   double ms;          /* duration between HIP events around the launch or the copy, on
-                         the stream that runs it (transfers: the copy stream, after any
-                         wait for the compute stream)                                   */
+                         the stream that runs it (transfers: the upload or the spill
+                         stream, after any wait for another stream)                     */
 } cdag_launch_record;
 
 /* One record of a traced execute (cdag_trace_execute). */
@@ -175,16 +180,18 @@ enum cdag_trace_op { CDAG_TR_RECORD = 0, CDAG_TR_WAIT = 1, CDAG_TR_READ = 2, CDA
 enum cdag_trace_space { CDAG_SPACE_ARENA = 0, CDAG_SPACE_SPILL = 1, CDAG_SPACE_STAGE = 2 };
 typedef struct {
   int32_t op;       /* cdag_trace_op                                                     */
-  int32_t stream;   /* 0: the compute stream, 1: the copy stream                         */
+  int32_t stream;   /* 0: the compute stream, 1: the upload stream, 2: the spill stream  */
   int64_t seq;      /* READ, WRITE: number of the operation (one host transfer, or all
                        kernels of one step) they belong to; -1 for events               */
   int64_t step;     /* plan step that issues the record                                  */
   int64_t node;     /* READ, WRITE: the tensor; -1 for events                            */
-  int64_t event;    /* RECORD, WAIT: 2 * step + stream of the event's step and stream    */
+  int64_t event;    /* RECORD, WAIT: 3 * step + stream of the event's step and stream
+                       (step counted over all passes); pass-end events:
+                       3 * (passes * steps per pass + pass) + stream              */
   int32_t space;    /* READ, WRITE: cdag_trace_space of the range                        */
   int32_t reserved;
-  int64_t off;      /* READ, WRITE: byte offset in the space (STAGE: 0 within the leaf's
-                       own staging buffer)                                               */
+  int64_t off;      /* READ, WRITE: byte offset in the space (STAGE: within the leaf's
+                       own staging buffer, 0 unless time-slice passes are in use)       */
   int64_t bytes;    /* READ, WRITE: bytes                                                */
 } cdag_trace_rec;
 
@@ -278,23 +285,43 @@ int set_mem_budget(cdag_ctx* c, uint64_t bytes);
  * takes the ready contractions (operands are leaves or earlier waves' outputs)
  * in schedule order and may pass over this many not-ready ones (default 0:
  * the schedule order is kept exactly; INT64_MAX: every ready contraction).
- * use_graphs: 1 (default) replays a transfer-free step sequence from a
- * captured HIP graph.  CDAG_E_INVALID for wave_max < 1 or a negative
- * lookahead. */
+ * use_graphs: 0 issues every step eagerly on three streams (kernels, uploads,
+ * spills) with event waits from the plan; 1 (default) replays captured HIP
+ * graphs with every step on one stream (one graph, or segments of 64 steps
+ * when the plan moves data); 2 replays one captured graph over the three
+ * streams with the plan's waits as graph edges (uploads and spills overlap
+ * kernels).  CDAG_E_INVALID for wave_max < 1, a negative lookahead or another
+ * use_graphs. */
 int cdag_set_options(cdag_ctx* c, int leaves_resident, int wave_max, int64_t wave_lookahead,
                      int use_graphs);
 
+/* Time-slice passes.  Every exterior contraction and trace acts on each time
+ * slice t on its own (Sec. II-B: hadron-node tensors batched over t), so the
+ * DAG may run as t_chunks passes, pass k over slices [k nt / t_chunks,
+ * (k + 1) nt / t_chunks) of every tensor.  Passes alternate between two halves
+ * of the budget (each pass is planned with tensors of size / t_chunks bytes
+ * under budget / 2), so the uploads of one pass overlap the kernels of the
+ * pass before.  Plan statistics are those of the whole execution (counters
+ * summed over passes, peak_resident over both halves); cdag_plan_ops lists
+ * the ops of one pass.  Results are bit-identical to t_chunks = 1 (split-K
+ * counts follow the whole nt).  t_chunks = 1 (default) keeps tensors whole,
+ * the memory model of Sec. II-C.  CDAG_E_INVALID for t_chunks < 1; planning
+ * fails with CDAG_E_INVALID when t_chunks does not divide every tensor's nt. */
+int cdag_set_time_chunks(cdag_ctx* c, int64_t t_chunks);
+
 /* timing: 1 records a HIP event pair around every kernel launch on the
- * compute stream and around every host transfer on the copy stream, reports
+ * compute stream and around every host transfer on its stream, reports
  * the summed exterior-contraction durations in t_hec_s and keeps per-launch
  * and per-transfer records (execution then runs without graph replay);
  * 0 (default) turns it off. */
 int cdag_set_timing(cdag_ctx* c, int timing);
-/* Host-only: the eager two-stream issue order that execute would follow for
- * (prec, batched), recorded without any HIP call: per step, the copy stream's
- * waits for compute events, its transfers (the ranges each reads and writes),
- * its event record, the compute stream's waits for copy events, the ranges
- * the step's kernels read and write, and the compute event record.  It lets a
+/* Host-only: the eager three-stream issue order that execute would follow for
+ * (prec, batched), recorded without any HIP call: per step, the spill
+ * stream's waits and spills (the ranges each reads and writes) and its event
+ * record, the upload stream's waits, uploads and event record, the compute
+ * stream's waits, the ranges the step's kernels read and write, and the
+ * compute event record; per time-slice pass, the pass-end records and the
+ * waits of the pass two later on them.  It lets a
  * CPU check that every pair of conflicting accesses is ordered by a stream or
  * an event (the plan's data movement, Sec. II-A and Sec. IV-C).  *n_out
  * (nullable) receives the count; at most cap records are written.

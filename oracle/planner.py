@@ -28,6 +28,13 @@ Per step s:
 leaves_resident=True models leaves kept permanently in a device region outside
 the budget: they are never uploaded, evicted or counted.
 
+t_chunks = C > 1 runs the DAG as C passes, each over nt / C time slices of
+every tensor (every contraction and trace acts on each slice on its own).
+Passes alternate between two halves of the budget, so one pass is planned as
+above with every size divided by C and budget // 2; the execution's counters
+are C times the pass's, its steps C times as many, and its resident peak twice
+the pass's (both halves in use).  The op records are those of one pass.
+
 Op records: (op, node, step) with op in D2H, DROP, H2D, ALLOC, EXEC, FREE.
 """
 from __future__ import annotations
@@ -87,9 +94,23 @@ def cut_waves(d: Dag, order: Sequence[int], size: Sequence[int], budget: int,
 
 def plan(d: Dag, order: Sequence[int], elem_bytes: int = 16, budget: int = UNLIMITED,
          batched: bool = False, wave_max: int = WAVE_MAX, leaves_resident: bool = False,
-         lookahead: int = 0) -> dict:
+         lookahead: int = 0, t_chunks: int = 1) -> dict:
+    if t_chunks > 1:
+        if any(d.nt[u] % t_chunks for u in range(d.n_nodes)):
+            raise ValueError("t_chunks must divide every tensor's nt")
+        one = _plan(d, order, elem_bytes, min(budget, UNLIMITED) // 2, batched, wave_max,
+                    leaves_resident, lookahead, t_chunks)
+        out = {k: (t_chunks * v if k in ("n_steps", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes")
+                   else v) for k, v in one.items()}
+        out["peak_resident"] = 2 * one["peak_resident"]
+        return out
+    return _plan(d, order, elem_bytes, budget, batched, wave_max, leaves_resident, lookahead, 1)
+
+
+def _plan(d: Dag, order: Sequence[int], elem_bytes: int, budget: int, batched: bool, wave_max: int,
+          leaves_resident: bool, lookahead: int, t_chunks: int) -> dict:
     n = d.n_nodes
-    size = [d.size(u, elem_bytes) for u in range(n)]
+    size = [d.size(u, elem_bytes) // t_chunks for u in range(n)]
     if leaves_resident:
         for u in range(d.n_leaves):
             size[u] = 0

@@ -19,7 +19,7 @@ OK, E_INVALID, E_STATE, E_BUDGET, E_HIP, E_NOMEM, E_RANGE = 0, -1, -2, -3, -4, -
 K22, K32, K33, HCA = 0, 1, 2, 3
 POLICY = {"input": 0, "sibling": 1, "tree": 2, "node": 3}
 SCHED_CHECK = 0x100
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 OP_NAMES = {0: "D2H", 1: "DROP", 2: "H2D", 3: "ALLOC", 4: "EXEC", 5: "FREE"}
 UNLIMITED = (1 << 64) - 1
 
@@ -111,6 +111,7 @@ def lib():
             "cdag_set_order": [P, C.POINTER(I64), I64],
             "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
             "cdag_set_timing": [P, C.c_int],
+            "cdag_set_time_chunks": [P, I64],
             "cdag_dag_stats": [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double),
                                C.POINTER(C.c_double)],
             "cdag_launch_records": [P, C.POINTER(cdag_launch_record), I64, C.POINTER(I64)],
@@ -141,7 +142,8 @@ def lib():
 
 
 EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "cdag_build_general", "schedule",
-            "set_mem_budget", "cdag_set_order", "cdag_set_options", "cdag_set_timing", "cdag_launch_records",
+            "set_mem_budget", "cdag_set_order", "cdag_set_options", "cdag_set_timing", "cdag_set_time_chunks",
+            "cdag_launch_records",
             "cdag_trace_execute", "cdag_dag_stats", "cdag_set_tile", "cdag_get_tile", "cdag_memsim",
             "cdag_plan", "cdag_plan_ops",
             "cdag_get_nodes", "cdag_graph_roots", "cdag_bind_device", "cdag_bind_arena",
@@ -242,10 +244,19 @@ def set_mem_budget(h, nbytes: Optional[int]) -> None:
 LOOKAHEAD_ALL = (1 << 63) - 1
 
 
+GRAPH_MODES = {0: "eager", 1: "one-stream segments", 2: "three-stream graph"}
+
+
 def cdag_set_options(h, leaves_resident=False, wave_max=4096, wave_lookahead=0,
-                     use_graphs=True) -> None:
+                     use_graphs=1) -> None:
+    """use_graphs: 0 (or False) eager, 1 (or True) one-stream captured segments,
+    2 one three-stream captured graph."""
     _check(lib().cdag_set_options(h, int(leaves_resident), int(wave_max), int(wave_lookahead),
                                   int(use_graphs)))
+
+
+def cdag_set_time_chunks(h, t_chunks: int) -> None:
+    _check(lib().cdag_set_time_chunks(h, int(t_chunks)))
 
 
 def cdag_set_timing(h, on: bool) -> None:
@@ -447,8 +458,11 @@ class Context:
     def set_mem_budget(self, nbytes):
         set_mem_budget(self.h, nbytes)
 
-    def set_options(self, leaves_resident=False, wave_max=4096, wave_lookahead=0, use_graphs=True):
+    def set_options(self, leaves_resident=False, wave_max=4096, wave_lookahead=0, use_graphs=1):
         cdag_set_options(self.h, leaves_resident, wave_max, wave_lookahead, use_graphs)
+
+    def set_time_chunks(self, t_chunks=1):
+        cdag_set_time_chunks(self.h, t_chunks)
 
     def set_timing(self, on=True):
         cdag_set_timing(self.h, on)

@@ -44,7 +44,8 @@ void need(bool ok, int code, const char* m) {
 }
 
 int elem_bytes_prec(int prec) {
-  need(prec == CDAG_FP64 || prec == CDAG_FP32 || prec == CDAG_BF16X3, CDAG_E_INVALID, "unknown precision");
+  need(prec == CDAG_FP64 || prec == CDAG_FP32 || prec == CDAG_BF16X3 || prec == CDAG_BF16X6, CDAG_E_INVALID,
+       "unknown precision");
   return prec == CDAG_FP64 ? 16 : 8;
 }
 }  // namespace
@@ -66,6 +67,7 @@ void ensure_plan(Ctx& c, int prec, int batched) {
   o.wave_max = c.wave_max;
   o.lookahead = c.wave_lookahead;
   o.leaves_resident = c.leaves_resident;
+  o.t_chunks = c.t_chunks;
   c.plan = make_plan(c.dag, c.order, o);
   place(c.dag, c.plan);
   c.kplan = make_kernel_plan(c.dag, c.plan, prec, c.tiles);
@@ -241,10 +243,20 @@ int cdag_set_options(cdag_ctx* h, int leaves_resident, int wave_max, int64_t wav
   return guard([&] {
     need(wave_max >= 1, CDAG_E_INVALID, "wave_max must be >= 1");
     need(wave_lookahead >= 0, CDAG_E_INVALID, "wave_lookahead must be >= 0");
+    need(use_graphs >= 0 && use_graphs <= 2, CDAG_E_INVALID, "use_graphs must be 0, 1 or 2");
     h->c.leaves_resident = leaves_resident != 0;
     h->c.wave_max = wave_max;
     h->c.wave_lookahead = wave_lookahead;
-    h->c.use_graphs = use_graphs != 0;
+    h->c.use_graphs = use_graphs;
+    h->c.version++;
+  });
+}
+
+int cdag_set_time_chunks(cdag_ctx* h, int64_t t_chunks) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    need(t_chunks >= 1, CDAG_E_INVALID, "t_chunks must be >= 1");
+    h->c.t_chunks = t_chunks;
     h->c.version++;
   });
 }
@@ -334,24 +346,25 @@ int cdag_memsim(cdag_ctx* h, const int64_t* order, int64_t n, int elem_bytes, in
 
 static void fill_plan_stats(const cdag::Ctx& c, cdag_plan_stats* s) {
   const cdag::Plan& p = c.plan;
+  const cdag::PlanTotals t = cdag::plan_totals(p);
   std::memset(s, 0, sizeof(*s));
   s->n_nodes = c.dag.n_nodes();
   s->n_leaves = c.dag.n_leaves;
   s->n_contr = c.dag.n_nodes() - c.dag.n_leaves;
   s->n_roots = (int64_t)c.dag.tree_root.size();
-  s->n_steps = (int64_t)p.steps.size();
+  s->n_steps = t.steps;
   s->peak_post = c.peak_post;
   s->peak_live = c.peak_live;
-  s->peak_resident = p.peak_resident;
-  s->n_evict = p.n_evict;
-  s->n_h2d = p.n_h2d;
-  s->h2d_bytes = p.h2d_bytes;
-  s->n_d2h = p.n_d2h;
-  s->d2h_bytes = p.d2h_bytes;
+  s->peak_resident = t.peak_resident;
+  s->n_evict = t.n_evict;
+  s->n_h2d = t.n_h2d;
+  s->h2d_bytes = t.h2d_bytes;
+  s->n_d2h = t.n_d2h;
+  s->d2h_bytes = t.d2h_bytes;
   s->budget = c.budget;
   s->arena_bytes = c.kplan.total_bytes;
-  s->tensor_highwater = p.leaf_region_bytes + p.pool_bytes;
-  s->host_spill_bytes = p.host_spill_bytes;
+  s->tensor_highwater = p.leaf_region_bytes + p.halves() * p.pool_bytes;
+  s->host_spill_bytes = p.halves() * p.host_spill_bytes;
   s->hec_items = c.kplan.hec_items;
   s->flops = c.kplan.flops;
   s->t_sched_s = c.t_sched;

@@ -31,7 +31,8 @@ struct Ctx {
   bool leaves_resident = false;
   int64_t wave_max = 4096;
   int64_t wave_lookahead = 0;
-  bool use_graphs = true;
+  int use_graphs = 1;            // 0 eager, 1 one-stream segments, 2 three-stream graph
+  int64_t t_chunks = 1;
   bool timing = false;
   TileTable tiles;               // (prec, kind, N) -> kernel variant overrides
   uint64_t version = 1;          // bumped by every change that invalidates a plan

@@ -116,10 +116,16 @@ struct PlanRec {
   int64_t dev_off = -1, host_off = -1;
   // EXEC: arena offsets of the left and right operands (dev_off: the output).
   int64_t a_off = -1, b_off = -1;
-  // synchronisation: before this op's copy (H2D) the copy stream waits for the
-  // compute work of step wait_comp; before an ALLOC's producing kernel the
-  // compute stream waits for the copy work of step wait_copy (-1: none).
-  int64_t wait_comp = -1, wait_copy = -1;
+  // Synchronisation between the three streams (compute, upload, spill), as
+  // steps of the same chunk whose work must have finished (-1: none):
+  //   D2H    wait_comp: kernels that last touched the tensor;
+  //          wait_h2d:  an upload that last read the host range it writes;
+  //   H2D    wait_comp: kernels that last touched the arena range it writes;
+  //          wait_d2h:  a spill that last read that arena range, or that
+  //                     wrote the tensor's host copy;
+  //   ALLOC  wait_d2h:  a spill that last read the arena range (the kernels
+  //                     of the step wait for it before writing the output).
+  int64_t wait_comp = -1, wait_h2d = -1, wait_d2h = -1;
 };
 
 struct PlanOpts {
@@ -129,8 +135,18 @@ struct PlanOpts {
   int64_t wave_max = 4096;
   int64_t lookahead = 0;
   bool leaves_resident = false;
+  // Time-slice chunks: every contraction and trace acts on each time slice t
+  // on its own, so the DAG can run as t_chunks passes over nt / t_chunks
+  // slices of every tensor.  Passes alternate between two halves of the
+  // budget, so the uploads of one pass overlap the kernels of the previous
+  // one.  Each pass follows the same plan, made for tensors of
+  // size / t_chunks bytes under budget / 2 (the whole budget when
+  // t_chunks = 1).
+  int64_t t_chunks = 1;
 };
 
+// Plan of one pass (t_chunks = 1: the whole execution).  Counters and the
+// resident peak are those of one pass; plan_totals() gives the execution's.
 struct Plan {
   PlanOpts opts;
   std::vector<std::vector<int64_t>> steps;  // contractions per step
@@ -138,15 +154,26 @@ struct Plan {
   std::vector<int64_t> rec_off;             // per step: first record index
   int64_t peak_resident = 0, n_evict = 0, n_h2d = 0, h2d_bytes = 0, n_d2h = 0, d2h_bytes = 0;
   // placement
-  int64_t pool_bytes = 0;                   // physical high-water of the tensor pool
-  int64_t host_spill_bytes = 0;
+  int64_t pool_bytes = 0;                   // physical high-water of one pass's tensor pool
+  int64_t host_spill_bytes = 0;             // host spill range of one pass
   std::vector<int64_t> leaf_off;            // leaves_resident: offsets in the leaf region
-  int64_t leaf_region_bytes = 0;
+  int64_t leaf_region_bytes = 0;            // whole leaves (all time slices)
+  int64_t chunks() const { return opts.t_chunks; }
+  int64_t halves() const { return opts.t_chunks > 1 ? 2 : 1; }
+  // Bytes of u's tensor in one pass.
+  int64_t tsize(const Dag& d, int64_t u) const { return d.size(u, opts.elem_bytes) / opts.t_chunks; }
 };
+
+// Counters of the whole execution: one pass's times t_chunks; the resident
+// peak of one pass per half of the budget in use.
+struct PlanTotals { int64_t steps, peak_resident, n_evict, n_h2d, h2d_bytes, n_d2h, d2h_bytes; };
+PlanTotals plan_totals(const Plan& p);
 
 std::vector<std::vector<int64_t>> cut_waves(const Dag& d, const std::vector<int64_t>& order,
                                             const std::vector<int64_t>& size, int64_t budget,
                                             int64_t wave_max, int64_t lookahead);
+// Throws Error(CDAG_E_INVALID) when t_chunks < 1 or does not divide the nt of
+// every node, Error(CDAG_E_BUDGET) when a step does not fit.
 Plan make_plan(const Dag& d, const std::vector<int64_t>& order, const PlanOpts& o);
 // Assign arena offsets (256-byte aligned, best fit) and host spill offsets,
 // and derive the cross-stream waits.

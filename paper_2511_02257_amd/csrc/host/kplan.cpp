@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <set>
 
 #include "../../../include/cdag.h"
 
@@ -41,7 +42,7 @@ std::map<std::pair<int, int>, TuneShape> tune_shapes(const Dag& d) {
   return out;
 }
 
-void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h) {
+void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h, int nt_run) {
   if (choice < 0 || choice >= kNumChoices) throw std::invalid_argument("kernel choice out of range");
   if (g.M > INT32_MAX || g.N > INT32_MAX || g.K > INT32_MAX)
     throw Error(CDAG_E_INVALID, "contraction dimensions exceed 2^31");
@@ -51,10 +52,10 @@ void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h) {
   h->N = (int32_t)g.N;
   h->K = (int32_t)g.K;
   const TileShape& ts = kTileShapes[variant_tile(variant)];
-  h->nt = nt;
+  h->nt = nt_run > 0 ? nt_run : nt;
   h->tiles_m = (h->M + ts.bm - 1) / ts.bm;
   h->tiles_n = (h->N + ts.bn - 1) / ts.bn;
-  const int64_t base = (int64_t)h->nt * h->tiles_m * h->tiles_n;
+  const int64_t base = (int64_t)nt * h->tiles_m * h->tiles_n;
   int64_t splits = std::min<int64_t>((kSplitTarget + base - 1) / base, h->K / kMinKSplit);
   splits = choice_split_k(choice) ? std::max<int64_t>(splits, 1) : 1;
   int64_t kspl = (h->K + splits - 1) / splits;
@@ -62,7 +63,7 @@ void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h) {
   splits = (h->K + kspl - 1) / kspl;
   h->splits = (int32_t)splits;
   h->k_split = (int32_t)kspl;
-  h->tile_count = (int32_t)(base * splits);
+  h->tile_count = (int32_t)((int64_t)h->nt * h->tiles_m * h->tiles_n * splits);
 }
 
 int default_tile(int prec, int kind, int n) {
@@ -109,10 +110,13 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
     auto it = tiles.find(std::make_tuple(prec, (int)d.kind[u], (int)d.nvec[u]));
     return it != tiles.end() ? it->second : default_tile(prec, d.kind[u], d.nvec[u]);
   };
+  // A pass covers nt / t_chunks slices; the split count follows the whole
+  // contraction (all nt slices), so it does not change with t_chunks and the
+  // results stay bit-identical.
   auto decomp = [&](int64_t u, HecDesc& h) {
     Gemm g;
     d.gemm_shape(u, &g.M, &g.N, &g.K);
-    decompose(g, d.nt[u], tile_of(u), prec, &h);
+    decompose(g, d.nt[u], tile_of(u), prec, &h, (int)(d.nt[u] / p.chunks()));
   };
 
   // pass 1: workspace size (max over steps) and descriptor counts
@@ -126,100 +130,125 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
     }
     kp.ws_bytes = std::max(kp.ws_bytes, ws);
   }
-  kp.tensors_end = align256(p.leaf_region_bytes + p.pool_bytes);
-  kp.ws_off = kp.tensors_end;
+  // [leaf region][half 0: tensor pool, workspace][half 1 (t_chunks > 1)]...
+  const int64_t C = p.chunks();
+  kp.chunks = C;
+  kp.half_bytes = align256(p.pool_bytes) + kp.ws_bytes;
+  kp.ws_off = align256(p.leaf_region_bytes + p.pool_bytes);
+  kp.tensors_end = p.leaf_region_bytes + p.halves() * kp.half_bytes;
 
-  // pass 2: descriptors (host blob; arena offset = blob_off + host offset)
-  kp.launch_off.reserve(S + 1);
-  for (int64_t s = 0; s < S; ++s) {
-    kp.launch_off.push_back((int64_t)kp.launches.size());
-    std::vector<HecDesc> hec[kNumVariants];
-    int64_t tiles[kNumVariants] = {0};
-    double v_flops[kNumVariants] = {0}, v_bytes[kNumVariants] = {0};
-    int32_t v_kinds[kNumVariants] = {0};
-    double red_bytes = 0, hca_flops = 0, hca_bytes = 0;
-    int32_t red_kinds = 0;
-    std::vector<RedDesc> red;
-    std::vector<HcaDesc> hca;
-    int64_t ws = kp.ws_off, items = 0;
-    for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
-      const PlanRec& r = p.recs[ri];
-      if (r.op != OP_EXEC) continue;
-      const int64_t u = r.node;
-      kp.flops += d.flops(u);
-      if (d.kind[u] == HCA) {
-        HcaDesc h{};
-        h.p_off = r.a_off;
-        h.q_off = r.b_off;
-        h.out_off = -1 - kp.tree_corr_off[tree_of[u]];   // fixed up below (needs corr_off)
-        h.n = d.nvec[u];
-        h.nt = d.nt[u];
-        hca.push_back(h);
-        hca_flops += d.flops(u);
-        hca_bytes += 2.0 * h.nt * (double)h.n * h.n * (double)elem_bytes_of(prec);
-        continue;
+  // pass 2: descriptors (host blob; arena offset = blob_off + host offset),
+  // one set per pass over the time slices: pass k runs in half k % 2 on
+  // slices [k nt / C, (k + 1) nt / C) of every tensor.
+  kp.launch_off.reserve(C * S + 1);
+  for (int64_t k = 0; k < C; ++k) {
+    const int64_t shift = (k % 2) * kp.half_bytes;
+    // arena offset of operand x of a contraction in pass k: a resident leaf's
+    // slices of this pass, else the planned offset in the pass's half
+    auto operand_off = [&](int64_t x, int64_t planned) {
+      if (p.opts.leaves_resident && d.is_leaf(x)) return p.leaf_off[x] + k * p.tsize(d, x);
+      return planned + shift;
+    };
+    for (int64_t s = 0; s < S; ++s) {
+      kp.launch_off.push_back((int64_t)kp.launches.size());
+      std::vector<HecDesc> hec[kNumVariants];
+      int64_t tiles[kNumVariants] = {0};
+      double v_flops[kNumVariants] = {0}, v_bytes[kNumVariants] = {0};
+      int32_t v_kinds[kNumVariants] = {0};
+      double red_bytes = 0, hca_flops = 0, hca_bytes = 0;
+      int32_t red_kinds = 0;
+      std::vector<RedDesc> red;
+      std::vector<HcaDesc> hca;
+      int64_t ws = kp.ws_off + shift, items = 0;
+      // algorithmic bytes of a launch: each distinct operand read once, each
+      // output written once (operands shared by contractions of one launch,
+      // e.g. a closing meson traced against many roots, count once)
+      std::set<int64_t> v_seen[kNumVariants], hca_seen;
+      auto operand_bytes = [&](std::set<int64_t>& seen, int64_t x) {
+        return seen.insert(x).second ? (double)p.tsize(d, x) : 0.0;
+      };
+      for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
+        const PlanRec& r = p.recs[ri];
+        if (r.op != OP_EXEC) continue;
+        const int64_t u = r.node;
+        const double fl = d.flops(u) / (double)C;
+        kp.flops += fl;
+        const int64_t a_off = operand_off(d.left[u], r.a_off), b_off = operand_off(d.right[u], r.b_off);
+        if (d.kind[u] == HCA) {
+          HcaDesc h{};
+          h.p_off = a_off;
+          h.q_off = b_off;
+          h.nt = (int32_t)(d.nt[u] / C);
+          // relative to the correlator buffer; fixed up below (needs corr_off)
+          h.out_off = -1 - (kp.tree_corr_off[tree_of[u]] + 16LL * k * h.nt);
+          h.n = d.nvec[u];
+          hca.push_back(h);
+          hca_flops += fl;
+          hca_bytes += operand_bytes(hca_seen, d.left[u]) + operand_bytes(hca_seen, d.right[u]);
+          continue;
+        }
+        HecDesc h{};
+        decomp(u, h);
+        const int tl = choice_variant(tile_of(u));
+        const double ab = operand_bytes(v_seen[tl], d.left[u]) + operand_bytes(v_seen[tl], d.right[u]) +
+                          (double)p.tsize(d, u);
+        kp.hec_flops += fl;
+        kp.hec_bytes += ab;
+        v_flops[tl] += fl;
+        v_bytes[tl] += ab;
+        v_kinds[tl] |= 1 << d.kind[u];
+        h.a_off = a_off;
+        h.b_off = b_off;
+        h.c_off = r.dev_off + shift;
+        h.ws_off = -1;
+        h.tile_begin = (int32_t)tiles[tl];
+        tiles[tl] += h.tile_count;
+        kp.hec_items += h.tile_count;
+        if (h.splits > 1) {
+          h.ws_off = ws;
+          RedDesc rd{};
+          rd.ws_off = ws;
+          rd.c_off = h.c_off;
+          rd.mn = h.M * h.N;
+          rd.nt = h.nt;
+          rd.splits = h.splits;
+          rd.item_begin = (int32_t)items;
+          items += (2LL * rd.nt * rd.mn + 255) / 256;
+          red.push_back(rd);
+          red_bytes += 2.0 * rd.nt * (double)rd.mn * ((double)rd.splits * acc_bytes + elem_bytes_of(prec));
+          red_kinds |= 1 << d.kind[u];
+          ws += align256((int64_t)h.splits * h.nt * 2 * h.M * h.N * acc_bytes);
+        }
+        hec[tl].push_back(h);
       }
-      HecDesc h{};
-      decomp(u, h);
-      const int tl = choice_variant(tile_of(u));
-      const double ab = (double)h.nt * ((double)h.M * h.K + (double)h.K * h.N + (double)h.M * h.N) *
-                        (double)elem_bytes_of(prec);
-      kp.hec_flops += d.flops(u);
-      kp.hec_bytes += ab;
-      v_flops[tl] += d.flops(u);
-      v_bytes[tl] += ab;
-      v_kinds[tl] |= 1 << d.kind[u];
-      h.a_off = r.a_off;
-      h.b_off = r.b_off;
-      h.c_off = r.dev_off;
-      h.ws_off = -1;
-      h.tile_begin = (int32_t)tiles[tl];
-      tiles[tl] += h.tile_count;
-      kp.hec_items += h.tile_count;
-      if (h.splits > 1) {
-        h.ws_off = ws;
-        RedDesc rd{};
-        rd.ws_off = ws;
-        rd.c_off = r.dev_off;
-        rd.mn = h.M * h.N;
-        rd.nt = h.nt;
-        rd.splits = h.splits;
-        rd.item_begin = (int32_t)items;
-        items += (2LL * rd.nt * rd.mn + 255) / 256;
-        red.push_back(rd);
-        red_bytes += 2.0 * rd.nt * (double)rd.mn * ((double)rd.splits * acc_bytes + elem_bytes_of(prec));
-        red_kinds |= 1 << d.kind[u];
-        ws += align256((int64_t)h.splits * h.nt * 2 * h.M * h.N * acc_bytes);
+      for (int tl = 0; tl < kNumVariants; ++tl) {
+        if (hec[tl].empty()) continue;
+        Launch L{L_HEC, tl, (int32_t)hec[tl].size(), 0, tiles[tl], 0};
+        L.flops = v_flops[tl];
+        L.bytes = v_bytes[tl];
+        L.kinds = v_kinds[tl];
+        L.host_desc = (int64_t)kp.blob.size();
+        for (auto& h : hec[tl]) put(kp.blob, h);
+        kp.launches.push_back(L);
       }
-      hec[tl].push_back(h);
-    }
-    for (int tl = 0; tl < kNumVariants; ++tl) {
-      if (hec[tl].empty()) continue;
-      Launch L{L_HEC, tl, (int32_t)hec[tl].size(), 0, tiles[tl], 0};
-      L.flops = v_flops[tl];
-      L.bytes = v_bytes[tl];
-      L.kinds = v_kinds[tl];
-      L.host_desc = (int64_t)kp.blob.size();
-      for (auto& h : hec[tl]) put(kp.blob, h);
-      kp.launches.push_back(L);
-    }
-    if (!red.empty()) {
-      Launch L{L_RED, 0, (int32_t)red.size(), 0, items, 0};
-      L.bytes = red_bytes;
-      L.kinds = red_kinds;
-      L.host_desc = (int64_t)kp.blob.size();
-      for (auto& x : red) put(kp.blob, x);
-      kp.launches.push_back(L);
-    }
-    if (!hca.empty()) {
-      Launch L{L_HCA, 0, (int32_t)hca.size(), 0, 0, 0};
-      L.flops = hca_flops;
-      L.bytes = hca_bytes;
-      L.kinds = 1 << HCA;
-      for (auto& h : hca) { h.item_begin = (int32_t)L.n_items; L.n_items += h.nt; }
-      L.host_desc = (int64_t)kp.blob.size();
-      for (auto& h : hca) put(kp.blob, h);
-      kp.launches.push_back(L);
+      if (!red.empty()) {
+        Launch L{L_RED, 0, (int32_t)red.size(), 0, items, 0};
+        L.bytes = red_bytes;
+        L.kinds = red_kinds;
+        L.host_desc = (int64_t)kp.blob.size();
+        for (auto& x : red) put(kp.blob, x);
+        kp.launches.push_back(L);
+      }
+      if (!hca.empty()) {
+        Launch L{L_HCA, 0, (int32_t)hca.size(), 0, 0, 0};
+        L.flops = hca_flops;
+        L.bytes = hca_bytes;
+        L.kinds = 1 << HCA;
+        for (auto& h : hca) { h.item_begin = (int32_t)L.n_items; L.n_items += h.nt; }
+        L.host_desc = (int64_t)kp.blob.size();
+        for (auto& h : hca) put(kp.blob, h);
+        kp.launches.push_back(L);
+      }
     }
   }
   kp.launch_off.push_back((int64_t)kp.launches.size());
@@ -246,7 +275,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
   for (auto& e : xe) put(kp.blob, e);
 
   // final layout and fix-ups of buffer-relative offsets
-  kp.blob_off = align256(kp.ws_off + kp.ws_bytes);
+  kp.blob_off = align256(kp.tensors_end);
   kp.corr_off = align256(kp.blob_off + (int64_t)kp.blob.size());
   kp.sums_off = kp.corr_off + kp.corr_bytes;
   kp.total_bytes = align256(kp.sums_off + kp.sums_bytes);

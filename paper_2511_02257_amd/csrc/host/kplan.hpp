@@ -54,29 +54,34 @@ int default_tile(int prec, int kind, int n);   // returns a choice
 // Complex GEMM per time slice of an exterior contraction (Dag::gemm_shape).
 struct Gemm { int64_t M, N, K; };
 // GEMM dimensions, tile counts and split-K of one contraction with GEMM g, nt
-// time slices and kernel `choice` (offsets and tile_begin unset).
-void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h);
+// time slices and kernel `choice` (offsets and tile_begin unset).  nt_run > 0:
+// the descriptor covers nt_run of the nt slices (one pass of a time-chunked
+// execution); the split count still follows all nt.
+void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h, int nt_run = 0);
 // Distinct (kind, N) among the exterior contractions of d (the keys of the
 // kernel-choice table), each with its largest Nt and its largest GEMM (a
 // general kind can occur with several operand ranks).
 struct TuneShape { int nt; Gemm gemm; };
 std::map<std::pair<int, int>, TuneShape> tune_shapes(const Dag& d);
 // k-step of the matrix-core kernels: FP64 and FP32 use 16, split-BF16 32.
-inline int k_step(int prec) { return prec == 2 ? 32 : 16; }
+inline int k_step(int prec) { return prec >= 2 ? 32 : 16; }
 // Split-K: aim for at least this many work items per contraction, keeping at
 // least kMinKSplit of K per split.
 constexpr int kSplitTarget = 512, kMinKSplit = 256;
 
 struct KernelPlan {
   int prec = 0;
-  std::vector<int64_t> launch_off;   // per step: first launch index (size n_steps + 1)
+  int64_t chunks = 1;                // passes over the time slices (PlanOpts::t_chunks)
+  std::vector<int64_t> launch_off;   // per step of each pass (k * n_steps + s): first launch index
+                                     // (size chunks * n_steps + 1)
   std::vector<Launch> launches;
   Launch xsum{};
   int64_t xsum_entries_off = 0;     // arena offset of the XsumEntry table
   std::vector<uint8_t> blob;         // all descriptor tables, uploaded to blob_off
   // arena layout
-  int64_t tensors_end = 0;           // leaf region + tensor pool
-  int64_t ws_off = 0, ws_bytes = 0;
+  int64_t tensors_end = 0;           // leaf region + tensor pool and workspace of each half
+  int64_t half_bytes = 0;            // tensor pool + workspace of one half (a pass's memory)
+  int64_t ws_off = 0, ws_bytes = 0;  // workspace of half 0 (half 1: + half_bytes)
   int64_t blob_off = 0;
   int64_t corr_off = 0, corr_bytes = 0;   // per tree: [nt][2] doubles
   int64_t sums_off = 0, sums_bytes = 0;   // per correlator: [nt][2] doubles

@@ -66,16 +66,28 @@ std::vector<std::vector<int64_t>> cut_waves(const Dag& d, const std::vector<int6
   return waves;
 }
 
+PlanTotals plan_totals(const Plan& p) {
+  const int64_t C = p.chunks();
+  return {C * (int64_t)p.steps.size(), p.halves() * p.peak_resident, C * p.n_evict, C * p.n_h2d,
+          C * p.h2d_bytes, C * p.n_d2h, C * p.d2h_bytes};
+}
+
 Plan make_plan(const Dag& d, const std::vector<int64_t>& order, const PlanOpts& o) {
   const int64_t n = d.n_nodes();
+  if (o.t_chunks < 1) throw Error(CDAG_E_INVALID, "t_chunks must be >= 1");
+  for (int64_t u = 0; u < n && o.t_chunks > 1; ++u)
+    if (d.nt[u] % o.t_chunks != 0)
+      throw Error(CDAG_E_INVALID, "t_chunks must divide the number of time slices of every tensor");
   Plan p;
   p.opts = o;
+  // one pass: tensors of nt / t_chunks slices in one half of the budget
+  const int64_t budget = o.t_chunks > 1 ? o.budget / 2 : o.budget;
   std::vector<int64_t> size(n);
-  for (int64_t u = 0; u < n; ++u) size[u] = d.size(u, o.elem_bytes);
+  for (int64_t u = 0; u < n; ++u) size[u] = p.tsize(d, u);
   if (o.leaves_resident)
     for (int64_t u = 0; u < d.n_leaves; ++u) size[u] = 0;
   if (o.batched) {
-    p.steps = cut_waves(d, order, size, o.budget, o.wave_max, o.lookahead);
+    p.steps = cut_waves(d, order, size, budget, o.wave_max, o.lookahead);
   } else {
     p.steps.reserve(order.size());
     for (int64_t c : order) p.steps.push_back({c});
@@ -132,7 +144,7 @@ Plan make_plan(const Dag& d, const std::vector<int64_t>& order, const PlanOpts& 
     // pinned residents are keyed by next use == s, below every other candidate
     for (int64_t x : operands)
       if (resident[x] && !(o.leaves_resident && d.is_leaf(x))) { cand_erase(x); cand_insert(x, s); }
-    while (used + need > o.budget) {
+    while (used + need > budget) {
       if (cand.empty()) throw Error(CDAG_E_BUDGET, "step " + std::to_string(s) + " does not fit in the budget");
       auto it = std::prev(cand.end());
       int64_t v = -std::get<2>(*it);
@@ -195,7 +207,8 @@ constexpr int64_t kAlign = 256;
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Best-fit allocator over [0, inf) that remembers, per free range, the last
-// compute step and the last copy step that touched the memory.
+// compute step that touched the memory and the last transfer that read it
+// (device ranges: a spill; host ranges: an upload).
 class Pool {
  public:
   struct Free { int64_t size, comp, copy; };
@@ -270,6 +283,7 @@ void place(const Dag& d, Plan& p) {
   p.leaf_off.assign(d.n_leaves, -1);
   int64_t base = 0;
   if (p.opts.leaves_resident) {
+    // whole leaves: every pass reads its own slices of them
     for (int64_t u = 0; u < d.n_leaves; ++u) {
       p.leaf_off[u] = base;
       base += align_up(d.size(u, eb));
@@ -277,19 +291,24 @@ void place(const Dag& d, Plan& p) {
   }
   p.leaf_region_bytes = base;
   Pool dev, host;
-  std::vector<int64_t> off(n, -1), hoff(n, -1), last_touch(n, -1);
+  // last_touch: step of the last kernels that read or wrote the tensor;
+  // spilled: step of the spill that wrote its host copy; uploaded: step of the
+  // last upload that read that host copy
+  std::vector<int64_t> off(n, -1), hoff(n, -1), last_touch(n, -1), spilled(n, -1), uploaded(n, -1);
   if (p.opts.leaves_resident)
     for (int64_t u = 0; u < d.n_leaves; ++u) off[u] = p.leaf_off[u];
   for (PlanRec& r : p.recs) {
-    const int64_t x = r.node, s = r.step, sz = d.size(x, eb);
+    const int64_t x = r.node, s = r.step, sz = p.tsize(d, x);
     switch (r.op) {
       case OP_D2H: {
-        int64_t c0, c1;
-        hoff[x] = host.alloc(sz, &c0, &c1);
+        int64_t c0, up;
+        hoff[x] = host.alloc(sz, &c0, &up);
         r.host_off = hoff[x];
         r.dev_off = off[x];
         r.wait_comp = last_touch[x];
+        r.wait_h2d = up;             // an upload still reading this host range
         dev.release(off[x] - base, sz, last_touch[x], s);
+        spilled[x] = s;
         off[x] = -1;
         break;
       }
@@ -299,18 +318,25 @@ void place(const Dag& d, Plan& p) {
         off[x] = -1;
         break;
       case OP_H2D: {
-        int64_t comp, copy;
-        off[x] = base + dev.alloc(sz, &comp, &copy);
+        int64_t comp, spill;
+        off[x] = base + dev.alloc(sz, &comp, &spill);
         r.dev_off = off[x];
-        r.host_off = d.is_leaf(x) ? -1 : hoff[x];
         r.wait_comp = comp;          // kernels that last touched this memory
+        if (d.is_leaf(x)) {
+          r.host_off = -1;
+          r.wait_d2h = spill;        // a spill still reading this memory
+        } else {
+          r.host_off = hoff[x];
+          r.wait_d2h = std::max(spill, spilled[x]);   // ... and the spill that wrote the host copy
+          uploaded[x] = s;
+        }
         break;
       }
       case OP_ALLOC: {
-        int64_t comp, copy;
-        off[x] = base + dev.alloc(sz, &comp, &copy);
+        int64_t comp, spill;
+        off[x] = base + dev.alloc(sz, &comp, &spill);
         r.dev_off = off[x];
-        r.wait_copy = copy;          // a D2H that last read this memory
+        r.wait_d2h = spill;          // a spill that last read this memory
         break;
       }
       case OP_EXEC:
@@ -325,8 +351,9 @@ void place(const Dag& d, Plan& p) {
         dev.release(off[x] - base, sz, s, -1);
         off[x] = -1;
         if (hoff[x] >= 0) {
-          host.release(hoff[x], sz, -1, -1);
+          host.release(hoff[x], sz, -1, uploaded[x]);
           hoff[x] = -1;
+          uploaded[x] = -1;
         }
         break;
     }

@@ -418,19 +418,43 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
 }
 
 // ------------------------------------------------------------------ split BF16
-// Each FP32 operand x is split as hi = bf16(x), lo = bf16(x - hi); a real
-// product is approximated by hi*hi' + hi*lo' + lo*hi' (the lo*lo' term is
-// dropped), accumulated in FP32 on the bf16 matrix cores.
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
+// Each FP32 operand x is split into P bf16 pieces by repeated rounding:
+// p0 = bf16(x), p1 = bf16(x - p0), p2 = bf16(x - p0 - p1) (each difference is
+// exact in FP32).  A piece is at most 2^-8 of the one before, so a real
+// product x y is approximated by the piece products p_i q_j with i + j < P:
+//   P = 2: hi*hi + hi*lo + lo*hi (three products; the dropped lo*lo and the
+//          remainders of the split leave up to ~3 * 2^-16 relative error);
+//   P = 3: the six products with i + j <= 2 (the dropped terms and the
+//          remainder are of order 2^-24, the FP32 rounding of the inputs).
+// The products accumulate in FP32 on the bf16 matrix cores, smallest first.
+template <int P>
+__device__ __forceinline__ void split_bf16(float x, __bf16 (&piece)[P]) {
+  float rest = x;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    piece[i] = (__bf16)rest;
+    rest -= (float)piece[i];
+  }
 }
 
-template <class TL, int ST, bool PF>
-__global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, const HecDesc* __restrict__ descs,
-                                                       int n_desc, int64_t n_items) {
+// Piece products kept for P pieces, smallest first: term t multiplies piece
+// term_x(t) of A by piece term_y(t) of B.
+template <int P> __device__ constexpr int n_terms() { return P == 2 ? 3 : 6; }
+template <int P> __device__ constexpr int term_x(int t) {
+  return P == 2 ? (t == 0 ? 1 : 0) : (t == 0 ? 2 : (t == 2 || t == 3) ? 1 : 0);
+}
+template <int P> __device__ constexpr int term_y(int t) {
+  return P == 2 ? (t == 1 ? 1 : 0) : (t == 1 ? 2 : (t == 2 || t == 4) ? 1 : 0);
+}
+
+template <class TL, int ST_, bool PF, int P>
+__global__ void __launch_bounds__(TL::NTH) hec_bf16(char* __restrict__ arena, const HecDesc* __restrict__ descs,
+                                                     int n_desc, int64_t n_items) {
   constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
   constexpr int BK = 32, PAD = BK + 8;     // bf16 per LDS row (16-byte aligned rows)
+  // Two stages of three pieces of the 128 x 64 tile would exceed the 160 KB of
+  // LDS; that variant keeps one stage (the arithmetic is the same either way).
+  constexpr int ST = (ST_ == 2 && 2 * 2 * P * (BM + BN) * PAD * 2 > 160 * 1024) ? 1 : ST_;
   // A: segments of 8 consecutive k of one row m.  B: segments of 8 consecutive
   // k of two adjacent columns n (consecutive lanes take consecutive column
   // pairs, so each of the 8 loads is coalesced), which become two 16-byte rows
@@ -438,9 +462,9 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
   constexpr int SEGA = 2 * BM * (BK / 8), SEGB = 2 * (BK / 8) * (BN / 2);
   constexpr int LA = (SEGA + NTH - 1) / NTH, LB = (SEGB + NTH - 1) / NTH;
   static_assert(BN % 2 == 0, "B column pairs");
-  // [stage][plane][hi/lo][row][k]: A rows are m, B rows are n (B is stored transposed)
-  __shared__ __attribute__((aligned(16))) __bf16 As[ST][2][2][BM][PAD];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[ST][2][2][BN][PAD];
+  // [stage][plane][piece][row][k]: A rows are m, B rows are n (B is stored transposed)
+  __shared__ __attribute__((aligned(16))) __bf16 As[ST][2][P][BM][PAD];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[ST][2][P][BN][PAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / TL::WGN, wn = wave % TL::WGN, li = lane & 15, lk = lane >> 4;
 
@@ -489,10 +513,10 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
         const int p = seg / (4 * BM), r = (seg % (4 * BM)) >> 2, qq = seg & 3;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-          __bf16 hi, lo;
-          split_bf16(ra[q][i], hi, lo);
-          As[st][p][0][r][8 * qq + i] = hi;
-          As[st][p][1][r][8 * qq + i] = lo;
+          __bf16 pc[P];
+          split_bf16<P>(ra[q][i], pc);
+#pragma unroll
+          for (int x = 0; x < P; ++x) As[st][p][x][r][8 * qq + i] = pc[x];
         }
       }
     }
@@ -504,16 +528,16 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
         const int g = rem / (BN / 2), cp = rem % (BN / 2);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          v8bf hi, lo;
+          v8bf pv[P];
 #pragma unroll
           for (int i = 0; i < 8; ++i) {
-            __bf16 h, l;
-            split_bf16(rb[q][i][c], h, l);
-            hi[i] = h;
-            lo[i] = l;
+            __bf16 pc[P];
+            split_bf16<P>(rb[q][i][c], pc);
+#pragma unroll
+            for (int x = 0; x < P; ++x) pv[x][i] = pc[x];
           }
-          *reinterpret_cast<v8bf*>(&Bs[st][p][0][2 * cp + c][8 * g]) = hi;
-          *reinterpret_cast<v8bf*>(&Bs[st][p][1][2 * cp + c][8 * g]) = lo;
+#pragma unroll
+          for (int x = 0; x < P; ++x) *reinterpret_cast<v8bf*>(&Bs[st][p][x][2 * cp + c][8 * g]) = pv[x];
         }
       }
     }
@@ -553,41 +577,48 @@ __global__ void __launch_bounds__(TL::NTH) hec_bf16x3(char* __restrict__ arena, 
       else if (PF && has_next)
         gload(nxt, nxt.kbeg);
       // one 16x16x32 step: lane holds k = 8*lk .. 8*lk+7 of row li (A) / column li (B)
-      v8bf a[TM][2][2], b[TN][2][2], bn_hi[TN], bn_lo[TN];   // [block][plane][hi/lo]
+      v8bf a[TM][2][P], b[TN][2][P], bn[TN][P];   // [block][plane][piece]; bn: pieces of -Bi
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-          for (int s = 0; s < 2; ++s)
-            a[i][p][s] = *reinterpret_cast<const v8bf*>(&As[st][p][s][(wm * TM + i) * 16 + li][8 * lk]);
+          for (int x = 0; x < P; ++x)
+            a[i][p][x] = *reinterpret_cast<const v8bf*>(&As[st][p][x][(wm * TM + i) * 16 + li][8 * lk]);
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-          for (int s = 0; s < 2; ++s)
-            b[j][p][s] = *reinterpret_cast<const v8bf*>(&Bs[st][p][s][(wn * TN + j) * 16 + li][8 * lk]);
+          for (int x = 0; x < P; ++x)
+            b[j][p][x] = *reinterpret_cast<const v8bf*>(&Bs[st][p][x][(wn * TN + j) * 16 + li][8 * lk]);
         // -Bi: flip the bf16 sign bits
-        v8s hs = *reinterpret_cast<v8s*>(&b[j][1][0]) ^ (short)0x8000;
-        v8s ls = *reinterpret_cast<v8s*>(&b[j][1][1]) ^ (short)0x8000;
-        bn_hi[j] = *reinterpret_cast<v8bf*>(&hs);
-        bn_lo[j] = *reinterpret_cast<v8bf*>(&ls);
+#pragma unroll
+        for (int x = 0; x < P; ++x) {
+          v8s sg = *reinterpret_cast<v8s*>(&b[j][1][x]) ^ (short)0x8000;
+          bn[j][x] = *reinterpret_cast<v8bf*>(&sg);
+        }
       }
-      // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br, each real product as
-      // lo*hi + hi*lo + hi*hi.  Term by term over all accumulators, so that
-      // consecutive instructions are independent; each accumulator adds its
-      // six terms in the same order.
-#define MM(acc, x, y) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, acc, 0, 0, 0)
+      // Re += Ar Br - Ai Bi ; Im += Ar Bi + Ai Br.  Each real product is the sum
+      // of the piece products (x, y) with x + y < P, smallest terms first:
+      // (1,0) (0,1) (0,0) for P = 2; (2,0) (0,2) (1,1) (1,0) (0,1) (0,0) for
+      // P = 3.  Term by term over all accumulators, so that consecutive
+      // instructions are independent; each accumulator adds its terms in the
+      // same order.
+#define MM(acc, u, v) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(u, v, acc, 0, 0, 0)
 #define TERM(CR_X, CR_Y, CI_X, CI_Y)            \
   _Pragma("unroll") for (int i = 0; i < TM; ++i) \
   _Pragma("unroll") for (int j = 0; j < TN; ++j) { MM(cr[i][j], CR_X, CR_Y); MM(ci[i][j], CI_X, CI_Y); }
-      TERM(a[i][0][1], b[j][0][0], a[i][0][1], b[j][1][0])
-      TERM(a[i][0][0], b[j][0][1], a[i][0][0], b[j][1][1])
-      TERM(a[i][0][0], b[j][0][0], a[i][0][0], b[j][1][0])
-      TERM(a[i][1][1], bn_hi[j], a[i][1][1], b[j][0][0])
-      TERM(a[i][1][0], bn_lo[j], a[i][1][0], b[j][0][1])
-      TERM(a[i][1][0], bn_hi[j], a[i][1][0], b[j][0][0])
+#pragma unroll
+      for (int t = 0; t < n_terms<P>(); ++t) {
+        const int x = term_x<P>(t), y = term_y<P>(t);
+        TERM(a[i][0][x], b[j][0][y], a[i][0][x], b[j][1][y])
+      }
+#pragma unroll
+      for (int t = 0; t < n_terms<P>(); ++t) {
+        const int x = term_x<P>(t), y = term_y<P>(t);
+        TERM(a[i][1][x], bn[j][y], a[i][1][x], b[j][0][y])
+      }
 #undef TERM
 #undef MM
       if (ST == 2 && c + 1 < nk) sstore(st ^ 1);
@@ -808,13 +839,12 @@ namespace {
 // Persistent launches: at most as many workgroups as can be resident at once
 // (compute units x occupancy of the kernel); each loops over work items with
 // a grid stride.  The occupancy query is made once per kernel.
-template <typename F>
-unsigned persistent_grid(F kernel, int block, int64_t items) {
+unsigned persistent_grid(const void* kernel, int block, int64_t items) {
   static std::mutex mu;
   static std::map<std::pair<const void*, int>, int> cache;   // (kernel, device) -> resident workgroups
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) dev = -1;
-  const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), dev);
+  const auto key = std::make_pair(kernel, dev);
   int resident;
   {
     std::lock_guard<std::mutex> lock(mu);
@@ -835,63 +865,74 @@ unsigned persistent_grid(F kernel, int block, int64_t items) {
 }
 constexpr int64_t kMaxGrid = 1 << 20;
 unsigned grid_for(int64_t items) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, kMaxGrid)); }
-}  // namespace
 
 template <class TL, int ST, bool PF>
-void launch_hec_kernel(int prec, unsigned grid, char* arena, const HecDesc* d, int n_desc, int64_t n_items,
-                       hipStream_t s) {
-  const dim3 block(TL::NTH);
-  if (prec == 0)
-    hipLaunchKernelGGL((hec_mfma<double, TL, ST, PF>), dim3(grid), block, 0, s, arena, d, n_desc, n_items);
-  else if (prec == 1)
-    hipLaunchKernelGGL((hec_mfma<float, TL, ST, PF>), dim3(grid), block, 0, s, arena, d, n_desc, n_items);
-  else
-    hipLaunchKernelGGL((hec_bf16x3<TL, ST, PF>), dim3(grid), block, 0, s, arena, d, n_desc, n_items);
+const void* hec_kernel(int prec) {
+  if (prec == 0) return reinterpret_cast<const void*>(&hec_mfma<double, TL, ST, PF>);
+  if (prec == 1) return reinterpret_cast<const void*>(&hec_mfma<float, TL, ST, PF>);
+  if (prec == 2) return reinterpret_cast<const void*>(&hec_bf16<TL, ST, PF, 2>);
+  return reinterpret_cast<const void*>(&hec_bf16<TL, ST, PF, 3>);
 }
 
 template <class TL, int ST>
-void launch_hec_tile(int prec, bool persistent, char* arena, const HecDesc* d, int n_desc, int64_t n_items,
-                     hipStream_t s) {
-  if (!persistent) {
-    launch_hec_kernel<TL, ST, false>(prec, grid_for(n_items), arena, d, n_desc, n_items, s);
-    return;
-  }
-  unsigned grid;
-  if (prec == 0)
-    grid = persistent_grid(hec_mfma<double, TL, ST, true>, TL::NTH, n_items);
-  else if (prec == 1)
-    grid = persistent_grid(hec_mfma<float, TL, ST, true>, TL::NTH, n_items);
-  else
-    grid = persistent_grid(hec_bf16x3<TL, ST, true>, TL::NTH, n_items);
-  launch_hec_kernel<TL, ST, true>(prec, grid, arena, d, n_desc, n_items, s);
+void hec_tile(KernelCall& k, int prec, bool persistent, int64_t n_items) {
+  k.fn = persistent ? hec_kernel<TL, ST, true>(prec) : hec_kernel<TL, ST, false>(prec);
+  k.block = TL::NTH;
+  k.grid = persistent ? persistent_grid(k.fn, TL::NTH, n_items) : grid_for(n_items);
 }
 
 template <int ST>
-void launch_hec_stages(int prec, int tile, bool persistent, char* arena, const HecDesc* d, int n_desc,
-                       int64_t n_items, hipStream_t s) {
+void hec_stages(KernelCall& k, int prec, int tile, bool persistent, int64_t n_items) {
   switch (tile) {
-    case 0: launch_hec_tile<Tile0, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    case 1: launch_hec_tile<Tile1, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    case 2: launch_hec_tile<Tile2, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    case 3: launch_hec_tile<Tile3, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    case 4: launch_hec_tile<Tile4, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
-    default: launch_hec_tile<Tile5, ST>(prec, persistent, arena, d, n_desc, n_items, s); break;
+    case 0: hec_tile<Tile0, ST>(k, prec, persistent, n_items); break;
+    case 1: hec_tile<Tile1, ST>(k, prec, persistent, n_items); break;
+    case 2: hec_tile<Tile2, ST>(k, prec, persistent, n_items); break;
+    case 3: hec_tile<Tile3, ST>(k, prec, persistent, n_items); break;
+    case 4: hec_tile<Tile4, ST>(k, prec, persistent, n_items); break;
+    default: hec_tile<Tile5, ST>(k, prec, persistent, n_items); break;
   }
+}
+
+void set_args(KernelCall& k, char* arena, const void* desc, int n_desc, int64_t n_items) {
+  k.arena = arena;
+  k.desc = desc;
+  k.n_desc = n_desc;
+  k.n_items = n_items;
+  k.n_args = 4;
+}
+}  // namespace
+
+void KernelCall::bind() {
+  args[0] = &arena;
+  args[1] = &desc;
+  if (n_args == 5) {
+    args[2] = &entries;
+    args[3] = &n_desc;
+    args[4] = nullptr;
+  } else {
+    args[2] = &n_desc;
+    args[3] = &n_items;
+  }
+}
+
+hipError_t launch(KernelCall& k, hipStream_t s) {
+  k.bind();
+  return hipLaunchKernel(k.fn, dim3(k.grid), dim3(k.block), k.args, 0, s);
 }
 
 // variant = tile + kNumTiles * (grid + 2 * stage_choice), stage_choice 0: two
 // LDS stages, 1: one; grid 0: persistent, 1: one workgroup per work item.
-hipError_t launch_hec(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
-                      hipStream_t s) {
-  if (variant < 0 || variant >= 4 * kNumTiles) return hipErrorInvalidValue;
-  const HecDesc* d = reinterpret_cast<const HecDesc*>(arena + desc_off);
+hipError_t hec_call(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
+                    KernelCall* k) {
+  if (variant < 0 || variant >= 4 * kNumTiles || prec < 0 || prec > 3) return hipErrorInvalidValue;
   const int tile = variant % kNumTiles;
   const bool persistent = (variant / kNumTiles) % 2 == 0;
   if (variant / (2 * kNumTiles) == 0)
-    launch_hec_stages<2>(prec, tile, persistent, arena, d, n_desc, n_items, s);
+    hec_stages<2>(*k, prec, tile, persistent, n_items);
   else
-    launch_hec_stages<1>(prec, tile, persistent, arena, d, n_desc, n_items, s);
-  return hipGetLastError();
+    hec_stages<1>(*k, prec, tile, persistent, n_items);
+  set_args(*k, arena, arena + desc_off, n_desc, n_items);
+  return hipSuccess;
 }
 
 static_assert(Tile0::BM == kTileShapes[0].bm && Tile0::BN == kTileShapes[0].bn && Tile0::NTH == kTileShapes[0].nth, "tile 0");
@@ -901,31 +942,57 @@ static_assert(Tile3::BM == kTileShapes[3].bm && Tile3::BN == kTileShapes[3].bn &
 static_assert(Tile4::BM == kTileShapes[4].bm && Tile4::BN == kTileShapes[4].bn && Tile4::NTH == kTileShapes[4].nth, "tile 4");
 static_assert(Tile5::BM == kTileShapes[5].bm && Tile5::BN == kTileShapes[5].bn && Tile5::NTH == kTileShapes[5].nth, "tile 5");
 
+hipError_t reduce_call(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, KernelCall* k) {
+  k->fn = prec == 0 ? reinterpret_cast<const void*>(&splitk_reduce<double>)
+                    : reinterpret_cast<const void*>(&splitk_reduce<float>);
+  k->grid = grid_for(n_items);
+  k->block = 256;
+  set_args(*k, arena, arena + desc_off, n_desc, n_items);
+  return hipSuccess;
+}
+
+hipError_t hca_call(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, KernelCall* k) {
+  k->fn = prec == 0 ? reinterpret_cast<const void*>(&hca_trace<double>)
+                    : reinterpret_cast<const void*>(&hca_trace<float>);
+  k->grid = grid_for((n_items + 3) / 4);
+  k->block = 256;
+  set_args(*k, arena, arena + desc_off, n_desc, n_items);
+  return hipSuccess;
+}
+
+hipError_t xsum_call(char* arena, int64_t desc_off, int64_t entries_off, int n_desc, KernelCall* k) {
+  k->fn = reinterpret_cast<const void*>(&xsum_kernel);
+  k->grid = grid_for(n_desc);
+  k->block = 256;
+  set_args(*k, arena, arena + desc_off, n_desc, 0);
+  k->entries = arena + entries_off;
+  k->n_args = 5;
+  return hipSuccess;
+}
+
+hipError_t launch_hec(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
+                      hipStream_t s) {
+  KernelCall k;
+  hipError_t e = hec_call(prec, variant, arena, desc_off, n_desc, n_items, &k);
+  return e != hipSuccess ? e : launch(k, s);
+}
+
 hipError_t launch_reduce(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s) {
-  const RedDesc* d = reinterpret_cast<const RedDesc*>(arena + desc_off);
-  if (prec == 0)
-    hipLaunchKernelGGL(splitk_reduce<double>, dim3(grid_for(n_items)), dim3(256), 0, s, arena, d, n_desc, n_items);
-  else
-    hipLaunchKernelGGL(splitk_reduce<float>, dim3(grid_for(n_items)), dim3(256), 0, s, arena, d, n_desc, n_items);
-  return hipGetLastError();
+  KernelCall k;
+  reduce_call(prec, arena, desc_off, n_desc, n_items, &k);
+  return launch(k, s);
 }
 
 hipError_t launch_hca(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s) {
-  const HcaDesc* d = reinterpret_cast<const HcaDesc*>(arena + desc_off);
-  if (prec == 0)
-    hipLaunchKernelGGL(hca_trace<double>, dim3(grid_for((n_items + 3) / 4)), dim3(256), 0, s, arena, d, n_desc,
-                       n_items);
-  else
-    hipLaunchKernelGGL(hca_trace<float>, dim3(grid_for((n_items + 3) / 4)), dim3(256), 0, s, arena, d, n_desc,
-                       n_items);
-  return hipGetLastError();
+  KernelCall k;
+  hca_call(prec, arena, desc_off, n_desc, n_items, &k);
+  return launch(k, s);
 }
 
 hipError_t launch_xsum(char* arena, int64_t desc_off, int64_t entries_off, int n_desc, hipStream_t s) {
-  const XsumDesc* d = reinterpret_cast<const XsumDesc*>(arena + desc_off);
-  const XsumEntry* e = reinterpret_cast<const XsumEntry*>(arena + entries_off);
-  hipLaunchKernelGGL(xsum_kernel, dim3(grid_for(n_desc)), dim3(256), 0, s, arena, d, e, n_desc);
-  return hipGetLastError();
+  KernelCall k;
+  xsum_call(arena, desc_off, entries_off, n_desc, &k);
+  return launch(k, s);
 }
 
 }  // namespace cdag

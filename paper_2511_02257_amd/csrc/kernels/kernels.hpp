@@ -1,10 +1,36 @@
 // Launchers of the HIP kernels (kernels.hip).  Every launcher takes the arena
-// base and arena-relative descriptor offsets; prec: 0 FP64, 1 FP32, 2 split-BF16.
+// base and arena-relative descriptor offsets; prec: 0 FP64, 1 FP32, 2 split-BF16
+// (two pieces), 3 split-BF16 (three pieces).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace cdag {
+
+// One kernel launch as a function and its arguments, so that it can be
+// launched on a stream or added to a graph as a kernel node.  Every kernel
+// takes (arena, descriptors, n_desc, n_items); the cross sum takes (arena,
+// descriptors, entries, n_desc).  bind() points args at the fields; a copied
+// KernelCall must be bound again.
+struct KernelCall {
+  const void* fn = nullptr;
+  unsigned grid = 1, block = 1;
+  char* arena = nullptr;
+  const void* desc = nullptr;
+  const void* entries = nullptr;
+  int n_desc = 0;
+  int64_t n_items = 0;
+  int n_args = 4;
+  void* args[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  void bind();
+};
+hipError_t launch(KernelCall& k, hipStream_t s);
+
+hipError_t hec_call(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
+                    KernelCall* k);
+hipError_t reduce_call(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, KernelCall* k);
+hipError_t hca_call(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, KernelCall* k);
+hipError_t xsum_call(char* arena, int64_t desc_off, int64_t entries_off, int n_desc, KernelCall* k);
 
 hipError_t launch_hec(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
                       hipStream_t s);

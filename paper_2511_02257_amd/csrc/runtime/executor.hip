@@ -1,17 +1,25 @@
 // Device runtime: leaf staging in pinned host memory, the arena borrowed from
-// the caller, and execution of a placed plan on two HIP streams.
+// the caller, and execution of a placed plan on three HIP streams.
 //
-// Eager execution: per step s the copy stream performs the step's spills
-// (D2H) and uploads (H2D) and records ev_copy[s]; the compute stream waits for
-// it when the step uploaded operands (or when an output reuses memory a spill
-// was still reading), launches the step's kernels and records ev_comp[s].  A
-// copy into memory that kernels last touched at step k first waits for
-// ev_comp[k].  All waits come from the plan (place()), so copies overlap
-// kernels of earlier steps whenever the memory they use is already free.
-// Graph replay: steps are captured in segments with transfers and kernels on
-// one stream, so the stream order alone carries every dependency.  The eager
-// walk can also be recorded instead of issued (trace_execute), so that its
-// ordering can be checked on a host without a GPU.
+// Eager execution: per step s the spill stream copies the step's evicted
+// intermediates to the host (D2H) and records ev_d2h[s]; the upload stream
+// copies its missing operands in (H2D) and records ev_h2d[s]; the compute
+// stream waits for the uploads of the step (and, where an output reuses
+// memory a spill was still reading, for that spill), launches the step's
+// kernels and records ev_comp[s].  A transfer into memory that kernels last
+// touched at step k first waits for ev_comp[k]; an upload into memory a spill
+// was reading, or of a tensor a spill wrote out, waits for that spill; a
+// spill into host memory an upload was reading waits for that upload.  All
+// waits come from the plan (place()), so uploads, spills and kernels overlap
+// whenever the memory they use is already free.
+// Time-slice passes (t_chunks > 1) repeat the plan on slices of every tensor,
+// alternating between two halves of the memory; a pass waits for the one two
+// before it (same half) to be done with that half.
+// Graph replay: the same walk captured on one stream (segments of steps, the
+// stream order carries every dependency), or added to one graph node by node
+// with the walk's waits as explicit edges (no capture).  The eager walk can also be
+// recorded instead of issued (trace_execute), so that its ordering can be
+// checked on a host without a GPU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,17 +52,21 @@ inline void ignore(hipError_t) {}
 double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
+
+// Stream roles; trace records and event ids use these numbers.
+enum StreamRole : int { S_COMP = 0, S_H2D = 1, S_D2H = 2, kStreams = 3 };
 }  // namespace
 
 struct Device {
   int device = -1;
-  hipStream_t comp = nullptr, copy = nullptr;
+  hipStream_t comp = nullptr, copy = nullptr;   // borrowed: kernels, uploads
+  hipStream_t spill_s = nullptr;                // owned: spills to the host
   char* arena = nullptr;
   uint64_t arena_bytes = 0;
   uint64_t arena_epoch = 0;                 // bumped when the arena is rebound
   // pinned staging of leaves in device layout, per precision mode
-  std::vector<void*> stage[3];
-  uint64_t stage_version[3] = {0, 0, 0};
+  std::vector<void*> stage[4];
+  uint64_t stage_version[4] = {0, 0, 0, 0};
   // host spill pool: pinned, or pageable when a pinned allocation of the
   // plan's size fails (then steps run eagerly, without captured segments)
   void* spill = nullptr;
@@ -63,17 +75,21 @@ struct Device {
   // pinned result buffer
   void* results = nullptr;
   int64_t results_bytes = 0;
-  std::vector<hipEvent_t> ev_comp, ev_copy;
+  // per step of every pass and per stream role; then per pass, the pass-end
+  // events of the three streams
+  std::vector<hipEvent_t> ev[kStreams], ev_end[kStreams];
   hipEvent_t t0 = nullptr, t1 = nullptr;
   // what is currently uploaded
   uint64_t blob_key = 0, blob_epoch = 0;
   int resident_prec = -1;
   uint64_t resident_key = 0, resident_epoch = 0;
   // captured step sequence: one graph per segment of consecutive steps
-  hipStream_t cap_comp = nullptr;   // stream the segments are captured on
+  hipStream_t cap = nullptr;        // stream the one-stream segments are captured on
+  hipEvent_t ev_join[2] = {nullptr, nullptr};
   std::vector<hipGraph_t> seg_graph;
   std::vector<hipGraphExec_t> seg_exec;
   uint64_t graph_key = 0, graph_epoch = 0, graph_stage = 0;
+  int graph_mode = 0;
   void* graph_spill = nullptr;
 
   void drop_graphs() {
@@ -107,12 +123,17 @@ struct Device {
   ~Device() {
     if (device >= 0) ignore(hipSetDevice(device));
     drop_graphs();
-    if (cap_comp) ignore(hipStreamDestroy(cap_comp));
-    for (auto e : ev_comp) ignore(hipEventDestroy(e));
-    for (auto e : ev_copy) ignore(hipEventDestroy(e));
+    if (cap) ignore(hipStreamDestroy(cap));
+    if (spill_s) ignore(hipStreamDestroy(spill_s));
+    for (int r = 0; r < kStreams; ++r) {
+      for (auto e : ev[r]) ignore(hipEventDestroy(e));
+      for (auto e : ev_end[r]) ignore(hipEventDestroy(e));
+    }
     for (auto e : tpool) ignore(hipEventDestroy(e));
     if (t0) ignore(hipEventDestroy(t0));
     if (t1) ignore(hipEventDestroy(t1));
+    for (auto e : ev_join)
+      if (e) ignore(hipEventDestroy(e));
     for (auto& v : stage)
       for (void* p : v)
         if (p) ignore(hipHostFree(p));
@@ -144,9 +165,12 @@ void device_bind(Ctx& c, int device, void* compute_stream, void* copy_stream) {
   c.dev->comp = (hipStream_t)compute_stream;
   c.dev->copy = (hipStream_t)copy_stream;
   if (!c.dev->t0) {
+    // library-owned streams keep the default priority
     HIPC(hipEventCreate(&c.dev->t0));
     HIPC(hipEventCreate(&c.dev->t1));
-    HIPC(hipStreamCreateWithFlags(&c.dev->cap_comp, hipStreamNonBlocking));
+    for (auto& e : c.dev->ev_join) HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPC(hipStreamCreateWithFlags(&c.dev->spill_s, hipStreamNonBlocking));
+    HIPC(hipStreamCreateWithFlags(&c.dev->cap, hipStreamNonBlocking));
   }
 }
 
@@ -203,16 +227,16 @@ void ensure_stage(Ctx& c, int prec) {
   D.stage_version[prec] = c.data_version;
 }
 
-void ensure_events(Device& D, size_t n) {
-  while (D.ev_comp.size() < n) {
-    hipEvent_t e;
-    HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    D.ev_comp.push_back(e);
-  }
-  while (D.ev_copy.size() < n) {
-    hipEvent_t e;
-    HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    D.ev_copy.push_back(e);
+void ensure_events(Device& D, size_t steps, size_t passes) {
+  for (int r = 0; r < kStreams; ++r) {
+    for (auto* v : {&D.ev[r], &D.ev_end[r]}) {
+      const size_t n = v == &D.ev[r] ? steps : passes;
+      while (v->size() < n) {
+        hipEvent_t e;
+        HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        v->push_back(e);
+      }
+    }
   }
 }
 
@@ -241,26 +265,33 @@ void ensure_pinned(void*& p, int64_t& have, int64_t need_bytes) {
   have = need_bytes;
 }
 
-hipError_t launch_one(const Launch& L, int prec, char* arena, hipStream_t st) {
+hipError_t call_of(const Launch& L, int prec, char* arena, KernelCall* k) {
   switch (L.type) {
-    case L_HEC: return launch_hec(prec, L.tile, arena, L.desc_off, L.n_desc, L.n_items, st);
-    case L_RED: return launch_reduce(prec, arena, L.desc_off, L.n_desc, L.n_items, st);
-    case L_HCA: return launch_hca(prec, arena, L.desc_off, L.n_desc, L.n_items, st);
+    case L_HEC: return hec_call(prec, L.tile, arena, L.desc_off, L.n_desc, L.n_items, k);
+    case L_RED: return reduce_call(prec, arena, L.desc_off, L.n_desc, L.n_items, k);
+    case L_HCA: return hca_call(prec, arena, L.desc_off, L.n_desc, L.n_items, k);
     default: throw Error(CDAG_E_STATE, "bad launch type");
   }
 }
 
-// Kernels of step s; with `timed`, every launch is bracketed by an event pair.
-int64_t launch_step(const KernelPlan& kp, int64_t s, int prec, char* arena, hipStream_t st, Device* timed) {
+hipError_t launch_one(const Launch& L, int prec, char* arena, hipStream_t st) {
+  KernelCall k;
+  const hipError_t e = call_of(L, prec, arena, &k);
+  return e != hipSuccess ? e : launch(k, st);
+}
+
+// Kernels of global step g; with `timed`, every launch is bracketed by an
+// event pair.
+int64_t launch_step(const KernelPlan& kp, int64_t g, int prec, char* arena, hipStream_t st, Device* timed) {
   int64_t n = 0;
-  for (int64_t li = kp.launch_off[s]; li < kp.launch_off[s + 1]; ++li) {
+  for (int64_t li = kp.launch_off[g]; li < kp.launch_off[g + 1]; ++li) {
     const Launch& L = kp.launches[li];
     if (timed) {
       hipEvent_t a = timed->timing_event(), b = timed->timing_event();
       HIPC(hipEventRecord(a, st));
       HIPC(launch_one(L, prec, arena, st));
       HIPC(hipEventRecord(b, st));
-      timed->tpairs.push_back({li, 0, 0, s, 0.0, a, b});
+      timed->tpairs.push_back({li, 0, 0, g, 0.0, a, b});
     } else {
       HIPC(launch_one(L, prec, arena, st));
     }
@@ -269,98 +300,150 @@ int64_t launch_step(const KernelPlan& kp, int64_t s, int prec, char* arena, hipS
   return n;
 }
 
-// Walk steps [s0, s1): each step's copies (with waits for the compute work
-// that last used their memory), then its kernels (after waiting for the copies
-// they need), with cross-stream waits from the plan.  With one_stream (how
-// segments are captured) every dependency is the stream order and no event is
-// used.  In a captured segment, waits on steps before s0 are left out: the
-// segments' graphs run one after another on one stream, so everything before
-// s0 has finished when the segment starts.  Ops issues the work (HipOps) or
-// records it (TraceOps).
+// Where pass k of a time-chunked execution keeps its data: the tensor pool and
+// workspace of half k % 2 of the arena, half k % 2 of the host spill pool, and
+// slices [k nt / C, (k + 1) nt / C) of every tensor (bytes(u) per pass).
+struct PassMap {
+  const Ctx& c;
+  int64_t k, dev_shift, host_shift;
+  PassMap(const Ctx& ctx, int64_t pass)
+      : c(ctx), k(pass), dev_shift((pass % 2) * ctx.kplan.half_bytes),
+        host_shift((pass % 2) * ctx.plan.host_spill_bytes) {}
+  int64_t bytes(int64_t u) const { return c.plan.tsize(c.dag, u); }
+  int64_t dev(int64_t off) const { return off + dev_shift; }
+  int64_t host(int64_t off) const { return off + host_shift; }
+  int64_t stage(int64_t u) const { return k * bytes(u); }   // in the leaf's staging buffer
+  // arena offset of operand x planned at `planned`: a resident leaf's slices of
+  // this pass, else the planned offset in the pass's half
+  int64_t operand(int64_t x, int64_t planned) const {
+    if (c.plan.opts.leaves_resident && c.dag.is_leaf(x)) return c.plan.leaf_off[x] + k * bytes(x);
+    return dev(planned);
+  }
+};
+
+// Walk global steps [g0, g1), g = k * S + s being step s of pass k: each
+// step's spills (after the kernels that last touched the tensor and any upload
+// still reading the host range), its uploads (after the kernels and spills
+// that last used the arena range, and the spill that wrote a re-uploaded
+// tensor), then its kernels (after the step's uploads and any spill still
+// reading an output's memory).  With one_stream (how one-stream segments are
+// captured) every dependency is the stream order and no event is used.  In a
+// captured segment, waits on steps before g0 are left out: the segments' graphs
+// run one after another on one stream, so everything before g0 has finished
+// when the segment starts.  Ops issues the work (HipOps) or records it
+// (TraceOps).
 template <class Ops>
-int64_t walk_steps(const Ctx& c, int prec, int64_t s0, int64_t s1, bool one_stream, bool in_capture, Ops& ops) {
+int64_t walk_steps(const Ctx& c, int64_t g0, int64_t g1, bool one_stream, bool in_capture, Ops& ops) {
   const Plan& p = c.plan;
-  const int eb = prec == CDAG_FP64 ? 16 : 8;
-  int64_t copy_waited = in_capture ? s0 - 1 : -1, comp_waited = in_capture ? s0 - 1 : -1;
+  const int64_t S = (int64_t)p.steps.size(), C = p.chunks();
+  // waited[to][from]: newest step of stream `from` that stream `to` has waited
+  // for; events of one stream complete in step order, so older ones are implied
+  int64_t waited[kStreams][kStreams];
+  for (auto& row : waited)
+    for (auto& x : row) x = in_capture ? g0 - 1 : -1;
+  auto wait = [&](int to, int from, int64_t g) {
+    if (one_stream || g < 0 || g <= waited[to][from]) return;
+    ops.wait(to, from, g, g);
+    waited[to][from] = g;
+  };
   int64_t n_launch = 0;
-  for (int64_t s = s0; s < s1; ++s) {
-    bool any_copy = false, any_h2d = false;
-    int64_t need_copy = -1;
+  for (int64_t g = g0; g < g1; ++g) {
+    const int64_t k = g / S, s = g % S, kS = k * S;
+    const PassMap m(c, k);
+    auto at = [&](int64_t step) { return step >= 0 ? kS + step : -1; };
+    if (s == 0 && k >= 2 && !one_stream && !(in_capture && (k - 1) * S <= g0)) {
+      // pass k - 2 used the same half of the arena and of the spill pool
+      ops.wait_pass(S_H2D, S_COMP, k - 2, g);
+      ops.wait_pass(S_H2D, S_D2H, k - 2, g);
+      ops.wait_pass(S_D2H, S_H2D, k - 2, g);
+      ops.wait_pass(S_COMP, S_D2H, k - 2, g);
+    }
+    bool any_d2h = false, any_h2d = false;
+    int64_t alloc_d2h = -1;
     for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
       const PlanRec& r = p.recs[ri];
-      if (r.op == OP_D2H || r.op == OP_H2D) {
-        if (!one_stream && r.wait_comp > copy_waited) {
-          ops.copy_waits_for_compute(r.wait_comp, s);
-          copy_waited = r.wait_comp;
-        }
-        ops.transfer(r, c.dag.size(r.node, eb), s);
-        any_h2d |= r.op == OP_H2D;
-        any_copy = true;
-      } else if (r.op == OP_ALLOC && r.wait_copy >= 0) {
-        need_copy = std::max(need_copy, r.wait_copy);
+      if (r.op != OP_D2H) continue;
+      wait(S_D2H, S_COMP, at(r.wait_comp));
+      wait(S_D2H, S_H2D, at(r.wait_h2d));
+      ops.transfer(r, m, g);
+      any_d2h = true;
+    }
+    if (any_d2h && !one_stream) ops.record(S_D2H, g);
+    for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
+      const PlanRec& r = p.recs[ri];
+      if (r.op == OP_H2D) {
+        wait(S_H2D, S_COMP, at(r.wait_comp));
+        wait(S_H2D, S_D2H, at(r.wait_d2h));
+        ops.transfer(r, m, g);
+        any_h2d = true;
+      } else if (r.op == OP_ALLOC) {
+        alloc_d2h = std::max(alloc_d2h, at(r.wait_d2h));
       }
     }
+    if (any_h2d && !one_stream) ops.record(S_H2D, g);
+    if (any_h2d) wait(S_COMP, S_H2D, g);
+    wait(S_COMP, S_D2H, alloc_d2h);
+    n_launch += ops.launch(g, m);
     if (!one_stream) {
-      if (any_copy) ops.record_copy(s);
-      if (any_h2d) need_copy = std::max(need_copy, s);
-      if (need_copy > comp_waited) {
-        ops.compute_waits_for_copy(need_copy, s);
-        comp_waited = need_copy;
-      }
+      ops.record(S_COMP, g);
+      if (s == S - 1 && k + 2 < C)
+        for (int r = 0; r < kStreams; ++r) ops.record_pass(r, k, g);
     }
-    n_launch += ops.launch(s);
-    if (!one_stream) ops.record_compute(s);
   }
   return n_launch;
 }
 
-// The issuing form: transfers on copy_s, kernels on comp_s, the device's
-// events ev_comp[s] / ev_copy[s] of step s.
+// The issuing form: kernels on st[S_COMP], uploads on st[S_H2D], spills on
+// st[S_D2H], with the device's per-step and per-pass events.
 struct HipOps {
   const Ctx& c;
   Device& D;
   int prec;
-  hipStream_t comp_s, copy_s;
+  hipStream_t st[kStreams];
   Device* timed;
 
-  void copy_waits_for_compute(int64_t step, int64_t) { HIPC(hipStreamWaitEvent(copy_s, D.ev_comp[step], 0)); }
-  void compute_waits_for_copy(int64_t step, int64_t) { HIPC(hipStreamWaitEvent(comp_s, D.ev_copy[step], 0)); }
-  void record_copy(int64_t s) { HIPC(hipEventRecord(D.ev_copy[s], copy_s)); }
-  void record_compute(int64_t s) { HIPC(hipEventRecord(D.ev_comp[s], comp_s)); }
-  int64_t launch(int64_t s) { return launch_step(c.kplan, s, prec, D.arena, comp_s, timed); }
-  void transfer(const PlanRec& r, int64_t bytes, int64_t s) {
-    const size_t sz = (size_t)bytes;
+  void wait(int to, int from, int64_t g, int64_t) { HIPC(hipStreamWaitEvent(st[to], D.ev[from][g], 0)); }
+  void record(int r, int64_t g) { HIPC(hipEventRecord(D.ev[r][g], st[r])); }
+  void wait_pass(int to, int from, int64_t k, int64_t) { HIPC(hipStreamWaitEvent(st[to], D.ev_end[from][k], 0)); }
+  void record_pass(int r, int64_t k, int64_t) { HIPC(hipEventRecord(D.ev_end[r][k], st[r])); }
+  int64_t launch(int64_t g, const PassMap&) { return launch_step(c.kplan, g, prec, D.arena, st[S_COMP], timed); }
+  void transfer(const PlanRec& r, const PassMap& m, int64_t g) {
+    const size_t sz = (size_t)m.bytes(r.node);
+    hipStream_t cs = st[r.op == OP_D2H ? S_D2H : S_H2D];
     hipEvent_t ta = nullptr, tb = nullptr;
     if (timed) {
       ta = timed->timing_event();
       tb = timed->timing_event();
-      HIPC(hipEventRecord(ta, copy_s));
+      HIPC(hipEventRecord(ta, cs));
     }
+    char* spill = (char*)D.spill;
     if (r.op == OP_D2H) {
-      HIPC(hipMemcpyAsync((char*)D.spill + r.host_off, D.arena + r.dev_off, sz, hipMemcpyDeviceToHost, copy_s));
+      HIPC(hipMemcpyAsync(spill + m.host(r.host_off), D.arena + m.dev(r.dev_off), sz, hipMemcpyDeviceToHost, cs));
     } else {
-      const void* src = c.dag.is_leaf(r.node) ? D.stage[prec][r.node] : (const void*)((char*)D.spill + r.host_off);
-      HIPC(hipMemcpyAsync(D.arena + r.dev_off, src, sz, hipMemcpyHostToDevice, copy_s));
+      const void* src = c.dag.is_leaf(r.node) ? (const void*)((const char*)D.stage[prec][r.node] + m.stage(r.node))
+                                              : (const void*)(spill + m.host(r.host_off));
+      HIPC(hipMemcpyAsync(D.arena + m.dev(r.dev_off), src, sz, hipMemcpyHostToDevice, cs));
     }
     if (timed) {
-      HIPC(hipEventRecord(tb, copy_s));
-      const int32_t k = c.dag.kind[r.node];
+      HIPC(hipEventRecord(tb, cs));
+      const int32_t kd = c.dag.kind[r.node];
       timed->tpairs.push_back({-2, r.op == OP_D2H ? CDAG_LAUNCH_D2H : CDAG_LAUNCH_H2D,
-                               k >= 0 ? (1 << k) : 0, s, (double)sz, ta, tb});
+                               kd >= 0 ? (1 << kd) : 0, g, (double)sz, ta, tb});
     }
   }
 };
 
-int64_t issue_steps(Ctx& c, Device& D, int prec, int64_t s0, int64_t s1, hipStream_t comp, hipStream_t copy,
-                    Device* timed, bool in_capture) {
-  HipOps ops{c, D, prec, comp, copy, timed};
-  return walk_steps(c, prec, s0, s1, copy == comp, in_capture, ops);
+int64_t issue_steps(Ctx& c, Device& D, int prec, int64_t g0, int64_t g1, hipStream_t comp, hipStream_t h2d,
+                    hipStream_t d2h, Device* timed, bool in_capture) {
+  HipOps ops{c, D, prec, {comp, h2d, d2h}, timed};
+  return walk_steps(c, g0, g1, comp == h2d, in_capture, ops);
 }
 
 // The recording form: the same walk with no HIP call, writing what each stream
 // would do (event records and waits, and the byte ranges that every transfer
-// and every step's kernels read and write).  fail_at >= 0 throws at that
-// record, as a failed HIP call would.
+// and every step's kernels read and write).  Event ids: kStreams * g + stream
+// for the step events, kStreams * (passes * S + k) + stream for the pass-end
+// events.  fail_at >= 0 throws at that record, as a failed HIP call would.
 struct TraceOps {
   const Ctx& c;
   int prec;
@@ -381,13 +464,16 @@ struct TraceOps {
     r.seq = r.node = r.event = -1;
     return r;
   }
-  void event(int32_t op, int32_t stream, int64_t ev_step, int32_t ev_stream, int64_t s) {
-    cdag_trace_rec r = blank(op, stream, s);
-    r.event = 2 * ev_step + ev_stream;
+  int64_t pass_event(int64_t k, int r) const {
+    return kStreams * (c.plan.chunks() * (int64_t)c.plan.steps.size() + k) + r;
+  }
+  void event(int32_t op, int32_t stream, int64_t id, int64_t g) {
+    cdag_trace_rec r = blank(op, stream, g);
+    r.event = id;
     put(r);
   }
-  void access(int32_t op, int32_t stream, int64_t s, int64_t node, int32_t space, int64_t off, int64_t bytes) {
-    cdag_trace_rec r = blank(op, stream, s);
+  void access(int32_t op, int32_t stream, int64_t g, int64_t node, int32_t space, int64_t off, int64_t bytes) {
+    cdag_trace_rec r = blank(op, stream, g);
     r.seq = seq;
     r.node = node;
     r.space = space;
@@ -395,39 +481,131 @@ struct TraceOps {
     r.bytes = bytes;
     put(r);
   }
-  void copy_waits_for_compute(int64_t step, int64_t s) { event(CDAG_TR_WAIT, 1, step, 0, s); }
-  void compute_waits_for_copy(int64_t step, int64_t s) { event(CDAG_TR_WAIT, 0, step, 1, s); }
-  void record_copy(int64_t s) { event(CDAG_TR_RECORD, 1, s, 1, s); }
-  void record_compute(int64_t s) { event(CDAG_TR_RECORD, 0, s, 0, s); }
-  void transfer(const PlanRec& r, int64_t bytes, int64_t s) {
+  void wait(int to, int from, int64_t ev_g, int64_t g) { event(CDAG_TR_WAIT, to, kStreams * ev_g + from, g); }
+  void record(int r, int64_t g) { event(CDAG_TR_RECORD, r, kStreams * g + r, g); }
+  void wait_pass(int to, int from, int64_t k, int64_t g) { event(CDAG_TR_WAIT, to, pass_event(k, from), g); }
+  void record_pass(int r, int64_t k, int64_t g) { event(CDAG_TR_RECORD, r, pass_event(k, r), g); }
+  void transfer(const PlanRec& r, const PassMap& m, int64_t g) {
+    const int64_t bytes = m.bytes(r.node);
     if (r.op == OP_D2H) {
-      access(CDAG_TR_READ, 1, s, r.node, CDAG_SPACE_ARENA, r.dev_off, bytes);
-      access(CDAG_TR_WRITE, 1, s, r.node, CDAG_SPACE_SPILL, r.host_off, bytes);
+      access(CDAG_TR_READ, S_D2H, g, r.node, CDAG_SPACE_ARENA, m.dev(r.dev_off), bytes);
+      access(CDAG_TR_WRITE, S_D2H, g, r.node, CDAG_SPACE_SPILL, m.host(r.host_off), bytes);
     } else {
-      if (c.dag.is_leaf(r.node)) access(CDAG_TR_READ, 1, s, r.node, CDAG_SPACE_STAGE, 0, bytes);
-      else access(CDAG_TR_READ, 1, s, r.node, CDAG_SPACE_SPILL, r.host_off, bytes);
-      access(CDAG_TR_WRITE, 1, s, r.node, CDAG_SPACE_ARENA, r.dev_off, bytes);
+      if (c.dag.is_leaf(r.node)) access(CDAG_TR_READ, S_H2D, g, r.node, CDAG_SPACE_STAGE, m.stage(r.node), bytes);
+      else access(CDAG_TR_READ, S_H2D, g, r.node, CDAG_SPACE_SPILL, m.host(r.host_off), bytes);
+      access(CDAG_TR_WRITE, S_H2D, g, r.node, CDAG_SPACE_ARENA, m.dev(r.dev_off), bytes);
     }
     ++seq;
   }
-  int64_t launch(int64_t s) {
+  int64_t launch(int64_t g, const PassMap& m) {
     const Plan& p = c.plan;
-    const int eb = prec == CDAG_FP64 ? 16 : 8;
+    const int64_t S = (int64_t)p.steps.size(), s = g % S;
     for (int64_t ri = p.rec_off[s]; ri < p.rec_off[s + 1]; ++ri) {
       const PlanRec& r = p.recs[ri];
       if (r.op != OP_EXEC) continue;
       const int64_t* ch = c.dag.children_begin(r.node);
-      access(CDAG_TR_READ, 0, s, ch[0], CDAG_SPACE_ARENA, r.a_off, c.dag.size(ch[0], eb));
-      access(CDAG_TR_READ, 0, s, ch[1], CDAG_SPACE_ARENA, r.b_off, c.dag.size(ch[1], eb));
+      access(CDAG_TR_READ, S_COMP, g, ch[0], CDAG_SPACE_ARENA, m.operand(ch[0], r.a_off), m.bytes(ch[0]));
+      access(CDAG_TR_READ, S_COMP, g, ch[1], CDAG_SPACE_ARENA, m.operand(ch[1], r.b_off), m.bytes(ch[1]));
       if (c.dag.kind[r.node] != HCA)
-        access(CDAG_TR_WRITE, 0, s, r.node, CDAG_SPACE_ARENA, r.dev_off, c.dag.size(r.node, eb));
+        access(CDAG_TR_WRITE, S_COMP, g, r.node, CDAG_SPACE_ARENA, m.dev(r.dev_off), m.bytes(r.node));
     }
     ++seq;
-    return c.kplan.launch_off[s + 1] - c.kplan.launch_off[s];
+    return c.kplan.launch_off[g + 1] - c.kplan.launch_off[g];
   }
 };
 
-constexpr int64_t kSegmentSteps = 64;   // steps per captured graph when transfers are present
+// The graph form: the same walk adding the transfers and kernels to a HIP
+// graph as nodes with explicit dependencies (no stream capture).  A node
+// depends on the previous node of its stream and on the nodes its stream
+// waited for since; an event stands for its stream's last node (joined with
+// that stream's pending waits) at the time it is recorded.
+struct GraphOps {
+  const Ctx& c;
+  Device& D;
+  int prec;
+  hipGraph_t graph;
+  hipGraphNode_t last[kStreams] = {nullptr, nullptr, nullptr};
+  std::vector<hipGraphNode_t> pending[kStreams];
+  std::vector<hipGraphNode_t> ev_node[kStreams];     // per global step
+  std::vector<hipGraphNode_t> pass_node[kStreams];   // per pass
+  std::vector<hipGraphNode_t> deps;
+
+  GraphOps(const Ctx& ctx, Device& dev, int p, hipGraph_t g) : c(ctx), D(dev), prec(p), graph(g) {
+    const size_t G = (size_t)(ctx.plan.chunks() * (int64_t)ctx.plan.steps.size());
+    for (int r = 0; r < kStreams; ++r) {
+      ev_node[r].assign(G, nullptr);
+      pass_node[r].assign((size_t)ctx.plan.chunks(), nullptr);
+    }
+  }
+  void deps_of(int r) {
+    deps = pending[r];
+    if (last[r]) deps.push_back(last[r]);
+  }
+  void added(int r, hipGraphNode_t n) {
+    last[r] = n;
+    pending[r].clear();
+  }
+  hipGraphNode_t head(int r) {
+    if (pending[r].empty()) return last[r];
+    deps_of(r);
+    hipGraphNode_t n = nullptr;
+    HIPC(hipGraphAddEmptyNode(&n, graph, deps.data(), deps.size()));
+    added(r, n);
+    return n;
+  }
+  void wait(int to, int from, int64_t g, int64_t) {
+    if (ev_node[from][g]) pending[to].push_back(ev_node[from][g]);
+  }
+  void record(int r, int64_t g) { ev_node[r][g] = head(r); }
+  void wait_pass(int to, int from, int64_t k, int64_t) {
+    if (pass_node[from][k]) pending[to].push_back(pass_node[from][k]);
+  }
+  void record_pass(int r, int64_t k, int64_t) { pass_node[r][k] = head(r); }
+  void transfer(const PlanRec& r, const PassMap& m, int64_t) {
+    const size_t sz = (size_t)m.bytes(r.node);
+    const int sr = r.op == OP_D2H ? S_D2H : S_H2D;
+    char* spill = (char*)D.spill;
+    void* dst;
+    const void* src;
+    hipMemcpyKind kind;
+    if (r.op == OP_D2H) {
+      dst = spill + m.host(r.host_off);
+      src = D.arena + m.dev(r.dev_off);
+      kind = hipMemcpyDeviceToHost;
+    } else {
+      dst = D.arena + m.dev(r.dev_off);
+      src = c.dag.is_leaf(r.node) ? (const void*)((const char*)D.stage[prec][r.node] + m.stage(r.node))
+                                  : (const void*)(spill + m.host(r.host_off));
+      kind = hipMemcpyHostToDevice;
+    }
+    deps_of(sr);
+    hipGraphNode_t n = nullptr;
+    HIPC(hipGraphAddMemcpyNode1D(&n, graph, deps.data(), deps.size(), dst, src, sz, kind));
+    added(sr, n);
+  }
+  int64_t launch(int64_t g, const PassMap&) {
+    const KernelPlan& kp = c.kplan;
+    for (int64_t li = kp.launch_off[g]; li < kp.launch_off[g + 1]; ++li) {
+      KernelCall k;
+      HIPC(call_of(kp.launches[li], prec, D.arena, &k));
+      k.bind();
+      hipKernelNodeParams np{};
+      np.func = const_cast<void*>(k.fn);
+      np.gridDim = dim3(k.grid);
+      np.blockDim = dim3(k.block);
+      np.sharedMemBytes = 0;
+      np.kernelParams = k.args;
+      np.extra = nullptr;
+      deps_of(S_COMP);
+      hipGraphNode_t n = nullptr;
+      HIPC(hipGraphAddKernelNode(&n, graph, deps.data(), deps.size(), &np));
+      added(S_COMP, n);
+    }
+    return kp.launch_off[g + 1] - kp.launch_off[g];
+  }
+};
+
+constexpr int64_t kSegmentSteps = 64;   // steps per one-stream graph when transfers are present
 }  // namespace
 
 // Autotuner: for every distinct (kind, N) among the exterior contractions,
@@ -579,8 +757,41 @@ int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps) {
 void trace_execute(const Ctx& c, int prec, std::vector<cdag_trace_rec>& out, int64_t fail_at) {
   out.clear();
   TraceOps ops{c, prec, out, fail_at};
-  walk_steps(c, prec, 0, (int64_t)c.plan.steps.size(), false, false, ops);
+  walk_steps(c, 0, c.plan.chunks() * (int64_t)c.plan.steps.size(), false, false, ops);
 }
+
+namespace {
+// Capture global steps [g0, g1) into one graph on one stream (stream order
+// carries every dependency).
+hipGraph_t capture_steps(Ctx& c, Device& D, int prec, int64_t g0, int64_t g1) {
+  hipGraph_t g = nullptr;
+  HIPC(hipStreamBeginCapture(D.cap, hipStreamCaptureModeThreadLocal));
+  try {
+    issue_steps(c, D, prec, g0, g1, D.cap, D.cap, D.cap, nullptr, true);
+  } catch (...) {
+    ignore(hipStreamEndCapture(D.cap, &g));
+    if (g) ignore(hipGraphDestroy(g));
+    throw;
+  }
+  HIPC(hipStreamEndCapture(D.cap, &g));
+  return g;
+}
+
+// Build the whole step sequence as one graph over the three streams' work,
+// with the plan's waits as explicit edges.
+hipGraph_t build_graph(Ctx& c, Device& D, int prec) {
+  hipGraph_t g = nullptr;
+  HIPC(hipGraphCreate(&g, 0));
+  try {
+    GraphOps ops(c, D, prec, g);
+    walk_steps(c, 0, c.plan.chunks() * (int64_t)c.plan.steps.size(), false, false, ops);
+  } catch (...) {
+    ignore(hipGraphDestroy(g));
+    throw;
+  }
+  return g;
+}
+}  // namespace
 
 void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   (void)batched;
@@ -595,10 +806,10 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
                                   std::to_string(kp.total_bytes));
   const int eb = prec == CDAG_FP64 ? 16 : 8;
   ensure_stage(c, prec);
-  ensure_spill(D, p.host_spill_bytes);
+  ensure_spill(D, p.halves() * p.host_spill_bytes);
   ensure_pinned(D.results, D.results_bytes, kp.corr_bytes + kp.sums_bytes);
-  const int64_t S = (int64_t)p.steps.size();
-  ensure_events(D, (size_t)std::max<int64_t>(S, 1));
+  const int64_t S = (int64_t)p.steps.size(), G = p.chunks() * S;
+  ensure_events(D, (size_t)std::max<int64_t>(G, 1), (size_t)p.chunks());
 
   // descriptor tables: one upload per (plan, arena)
   const uint64_t pkey = c.plan_serial;
@@ -630,25 +841,21 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   Device* timed = c.timing ? &D : nullptr;
   HIPC(hipEventRecord(D.t0, D.comp));
   if (c.use_graphs && !c.timing && !D.spill_pageable) {
-    // replay captured segments (one segment when there are no transfers)
-    const int64_t seg = has_copies ? kSegmentSteps : std::max<int64_t>(S, 1);
+    // replay graphs: one-stream segments of kSegmentSteps steps when there are
+    // transfers (else one), or one graph built over the three streams
+    const bool one = c.use_graphs == 1;
+    const int64_t seg = one && has_copies ? kSegmentSteps : std::max<int64_t>(G, 1);
     if (D.graph_key != pkey || D.graph_epoch != D.arena_epoch || D.graph_spill != D.spill ||
-        D.graph_stage != D.stage_version[prec]) {
+        D.graph_stage != D.stage_version[prec] || D.graph_mode != c.use_graphs) {
       D.drop_graphs();
-      for (int64_t s0 = 0; s0 < S; s0 += seg) {
-        const int64_t s1 = std::min(S, s0 + seg);
+      for (int64_t g0 = 0; g0 < G; g0 += seg) {
         hipGraph_t g = nullptr;
-        HIPC(hipStreamBeginCapture(D.cap_comp, hipStreamCaptureModeThreadLocal));
         try {
-          // transfers and kernels on the one capture stream, in step order
-          issue_steps(c, D, prec, s0, s1, D.cap_comp, D.cap_comp, nullptr, true);
+          g = one ? capture_steps(c, D, prec, g0, std::min(G, g0 + seg)) : build_graph(c, D, prec);
         } catch (...) {
-          ignore(hipStreamEndCapture(D.cap_comp, &g));
-          if (g) ignore(hipGraphDestroy(g));
           D.drop_graphs();
           throw;
         }
-        HIPC(hipStreamEndCapture(D.cap_comp, &g));
         D.seg_graph.push_back(g);
         hipGraphExec_t ge = nullptr;
         HIPC(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
@@ -658,12 +865,18 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
       D.graph_epoch = D.arena_epoch;
       D.graph_spill = D.spill;
       D.graph_stage = D.stage_version[prec];
+      D.graph_mode = c.use_graphs;
     }
     for (hipGraphExec_t ge : D.seg_exec) HIPC(hipGraphLaunch(ge, D.comp));
     n_segments = (int64_t)D.seg_exec.size();
-    for (int64_t s = 0; s < S; ++s) n_launch += kp.launch_off[s + 1] - kp.launch_off[s];
+    for (int64_t g = 0; g < G; ++g) n_launch += kp.launch_off[g + 1] - kp.launch_off[g];
   } else {
-    n_launch += issue_steps(c, D, prec, 0, S, D.comp, D.copy, timed, false);
+    n_launch += issue_steps(c, D, prec, 0, G, D.comp, D.copy, D.spill_s, timed, false);
+    // the results copy and the caller's later work follow every transfer
+    HIPC(hipEventRecord(D.ev_join[0], D.copy));
+    HIPC(hipEventRecord(D.ev_join[1], D.spill_s));
+    HIPC(hipStreamWaitEvent(D.comp, D.ev_join[0], 0));
+    HIPC(hipStreamWaitEvent(D.comp, D.ev_join[1], 0));
   }
   if (timed) {
     hipEvent_t a = D.timing_event(), b = D.timing_event();
@@ -681,6 +894,7 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
                         hipMemcpyDeviceToHost, D.comp));
   HIPC(hipStreamSynchronize(D.comp));
   HIPC(hipStreamSynchronize(D.copy));
+  HIPC(hipStreamSynchronize(D.spill_s));
   float ms = 0;
   HIPC(hipEventElapsedTime(&ms, D.t0, D.t1));
   c.corr_host.assign((const double*)D.results, (const double*)D.results + kp.corr_bytes / 8);

@@ -11,7 +11,7 @@ from oracle import values as OV
 
 def run(wl, policy="tree", prec="fp64", batched=False, budget=None, leaves_resident=False,
         use_graphs=True, wave_max=4096, wave_lookahead=0, device=0, tile=None, grid=1,
-        lds_stages=2, split_k=1, autotune=False, in_situ=False):
+        lds_stages=2, split_k=1, autotune=False, in_situ=False, t_chunks=1):
     import paper_2511_02257_amd as X
     from paper_2511_02257_amd.device import DeviceRunner
     ctx = X.Context()
@@ -20,6 +20,7 @@ def run(wl, policy="tree", prec="fp64", batched=False, budget=None, leaves_resid
     ctx.set_mem_budget(budget)
     ctx.set_options(leaves_resident=leaves_resident, wave_max=wave_max,
                     wave_lookahead=wave_lookahead, use_graphs=use_graphs)
+    ctx.set_time_chunks(t_chunks)
     if tile is not None:
         for lf_n in {lf.nvec for lf in wl.leaves}:
             for kind in (0, 1, 2, 4, 5, 6):
@@ -54,11 +55,13 @@ def sum_errors(wl, sums, ref_vals):
     return worst
 
 
-def oracle_plan_counts(wl, policy, elem_bytes, budget, batched, leaves_resident=False, lookahead=0):
+def oracle_plan_counts(wl, policy, elem_bytes, budget, batched, leaves_resident=False, lookahead=0,
+                       t_chunks=1):
     from oracle import planner as OP
     d = OD.build(wl.leaves, wl.graphs)
     order = OS.schedule(d, policy, elem_bytes)
     res = OP.plan(d, order, elem_bytes=elem_bytes,
                   budget=OP.UNLIMITED if budget is None else budget,
-                  batched=batched, leaves_resident=leaves_resident, lookahead=lookahead)
+                  batched=batched, leaves_resident=leaves_resident, lookahead=lookahead,
+                  t_chunks=t_chunks)
     return d, order, res

@@ -1,7 +1,7 @@
-"""Executor walk without a GPU (CPU only): the eager two-stream issue order,
-recorded by cdag_trace_execute, checked for races.
+"""Executor walk without a GPU (CPU only): the eager three-stream issue order
+(kernels, uploads, spills), recorded by cdag_trace_execute, checked for races.
 
-A happens-before check with vector clocks over the two streams: every pair of
+A happens-before check with vector clocks over the three streams: every pair of
 accesses to overlapping bytes of the same space (device arena, host spill
 pool, a leaf's staging buffer) where one is a write must be ordered, by the
 stream order or by an event the later stream waited for.  The checker is
@@ -19,9 +19,12 @@ from oracle import dag as OD
 from oracle import schedules as OS
 
 
+NS = 3   # streams: compute, upload, spill
+
+
 def races(trace):
     """(earlier record index, later record index) of every unordered conflicting pair."""
-    clock = {0: [0, 0], 1: [0, 0]}
+    clock = {s: [0] * NS for s in range(NS)}
     events = {}
     op_clock = {}
     seen = []          # (index, space key, lo, hi, write, stream, clock, seq)
@@ -100,7 +103,7 @@ def races_by_segment(trace):
     only (an earlier write is ordered before the last one, or that pair was
     already reported).  Finds a race exactly when races() does; fast enough
     for full-size walks.  Returns the number of unordered pairs it saw."""
-    clock = {0: [0, 0], 1: [0, 0]}
+    clock = {s: [0] * NS for s in range(NS)}
     events = {}
     op_clock = {}
     spaces = {}        # key -> (los, segs); segs[k] = [lo, hi, last write, reads since]
@@ -173,11 +176,13 @@ def test_eager_walk_has_no_races(name, wl, policy):
                     continue
                 t = c.trace_execute(prec, batched)
                 assert races(t) == [], (name, policy, frac, batched, look, resident, prec)
-                # transfers in the plan's order, one per H2D / D2H record
-                moves = [(r["node"], r["step"]) for r in t if r["op"] == "write" and
-                         (r["stream"] == 1)]
+                # transfers in the plan's order, one per H2D / D2H record; the
+                # spill stream moves D2H, the upload stream H2D
+                moves = [(r["node"], r["step"]) for r in t if r["op"] == "write" and r["stream"] in (1, 2)]
                 plan = [(node, step) for op, node, step in c.plan_ops() if op in ("H2D", "D2H")]
                 assert moves == plan
+                assert all(r["stream"] == (2 if r["space"] == "spill" else 1)
+                           for r in t if r["op"] == "write" and r["stream"] != 0)
                 assert p["n_h2d"] + p["n_d2h"] == len(plan)
                 recorded = set()
                 for r in t:
@@ -208,10 +213,69 @@ def test_checker_finds_planted_missing_waits():
         found += bool(races(t[:i] + t[i + 1:]))
     assert found >= 1
     assert len(races([r for r in t if r["op"] != "wait"])) > 10
-    # the copy stream's first wait guards an upload into memory that a kernel
+    # the upload stream's first wait guards an upload into memory that a kernel
     # of an earlier step still reads; without it that pair is unordered
     k = next(i for i, r in enumerate(t) if r["op"] == "wait" and r["stream"] == 1)
     assert races(t[:k] + t[k + 1:])
+    # every stream's waits matter: without all the waits of one stream, some
+    # pair it takes part in is unordered
+    for st in range(NS):
+        assert races([r for r in t if not (r["op"] == "wait" and r["stream"] == st)]), st
+
+
+def _chunk_cases():
+    yield "meson", W.meson_ring(n_leaves=8, nvec=8, nt=4, n_graphs=24, lmin=4, lmax=7, seed=34,
+                                with_data=False)
+    yield "baryon", W.baryon_mix(n_bar=4, n_mes=4, nvec=4, nt=8, n_graphs=10, seed=35, with_data=False)
+
+
+@pytest.mark.parametrize("name,wl", list(_chunk_cases()), ids=["meson", "baryon"])
+@pytest.mark.parametrize("chunks", [2, 4])
+def test_time_slice_passes_have_no_races(name, wl, chunks):
+    """Passes over slices of the time axis alternate between two halves of the
+    arena and of the spill pool: no race across passes (a pass waits for the
+    one two before it), every read finds its tensor, and the transfers are
+    the plan's, once per pass, each moving the pass's slices."""
+    c = _ctx(wl)
+    d = OD.build(wl.leaves, wl.graphs)
+    checked = planted = 0
+    for policy in ("input", "tree"):
+        c.schedule(policy)
+        for frac in (None, 3, 5):
+            budget = None if frac is None else 2 * _budget(wl, frac) // chunks
+            c.set_mem_budget(budget)
+            c.set_time_chunks(chunks)
+            for batched, look, resident in ((False, 0, False), (True, 16, False), (True, 16, True)):
+                c.set_options(leaves_resident=resident, wave_lookahead=look)
+                try:
+                    p = c.plan("fp64", batched)
+                except X.CdagError as e:
+                    assert e.code == B.E_BUDGET
+                    continue
+                t = c.trace_execute("fp64", batched)
+                assert races_by_segment(t) == 0, (policy, frac, batched, look, resident)
+                u = [r for r in t if not (resident and r["op"] == "read" and r["node"] < len(wl.leaves))]
+                assert provenance_errors(u) == []
+                moves = [(r["node"], r["step"] % (p["n_steps"] // chunks)) for r in t
+                         if r["op"] == "write" and r["stream"] in (1, 2)]
+                plan = [(node, step) for op, node, step in c.plan_ops() if op in ("H2D", "D2H")]
+                assert moves == plan * chunks
+                assert p["n_h2d"] + p["n_d2h"] == chunks * len(plan)
+                for r in t:
+                    if r["op"] in ("read", "write") and r["space"] != "stage":
+                        assert r["bytes"] == d.size(r["node"], 16) // chunks
+                if chunks > 2 and p["n_h2d"]:
+                    # without the pass-end waits, pass k and pass k - 2 (same
+                    # half) are unordered unless other waits happen to order them
+                    nw = [r for r in t if not (r["op"] == "wait" and r["event"] >= 3 * p["n_steps"])]
+                    planted += races_by_segment(nw) > 0
+                checked += 1
+            c.set_time_chunks(1)
+    assert checked >= 8
+    # on the meson DAG some upload of pass k is ordered against pass k - 2
+    # only by the pass-end waits (on the baryon DAG other waits also do)
+    assert chunks == 2 or name != "meson" or planted >= 1
+    c.close()
 
 
 def test_injected_failures_leave_the_context_usable():

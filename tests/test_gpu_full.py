@@ -52,7 +52,9 @@ def test_meson_ring_full_fp64_bench_configuration(meson):
                           np.concatenate(r["corr"]).view(np.uint64))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 4e-5)])
+# Split-BF16 with two pieces misses 1e-5 on the longest meson rings (about
+# 1.6e-5 measured): its bound here is 4e-5; three pieces meet 1e-5.
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 4e-5), ("bf16x6", 1e-5)])
 def test_meson_ring_full_mixed(meson, prec, tol):
     wl, ref = meson
     r = run(wl, "tree", prec, True, leaves_resident=True, wave_lookahead=ALL, use_graphs=True)
@@ -65,13 +67,19 @@ def test_meson_ring_full_mixed(meson, prec, tol):
 
 @pytest.fixture(scope="module")
 def baryon():
+    """Sample: for every distinct K32 output X = K32(B_a, M_b) of the DAG the
+    first graph that uses it, so that each is compared at least once, plus ten
+    seeded graphs."""
     wl = W.config("baryon_mix")
+    first = {}
+    for g, spec in enumerate(wl.graphs):
+        first.setdefault(tuple(spec.ops[0]), g)
     rng = np.random.default_rng(77)
-    sample = sorted(int(g) for g in rng.choice(len(wl.graphs), size=10, replace=False))
+    sample = sorted(set(first.values()) | {int(g) for g in rng.choice(len(wl.graphs), size=10, replace=False)})
     return wl, sample, OV.correlators(wl, sample)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 1e-5), ("bf16x6", 1e-5)])
 def test_baryon_mix_full_sampled(baryon, prec, tol):
     wl, sample, ref = baryon
     budget = 32 * 10**9 if prec == "fp64" else 16 * 10**9
@@ -100,7 +108,7 @@ def batched():
     return wl, sorted(sample), OV.correlators(wl, sorted(sample))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 4e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-5), ("bf16x6", 1e-5)])
 def test_batched_full_sampled(batched, prec, tol):
     """Five N families, just over 20,000 merged contractions, complex64 storage,
     64 GB budget: waves of every ready contraction, captured segments, autotuned tiles."""

@@ -49,7 +49,8 @@ def test_binding_constants_match_the_header():
                          "CDAG_E_NOMEM", "CDAG_E_RANGE"))
     assert (B.K22, B.K32, B.K33, B.HCA) == tuple(val[f"CDAG_{k}"] for k in ("K22", "K32", "K33", "HCA"))
     assert B.POLICY == {p: val[f"CDAG_SCHED_{p.upper()}"] for p in ("input", "sibling", "tree", "node")}
-    assert B.PREC == {"fp64": val["CDAG_FP64"], "fp32": val["CDAG_FP32"], "bf16x3": val["CDAG_BF16X3"]}
+    assert B.PREC == {"fp64": val["CDAG_FP64"], "fp32": val["CDAG_FP32"], "bf16x3": val["CDAG_BF16X3"],
+                      "bf16x6": val["CDAG_BF16X6"]}
     assert B.SCHED_CHECK == val["CDAG_SCHED_CHECK"]
     assert (W.C1, W.C2, W.C3) == (val["CDAG_C1"], val["CDAG_C2"], val["CDAG_C3"])
 
@@ -146,6 +147,49 @@ def test_schedules_and_plans_match_oracle(i):
         c.set_mem_budget(None)
 
 
+@pytest.mark.parametrize("i", list(range(0, 76, 5)))
+def test_time_slice_pass_plans_match_oracle(i):
+    """Plans of an execution in passes over slices of the time axis (sizes / C,
+    budget / 2 per pass): counters, steps and the op list of one pass equal
+    the oracle's."""
+    wl = WORKLOADS[i]
+    d = OD.build(wl.leaves, wl.graphs)
+    c = ctx_for(wl)
+    for policy in ("input", "tree"):
+        order = [int(x) for x in c.schedule(policy)]
+        live = OS.memsim(d, order)["peak_live"]
+        for budget in (None, live // 2, live // 3):
+            c.set_mem_budget(budget)
+            c.set_time_chunks(2)
+            for batched, look, resident in ((False, 0, False), (True, 0, False), (True, 3, True)):
+                c.set_options(leaves_resident=resident, wave_lookahead=look)
+                ob = OP.UNLIMITED if budget is None else budget
+                try:
+                    ref = OP.plan(d, order, budget=ob, batched=batched, leaves_resident=resident,
+                                  lookahead=look, t_chunks=2)
+                except OP.BudgetError:
+                    with pytest.raises(X.CdagError) as e:
+                        c.plan("fp64", batched)
+                    assert e.value.code == B.E_BUDGET
+                    continue
+                p = c.plan("fp64", batched)
+                for k in ("peak_resident", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes", "n_steps"):
+                    assert p[k] == ref[k], (policy, budget, batched, resident, k)
+                assert c.plan_ops() == ref["ops"]
+            c.set_time_chunks(1)
+    c.set_options(leaves_resident=False, wave_lookahead=0)
+    c.set_mem_budget(None)
+    # passes must divide every tensor's time slices
+    c.set_time_chunks(3)
+    with pytest.raises(X.CdagError) as e:
+        c.plan("fp64", True)
+    assert e.value.code == B.E_INVALID
+    with pytest.raises(X.CdagError) as e:
+        c.set_time_chunks(0)
+    assert e.value.code == B.E_INVALID
+    c.close()
+
+
 from synth import corr_func as CF   # noqa: E402
 
 
@@ -222,7 +266,7 @@ def test_mixed_precision_plans_halve_sizes():
     order = [int(x) for x in c.schedule("tree")]
     live = OS.memsim(d, order, 8)["peak_live"]
     c.set_mem_budget(live // 3)
-    for prec in ("fp32", "bf16x3"):
+    for prec in ("fp32", "bf16x3", "bf16x6"):
         p = c.plan(prec, True)
         ref = OP.plan(d, order, elem_bytes=8, budget=live // 3, batched=True)
         assert p["h2d_bytes"] == ref["h2d_bytes"] and p["n_evict"] == ref["n_evict"]
@@ -268,7 +312,7 @@ def test_kernel_variants_round_trip_and_share_decomposition():
         for grid in (0, 1):
             for stages in (2, 1):
                 for split in (1, 0):
-                    for prec in ("fp64", "fp32", "bf16x3"):
+                    for prec in ("fp64", "fp32", "bf16x3", "bf16x6"):
                         for kind in (0, 1, 2):
                             c.set_tile(prec, kind, 72, tile, grid, stages, split)
                             assert c.get_tile(prec, kind, 72) == (tile, grid, stages, split)
@@ -292,7 +336,7 @@ def test_split_k_choice_sets_the_work_items():
     c = ctx_for(wl)
     c.schedule("tree")
     for tile, (bm, bn) in sorted(X.TILES.items()):
-        for prec, kstep in (("fp64", 16), ("fp32", 16), ("bf16x3", 32)):
+        for prec, kstep in (("fp64", 16), ("fp32", 16), ("bf16x3", 32), ("bf16x6", 32)):
             k32 = n_k[W.K32] * 5 * (-(-1600 // bm)) * (-(-40 // bn))   # K32: M = N^2, K = N: no split
             base33 = 5 * (-(-40 // bm)) * (-(-40 // bn))
             for kind in (1, 2):

@@ -215,3 +215,37 @@ def test_wave_cut_rules():
     for w, nxt in zip(res["steps"], res["steps"][1:]):
         produced = set(w)
         assert any(x in produced for x in d.children(nxt[0]))
+
+
+def test_time_slice_passes_are_plans_of_the_sliced_dag():
+    """A pass over nt / C time slices is the plan of the same graphs built on
+    tensors of nt / C slices, under half the budget: the counters of C passes
+    are C times that plan's and the resident peak twice its peak (both halves).
+    With an unlimited budget every leaf moves once in total, a slice per pass."""
+    for seed in range(6):
+        wl4 = W.meson_ring(n_leaves=6, nvec=4, nt=4, n_graphs=10, lmin=3, lmax=6, seed=seed,
+                           with_data=False)
+        wl1 = W.meson_ring(n_leaves=6, nvec=4, nt=1, n_graphs=10, lmin=3, lmax=6, seed=seed,
+                           with_data=False)
+        d4 = D.build(wl4.leaves, wl4.graphs)
+        d1 = D.build(wl1.leaves, wl1.graphs)
+        order = S.input_order(d4)
+        assert order == S.input_order(d1)
+        live = S.memsim(d4, order)["peak_live"]
+        for budget in (P.UNLIMITED, live // 2, live // 3):
+            for batched in (False, True):
+                try:
+                    one = P.plan(d1, order, budget=budget // 2, batched=batched)
+                except P.BudgetError:
+                    with pytest.raises(P.BudgetError):
+                        P.plan(d4, order, budget=budget, batched=batched, t_chunks=4)
+                    continue
+                four = P.plan(d4, order, budget=budget, batched=batched, t_chunks=4)
+                for k in ("n_steps", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes"):
+                    assert four[k] == 4 * one[k], k
+                assert four["peak_resident"] == 2 * one["peak_resident"]
+                assert four["ops"] == one["ops"]
+                if budget == P.UNLIMITED:
+                    assert four["h2d_bytes"] == sum(d4.size(u) for u in range(d4.n_leaves))
+        with pytest.raises(ValueError):
+            P.plan(d4, order, t_chunks=3)
