@@ -3,9 +3,9 @@
 // plus the Sec. II-C memory model.
 //
 // Readings where the paper is silent or garbled:
-//   * Sibling picks the WAITING leaf with the smallest id when all queues are
-//     empty; queues are FIFO; PROP-DOWN visits the left child first; "the
-//     sibling of u under v" is v's other child.
+//   * Sibling picks the waiting leaf with the smallest id when all queues are
+//     empty; queues are FIFO; the sibling subtree's leaves are brought in left
+//     child first; "the sibling of u under v" is v's other child.
 //   * Tree: TR-INIT accumulates the individual gains igain (not the counts g)
 //     into tgain; PROCESS-CHILD removes u from x's AVAIL parents; ties in the
 //     argmax go to the lowest tree index; PROCESS-CTREE visits each not yet
@@ -42,88 +42,122 @@ std::vector<int64_t> sched_input(const Dag& d) {
 }
 
 // ---------------------------------------------------------------- Sibling
+// Sibling (Sec. III-A) as an event machine.  Ready contractions wait in one
+// FIFO per rank of Eq. (1); the highest non-empty rank runs next, and when
+// every rank is empty the lowest-id leaf not yet in memory is brought in.  A
+// tensor that arrives in memory (a leaf brought in, a contraction run) is an
+// event for each of its parents in turn: the parent's count of missing
+// children drops; with one child missing, the leaves still waiting in that
+// sibling's subtree are brought in, depth first, left before right (each such
+// leaf being an arrival of its own, handled before the next pending event);
+// with none missing, the parent joins its rank's FIFO.  Pending work is kept
+// on an explicit stack, so deep subtrees need no recursion.
 namespace {
 enum SbState : uint8_t { WAITING, QUEUED, INMEM, RELEASED };
 
-struct Sibling {
-  const Dag& d;
-  std::vector<int32_t> rank;
-  std::vector<int64_t> rs, rp;
-  std::vector<uint8_t> state;
-  std::vector<std::deque<int64_t>> q;   // q[r] for r = 1..max rank
-  std::vector<int64_t> order;
-  explicit Sibling(const Dag& dd) : d(dd) {
+class SiblingMachine {
+ public:
+  explicit SiblingMachine(const Dag& dd) : d(dd) {
     const int64_t n = d.n_nodes();
     for (int64_t u = d.n_leaves; u < n; ++u)
       if (d.n_children(u) != 2)
         throw Error(CDAG_E_INVALID, "sibling: node " + std::to_string(u) + " does not have two children");
     rank.assign(n, 0);
-    int32_t qmax = 0;
+    int32_t top = 0;
     for (int64_t u = d.n_leaves; u < n; ++u) {   // Eq. (1); ids are topological
       rank[u] = 1 + std::max(rank[d.left[u]], rank[d.right[u]]);
-      qmax = std::max(qmax, rank[u]);
+      top = std::max(top, rank[u]);
     }
-    rs.resize(n);
-    rp.resize(n);
+    users.resize(n);
+    missing.resize(n);
     for (int64_t u = 0; u < n; ++u) {
-      rs[u] = d.n_parents(u);
-      rp[u] = d.is_leaf(u) ? 0 : 2;
+      users[u] = d.n_parents(u);
+      missing[u] = d.is_leaf(u) ? 0 : 2;
     }
     state.assign(n, WAITING);
-    q.resize(qmax + 1);
+    ready.resize(top + 1);
   }
-  void process(int64_t u) {                       // SB-PROCESS
-    if (!d.is_leaf(u)) order.push_back(u);        // perform the contraction
-    state[u] = INMEM;
-    if (!d.is_leaf(u)) {
-      for (int64_t v : {d.left[u], d.right[u]})
-        if (--rs[v] == 0) state[v] = RELEASED;
-      if (d.n_parents(u) == 0) state[u] = RELEASED;   // a ROOT
-    }
-    for (int64_t e = d.par_off[u]; e < d.par_off[u + 1]; ++e) {
-      int64_t v = d.par[e];
-      rp[v] -= 1;
-      if (rp[v] == 1) {
-        int64_t w = d.left[v] == u ? d.right[v] : d.left[v];
-        if (state[w] == WAITING) prop_down(w);
-      } else if (rp[v] == 0) {
-        q[rank[v]].push_back(v);
-        state[v] = QUEUED;
-      }
-    }
-  }
-  void prop_down(int64_t u) {                     // SB-PROP-DOWN
-    if (state[u] != WAITING) return;
-    if (d.is_leaf(u)) { process(u); return; }
-    prop_down(d.left[u]);
-    prop_down(d.right[u]);
-  }
-  void run() {                                    // SB-SCHEDULER
+
+  std::vector<int64_t> run() {
     const int64_t n_contr = d.n_nodes() - d.n_leaves;
     int64_t next_leaf = 0;
     while ((int64_t)order.size() < n_contr) {
-      int64_t r = (int64_t)q.size() - 1;
-      while (r >= 1 && q[r].empty()) --r;
-      int64_t u;
-      if (r < 1) {
-        while (next_leaf < d.n_leaves && state[next_leaf] != WAITING) ++next_leaf;
-        if (next_leaf >= d.n_leaves) throw Error(CDAG_E_STATE, "sibling: no WAITING leaf left");
-        u = next_leaf;
+      while (high >= 1 && ready[high].empty()) --high;
+      if (high >= 1) {
+        const int64_t v = ready[high].front();
+        ready[high].pop_front();
+        contract(v);
       } else {
-        u = q[r].front();
-        q[r].pop_front();
+        while (next_leaf < d.n_leaves && state[next_leaf] != WAITING) ++next_leaf;
+        if (next_leaf >= d.n_leaves) throw Error(CDAG_E_STATE, "sibling: no waiting leaf left");
+        bring(next_leaf);
       }
-      process(u);
+      drain();
+    }
+    return std::move(order);
+  }
+
+ private:
+  // Stack work: NOTIFY walks the parents of an arrived tensor (edge = the next
+  // parent edge); FETCH brings in the waiting leaves of a subtree.
+  enum Kind : uint8_t { NOTIFY, FETCH };
+  struct Work { Kind kind; int64_t node, edge; };
+
+  const Dag& d;
+  std::vector<int32_t> rank;
+  std::vector<int64_t> users, missing;     // parents still to run; children not yet in memory
+  std::vector<uint8_t> state;
+  std::vector<std::deque<int64_t>> ready;  // FIFO per rank
+  int32_t high = 0;                        // no rank above this one holds work
+  std::vector<Work> stack;
+  std::vector<int64_t> order;
+
+  void arrived(int64_t u) {
+    state[u] = INMEM;
+    stack.push_back({NOTIFY, u, d.par_off[u]});
+  }
+  void bring(int64_t leaf) { arrived(leaf); }
+  void contract(int64_t v) {
+    order.push_back(v);
+    arrived(v);
+    for (int64_t c : {d.left[v], d.right[v]})
+      if (--users[c] == 0) state[c] = RELEASED;
+    if (d.n_parents(v) == 0) state[v] = RELEASED;   // a root's value leaves at once
+  }
+  void drain() {
+    while (!stack.empty()) {
+      Work& w = stack.back();
+      if (w.kind == FETCH) {
+        const int64_t u = w.node;
+        stack.pop_back();
+        if (state[u] != WAITING) continue;
+        if (d.is_leaf(u)) {
+          bring(u);
+        } else {                                    // left subtree first
+          stack.push_back({FETCH, d.right[u], 0});
+          stack.push_back({FETCH, d.left[u], 0});
+        }
+        continue;
+      }
+      if (w.edge == d.par_off[w.node + 1]) {
+        stack.pop_back();
+        continue;
+      }
+      const int64_t u = w.node, v = d.par[w.edge++];
+      if (--missing[v] == 1) {
+        const int64_t sib = d.left[v] == u ? d.right[v] : d.left[v];
+        if (state[sib] == WAITING) stack.push_back({FETCH, sib, 0});
+      } else if (missing[v] == 0) {
+        ready[rank[v]].push_back(v);
+        state[v] = QUEUED;
+        high = std::max(high, rank[v]);
+      }
     }
   }
 };
 }  // namespace
 
-std::vector<int64_t> sched_sibling(const Dag& d) {
-  Sibling s(d);
-  s.run();
-  return std::move(s.order);
-}
+std::vector<int64_t> sched_sibling(const Dag& d) { return SiblingMachine(d).run(); }
 
 // ---------------------------------------------------------------- Tree
 namespace {
