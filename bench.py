@@ -335,8 +335,13 @@ def meson_budgeted(args, X, W, DeviceRunner):
     out["resident_tree_ms"] = round(d2 / 10 * 1e3, 3)
     ref = np.concatenate(ctx.fetch_correlators()).view(np.uint64).copy()
     ctx.set_mem_budget(budget)
-    for policy, look in (("input", 16), ("tree", 16), ("tree", 0), ("node", 16)):
+    # whole tensors (the memory model of Sec. II-C), then Tree in passes over
+    # the time slices under the same budget (a pass holds slices of every
+    # tensor, so the budget binds less and the plan moves less)
+    for policy, look, chunks in (("input", 16, 1), ("tree", 16, 1), ("tree", 0, 1), ("node", 16, 1),
+                                 ("tree", 16, 2), ("tree", 16, 4)):
         ctx.schedule(policy)
+        ctx.set_time_chunks(chunks)
         row = {}
         for mode in (0, 1, 2):
             ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=mode)
@@ -345,8 +350,10 @@ def meson_budgeted(args, X, W, DeviceRunner):
         row["bits_equal_resident"] = bool(np.array_equal(np.concatenate(ctx.fetch_correlators()).view(np.uint64), ref))
         row.update(plan_summary(s2["plan"]))
         row["tflops_best"] = round(s2["plan"]["flops"] / (min(v for k, v in row.items() if k.endswith("_ms")) * 1e-3) / 1e12, 3)
-        out[f"{policy}_lookahead{look}"] = row
-        log("meson", policy, look, row)
+        key = f"{policy}_lookahead{look}" + (f"_{chunks}passes" if chunks > 1 else "")
+        out[key] = row
+        log("meson", key, row)
+    ctx.set_time_chunks(1)
     ctx.schedule("tree")
     ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=0)
     ctx.set_timing(True)

@@ -424,7 +424,11 @@ int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
  * variant and split_k setting, shape by shape, with launch timing on, and keep
  * the least time of exterior contractions and split-K reductions in the
  * fastest of the reps
- * (needs leaf data; costs up to 40 * reps executes per shape).  *n_tuned
+ * (needs leaf data; costs up to 40 * reps executes per shape).  mode 2
+ * (synthetic, uniform): the timings of mode 0, then one choice for every
+ * shape, the one whose summed time over the DAG (time per slice times the
+ * slices of each shape) is least, so that each wave's exterior contractions
+ * run in one grouped launch.  *n_tuned
  * (nullable) receives the number of shapes tuned.  Needs cdag_bind_device and
  * an arena of at least the plan's arena_bytes; invalidates the current plan
  * and results. */

@@ -380,9 +380,12 @@ def execute(h, prec: str = "fp64", batched: bool = False) -> dict:
 
 
 def cdag_autotune(h, prec: str = "fp64", batched: bool = True, reps: int = 3,
-                  in_situ: bool = False) -> int:
+                  in_situ: bool = False, uniform: bool = False) -> int:
+    """Mode 0 synthetic per shape, 1 in situ per shape, 2 synthetic with one
+    choice for every shape (one grouped launch per wave)."""
     n = C.c_int64()
-    _check(lib().cdag_autotune(h, PREC[prec], int(batched), int(reps), int(bool(in_situ)), C.byref(n)))
+    mode = 1 if in_situ else (2 if uniform else 0)
+    _check(lib().cdag_autotune(h, PREC[prec], int(batched), int(reps), mode, C.byref(n)))
     return n.value
 
 
@@ -506,8 +509,8 @@ class Context:
     def trace_execute(self, prec="fp64", batched=False, fail_at=-1):
         return cdag_trace_execute(self.h, prec, batched, fail_at)
 
-    def autotune(self, prec="fp64", batched=True, reps=3, in_situ=False):
-        return cdag_autotune(self.h, prec, batched, reps, in_situ)
+    def autotune(self, prec="fp64", batched=True, reps=3, in_situ=False, uniform=False):
+        return cdag_autotune(self.h, prec, batched, reps, in_situ, uniform)
 
     def fetch_correlators(self):
         return fetch_correlators(self.h, self.graph_nt)

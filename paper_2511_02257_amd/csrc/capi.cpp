@@ -71,6 +71,10 @@ void ensure_plan(Ctx& c, int prec, int batched) {
   c.plan = make_plan(c.dag, c.order, o);
   place(c.dag, c.plan);
   c.kplan = make_kernel_plan(c.dag, c.plan, prec, c.tiles);
+  // host result buffers sized with the plan (an execute then writes them
+  // without allocating)
+  c.corr_host.resize(c.kplan.corr_bytes / 8);
+  c.sums_host.resize(c.kplan.sums_bytes / 8);
   MemSim ms = memsim(c.dag, c.order, eb);
   c.peak_post = ms.peak_post;
   c.peak_live = ms.peak_live;
@@ -489,12 +493,12 @@ int cdag_autotune(cdag_ctx* h, int prec, int batched, int reps, int mode, int64_
   return guard([&] {
     cdag::Ctx& c = h->c;
     need(reps >= 1, CDAG_E_INVALID, "reps must be >= 1");
-    need(mode == 0 || mode == 1, CDAG_E_INVALID, "mode must be 0 (synthetic) or 1 (in situ)");
+    need(mode >= 0 && mode <= 2, CDAG_E_INVALID, "mode must be 0 (synthetic), 1 (in situ) or 2 (synthetic, uniform)");
     need(c.dev != nullptr, CDAG_E_STATE, "cdag_bind_device first");
     need(mode == 0 || c.has_data, CDAG_E_STATE, "in-situ tuning needs leaf data");
     cdag::ensure_plan(c, prec, batched);
-    int64_t n = mode == 0 ? cdag::device_autotune(c, prec, batched, reps)
-                          : cdag::device_autotune_insitu(c, prec, batched, reps);
+    int64_t n = mode == 1 ? cdag::device_autotune_insitu(c, prec, batched, reps)
+                          : cdag::device_autotune(c, prec, batched, reps, mode == 2);
     c.version++;
     c.have_results = false;
     if (n_tuned) *n_tuned = n;

@@ -63,7 +63,7 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st);
 // The eager two-stream issue order of the planned execute, recorded instead of
 // issued (no HIP call); fail_at >= 0 throws Error(CDAG_E_HIP) at that record.
 void trace_execute(const Ctx& c, int prec, std::vector<cdag_trace_rec>& out, int64_t fail_at);
-int64_t device_autotune(Ctx& c, int prec, int batched, int reps);
+int64_t device_autotune(Ctx& c, int prec, int batched, int reps, bool uniform);
 int64_t device_autotune_insitu(Ctx& c, int prec, int batched, int reps);
 
 }  // namespace cdag

@@ -38,4 +38,5 @@ hipError_t launch_reduce(int prec, char* arena, int64_t desc_off, int n_desc, in
 hipError_t launch_hca(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s);
 hipError_t launch_xsum(char* arena, int64_t desc_off, int64_t entries_off, int n_desc, hipStream_t s);
 
+
 }  // namespace cdag

@@ -609,10 +609,14 @@ constexpr int64_t kSegmentSteps = 64;   // steps per one-stream graph when trans
 }  // namespace
 
 // Autotuner: for every distinct (kind, N) among the exterior contractions,
-// time each tile shape on a synthetic contraction of that shape (operands in
-// the arena's tensor pool, which holds nothing between executes) and keep the
-// fastest per time slice.  The choice enters the tile table of the context.
-int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
+// time each kernel choice on a synthetic contraction of that shape (operands
+// in the arena's tensor pool, which holds nothing between executes).  uniform
+// = false keeps the fastest choice per time slice of each shape; uniform =
+// true keeps the one choice whose time over the whole DAG (per-slice time x
+// the slices of that shape in the DAG, summed over shapes) is least, so that
+// every wave runs its exterior contractions in one grouped launch.  The
+// choices enter the tile table of the context.
+int64_t device_autotune(Ctx& c, int prec, int batched, int reps, bool uniform) {
   Device& D = *c.dev;
   HIPC(hipSetDevice(D.device));
   const Plan& p = c.plan;
@@ -624,6 +628,11 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
   auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
   const int64_t lo = al(p.leaf_region_bytes), hi = kp.ws_off + kp.ws_bytes;
   const auto shapes = tune_shapes(c.dag);
+  // slices of each shape in the DAG (the uniform choice's weights)
+  std::map<std::pair<int, int>, double> weight;
+  for (int64_t u = c.dag.n_leaves; u < c.dag.n_nodes(); ++u)
+    if (c.dag.kind[u] != HCA) weight[{c.dag.kind[u], c.dag.nvec[u]}] += c.dag.nt[u];
+  std::map<std::pair<int, int>, std::vector<double>> per_slice;   // shape -> time per slice, per choice
   hipEvent_t e0, e1;
   HIPC(hipEventCreate(&e0));
   HIPC(hipEventCreate(&e1));
@@ -634,13 +643,18 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
       double best = 1e300;
       int best_tile = -1;
       const int snt = sh.second.nt;
+      std::vector<double>& row = per_slice[sh.first];
+      row.assign(kNumChoices, 1e300);
       for (int ch = 0; ch < kNumChoices; ++ch) {
         HecDesc h{};
         decompose(sh.second.gemm, snt, ch, prec, &h);   // split count of a real contraction
         if (!choice_split_k(ch)) {
           HecDesc a{};
           decompose(sh.second.gemm, snt, choice_variant(ch), prec, &a);
-          if (a.splits == 1) continue;                  // same work items as the split choice
+          if (a.splits == 1) {                          // same work items as the split choice
+            row[ch] = row[choice_of(choice_variant(ch), true)];
+            continue;
+          }
         }
         const int64_t slice_items = (int64_t)h.tiles_m * h.tiles_n * h.splits;
         const int64_t slice = (int64_t)h.M * h.K * eb + (int64_t)h.K * h.N * eb + (int64_t)h.M * h.N * eb;
@@ -679,13 +693,28 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps) {
         HIPC(hipEventSynchronize(e1));
         float ms = 0;
         HIPC(hipEventElapsedTime(&ms, e0, e1));
-        const double per_slice = ms / reps / (double)nt;
-        if (per_slice < best) { best = per_slice; best_tile = ch; }
+        const double t_slice = ms / reps / (double)nt;
+        row[ch] = t_slice;
+        if (t_slice < best) { best = t_slice; best_tile = ch; }
       }
-      if (best_tile >= 0) {
+      if (best_tile >= 0 && !uniform) {
         c.tiles[std::make_tuple(prec, kind, n)] = best_tile;
         ++tuned;
       }
+    }
+    if (uniform && !per_slice.empty()) {
+      double best = 1e300;
+      int best_ch = -1;
+      for (int ch = 0; ch < kNumChoices; ++ch) {
+        double t = 0;
+        for (const auto& kv : per_slice) t += weight[kv.first] * kv.second[ch];
+        if (t < best) { best = t; best_ch = ch; }
+      }
+      if (best_ch >= 0 && best < 1e299)
+        for (const auto& kv : per_slice) {
+          c.tiles[std::make_tuple(prec, kv.first.first, kv.first.second)] = best_ch;
+          ++tuned;
+        }
     }
   } catch (...) {
     ignore(hipEventDestroy(e0));

@@ -37,12 +37,12 @@ class DeviceRunner:
             self.arena = self.torch.empty(max(256, nbytes), dtype=self.torch.uint8, device=self.dev)
             self.ctx.bind_arena(self.arena.data_ptr(), self.arena.numel())
 
-    def autotune(self, prec="fp64", batched=True, reps=3, in_situ=False):
+    def autotune(self, prec="fp64", batched=True, reps=3, in_situ=False, uniform=False):
         """Size the arena for the plan (with room for every variant's workspace),
         then let the library pick kernel variants."""
         plan = self.ctx.plan(prec, batched)
         self.ensure_arena(int(plan["arena_bytes"] * 1.25) + (1 << 20))
-        return self.ctx.autotune(prec, batched, reps, in_situ)
+        return self.ctx.autotune(prec, batched, reps, in_situ, uniform)
 
     def run(self, prec="fp64", batched=False):
         plan = self.ctx.plan(prec, batched)
