@@ -257,6 +257,9 @@ def headline(args, X, W, DeviceRunner, sample):
         "all_kernels_timed_execute": kernel_table(recs, "fp64"),
         "transfers_timed_execute": transfer_rates(recs, t_timed)}
     extras = {}
+    if args.only == "headline-fp64":
+        ctx.close()
+        return fields, extras, corr
     # references on the same DAG: one pass (whole tensors), and every leaf resident
     for name, chunks, resident in (("one_pass", 1, False), ("resident", 1, True)):
         ctx.set_time_chunks(chunks)
@@ -573,9 +576,10 @@ def main():
     ap.add_argument("--chunks", type=int, default=8, help="time-slice passes of the headline execute")
     ap.add_argument("--link-GBps", type=float, default=55.0,
                     help="host-link rate for the upload floor of the headline (large pinned copies)")
-    ap.add_argument("--only", default=None, choices=("headline", "meson", "batched"),
-                    help="one part: the headline (with its references and precision form), the budgeted "
-                         "meson configuration, or the batched configuration")
+    ap.add_argument("--only", default=None, choices=("headline", "headline-fp64", "meson", "batched"),
+                    help="one part: the headline (with its references and precision form), the headline "
+                         "FP64 execute alone (for profiling), the budgeted meson configuration, or the "
+                         "batched configuration")
     ap.add_argument("--tiles-from", default=None, metavar="JSON",
                     help="take the headline's kernel choices from the JSON line of an earlier run "
                          "instead of autotuning (so that profiled runs use the same kernels)")
@@ -622,13 +626,14 @@ def main():
         print(json.dumps({"batched_budgeted": batched_budgeted(args, X, W, DeviceRunner)}), flush=True)
         return
     # the oracle's sample first (its correlators also give the precision errors)
-    base, ref = cpu_baseline(args.cpu_seconds if args.only is None else min(args.cpu_seconds, 3.0))
+    base, ref = cpu_baseline(args.cpu_seconds if args.only is None else min(args.cpu_seconds, 2.0))
     fields, extras, corr = headline(args, X, W, DeviceRunner, sorted(ref))
     out.update(fields)
     errs = {p: errors_vs_oracle(c, ref) for p, c in corr.items()}
     out["config"]["correlator_error_vs_fp64_oracle"] = errs["fp64"]
     for p in ("fp32", "bf16x3", "bf16x6"):
-        extras[p]["correlator_error_vs_fp64_oracle"] = errs[p]
+        if p in extras:
+            extras[p]["correlator_error_vs_fp64_oracle"] = errs[p]
     out["extras"] = {"baryon_mix": extras}
     if args.only is None:
         out["extras"]["meson_ring_budgeted"] = meson_budgeted(args, X, W, DeviceRunner)
