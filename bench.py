@@ -382,9 +382,10 @@ def meson_budgeted(args, X, W, DeviceRunner):
 def batched_budgeted(args, X, W, DeviceRunner):
     """The batched configuration: five N families (32..128), Nt = 64, complex64
     storage, just over 20,000 contractions; HBM budget 64e9 bytes; leaves in
-    pinned host memory; Tree order; synthetic autotuner.  Waves (one grouped
-    launch per kernel choice and wave) against one launch per contraction,
-    FP32 (and split-BF16 with two pieces, waves)."""
+    pinned host memory; Tree order; synthetic autotuner.  Waves with the kernel
+    choice tuned per (kind, N) (one grouped launch per choice and wave) and
+    with one choice for all shapes (one grouped launch per wave), against one
+    launch per contraction; FP32 and split-BF16 with two pieces."""
     torch = __import__("torch")
     wl = W.config("batched")
     ctx = X.Context()
@@ -396,28 +397,33 @@ def batched_budgeted(args, X, W, DeviceRunner):
     runner = DeviceRunner(ctx, 0)
     out = {}
     for prec in ("fp32", "bf16x3"):
-        ctx.set_time_chunks(1)
-        ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=0)
-        runner.autotune(prec, True, reps=1, in_situ=False)
-        ref = None
-        rows = (("waves_lookahead16", True, 1, 16), ("waves_lookahead16_4passes", True, 4, 16),
-                ("per_contraction", False, 1, 0))
-        for name, batched, chunks, look in rows:
-            if prec != "fp32" and not batched:
-                continue
-            ctx.set_time_chunks(chunks)
-            m, mt = best_mode(runner, ctx, prec, batched, modes=(0, 2) if batched else (0,), reps=1,
-                              leaves_resident=False, wave_lookahead=look)
-            d2, s2 = timed_steps(runner, prec, batched, 1, 0)
-            bits = np.concatenate(ctx.fetch_correlators()).view(np.uint64)
-            if ref is None:
-                ref = bits.copy()
-            row = {"tts_s": round(d2, 4), "tflops": round(s2["plan"]["flops"] / d2 / 1e12, 3),
-                   "issue_mode": X.binding.GRAPH_MODES[m], "n_hec_launches": s2["n_hec_launches"],
-                   "n_launches": s2["n_launches"], "bits_equal_first": bool(np.array_equal(bits, ref)),
-                   "n_contractions": s2["plan"]["n_contr"], **plan_summary(s2["plan"])}
-            out[f"{prec}_{name}"] = row
-            log("batched", prec, name, row)
+        for uniform in (False, True):
+            ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=0)
+            runner.autotune(prec, True, reps=1, in_situ=False, uniform=uniform)
+            ref = None
+            rows = (("waves_lookahead16", True, 16),) + ((("per_contraction", False, 0),)
+                                                          if prec == "fp32" and not uniform else ())
+            for name, batched, look in rows:
+                m, mt = best_mode(runner, ctx, prec, batched, modes=(0, 2) if batched else (0,), reps=1,
+                                  leaves_resident=False, wave_lookahead=look)
+                d2, s2 = timed_steps(runner, prec, batched, 1, 0)
+                bits = np.concatenate(ctx.fetch_correlators()).view(np.uint64)
+                if ref is None:
+                    ref = bits.copy()
+                row = {"tts_s": round(d2, 4), "tflops": round(s2["plan"]["flops"] / d2 / 1e12, 3),
+                       "issue_mode": X.binding.GRAPH_MODES[m], "n_hec_launches": s2["n_hec_launches"],
+                       "n_launches": s2["n_launches"], "bits_equal_first": bool(np.array_equal(bits, ref)),
+                       "n_contractions": s2["plan"]["n_contr"], **plan_summary(s2["plan"])}
+                key = f"{prec}_{name}" + ("_one_choice" if uniform else "")
+                if uniform:
+                    t, g, st_, sk = ctx.get_tile(prec, 2, 128)
+                    row["choice"] = {"tile": list(X.TILES[t]), "grid": X.binding.GRIDS[g], "lds_stages": st_,
+                                     "split_k": sk}
+                out[key] = row
+                log("batched", key, row)
+        for kind in (0, 1, 2):            # back to the per-shape default before the next precision
+            for n in (32, 48, 64, 96, 128):
+                ctx.set_tile(prec, kind, n, -1)
     ctx.close()
     runner.arena = None
     del runner

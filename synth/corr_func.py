@@ -161,3 +161,16 @@ def corr_func_like(row: str, n_trees: Optional[int] = None, skew: Optional[float
     graphs = [_graph(tab["system"], par["mix"], mes, bar, rg) for _ in range(k)]
     return Workload(row, leaves, graphs, meta=dict(seed=seed, kind="corr_func", system=tab["system"],
                                                    skew=s))
+
+
+def with_data(wl: Workload, seed: int = 2100, sigma: Optional[float] = None) -> Workload:
+    """The same workload with seeded leaf entries (re and im iid N(0, sigma^2),
+    sigma = 1/N by default), so that a Table corr-func-shaped DAG can run on
+    the device and be checked against the oracle.  Random numbers only."""
+    from .workloads import _draw
+    rg = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    leaves = []
+    for lf in wl.leaves:
+        sg = 1.0 / lf.nvec if sigma is None else sigma
+        leaves.append(Leaf(lf.rank, lf.nvec, lf.nt, _draw(rg, (lf.nt,) + (lf.nvec,) * lf.rank, sg)))
+    return Workload(wl.name, leaves, wl.graphs, meta=dict(wl.meta, data_seed=seed))
