@@ -413,6 +413,28 @@ int cdag_bind_arena(cdag_ctx* c, void* dev_arena, uint64_t bytes);
  * allocated. */
 int execute(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
 
+/* Size of the static device array behind cdag_execute_static. */
+#define CDAG_STATIC_SCRATCH_BYTES (64LL << 20)
+
+/* For callers that cannot allocate device or pinned host memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * execute with every device byte in a static array of
+ * CDAG_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on until
+ * the process ends, instead of the bound arena.  Results and statistics are
+ * those of execute (bit-identical correlators for the same plan);
+ * fetch_correlators and cdag_fetch_sums read them afterwards.  Everything runs
+ * on the compute stream in plan order (no events, no graphs); leaves are
+ * copied from the library's own host copy and converted to the device layout
+ * on the device.  Needs a plan made beforehand with cdag_plan for the same
+ * (prec, batched) (CDAG_E_STATE otherwise: planning allocates host memory),
+ * one pass over the time slices and no spill to host memory (CDAG_E_BUDGET);
+ * CDAG_E_NOMEM when the plan's arena plus a staging range for the largest leaf
+ * exceed CDAG_STATIC_SCRATCH_BYTES.  The array is shared by every context on
+ * that GPU and keeps the last call's contents: calls that overlap on one GPU
+ * race (serialise them; none may overlap an execute of another context that
+ * uses it). */
+int cdag_execute_static(cdag_ctx* c, int prec, int batched, cdag_exec_stats* out);
+
 /* Autotuner over the kernel variants of cdag_set_tile, for every distinct
  * (kind, N) among the exterior contractions of the DAG.  mode 0 (synthetic):
  * time each variant and split_k setting `reps` times on a batch of time

@@ -127,6 +127,7 @@ def lib():
             "cdag_bind_device": [P, C.c_int, P, P],
             "cdag_bind_arena": [P, P, C.c_uint64],
             "execute": [P, C.c_int, C.c_int, C.POINTER(cdag_exec_stats)],
+            "cdag_execute_static": [P, C.c_int, C.c_int, C.POINTER(cdag_exec_stats)],
             "cdag_autotune": [P, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(I64)],
             "fetch_correlators": [P, C.POINTER(C.c_double), I64],
             "cdag_fetch_sums": [P, C.POINTER(C.c_double), I64],
@@ -147,7 +148,7 @@ EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "cda
             "cdag_trace_execute", "cdag_dag_stats", "cdag_set_tile", "cdag_get_tile", "cdag_memsim",
             "cdag_plan", "cdag_plan_ops",
             "cdag_get_nodes", "cdag_graph_roots", "cdag_bind_device", "cdag_bind_arena",
-            "execute", "cdag_autotune", "fetch_correlators", "cdag_fetch_sums")
+            "execute", "cdag_execute_static", "cdag_autotune", "fetch_correlators", "cdag_fetch_sums")
 
 
 def _check(rc: int):
@@ -379,6 +380,15 @@ def execute(h, prec: str = "fp64", batched: bool = False) -> dict:
     return _struct_dict(st)
 
 
+def cdag_execute_static(h, prec: str = "fp64", batched: bool = False) -> dict:
+    st = cdag_exec_stats()
+    _check(lib().cdag_execute_static(h, PREC[prec], int(batched), C.byref(st)))
+    return _struct_dict(st)
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
 def cdag_autotune(h, prec: str = "fp64", batched: bool = True, reps: int = 3,
                   in_situ: bool = False, uniform: bool = False) -> int:
     """Mode 0 synthetic per shape, 1 in situ per shape, 2 synthetic with one
@@ -505,6 +515,9 @@ class Context:
 
     def execute(self, prec="fp64", batched=False):
         return execute(self.h, prec, batched)
+
+    def execute_static(self, prec="fp64", batched=False):
+        return cdag_execute_static(self.h, prec, batched)
 
     def trace_execute(self, prec="fp64", batched=False, fail_at=-1):
         return cdag_trace_execute(self.h, prec, batched, fail_at)

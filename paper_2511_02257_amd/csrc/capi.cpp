@@ -488,6 +488,28 @@ int execute(cdag_ctx* h, int prec, int batched, cdag_exec_stats* out) {
   });
 }
 
+int cdag_execute_static(cdag_ctx* h, int prec, int batched, cdag_exec_stats* out) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    cdag::Ctx& c = h->c;
+    need(c.built, CDAG_E_STATE, "build_cdag first");
+    need(c.has_data, CDAG_E_STATE, "the DAG was built without leaf data");
+    need(c.dev != nullptr, CDAG_E_STATE, "cdag_bind_device first");
+    elem_bytes_prec(prec);
+    static_assert(CDAG_STATIC_SCRATCH_BYTES == (64LL << 20), "scratch size in the header");
+    // planning allocates host memory: the plan must exist already
+    need(c.planned && c.plan_version == c.version && c.plan_prec == prec && c.plan_batched == (batched ? 1 : 0),
+         CDAG_E_STATE, "cdag_plan for the same precision and batching first");
+    c.have_results = false;
+    cdag_exec_stats st;
+    std::memset(&st, 0, sizeof(st));
+    cdag::device_execute_static(c, prec, &st);
+    fill_plan_stats(c, &st.plan);
+    c.have_results = true;
+    if (out) *out = st;
+  });
+}
+
 int cdag_autotune(cdag_ctx* h, int prec, int batched, int reps, int mode, int64_t* n_tuned) {
   if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
   return guard([&] {

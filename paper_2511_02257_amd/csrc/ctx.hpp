@@ -60,6 +60,9 @@ void device_destroy(Device* d);
 void device_bind(Ctx& c, int device, void* compute_stream, void* copy_stream);
 void device_bind_arena(Ctx& c, void* arena, uint64_t bytes);
 void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st);
+// The planned execute on the compute stream alone, with the static scratch
+// as the arena and no allocation (see cdag_execute_static).
+void device_execute_static(Ctx& c, int prec, cdag_exec_stats* st);
 // The eager two-stream issue order of the planned execute, recorded instead of
 // issued (no HIP call); fail_at >= 0 throws Error(CDAG_E_HIP) at that record.
 void trace_execute(const Ctx& c, int prec, std::vector<cdag_trace_rec>& out, int64_t fail_at);

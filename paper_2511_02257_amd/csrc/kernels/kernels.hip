@@ -834,6 +834,22 @@ __global__ void __launch_bounds__(256) xsum_kernel(char* __restrict__ arena, con
   }
 }
 
+// ------------------------------------------------------------------ layout conversion
+// Interleaved complex [nt][e] (S: double or float) -> the device layout
+// [nt][2][e] in T, converted on the device (the path that copies host data
+// straight into device memory, without a pinned staging copy in device layout).
+template <typename S, typename T>
+__global__ void __launch_bounds__(256) to_planar(const S* __restrict__ src, T* __restrict__ dst, int64_t nt,
+                                                 int64_t e) {
+  const int64_t total = nt * e;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+    const int64_t t = i / e, x = i - t * e;
+    const S re = src[2 * i], im = src[2 * i + 1];
+    dst[2 * t * e + x] = (T)re;
+    dst[(2 * t + 1) * e + x] = (T)im;
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 namespace {
 // Persistent launches: at most as many workgroups as can be resident at once
@@ -987,6 +1003,20 @@ hipError_t launch_hca(int prec, char* arena, int64_t desc_off, int n_desc, int64
   KernelCall k;
   hca_call(prec, arena, desc_off, n_desc, n_items, &k);
   return launch(k, s);
+}
+
+hipError_t launch_to_planar(bool src_double, bool dst_double, const void* src, void* dst, int64_t nt, int64_t e,
+                           hipStream_t s) {
+  const dim3 grid(grid_for((nt * e + 255) / 256)), block(256);
+  if (src_double && dst_double)
+    hipLaunchKernelGGL((to_planar<double, double>), grid, block, 0, s, (const double*)src, (double*)dst, nt, e);
+  else if (src_double)
+    hipLaunchKernelGGL((to_planar<double, float>), grid, block, 0, s, (const double*)src, (float*)dst, nt, e);
+  else if (dst_double)
+    hipLaunchKernelGGL((to_planar<float, double>), grid, block, 0, s, (const float*)src, (double*)dst, nt, e);
+  else
+    hipLaunchKernelGGL((to_planar<float, float>), grid, block, 0, s, (const float*)src, (float*)dst, nt, e);
+  return hipGetLastError();
 }
 
 hipError_t launch_xsum(char* arena, int64_t desc_off, int64_t entries_off, int n_desc, hipStream_t s) {

@@ -37,6 +37,9 @@ hipError_t launch_hec(int prec, int variant, char* arena, int64_t desc_off, int 
 hipError_t launch_reduce(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s);
 hipError_t launch_hca(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s);
 hipError_t launch_xsum(char* arena, int64_t desc_off, int64_t entries_off, int n_desc, hipStream_t s);
-
+// Interleaved complex [nt][e] (double or float) -> device layout [nt][2][e]
+// (double or float), both in device memory.
+hipError_t launch_to_planar(bool src_double, bool dst_double, const void* src, void* dst, int64_t nt, int64_t e,
+                           hipStream_t s);
 
 }  // namespace cdag

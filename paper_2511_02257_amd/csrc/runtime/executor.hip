@@ -26,6 +26,7 @@
 #include <chrono>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <cstdlib>
 #include <thread>
@@ -55,6 +56,35 @@ double now() {
 
 // Stream roles; trace records and event ids use these numbers.
 enum StreamRole : int { S_COMP = 0, S_H2D = 1, S_D2H = 2, kStreams = 3 };
+}  // namespace
+
+// ---------------------------------------------------------------- static scratch
+// Device memory for cdag_execute_static, which allocates nothing: a fixed
+// array that every GPU the library runs on holds until the process ends.  In
+// host code `scratch` only names the symbol; its device address (one per GPU)
+// comes from hipGetSymbolAddress when a context binds a device, and only that
+// address is ever passed to kernels or copies.
+constexpr int64_t kScratchBytes = CDAG_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;   // device ordinal -> device address of `scratch`
+
+// Called with `device` current; once per device.
+void ensure_scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return;
+  void* ptr = nullptr;
+  hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+  g_scratch_ptr[device] = static_cast<char*>(ptr);
+}
+
+char* scratch_address(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
 }  // namespace
 
 struct Device {
@@ -162,6 +192,7 @@ void device_bind(Ctx& c, int device, void* compute_stream, void* copy_stream) {
     c.dev->device = device;
   }
   HIPC(hipSetDevice(device));
+  ensure_scratch_address(device);
   c.dev->comp = (hipStream_t)compute_stream;
   c.dev->copy = (hipStream_t)copy_stream;
   if (!c.dev->t0) {
@@ -972,6 +1003,77 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
   st->t_device_s = ms * 1e-3;
   st->n_launches = n_launch;
   st->n_graph_segments = n_segments;
+}
+
+// ---------------------------------------------------------------- no allocation
+namespace {
+// The one-stream walk with every byte in the static scratch: leaf uploads copy
+// the library's interleaved host copy into a staging range at the end of the
+// scratch and convert it into place on the device.
+struct StaticOps {
+  const Ctx& c;
+  int prec;
+  char* base;
+  int64_t staging;    // offset of the staging range in the scratch
+  hipStream_t st;
+
+  void wait(int, int, int64_t, int64_t) {}
+  void record(int, int64_t) {}
+  void wait_pass(int, int, int64_t, int64_t) {}
+  void record_pass(int, int64_t, int64_t) {}
+  void upload_leaf(int64_t u, int64_t dev_off) const {
+    const bool src_double = c.leaf_dtype[u] == CDAG_C128;
+    const int64_t nt = c.dag.nt[u], e = c.dag.elems(u) / nt;
+    HIPC(hipMemcpyAsync(base + staging, c.leaf_data[u].data(), c.leaf_data[u].size(), hipMemcpyHostToDevice, st));
+    HIPC(launch_to_planar(src_double, prec == CDAG_FP64, base + staging, base + dev_off, nt, e, st));
+  }
+  void transfer(const PlanRec& r, const PassMap&, int64_t) {
+    if (r.op != OP_H2D || !c.dag.is_leaf(r.node)) throw Error(CDAG_E_STATE, "static execute: a spill in the plan");
+    upload_leaf(r.node, r.dev_off);
+  }
+  int64_t launch(int64_t g, const PassMap&) { return launch_step(c.kplan, g, prec, base, st, nullptr); }
+};
+}  // namespace
+
+void device_execute_static(Ctx& c, int prec, cdag_exec_stats* st) {
+  Device& D = *c.dev;
+  const double tw0 = now();
+  HIPC(hipSetDevice(D.device));
+  char* base = scratch_address(D.device);
+  if (!base) throw Error(CDAG_E_STATE, "static scratch not set up on this device");
+  const Plan& p = c.plan;
+  const KernelPlan& kp = c.kplan;
+  if (p.chunks() != 1) throw Error(CDAG_E_STATE, "static execute runs whole tensors (t_chunks 1)");
+  if (p.n_d2h > 0) throw Error(CDAG_E_BUDGET, "static execute: the plan spills to host memory");
+  int64_t staging = 0;
+  for (int64_t u = 0; u < c.dag.n_leaves; ++u) staging = std::max<int64_t>(staging, (int64_t)c.leaf_data[u].size());
+  const int64_t stage_off = (kp.total_bytes + 255) / 256 * 256;
+  if (stage_off + staging > kScratchBytes)
+    throw Error(CDAG_E_NOMEM, "static execute needs " + std::to_string(stage_off + staging) +
+                                  " bytes of device memory, the static scratch holds " + std::to_string(kScratchBytes));
+  if ((int64_t)c.corr_host.size() * 8 < kp.corr_bytes || (int64_t)c.sums_host.size() * 8 < kp.sums_bytes)
+    throw Error(CDAG_E_STATE, "static execute: result buffers not sized by the plan");
+  hipStream_t s = D.comp;
+  StaticOps ops{c, prec, base, stage_off, s};
+  // descriptor tables (every call: another context may have used the scratch)
+  HIPC(hipMemcpyAsync(base + kp.blob_off, kp.blob.data(), kp.blob.size(), hipMemcpyHostToDevice, s));
+  if (c.leaves_resident)
+    for (int64_t u = 0; u < c.dag.n_leaves; ++u) ops.upload_leaf(u, p.leaf_off[u]);
+  const int64_t G = (int64_t)p.steps.size();
+  int64_t n_launch = walk_steps(c, 0, G, true, false, ops);
+  HIPC(launch_xsum(base, kp.xsum.desc_off, kp.xsum_entries_off, kp.xsum.n_desc, s));
+  ++n_launch;
+  HIPC(hipMemcpyAsync(c.corr_host.data(), base + kp.corr_off, (size_t)kp.corr_bytes, hipMemcpyDeviceToHost, s));
+  HIPC(hipMemcpyAsync(c.sums_host.data(), base + kp.sums_off, (size_t)kp.sums_bytes, hipMemcpyDeviceToHost, s));
+  HIPC(hipStreamSynchronize(s));
+  int64_t n_hec = 0;
+  for (const Launch& L : kp.launches) n_hec += L.type == L_HEC;
+  st->hec_flops = kp.hec_flops;
+  st->hec_bytes = kp.hec_bytes;
+  st->n_hec_launches = n_hec;
+  st->n_launches = n_launch;
+  st->arena_highwater = stage_off + staging;
+  st->t_total_s = now() - tw0;
 }
 
 }  // namespace cdag

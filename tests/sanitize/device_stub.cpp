@@ -11,6 +11,7 @@ void device_destroy(Device*) {}
 void device_bind(Ctx&, int, void*, void*) { no_device(); }
 void device_bind_arena(Ctx&, void*, uint64_t) { no_device(); }
 void device_execute(Ctx&, int, int, cdag_exec_stats*) { no_device(); }
+void device_execute_static(Ctx&, int, cdag_exec_stats*) { no_device(); }
 int64_t device_autotune(Ctx&, int, int, int, bool) { no_device(); }
 int64_t device_autotune_insitu(Ctx&, int, int, int) { no_device(); }
 void trace_execute(const Ctx&, int, std::vector<cdag_trace_rec>&, int64_t) { no_device(); }
