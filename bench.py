@@ -195,10 +195,16 @@ def headline(args, X, W, DeviceRunner, sample):
     opts = dict(leaves_resident=False, wave_lookahead=ALL)
     ctx.set_options(use_graphs=0, **opts)
     tiles = {}
-    if args.tiles_from:
-        with open(args.tiles_from) as f:
-            prev = json.loads(f.read().strip().splitlines()[-1])
-        tiles = prev["config"]["kernel_choices"]
+    if args.tiles_from or args.tiles:
+        if args.tiles_from:
+            with open(args.tiles_from) as f:
+                prev = json.loads(f.read().strip().splitlines()[-1])
+            tiles = prev["config"]["kernel_choices"]
+        else:
+            for part in args.tiles.split(";"):
+                prec, rest = part.split(":")
+                tiles[prec] = {k: [int(x) for x in v.split(".")] for k, v in
+                               (item.split("=") for item in rest.split(","))}
         for prec, table in tiles.items():
             for key, choice in table.items():
                 kname, n = key.split("_N")
@@ -589,6 +595,9 @@ def main():
     ap.add_argument("--tiles-from", default=None, metavar="JSON",
                     help="take the headline's kernel choices from the JSON line of an earlier run "
                          "instead of autotuning (so that profiled runs use the same kernels)")
+    ap.add_argument("--tiles", default=None, metavar="PREC:KIND_N=T.G.S.K,...",
+                    help="the headline's kernel choices written out, e.g. "
+                         "fp64:K32_N64=5.1.1.1,K33_N64=5.1.1.0 (tile, grid, LDS stages, split_k)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--study", default=None, choices=("corr_func", "general"),
                     help="host-only: peak memory and scheduler time on the Table corr-func-shaped "
