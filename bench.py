@@ -47,7 +47,7 @@ METRIC = "CDAG time-to-solution, complex TFLOP/s, H2D GB, peak HBM (FP64 vs mixe
 # products per real product on the 2.5 PFLOP/s dense BF16 matrix cores.
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0 / 3.0, "bf16x6": 2500.0 / 6.0}
 HBM_PEAK = 8000.0   # GB/s
-KIND_NAMES = {0: "K22", 1: "K32", 2: "K33", 3: "HCA", 4: "C1", 5: "C2", 6: "C3"}
+KIND_NAMES = {0: "K22", 1: "K32", 2: "K33", 3: "HCA", 4: "C1", 5: "C2", 6: "C3", 7: "pairs"}
 GAUSS_TILES = {1, 4, 5}   # FP64/FP32 tiles forming a complex product from three real ones
 ALL = (1 << 63) - 1
 
@@ -86,7 +86,7 @@ def kernel_table(records, prec):
         a["ms"] += r["ms"]
         a["flops"] += r["flops"]
         a["bytes"] += r["bytes"]
-        gauss = r["type"] == "hec" and prec in ("fp64", "fp32") and r["variant"] % 6 in GAUSS_TILES
+        gauss = r["type"] == "hec" and prec in ("fp64", "fp32") and (r["variant"] % 6 in GAUSS_TILES or r["variant"] == 24)
         a["pipe_flops"] += r["flops"] * (0.75 if gauss else 1.0)
     for key in [k for k in agg if k.startswith("reduce:")]:
         hk = "hec:" + key.split(":", 1)[1]

@@ -59,6 +59,25 @@ enum cdag_status {
  * the general kinds give the rank-4 intermediates of larger systems). */
 enum cdag_kind { CDAG_K22 = 0, CDAG_K32 = 1, CDAG_K33 = 2, CDAG_HCA = 3,
                  CDAG_C1 = 4, CDAG_C2 = 5, CDAG_C3 = 6 };
+/* Op kind CDAG_SPEC_BASE + i: a contraction over any index pairs, described by
+ * spec i of cdag_set_specs. */
+#define CDAG_SPEC_BASE 16
+
+/* A contraction over any index pairs (Sec. II-B's nodes contract hadron
+ * tensors over whichever indices the quark lines join), per time slice: the
+ * operands have ranks rank_l and rank_r (2..4); axis pair_l[k] of the left
+ * operand is summed against axis pair_r[k] of the right one, k < n_pairs
+ * (1..3, each axis at most once); the output lists the left operand's free
+ * axes in order, then the right one's, and output axis j is axis perm[j] of
+ * that list (perm: a permutation of 0..rank_l + rank_r - 2 n_pairs - 1, an
+ * output rank of 2..4).  Axes count from 0 after the time axis.  A spec that
+ * sums the last n_pairs axes of the left operand against the first ones of
+ * the right one, in order, with perm the identity, is CDAG_C<n_pairs> and is
+ * stored as that kind. */
+typedef struct {
+  int32_t rank_l, rank_r, n_pairs;
+  int32_t pair_l[3], pair_r[3], perm[4];
+} cdag_spec;
 
 /* Schedulers: input order (each graph's tree in post-order, left first),
  * Sibling (Sec. III-A, Algs. 1-3), Tree (Sec. III-B, Algs. 4-8), and Node:
@@ -160,7 +179,8 @@ enum cdag_launch_type { CDAG_LAUNCH_HEC = 0, CDAG_LAUNCH_REDUCE = 1, CDAG_LAUNCH
 typedef struct {
   int32_t type;       /* cdag_launch_type                                                */
   int32_t variant;    /* HEC: kernel variant index; else 0                              */
-  int32_t kinds;      /* bit k set when a contraction of cdag_kind k is in the launch;
+  int32_t kinds;      /* bit k set when a contraction of cdag_kind k is in the launch (bit 7:
+                         a contraction over any index pairs);
                          H2D, D2H: the moved tensor's cdag_kind bit (leaves: 0)         */
   int32_t reserved;
   int64_t step;       /* plan step (wave); -1 for the cross-diagram sum                */
@@ -221,6 +241,16 @@ const char* cdag_last_error(void);
  * operands, root not HCA or HCA not last, unused op. */
 int build_cdag(cdag_ctx* c, const cdag_leaf* leaves, int64_t n_leaves,
                const cdag_graph* graphs, int64_t n_graphs);
+
+/* The contraction specs that op kinds CDAG_SPEC_BASE + i name in the graphs
+ * of the next build_cdag (copied; at most 1024).  Such contractions run in
+ * FP64 and FP32 on a general kernel with index-mapped loads and stores (no
+ * split-K); planning in a split-BF16 mode fails with CDAG_E_INVALID.
+ * build_cdag validates each use against its operands (CDAG_E_INVALID: ranks
+ * that differ from the spec's, axes out of range or repeated, a perm that is
+ * not a permutation, an output rank outside 2..4).  CDAG_E_INVALID for n
+ * outside 0..1024 or a NULL specs with n > 0. */
+int cdag_set_specs(cdag_ctx* c, const cdag_spec* specs, int64_t n);
 
 /* Host-only: a general DAG for scheduling and the memory model, whose nodes
  * may have any number of children (Sec. II-B notes that the schedulers extend

@@ -20,6 +20,7 @@ K22, K32, K33, HCA = 0, 1, 2, 3
 # General contractions of the last c axes of the left operand with the first c
 # axes of the right one (c = 1, 2, 3), for operand and output ranks 2..4.
 C1, C2, C3 = 4, 5, 6
+SPEC_BASE = 16   # kind SPEC_BASE + i: the contraction spec i (any index pairs, output order)
 MIN_RANK, MAX_RANK = 2, 4
 
 # (left rank, right rank) -> output rank, per named kind; HCA outputs a scalar per t.
@@ -51,6 +52,30 @@ def normalize(kind: int, rl: int, rr: int):
 
 class InvalidGraph(ValueError):
     pass
+
+
+def normalize_spec(spec, rl: int, rr: int):
+    """(c, output rank, canonical) of a contraction spec applied to operands of
+    ranks rl, rr.  canonical: the spec sums the last c axes of X against the
+    first c of Y in order and keeps the natural output order, i.e. it is C_c.
+    Raises InvalidGraph for a spec that does not fit the operands or is
+    malformed (repeated axes, a perm that is not a permutation)."""
+    if (spec.rank_l, spec.rank_r) != (rl, rr):
+        raise InvalidGraph("operand ranks differ from the spec's")
+    c = len(spec.pairs)
+    ro = rl + rr - 2 * c
+    if not (1 <= c <= 3 and MIN_RANK <= rl <= MAX_RANK and MIN_RANK <= rr <= MAX_RANK
+            and MIN_RANK <= ro <= MAX_RANK):
+        raise InvalidGraph("spec ranks out of range")
+    xa = [a for a, _ in spec.pairs]
+    yb = [b for _, b in spec.pairs]
+    if len(set(xa)) != c or len(set(yb)) != c or not all(0 <= a < rl for a in xa) \
+            or not all(0 <= b < rr for b in yb):
+        raise InvalidGraph("spec axes out of range or repeated")
+    if sorted(spec.perm) != list(range(ro)):
+        raise InvalidGraph("spec perm is not a permutation of the output axes")
+    canonical = xa == list(range(rl - c, rl)) and yb == list(range(c)) and list(spec.perm) == list(range(ro))
+    return c, ro, canonical
 
 
 @dataclass
@@ -109,11 +134,14 @@ class Dag:
         return out
 
 
-def build(leaves, graphs) -> Dag:
+def build(leaves, graphs, specs=()) -> Dag:
     """Merge the graphs into one DAG by hash-consing (kind, left, right).
 
     `leaves`: sequence of objects with .rank .nvec .nt; `graphs`: sequence with
-    .ops = [(kind, left, right), ...].  Raises InvalidGraph for malformed input.
+    .ops = [(kind, left, right), ...]; `specs`: the contraction specs that op
+    kinds SPEC_BASE + i name.  A spec equal to C1, C2 or C3 on its operands is
+    stored as that kind (and so as K22, K32 or K33 where those apply), so it
+    merges with them.  Raises InvalidGraph for malformed input.
     """
     d = Dag(n_leaves=len(leaves))
     for lf in leaves:
@@ -135,7 +163,7 @@ def build(leaves, graphs) -> Dag:
         local: List[int] = []
         consumed = [0] * len(ops)
         for oi, (kind, l, r) in enumerate(ops):
-            if kind not in _RANKS and kind not in (C1, C2, C3):
+            if kind not in _RANKS and kind not in (C1, C2, C3) and not SPEC_BASE <= kind < SPEC_BASE + len(specs):
                 raise InvalidGraph("bad kind")
             if (kind == HCA) != (oi == len(ops) - 1):
                 raise InvalidGraph("the root, and only the root, must be a trace")
@@ -154,7 +182,12 @@ def build(leaves, graphs) -> Dag:
             lid, rid = ids
             if lid == rid:
                 raise InvalidGraph("identical operands")
-            kind, ro = normalize(kind, d.rank[lid], d.rank[rid])
+            if kind >= SPEC_BASE:
+                c, ro, canonical = normalize_spec(specs[kind - SPEC_BASE], d.rank[lid], d.rank[rid])
+                if canonical:
+                    kind, ro = normalize((C1, C2, C3)[c - 1], d.rank[lid], d.rank[rid])
+            else:
+                kind, ro = normalize(kind, d.rank[lid], d.rank[rid])
             if d.nvec[lid] != d.nvec[rid] or d.nt[lid] != d.nt[rid]:
                 raise InvalidGraph("operand N or Nt mismatch")
             key = (kind, lid, rid)

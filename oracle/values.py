@@ -17,6 +17,10 @@ the paper states for meson and baryon systems):
        e.g. C1 on two rank-3 tensors: O[i,j,l,m] = sum_k X[i,j,k] Y[k,l,m]
        (rank 4, O(N^5) per time slice); K22, K32 and K33 are C1, C1 and C2
        on ranks (2,2), (3,2) and (3,3).
+  General pairs (kind SPEC_BASE + i, the workload's spec i): the axes
+       pairs[k] = (a_k of X, b_k of Y) are summed; the output holds X's free
+       axes in X's order, then Y's free axes in Y's order, rearranged so that
+       output axis j is axis perm[j] of that list.
 The cross-diagram sum of a correlator c is S_c(t) = sum_{g in c} w_g C_g(t),
 taken as a correctly rounded sum (math.fsum) of the FP64 terms.
 """
@@ -29,7 +33,28 @@ import numpy as np
 
 K22, K32, K33, HCA = 0, 1, 2, 3
 C1, C2, C3 = 4, 5, 6
+SPEC_BASE = 16
 _AXES = {K22: 1, K32: 1, K33: 2, C1: 1, C2: 2, C3: 3}
+
+
+def contract_pairs(X: np.ndarray, Y: np.ndarray, pairs, perm) -> np.ndarray:
+    """The general contraction written as one einsum, batched over the leading t
+    axis: summed labels are shared by the paired axes; the output labels are X's
+    free ones, then Y's, taken in the order perm gives."""
+    rl, rr = X.ndim - 1, Y.ndim - 1
+    letters = iter("abcdefghijklmnopqrsuvwxyz")      # t is the time slice
+    lx = [next(letters) for _ in range(rl)]
+    ly = [None] * rr
+    for a, b in pairs:
+        ly[b] = lx[a]
+    for j in range(rr):
+        if ly[j] is None:
+            ly[j] = next(letters)
+    paired_x = {a for a, _ in pairs}
+    paired_y = {b for _, b in pairs}
+    natural = [lx[i] for i in range(rl) if i not in paired_x] + [ly[j] for j in range(rr) if j not in paired_y]
+    out = "".join(natural[p] for p in perm)
+    return np.einsum(f"t{''.join(lx)},t{''.join(ly)}->t{out}", X, Y)
 
 
 def contract(kind: int, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
@@ -58,21 +83,27 @@ def contract_einsum(kind: int, X: np.ndarray, Y: np.ndarray) -> np.ndarray:
     return np.einsum(f"t{free_l}{summed},t{summed}{free_r}->t{free_l}{free_r}", X, Y)
 
 
-def evaluate_graph(leaves: Sequence[np.ndarray], ops) -> np.ndarray:
-    """C_g(t) for one graph: its ops in order; operand >= 0 is a leaf, < 0 an earlier op."""
+def evaluate_graph(leaves: Sequence[np.ndarray], ops, specs=()) -> np.ndarray:
+    """C_g(t) for one graph: its ops in order; operand >= 0 is a leaf, < 0 an earlier op;
+    a kind SPEC_BASE + i uses specs[i] (objects with .pairs and .perm)."""
     vals: List[np.ndarray] = []
     for kind, l, r in ops:
         X = np.asarray(leaves[l], dtype=np.complex128) if l >= 0 else vals[-l - 1]
         Y = np.asarray(leaves[r], dtype=np.complex128) if r >= 0 else vals[-r - 1]
-        vals.append(contract(kind, X, Y))
+        if kind >= SPEC_BASE:
+            sp = specs[kind - SPEC_BASE]
+            vals.append(contract_pairs(X, Y, sp.pairs, sp.perm))
+        else:
+            vals.append(contract(kind, X, Y))
     return vals[-1]
 
 
 def correlators(workload, graphs: Sequence[int] = None) -> Dict[int, np.ndarray]:
     """{graph index: complex128 [nt]} for the chosen graphs (all by default)."""
     data = [lf.data for lf in workload.leaves]
+    specs = getattr(workload, "specs", ())
     idx = range(len(workload.graphs)) if graphs is None else graphs
-    return {g: evaluate_graph(data, workload.graphs[g].ops) for g in idx}
+    return {g: evaluate_graph(data, workload.graphs[g].ops, specs) for g in idx}
 
 
 def trace4_loops(A, B, C, D) -> np.ndarray:

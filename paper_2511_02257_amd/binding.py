@@ -39,6 +39,14 @@ class cdag_op(C.Structure):
     _fields_ = [("kind", C.c_int32), ("left", C.c_int32), ("right", C.c_int32)]
 
 
+class cdag_spec(C.Structure):
+    _fields_ = [("rank_l", C.c_int32), ("rank_r", C.c_int32), ("n_pairs", C.c_int32),
+                ("pair_l", C.c_int32 * 3), ("pair_r", C.c_int32 * 3), ("perm", C.c_int32 * 4)]
+
+
+SPEC_BASE = 16
+
+
 class cdag_graph(C.Structure):
     _fields_ = [("n_ops", C.c_int32), ("corr_id", C.c_int32), ("ops", C.POINTER(cdag_op)),
                 ("w_re", C.c_double), ("w_im", C.c_double)]
@@ -106,6 +114,7 @@ def lib():
             "cdag_destroy": [P],
             "build_cdag": [P, C.POINTER(cdag_leaf), I64, C.POINTER(cdag_graph), I64],
             "cdag_build_general": [P, I64, I64, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)],
+            "cdag_set_specs": [P, C.POINTER(cdag_spec), I64],
             "schedule": [P, C.c_int, C.POINTER(I64), I64, C.POINTER(I64)],
             "set_mem_budget": [P, C.c_uint64],
             "cdag_set_order": [P, C.POINTER(I64), I64],
@@ -142,7 +151,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "cdag_build_general", "schedule",
+EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "cdag_build_general",
+            "cdag_set_specs", "schedule",
             "set_mem_budget", "cdag_set_order", "cdag_set_options", "cdag_set_timing", "cdag_set_time_chunks",
             "cdag_launch_records",
             "cdag_trace_execute", "cdag_dag_stats", "cdag_set_tile", "cdag_get_tile", "cdag_memsim",
@@ -207,6 +217,18 @@ def build_cdag(h, leaves: Sequence, graphs: Sequence) -> None:
         G[g].w_re, G[g].w_im = w.real, w.imag
     _check(lib().build_cdag(h, L, n, G, len(graphs)))
     del keep
+
+
+def cdag_set_specs(h, specs: Sequence) -> None:
+    """specs: objects with rank_l, rank_r, pairs [(left axis, right axis), ...] and perm."""
+    arr = (cdag_spec * max(1, len(specs)))()
+    for i, sp in enumerate(specs):
+        arr[i].rank_l, arr[i].rank_r, arr[i].n_pairs = sp.rank_l, sp.rank_r, len(sp.pairs)
+        for k, (a, b) in enumerate(sp.pairs):
+            arr[i].pair_l[k], arr[i].pair_r[k] = a, b
+        for j, q in enumerate(sp.perm):
+            arr[i].perm[j] = q
+    _check(lib().cdag_set_specs(h, arr, len(specs)))
 
 
 def cdag_build_general(h, n_leaves: int, sizes: Sequence[int], children: Sequence[Sequence[int]]) -> None:
@@ -282,7 +304,7 @@ def cdag_launch_records(h):
     out = []
     for r in buf[:n.value]:
         out.append({"type": LAUNCH_TYPES[r.type], "variant": r.variant,
-                    "kinds": [k for k in range(7) if r.kinds >> k & 1], "step": r.step,
+                    "kinds": [k for k in range(8) if r.kinds >> k & 1], "step": r.step,
                     "n_items": r.n_items, "flops": r.flops, "bytes": r.bytes, "ms": r.ms})
     return out
 
@@ -445,7 +467,9 @@ class Context:
         except Exception:
             pass
 
-    def build_cdag(self, leaves, graphs):
+    def build_cdag(self, leaves, graphs, specs=()):
+        """specs: the contraction specs that op kinds SPEC_BASE + i name."""
+        cdag_set_specs(self.h, specs)
         build_cdag(self.h, leaves, graphs)
         nt_of = []
         for spec in graphs:

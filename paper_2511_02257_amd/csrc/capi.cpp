@@ -127,7 +127,7 @@ int build_cdag(cdag_ctx* h, const cdag_leaf* leaves, int64_t n_leaves, const cda
     for (int64_t g = 0; g < n_graphs; ++g)
       G[g] = {graphs[g].n_ops, graphs[g].corr_id, reinterpret_cast<const cdag::OpIn*>(graphs[g].ops),
               graphs[g].w_re, graphs[g].w_im};
-    cdag::Dag d = cdag::build(L, G);
+    cdag::Dag d = cdag::build(L, G, c.specs);
     // every correlator's graphs must share Nt
     int32_t n_corr = 0;
     for (int32_t x : d.corr) n_corr = std::max(n_corr, x + 1);
@@ -159,6 +159,17 @@ int build_cdag(cdag_ctx* h, const cdag_leaf* leaves, int64_t n_leaves, const cda
     c.planned = false;
     c.have_results = false;
     c.version++;
+  });
+}
+
+int cdag_set_specs(cdag_ctx* h, const cdag_spec* specs, int64_t n) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    need(n >= 0 && n <= 1024 && (n == 0 || specs), CDAG_E_INVALID, "specs: 0..1024 entries, non-NULL");
+    std::vector<cdag::Spec> v(n);
+    static_assert(sizeof(cdag::Spec) == sizeof(cdag_spec), "spec layout");
+    for (int64_t i = 0; i < n; ++i) std::memcpy(&v[i], &specs[i], sizeof(cdag_spec));
+    h->c.specs = std::move(v);
   });
 }
 

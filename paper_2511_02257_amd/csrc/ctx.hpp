@@ -14,6 +14,8 @@ namespace cdag {
 struct Device;   // device-side state, defined in runtime/executor.hip
 
 struct Ctx {
+  // contraction specs (op kinds kSpecBase + i) for the next build_cdag
+  std::vector<Spec> specs;
   // build
   bool built = false;
   Dag dag;

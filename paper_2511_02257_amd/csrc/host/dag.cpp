@@ -71,7 +71,7 @@ bool Dag::in_tree(int64_t u, int64_t t) const {
 }
 
 void Dag::gemm_shape(int64_t u, int64_t* M, int64_t* Ncols, int64_t* K) const {
-  const int c = contracted_axes(kind[u]);
+  const int c = axes(u);
   const int64_t n = nvec[u];
   *M = ipow(n, rank[left[u]] - c);
   *Ncols = ipow(n, rank[right[u]] - c);
@@ -86,9 +86,37 @@ double Dag::flops(int64_t u) const {
   return 8.0 * nt[u] * (double)M * (double)N * (double)K;
 }
 
-Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs) {
+// Checks spec s against operand ranks (rl, rr); returns its output rank and
+// sets *canonical when it is C_c in the engine's own order.
+static int check_spec(const Spec& s, int rl, int rr, const std::string& where, bool* canonical) {
+  if (s.rank_l != rl || s.rank_r != rr) invalid(where + "operand ranks differ from the spec's");
+  const int c = s.n_pairs, ro = rl + rr - 2 * c;
+  if (c < 1 || c > 3 || ro < kMinRank || ro > kMaxRank) invalid(where + "spec ranks out of range");
+  int seen_l = 0, seen_r = 0;
+  bool canon = true;
+  for (int k = 0; k < c; ++k) {
+    const int a = s.pair_l[k], b = s.pair_r[k];
+    if (a < 0 || a >= rl || b < 0 || b >= rr || (seen_l >> a & 1) || (seen_r >> b & 1))
+      invalid(where + "spec axes out of range or repeated");
+    seen_l |= 1 << a;
+    seen_r |= 1 << b;
+    canon = canon && a == rl - c + k && b == k;
+  }
+  int seen_o = 0;
+  for (int j = 0; j < ro; ++j) {
+    const int q = s.perm[j];
+    if (q < 0 || q >= ro || (seen_o >> q & 1)) invalid(where + "spec perm is not a permutation of the output axes");
+    seen_o |= 1 << q;
+    canon = canon && q == j;
+  }
+  *canonical = canon;
+  return ro;
+}
+
+Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs, const std::vector<Spec>& specs) {
   Dag d;
   d.n_leaves = (int64_t)leaves.size();
+  d.specs = specs;
   for (const auto& l : leaves) {
     if (l.rank < kMinRank || l.rank > kMaxRank || l.nvec < 1 || l.nt < 1)
       invalid("leaf: rank must be 2..4, nvec and nt >= 1");
@@ -111,7 +139,8 @@ Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs)
     for (int32_t oi = 0; oi < g.n_ops; ++oi) {
       const OpIn& op = g.ops[oi];
       std::string where = "graph " + std::to_string(gi) + " op " + std::to_string(oi) + ": ";
-      if (op.kind < K22 || op.kind > C3) invalid(where + "unknown kind");
+      if ((op.kind < K22 || op.kind > C3) && !(is_spec(op.kind) && op.kind - kSpecBase < (int64_t)specs.size()))
+        invalid(where + "unknown kind");
       if ((op.kind == HCA) != (oi == g.n_ops - 1)) invalid(where + "the root, and only the root, must be HCA");
       int64_t ids[2];
       const int32_t xs[2] = {op.left, op.right};
@@ -135,8 +164,17 @@ Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs)
         if (rl != 2 || rr != 2) invalid(where + "operand rank mismatch");
         ro = 0;
       } else {
-        const int c = contracted_axes(kind);
-        ro = rl + rr - 2 * c;
+        int c;
+        if (is_spec(kind)) {
+          const Spec& sp = specs[kind - kSpecBase];
+          bool canonical = false;
+          ro = check_spec(sp, rl, rr, where, &canonical);
+          c = sp.n_pairs;
+          if (canonical) kind = c == 1 ? C1 : c == 2 ? C2 : C3;
+        } else {
+          c = contracted_axes(kind);
+          ro = rl + rr - 2 * c;
+        }
         if (kind == K22 && (rl != 2 || rr != 2)) invalid(where + "operand rank mismatch");
         if (kind == K32 && (rl != 3 || rr != 2)) invalid(where + "operand rank mismatch");
         if (kind == K33 && (rl != 3 || rr != 3)) invalid(where + "operand rank mismatch");

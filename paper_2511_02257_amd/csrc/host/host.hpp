@@ -18,6 +18,18 @@ namespace cdag {
 // by the caller), which is scheduled and simulated but never executed.
 enum Kind : int32_t { K22 = 0, K32 = 1, K33 = 2, HCA = 3, C1 = 4, C2 = 5, C3 = 6, NARY = 7, LEAF = -1 };
 constexpr int kMinRank = 2, kMaxRank = 4;
+// Kind kSpecBase + i: a contraction over any index pairs, the context's spec i.
+constexpr int32_t kSpecBase = 16;
+inline bool is_spec(int32_t kind) { return kind >= kSpecBase; }
+
+// A contraction over any index pairs (rank_l, rank_r operands): axis pair_l[k]
+// of the left operand is summed against axis pair_r[k] of the right one; the
+// output lists the left operand's free axes in order, then the right one's,
+// and output axis j is axis perm[j] of that list.
+struct Spec {
+  int32_t rank_l, rank_r, n_pairs;
+  int32_t pair_l[3], pair_r[3], perm[4];
+};
 inline int contracted_axes(int kind) {
   switch (kind) {
     case K22: case K32: case C1: return 1;
@@ -47,6 +59,7 @@ struct Dag {
   // per input graph: correlator id and weight
   std::vector<int32_t> corr;
   std::vector<double> w_re, w_im;
+  std::vector<Spec> specs;                  // contraction specs (kinds kSpecBase + i)
   // A general DAG (build_general) carries per-node sizes in bytes instead of
   // tensor shapes; it can be scheduled and simulated, not planned or run.
   bool general = false;
@@ -70,6 +83,8 @@ struct Dag {
     return kind[u] == HCA ? 0 : elems(u) * elem_bytes;
   }
   bool in_tree(int64_t u, int64_t t) const;   // binary search in ctree(u)
+  // Summed axes of contraction u (named, general or spec kind).
+  int axes(int64_t u) const { return is_spec(kind[u]) ? specs[kind[u] - kSpecBase].n_pairs : contracted_axes(kind[u]); }
   // Algorithmic flops of contraction u (8 per complex multiply-add).
   double flops(int64_t u) const;
   // Exterior contraction u as a complex GEMM per time slice: M = N^(rl - c),
@@ -81,7 +96,12 @@ struct LeafIn { int32_t rank, nvec, nt; };
 struct OpIn { int32_t kind, left, right; };
 struct GraphIn { int32_t n_ops, corr; const OpIn* ops; double w_re, w_im; };
 
-Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs);
+// specs: the contraction specs that op kinds kSpecBase + i name.  A spec equal
+// to C1, C2 or C3 on its operands (the last c axes of the left one against the
+// first c of the right one, in order, natural output order) is stored as that
+// kind.
+Dag build(const std::vector<LeafIn>& leaves, const std::vector<GraphIn>& graphs,
+          const std::vector<Spec>& specs = {});
 // A general DAG: nodes 0..n_leaves-1 are leaves, every other node lists its
 // children (child_off/child, CSR, ids smaller than its own, no repeats) and
 // size[u] is the bytes of u's tensor.  Trees are rooted at the non-leaf nodes

@@ -24,10 +24,46 @@ int64_t put(std::vector<uint8_t>& blob, const T& v) {
 
 int64_t elem_bytes_of(int prec) { return prec == CDAG_FP64 ? 16 : 8; }
 
+IndexMap index_map(const Spec& s, int n) {
+  IndexMap m{};
+  const int rl = s.rank_l, rr = s.rank_r, c = s.n_pairs, ro = rl + rr - 2 * c;
+  auto stride = [&](int rank, int axis) {
+    int64_t x = 1;
+    for (int i = axis + 1; i < rank; ++i) x *= n;
+    return x;
+  };
+  m.n = n;
+  m.dk = c;
+  int dm = 0, dn = 0;
+  for (int a = 0; a < rl; ++a) {
+    bool paired = false;
+    for (int k = 0; k < c; ++k) paired |= s.pair_l[k] == a;
+    if (!paired) m.a_m[dm++] = stride(rl, a);
+  }
+  for (int b = 0; b < rr; ++b) {
+    bool paired = false;
+    for (int k = 0; k < c; ++k) paired |= s.pair_r[k] == b;
+    if (!paired) m.b_n[dn++] = stride(rr, b);
+  }
+  for (int k = 0; k < c; ++k) {
+    m.a_k[k] = stride(rl, s.pair_l[k]);
+    m.b_k[k] = stride(rr, s.pair_r[k]);
+  }
+  m.dm = dm;
+  m.dn = dn;
+  // natural output position q (m digits, then n digits) sits at output axis j
+  // with perm[j] = q
+  int64_t at[8];
+  for (int j = 0; j < ro; ++j) at[s.perm[j]] = stride(ro, j);
+  for (int d = 0; d < dm; ++d) m.c_m[d] = at[d];
+  for (int d = 0; d < dn; ++d) m.c_n[d] = at[dm + d];
+  return m;
+}
+
 std::map<std::pair<int, int>, TuneShape> tune_shapes(const Dag& d) {
   std::map<std::pair<int, int>, TuneShape> out;
   for (int64_t u = d.n_leaves; u < d.n_nodes(); ++u) {
-    if (d.kind[u] == HCA) continue;
+    if (d.kind[u] == HCA || is_spec(d.kind[u])) continue;   // specs always run the general kernel
     Gemm g;
     d.gemm_shape(u, &g.M, &g.N, &g.K);
     auto it = out.find({d.kind[u], d.nvec[u]});
@@ -48,6 +84,7 @@ void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h, int nt_r
     throw Error(CDAG_E_INVALID, "contraction dimensions exceed 2^31");
   const int variant = choice_variant(choice);
   const int ks = k_step(prec);
+  h->map_off = -1;                           // set by the caller for a contraction over index pairs
   h->M = (int32_t)g.M;
   h->N = (int32_t)g.N;
   h->K = (int32_t)g.K;
@@ -107,9 +144,16 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
   // split-K decision per contraction (independent of batching, so results do
   // not depend on how contractions are grouped into launches)
   auto tile_of = [&](int64_t u) -> int {
+    if (is_spec(d.kind[u])) return choice_of(variant_of(kGenTile, 1, 2), false);
     auto it = tiles.find(std::make_tuple(prec, (int)d.kind[u], (int)d.nvec[u]));
     return it != tiles.end() ? it->second : default_tile(prec, d.kind[u], d.nvec[u]);
   };
+  for (int64_t u = d.n_leaves; u < d.n_nodes(); ++u)
+    if (is_spec(d.kind[u]) && prec >= 2)
+      throw Error(CDAG_E_INVALID, "contractions over any index pairs run in FP64 and FP32 only");
+  // one index map per (spec, N), laid out after the descriptor tables
+  std::map<std::pair<int32_t, int32_t>, int64_t> map_index;
+  std::vector<IndexMap> maps;
   // A pass covers nt / t_chunks slices; the split count follows the whole
   // contraction (all nt slices), so it does not change with t_chunks and the
   // results stay bit-identical.
@@ -151,10 +195,11 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
     };
     for (int64_t s = 0; s < S; ++s) {
       kp.launch_off.push_back((int64_t)kp.launches.size());
-      std::vector<HecDesc> hec[kNumVariants];
-      int64_t tiles[kNumVariants] = {0};
-      double v_flops[kNumVariants] = {0}, v_bytes[kNumVariants] = {0};
-      int32_t v_kinds[kNumVariants] = {0};
+      constexpr int kGroups = kNumVariants + 1;   // the variants, then the general kernel
+      std::vector<HecDesc> hec[kGroups];
+      int64_t tiles[kGroups] = {0};
+      double v_flops[kGroups] = {0}, v_bytes[kGroups] = {0};
+      int32_t v_kinds[kGroups] = {0};
       double red_bytes = 0, hca_flops = 0, hca_bytes = 0;
       int32_t red_kinds = 0;
       std::vector<RedDesc> red;
@@ -163,7 +208,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
       // algorithmic bytes of a launch: each distinct operand read once, each
       // output written once (operands shared by contractions of one launch,
       // e.g. a closing meson traced against many roots, count once)
-      std::set<int64_t> v_seen[kNumVariants], hca_seen;
+      std::set<int64_t> v_seen[kGroups], hca_seen;
       auto operand_bytes = [&](std::set<int64_t>& seen, int64_t x) {
         return seen.insert(x).second ? (double)p.tsize(d, x) : 0.0;
       };
@@ -189,14 +234,25 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
         }
         HecDesc h{};
         decomp(u, h);
-        const int tl = choice_variant(tile_of(u));
+        const bool gen = is_spec(d.kind[u]);
+        const int tl = gen ? kGenVariant : choice_variant(tile_of(u));
+        h.map_off = -1;
+        if (gen) {
+          const auto key = std::make_pair(d.kind[u], d.nvec[u]);
+          auto it = map_index.find(key);
+          if (it == map_index.end()) {
+            it = map_index.emplace(key, (int64_t)maps.size()).first;
+            maps.push_back(index_map(d.specs[d.kind[u] - kSpecBase], d.nvec[u]));
+          }
+          h.map_off = -2 - it->second;                   // fixed up below (needs the layout)
+        }
         const double ab = operand_bytes(v_seen[tl], d.left[u]) + operand_bytes(v_seen[tl], d.right[u]) +
                           (double)p.tsize(d, u);
         kp.hec_flops += fl;
         kp.hec_bytes += ab;
         v_flops[tl] += fl;
         v_bytes[tl] += ab;
-        v_kinds[tl] |= 1 << d.kind[u];
+        v_kinds[tl] |= 1 << std::min<int32_t>(d.kind[u], 7);
         h.a_off = a_off;
         h.b_off = b_off;
         h.c_off = r.dev_off + shift;
@@ -221,7 +277,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
         }
         hec[tl].push_back(h);
       }
-      for (int tl = 0; tl < kNumVariants; ++tl) {
+      for (int tl = 0; tl < kGroups; ++tl) {
         if (hec[tl].empty()) continue;
         Launch L{L_HEC, tl, (int32_t)hec[tl].size(), 0, tiles[tl], 0};
         L.flops = v_flops[tl];
@@ -273,6 +329,9 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
   for (auto& x : xd) put(kp.blob, x);
   const int64_t entries_host = (int64_t)kp.blob.size();
   for (auto& e : xe) put(kp.blob, e);
+  while (kp.blob.size() % 16) kp.blob.push_back(0);
+  const int64_t maps_host = (int64_t)kp.blob.size();
+  for (auto& m : maps) put(kp.blob, m);
 
   // final layout and fix-ups of buffer-relative offsets
   kp.blob_off = align256(kp.tensors_end);
@@ -281,6 +340,11 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
   kp.total_bytes = align256(kp.sums_off + kp.sums_bytes);
   for (Launch& L : kp.launches) {
     L.desc_off = kp.blob_off + L.host_desc;
+    if (L.type == L_HEC && L.tile == kGenVariant) {
+      auto* h = reinterpret_cast<HecDesc*>(kp.blob.data() + L.host_desc);
+      for (int32_t i = 0; i < L.n_desc; ++i)
+        h[i].map_off = kp.blob_off + maps_host + (-2 - h[i].map_off) * (int64_t)sizeof(IndexMap);
+    }
     if (L.type == L_HCA) {
       auto* h = reinterpret_cast<HcaDesc*>(kp.blob.data() + L.host_desc);
       for (int32_t i = 0; i < L.n_desc; ++i) h[i].out_off = kp.corr_off + (-1 - h[i].out_off);

@@ -44,6 +44,12 @@ inline int variant_stages(int v) { return 2 - v / (2 * kNumTiles); }
 // split count depends only on the contraction and the choice, never on how
 // contractions are grouped into launches.
 constexpr int kNumChoices = 2 * kNumVariants;
+// Contractions over any index pairs run in their own launches of the general
+// kernel (index-mapped loads and stores, 32 x 32 tiles of 256 threads, no
+// split-K), launch variant kGenVariant; FP64 and FP32 only.
+constexpr int kGenVariant = kNumVariants;
+constexpr int kGenTile = 1;
+static_assert(kGenVariant == kGenVariantId, "general kernel's launch variant");
 inline int choice_of(int variant, bool split_k) { return variant + kNumVariants * (split_k ? 0 : 1); }
 inline int choice_variant(int c) { return c % kNumVariants; }
 inline bool choice_split_k(int c) { return c < kNumVariants; }
@@ -95,6 +101,8 @@ struct KernelPlan {
 };
 
 int64_t elem_bytes_of(int prec);                 // 16 for FP64, 8 otherwise
+// Strides of spec s on tensors of dimension n (desc.hpp, IndexMap).
+IndexMap index_map(const Spec& s, int n);
 KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTable& tiles);
 
 }  // namespace cdag

@@ -22,13 +22,31 @@ constexpr int kNumTiles = 6;
 constexpr TileShape kTileShapes[kNumTiles] = {
     {64, 64, 256}, {32, 32, 256}, {48, 48, 64}, {128, 64, 256}, {64, 32, 256}, {64, 64, 512}};
 
+// Launch variant of the general kernel (contractions over any index pairs):
+// one past the tile x grid x stages variants.
+constexpr int kGenVariantId = 4 * kNumTiles;
+
 // One exterior contraction inside a grouped launch.
 struct HecDesc {
   int64_t a_off, b_off, c_off;   // t = 0 slice of A, B and C
   int64_t ws_off;                // split-K partials [splits][nt][2][M*N] (accumulator type), or -1
+  int64_t map_off;               // IndexMap of a contraction over any index pairs, or -1
   int32_t M, N, K, nt;
   int32_t tiles_m, tiles_n, splits, k_split;   // k_split: K range per split (multiple of the k-step)
   int32_t tile_begin, tile_count;              // this op's work items in the launch
+};
+
+// Element strides of a contraction over any index pairs, digit by digit.  The
+// GEMM indices m (the left operand's free axes, in order), k (the summed axes,
+// in pair order) and n (the right operand's free axes) are mixed-radix numbers
+// in N, most significant digit first; the element offset within one plane is
+// A(m, k) = sum_d m_d a_m[d] + sum_d k_d a_k[d], and likewise for B(k, n) and
+// for C(m, n), whose strides carry the output's axis order.
+struct IndexMap {
+  int32_t n, dm, dk, dn;         // radix N; digits of m, k and n
+  int64_t a_m[3], a_k[3];
+  int64_t b_k[3], b_n[3];
+  int64_t c_m[3], c_n[3];
 };
 
 // Fixed-order reduction of split-K partials into C (one per split op).

@@ -109,7 +109,22 @@ struct ItemView {
   const T* B;
   int M, N, K, t, sp, m0, n0, kbeg, kend;
   bool avec;         // rows of A allow 8-element vector loads
+  const IndexMap* map;   // a contraction over any index pairs, else nullptr
 };
+
+// Element offset of a mixed-radix index x (nd digits in radix n, most
+// significant first) with per-digit strides st.
+__device__ __forceinline__ int64_t digit_offset(int64_t x, int nd, int n, const int64_t* st) {
+  int64_t off = 0;
+#pragma unroll
+  for (int d = 2; d >= 0; --d) {
+    if (d < nd) {
+      off += (x % n) * st[d];
+      x /= n;
+    }
+  }
+  return off;
+}
 
 template <typename T, int BM, int BN>
 __device__ __forceinline__ ItemView<T> view_item(char* arena, const HecDesc* descs, int n_desc, int64_t item) {
@@ -127,7 +142,8 @@ __device__ __forceinline__ ItemView<T> view_item(char* arena, const HecDesc* des
   v.kend = w.kend;
   v.A = reinterpret_cast<const T*>(arena + w.h->a_off) + (int64_t)w.t * 2 * v.M * v.K;
   v.B = reinterpret_cast<const T*>(arena + w.h->b_off) + (int64_t)w.t * 2 * v.K * v.N;
-  v.avec = (v.K & 7) == 0;
+  v.map = w.h->map_off >= 0 ? reinterpret_cast<const IndexMap*>(arena + w.h->map_off) : nullptr;
+  v.avec = (v.K & 7) == 0 && v.map == nullptr;
   return v;
 }
 
@@ -203,13 +219,16 @@ __device__ __forceinline__ void load16b(T (&r)[16 / sizeof(T)], const T* src, in
 // items are still reading from L2.
 template <typename T, typename V, bool NT>
 __device__ __forceinline__ void store_block(T* C, int M, int N, int row0, int col, const V& re, const V& im,
-                                           int lk) {
+                                           int lk, const IndexMap* map = nullptr) {
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int m = row0 + Mfma<T>::row(lk, v);
     if (m < M && col < N) {
-      T* pr = &C[(int64_t)m * N + col];
-      T* pi = &C[(int64_t)M * N + (int64_t)m * N + col];
+      // a general contraction writes C(m, n) at its output axis order
+      const int64_t off = map ? digit_offset(m, map->dm, map->n, map->c_m) + digit_offset(col, map->dn, map->n, map->c_n)
+                              : (int64_t)m * N + col;
+      T* pr = &C[off];
+      T* pi = &C[(int64_t)M * N + off];
       if (NT) {
         __builtin_nontemporal_store(re[v], pr);
         __builtin_nontemporal_store(im[v], pi);
@@ -225,7 +244,9 @@ __device__ __forceinline__ void store_block(T* C, int M, int N, int row0, int co
 // buffer refilled from the register prefetch (two barriers per k-chunk, half
 // the LDS, more workgroups per compute unit).  PF: a workgroup that strides
 // over several items (persistent grid) prefetches its next item.
-template <typename T, class TL, int ST, bool PF>
+// GEN: every work item is a contraction over any index pairs; operands are
+// loaded and the output stored through its IndexMap, element by element.
+template <typename T, class TL, int ST, bool PF, bool GEN = false>
 __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs,
                                                      int n_desc, int64_t n_items) {
   typedef typename Mfma<T>::V V;
@@ -252,8 +273,17 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
       if (seg < SEGA) {
         const int p = seg / (2 * BM), r = (seg % (2 * BM)) >> 1, hh = seg & 1;
         const int am = o.m0 + r, ak = k0 + 8 * hh;
-        const int av = am < o.M ? max(0, min(8, o.kend - ak)) : 0;
-        load8<T>(ra[q], o.A + (int64_t)p * o.M * o.K + (int64_t)am * o.K + ak, av, o.avec);
+        if constexpr (GEN) {
+          const IndexMap& mp = *o.map;
+          const T* plane = o.A + (int64_t)p * o.M * o.K;
+          const int64_t row = am < o.M ? digit_offset(am, mp.dm, mp.n, mp.a_m) : 0;
+#pragma unroll
+          for (int i = 0; i < 8; ++i)
+            ra[q][i] = (am < o.M && ak + i < o.kend) ? plane[row + digit_offset(ak + i, mp.dk, mp.n, mp.a_k)] : T(0);
+        } else {
+          const int av = am < o.M ? max(0, min(8, o.kend - ak)) : 0;
+          load8<T>(ra[q], o.A + (int64_t)p * o.M * o.K + (int64_t)am * o.K + ak, av, o.avec);
+        }
       }
     }
     const bool bvw = (o.N % W) == 0;
@@ -264,8 +294,17 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
         const int p = seg / (BK * (BN / W)), rem = seg % (BK * (BN / W));
         const int kk = rem / (BN / W), cw = rem % (BN / W);
         const int bkk = k0 + kk, bn = o.n0 + W * cw;
-        const int bv = bkk < o.kend ? max(0, min(W, o.N - bn)) : 0;
-        load16b<T>(rb[q], o.B + (int64_t)p * o.K * o.N + (int64_t)bkk * o.N + bn, bv, bvw);
+        if constexpr (GEN) {
+          const IndexMap& mp = *o.map;
+          const T* plane = o.B + (int64_t)p * o.K * o.N;
+          const int64_t row = bkk < o.kend ? digit_offset(bkk, mp.dk, mp.n, mp.b_k) : 0;
+#pragma unroll
+          for (int i = 0; i < W; ++i)
+            rb[q][i] = (bkk < o.kend && bn + i < o.N) ? plane[row + digit_offset(bn + i, mp.dn, mp.n, mp.b_n)] : T(0);
+        } else {
+          const int bv = bkk < o.kend ? max(0, min(W, o.N - bn)) : 0;
+          load16b<T>(rb[q], o.B + (int64_t)p * o.K * o.N + (int64_t)bkk * o.N + bn, bv, bvw);
+        }
       }
     }
   };
@@ -404,7 +443,7 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
           }
         }
         store_block<T, V, true>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li, re, im,
-                                lk);
+                                lk, GEN ? cur.map : nullptr);
       }
     if (!has_next) break;
     item = next;
@@ -940,6 +979,15 @@ hipError_t launch(KernelCall& k, hipStream_t s) {
 // LDS stages, 1: one; grid 0: persistent, 1: one workgroup per work item.
 hipError_t hec_call(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
                     KernelCall* k) {
+  if (variant == kGenVariantId) {        // contractions over any index pairs: FP64 and FP32
+    if (prec > 1) return hipErrorInvalidValue;
+    k->fn = prec == 0 ? reinterpret_cast<const void*>(&hec_mfma<double, Tile1, 2, false, true>)
+                      : reinterpret_cast<const void*>(&hec_mfma<float, Tile1, 2, false, true>);
+    k->block = Tile1::NTH;
+    k->grid = grid_for(n_items);
+    set_args(*k, arena, arena + desc_off, n_desc, n_items);
+    return hipSuccess;
+  }
   if (variant < 0 || variant >= 4 * kNumTiles || prec < 0 || prec > 3) return hipErrorInvalidValue;
   const int tile = variant % kNumTiles;
   const bool persistent = (variant / kNumTiles) % 2 == 0;

@@ -28,6 +28,7 @@ import numpy as np
 
 K22, K32, K33, HCA = 0, 1, 2, 3
 C1, C2, C3 = 4, 5, 6      # general: last c axes of X against the first c of Y
+SPEC_BASE = 16            # op kind SPEC_BASE + i: the workload's contraction spec i
 KIND_NAMES = {K22: "K22", K32: "K32", K33: "K33", HCA: "HCA", C1: "C1", C2: "C2", C3: "C3"}
 
 
@@ -37,6 +38,19 @@ class Leaf:
     nvec: int
     nt: int
     data: Optional[np.ndarray] = None  # complex128, shape [nt] + [nvec]*rank
+
+
+@dataclass
+class Spec:
+    """A contraction over any index pairs: operands of ranks rank_l and rank_r,
+    axis pairs[k][0] of the left one summed against axis pairs[k][1] of the
+    right one; the output holds the left operand's free axes in order, then the
+    right one's, arranged so that output axis j is axis perm[j] of that list
+    (axes count from 0 after the time slice)."""
+    rank_l: int
+    rank_r: int
+    pairs: Tuple[Tuple[int, int], ...]
+    perm: Tuple[int, ...]
 
 
 @dataclass
@@ -57,6 +71,7 @@ class Workload:
     budget_bytes: Optional[int] = None
     budget_rule: str = "unlimited"
     meta: dict = field(default_factory=dict)
+    specs: List[Spec] = field(default_factory=list)   # op kinds SPEC_BASE + i
 
     @property
     def n_corr(self) -> int:
@@ -225,6 +240,65 @@ def rank4_mix(n_bar=5, n_mes=4, n_r4=2, nvec=6, nt=3, n_graphs=24, sigma=None, n
     r4 = list(range(n_bar + n_mes, n_bar + n_mes + n_r4))
     graphs = [_rank4_graph(rg, bar, mes, r4, n_corr) for _ in range(n_graphs)]
     return Workload(name, leaves, graphs, meta=dict(seed=seed, kind="rank4"))
+
+
+# Contraction specs over other index pairs than the trailing-against-leading
+# ones, with output orders other than the natural one (Spec); the fifth is C1
+# on two baryons written as a spec.
+PAIR_SPECS = (
+    Spec(3, 2, ((0, 1),), (2, 0, 1)),          # X[i,j,l] Y[k,i] -> O[k,j,l]
+    Spec(3, 3, ((2, 0), (0, 2)), (1, 0)),      # X[a,b,c] Y[c,e,a] -> O[e,b]
+    Spec(2, 2, ((0, 0),), (1, 0)),             # X[i,j] Y[i,k] -> O[k,j]
+    Spec(4, 3, ((1, 0), (3, 2)), (0, 2, 1)),   # X[a,b,c,d] Y[b,e,d] -> O[a,e,c]
+    Spec(3, 3, ((2, 0),), (0, 1, 2, 3)),       # C1 on two baryons
+    Spec(3, 3, ((1, 1),), (3, 1, 0, 2)),       # X[a,b,c] Y[d,b,e] -> O[e,c,a,d]
+)
+
+
+def _pairs_graph(rg, bar: List[int], mes: List[int], r4: List[int], n_corr: int) -> GraphSpec:
+    """One graph through contractions over other index pairs (PAIR_SPECS,
+    kinds SPEC_BASE + i); templates (distinct leaves a, b, c, ...):
+      0: HCA(S1(S0(B_a, M_b), B_c), M_d)
+      1: HCA(S2(M_a, M_b), M_c)
+      2: HCA(S1(B_a, B_b), S2(M_a, M_b))
+      3: HCA(S1(S3(R, B_a), B_b), M_c)
+      4: HCA(K33(C2(S4(B_a, B_b), B_c), B_d), M_e)     S4 is C1 written as a spec
+      5: HCA(K33(C2(C1(B_a, B_b), B_c), B_d), M_e)     (merges with template 4)
+      6: HCA(C2(S5(B_a, B_b), M_c), M_d)"""
+    S = [SPEC_BASE + i for i in range(len(PAIR_SPECS))]
+    t = int(rg.integers(0, 7))
+    b = [bar[int(i)] for i in rg.choice(len(bar), size=4, replace=False)]
+    m = [mes[int(i)] for i in rg.choice(len(mes), size=3, replace=False)]
+    r = r4[int(rg.integers(0, len(r4)))]
+    if t == 0:
+        ops = [(S[0], b[0], m[0]), (S[1], -1, b[1]), (HCA, -2, m[1])]
+    elif t == 1:
+        ops = [(S[2], m[0], m[1]), (HCA, -1, m[2])]
+    elif t == 2:
+        ops = [(S[1], b[0], b[1]), (S[2], m[0], m[1]), (HCA, -1, -2)]
+    elif t == 3:
+        ops = [(S[3], r, b[0]), (S[1], -1, b[1]), (HCA, -2, m[0])]
+    elif t in (4, 5):
+        ops = [(S[4] if t == 4 else C1, b[0], b[1]), (C2, -1, b[2]), (K33, -2, b[3]), (HCA, -3, m[0])]
+    else:
+        ops = [(S[5], b[0], b[1]), (C2, -1, m[0]), (HCA, -2, m[1])]
+    return GraphSpec(ops, int(rg.integers(0, n_corr)), float(rg.choice(np.array([-1.0, 1.0]))))
+
+
+def pairs_mix(n_bar=5, n_mes=5, n_r4=2, nvec=6, nt=3, n_graphs=30, sigma=None, n_corr=2, seed=1007,
+              with_data=True, name="pairs") -> Workload:
+    """Graphs through contractions over other index pairs and output orders
+    (PAIR_SPECS), beside named and general kinds; entries N(0,1)/N."""
+    rt, rg = _streams(seed)
+    sg = 1.0 / nvec if sigma is None else sigma
+    leaves = [_leaf(rt, 3, nvec, nt, sg, with_data) for _ in range(n_bar)]
+    leaves += [_leaf(rt, 2, nvec, nt, sg, with_data) for _ in range(n_mes)]
+    leaves += [_leaf(rt, 4, nvec, nt, sg, with_data) for _ in range(n_r4)]
+    bar = list(range(n_bar))
+    mes = list(range(n_bar, n_bar + n_mes))
+    r4 = list(range(n_bar + n_mes, n_bar + n_mes + n_r4))
+    graphs = [_pairs_graph(rg, bar, mes, r4, n_corr) for _ in range(n_graphs)]
+    return Workload(name, leaves, graphs, meta=dict(seed=seed, kind="pairs"), specs=list(PAIR_SPECS))
 
 
 BATCHED_NVECS = (32, 48, 64, 96, 128)

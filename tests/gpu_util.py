@@ -15,7 +15,7 @@ def run(wl, policy="tree", prec="fp64", batched=False, budget=None, leaves_resid
     import paper_2511_02257_amd as X
     from paper_2511_02257_amd.device import DeviceRunner
     ctx = X.Context()
-    ctx.build_cdag(wl.leaves, wl.graphs)
+    ctx.build_cdag(wl.leaves, wl.graphs, getattr(wl, "specs", ()))
     order = ctx.schedule(policy)
     ctx.set_mem_budget(budget)
     ctx.set_options(leaves_resident=leaves_resident, wave_max=wave_max,
@@ -58,7 +58,7 @@ def sum_errors(wl, sums, ref_vals):
 def oracle_plan_counts(wl, policy, elem_bytes, budget, batched, leaves_resident=False, lookahead=0,
                        t_chunks=1):
     from oracle import planner as OP
-    d = OD.build(wl.leaves, wl.graphs)
+    d = OD.build(wl.leaves, wl.graphs, getattr(wl, "specs", ()))
     order = OS.schedule(d, policy, elem_bytes)
     res = OP.plan(d, order, elem_bytes=elem_bytes,
                   budget=OP.UNLIMITED if budget is None else budget,

@@ -143,6 +143,32 @@ void malformed(cdag_ctx* c) {
   expect(cdag_build_general(c, 3, 2, sz, off, dup) == CDAG_E_INVALID, "repeated child refused");
   const int64_t order[1] = {0};
   expect(cdag_set_order(c, order, 1) != CDAG_OK, "bad order refused");
+  expect(cdag_set_specs(c, nullptr, 2) == CDAG_E_INVALID, "NULL specs refused");
+}
+
+// Contractions over index pairs: a chain through a spec on two baryons
+// (pairs (2,0) and (0,2), output reversed), scheduled and planned; then a
+// spec that does not fit its operands.
+void index_pairs(cdag_ctx* c) {
+  const cdag_spec specs[2] = {{3, 3, 2, {2, 0, 0}, {0, 2, 0}, {1, 0, 0, 0}},
+                              {3, 2, 1, {0, 0, 0}, {1, 0, 0}, {2, 0, 1, 0}}};
+  expect(cdag_set_specs(c, specs, 2) == CDAG_OK, "set_specs");
+  cdag_leaf L[4] = {{3, 4, 2, CDAG_C128, nullptr}, {3, 4, 2, CDAG_C128, nullptr},
+                    {2, 4, 2, CDAG_C128, nullptr}, {2, 4, 2, CDAG_C128, nullptr}};
+  const cdag_op ops[3] = {{CDAG_SPEC_BASE + 1, 0, 2}, {CDAG_SPEC_BASE, -1, 1}, {CDAG_HCA, -2, 3}};
+  cdag_graph g = {3, 0, ops, 1.0, 0.0};
+  expect(build_cdag(c, L, 4, &g, 1) == CDAG_OK, "build with specs");
+  int64_t n = 0;
+  expect(schedule(c, CDAG_SCHED_TREE, nullptr, 0, &n) == CDAG_OK && n == 3, "schedule with specs");
+  cdag_plan_stats st;
+  expect(cdag_plan(c, CDAG_FP64, 1, &st) == CDAG_OK, "plan with specs");
+  expect(cdag_plan(c, CDAG_BF16X3, 1, &st) == CDAG_E_INVALID, "split-BF16 refuses specs");
+  std::vector<cdag_plan_stats> again(1);
+  expect(cdag_plan(c, CDAG_FP32, 0, again.data()) == CDAG_OK, "per-contraction plan with specs");
+  const cdag_op wrong[2] = {{CDAG_SPEC_BASE + 1, 0, 1}, {CDAG_HCA, -1, 3}};
+  cdag_graph w = {2, 0, wrong, 1.0, 0.0};
+  expect(build_cdag(c, L, 4, &w, 1) == CDAG_E_INVALID, "spec on the wrong ranks refused");
+  expect(cdag_set_specs(c, nullptr, 0) == CDAG_OK, "clear specs");
 }
 }  // namespace
 
@@ -156,6 +182,7 @@ int main() {
     exercise(c, true);
   }
   malformed(c);
+  index_pairs(c);
   build_mixed(c, 8, 4, 40, 4);
   exercise(c, false);
   expect(cdag_destroy(c) == CDAG_OK, "destroy");

@@ -136,3 +136,50 @@ def test_batched_per_contraction_matches_waves(batched):
     ta, tb = a["stats"]["t_total_s"], b["stats"]["t_total_s"]
     print(f"batched fp32: per-contraction {ta * 1e3:.1f} ms ({a['stats']['n_launches']} launches), "
           f"waves {tb * 1e3:.1f} ms ({b['stats']['n_launches']} launches)")
+
+
+@pytest.fixture(scope="module")
+def tritium():
+    """The Table corr-func tritium-shaped DAG (BxBxB, N = 32, 6085 graphs merged
+    into 7588 contractions through rank-4 intermediates: C1 of two baryons,
+    the O(N^5) step, then C2 and K33) with seeded entries and Nt = 2.  Sample:
+    graphs that together use every distinct C1 -> C2 pair of the DAG, plus ten
+    seeded ones."""
+    from synth import corr_func as CF
+    wl = CF.with_data(CF.corr_func_like("tritium", nt=2))
+    keys, sample = set(), []
+    for g, spec in enumerate(wl.graphs):
+        ops = spec.ops
+        mine = set()
+        for i, (k, l, r) in enumerate(ops):
+            if k == W.C2 and r >= 0 and ops[-l - 1][0] == W.C1:
+                mine.add((ops[-l - 1][1], ops[-l - 1][2], r))
+        if mine - keys:
+            keys |= mine
+            sample.append(g)
+    rng = np.random.default_rng(78)
+    sample = sorted(set(sample) | {int(g) for g in rng.choice(len(wl.graphs), size=10, replace=False)})
+    return wl, sample, OV.correlators(wl, sample)
+
+
+# Split-BF16 with two pieces carries up to ~3 * 2^-16 relative error per
+# product; the tritium-shaped chains run six to seven contractions deep on both
+# sides of the trace (measured 5.5e-5), so its bound here is 1e-4.
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 1e-4), ("bf16x6", 1e-5)])
+def test_tritium_shaped_full(tritium, prec, tol):
+    wl, sample, ref = tritium
+    r = run(wl, "tree", prec, True, wave_lookahead=ALL, autotune=True)
+    p = r["stats"]["plan"]
+    assert p["n_contr"] == 7588
+    err = np.array([np.linalg.norm(r["corr"][g] - ref[g]) / np.linalg.norm(ref[g]) for g in sample])
+    print(f"tritium-shaped {prec}: {p['n_contr']} contractions, waves={p['n_steps']}, sample {len(sample)} graphs, "
+          f"max rel {err.max():.3e} median {np.median(err):.3e}, device {r['stats']['t_device_s'] * 1e3:.1f} ms")
+    assert err.max() <= tol
+    if prec == "fp64":
+        # default kernel choices: waves and one contraction per step give the
+        # same bits (split counts do not depend on grouping)
+        a = run(wl, "tree", prec, True, wave_lookahead=ALL)
+        b = run(wl, "input", prec, False)
+        for g in sample:
+            assert np.array_equal(a["corr"][g].view(np.uint64), b["corr"][g].view(np.uint64))
+            assert np.linalg.norm(a["corr"][g] - ref[g]) / np.linalg.norm(ref[g]) <= tol

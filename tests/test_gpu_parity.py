@@ -546,3 +546,43 @@ def test_time_slice_passes_and_stream_modes(nt4_workloads, prec, mode):
                 got = np.concatenate(r["corr"]).view(np.uint64)
                 print(f"  steps={p['n_steps']} evict={p['n_evict']} d2h={p['n_d2h']}")
                 assert np.array_equal(got, want), (wl.name, chunks, batched, look, mode)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_index_pair_contractions(prec):
+    """Contractions over other index pairs and output orders (the general
+    kernel: index-mapped loads and stores), beside named and general kinds,
+    N = 7 (ragged tiles) and N = 16, in every schedule, waves and one launch
+    per contraction, under a budget that forces spills: against the oracle,
+    identical bits across schedules and batching."""
+    from oracle import dag as OD, schedules as OS
+    for nvec, nt in ((7, 3), (16, 2)):
+        wl = W.pairs_mix(nvec=nvec, nt=nt, n_graphs=40, seed=50 + nvec)
+        ref = OV.correlators(wl)
+        d = OD.build(wl.leaves, wl.graphs, wl.specs)
+        assert any(k >= W.SPEC_BASE for k in d.kind)
+        eb = 16 if prec == "fp64" else 8
+        budget = OS.memsim(d, OS.input_order(d), eb)["peak_live"] // 2
+        base = None
+        for policy, batched, look, bud in (("input", False, 0, None), ("tree", True, 0, None),
+                                           ("tree", True, 1 << 62, None), ("sibling", True, 16, budget),
+                                           ("node", False, 0, budget)):
+            r = run(wl, policy, prec, batched, budget=bud, wave_lookahead=look)
+            err = rel_errors(r["corr"], ref)
+            print(f"pairs N={nvec} {prec} {policy} batched={batched} look={look} budget={bud}: "
+                  f"max rel {err.max():.3e}")
+            assert err.max() <= TOL[prec]
+            assert sum_errors(wl, r["sums"], ref) <= TOL[prec]
+            bits = np.concatenate(r["corr"]).view(np.uint64)
+            if base is None:
+                base = bits
+            assert np.array_equal(bits, base)
+
+
+def test_index_pair_contractions_refused_in_split_bf16():
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd import binding as B
+    wl = W.pairs_mix(nvec=5, nt=2, n_graphs=10, seed=3)
+    with pytest.raises(X.CdagError) as e:
+        run(wl, "tree", "bf16x3", True)
+    assert e.value.code == B.E_INVALID

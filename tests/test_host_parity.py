@@ -24,7 +24,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "cdag.h")
 
 def ctx_for(wl):
     c = X.Context()
-    c.build_cdag(wl.leaves, wl.graphs)
+    c.build_cdag(wl.leaves, wl.graphs, wl.specs)
     return c
 
 
@@ -100,6 +100,8 @@ def _random_workloads():
                                  with_data=False))
     for seed in range(10):
         out.append(W.rank4_mix(nvec=3, nt=2, n_graphs=16, seed=300 + seed, with_data=False))
+    for seed in range(6):
+        out.append(W.pairs_mix(nvec=3, nt=2, n_graphs=20, seed=400 + seed, with_data=False))
     return out
 
 
@@ -109,7 +111,7 @@ WORKLOADS = _random_workloads()
 @pytest.mark.parametrize("i", range(len(WORKLOADS)))
 def test_schedules_and_plans_match_oracle(i):
     wl = WORKLOADS[i]
-    d = OD.build(wl.leaves, wl.graphs)
+    d = OD.build(wl.leaves, wl.graphs, wl.specs)
     c = ctx_for(wl)
     kind, left, right = c.nodes()
     assert list(left) == d.left and list(right) == d.right
@@ -612,3 +614,37 @@ def test_node_scheduler_self_check_at_full_size(which):
         c.build_cdag(wl.leaves, wl.graphs)
     assert list(c.schedule("node", check=True)) == list(c.schedule("node"))
     c.close()
+
+
+def test_index_pair_specs_build_and_validation():
+    """Contractions over index pairs: node kinds, ranks and merging equal the
+    oracle's (a spec equal to C1 merges with C1 nodes); every malformed spec
+    or use is refused with CDAG_E_INVALID; split-BF16 plans refuse them."""
+    wl = W.pairs_mix(nvec=3, nt=2, n_graphs=40, seed=9, with_data=False)
+    d = OD.build(wl.leaves, wl.graphs, wl.specs)
+    c = ctx_for(wl)
+    kind, left, right = c.nodes()
+    assert [int(k) for k in kind] == d.kind and list(left) == d.left and list(right) == d.right
+    assert W.SPEC_BASE + 4 not in d.kind and W.C1 in d.kind          # the C1-shaped spec merged
+    c.schedule("tree")
+    assert c.plan("fp64", True)["n_contr"] == d.n_nodes - d.n_leaves
+    with pytest.raises(X.CdagError) as e:
+        c.plan("bf16x3", True)
+    assert e.value.code == B.E_INVALID
+    L = [W.Leaf(3, 3, 1), W.Leaf(3, 3, 1), W.Leaf(2, 3, 1)]
+    bad = [W.Spec(3, 3, ((0, 0), (0, 1)), (0, 1)),          # an axis twice
+           W.Spec(3, 3, ((3, 0),), (0, 1, 2, 3)),          # axis out of range
+           W.Spec(3, 3, ((0, 0),), (0, 1, 1, 2)),          # perm not a permutation
+           W.Spec(3, 2, ((0, 0),), (0, 1, 2)),             # ranks differ from the operands'
+           W.Spec(3, 3, ((0, 0), (1, 1), (2, 2)), (0,))]   # output rank 0
+    for sp in bad:
+        g = [W.GraphSpec([(W.SPEC_BASE, 0, 1), (W.HCA, -1, 2)])] if len(sp.perm) == 2 else \
+            [W.GraphSpec([(W.SPEC_BASE, 0, 1), (W.C2, -1, 0), (W.HCA, -1, 2)])]
+        with pytest.raises(X.CdagError) as e:
+            X.Context().build_cdag(L, g, [sp])
+        assert e.value.code == B.E_INVALID, sp
+        with pytest.raises(OD.InvalidGraph):
+            OD.build(L, g, [sp])
+    with pytest.raises(X.CdagError) as e:                  # a kind with no spec
+        X.Context().build_cdag(L, [W.GraphSpec([(W.SPEC_BASE + 1, 0, 1), (W.HCA, -1, 2)])], [])
+    assert e.value.code == B.E_INVALID

@@ -190,3 +190,72 @@ def test_cross_sum_scale_by_hand():
     s = V.cross_sums(Wl, vals)
     for c in sc:
         assert np.all(np.abs(s[c]) <= sc[c] * (1 + 1e-15))
+
+
+def _loops_pairs(X, Y, pairs, perm):
+    """The contraction over index pairs by explicit loops: every combination of
+    free and summed indices, products accumulated into the output element the
+    permutation names."""
+    nt, n = X.shape[0], X.shape[1]
+    rl, rr = X.ndim - 1, Y.ndim - 1
+    px = [a for a, _ in pairs]
+    py = [b for _, b in pairs]
+    fx = [a for a in range(rl) if a not in px]
+    fy = [b for b in range(rr) if b not in py]
+    ro = len(fx) + len(fy)
+    out = np.zeros((nt,) + (n,) * ro, dtype=np.complex128)
+    for t in range(nt):
+        for free in itertools.product(range(n), repeat=ro):
+            natural = list(free)                       # indices of fx then fy
+            s = 0j
+            for summed in itertools.product(range(n), repeat=len(pairs)):
+                ix = [0] * rl
+                iy = [0] * rr
+                for q, a in enumerate(fx):
+                    ix[a] = natural[q]
+                for q, b in enumerate(fy):
+                    iy[b] = natural[len(fx) + q]
+                for k in range(len(pairs)):
+                    ix[px[k]] = summed[k]
+                    iy[py[k]] = summed[k]
+                s += X[(t, *ix)] * Y[(t, *iy)]
+            # output axis j holds natural axis perm[j]
+            out[(t, *[natural[perm[j]] for j in range(ro)])] = s
+    return out
+
+
+@pytest.mark.parametrize("i", range(len(W.PAIR_SPECS)))
+def test_index_pair_contractions_by_loops(i):
+    sp = W.PAIR_SPECS[i]
+    rng = np.random.default_rng(40 + i)
+    n, nt = 3, 2
+    X = W._draw(rng, (nt,) + (n,) * sp.rank_l, 1.0)
+    Y = W._draw(rng, (nt,) + (n,) * sp.rank_r, 1.0)
+    got = V.contract_pairs(X, Y, sp.pairs, sp.perm)
+    want = _loops_pairs(X, Y, sp.pairs, sp.perm)
+    assert got.shape == want.shape
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-13)
+
+
+def test_index_pairs_hand_case():
+    """X[i,j] = i + 2j, Y[i,k] = 1 + i k (n = 2): sum over i of X[i,j] Y[i,k],
+    output (k, j): O[k,j] = (2j)(1) + (1 + 2j)(1 + k)."""
+    X = np.array([[[0, 2], [1, 3]]], dtype=np.complex128)       # X[0][i][j] = i + 2j
+    Y = np.array([[[1, 1], [1, 2]]], dtype=np.complex128)       # Y[0][i][k] = 1 + i k
+    got = V.contract_pairs(X, Y, ((0, 0),), (1, 0))
+    want = np.array([[[2 * j + (1 + 2 * j) * (1 + k) for j in range(2)] for k in range(2)]], dtype=np.complex128)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("c,rl,rr", [(1, 2, 2), (1, 3, 2), (2, 3, 3), (1, 3, 3), (2, 4, 3), (3, 4, 4)])
+def test_trailing_leading_pairs_are_the_general_kinds(c, rl, rr):
+    """Pairs (last c axes of X, first c axes of Y) in order with the natural
+    output order are C_c (and so K22, K32, K33): the batched-matmul route."""
+    rng = np.random.default_rng(7 * c + rl + rr)
+    n, nt = 3, 2
+    X = W._draw(rng, (nt,) + (n,) * rl, 1.0)
+    Y = W._draw(rng, (nt,) + (n,) * rr, 1.0)
+    pairs = tuple((rl - c + k, k) for k in range(c))
+    ro = rl + rr - 2 * c
+    got = V.contract_pairs(X, Y, pairs, tuple(range(ro)))
+    assert np.allclose(got, V.contract((V.C1, V.C2, V.C3)[c - 1], X, Y), rtol=1e-13, atol=1e-13)
