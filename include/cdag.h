@@ -182,7 +182,9 @@ typedef struct {
   int32_t kinds;      /* bit k set when a contraction of cdag_kind k is in the launch (bit 7:
                          a contraction over any index pairs);
                          H2D, D2H: the moved tensor's cdag_kind bit (leaves: 0)         */
-  int32_t reserved;
+  int32_t interior;   /* HEC: 1 when every contraction of the launch is a whole number of
+                         tiles and k-steps with aligned rows, so the kernel ran its
+                         form without bounds tests; else 0                              */
   int64_t step;       /* plan step (wave); -1 for the cross-diagram sum                */
   int64_t n_items;    /* workgroup work items; H2D, D2H: 1                               */
   double flops;       /* algorithmic flops (8 per complex multiply-add); transfers: 0   */

@@ -72,7 +72,7 @@ class cdag_exec_stats(C.Structure):
 
 class cdag_launch_record(C.Structure):
     _fields_ = [("type", C.c_int32), ("variant", C.c_int32), ("kinds", C.c_int32),
-                ("reserved", C.c_int32), ("step", C.c_int64), ("n_items", C.c_int64),
+                ("interior", C.c_int32), ("step", C.c_int64), ("n_items", C.c_int64),
                 ("flops", C.c_double), ("bytes", C.c_double), ("ms", C.c_double)]
 
 
@@ -303,7 +303,7 @@ def cdag_launch_records(h):
     _check(lib().cdag_launch_records(h, buf, n.value, C.byref(n)))
     out = []
     for r in buf[:n.value]:
-        out.append({"type": LAUNCH_TYPES[r.type], "variant": r.variant,
+        out.append({"type": LAUNCH_TYPES[r.type], "variant": r.variant, "interior": bool(r.interior),
                     "kinds": [k for k in range(8) if r.kinds >> k & 1], "step": r.step,
                     "n_items": r.n_items, "flops": r.flops, "bytes": r.bytes, "ms": r.ms})
     return out

@@ -19,7 +19,8 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SOURCES = ["host/dag.cpp", "host/sched.cpp", "host/plan.cpp", "host/kplan.cpp", "capi.cpp"]
-HIP_SOURCES = ["kernels/kernels.hip", "runtime/executor.hip"]
+HIP_SOURCES = ["kernels/kernels.hip", "kernels/hec_f64.hip", "kernels/hec_f32.hip", "kernels/hec_bf16x2.hip",
+               "kernels/hec_bf16x3.hip", "runtime/executor.hip"]
 # Packed FP32 instructions stay off: the compiler must not form v_pk_* FP32 ops.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -200,6 +200,8 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
       int64_t tiles[kGroups] = {0};
       double v_flops[kGroups] = {0}, v_bytes[kGroups] = {0};
       int32_t v_kinds[kGroups] = {0};
+      bool v_interior[kGroups];
+      std::fill(v_interior, v_interior + kGroups, true);
       double red_bytes = 0, hca_flops = 0, hca_bytes = 0;
       int32_t red_kinds = 0;
       std::vector<RedDesc> red;
@@ -259,6 +261,8 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
         h.ws_off = -1;
         h.tile_begin = (int32_t)tiles[tl];
         tiles[tl] += h.tile_count;
+        if (gen || !hec_interior(h, kTileShapes[variant_tile(tl)].bm, kTileShapes[variant_tile(tl)].bn, k_step(prec)))
+          v_interior[tl] = false;
         kp.hec_items += h.tile_count;
         if (h.splits > 1) {
           h.ws_off = ws;
@@ -283,6 +287,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
         L.flops = v_flops[tl];
         L.bytes = v_bytes[tl];
         L.kinds = v_kinds[tl];
+        L.interior = v_interior[tl] ? 1 : 0;
         L.host_desc = (int64_t)kp.blob.size();
         for (auto& h : hec[tl]) put(kp.blob, h);
         kp.launches.push_back(L);

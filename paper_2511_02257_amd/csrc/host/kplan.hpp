@@ -24,6 +24,7 @@ struct Launch {
   double flops = 0;   // algorithmic flops of the launch (HEC, HCA)
   double bytes = 0;   // HEC, HCA: algorithmic bytes; RED: workspace read + output write
   int32_t kinds = 0;  // bit k set when a contraction of kind k is in the launch
+  int32_t interior = 0;   // HEC: every contraction interior (hec_interior) for the variant's tile
 };
 
 // Kernel variant of an exterior contraction: a tile shape (index into

@@ -36,6 +36,16 @@ struct HecDesc {
   int32_t tile_begin, tile_count;              // this op's work items in the launch
 };
 
+// An interior contraction for a tile of bm x bn and a k-step bk: every work
+// item is a whole tile with whole k-slices, rows of A and B hold a multiple of
+// 8 elements, and both operand slices start 16-byte aligned (planes and time
+// slices then stay aligned).  A launch whose contractions are all interior
+// runs the kernel form with unpredicated vector loads and stores.
+inline bool hec_interior(const HecDesc& h, int bm, int bn, int bk) {
+  return h.map_off < 0 && h.M % bm == 0 && h.N % bn == 0 && h.K % 8 == 0 && h.N % 8 == 0 && h.K % bk == 0 &&
+         h.k_split % bk == 0 && (h.a_off & 15) == 0 && (h.b_off & 15) == 0;
+}
+
 // Element strides of a contraction over any index pairs, digit by digit.  The
 // GEMM indices m (the left operand's free axes, in order), k (the summed axes,
 // in pair order) and n (the right operand's free axes) are mixed-radix numbers

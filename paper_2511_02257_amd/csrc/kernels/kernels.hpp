@@ -1,4 +1,4 @@
-// Launchers of the HIP kernels (kernels.hip).  Every launcher takes the arena
+// Launchers of the HIP kernels (kernels.hip, hec_*.hip).  Every launcher takes the arena
 // base and arena-relative descriptor offsets; prec: 0 FP64, 1 FP32, 2 split-BF16
 // (two pieces), 3 split-BF16 (three pieces).
 #pragma once
@@ -26,17 +26,32 @@ struct KernelCall {
 };
 hipError_t launch(KernelCall& k, hipStream_t s);
 
-hipError_t hec_call(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
-                    KernelCall* k);
+// Exterior-contraction launch of kernel variant `variant`; interior: every
+// contraction of the launch passes hec_interior (desc.hpp) for the variant's
+// tile and the precision's k-step.
+hipError_t hec_call(int prec, int variant, bool interior, char* arena, int64_t desc_off, int n_desc,
+                    int64_t n_items, KernelCall* k);
 hipError_t reduce_call(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, KernelCall* k);
 hipError_t hca_call(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, KernelCall* k);
 hipError_t xsum_call(char* arena, int64_t desc_off, int64_t entries_off, int n_desc, KernelCall* k);
 
-hipError_t launch_hec(int prec, int variant, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
-                      hipStream_t s);
+hipError_t launch_hec(int prec, int variant, bool interior, char* arena, int64_t desc_off, int n_desc,
+                      int64_t n_items, hipStream_t s);
 hipError_t launch_reduce(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s);
 hipError_t launch_hca(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, hipStream_t s);
 hipError_t launch_xsum(char* arena, int64_t desc_off, int64_t entries_off, int n_desc, hipStream_t s);
+// Kernel tables of the exterior contractions, one translation unit per
+// precision (hec_f64.hip, hec_f32.hip, hec_bf16x2.hip, hec_bf16x3.hip): the
+// kernel of tile `tile` (index into kTileShapes), `stages` LDS stages (1 or 2),
+// persistent grid or one workgroup per item, interior launch or not; nullptr
+// for a tile out of range.  hec_general_*: the kernel of contractions over any
+// index pairs.
+const void* hec_kernel_f64(int tile, int stages, bool persistent, bool interior);
+const void* hec_kernel_f32(int tile, int stages, bool persistent, bool interior);
+const void* hec_kernel_bf16x2(int tile, int stages, bool persistent, bool interior);
+const void* hec_kernel_bf16x3(int tile, int stages, bool persistent, bool interior);
+const void* hec_general_f64();
+const void* hec_general_f32();
 // Interleaved complex [nt][e] (double or float) -> device layout [nt][2][e]
 // (double or float), both in device memory.
 hipError_t launch_to_planar(bool src_double, bool dst_double, const void* src, void* dst, int64_t nt, int64_t e,

@@ -298,7 +298,7 @@ void ensure_pinned(void*& p, int64_t& have, int64_t need_bytes) {
 
 hipError_t call_of(const Launch& L, int prec, char* arena, KernelCall* k) {
   switch (L.type) {
-    case L_HEC: return hec_call(prec, L.tile, arena, L.desc_off, L.n_desc, L.n_items, k);
+    case L_HEC: return hec_call(prec, L.tile, L.interior != 0, arena, L.desc_off, L.n_desc, L.n_items, k);
     case L_RED: return reduce_call(prec, arena, L.desc_off, L.n_desc, L.n_items, k);
     case L_HCA: return hca_call(prec, arena, L.desc_off, L.n_desc, L.n_items, k);
     default: throw Error(CDAG_E_STATE, "bad launch type");
@@ -713,8 +713,11 @@ int64_t device_autotune(Ctx& c, int prec, int batched, int reps, bool uniform) {
         HIPC(hipMemsetAsync(D.arena + a, 0, (size_t)(ws - a), D.comp));
         HIPC(hipMemcpyAsync(D.arena + desc, &h, sizeof(h), hipMemcpyHostToDevice, D.comp));
         HIPC(hipMemcpyAsync(D.arena + desc + 128, &r, sizeof(r), hipMemcpyHostToDevice, D.comp));
+        const int v = choice_variant(ch);
+        const bool interior =
+            hec_interior(h, kTileShapes[variant_tile(v)].bm, kTileShapes[variant_tile(v)].bn, k_step(prec));
         auto once = [&] {
-          HIPC(launch_hec(prec, choice_variant(ch), D.arena, desc, 1, h.tile_count, D.comp));
+          HIPC(launch_hec(prec, v, interior, D.arena, desc, 1, h.tile_count, D.comp));
           if (h.splits > 1) HIPC(launch_reduce(prec, D.arena, desc + 128, 1, red_items, D.comp));
         };
         once();
@@ -982,6 +985,7 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
       const Launch& L = pr.launch >= 0 ? kp.launches[pr.launch] : kp.xsum;
       r.type = L.type;
       r.variant = L.type == L_HEC ? L.tile : 0;
+      r.interior = L.type == L_HEC ? L.interior : 0;
       r.kinds = L.kinds;
       r.n_items = L.n_items;
       r.flops = L.flops;

@@ -64,7 +64,8 @@ def dispatches(args):
 
 def kernel_source_sha256():
     h = hashlib.sha256()
-    for rel in ("paper_2511_02257_amd/csrc/kernels/kernels.hip", "paper_2511_02257_amd/csrc/kernels/desc.hpp"):
+    for rel in ("paper_2511_02257_amd/csrc/kernels/kernels.hip", "paper_2511_02257_amd/csrc/kernels/hec.hpp",
+                "paper_2511_02257_amd/csrc/kernels/hec_f64.hip", "paper_2511_02257_amd/csrc/kernels/desc.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

@@ -140,6 +140,72 @@ def test_every_tile_shape(meson_small, baryon_small, prec, tile, grid, stages):
         assert err.max() <= TOL[prec]
 
 
+def _wl_interior():
+    # N = 64 and 48: contractions that are a whole number of tiles for the tile
+    # shapes dividing their GEMM, whose launches run the kernel form without
+    # bounds tests (K33 at N = 64 runs split-K with K = 4096)
+    return [W.meson_ring(n_leaves=6, nvec=64, nt=2, n_graphs=16, lmin=4, lmax=6, sigma=1 / 8, n_corr=2,
+                         seed=61, name="meson_n64"),
+            W.baryon_mix(n_bar=3, n_mes=3, nvec=64, nt=2, n_graphs=8, sigma=1 / 16, n_corr=2, seed=62,
+                         name="baryon_n64"),
+            W.baryon_mix(n_bar=3, n_mes=3, nvec=48, nt=2, n_graphs=8, sigma=1 / 16, n_corr=2, seed=63,
+                         name="baryon_n48")]
+
+
+@pytest.fixture(scope="module")
+def interior_workloads():
+    return [(wl, OV.correlators(wl)) for wl in _wl_interior()]
+
+
+def _interior_expected(name, tile, prec):
+    """Which exterior-contraction launches are interior: 'all', 'some' or
+    'none', from the GEMM shapes (K22 64 x 64 x 64; K32 N^2 x N x N; K33
+    N x N x N^2) against the tile and the k-step (16, split BF16 32)."""
+    bm, bn = {0: (64, 64), 1: (32, 32), 2: (48, 48), 3: (128, 64), 4: (64, 32), 5: (64, 64)}[tile]
+    n = 64 if name.endswith("n64") else 48
+    bk = 32 if prec.startswith("bf16") else 16
+    shapes = [(n, n, n)] if name.startswith("meson") else [(n * n, n, n), (n, n, n * n)]
+    ok = [m % bm == 0 and nn % bn == 0 and k % bk == 0 for m, nn, k in shapes]
+    return "all" if all(ok) else "some" if any(ok) else "none"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("grid", [0, 1])
+@pytest.mark.parametrize("stages", [2, 1])
+def test_every_tile_shape_interior(interior_workloads, prec, tile, grid, stages):
+    """Whole tiles: every variant in its interior form (unpredicated vector
+    loads, stores without bounds tests) against the oracle, and the launch
+    records say which launches ran it."""
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd.device import DeviceRunner
+    for wl, ref in interior_workloads:
+        ctx = X.Context()
+        ctx.build_cdag(wl.leaves, wl.graphs)
+        ctx.schedule("tree")
+        ctx.set_options(wave_lookahead=X.binding.LOOKAHEAD_ALL)
+        for kind in (0, 1, 2):
+            ctx.set_tile(prec, kind, wl.leaves[0].nvec, tile, grid, stages, 1)
+        runner = DeviceRunner(ctx, 0)
+        ctx.set_timing(True)
+        runner.run(prec, True)
+        hec = [r for r in ctx.launch_records() if r["type"] == "hec"]
+        corr = ctx.fetch_correlators()
+        ctx.close()
+        err = rel_errors(corr, ref)
+        inner = [r["interior"] for r in hec]
+        expect = _interior_expected(wl.name, tile, prec)
+        print(f"{wl.name} {prec} tile {tile} grid {grid} stages {stages}: interior {sum(inner)}/{len(inner)} "
+              f"(expected {expect}), max rel {err.max():.3e}")
+        assert err.max() <= TOL[prec]
+        if expect == "all":
+            assert all(inner)
+        elif expect == "some":
+            assert any(inner)
+        else:
+            assert not any(inner)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
 def test_without_split_k(baryon_small, prec):
     """split_k 0: K33 (K = 1600) runs as one work item per output tile with the
