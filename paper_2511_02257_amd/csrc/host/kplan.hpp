@@ -70,8 +70,8 @@ void decompose(const Gemm& g, int nt, int choice, int prec, HecDesc* h, int nt_r
 // general kind can occur with several operand ranks).
 struct TuneShape { int nt; Gemm gemm; };
 std::map<std::pair<int, int>, TuneShape> tune_shapes(const Dag& d);
-// k-step of the matrix-core kernels: FP64 and FP32 use 16, split-BF16 32.
-inline int k_step(int prec) { return prec >= 2 ? 32 : 16; }
+// k-step of the matrix-core kernels: FP64 uses 16, FP32 and split-BF16 32.
+inline int k_step(int prec) { return prec == 0 ? 16 : 32; }
 // Split-K: aim for at least this many work items per contraction, keeping at
 // least kMinKSplit of K per split.
 constexpr int kSplitTarget = 512, kMinKSplit = 256;

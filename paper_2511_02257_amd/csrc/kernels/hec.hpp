@@ -60,6 +60,35 @@ typedef Tile<2, 2, 4, 2> Tile3;   // 128 x 64, 256 threads
 typedef Tile<2, 2, 2, 1> Tile4;   //  64 x 32, 256 threads
 typedef Tile<2, 4, 2, 1> Tile5;   //  64 x 64, 512 threads (half the accumulators per wave)
 
+// Occupancy target of an exterior-contraction kernel: the waves per SIMD that
+// its register budget must allow (the compiler keeps each lane within
+// 512 / waves registers).  P: 0 FP64, 1 FP32, 2 split BF16 (either piece
+// count); 1 leaves the register budget to the compiler.
+template <int P, class TL, int ST, bool PF>
+struct Occupancy {
+  static constexpr int waves = 1;
+};
+// Targets that shrink a variant's registers without spilling, where LDS leaves
+// room for the extra workgroups (measured: FP32 K22/K32 +3 %, split-BF16 K33
+// on the 64 x 64 / 256 tile +3 %, the others within noise).  Only the grids of
+// one workgroup per item take them: squeezed to 127 registers, the persistent
+// FP32 one-stage 64 x 64 kernels with 32-deep k-slices gave wrong results.
+#define CDAG_OCCUPANCY(P, TL, ST, W) \
+  template <> struct Occupancy<P, TL, ST, false> { static constexpr int waves = W; };
+CDAG_OCCUPANCY(0, Tile0, 1, 3)
+CDAG_OCCUPANCY(0, Tile0, 2, 2)
+CDAG_OCCUPANCY(0, Tile4, 1, 3)
+CDAG_OCCUPANCY(0, Tile4, 2, 2)
+CDAG_OCCUPANCY(0, Tile1, 1, 4)
+CDAG_OCCUPANCY(1, Tile0, 1, 4)
+CDAG_OCCUPANCY(1, Tile0, 2, 4)
+CDAG_OCCUPANCY(1, Tile3, 1, 3)
+CDAG_OCCUPANCY(1, Tile4, 1, 4)
+CDAG_OCCUPANCY(1, Tile4, 2, 4)
+CDAG_OCCUPANCY(2, Tile0, 1, 3)
+CDAG_OCCUPANCY(2, Tile3, 1, 2)
+#undef CDAG_OCCUPANCY
+
 struct WorkItem {
   const HecDesc* h;
   int t, m0, n0, sp, kbeg, kend;
@@ -267,18 +296,22 @@ __device__ __forceinline__ void store_block(T* C, int M, int N, int row0, int co
 // FULL: every contraction of the launch is interior (hec_interior): operands
 // load with unpredicated 16-byte loads and outputs store without bounds tests.
 template <typename T, class TL, int ST, bool PF, bool GEN = false, bool FULL = false>
-__global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs,
-                                                     int n_desc, int64_t n_items) {
+__global__ void __launch_bounds__(TL::NTH, (Occupancy<sizeof(T) == 8 ? 0 : 1, TL, ST, PF>::waves))
+hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc, int64_t n_items) {
   static_assert(!(GEN && FULL), "a general contraction is never interior");
   typedef typename Mfma<T>::V V;
   constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
-  constexpr int BK = 16, APAD = BK + 1, BPAD = BN + 16;
+  // k-slice: 16 (FP64) or 32 (FP32) k per LDS stage, so that a K = 64
+  // contraction's item runs four or two slices.  A rows are padded so that
+  // the 16 rows read by one instruction fall in distinct LDS banks.
+  constexpr int BK = sizeof(T) == 8 ? 16 : 32, APAD = BK + (sizeof(T) == 8 ? 1 : 4), BPAD = BN + 16;
+  constexpr int SPR = BK / 8;   // 8-element A segments per row
   // The A tile is split into 8-element row segments ([plane][row][k / 8]); the
   // B tile into 16-byte row chunks of W elements ([plane][k][n / W]), so that
   // consecutive lanes load and store consecutive 16 bytes (coalesced loads,
   // LDS stores free of bank conflicts).
   constexpr int W = 16 / (int)sizeof(T);
-  constexpr int SEGA = 2 * BM * (BK / 8), SEGB = 2 * BK * (BN / W);
+  constexpr int SEGA = 2 * BM * SPR, SEGB = 2 * BK * (BN / W);
   constexpr int LA = (SEGA + NTH - 1) / NTH, LB = (SEGB + NTH - 1) / NTH;
   static_assert(BN % W == 0, "B chunks must tile the row");
   __shared__ __attribute__((aligned(16))) T As[ST][2][BM][APAD];   // [stage][plane][m][k]
@@ -296,7 +329,7 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
       for (int q = 0; q < LA; ++q) {
         const int seg = tid + q * NTH;
         if (SEGA % NTH == 0 || seg < SEGA) {
-          const int p = seg / (2 * BM), r = (seg % (2 * BM)) >> 1, hh = seg & 1;
+          const int p = seg / (SPR * BM), r = (seg % (SPR * BM)) / SPR, hh = seg % SPR;
           const VL* src = reinterpret_cast<const VL*>(o.A + (int64_t)p * o.M * o.K + (int64_t)(o.m0 + r) * o.K +
                                                       k0 + 8 * hh);
 #pragma unroll
@@ -320,7 +353,7 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
     for (int q = 0; q < LA; ++q) {
       const int seg = tid + q * NTH;
       if (SEGA % NTH == 0 || seg < SEGA) {
-        const int p = seg / (2 * BM), r = (seg % (2 * BM)) >> 1, hh = seg & 1;
+        const int p = seg / (SPR * BM), r = (seg % (SPR * BM)) / SPR, hh = seg % SPR;
         const int am = o.m0 + r, ak = k0 + 8 * hh;
         T e[8];
         if constexpr (GEN) {
@@ -369,7 +402,7 @@ __global__ void __launch_bounds__(TL::NTH) hec_mfma(char* __restrict__ arena, co
     for (int q = 0; q < LA; ++q) {
       const int seg = tid + q * NTH;
       if (SEGA % NTH == 0 || seg < SEGA) {
-        const int p = seg / (2 * BM), r = (seg % (2 * BM)) >> 1, hh = seg & 1;
+        const int p = seg / (SPR * BM), r = (seg % (SPR * BM)) / SPR, hh = seg % SPR;
 #pragma unroll
         for (int i = 0; i < 8; ++i) As[st][p][r][8 * hh + i] = ra[q][i / W][i % W];
       }
@@ -565,8 +598,8 @@ template <int P> __device__ constexpr int term_y(int t) {
 }
 
 template <class TL, int ST_, bool PF, int P, bool FULL = false>
-__global__ void __launch_bounds__(TL::NTH) hec_bf16(char* __restrict__ arena, const HecDesc* __restrict__ descs,
-                                                     int n_desc, int64_t n_items) {
+__global__ void __launch_bounds__(TL::NTH, (Occupancy<2, TL, ST_, PF>::waves))
+hec_bf16(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc, int64_t n_items) {
   constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
   constexpr int BK = 32, PAD = BK + 8;     // bf16 per LDS row (16-byte aligned rows)
   // Two stages of three pieces of the 128 x 64 tile would exceed the 160 KB of

@@ -160,10 +160,11 @@ def interior_workloads():
 def _interior_expected(name, tile, prec):
     """Which exterior-contraction launches are interior: 'all', 'some' or
     'none', from the GEMM shapes (K22 64 x 64 x 64; K32 N^2 x N x N; K33
-    N x N x N^2) against the tile and the k-step (16, split BF16 32)."""
+    N x N x N^2) against the tile and the k-step (FP64 16, FP32 and split
+    BF16 32)."""
     bm, bn = {0: (64, 64), 1: (32, 32), 2: (48, 48), 3: (128, 64), 4: (64, 32), 5: (64, 64)}[tile]
     n = 64 if name.endswith("n64") else 48
-    bk = 32 if prec.startswith("bf16") else 16
+    bk = 16 if prec == "fp64" else 32
     shapes = [(n, n, n)] if name.startswith("meson") else [(n * n, n, n), (n, n, n * n)]
     ok = [m % bm == 0 and nn % bn == 0 and k % bk == 0 for m, nn, k in shapes]
     return "all" if all(ok) else "some" if any(ok) else "none"
@@ -360,13 +361,14 @@ def test_identity_trace_exact(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("tile", [0, 1])
+@pytest.mark.parametrize("tile", [0, 1, 5])
 def test_times_identity_and_selector(prec, tile):
     """X I and a selector tensor against the direct trace.  Tile 0 (64 x 64,
     four real products per complex one) reproduces the direct trace bit for
-    bit: every product is by 0 or 1 and every sum adds zeros.  Tile 1 (32 x 32,
-    Gauss's three products) rounds Ar + Ai and then cancels Ar against it, so
-    there the two agree only to rounding."""
+    bit: every product is by 0 or 1 and every sum adds zeros.  Tiles 1 and 5
+    (Gauss's three products; tile 5 is the one the autotuner picks at N = 64)
+    round Ar + Ai and then cancel Ar against it, so there the two agree only
+    to rounding."""
     rng = np.random.default_rng(3)
     nt, n = 3, 24
     X2 = W._draw(rng, (nt, n, n), 0.5)

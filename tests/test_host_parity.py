@@ -338,7 +338,7 @@ def test_split_k_choice_sets_the_work_items():
     c = ctx_for(wl)
     c.schedule("tree")
     for tile, (bm, bn) in sorted(X.TILES.items()):
-        for prec, kstep in (("fp64", 16), ("fp32", 16), ("bf16x3", 32), ("bf16x6", 32)):
+        for prec, kstep in (("fp64", 16), ("fp32", 32), ("bf16x3", 32), ("bf16x6", 32)):
             k32 = n_k[W.K32] * 5 * (-(-1600 // bm)) * (-(-40 // bn))   # K32: M = N^2, K = N: no split
             base33 = 5 * (-(-40 // bm)) * (-(-40 // bn))
             for kind in (1, 2):
