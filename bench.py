@@ -175,6 +175,65 @@ def sample_bits(ctx, sample):
 
 
 # ---------------------------------------------------------------- headline
+def given_tiles(args):
+    """Kernel choices from --tiles-from or --tiles: {prec: {"K32_N64": [tile, grid, stages,
+    split_k], ...}}, or {} when neither is given."""
+    tiles = {}
+    if args.tiles_from:
+        with open(args.tiles_from) as f:
+            prev = json.loads(f.read().strip().splitlines()[-1])
+        tiles = prev["config"]["kernel_choices"]
+    elif args.tiles:
+        for part in args.tiles.split(";"):
+            prec, rest = part.split(":")
+            tiles[prec] = {k: [int(x) for x in v.split(".")] for k, v in
+                           (item.split("=") for item in rest.split(","))}
+    return tiles
+
+
+def set_tiles(ctx, tiles, precs=None):
+    for prec, table in tiles.items():
+        if precs is not None and prec not in precs:
+            continue
+        for key, choice in table.items():
+            kname, n = key.split("_N")
+            ctx.set_tile(prec, {v: k for k, v in KIND_NAMES.items()}[kname], int(n), *choice)
+
+
+def k64_kernels(args, X, W, DeviceRunner):
+    """Kernel-only references of the K = 64 exterior contractions, for profiling: the
+    meson DAG (K22) in FP64 and FP32 and the baryon DAG (K32, K33) in FP32, every leaf
+    resident, Tree order, every ready contraction in a wave, eager issue.  Kernel choices
+    from --tiles (else the in-situ autotuner).  Per part: the time per execute and the
+    kernel table of one timed execute."""
+    tiles = given_tiles(args)
+    out = {}
+    for name, prec in (("meson_ring", "fp64"), ("meson_ring", "fp32"), ("baryon_mix", "fp32")):
+        wl = W.config(name)
+        ctx = X.Context()
+        ctx.build_cdag(wl.leaves, wl.graphs)
+        del wl
+        ctx.schedule("tree")
+        ctx.set_options(leaves_resident=True, wave_lookahead=ALL, use_graphs=0)
+        runner = DeviceRunner(ctx, 0)
+        if prec in tiles:
+            set_tiles(ctx, tiles, (prec,))
+            runner.ensure_arena(ctx.plan(prec, True)["arena_bytes"])
+        else:
+            runner.autotune(prec, True, reps=2, in_situ=True)
+        choices = {f"{KIND_NAMES[k]}_N64": list(ctx.get_tile(prec, k, 64)) for k in (0, 1, 2)}
+        dt, st = timed_steps(runner, prec, True, args.steps, args.warmup)
+        ctx.set_timing(True)
+        runner.run(prec, True)
+        kt = kernel_table(ctx.launch_records(), prec)
+        ctx.set_timing(False)
+        ctx.close()
+        log(f"k64 {name} {prec}: {dt / args.steps * 1e3:.3f} ms", {k: v.get("frac_mfma") for k, v in kt.items()})
+        out[f"{name}_{prec}"] = {"ms_per_step": round(dt / args.steps * 1e3, 4), "kernel_choices": choices,
+                                 "kernels": kt}
+    return out
+
+
 def headline(args, X, W, DeviceRunner, sample):
     """The baryon configuration as stated, FP64, plus its references: every
     leaf resident (kernel time), one pass (whole tensors), the precision
@@ -194,21 +253,9 @@ def headline(args, X, W, DeviceRunner, sample):
     ctx.set_time_chunks(args.chunks)
     opts = dict(leaves_resident=False, wave_lookahead=ALL)
     ctx.set_options(use_graphs=0, **opts)
-    tiles = {}
-    if args.tiles_from or args.tiles:
-        if args.tiles_from:
-            with open(args.tiles_from) as f:
-                prev = json.loads(f.read().strip().splitlines()[-1])
-            tiles = prev["config"]["kernel_choices"]
-        else:
-            for part in args.tiles.split(";"):
-                prec, rest = part.split(":")
-                tiles[prec] = {k: [int(x) for x in v.split(".")] for k, v in
-                               (item.split("=") for item in rest.split(","))}
-        for prec, table in tiles.items():
-            for key, choice in table.items():
-                kname, n = key.split("_N")
-                ctx.set_tile(prec, {v: k for k, v in KIND_NAMES.items()}[kname], int(n), *choice)
+    tiles = given_tiles(args)
+    if tiles:
+        set_tiles(ctx, tiles)
         runner.ensure_arena(ctx.plan("fp64", True)["arena_bytes"])
     else:
         runner.autotune("fp64", True, reps=2, in_situ=True)
@@ -588,10 +635,11 @@ def main():
     ap.add_argument("--chunks", type=int, default=8, help="time-slice passes of the headline execute")
     ap.add_argument("--link-GBps", type=float, default=55.0,
                     help="host-link rate for the upload floor of the headline (large pinned copies)")
-    ap.add_argument("--only", default=None, choices=("headline", "headline-fp64", "meson", "batched"),
+    ap.add_argument("--only", default=None, choices=("headline", "headline-fp64", "meson", "batched", "k64"),
                     help="one part: the headline (with its references and precision form), the headline "
-                         "FP64 execute alone (for profiling), the budgeted meson configuration, or the "
-                         "batched configuration")
+                         "FP64 execute alone (for profiling), the budgeted meson configuration, the "
+                         "batched configuration, or the K = 64 contraction kernels on resident DAGs "
+                         "(for profiling)")
     ap.add_argument("--tiles-from", default=None, metavar="JSON",
                     help="take the headline's kernel choices from the JSON line of an earlier run "
                          "instead of autotuning (so that profiled runs use the same kernels)")
@@ -639,6 +687,9 @@ def main():
         return
     if args.only == "batched":
         print(json.dumps({"batched_budgeted": batched_budgeted(args, X, W, DeviceRunner)}), flush=True)
+        return
+    if args.only == "k64":
+        print(json.dumps({"k64_kernels": k64_kernels(args, X, W, DeviceRunner)}), flush=True)
         return
     # the oracle's sample first (its correlators also give the precision errors)
     base, ref = cpu_baseline(args.cpu_seconds if args.only is None else min(args.cpu_seconds, 2.0))
