@@ -314,8 +314,19 @@ hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc
   constexpr int SEGA = 2 * BM * SPR, SEGB = 2 * BK * (BN / W);
   constexpr int LA = (SEGA + NTH - 1) / NTH, LB = (SEGB + NTH - 1) / NTH;
   static_assert(BN % W == 0, "B chunks must tile the row");
-  __shared__ __attribute__((aligned(16))) T As[ST][2][BM][APAD];   // [stage][plane][m][k]
-  __shared__ __attribute__((aligned(16))) T Bs[ST][2][BK][BPAD];   // [stage][plane][k][n]
+  // CT: the FP32 output tile of an interior launch goes through LDS, so that
+  // every thread stores whole 16-byte pieces of 128-byte lines (the f32
+  // accumulator layout alone gives 64-byte row segments per 16 lanes, and
+  // the memory then writes 1.3 x the output bytes).  The tile [plane][m][n]
+  // reuses the operand stages' LDS once the item's last slice is done.
+  constexpr bool CT = FULL && sizeof(T) == 4;
+  constexpr int CPAD = BN + 4;          // 16-lane row groups of one instruction in distinct banks
+  constexpr int A_ELEMS = ST * 2 * BM * APAD, B_ELEMS = ST * 2 * BK * BPAD, C_ELEMS = CT ? 2 * BM * CPAD : 0;
+  constexpr int SMEM = A_ELEMS + B_ELEMS > C_ELEMS ? A_ELEMS + B_ELEMS : C_ELEMS;
+  __shared__ __attribute__((aligned(16))) T smem[SMEM];
+  T (&As)[ST][2][BM][APAD] = *reinterpret_cast<T (*)[ST][2][BM][APAD]>(smem);            // [stage][plane][m][k]
+  T (&Bs)[ST][2][BK][BPAD] = *reinterpret_cast<T (*)[ST][2][BK][BPAD]>(smem + A_ELEMS);  // [stage][plane][k][n]
+  T (&Cs)[2][BM][CPAD] = *reinterpret_cast<T (*)[2][BM][CPAD]>(smem);                   // [plane][m][n]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / TL::WGN, wn = wave % TL::WGN, li = lane & 15, lk = lane >> 4;
 
@@ -553,9 +564,31 @@ hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc
             im[v] = p3[i][j][v] - (p1[i][j][v] + p2[i][j][v]);
           }
         }
-        store_block<T, V, true, FULL>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li, re,
-                                      im, lk, GEN ? cur.map : nullptr);
+        if constexpr (CT) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = (wm * TM + i) * 16 + Mfma<T>::row(lk, v), cc = (wn * TN + j) * 16 + li;
+            Cs[0][r][cc] = re[v];
+            Cs[1][r][cc] = im[v];
+          }
+        } else {
+          store_block<T, V, true, FULL>(C, M, N, cur.m0 + (wm * TM + i) * 16, cur.n0 + (wn * TN + j) * 16 + li,
+                                        re, im, lk, GEN ? cur.map : nullptr);
+        }
       }
+    if constexpr (CT) {
+      __syncthreads();
+      typedef typename Vec16<T>::V VC;
+      constexpr int QR = BN / 4;   // 16-byte pieces per tile row
+#pragma unroll
+      for (int e = tid; e < 2 * BM * QR; e += NTH) {
+        const int p = e / (BM * QR), rem = e % (BM * QR), r = rem / QR, c4 = rem % QR;
+        const VC val = *reinterpret_cast<const VC*>(&Cs[p][r][4 * c4]);
+        T* dst = C + (int64_t)p * M * N + (int64_t)(cur.m0 + r) * N + cur.n0 + 4 * c4;
+        __builtin_nontemporal_store(val, reinterpret_cast<VC*>(dst));
+      }
+      __syncthreads();   // the next item's first LDS store reuses Cs
+    }
     if (!has_next) break;
     item = next;
     if (PF) {
@@ -585,6 +618,26 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 (&piece)[P]) {
     piece[i] = (__bf16)rest;
     rest -= (float)piece[i];
   }
+}
+
+// The same split for two values at once: each rounding is one packed
+// conversion of the pair (v_cvt_pk_bf16_f32), each difference two FP32
+// subtractions, with the same results as split_bf16 on each value.
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf_t __attribute__((ext_vector_type(2)));
+typedef __bf16 v4bf_t __attribute__((ext_vector_type(4)));
+template <int P>
+__device__ __forceinline__ void split_bf16_pair(v2f_t x, v2bf_t (&piece)[P]) {
+  v2f_t rest = x;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    piece[i] = __builtin_convertvector(rest, v2bf_t);
+    rest = rest - __builtin_convertvector(piece[i], v2f_t);
+  }
+}
+__device__ __forceinline__ v8bf cat_bf16(v2bf_t a, v2bf_t b, v2bf_t c, v2bf_t d) {
+  const v4bf_t ab = __builtin_shufflevector(a, b, 0, 1, 2, 3), cd = __builtin_shufflevector(c, d, 0, 1, 2, 3);
+  return __builtin_shufflevector(ab, cd, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 // Piece products kept for P pieces, smallest first: term t multiplies piece
@@ -670,13 +723,14 @@ hec_bf16(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc
       const int seg = tid + q * NTH;
       if (SEGA % NTH == 0 || seg < SEGA) {
         const int p = seg / (4 * BM), r = (seg % (4 * BM)) >> 2, qq = seg & 3;
+        // the 8 values as 4 adjacent pairs; each piece is one 16-byte row segment
+        v2bf_t pc[4][P];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          __bf16 pc[P];
-          split_bf16<P>(ra[q][i / 4][i % 4], pc);
+        for (int j = 0; j < 4; ++j)
+          split_bf16_pair<P>(v2f_t{ra[q][j / 2][2 * (j % 2)], ra[q][j / 2][2 * (j % 2) + 1]}, pc[j]);
 #pragma unroll
-          for (int x = 0; x < P; ++x) As[st][p][x][r][8 * qq + i] = pc[x];
-        }
+        for (int x = 0; x < P; ++x)
+          *reinterpret_cast<v8bf*>(&As[st][p][x][r][8 * qq]) = cat_bf16(pc[0][x], pc[1][x], pc[2][x], pc[3][x]);
       }
     }
 #pragma unroll
@@ -687,16 +741,14 @@ hec_bf16(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc
         const int g = rem / (BN / 2), cp = rem % (BN / 2);
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          v8bf pv[P];
+          // column c's 8 values of k as 4 pairs of consecutive k
+          v2bf_t pc[4][P];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            __bf16 pc[P];
-            split_bf16<P>(rb[q][i][c], pc);
+          for (int j = 0; j < 4; ++j) split_bf16_pair<P>(v2f_t{rb[q][2 * j][c], rb[q][2 * j + 1][c]}, pc[j]);
 #pragma unroll
-            for (int x = 0; x < P; ++x) pv[x][i] = pc[x];
-          }
-#pragma unroll
-          for (int x = 0; x < P; ++x) *reinterpret_cast<v8bf*>(&Bs[st][p][x][2 * cp + c][8 * g]) = pv[x];
+          for (int x = 0; x < P; ++x)
+            *reinterpret_cast<v8bf*>(&Bs[st][p][x][2 * cp + c][8 * g]) =
+                cat_bf16(pc[0][x], pc[1][x], pc[2][x], pc[3][x]);
         }
       }
     }
