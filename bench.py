@@ -344,6 +344,20 @@ def headline(args, X, W, DeviceRunner, sample):
                         "issue_mode": X.binding.GRAPH_MODES[m], "kernel_choices": tiles[prec],
                         **plan_summary(s2["plan"])}
         log(prec, extras[prec])
+    # the schedules on the same configuration (FP64, budget, passes, kernel
+    # choices, eager issue) with waves of lookahead 16, where the order decides
+    # the resident peak (with every ready contraction in a wave all orders give
+    # the same three waves)
+    sched = {}
+    ctx.set_options(use_graphs=0, leaves_resident=False, wave_lookahead=16)
+    for policy in ("input", "sibling", "node", "tree"):
+        ctx.schedule(policy)
+        n = max(3, args.steps // 4)
+        d2, s2 = timed_steps(runner, "fp64", True, n, 1)
+        sched[policy] = {"ms_per_step": round(d2 / n * 1e3, 3),
+                         "tflops": round(s2["plan"]["flops"] / (d2 / n) / 1e12, 3), **plan_summary(s2["plan"])}
+        log("schedule", policy, sched[policy])
+    extras["fp64_schedules"] = sched
     ctx.close()
     runner.arena = None
     del runner
