@@ -385,9 +385,10 @@ def measured_traffic(workload, variant):
 def meson_budgeted(args, X, W, DeviceRunner):
     """The memory-bound meson configuration: 16 mesons complex128 [32][64][64],
     2000 ring traces; budget a quarter of the input-order live peak; leaves in
-    pinned host memory.  Input order and Tree (waves with lookahead 16, and
-    Tree without lookahead) in each issue mode; host-transfer rates of the
-    eager Tree run beside a pinned-copy link reference."""
+    pinned host memory.  Input order, Tree and node order on whole tensors
+    (waves with lookahead 16, and Tree without lookahead), then passes over the
+    time slices, each in every issue mode; host-transfer rates of the eager
+    Tree run beside a pinned-copy link reference."""
     torch = __import__("torch")
     wl = W.config("meson_ring")
     ctx = X.Context()
@@ -405,11 +406,13 @@ def meson_budgeted(args, X, W, DeviceRunner):
     out["resident_tree_ms"] = round(d2 / 10 * 1e3, 3)
     ref = np.concatenate(ctx.fetch_correlators()).view(np.uint64).copy()
     ctx.set_mem_budget(budget)
-    # whole tensors (the memory model of Sec. II-C), then Tree in passes over
-    # the time slices under the same budget (a pass holds slices of every
-    # tensor, so the budget binds less and the plan moves less)
+    # whole tensors (the memory model of Sec. II-C), then passes over the time
+    # slices under the same budget: a pass holds slices of every tensor in half
+    # the budget, so the budget binds less, the plan moves less, and larger
+    # waves fit (16 passes with lookahead 384 is the fastest of a sweep over
+    # 1-32 passes and lookahead 16-768; every leaf is uploaded once)
     for policy, look, chunks in (("input", 16, 1), ("tree", 16, 1), ("tree", 0, 1), ("node", 16, 1),
-                                 ("tree", 16, 2), ("tree", 16, 4)):
+                                 ("tree", 16, 4), ("tree", 384, 16), ("input", 384, 16)):
         ctx.schedule(policy)
         ctx.set_time_chunks(chunks)
         row = {}
