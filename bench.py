@@ -454,8 +454,9 @@ def batched_budgeted(args, X, W, DeviceRunner):
     storage, just over 20,000 contractions; HBM budget 64e9 bytes; leaves in
     pinned host memory; Tree order; synthetic autotuner.  Waves with the kernel
     choice tuned per (kind, N) (one grouped launch per choice and wave) and
-    with one choice for all shapes (one grouped launch per wave), against one
-    launch per contraction; FP32 and split-BF16 with two pieces."""
+    with one choice for all shapes (one grouped launch per wave), every ready
+    contraction in a wave over 8 passes of the time slices, against one launch
+    per contraction; FP32 and split-BF16 with two pieces."""
     torch = __import__("torch")
     wl = W.config("batched")
     ctx = X.Context()
@@ -471,9 +472,17 @@ def batched_budgeted(args, X, W, DeviceRunner):
             ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=0)
             runner.autotune(prec, True, reps=1, in_situ=False, uniform=uniform)
             ref = None
-            rows = (("waves_lookahead16", True, 16),) + ((("per_contraction", False, 0),)
-                                                          if prec == "fp32" and not uniform else ())
-            for name, batched, look in rows:
+            # waves of lookahead 16 on whole tensors; every ready contraction in a
+            # wave over 8 passes of the time slices (the fastest of a sweep over
+            # 1-64 passes and lookahead 16 to all; no eviction under the budget);
+            # one launch per contraction
+            rows = (("waves_lookahead16", True, 16, 1),)
+            if not uniform:
+                rows += (("waves_all_8passes", True, ALL, 8),)
+                if prec == "fp32":
+                    rows += (("per_contraction", False, 0, 1),)
+            for name, batched, look, chunks in rows:
+                ctx.set_time_chunks(chunks)
                 m, mt = best_mode(runner, ctx, prec, batched, modes=(0, 2) if batched else (0,), reps=1,
                                   leaves_resident=False, wave_lookahead=look)
                 d2, s2 = timed_steps(runner, prec, batched, 1, 0)
@@ -491,6 +500,7 @@ def batched_budgeted(args, X, W, DeviceRunner):
                                      "split_k": sk}
                 out[key] = row
                 log("batched", key, row)
+            ctx.set_time_chunks(1)
         for kind in (0, 1, 2):            # back to the per-shape default before the next precision
             for n in (32, 48, 64, 96, 128):
                 ctx.set_tile(prec, kind, n, -1)

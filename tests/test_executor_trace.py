@@ -403,3 +403,31 @@ def test_full_configuration_walks_under_their_budgets(name, prec, policy):
         assert p["n_evict"] > 0 and p["n_d2h"] > 0
     assert races_by_segment(t) == 0
     assert provenance_errors(t) == []
+
+
+@pytest.mark.parametrize("name,prec,policy,chunks,look", [
+    ("meson_ring", "fp64", "tree", 16, 384), ("meson_ring", "fp64", "input", 16, 384),
+    ("baryon_mix", "fp64", "tree", 8, None), ("batched", "fp32", "tree", 8, None)])
+def test_full_configurations_in_passes_have_no_races(name, prec, policy, chunks, look):
+    """The bench's pass configurations at full size: the meson DAG in 16 passes
+    with lookahead 384 under a quarter of the input-order live peak, the
+    headline and batched DAGs in 8 passes with every ready contraction in a
+    wave under their budgets.  No race between the three streams, and every
+    read finds its tensor."""
+    wl = W.config(name, with_data=False)
+    c = _ctx(wl)
+    if name == "meson_ring":
+        c.schedule("input")
+        budget = c.plan(prec, False)["peak_live"] // 4
+    else:
+        budget = wl.budget_bytes
+    c.schedule(policy)
+    c.set_mem_budget(budget)
+    c.set_time_chunks(chunks)
+    c.set_options(leaves_resident=False, wave_lookahead=X.binding.LOOKAHEAD_ALL if look is None else look)
+    p = c.plan(prec, True)
+    t = c.trace_execute(prec, True)
+    c.close()
+    assert p["peak_resident"] <= budget
+    assert races_by_segment(t) == 0
+    assert provenance_errors(t) == []
