@@ -69,10 +69,10 @@ struct Occupancy {
   static constexpr int waves = 1;
 };
 // Targets that shrink a variant's registers without spilling, where LDS leaves
-// room for the extra workgroups (measured: FP32 K22/K32 +3 %, split-BF16 K33
-// on the 64 x 64 / 256 tile +3 %, the others within noise).  Only the grids of
-// one workgroup per item take them: squeezed to 127 registers, the persistent
-// FP32 one-stage 64 x 64 kernels with 32-deep k-slices gave wrong results.
+// room for the extra workgroups (measured: split-BF16 K33 on the 64 x 64 / 256
+// tile +3 %; the others within noise).  Only the grids of one workgroup per
+// item take them: squeezed to 127 registers, the persistent FP32 one-stage
+// 64 x 64 kernels with 32-deep k-slices gave wrong results.
 #define CDAG_OCCUPANCY(P, TL, ST, W) \
   template <> struct Occupancy<P, TL, ST, false> { static constexpr int waves = W; };
 CDAG_OCCUPANCY(0, Tile0, 1, 3)

@@ -62,12 +62,21 @@ def dispatches(args):
         print(f"| `{short}` | {grid} | {len(ds)} | {sum(ds) / len(ds):.1f} | {min(ds):.1f} | {max(ds):.1f} |")
 
 
+def _code_only(text):
+    """Source text without comments and with whitespace collapsed, so that an
+    edit of a comment does not count as a change of the kernel."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_sha256():
     h = hashlib.sha256()
     for rel in ("paper_2511_02257_amd/csrc/kernels/kernels.hip", "paper_2511_02257_amd/csrc/kernels/hec.hpp",
                 "paper_2511_02257_amd/csrc/kernels/hec_f64.hip", "paper_2511_02257_amd/csrc/kernels/desc.hpp"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()
 
 
