@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "desc.hpp"
 #include "hec.hpp"
@@ -68,95 +69,129 @@ __device__ __forceinline__ void load4v(T (&r)[4], const T* src) {
   }
 }
 
-// C(t) = sum_ij P[i,j] Q[j,i]: one wave per (root, t), four per workgroup.
-// Lane l takes the 4 x 4 blocks b = l, l + 64, ... with block row ib = b / nb
-// and block column jb = b % nb (nb = ceil(N / 4)): it reads rows 4ib.. of P
-// over columns 4jb.. and rows 4jb.. of Q over columns 4ib.., so every load is
-// a row segment and the transpose happens in registers (no LDS, no barrier).
-// Products and sums in FP64 (exact products for FP32 inputs); each lane adds
-// its blocks in order and the 64 lane sums meet in a fixed butterfly, so the
-// result depends only on the data and N.
-template <typename T>
-__global__ void __launch_bounds__(256) hca_trace(char* __restrict__ arena, const HcaDesc* __restrict__ descs,
+// C(t) = sum_ij P[i,j] Q[j,i] over 4 x 4 blocks b = 0 .. nb^2 - 1 (block row
+// ib = b / nb, block column jb = b % nb, nb = ceil(N / 4)).  A block's loads
+// are 4 rows of P over columns 4jb.. and 4 rows of Q over columns 4ib.., so
+// every load is a row segment and the transpose happens in registers.
+// Summation order, the same in both layouts below: 256 partial sums, sum v
+// adding (by fused multiply-adds, in FP64; exact products for FP32 inputs)
+// the blocks v, v + 256, v + 512, ... in that order; sums 64w .. 64w + 63 meet
+// in a fixed butterfly across a wave's lanes, and the four results are added
+// in order w = 0, 1, 2, 3.  The result depends only on the data and N.
+// Layouts: WG = false, one wave per (root, t), four per workgroup, lane l
+// keeping the sums l, l + 64, l + 128, l + 192 (launches with many traces);
+// WG = true, one workgroup per (root, t), thread x keeping sum x (launches
+// with few traces, which one wave each would spread over few compute units
+// with several rounds of loads per wave).
+template <typename T, bool WG>
+__global__ void __launch_bounds__(256, 3) hca_trace(char* __restrict__ arena, const HcaDesc* __restrict__ descs,
                                                  int n_desc, int64_t n_items) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t base = (int64_t)blockIdx.x * 4; base < n_items; base += (int64_t)gridDim.x * 4) {
-    const int64_t item = base + wave;
-    if (item >= n_items) break;
+  __shared__ double part[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NS = WG ? 1 : 4;      // partial sums per thread
+  constexpr int W = WG ? 256 : 64;    // distance between a thread's sums' first blocks
+  const int x = WG ? tid : lane;
+  const int64_t first = WG ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wave;
+  const int64_t stride = WG ? (int64_t)gridDim.x : (int64_t)gridDim.x * 4;
+  for (int64_t item = first; item - (WG ? 0 : wave) < n_items; item += stride) {
+    if (!WG && item >= n_items) break;
     const int di = find_desc(&descs[0].item_begin, sizeof(HcaDesc) / 4, n_desc, item);
     const HcaDesc& h = descs[di];
     const int t = (int)(item - h.item_begin), n = h.n;
     const int64_t nn = (int64_t)n * n;
     const T* P = reinterpret_cast<const T*>(arena + h.p_off) + (int64_t)t * 2 * nn;
     const T* Q = reinterpret_cast<const T*>(arena + h.q_off) + (int64_t)t * 2 * nn;
-    const int nb = (n + 3) >> 2;
-    double sr = 0.0, si = 0.0;
-    // FP32 blocks are half the bytes, so the whole-block path keeps two of
-    // them in flight per lane (the same bytes as one FP64 block).
-    constexpr int BPI = sizeof(T) == 4 ? 2 : 1;
-    T pr[BPI][4][4], pi[BPI][4][4], qr[BPI][4][4], qi[BPI][4][4];
-    auto accumulate = [&](int u) {
+    const int nb = (n + 3) >> 2, nbb = nb * nb;
+    double sr[NS], si[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) sr[j] = si[j] = 0.0;
+    T pr[4][4], pi[4][4], qr[4][4], qi[4][4];
+    auto accumulate = [&]() {
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const double xr = (double)pr[u][a][c], xi = (double)pi[u][a][c];
-          const double yr = (double)qr[u][c][a], yi = (double)qi[u][c][a];
-          sr += xr * yr - xi * yi;
-          si += xr * yi + xi * yr;
+          const double xr = (double)pr[a][c], xi = (double)pi[a][c];
+          const double yr = (double)qr[c][a], yi = (double)qi[c][a];
+          sr[0] = __builtin_fma(xr, yr, sr[0]);
+          sr[0] = __builtin_fma(-xi, yi, sr[0]);
+          si[0] = __builtin_fma(xr, yi, si[0]);
+          si[0] = __builtin_fma(xi, yr, si[0]);
         }
     };
-    if ((n & 3) == 0) {
-      // N a multiple of 4: every block is whole and every row segment is a
-      // 16-byte aligned run, so the loads are plain vector loads (no masks,
-      // which would otherwise be merged into element-wise loads).
-      for (int b0 = lane; b0 < nb * nb; b0 += 64 * BPI) {
-#pragma unroll
-        for (int u = 0; u < BPI; ++u) {
-          // a block past the end reloads block b0 (in bounds) and is not added
-          const int b = b0 + 64 * u < nb * nb ? b0 + 64 * u : b0;
+    // chunk c0: one block for each of the thread's sums (block c0 + W j for
+    // sum j), each added into sum 0, after which the sums rotate by one, so
+    // that the chunk ends with every sum back in its place (the loop stays
+    // rolled, which keeps one block's registers live at a time).  WHOLE: N a
+    // multiple of 4, so every block is whole and every row segment a 16-byte
+    // aligned run, loaded as plain vector loads (masks would let the compiler
+    // merge them into element-wise loads).
+    auto sweep = [&](auto whole) {
+      constexpr bool WHOLE = decltype(whole)::value;
+      for (int c0 = x; c0 < nbb; c0 += W * NS) {
+#pragma unroll 1
+        for (int q = 0; q < NS; ++q) {
+          // a block past the end reloads block c0 (in bounds) and is not added
+          const int b = c0 + W * q < nbb ? c0 + W * q : c0;
           const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
+          const int vj = min(4, n - j0), vi = min(4, n - i0);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
-            load4v<T>(pr[u][r], P + po);
-            load4v<T>(pi[u][r], P + nn + po);
-            load4v<T>(qr[u][r], Q + qo);
-            load4v<T>(qi[u][r], Q + nn + qo);
+            if constexpr (WHOLE) {
+              load4v<T>(pr[r], P + po);
+              load4v<T>(pi[r], P + nn + po);
+              load4v<T>(qr[r], Q + qo);
+              load4v<T>(qi[r], Q + nn + qo);
+            } else {
+              load4<T>(pr[r], P + po, i0 + r < n ? vj : 0, false);
+              load4<T>(pi[r], P + nn + po, i0 + r < n ? vj : 0, false);
+              load4<T>(qr[r], Q + qo, j0 + r < n ? vi : 0, false);
+              load4<T>(qi[r], Q + nn + qo, j0 + r < n ? vi : 0, false);
+            }
+          }
+          // every load of the block ahead of its first use, so that they are
+          // all in flight at once
+          __builtin_amdgcn_sched_barrier(0);
+          if (c0 + W * q < nbb) accumulate();
+          __builtin_amdgcn_sched_barrier(0);
+          if constexpr (NS > 1) {
+            const double r0 = sr[0], i0s = si[0];
+#pragma unroll
+            for (int j = 0; j + 1 < NS; ++j) {
+              sr[j] = sr[j + 1];
+              si[j] = si[j + 1];
+            }
+            sr[NS - 1] = r0;
+            si[NS - 1] = i0s;
           }
         }
-        // Keep every load of the iteration ahead of its first use, so that
-        // the wave has them all in flight at once instead of waiting between
-        // groups of loads.
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < BPI; ++u)
-          if (b0 + 64 * u < nb * nb) accumulate(u);
       }
-    } else {
-      for (int b = lane; b < nb * nb; b += 64) {
-        const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
-        const int vj = min(4, n - j0), vi = min(4, n - i0);
+    };
+    if ((n & 3) == 0) sweep(std::true_type{});
+    else sweep(std::false_type{});
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
-          load4<T>(pr[0][r], P + po, i0 + r < n ? vj : 0, false);
-          load4<T>(pi[0][r], P + nn + po, i0 + r < n ? vj : 0, false);
-          load4<T>(qr[0][r], Q + qo, j0 + r < n ? vi : 0, false);
-          load4<T>(qi[0][r], Q + nn + qo, j0 + r < n ? vi : 0, false);
-        }
-        accumulate(0);
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        sr[j] += __shfl_xor(sr[j], o);
+        si[j] += __shfl_xor(si[j], o);
       }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      sr += __shfl_xor(sr, o);
-      si += __shfl_xor(si, o);
-    }
-    if (lane == 0) {
-      double* out = reinterpret_cast<double*>(arena + h.out_off);
-      out[2 * t] = sr;
-      out[2 * t + 1] = si;
+    double* out = reinterpret_cast<double*>(arena + h.out_off);
+    if constexpr (WG) {
+      if (lane == 0) {
+        part[0][wave] = sr[0];
+        part[1][wave] = si[0];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        out[2 * t] = ((part[0][0] + part[0][1]) + part[0][2]) + part[0][3];
+        out[2 * t + 1] = ((part[1][0] + part[1][1]) + part[1][2]) + part[1][3];
+      }
+      __syncthreads();
+    } else if (lane == 0) {
+      out[2 * t] = ((sr[0] + sr[1]) + sr[2]) + sr[3];
+      out[2 * t + 1] = ((si[0] + si[1]) + si[2]) + si[3];
     }
   }
 }
@@ -245,6 +280,9 @@ unsigned persistent_grid(const void* kernel, int block, int64_t items) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, resident));
 }
 constexpr int64_t kMaxGrid = 1 << 20;
+// traces per launch from which one wave per trace still fills 256 compute
+// units with a workgroup of four waves each
+constexpr int64_t kHcaWaveItems = 4 * 256;
 unsigned grid_for(int64_t items) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, kMaxGrid)); }
 
 void set_args(KernelCall& k, char* arena, const void* desc, int n_desc, int64_t n_items) {
@@ -313,10 +351,15 @@ hipError_t reduce_call(int prec, char* arena, int64_t desc_off, int n_desc, int6
   return hipSuccess;
 }
 
+// The trace layout by launch size: one wave per trace while that still gives
+// every compute unit a workgroup (256 CUs), else one workgroup per trace.
 hipError_t hca_call(int prec, char* arena, int64_t desc_off, int n_desc, int64_t n_items, KernelCall* k) {
-  k->fn = prec == 0 ? reinterpret_cast<const void*>(&hca_trace<double>)
-                    : reinterpret_cast<const void*>(&hca_trace<float>);
-  k->grid = grid_for((n_items + 3) / 4);
+  const bool wg = n_items < kHcaWaveItems;
+  k->fn = prec == 0 ? (wg ? reinterpret_cast<const void*>(&hca_trace<double, true>)
+                          : reinterpret_cast<const void*>(&hca_trace<double, false>))
+                    : (wg ? reinterpret_cast<const void*>(&hca_trace<float, true>)
+                          : reinterpret_cast<const void*>(&hca_trace<float, false>));
+  k->grid = grid_for(wg ? n_items : (n_items + 3) / 4);
   k->block = 256;
   set_args(*k, arena, arena + desc_off, n_desc, n_items);
   return hipSuccess;

@@ -493,6 +493,40 @@ def test_captured_transfer_segments_replay(meson_small, prec, policy, look, mode
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nvec", [7, 12])
+def test_trace_layouts(prec, nvec):
+    """The root trace in both of its layouts: launches of at least 1024 traces
+    (one wave per trace) and of fewer (one workgroup per trace), with N a
+    multiple of 4 (vector loads) and not (masked loads): against the oracle,
+    and the same bits from both layouts (waves of every ready contraction
+    against one launch per contraction, on the same DAG)."""
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd.device import DeviceRunner
+    for nt, many in ((64, True), (3, False)):
+        wl = W.meson_ring(n_leaves=10, nvec=nvec, nt=nt, n_graphs=60, lmin=2, lmax=3, sigma=1 / 4, n_corr=3,
+                          seed=41, name="trace_layouts")
+        ref = OV.correlators(wl)
+        ctx = X.Context()
+        ctx.build_cdag(wl.leaves, wl.graphs)
+        ctx.schedule("tree")
+        runner = DeviceRunner(ctx, 0)
+        bits = []
+        for batched in (True, False):
+            ctx.set_options(leaves_resident=True, wave_lookahead=X.binding.LOOKAHEAD_ALL, use_graphs=0)
+            ctx.set_timing(True)
+            runner.run(prec, batched)
+            items = [r["n_items"] for r in ctx.launch_records() if r["type"] == "hca"]
+            assert (max(items) >= 1024) == (many and batched), items
+            err = rel_errors(ctx.fetch_correlators(), ref)
+            print(f"N={nvec} nt={nt} {prec} batched={batched}: trace launches of at most {max(items)}, "
+                  f"max rel {err.max():.3e}")
+            assert err.max() <= TOL[prec]
+            bits.append(np.concatenate(ctx.fetch_correlators()).view(np.uint64).copy())
+        assert np.array_equal(bits[0], bits[1])
+        ctx.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
 def test_degenerate_dags(prec):
     """Edge cases of the method: a DAG of leaves with no graph; roots that
