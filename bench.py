@@ -75,17 +75,22 @@ def kernel_table(records, prec):
     frac_mfma counts algorithmic flops; frac_pipe the flops the matrix cores
     execute (three real products per complex one in the Gauss tiles: 3/4 of
     the algorithmic count).  A split-K contraction kind also gets an entry
-    that charges its reduction kernels to it ("hec+reduce")."""
+    that charges its reduction kernels to it ("hec+reduce").  A contraction
+    launch that carries its step's root traces ("hec:...+HCA") counts their
+    flops and bytes in its totals; frac_mfma and frac_pipe count only the
+    contractions' flops."""
     agg = {}
     for r in records:
         if r["type"] in ("h2d", "d2h"):
             continue
         key = r["type"] if r["type"] == "xsum" else r["type"] + ":" + "+".join(KIND_NAMES[k] for k in r["kinds"])
-        a = agg.setdefault(key, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0, "pipe_flops": 0.0})
+        a = agg.setdefault(key, {"launches": 0, "ms": 0.0, "flops": 0.0, "bytes": 0.0, "mfma_flops": 0.0,
+                                 "pipe_flops": 0.0})
         a["launches"] += 1
         a["ms"] += r["ms"]
-        a["flops"] += r["flops"]
-        a["bytes"] += r["bytes"]
+        a["flops"] += r["flops"] + r.get("trace_flops", 0.0)
+        a["bytes"] += r["bytes"] + r.get("trace_bytes", 0.0)
+        a["mfma_flops"] += r["flops"]
         gauss = r["type"] == "hec" and prec in ("fp64", "fp32") and (r["variant"] % 6 in GAUSS_TILES or r["variant"] == 24)
         a["pipe_flops"] += r["flops"] * (0.75 if gauss else 1.0)
     for key in [k for k in agg if k.startswith("reduce:")]:
@@ -94,7 +99,8 @@ def kernel_table(records, prec):
             agg["hec+reduce:" + key.split(":", 1)[1]] = {
                 "launches": agg[hk]["launches"] + agg[key]["launches"],
                 "ms": agg[hk]["ms"] + agg[key]["ms"], "flops": agg[hk]["flops"],
-                "bytes": agg[hk]["bytes"], "pipe_flops": agg[hk]["pipe_flops"]}
+                "bytes": agg[hk]["bytes"], "mfma_flops": agg[hk]["mfma_flops"],
+                "pipe_flops": agg[hk]["pipe_flops"]}
     for key, a in agg.items():
         sec = a["ms"] * 1e-3
         if sec <= 0:
@@ -102,12 +108,12 @@ def kernel_table(records, prec):
         a["TFLOP/s"] = round(a["flops"] / sec / 1e12, 3)
         a["GB/s"] = round(a["bytes"] / sec / 1e9, 1)
         if key.startswith("hec"):
-            a["frac_mfma"] = round(a["flops"] / sec / 1e12 / PEAK[prec], 4)
+            a["frac_mfma"] = round(a["mfma_flops"] / sec / 1e12 / PEAK[prec], 4)
             a["frac_pipe"] = round(a["pipe_flops"] / sec / 1e12 / PEAK[prec], 4)
         if not key.startswith("reduce"):
             a["frac_hbm"] = round(a["bytes"] / sec / 1e9 / HBM_PEAK, 4)
         a["ms"] = round(a["ms"], 4)
-        del a["pipe_flops"]
+        del a["pipe_flops"], a["mfma_flops"]
     return agg
 
 
@@ -204,8 +210,9 @@ def k64_kernels(args, X, W, DeviceRunner):
     """Kernel-only references of the K = 64 exterior contractions, for profiling: the
     meson DAG (K22) in FP64 and FP32 and the baryon DAG (K32, K33) in FP32, every leaf
     resident, Tree order, every ready contraction in a wave, eager issue.  Kernel choices
-    from --tiles (else the in-situ autotuner).  Per part: the time per execute and the
-    kernel table of one timed execute."""
+    from --tiles (else the in-situ autotuner); root traces in launches of their own, so
+    that the contraction launches time the contractions alone.  Per part: the time per
+    execute and the kernel table of one timed execute."""
     tiles = given_tiles(args)
     out = {}
     for name, prec in (("meson_ring", "fp64"), ("meson_ring", "fp32"), ("baryon_mix", "fp32")):
@@ -214,6 +221,7 @@ def k64_kernels(args, X, W, DeviceRunner):
         ctx.build_cdag(wl.leaves, wl.graphs)
         del wl
         ctx.schedule("tree")
+        ctx.set_trace_fusion(False)
         ctx.set_options(leaves_resident=True, wave_lookahead=ALL, use_graphs=0)
         runner = DeviceRunner(ctx, 0)
         if prec in tiles:
@@ -423,6 +431,13 @@ def meson_budgeted(args, X, W, DeviceRunner):
         row["bits_equal_resident"] = bool(np.array_equal(np.concatenate(ctx.fetch_correlators()).view(np.uint64), ref))
         row.update(plan_summary(s2["plan"]))
         row["tflops_best"] = round(s2["plan"]["flops"] / (min(v for k, v in row.items() if k.endswith("_ms")) * 1e-3) / 1e12, 3)
+        if (policy, look, chunks) == ("tree", 384, 16):
+            # the same with every step's root traces in a launch of their own
+            ctx.set_trace_fusion(False)
+            ctx.set_options(leaves_resident=False, wave_lookahead=look, use_graphs=1)
+            d2, _ = timed_steps(runner, "fp64", True, 3, 1)
+            row["one-stream segments_traces_unfused_ms"] = round(d2 / 3 * 1e3, 3)
+            ctx.set_trace_fusion(True)
         key = f"{policy}_lookahead{look}" + (f"_{chunks}passes" if chunks > 1 else "")
         out[key] = row
         log("meson", key, row)

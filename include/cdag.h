@@ -195,6 +195,10 @@ typedef struct {
   double ms;          /* duration between HIP events around the launch or the copy, on
                          the stream that runs it (transfers: the upload or the spill
                          stream, after any wait for another stream)                     */
+  int64_t trace_items;  /* HEC carrying its step's root traces (cdag_set_trace_fusion):
+                           the (root, t) traces it ran besides n_items; else 0          */
+  double trace_flops;   /* their algorithmic flops and bytes (not in flops and bytes);  */
+  double trace_bytes;   /* else 0                                                       */
 } cdag_launch_record;
 
 /* One record of a traced execute (cdag_trace_execute). */
@@ -340,6 +344,19 @@ int cdag_set_options(cdag_ctx* c, int leaves_resident, int wave_max, int64_t wav
  * the memory model of Sec. II-C.  CDAG_E_INVALID for t_chunks < 1; planning
  * fails with CDAG_E_INVALID when t_chunks does not divide every tensor's nt. */
 int cdag_set_time_chunks(cdag_ctx* c, int64_t t_chunks);
+
+/* Trace fusion (engine design, Sec. IV-B's execution queue): with on != 0 the
+ * root traces of a plan step (Sec. IV-B, "contract all") ride in one of the
+ * step's exterior-contraction launches, in workgroups after its contractions'
+ * work items, instead of a launch of their own, so that a step whose
+ * contractions and traces are both ready is one kernel.  The carrier is the
+ * step's last contraction launch of one workgroup per item (not the general
+ * kernel); a step without one keeps a trace launch.  Correlators are
+ * bit-identical either way (the traces' summation order does not depend on
+ * how they are launched).  Launch records then show the traces inside the
+ * carrier (CDAG_KIND bit CDAG_HCA_TRACE in kinds; trace_items, trace_flops,
+ * trace_bytes).  Default 1. */
+int cdag_set_trace_fusion(cdag_ctx* c, int on);
 
 /* timing: 1 records a HIP event pair around every kernel launch on the
  * compute stream and around every host transfer on its stream, reports

@@ -73,7 +73,8 @@ class cdag_exec_stats(C.Structure):
 class cdag_launch_record(C.Structure):
     _fields_ = [("type", C.c_int32), ("variant", C.c_int32), ("kinds", C.c_int32),
                 ("interior", C.c_int32), ("step", C.c_int64), ("n_items", C.c_int64),
-                ("flops", C.c_double), ("bytes", C.c_double), ("ms", C.c_double)]
+                ("flops", C.c_double), ("bytes", C.c_double), ("ms", C.c_double),
+                ("trace_items", C.c_int64), ("trace_flops", C.c_double), ("trace_bytes", C.c_double)]
 
 
 LAUNCH_TYPES = {0: "hec", 1: "reduce", 2: "hca", 3: "xsum", 4: "h2d", 5: "d2h"}
@@ -121,6 +122,7 @@ def lib():
             "cdag_set_options": [P, C.c_int, C.c_int, I64, C.c_int],
             "cdag_set_timing": [P, C.c_int],
             "cdag_set_time_chunks": [P, I64],
+            "cdag_set_trace_fusion": [P, C.c_int],
             "cdag_dag_stats": [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_double),
                                C.POINTER(C.c_double)],
             "cdag_launch_records": [P, C.POINTER(cdag_launch_record), I64, C.POINTER(I64)],
@@ -154,6 +156,7 @@ def lib():
 EXPORTED = ("cdag_create", "cdag_destroy", "cdag_last_error", "build_cdag", "cdag_build_general",
             "cdag_set_specs", "schedule",
             "set_mem_budget", "cdag_set_order", "cdag_set_options", "cdag_set_timing", "cdag_set_time_chunks",
+            "cdag_set_trace_fusion",
             "cdag_launch_records",
             "cdag_trace_execute", "cdag_dag_stats", "cdag_set_tile", "cdag_get_tile", "cdag_memsim",
             "cdag_plan", "cdag_plan_ops",
@@ -282,6 +285,10 @@ def cdag_set_time_chunks(h, t_chunks: int) -> None:
     _check(lib().cdag_set_time_chunks(h, int(t_chunks)))
 
 
+def cdag_set_trace_fusion(h, on: bool) -> None:
+    _check(lib().cdag_set_trace_fusion(h, int(bool(on))))
+
+
 def cdag_set_timing(h, on: bool) -> None:
     _check(lib().cdag_set_timing(h, int(bool(on))))
 
@@ -305,7 +312,8 @@ def cdag_launch_records(h):
     for r in buf[:n.value]:
         out.append({"type": LAUNCH_TYPES[r.type], "variant": r.variant, "interior": bool(r.interior),
                     "kinds": [k for k in range(8) if r.kinds >> k & 1], "step": r.step,
-                    "n_items": r.n_items, "flops": r.flops, "bytes": r.bytes, "ms": r.ms})
+                    "n_items": r.n_items, "flops": r.flops, "bytes": r.bytes, "ms": r.ms,
+                    "trace_items": r.trace_items, "trace_flops": r.trace_flops, "trace_bytes": r.trace_bytes})
     return out
 
 
@@ -500,6 +508,9 @@ class Context:
 
     def set_time_chunks(self, t_chunks=1):
         cdag_set_time_chunks(self.h, t_chunks)
+
+    def set_trace_fusion(self, on=True):
+        cdag_set_trace_fusion(self.h, on)
 
     def set_timing(self, on=True):
         cdag_set_timing(self.h, on)

@@ -70,7 +70,7 @@ void ensure_plan(Ctx& c, int prec, int batched) {
   o.t_chunks = c.t_chunks;
   c.plan = make_plan(c.dag, c.order, o);
   place(c.dag, c.plan);
-  c.kplan = make_kernel_plan(c.dag, c.plan, prec, c.tiles);
+  c.kplan = make_kernel_plan(c.dag, c.plan, prec, c.tiles, c.fuse_traces);
   // host result buffers sized with the plan (an execute then writes them
   // without allocating)
   c.corr_host.resize(c.kplan.corr_bytes / 8);
@@ -272,6 +272,14 @@ int cdag_set_time_chunks(cdag_ctx* h, int64_t t_chunks) {
   return guard([&] {
     need(t_chunks >= 1, CDAG_E_INVALID, "t_chunks must be >= 1");
     h->c.t_chunks = t_chunks;
+    h->c.version++;
+  });
+}
+
+int cdag_set_trace_fusion(cdag_ctx* h, int on) {
+  if (!h) return fail(CDAG_E_INVALID, "ctx is NULL");
+  return guard([&] {
+    h->c.fuse_traces = on != 0;
     h->c.version++;
   });
 }

@@ -35,6 +35,7 @@ struct Ctx {
   int64_t wave_lookahead = 0;
   int use_graphs = 1;            // 0 eager, 1 one-stream segments, 2 three-stream graph
   int64_t t_chunks = 1;
+  bool fuse_traces = true;       // a step's traces ride in one of its contraction launches
   bool timing = false;
   TileTable tiles;               // (prec, kind, N) -> kernel variant overrides
   uint64_t version = 1;          // bumped by every change that invalidates a plan

@@ -113,7 +113,7 @@ int default_tile(int prec, int kind, int n) {
   return choice_of(variant_of(tile, 1), true);
 }
 
-KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTable& tiles) {
+KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTable& tiles, bool fuse_traces) {
   KernelPlan kp;
   kp.prec = prec;
   const int64_t acc_bytes = prec == CDAG_FP64 ? 8 : 4;   // one real accumulator
@@ -194,6 +194,7 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
       return planned + shift;
     };
     for (int64_t s = 0; s < S; ++s) {
+      const size_t step_first = kp.launches.size();
       kp.launch_off.push_back((int64_t)kp.launches.size());
       constexpr int kGroups = kNumVariants + 1;   // the variants, then the general kernel
       std::vector<HecDesc> hec[kGroups];
@@ -301,14 +302,36 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
         kp.launches.push_back(L);
       }
       if (!hca.empty()) {
-        Launch L{L_HCA, 0, (int32_t)hca.size(), 0, 0, 0};
-        L.flops = hca_flops;
-        L.bytes = hca_bytes;
-        L.kinds = 1 << HCA;
-        for (auto& h : hca) { h.item_begin = (int32_t)L.n_items; L.n_items += h.nt; }
-        L.host_desc = (int64_t)kp.blob.size();
-        for (auto& h : hca) put(kp.blob, h);
-        kp.launches.push_back(L);
+        int64_t n_titems = 0;
+        for (auto& h : hca) { h.item_begin = (int32_t)n_titems; n_titems += h.nt; }
+        // the exterior-contraction launch of this step that carries the
+        // traces, if fused: the last one of one workgroup per item whose grid
+        // stays within kMaxGrid with the trace workgroups added
+        Launch* carrier = nullptr;
+        for (size_t li = kp.launches.size(); fuse_traces && li-- > step_first;) {
+          Launch& L = kp.launches[li];
+          if (L.type != L_HEC || L.tile == kGenVariant || variant_grid(L.tile) != 1) continue;
+          if (L.n_items + trace_blocks(kTileShapes[variant_tile(L.tile)].nth, n_titems) > kMaxGrid) continue;
+          carrier = &L;
+          break;
+        }
+        if (carrier) {
+          carrier->tr_n_desc = (int32_t)hca.size();
+          carrier->tr_n_items = n_titems;
+          carrier->tr_flops = hca_flops;
+          carrier->tr_bytes = hca_bytes;
+          carrier->kinds |= 1 << HCA;
+          carrier->tr_host_desc = (int64_t)kp.blob.size();
+          for (auto& h : hca) put(kp.blob, h);
+        } else {
+          Launch L{L_HCA, 0, (int32_t)hca.size(), 0, n_titems, 0};
+          L.flops = hca_flops;
+          L.bytes = hca_bytes;
+          L.kinds = 1 << HCA;
+          L.host_desc = (int64_t)kp.blob.size();
+          for (auto& h : hca) put(kp.blob, h);
+          kp.launches.push_back(L);
+        }
       }
     }
   }
@@ -353,6 +376,11 @@ KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTab
     if (L.type == L_HCA) {
       auto* h = reinterpret_cast<HcaDesc*>(kp.blob.data() + L.host_desc);
       for (int32_t i = 0; i < L.n_desc; ++i) h[i].out_off = kp.corr_off + (-1 - h[i].out_off);
+    }
+    if (L.tr_n_desc > 0) {
+      L.tr_desc_off = kp.blob_off + L.tr_host_desc;
+      auto* h = reinterpret_cast<HcaDesc*>(kp.blob.data() + L.tr_host_desc);
+      for (int32_t i = 0; i < L.tr_n_desc; ++i) h[i].out_off = kp.corr_off + (-1 - h[i].out_off);
     }
   }
   kp.xsum.desc_off = kp.blob_off + kp.xsum.host_desc;

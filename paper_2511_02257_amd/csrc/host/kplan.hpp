@@ -25,6 +25,12 @@ struct Launch {
   double bytes = 0;   // HEC, HCA: algorithmic bytes; RED: workspace read + output write
   int32_t kinds = 0;  // bit k set when a contraction of kind k is in the launch
   int32_t interior = 0;   // HEC: every contraction interior (hec_interior) for the variant's tile
+  // HEC carrying the root traces of its step (trace fusion): tr_n_desc HcaDesc
+  // at tr_desc_off (blob offset tr_host_desc), tr_n_items (root, t) items, and
+  // their algorithmic flops and bytes (not in flops and bytes above)
+  int32_t tr_n_desc = 0;
+  int64_t tr_desc_off = 0, tr_host_desc = 0, tr_n_items = 0;
+  double tr_flops = 0, tr_bytes = 0;
 };
 
 // Kernel variant of an exterior contraction: a tile shape (index into
@@ -104,6 +110,10 @@ struct KernelPlan {
 int64_t elem_bytes_of(int prec);                 // 16 for FP64, 8 otherwise
 // Strides of spec s on tensors of dimension n (desc.hpp, IndexMap).
 IndexMap index_map(const Spec& s, int n);
-KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTable& tiles);
+// fuse_traces: a step's root traces ride in one of its exterior-contraction
+// launches (the last of one workgroup per item, not the general kernel) when
+// it has one, instead of a launch of their own; either way the traces give
+// the same bits.
+KernelPlan make_kernel_plan(const Dag& d, const Plan& p, int prec, const TileTable& tiles, bool fuse_traces = false);
 
 }  // namespace cdag

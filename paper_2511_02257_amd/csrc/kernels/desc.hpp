@@ -26,6 +26,17 @@ constexpr TileShape kTileShapes[kNumTiles] = {
 // one past the tile x grid x stages variants.
 constexpr int kGenVariantId = 4 * kNumTiles;
 
+// Most workgroups in one launch; a launch with more work items strides.
+constexpr int64_t kMaxGrid = 1 << 20;
+// Root traces that one workgroup of `nth` threads takes when an exterior-
+// contraction launch carries its step's traces (a group of four waves per
+// trace; a 64-thread workgroup takes one as a single wave), and the
+// workgroups that n of them need.
+constexpr int traces_per_block(int nth) { return nth >= 256 ? nth / 256 : 1; }
+constexpr int64_t trace_blocks(int nth, int64_t n) {
+  return (n + traces_per_block(nth) - 1) / traces_per_block(nth);
+}
+
 // One exterior contraction inside a grouped launch.
 struct HecDesc {
   int64_t a_off, b_off, c_off;   // t = 0 slice of A, B and C

@@ -259,6 +259,218 @@ __device__ __forceinline__ void load16b(T (&r)[16 / sizeof(T)], const T* src, in
   }
 }
 
+// ------------------------------------------------------------------ root traces
+// K consecutive elements of one row (K = 2 or 4): WHOLE, vector loads from a
+// K-element aligned address; otherwise element-wise, the first `valid` of
+// them, with zero fill: every lane loads (element 0 in place of one past the
+// run, and `safe`, an address in range, when the run is empty), so that no
+// load sits behind a branch and the addresses need not stay live.
+template <typename T, int K, bool WHOLE>
+__device__ __forceinline__ void load_run(T (&r)[K], const T* src, int valid, const T* safe) {
+  if constexpr (WHOLE) {
+    constexpr int V = (int)(16 / sizeof(T)) < K ? (int)(16 / sizeof(T)) : K;   // elements per load
+    typedef T VT __attribute__((ext_vector_type(V)));
+#pragma unroll
+    for (int q = 0; q < K / V; ++q) {
+      const VT v = *reinterpret_cast<const VT*>(src + q * V);
+#pragma unroll
+      for (int x = 0; x < V; ++x) r[q * V + x] = v[x];
+    }
+  } else {
+    const T* base = valid > 0 ? src : safe;
+#pragma unroll
+    for (int x = 0; x < K; ++x) {
+      const T v = base[x < valid ? x : 0];
+      r[x] = x < valid ? v : T(0);
+    }
+  }
+}
+
+// C(t) = sum_ij P[i,j] Q[j,i] over 4 x 4 blocks b = 0 .. nb^2 - 1 (block row
+// ib = b / nb, block column jb = b % nb, nb = ceil(N / 4)).  A block reads 4
+// rows of P over columns 4jb.. and 4 rows of Q over columns 4ib.., so every
+// load is a row segment and the transpose happens in registers; within a
+// block the terms P[a][c] Q[c][a] are added for a = 0..3, c = 0..3 in that
+// order.  Summation order, the same in every layout: 256 partial sums, sum v
+// adding (by fused multiply-adds, in FP64; exact products for FP32 inputs) the
+// blocks v, v + 256, v + 512, ... in that order; sums 64w .. 64w + 63 meet in
+// a fixed butterfly across a wave's lanes, and the four results are added in
+// order w = 0, 1, 2, 3.  The result depends only on the data and N.
+//
+// The NS partial sums of one thread: sum j takes the blocks x + W j + 256 r,
+// r = 0, 1, ... (x: the thread's place in its layout; W NS = 256).  A chunk
+// brings one block for each of the sums, each added into sum 0, after which
+// the sums rotate by one, so that the chunk ends with every sum back in its
+// place (the loop stays rolled, which keeps one block's registers live at a
+// time).  A block is loaded RPB rows of P (a = h RPB ..) at a time, with the
+// matching RPB columns of Q's 4 rows: RPB = 4, all of it at once; RPB = 2, in
+// two halves, which halves the registers (the order of the terms is the
+// same).  WHOLE: N a multiple of 4, so every block is whole and every row
+// segment aligned, loaded as plain vector loads (masks would let the
+// compiler merge them into element-wise loads).
+template <typename T, int NS, bool WHOLE, int RPB>
+__device__ __forceinline__ void trace_sums(const T* P, const T* Q, int n, int x, double (&sr)[NS],
+                                           double (&si)[NS]) {
+  constexpr int W = 256 / NS;
+  const int64_t nn = (int64_t)n * n;
+  const int nb = (n + 3) >> 2, nbb = nb * nb;
+  T pr[RPB][4], pi[RPB][4], qr[4][RPB], qi[4][RPB];
+#pragma unroll 1
+  for (int c0 = x; c0 < nbb; c0 += 256) {
+#pragma unroll 1
+    for (int q = 0; q < NS; ++q) {
+      // a block past the end reloads block c0 (in bounds) and is not added
+      const bool add = c0 + W * q < nbb;
+      const int b = add ? c0 + W * q : c0;
+      const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
+#pragma unroll
+      for (int h = 0; h < 4 / RPB; ++h) {
+        const int ia = i0 + h * RPB;    // first P row (and Q column) of this part
+#pragma unroll
+        for (int r = 0; r < RPB; ++r) {
+          const int64_t po = (int64_t)(ia + r) * n + j0;
+          const int valid = ia + r < n ? min(4, n - j0) : 0;
+          load_run<T, 4, WHOLE>(pr[r], P + po, valid, P);
+          load_run<T, 4, WHOLE>(pi[r], P + nn + po, valid, P);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t qo = (int64_t)(j0 + c) * n + ia;
+          const int valid = j0 + c < n ? max(0, min(RPB, n - ia)) : 0;
+          load_run<T, RPB, WHOLE>(qr[c], Q + qo, valid, Q);
+          load_run<T, RPB, WHOLE>(qi[c], Q + nn + qo, valid, Q);
+        }
+        // every load of the part ahead of its first use, so that they are all
+        // in flight at once
+        __builtin_amdgcn_sched_barrier(0);
+        if (add) {
+#pragma unroll
+          for (int a = 0; a < RPB; ++a)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+              const double xr = (double)pr[a][c], xi = (double)pi[a][c];
+              const double yr = (double)qr[c][a], yi = (double)qi[c][a];
+              sr[0] = __builtin_fma(xr, yr, sr[0]);
+              sr[0] = __builtin_fma(-xi, yi, sr[0]);
+              si[0] = __builtin_fma(xr, yi, si[0]);
+              si[0] = __builtin_fma(xi, yr, si[0]);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // the next part's loads stay after this part's products (the
+        // compiler would otherwise merge Q's adjacent column pairs of the two
+        // halves into one load, and hold both halves' registers)
+        if constexpr (RPB < 4) asm volatile("" ::: "memory");
+      }
+      if constexpr (NS > 1) {
+        const double r0 = sr[0], i0s = si[0];
+#pragma unroll
+        for (int j = 0; j + 1 < NS; ++j) {
+          sr[j] = sr[j + 1];
+          si[j] = si[j + 1];
+        }
+        sr[NS - 1] = r0;
+        si[NS - 1] = i0s;
+      }
+    }
+  }
+}
+
+// Where trace item `item` reads and writes (every lane of the wave calls it
+// with the same item).
+template <typename T>
+struct TraceItem {
+  const T *P, *Q;
+  int n, t;
+  double* out;
+  __device__ __forceinline__ TraceItem(char* arena, const HcaDesc* descs, int n_desc, int64_t item) {
+    const HcaDesc& h = descs[find_desc(&descs[0].item_begin, sizeof(HcaDesc) / 4, n_desc, item)];
+    t = (int)(item - h.item_begin);
+    n = h.n;
+    const int64_t nn = (int64_t)n * n;
+    P = reinterpret_cast<const T*>(arena + h.p_off) + (int64_t)t * 2 * nn;
+    Q = reinterpret_cast<const T*>(arena + h.q_off) + (int64_t)t * 2 * nn;
+    out = reinterpret_cast<double*>(arena + h.out_off) + 2 * t;
+  }
+  template <int NS, int RPB>
+  __device__ __forceinline__ void sums(int x, double (&sr)[NS], double (&si)[NS]) const {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) sr[j] = si[j] = 0.0;
+    if ((n & 3) == 0) trace_sums<T, NS, true, RPB>(P, Q, n, x, sr, si);
+    else trace_sums<T, NS, false, RPB>(P, Q, n, x, sr, si);
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        sr[j] += __shfl_xor(sr[j], o);
+        si[j] += __shfl_xor(si[j], o);
+      }
+  }
+};
+
+// Wave layout: one trace per wave, lane l keeping the sums l, l + 64, l + 128,
+// l + 192.  No barrier.
+template <typename T, int RPB>
+__device__ __forceinline__ void trace_wave(char* arena, const HcaDesc* descs, int n_desc, int64_t item) {
+  const TraceItem<T> it(arena, descs, n_desc, item);
+  double sr[4], si[4];
+  it.template sums<4, RPB>(threadIdx.x & 63, sr, si);
+  if ((threadIdx.x & 63) == 0) {
+    it.out[0] = ((sr[0] + sr[1]) + sr[2]) + sr[3];
+    it.out[1] = ((si[0] + si[1]) + si[2]) + si[3];
+  }
+}
+
+// Workgroup layout: one trace per group of four waves (g_tid = 0 .. 255, the
+// thread's place in its group), thread x keeping sum x; the four wave sums
+// meet in `part` (the group's LDS).  Holds two workgroup barriers, so every
+// thread of the workgroup calls it equally often; a group with active = false
+// takes part in the barriers only.
+template <typename T, int RPB>
+__device__ __forceinline__ void trace_group(char* arena, const HcaDesc* descs, int n_desc, int64_t item, bool active,
+                                            int g_tid, double (&part)[2][4]) {
+  const int wave = g_tid >> 6;
+  double sr[1] = {0.0}, si[1] = {0.0};
+  double* out = nullptr;
+  if (active) {
+    const TraceItem<T> it(arena, descs, n_desc, item);
+    it.template sums<1, RPB>(g_tid, sr, si);
+    out = it.out;
+    if ((g_tid & 63) == 0) {
+      part[0][wave] = sr[0];
+      part[1][wave] = si[0];
+    }
+  }
+  __syncthreads();
+  if (active && g_tid == 0) {
+    out[0] = ((part[0][0] + part[0][1]) + part[0][2]) + part[0][3];
+    out[1] = ((part[1][0] + part[1][1]) + part[1][2]) + part[1][3];
+  }
+  __syncthreads();
+}
+
+// Traces carried by an exterior-contraction launch (the traces of the same
+// plan step, which read only earlier steps' outputs): block b after the
+// contractions' work items takes traces b * G .. b * G + G - 1, G = NTH / 256
+// (traces_per_block) in the workgroup layout, or one in the wave layout for
+// 64-thread tiles; blocks load in halves, so that the trace path needs no
+// more registers than the contractions do.
+template <typename T, int NTH>
+__device__ __forceinline__ void trace_block(char* arena, const HcaDesc* descs, int n_desc, int64_t n_items,
+                                            int64_t b) {
+  if constexpr (NTH >= 256) {
+    static_assert(NTH % 256 == 0, "whole groups of four waves");
+    constexpr int G = traces_per_block(NTH);
+    __shared__ double part[G][2][4];
+    const int g = (int)threadIdx.x / 256;
+    const int64_t item = b * G + g;
+    trace_group<T, 2>(arena, descs, n_desc, item, item < n_items, (int)threadIdx.x % 256, part[g]);
+  } else {
+    static_assert(NTH == 64, "one wave");
+    if (b < n_items) trace_wave<T, 2>(arena, descs, n_desc, b);
+  }
+}
+
 // Store one 16x16 block pair (Re, Im) of accumulators with the instruction's
 // row layout; rows and columns outside M x N are skipped (INNER: the block is
 // known to lie inside).  NT: non-temporal stores, which keep a launch's
@@ -295,10 +507,16 @@ __device__ __forceinline__ void store_block(T* C, int M, int N, int row0, int co
 // loaded and the output stored through its IndexMap, element by element.
 // FULL: every contraction of the launch is interior (hec_interior): operands
 // load with unpredicated 16-byte loads and outputs store without bounds tests.
-template <typename T, class TL, int ST, bool PF, bool GEN = false, bool FULL = false>
+// TR: the launch also carries the root traces of its plan step (n_titems
+// (root, t) items described by tdescs), in the workgroups after the
+// contractions' work items (one workgroup per item; trace_block); without TR
+// the last three arguments are unused.
+template <typename T, class TL, int ST, bool PF, bool GEN = false, bool FULL = false, bool TR = false>
 __global__ void __launch_bounds__(TL::NTH, (Occupancy<sizeof(T) == 8 ? 0 : 1, TL, ST, PF>::waves))
-hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc, int64_t n_items) {
+hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc, int64_t n_items,
+         const HcaDesc* __restrict__ tdescs, int n_tdesc, int64_t n_titems) {
   static_assert(!(GEN && FULL), "a general contraction is never interior");
+  static_assert(!(TR && (PF || GEN)), "traces ride only in launches of one workgroup per item");
   typedef typename Mfma<T>::V V;
   constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
   // k-slice: 16 (FP64) or 32 (FP32) k per LDS stage, so that a K = 64
@@ -430,6 +648,12 @@ hec_mfma(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc
   };
 
   int64_t item = blockIdx.x;
+  if constexpr (TR) {
+    if (item >= n_items) {
+      trace_block<T, NTH>(arena, tdescs, n_tdesc, n_titems, item - n_items);
+      return;
+    }
+  }
   if (item >= n_items) return;
   ItemView<T> cur = view_item<T, BM, BN>(arena, descs, n_desc, item);
   gload(cur, cur.kbeg);
@@ -650,9 +874,12 @@ template <int P> __device__ constexpr int term_y(int t) {
   return P == 2 ? (t == 1 ? 1 : 0) : (t == 1 ? 2 : (t == 2 || t == 4) ? 1 : 0);
 }
 
-template <class TL, int ST_, bool PF, int P, bool FULL = false>
+// TR as in hec_mfma (the traces read the FP32 storage of these modes).
+template <class TL, int ST_, bool PF, int P, bool FULL = false, bool TR = false>
 __global__ void __launch_bounds__(TL::NTH, (Occupancy<2, TL, ST_, PF>::waves))
-hec_bf16(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc, int64_t n_items) {
+hec_bf16(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc, int64_t n_items,
+         const HcaDesc* __restrict__ tdescs, int n_tdesc, int64_t n_titems) {
+  static_assert(!(TR && PF), "traces ride only in launches of one workgroup per item");
   constexpr int NTH = TL::NTH, BM = TL::BM, BN = TL::BN, TM = TL::TM, TN = TL::TN;
   constexpr int BK = 32, PAD = BK + 8;     // bf16 per LDS row (16-byte aligned rows)
   // Two stages of three pieces of the 128 x 64 tile would exceed the 160 KB of
@@ -755,6 +982,12 @@ hec_bf16(char* __restrict__ arena, const HecDesc* __restrict__ descs, int n_desc
   };
 
   int64_t item = blockIdx.x;
+  if constexpr (TR) {
+    if (item >= n_items) {
+      trace_block<float, NTH>(arena, tdescs, n_tdesc, n_titems, item - n_items);
+      return;
+    }
+  }
   if (item >= n_items) return;
   ItemView<float> cur = view_item<float, BM, BN>(arena, descs, n_desc, item);
   gload(cur, cur.kbeg);
@@ -887,27 +1120,33 @@ static_assert(Tile3::BM == kTileShapes[3].bm && Tile3::BN == kTileShapes[3].bn &
 static_assert(Tile4::BM == kTileShapes[4].bm && Tile4::BN == kTileShapes[4].bn && Tile4::NTH == kTileShapes[4].nth, "tile 4");
 static_assert(Tile5::BM == kTileShapes[5].bm && Tile5::BN == kTileShapes[5].bn && Tile5::NTH == kTileShapes[5].nth, "tile 5");
 
-// Kernel of one launch variant in a per-precision table: K<TL, ST, PF, IN>::fn()
-// is the kernel for tile TL, ST LDS stages, persistent grid PF and interior
-// launch IN (every contraction interior, hec_interior).
-template <template <class, int, bool, bool> class K, class TL>
-const void* hec_pick(int stages, bool persistent, bool interior) {
-  if (stages == 2) {
-    if (persistent) return interior ? K<TL, 2, true, true>::fn() : K<TL, 2, true, false>::fn();
-    return interior ? K<TL, 2, false, true>::fn() : K<TL, 2, false, false>::fn();
+// Kernel of one launch variant in a per-precision table: K<TL, ST, PF, IN, TR>::fn()
+// is the kernel for tile TL, ST LDS stages, persistent grid PF, interior
+// launch IN (every contraction interior, hec_interior) and carried traces TR
+// (grids of one workgroup per item only: nullptr for a persistent one).
+template <template <class, int, bool, bool, bool> class K, class TL, int ST>
+const void* hec_pick_st(bool persistent, bool interior, bool traces) {
+  if (persistent) {
+    if (traces) return nullptr;
+    return interior ? K<TL, ST, true, true, false>::fn() : K<TL, ST, true, false, false>::fn();
   }
-  if (persistent) return interior ? K<TL, 1, true, true>::fn() : K<TL, 1, true, false>::fn();
-  return interior ? K<TL, 1, false, true>::fn() : K<TL, 1, false, false>::fn();
+  if (traces) return interior ? K<TL, ST, false, true, true>::fn() : K<TL, ST, false, false, true>::fn();
+  return interior ? K<TL, ST, false, true, false>::fn() : K<TL, ST, false, false, false>::fn();
 }
-template <template <class, int, bool, bool> class K>
-const void* hec_table(int tile, int stages, bool persistent, bool interior) {
+template <template <class, int, bool, bool, bool> class K, class TL>
+const void* hec_pick(int stages, bool persistent, bool interior, bool traces) {
+  return stages == 2 ? hec_pick_st<K, TL, 2>(persistent, interior, traces)
+                     : hec_pick_st<K, TL, 1>(persistent, interior, traces);
+}
+template <template <class, int, bool, bool, bool> class K>
+const void* hec_table(int tile, int stages, bool persistent, bool interior, bool traces) {
   switch (tile) {
-    case 0: return hec_pick<K, Tile0>(stages, persistent, interior);
-    case 1: return hec_pick<K, Tile1>(stages, persistent, interior);
-    case 2: return hec_pick<K, Tile2>(stages, persistent, interior);
-    case 3: return hec_pick<K, Tile3>(stages, persistent, interior);
-    case 4: return hec_pick<K, Tile4>(stages, persistent, interior);
-    case 5: return hec_pick<K, Tile5>(stages, persistent, interior);
+    case 0: return hec_pick<K, Tile0>(stages, persistent, interior, traces);
+    case 1: return hec_pick<K, Tile1>(stages, persistent, interior, traces);
+    case 2: return hec_pick<K, Tile2>(stages, persistent, interior, traces);
+    case 3: return hec_pick<K, Tile3>(stages, persistent, interior, traces);
+    case 4: return hec_pick<K, Tile4>(stages, persistent, interior, traces);
+    case 5: return hec_pick<K, Tile5>(stages, persistent, interior, traces);
     default: return nullptr;
   }
 }

@@ -7,7 +7,6 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
-#include <type_traits>
 
 #include "desc.hpp"
 #include "hec.hpp"
@@ -33,165 +32,24 @@ __global__ void __launch_bounds__(256) splitk_reduce(char* __restrict__ arena, c
 }
 
 // ------------------------------------------------------------------ root trace (FP64)
-// 4 consecutive elements of one row: vector loads when all 4 are in range and
-// the row is 4-element aligned, otherwise element-wise with zero fill.
-template <typename T>
-__device__ __forceinline__ void load4(T (&r)[4], const T* src, int valid, bool vec) {
-  if (vec && valid == 4) {
-    typedef typename Vec2<T>::V V;
-    constexpr int W = Vec2<T>::n;
-    const V* s = reinterpret_cast<const V*>(src);
-#pragma unroll
-    for (int q = 0; q < 4 / W; ++q) {
-      V v = s[q];
-      const T* e = reinterpret_cast<const T*>(&v);
-#pragma unroll
-      for (int x = 0; x < W; ++x) r[q * W + x] = e[x];
-    }
-  } else {
-#pragma unroll
-    for (int x = 0; x < 4; ++x) r[x] = x < valid ? src[x] : T(0);
-  }
-}
-
-// Four consecutive elements from a 16-byte aligned address, as vector loads.
-template <typename T>
-__device__ __forceinline__ void load4v(T (&r)[4], const T* src) {
-  typedef typename Vec2<T>::V V;
-  constexpr int W = Vec2<T>::n;
-  const V* s = reinterpret_cast<const V*>(src);
-#pragma unroll
-  for (int q = 0; q < 4 / W; ++q) {
-    V v = s[q];
-    const T* e = reinterpret_cast<const T*>(&v);
-#pragma unroll
-    for (int x = 0; x < W; ++x) r[q * W + x] = e[x];
-  }
-}
-
-// C(t) = sum_ij P[i,j] Q[j,i] over 4 x 4 blocks b = 0 .. nb^2 - 1 (block row
-// ib = b / nb, block column jb = b % nb, nb = ceil(N / 4)).  A block's loads
-// are 4 rows of P over columns 4jb.. and 4 rows of Q over columns 4ib.., so
-// every load is a row segment and the transpose happens in registers.
-// Summation order, the same in both layouts below: 256 partial sums, sum v
-// adding (by fused multiply-adds, in FP64; exact products for FP32 inputs)
-// the blocks v, v + 256, v + 512, ... in that order; sums 64w .. 64w + 63 meet
-// in a fixed butterfly across a wave's lanes, and the four results are added
-// in order w = 0, 1, 2, 3.  The result depends only on the data and N.
-// Layouts: WG = false, one wave per (root, t), four per workgroup, lane l
-// keeping the sums l, l + 64, l + 128, l + 192 (launches with many traces);
-// WG = true, one workgroup per (root, t), thread x keeping sum x (launches
-// with few traces, which one wave each would spread over few compute units
-// with several rounds of loads per wave).
+// The traces of one launch (device code and summation order: hec.hpp), in one
+// of two layouts of the same order.  WG = false: one wave per (root, t), four
+// per workgroup, for launches with many traces.  WG = true: one workgroup per
+// (root, t), for launches with few traces (small waves), which one wave each
+// would spread over few compute units with several rounds of loads per wave.
 template <typename T, bool WG>
 __global__ void __launch_bounds__(256, 3) hca_trace(char* __restrict__ arena, const HcaDesc* __restrict__ descs,
-                                                 int n_desc, int64_t n_items) {
-  __shared__ double part[2][4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int NS = WG ? 1 : 4;      // partial sums per thread
-  constexpr int W = WG ? 256 : 64;    // distance between a thread's sums' first blocks
-  const int x = WG ? tid : lane;
-  const int64_t first = WG ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wave;
-  const int64_t stride = WG ? (int64_t)gridDim.x : (int64_t)gridDim.x * 4;
-  for (int64_t item = first; item - (WG ? 0 : wave) < n_items; item += stride) {
-    if (!WG && item >= n_items) break;
-    const int di = find_desc(&descs[0].item_begin, sizeof(HcaDesc) / 4, n_desc, item);
-    const HcaDesc& h = descs[di];
-    const int t = (int)(item - h.item_begin), n = h.n;
-    const int64_t nn = (int64_t)n * n;
-    const T* P = reinterpret_cast<const T*>(arena + h.p_off) + (int64_t)t * 2 * nn;
-    const T* Q = reinterpret_cast<const T*>(arena + h.q_off) + (int64_t)t * 2 * nn;
-    const int nb = (n + 3) >> 2, nbb = nb * nb;
-    double sr[NS], si[NS];
-#pragma unroll
-    for (int j = 0; j < NS; ++j) sr[j] = si[j] = 0.0;
-    T pr[4][4], pi[4][4], qr[4][4], qi[4][4];
-    auto accumulate = [&]() {
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double xr = (double)pr[a][c], xi = (double)pi[a][c];
-          const double yr = (double)qr[c][a], yi = (double)qi[c][a];
-          sr[0] = __builtin_fma(xr, yr, sr[0]);
-          sr[0] = __builtin_fma(-xi, yi, sr[0]);
-          si[0] = __builtin_fma(xr, yi, si[0]);
-          si[0] = __builtin_fma(xi, yr, si[0]);
-        }
-    };
-    // chunk c0: one block for each of the thread's sums (block c0 + W j for
-    // sum j), each added into sum 0, after which the sums rotate by one, so
-    // that the chunk ends with every sum back in its place (the loop stays
-    // rolled, which keeps one block's registers live at a time).  WHOLE: N a
-    // multiple of 4, so every block is whole and every row segment a 16-byte
-    // aligned run, loaded as plain vector loads (masks would let the compiler
-    // merge them into element-wise loads).
-    auto sweep = [&](auto whole) {
-      constexpr bool WHOLE = decltype(whole)::value;
-      for (int c0 = x; c0 < nbb; c0 += W * NS) {
-#pragma unroll 1
-        for (int q = 0; q < NS; ++q) {
-          // a block past the end reloads block c0 (in bounds) and is not added
-          const int b = c0 + W * q < nbb ? c0 + W * q : c0;
-          const int i0 = 4 * (b / nb), j0 = 4 * (b % nb);
-          const int vj = min(4, n - j0), vi = min(4, n - i0);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int64_t po = (int64_t)(i0 + r) * n + j0, qo = (int64_t)(j0 + r) * n + i0;
-            if constexpr (WHOLE) {
-              load4v<T>(pr[r], P + po);
-              load4v<T>(pi[r], P + nn + po);
-              load4v<T>(qr[r], Q + qo);
-              load4v<T>(qi[r], Q + nn + qo);
-            } else {
-              load4<T>(pr[r], P + po, i0 + r < n ? vj : 0, false);
-              load4<T>(pi[r], P + nn + po, i0 + r < n ? vj : 0, false);
-              load4<T>(qr[r], Q + qo, j0 + r < n ? vi : 0, false);
-              load4<T>(qi[r], Q + nn + qo, j0 + r < n ? vi : 0, false);
-            }
-          }
-          // every load of the block ahead of its first use, so that they are
-          // all in flight at once
-          __builtin_amdgcn_sched_barrier(0);
-          if (c0 + W * q < nbb) accumulate();
-          __builtin_amdgcn_sched_barrier(0);
-          if constexpr (NS > 1) {
-            const double r0 = sr[0], i0s = si[0];
-#pragma unroll
-            for (int j = 0; j + 1 < NS; ++j) {
-              sr[j] = sr[j + 1];
-              si[j] = si[j + 1];
-            }
-            sr[NS - 1] = r0;
-            si[NS - 1] = i0s;
-          }
-        }
-      }
-    };
-    if ((n & 3) == 0) sweep(std::true_type{});
-    else sweep(std::false_type{});
-#pragma unroll
-    for (int j = 0; j < NS; ++j)
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        sr[j] += __shfl_xor(sr[j], o);
-        si[j] += __shfl_xor(si[j], o);
-      }
-    double* out = reinterpret_cast<double*>(arena + h.out_off);
-    if constexpr (WG) {
-      if (lane == 0) {
-        part[0][wave] = sr[0];
-        part[1][wave] = si[0];
-      }
-      __syncthreads();
-      if (tid == 0) {
-        out[2 * t] = ((part[0][0] + part[0][1]) + part[0][2]) + part[0][3];
-        out[2 * t + 1] = ((part[1][0] + part[1][1]) + part[1][2]) + part[1][3];
-      }
-      __syncthreads();
-    } else if (lane == 0) {
-      out[2 * t] = ((sr[0] + sr[1]) + sr[2]) + sr[3];
-      out[2 * t + 1] = ((si[0] + si[1]) + si[2]) + si[3];
+                                                    int n_desc, int64_t n_items) {
+  if constexpr (WG) {
+    __shared__ double part[2][4];
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x)
+      trace_group<T, 4>(arena, descs, n_desc, item, true, (int)threadIdx.x, part);
+  } else {
+    const int wave = (int)threadIdx.x >> 6;
+    for (int64_t base = (int64_t)blockIdx.x * 4; base < n_items; base += (int64_t)gridDim.x * 4) {
+      const int64_t item = base + wave;
+      if (item >= n_items) break;
+      trace_wave<T, 4>(arena, descs, n_desc, item);
     }
   }
 }
@@ -279,7 +137,6 @@ unsigned persistent_grid(const void* kernel, int block, int64_t items) {
   }
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, resident));
 }
-constexpr int64_t kMaxGrid = 1 << 20;
 // traces per launch from which one wave per trace still fills 256 compute
 // units with a workgroup of four waves each
 constexpr int64_t kHcaWaveItems = 4 * 256;
@@ -304,6 +161,11 @@ void KernelCall::bind() {
   } else {
     args[2] = &n_desc;
     args[3] = &n_items;
+    if (n_args == 7) {
+      args[4] = &tdesc;
+      args[5] = &n_tdesc;
+      args[6] = &n_titems;
+    }
   }
 }
 
@@ -317,28 +179,44 @@ hipError_t launch(KernelCall& k, hipStream_t s) {
 // interior: every contraction of the launch passes hec_interior for the
 // variant's tile and the precision's k-step (the host checks it).
 hipError_t hec_call(int prec, int variant, bool interior, char* arena, int64_t desc_off, int n_desc, int64_t n_items,
-                    KernelCall* k) {
+                    KernelCall* k, int64_t tdesc_off, int n_tdesc, int64_t n_titems) {
+  const bool traces = n_titems > 0;
   if (variant == kGenVariantId) {        // contractions over any index pairs: FP64 and FP32
-    if (prec > 1) return hipErrorInvalidValue;
+    if (prec > 1 || traces) return hipErrorInvalidValue;
     k->fn = prec == 0 ? hec_general_f64() : hec_general_f32();
     k->block = kTileShapes[1].nth;
     k->grid = grid_for(n_items);
     set_args(*k, arena, arena + desc_off, n_desc, n_items);
+    k->n_args = 7;
     return hipSuccess;
   }
   if (variant < 0 || variant >= 4 * kNumTiles || prec < 0 || prec > 3) return hipErrorInvalidValue;
   const int tile = variant % kNumTiles;
   const bool persistent = (variant / kNumTiles) % 2 == 0;
   const int stages = variant / (2 * kNumTiles) == 0 ? 2 : 1;
-  const void* fn = prec == 0   ? hec_kernel_f64(tile, stages, persistent, interior)
-                   : prec == 1 ? hec_kernel_f32(tile, stages, persistent, interior)
-                   : prec == 2 ? hec_kernel_bf16x2(tile, stages, persistent, interior)
-                               : hec_kernel_bf16x3(tile, stages, persistent, interior);
+  const void* fn = prec == 0   ? hec_kernel_f64(tile, stages, persistent, interior, traces)
+                   : prec == 1 ? hec_kernel_f32(tile, stages, persistent, interior, traces)
+                   : prec == 2 ? hec_kernel_bf16x2(tile, stages, persistent, interior, traces)
+                               : hec_kernel_bf16x3(tile, stages, persistent, interior, traces);
   if (fn == nullptr) return hipErrorInvalidValue;
   k->fn = fn;
   k->block = kTileShapes[tile].nth;
-  k->grid = persistent ? persistent_grid(fn, k->block, n_items) : grid_for(n_items);
   set_args(*k, arena, arena + desc_off, n_desc, n_items);
+  k->n_args = 7;
+  if (traces) {
+    // one workgroup per contraction work item, then the trace workgroups
+    const int64_t blocks = n_items + trace_blocks(k->block, n_titems);
+    if (blocks > kMaxGrid) return hipErrorInvalidValue;
+    k->grid = (unsigned)blocks;
+    k->tdesc = arena + tdesc_off;
+    k->n_tdesc = n_tdesc;
+    k->n_titems = n_titems;
+  } else {
+    k->grid = persistent ? persistent_grid(fn, k->block, n_items) : grid_for(n_items);
+    k->tdesc = nullptr;
+    k->n_tdesc = 0;
+    k->n_titems = 0;
+  }
   return hipSuccess;
 }
 

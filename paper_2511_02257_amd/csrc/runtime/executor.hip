@@ -298,7 +298,9 @@ void ensure_pinned(void*& p, int64_t& have, int64_t need_bytes) {
 
 hipError_t call_of(const Launch& L, int prec, char* arena, KernelCall* k) {
   switch (L.type) {
-    case L_HEC: return hec_call(prec, L.tile, L.interior != 0, arena, L.desc_off, L.n_desc, L.n_items, k);
+    case L_HEC:
+      return hec_call(prec, L.tile, L.interior != 0, arena, L.desc_off, L.n_desc, L.n_items, k, L.tr_desc_off,
+                      L.tr_n_desc, L.tr_n_items);
     case L_RED: return reduce_call(prec, arena, L.desc_off, L.n_desc, L.n_items, k);
     case L_HCA: return hca_call(prec, arena, L.desc_off, L.n_desc, L.n_items, k);
     default: throw Error(CDAG_E_STATE, "bad launch type");
@@ -893,6 +895,9 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
     D.resident_epoch = D.arena_epoch;
     D.resident_key = D.stage_version[prec];
   }
+  // a plan with the leaves on the host keeps its own tensors where a resident
+  // plan keeps the leaves, so the next resident execute uploads them again
+  if (!c.leaves_resident) D.resident_prec = -1;
 
   bool has_copies = false;
   for (const PlanRec& r : p.recs)
@@ -990,6 +995,9 @@ void device_execute(Ctx& c, int prec, int batched, cdag_exec_stats* st) {
       r.n_items = L.n_items;
       r.flops = L.flops;
       r.bytes = L.bytes;
+      r.trace_items = L.tr_n_items;
+      r.trace_flops = L.tr_flops;
+      r.trace_bytes = L.tr_bytes;
       c.records.push_back(r);
       if (L.type == L_HEC) t_hec += x * 1e-3;
     }

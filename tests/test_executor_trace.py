@@ -278,6 +278,26 @@ def test_time_slice_passes_have_no_races(name, wl, chunks):
     c.close()
 
 
+def test_trace_fusion_leaves_plan_and_walk_unchanged():
+    """Trace fusion changes only how a step's kernels are grouped into
+    launches: the plan and the executor's walk (transfers, waits, the ranges
+    each step's kernels read and write) are the same with it on."""
+    for name, wl in CASES:
+        c = _ctx(wl)
+        c.schedule("tree")
+        c.set_mem_budget(_budget(wl, 2))
+        c.set_options(leaves_resident=False, wave_lookahead=16)
+        c.set_trace_fusion(False)
+        p0, t0 = c.plan("fp64", True), c.trace_execute("fp64", True)
+        assert p0["n_h2d"] > 0
+        c.set_trace_fusion(True)
+        p1, t1 = c.plan("fp64", True), c.trace_execute("fp64", True)
+        c.close()
+        assert {k: v for k, v in p0.items() if not k.startswith("t_")} == \
+            {k: v for k, v in p1.items() if not k.startswith("t_")}, name
+        assert t0 == t1, name
+
+
 def test_injected_failures_leave_the_context_usable():
     name, wl = CASES[0]
     c = _ctx(wl)

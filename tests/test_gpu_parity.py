@@ -290,8 +290,9 @@ def test_timed_execute_records_every_launch(baryon_small):
     assert sum(r["flops"] for r in hec) == st["hec_flops"]
     assert sum(r["bytes"] for r in hec) == st["hec_bytes"]
     hca = [r for r in recs if r["type"] == "hca"]
-    assert sum(r["flops"] for r in hec + hca) == st["plan"]["flops"]
-    assert sum(r["n_items"] for r in hca) == 3 * st["plan"]["n_roots"]     # (root, t) pairs
+    # traces in launches of their own or carried by a contraction launch
+    assert sum(r["flops"] + r["trace_flops"] for r in hec + hca) == pytest.approx(st["plan"]["flops"], rel=1e-12)
+    assert sum(r["n_items"] for r in hca) + sum(r["trace_items"] for r in hec) == 3 * st["plan"]["n_roots"]
     assert any(r["type"] == "reduce" and r["kinds"] == [2] for r in recs)   # K33 split-K
     assert recs[-1]["type"] == "xsum" and recs[-1]["step"] == -1
     steps = [r["step"] for r in recs[:-1]]
@@ -510,6 +511,7 @@ def test_trace_layouts(prec, nvec):
         ctx = X.Context()
         ctx.build_cdag(wl.leaves, wl.graphs)
         ctx.schedule("tree")
+        ctx.set_trace_fusion(False)     # the trace kernel's own launches
         runner = DeviceRunner(ctx, 0)
         bits = []
         for batched in (True, False):
@@ -524,6 +526,89 @@ def test_trace_layouts(prec, nvec):
             assert err.max() <= TOL[prec]
             bits.append(np.concatenate(ctx.fetch_correlators()).view(np.uint64).copy())
         assert np.array_equal(bits[0], bits[1])
+        ctx.close()
+
+
+def test_resident_leaves_after_a_host_leaf_execute(meson_small):
+    """A plan with the leaves on the host uses the memory where a resident
+    plan keeps them; the resident execute that follows uploads them again and
+    gives the same bits as before."""
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd.device import DeviceRunner
+    from oracle import dag as OD, schedules as OS
+    wl, ref = meson_small
+    d = OD.build(wl.leaves, wl.graphs)
+    ctx = X.Context()
+    ctx.build_cdag(wl.leaves, wl.graphs)
+    ctx.schedule("tree")
+    runner = DeviceRunner(ctx, 0)
+    ctx.set_options(leaves_resident=True, wave_lookahead=16, use_graphs=0)
+    runner.run("fp64", True)
+    first = np.concatenate(ctx.fetch_correlators()).view(np.uint64).copy()
+    ctx.set_mem_budget(OS.memsim(d, OS.input_order(d), 16)["peak_live"] // 4)
+    ctx.set_options(leaves_resident=False, wave_lookahead=16, use_graphs=0)
+    runner.run("fp64", True)
+    assert rel_errors(ctx.fetch_correlators(), ref).max() <= TOL["fp64"]
+    ctx.set_options(leaves_resident=True, wave_lookahead=16, use_graphs=0)
+    runner.run("fp64", True)
+    again = np.concatenate(ctx.fetch_correlators()).view(np.uint64)
+    ctx.close()
+    assert np.array_equal(first, again)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_trace_fusion(meson_small, rank4_small, prec):
+    """Trace fusion (a step's root traces ride in one of its contraction
+    launches): the same bits as separate trace launches for every tile shape
+    (a 64-thread workgroup carries one trace as one wave, a 256-thread one one
+    trace, a 512-thread one two, with an idle group when the count is odd),
+    with leaves resident and under a budget that forces spills, in each issue
+    mode; the launch records carry every trace exactly once."""
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd.device import DeviceRunner
+    from oracle import dag as OD, schedules as OS
+    ALL = X.binding.LOOKAHEAD_ALL
+    eb = 16 if prec == "fp64" else 8
+    for wl, ref in (meson_small, rank4_small):
+        d = OD.build(wl.leaves, wl.graphs)
+        budget = OS.memsim(d, OS.input_order(d), eb)["peak_live"] // 4 if wl.name == "meson_small" else None
+        ctx = X.Context()
+        ctx.build_cdag(wl.leaves, wl.graphs)
+        ctx.schedule("tree")
+        runner = DeviceRunner(ctx, 0)
+        nt = wl.leaves[0].nt
+        for tile in (0, 1, 2, 4, 5):
+            for n in {lf.nvec for lf in wl.leaves}:
+                for kind in (0, 1, 2, 4, 5, 6):
+                    ctx.set_tile(prec, kind, n, tile, 1, 1, 1)
+            for resident, bud, look, mode in ((True, None, ALL, 0), (False, budget, 16, 1), (False, budget, 16, 2)):
+                bits = []
+                for fuse in (False, True):
+                    ctx.set_trace_fusion(fuse)
+                    ctx.set_mem_budget(bud)
+                    ctx.set_options(leaves_resident=resident, wave_lookahead=look, use_graphs=mode)
+                    runner.run(prec, True)
+                    corr = ctx.fetch_correlators()
+                    assert rel_errors(corr, ref).max() <= TOL[prec], (wl.name, tile, resident, mode, fuse)
+                    bits.append(np.concatenate(corr).view(np.uint64).copy())
+                assert np.array_equal(bits[0], bits[1]), (wl.name, prec, tile, resident, mode)
+            ctx.set_trace_fusion(True)
+            ctx.set_mem_budget(None)
+            ctx.set_options(leaves_resident=True, wave_lookahead=ALL, use_graphs=0)
+            ctx.set_timing(True)
+            st = runner.run(prec, True)
+            recs = [r for r in ctx.launch_records() if r["type"] not in ("h2d", "d2h")]
+            ctx.set_timing(False)
+            carried = sum(r["trace_items"] for r in recs if r["type"] == "hec")
+            alone = sum(r["n_items"] for r in recs if r["type"] == "hca")
+            print(f"{wl.name} {prec} tile {tile}: {carried} traces carried, {alone} in trace launches, "
+                  f"{len(recs)} launches")
+            assert carried > 0 and carried + alone == st["plan"]["n_roots"] * nt
+            assert all(3 in r["kinds"] for r in recs if r["trace_items"] > 0)
+            assert all(r["trace_items"] == 0 for r in recs if r["type"] != "hec")
+            total = sum(r["flops"] + r["trace_flops"] for r in recs)
+            assert abs(total - st["plan"]["flops"]) <= 1e-9 * st["plan"]["flops"]
+        ctx.set_trace_fusion(False)
         ctx.close()
 
 
