@@ -15,7 +15,7 @@ import pytest
 from synth import workloads as W
 from oracle import values as OV
 
-from gpu_util import run, rel_errors, sum_errors
+from gpu_util import run, rel_errors, sum_errors, oracle_plan_counts
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +49,15 @@ def test_meson_ring_full_fp64_bench_configuration(meson):
     n = run(wl, "node", "fp64", True, budget=gold["budget"], wave_lookahead=16)
     assert n["stats"]["plan"]["n_evict"] > 0
     assert np.array_equal(np.concatenate(n["corr"]).view(np.uint64),
+                          np.concatenate(r["corr"]).view(np.uint64))
+    # the bench's fastest budgeted form: 16 passes over the time slices with
+    # lookahead 384, captured segments; plan counters equal the oracle's
+    _, _, o = oracle_plan_counts(wl, "tree", 16, gold["budget"], True, lookahead=384, t_chunks=16)
+    c = run(wl, "tree", "fp64", True, budget=gold["budget"], wave_lookahead=384, t_chunks=16)
+    p = c["stats"]["plan"]
+    for k in ("peak_resident", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes", "n_steps"):
+        assert p[k] == o[k], k
+    assert np.array_equal(np.concatenate(c["corr"]).view(np.uint64),
                           np.concatenate(r["corr"]).view(np.uint64))
 
 
@@ -94,6 +103,43 @@ def test_baryon_mix_full_sampled(baryon, prec, tol):
     assert err.max() <= tol
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 1e-5), ("bf16x6", 1e-5)])
+def test_baryon_mix_headline_configuration(baryon, prec, tol):
+    """The launch configuration of the bench's headline and precision-form
+    rows: 8 passes over the time slices, every ready contraction in a wave,
+    a 32e9 B budget, leaves in pinned host memory, eager issue on three
+    streams, the bench's kernel choices (FP64: 64x64 tiles of 512 threads, one
+    LDS stage, K33 without split-K; the other modes tuned in situ).  Plan
+    counters equal the oracle's; the sampled correlators are within the bound."""
+    import paper_2511_02257_amd as X
+    from paper_2511_02257_amd.device import DeviceRunner
+    wl, sample, ref = baryon
+    budget = 32 * 10**9
+    _, _, o = oracle_plan_counts(wl, "tree", 16 if prec == "fp64" else 8, budget, True, lookahead=ALL, t_chunks=8)
+    ctx = X.Context()
+    ctx.build_cdag(wl.leaves, wl.graphs)
+    ctx.schedule("tree")
+    ctx.set_mem_budget(budget)
+    ctx.set_time_chunks(8)
+    ctx.set_options(leaves_resident=False, wave_lookahead=ALL, use_graphs=0)
+    runner = DeviceRunner(ctx, 0)
+    if prec == "fp64":
+        ctx.set_tile("fp64", W.K32, 64, 5, 1, 1, 1)
+        ctx.set_tile("fp64", W.K33, 64, 5, 1, 1, 0)
+    else:
+        runner.autotune(prec, True, reps=1, in_situ=True)
+    st = runner.run(prec, True)
+    p = st["plan"]
+    for k in ("peak_resident", "n_evict", "n_h2d", "h2d_bytes", "n_d2h", "d2h_bytes", "n_steps"):
+        assert p[k] == o[k], k
+    corr = ctx.fetch_correlators()
+    ctx.close()
+    err = np.array([np.linalg.norm(corr[g] - ref[g]) / np.linalg.norm(ref[g]) for g in sample])
+    print(f"baryon_mix headline configuration {prec}: steps={p['n_steps']} h2d={p['h2d_bytes'] / 1e9:.2f} GB "
+          f"max rel {err.max():.3e} median {np.median(err):.3e}")
+    assert err.max() <= tol
+
+
 @pytest.fixture(scope="module")
 def batched():
     wl = W.config("batched")
@@ -131,8 +177,13 @@ def test_batched_per_contraction_matches_waves(batched):
     wl, sample, ref = batched
     a = run(wl, "tree", "fp32", False, budget=64 * 10**9)
     b = run(wl, "tree", "fp32", True, budget=64 * 10**9, wave_lookahead=ALL)
+    # the bench's passes form: 8 passes over the time slices, every ready
+    # contraction in a wave, eager issue
+    c = run(wl, "tree", "fp32", True, budget=64 * 10**9, wave_lookahead=ALL, use_graphs=False, t_chunks=8)
+    assert c["stats"]["plan"]["n_evict"] == 0
     for g in sample:
         assert np.array_equal(a["corr"][g].view(np.uint64), b["corr"][g].view(np.uint64))
+        assert np.array_equal(c["corr"][g].view(np.uint64), b["corr"][g].view(np.uint64))
     ta, tb = a["stats"]["t_total_s"], b["stats"]["t_total_s"]
     print(f"batched fp32: per-contraction {ta * 1e3:.1f} ms ({a['stats']['n_launches']} launches), "
           f"waves {tb * 1e3:.1f} ms ({b['stats']['n_launches']} launches)")
